@@ -1,0 +1,205 @@
+"""Ensemble-level pins of the reference Monte Carlo: stationary energy at
+zero field, the Drude transient, the first-real-scattering survival law,
+exact free flight, and thread-count independence."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1707_09073_amd import workloads as W
+
+QE, HBAR, M0, KB = 1.602176634e-19, 1.054571817e-34, 9.1093837015e-31, 1.380649e-23
+CK = HBAR ** 2 / (2 * M0 * QE) * 1e18       # eV nm^2
+CF = QE / HBAR * 1e-15                       # 1/(nm fs) per V/nm
+CV = HBAR / M0 * 1e3                         # nm^2/fs
+
+
+def _kane_E(g, a):
+    return 2 * g / (1 + np.sqrt(1 + 4 * a * g))
+
+
+def test_zero_field_stationary_mean_energy(oracle_mod):
+    """With zero field the only inelastic events are LO absorption/emission
+    (+-hw); energy modulo hw is conserved, and along each ladder E0 + n hw the
+    stationary occupation satisfies p_{n+1}/p_n = W_ab(E_n)/W_em(E_{n+1}).
+    Starting from a 600 K Maxwellian in a 300 K lattice, the mean energy must
+    relax to the prediction built from the initial ladder offsets."""
+    cfg = W.bulk_config(n_particles=20000, field_V_per_nm=0.0, doping_cm3=1e17, substeps=10)
+    cfg["T_init_K"] = 600.0
+    mat = cfg["material"]
+    a, m = mat["alpha"][0], mat["m_eff"][0]
+    hw, dE = mat["hw_lo_eV"], cfg["dE_eV"]
+    o = oracle_mod.Oracle(cfg)
+    o.run(500)                        # 5 ps
+    h = o.history()
+    Et = h[:, 4] / h[:, 0]
+    win = Et[300:]                    # last 2 ps
+    blocks = win.reshape(10, -1).mean(axis=1)
+    sig = blocks.std(ddof=1) / math.sqrt(len(blocks))
+    # prediction
+    kTi = KB * 600.0 / QE
+    mid = lambda E: (np.floor(E / dE) + 0.5) * dE
+    rate = lambda mech, E: oracle_mod.rate(cfg, 0, mech, float(E), 300.0)
+    E0 = (np.arange(4000) + 0.5) * hw / 4000
+    nr = 12
+    tot = 0.0
+    norm = 0.0
+    for e0 in E0:
+        En = e0 + hw * np.arange(nr)
+        g = En * (1 + a * En)
+        pE = 2 * np.sqrt(g) / (math.sqrt(math.pi) * kTi ** 1.5) * np.exp(-g / kTi) * (1 + 2 * a * En)
+        rho0 = pE.sum()
+        p = np.ones(nr)
+        for n in range(nr - 1):
+            p[n + 1] = p[n] * rate(2, mid(En[n])) / rate(3, mid(En[n + 1]))
+        p /= p.sum()
+        tot += rho0 * (p * En).sum()
+        norm += rho0
+    pred = tot / norm
+    assert abs(win.mean() - pred) < max(4 * sig, 0.004 * pred), (win.mean(), pred, sig)
+    # and it is not the starting value (the test can fail)
+    assert abs(Et[0] - pred) > 10 * sig
+
+
+def test_drude_transient(oracle_mod):
+    """Test-only constant-rate isotropic elastic mechanism (rate G0), alpha = 0,
+    electrons at rest: <v_z>(t) = -(eF/(m G0)) (1 - exp(-G0 t))."""
+    cfg = W.bulk_config(n_particles=50000, field_V_per_nm=1e-3, substeps=1)
+    cfg["material"]["alpha"] = [0.0, 0.0, 0.0]
+    o = oracle_mod.Oracle(cfg)
+    G0 = 0.01  # 1/fs = 1e13 1/s
+    S, K4 = o.tables()
+    S[:] = 0.0
+    S[:, :, 0] = G0 / cfg["T0_K"]
+    o.set_tables(S, K4)
+    assert o.gamma() == pytest.approx([G0] * 3, rel=1e-15)
+    P = o.particles()
+    P["k"][:] = 0.0
+    o.set_particles(P["k"], P["r"], P["valley"], P["alive"], P["id"])
+    o.run(600)
+    h = o.history()
+    vz = h[:, 3] / h[:, 0] * 1e6         # m/s
+    t = np.arange(1, 601, dtype=float)
+    m = cfg["material"]["m_eff"][0] * M0
+    F = cfg["F_bulk"][2] * 1e9
+    pred = -(QE * F / (m * G0 * 1e15)) * (1 - np.exp(-G0 * t))
+    assert QE * F / (m * G0 * 1e15) == pytest.approx(8.375e4, rel=2e-3)
+    for lo in range(0, 600, 100):
+        sl = slice(lo, lo + 100)
+        # spread of v_z across particles grows with the heating; per-sample error
+        E = h[sl, 4] / h[sl, 0]
+        sig = np.sqrt(2 * E.max() * QE / m / 3) / math.sqrt(h[0, 0])
+        assert abs(vz[sl].mean() - pred[sl].mean()) < 4 * sig, (lo, vz[sl].mean(), pred[sl].mean(), sig)
+
+
+def test_first_real_scattering_survival(oracle_mod):
+    """Self-scattering with a fresh flight time each interval reproduces the
+    survival law P(t) = exp(-int_0^t W_real(E(t')) dt') along the
+    deterministic trajectory from a fixed k0."""
+    n = 40000
+    cfg = W.bulk_config(n_particles=n, field_V_per_nm=1e-2, doping_cm3=1e17, substeps=1)
+    mat = cfg["material"]
+    o = oracle_mod.Oracle(cfg)
+    P = o.particles()
+    k0 = np.array([0.0, 0.3, 1.4])
+    P["k"][:] = k0
+    o.set_particles(P["k"], P["r"], P["valley"], P["alive"], P["id"])
+    S, K4 = o.tables()
+    f = o.factors()[0]
+    g0 = o.gamma()[0]
+    F = np.array(cfg["F_bulk"])
+    alive = np.ones(n, bool)
+    surv = []
+    T = 40
+    for step in range(1, T + 1):
+        o.run(1)
+        k = o.particles()["k"]
+        det = k0 - CF * F * step
+        same = np.all(np.abs(k - det) <= 1e-12 * np.linalg.norm(det), axis=1)
+        alive &= same
+        surv.append(alive.mean())
+    # prediction: integrate the tabulated real-rate along k(t)
+    dt = 1e-3
+    ts = (np.arange(int(T / dt)) + 0.5) * dt
+    kt = k0[None, :] - CF * F[None, :] * ts[:, None]
+    E = _kane_E(CK * (kt ** 2).sum(1) / mat["m_eff"][0], mat["alpha"][0])
+    b = np.minimum((E / cfg["dE_eV"]).astype(int), cfg["n_bins"] - 1)
+    Wr = f[0] * S[0, b, 0] + (S[0, b, 1] * f[1]) / (f[6] + K4[0, b]) + f[2] * S[0, b, 2]
+    Wr = Wr + np.where(E > mat["hw_lo_eV"], f[3] * S[0, b, 3], 0.0)
+    for j in range(3):
+        for em in (0, 1):
+            Ep = E + mat["E_c"][0] - mat["E_c"][j] + (-1 if em else 1) * mat["hw_iv_eV"]
+            Wr = Wr + np.where(Ep > 0, (f[5] if em else f[4]) * S[0, b, 4 + 2 * j + em], 0.0)
+    assert Wr.max() <= g0
+    cum = np.cumsum(Wr) * dt
+    for step in (2, 5, 10, 20, 30, 40):
+        pred = math.exp(-cum[int(step / dt) - 1])
+        sig = math.sqrt(pred * (1 - pred) / n)
+        assert abs(surv[step - 1] - pred) < 4.5 * sig + 1e-4, (step, surv[step - 1], pred)
+    assert surv[-1] < 0.5  # real events happen: the test can fail
+
+
+def test_free_flight_exact_k_and_trapezoid_r(oracle_mod):
+    """Scattering switched off: over one interval k moves exactly by -eF T/hbar
+    in the cell field at the flight start, and r agrees with an RK4 solution
+    of dr/dt = v(k(t)) to within the trapezoid error bound."""
+    cfg = W.device_config(n_particles=3000, precision="fp64", Vds=1.0, n_cells=(10, 3, 6),
+                          L_nm=(100.0, 60.0, 120.0))
+    o = oracle_mod.Oracle(cfg)
+    S, K4 = o.tables()
+    o.set_tables(np.zeros_like(S), K4)
+    _, Fc, _ = o.fields()
+    P0 = o.particles()
+    o.run(1)
+    P1 = o.particles()
+    mat = cfg["material"]
+    TP = cfg["dt_fs"] * cfg["substeps"]
+    dx, dy, dz = [L / n for L, n in zip(cfg["L_nm"], cfg["n_cells"])]
+    checked = 0
+    for p in np.nonzero(P0["alive"])[0][:150]:
+        r0, k0 = P0["r"][p], P0["k"][p]
+        if not P1["alive"][p] or P1["id"][p] != P0["id"][p]:
+            continue  # exited (the slot may hold a newly injected electron)
+        ix, iy, iz = int(r0[0] // dx), int(r0[1] // dy), int(r0[2] // dz)
+        F = Fc[(ix * 3 + iy) * 6 + iz]
+        k1 = k0 - CF * F * TP
+        if np.any(np.sign(P1["k"][p][1:]) != np.sign(k1[1:])):
+            continue  # a lateral reflection flipped a component
+        assert np.allclose(P1["k"][p], k1, rtol=1e-14, atol=1e-15)
+        m, a = mat["m_eff"][0], mat["alpha"][0]
+
+        def vel(t):
+            k = k0 - CF * F * t
+            E = _kane_E(CK * k.dot(k) / m, a)
+            return CV * k / (m * (1 + 2 * a * E))
+
+        h = TP / 400
+        r = r0.copy()
+        for i in range(400):
+            t = i * h
+            k1_, k2_, k4_ = vel(t), vel(t + h / 2), vel(t + h)
+            r = r + h / 6 * (k1_ + 4 * k2_ + k4_)
+        # trapezoid error bound (T^3/12) max|v''|
+        ts = np.linspace(0, TP, 41)
+        vs = np.array([vel(t) for t in ts])
+        d2 = np.abs(np.diff(vs, 2, axis=0)).max() / (ts[1] - ts[0]) ** 2
+        bound = TP ** 3 / 12 * d2 * 1.5 + 1e-12
+        assert np.all(np.abs(P1["r"][p] - r) <= bound), (p, P1["r"][p] - r, bound)
+        checked += 1
+    assert checked > 40
+
+
+def test_thread_count_independence(oracle_mod):
+    for cfg in (W.bulk_config(n_particles=3000, substeps=5),
+                W.device_config(n_particles=3600, precision="fp64", n_cells=(10, 3, 6), L_nm=(100.0, 60.0, 120.0),
+                                Vds=2.0)):
+        a, b = oracle_mod.Oracle(cfg), oracle_mod.Oracle(cfg)
+        a.run(20, 1)
+        b.run(20, 8)
+        pa, pb = a.particles(), b.particles()
+        for key in pa:
+            assert np.array_equal(pa[key], pb[key]), key
+        ca, cb = a.counts(), b.counts()
+        assert ca["selections"] == cb["selections"] and np.array_equal(ca["real"], cb["real"])
+        ha, hb = a.maps(), b.maps()
+        assert np.array_equal(ha[0], hb[0]) and np.array_equal(ha[1], hb[1])
