@@ -1,0 +1,154 @@
+"""Benchmark of the electron Monte Carlo hot path on one MI355X.
+
+Workload: the half-nanowire FinFET device (60 x 120 nm cross-section, 1 um
+channel, 3x6x100 subcells) with 10 million superparticles, FP32 particle
+state with FP64 tallies and Poisson, 1e18 cm^-3 doping, Vgs = 0, Vds = 5 V,
+lattice temperature 300 K plus a +150 K Gaussian hot spot at the drain end.
+One step = one flight interval: 10 sub-steps of 1 fs of free flight and
+scattering for every electron, then the subcell deposit, the contact refill
+and the Poisson refresh.  The default run times 500 steps (5 ps).
+
+Prints one JSON line.  The metric counts free-flight segments (one per
+electron per sub-step plus one per scattering selection, real or self) per
+second; real scattering events/s and electron-fs/s are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "electron scatter+flight events/s per MI355X; surrogate vs MC heat-map time @2% err"
+HBM_PEAK_GBS = 8000.0
+# FP32 lane-ops per second: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (no packed math)
+ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_intervals: int = 3) -> dict:
+    """The FP64 CPU reference on the same workload, timed on the host cores
+    for its first few flight intervals after initialisation."""
+    from oracle import emc_oracle
+    from paper_1707_09073_amd import workloads as W
+    emc_oracle.build()
+    cfg = W.large_device_config()
+    cfg["precision"] = "fp64"
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    o = emc_oracle.Oracle(cfg)
+    t_init = time.perf_counter() - t0
+    o.reset_window()
+    t0 = time.perf_counter()
+    o.run(n_intervals, threads)
+    dt = time.perf_counter() - t0
+    c = o.counts()
+    # alive electrons x sub-steps + selections, as for the GPU
+    import numpy as np
+    alive = int(np.count_nonzero(o.particles()["alive"]))
+    segs = alive * cfg["substeps"] * n_intervals + c["selections"]
+    return dict(value=segs / dt, unit="events/s", cores=threads, kind="oracle",
+                sample=(f"same 1e7-superparticle device workload in FP64, first {n_intervals} flight intervals "
+                        f"({n_intervals * cfg['substeps']} fs) after initialisation; {dt:.1f} s timed, "
+                        f"init {t_init:.1f} s untimed; segments counted as on the GPU (alive x sub-steps "
+                        f"approximated by the final alive count)"))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500, help="timed flight intervals (10 fs each)")
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--particles", type=int, default=10_000_000)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--graph", action="store_true", help="replay intervals from a hipGraph (no per-kernel timing)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the hot path here is the per-GPU share and is not sharded "
+              "(see the design notes for how it would shard).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1707_09073_amd import gfmc, workloads as W
+    if not os.path.exists(gfmc.LIB_PATH):
+        from paper_1707_09073_amd import build as B
+        B.build(force=True)
+    torch.cuda.set_device(0)
+    cfg = W.large_device_config(n_particles=args.particles)
+    K = cfg["substeps"]
+    _log(f"init: {args.particles} superparticles, capacity {cfg['capacity']}")
+    ens = gfmc.Ensemble(cfg, device="cuda:0")
+    if args.block and args.tile:
+        ens.mc_set_launch(args.block, args.tile)
+    block, tile, n_tiles = ens.mc_get_launch()
+    ens.mc_use_graph(args.graph)
+    _log(f"launch: block {block}, tile {tile}, {n_tiles} tiles; warmup {args.warmup} intervals")
+    ens.mc_step(args.warmup * K)
+    ens.mc_tally(reset_window=True)
+    ens.mc_profile(not args.graph)
+    torch.cuda.synchronize()
+    _log(f"timing {args.steps} intervals")
+    t0 = time.perf_counter()
+    ens.mc_step(args.steps * K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tal = ens.mc_tally()
+    prof = ens.mc_profile_read() if not args.graph else None
+    segments = tal["segments"]
+    real = int(tal["real"].sum())
+    proc = (segments - tal["selections"]) // K           # electrons processed per interval, summed
+    value = segments / wall
+    _log(f"wall {wall:.3f} s, segments {segments}, selections {tal['selections']}, real {real}")
+
+    roofline = None
+    if prof and prof["n_flight"]:
+        flight_s = prof["flight_ms"] / prof["n_flight"] * 1e-3
+        per_launch = proc / prof["n_flight"]
+        # algorithmic HBM bytes per launch: the SoA state (6 x FP32 + u32 meta) read and written once
+        bytes_launch = per_launch * 28 * 2
+        roofline = dict(bound="hbm", achieved=bytes_launch / flight_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=bytes_launch / flight_s / 1e9 / HBM_PEAK_GBS, traffic=None,
+                        kernel="k_flight<float,true>", avg_launch_ms=flight_s * 1e3,
+                        refresh_avg_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]),
+                        flight_share=prof["flight_ms"] / (prof["flight_ms"] + prof["refresh_ms"]))
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "half-nanowire GaN FinFET device MC, 10M superparticles, 3x6x100 subcells, "
+                               "Vgs=0 V, Vds=5 V, 1e18 cm^-3, 300 K + 150 K drain hot spot, 1 fs x 10 per step",
+                   "particles": args.particles, "substeps_per_step": K, "block": block, "tile": tile,
+                   "graph": bool(args.graph)},
+        "real_events_per_s": real / wall,
+        "electron_fs_per_s": proc * cfg["dt_fs"] * K / wall,
+        "drain_current_A": tal["drain_current_A"],
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        _log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

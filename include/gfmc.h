@@ -1,0 +1,229 @@
+/*
+ * gfmc.h -- C ABI of the MI355X (gfx950) ensemble electron Monte Carlo
+ * library libgfmc.so.
+ *
+ * The library advances an ensemble of electrons in wurtzite GaN by the method
+ * of Hao, Zhao, Xiao and Kronenfeld, arXiv:1707.09073 (electron Monte Carlo
+ * paragraph and Table I): Kane-nonparabolic free flight in the Gamma1, U and
+ * Gamma3 valleys under the local field, scattering chosen by self-scattering
+ * against tabulated ionized-impurity, polar-optical, acoustic and intervalley
+ * rates, electrons counted in 3x6x100 subcells of the half nanowire, the
+ * field refreshed from the Poisson equation with the terminal voltages, and
+ * the electron-phonon energy exchange counted per subcell.
+ *
+ * Conventions for every entry point:
+ *  - Plain C.  Every call returns an mc_status (0 = MC_OK, < 0 = error) and
+ *    never throws or aborts; mc_status_string() names a code and
+ *    mc_last_error() gives the detail of the last failure on a context.
+ *  - The library never allocates device memory.  The caller passes one
+ *    device workspace of at least mc_workspace_bytes() bytes (256-byte
+ *    aligned) and keeps it alive until mc_destroy().  The library carves all
+ *    device state out of it.
+ *  - The caller owns the HIP stream (a hipStream_t passed as void*); all
+ *    device work is enqueued on it asynchronously.  Calls that return host
+ *    data (mc_tally, mc_maps, mc_history, mc_read_*) synchronise the stream.
+ *  - Host pointers are caller-owned and only read or written during the call.
+ *  - A context is not thread-safe; use one context per host thread.
+ *
+ * Units: energy eV, wave vector 1/nm, position nm, time fs, field V/nm,
+ * potential V, doping and densities 1/m^3, temperature K.
+ */
+#ifndef GFMC_H
+#define GFMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MC_OK = 0,
+  MC_E_ARG = -1,      /* invalid argument or configuration */
+  MC_E_HIP = -2,      /* a HIP runtime call failed */
+  MC_E_CAPACITY = -3, /* particle slots exhausted, or identity space exhausted */
+  MC_E_RANGE = -4,    /* an event-count guard was hit in a flight */
+  MC_E_STATE = -5,    /* call not valid in the current state */
+  MC_E_NAN = -6       /* a non-finite particle state was produced */
+} mc_status;
+
+typedef enum { MC_PREC_FP64 = 0, MC_PREC_FP32_STATE = 1 } mc_precision;
+typedef enum { MC_BULK = 0, MC_DEVICE = 1 } mc_mode;
+
+/* Material: Table I of the paper plus the readings of silent points.  Valley
+ * order Gamma1, U, Gamma3. */
+typedef struct {
+  double m_eff[3];  /* band-edge effective mass, m0 */
+  double alpha[3];  /* Kane nonparabolicity, 1/eV */
+  double E_c[3];    /* valley minimum, eV */
+  int32_t Z[3];     /* number of equivalent valleys */
+  double eps_s, eps_inf; /* static and optical dielectric constants, eps0 */
+  double rho;       /* mass density, kg/m^3 */
+  double D_ac_eV;   /* acoustic deformation potential, eV */
+  double D_iv_eVm;  /* intervalley deformation potential, eV/m */
+  double hw_lo_eV;  /* LO phonon energy, eV */
+  double hw_iv_eV;  /* intervalley phonon energy, eV */
+  double u_ac;      /* sound velocity used by the acoustic rate, m/s */
+} mc_material;
+
+/* One instance (one bias point / one ensemble).  All instances of a context
+ * must share material, mode, precision, time step, sub-steps, table grid and
+ * geometry; seed, ensemble size, doping, temperatures and voltages may
+ * differ. */
+typedef struct {
+  mc_mode mode;
+  mc_precision prec;
+  mc_material mat;
+  uint64_t seed;         /* Philox key */
+  uint32_t instance;     /* enters every Philox counter; unique per ensemble */
+  int32_t n_particles;   /* initial electrons */
+  int32_t capacity;      /* particle slots (>= n_particles) */
+  double dt_fs;          /* sub-step */
+  int32_t substeps;      /* sub-steps per flight interval = per Poisson refresh */
+  int32_t n_bins;        /* rate-table bins */
+  double dE_eV;          /* rate-table bin width */
+  double T0_K;           /* uniform lattice temperature (see mc_set_lattice_temperature) */
+  double T_init_K;       /* temperature of the initial Maxwellian */
+  double N_D_m3;         /* donor density (all active: N_I = n = N_D) */
+  double F_bulk[3];      /* bulk mode: uniform field, V/nm */
+  double L_nm[3];        /* device mode: domain x (channel), y (cut width), z (height) */
+  int32_t n_cells[3];    /* device mode: subcells along x, y, z */
+  double gate_x_nm[2];   /* device mode: gated channel stretch */
+  double Vgs, Vds, phi_offset; /* device mode: gate, drain, gate work-function offset (V) */
+} mc_config;
+
+/* Window tallies of one instance, accumulated since the last reset. */
+typedef struct {
+  uint32_t intervals;       /* flight intervals in the window */
+  uint32_t intervals_total; /* intervals since mc_init */
+  double t_window_fs;
+  uint64_t n_alive;         /* electrons alive now */
+  uint64_t selections;      /* scattering selections (real + self) */
+  uint64_t self_events;
+  uint64_t overflow;        /* selections above the table top (clamped to the last bin) */
+  uint64_t real[3][10];     /* real events per initial valley and mechanism */
+  uint64_t exits[2];        /* electrons absorbed by source (0) and drain (1) */
+  uint64_t injections[2];   /* electrons injected at source and drain */
+  uint64_t segments;        /* free-flight segments: alive x substeps + selections */
+  uint64_t reflect_guard;   /* lateral reflections that needed clamping */
+  double weight;            /* electrons per superparticle (device mode) */
+  double drain_current_A;   /* e w (exits_D - injections_D) / t_window */
+  int32_t flags;            /* sticky device error flags (mc_status of the first) */
+} mc_tally_out;
+
+/* Device pointers of one instance's structure-of-arrays particle state.
+ * kx..z have `elem_bytes` bytes each (8 in FP64 mode, 4 in FP32 mode); meta
+ * packs id << 3 | alive << 2 | valley. */
+typedef struct {
+  void *kx, *ky, *kz, *x, *y, *z;
+  uint32_t *meta;
+  int32_t capacity;
+  int32_t elem_bytes;
+} mc_particles_view;
+
+typedef struct mc_ctx mc_ctx;
+
+const char *mc_status_string(int status);
+const char *mc_last_error(const mc_ctx *ctx);
+
+/* Bytes of device workspace needed for `n_instances` configurations;
+ * 0 if the configurations are invalid. */
+size_t mc_workspace_bytes(const mc_config *cfgs, int n_instances);
+
+/* Validate, build the rate tables (1 meV midpoints to the table top) and
+ * per-subcell factors, the self-scattering bounds Gamma_v, the initial
+ * Maxwellian ensemble, the Poisson factors and (device mode) the first
+ * deposit/injection/Poisson refresh (electron MC paragraph).  MC_E_ARG for
+ * capacity < n_particles, dt <= 0, table top < 3 eV, inconsistent instances
+ * or a workspace that is too small. */
+int mc_init(mc_ctx **out, const mc_config *cfgs, int n_instances, void *d_workspace, size_t ws_bytes,
+            void *hip_stream);
+int mc_destroy(mc_ctx *ctx);
+
+/* Per-subcell lattice temperature of one instance (ncell host doubles,
+ * index (ix*ny + iy)*nz + iz; one value in bulk mode).  Rebuilds the
+ * factors and Gamma_v: the lattice temperature sets the electron rates
+ * (coupling paragraph). */
+int mc_set_lattice_temperature(mc_ctx *ctx, int instance, const double *h_T_cells);
+
+/* Replace the T-independent rate shapes (host [3][n_bins][10] doubles and
+ * 4k^2 at bin midpoints [3][n_bins]) and rebuild Gamma_v. */
+int mc_set_tables(mc_ctx *ctx, const double *h_shape, const double *h_k4);
+
+/* Advance every instance by n_substeps sub-steps (a multiple of `substeps`):
+ * per interval, free flight and scattering with heat counts, then in device
+ * mode deposit, contact injection and Poisson refresh. */
+int mc_step(mc_ctx *ctx, int n_substeps);
+
+/* Deposit electrons per subcell, refill the contact subcells to neutrality,
+ * solve the Poisson equation and refresh the field, for all instances
+ * (device mode; done after every interval by mc_step). */
+int poisson_update(mc_ctx *ctx);
+
+/* Copy the window tallies of one instance; reset_window != 0 starts a new
+ * window afterwards.  Returns the first sticky device error, if any. */
+int mc_tally(mc_ctx *ctx, int instance, mc_tally_out *h_out, int reset_window);
+
+/* Window maps of one instance: h_heat4 [ncell][4] phonon counts (LO emit, LO
+ * absorb, intervalley emit, intervalley absorb), h_dens_sum [ncell] electron
+ * counts summed over the window's refreshes, and the derived FP64 maps
+ * h_heat_Wm3 (net phonon-emission power density) and h_density_m3.  Any
+ * pointer may be NULL. */
+int mc_maps(mc_ctx *ctx, int instance, uint64_t *h_heat4, uint64_t *h_dens_sum, double *h_heat_Wm3,
+            double *h_density_m3);
+
+/* Bulk mode: per-interval rows (n_alive, sum vx, sum vy, sum vz, sum E,
+ * N_Gamma1, N_U, N_Gamma3) recorded at each interval end, since the last
+ * window reset. */
+int mc_history(mc_ctx *ctx, int instance, double *h_rows, int max_rows, int *n_rows);
+
+/* Device pointers of one instance's particle state (for in-place readers). */
+int mc_particles(mc_ctx *ctx, int instance, mc_particles_view *out);
+
+/* Copy one instance's particles to / from host arrays of `capacity` entries:
+ * k[cap][3], r[cap][3] (FP64), valley, alive (int32), id (uint32). */
+int mc_read_particles(mc_ctx *ctx, int instance, double *h_k, double *h_r, int32_t *h_valley, int32_t *h_alive,
+                      uint32_t *h_id);
+int mc_write_particles(mc_ctx *ctx, int instance, const double *h_k, const double *h_r, const int32_t *h_valley,
+                       const int32_t *h_alive, const uint32_t *h_id);
+
+/* Potential, field and electron counts of the last refresh (ncell entries). */
+int mc_read_fields(mc_ctx *ctx, int instance, double *h_phi, double *h_field, uint32_t *h_count);
+
+/* Rate shapes [3][n_bins][10], 4k^2 [3][n_bins], per-cell factors [ncell][7]
+ * and Gamma_v [3] (1/fs) of one instance.  Any pointer may be NULL. */
+int mc_read_tables(mc_ctx *ctx, int instance, double *h_shape, double *h_k4, double *h_factors, double *h_gamma);
+
+/* Launch shape of the particle kernel: workgroup size (64..256, multiple of
+ * 64) and tile size (particles per tile, multiple of the workgroup size).
+ * Results do not depend on the shape.  MC_E_ARG if unsupported. */
+int mc_set_launch(mc_ctx *ctx, int block, int tile);
+int mc_get_launch(const mc_ctx *ctx, int *block, int *tile, int *n_tiles);
+
+/* Particle-kernel variant: 0 = lane refill (each lane pulls the next electron
+ * of its tile as soon as its own finishes the interval; default), 1 = one
+ * electron per lane per pass.  Results are identical up to the compiler's
+ * floating-point contraction choices in each variant.  MC_E_ARG otherwise. */
+int mc_set_variant(mc_ctx *ctx, int variant);
+
+/* Replay each interval from a captured hipGraph (1) or launch eagerly (0). */
+int mc_use_graph(mc_ctx *ctx, int enable);
+
+/* Time the particle kernel and the refresh chain of every interval with HIP
+ * events recorded on the context's stream (eager launches; graph replay is
+ * switched off while profiling).  mc_profile_read synchronises and returns
+ * total milliseconds and launch counts since the last reset. */
+int mc_profile(mc_ctx *ctx, int enable);
+int mc_profile_read(mc_ctx *ctx, double *flight_ms, int *n_flight, double *refresh_ms, int *n_refresh, int reset);
+
+/* Bytes and contents of a checkpoint (particle state, counters, tallies,
+ * fields); restoring into a context built from the same configurations
+ * continues bit-identically. */
+int mc_checkpoint(mc_ctx *ctx, void *h_buf, size_t *bytes);
+int mc_restore(mc_ctx *ctx, const void *h_buf, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFMC_H */

@@ -583,23 +583,26 @@ static int scatter(const or_ctx *X, double k[3], int *pv, int cell, const uint32
     else if (m == OR_POP_AB) heat[4 * cell + 1]++;
     else if (m >= OR_IV0) heat[4 * cell + ((m - OR_IV0) % 2 ? 2 : 3)]++;
   }
-  /* polar angle relative to the initial direction */
+  /* polar angle relative to the initial direction, sampled as X = 1 - cos:
+   * sin = sqrt(X (2 - X)) keeps full relative accuracy for forward
+   * scattering, where 1 - cos^2 would cancel */
   double u2 = u01(w[2]), u3 = u01(w[3]);
-  double ct;
+  double Xc;
   if (m == OR_II) {
     double a4 = 4.0 * k2 / f[F_B2];
-    ct = 1.0 - 2.0 * u2 / (1.0 + (1.0 - u2) * a4);
+    Xc = 2.0 * u2 / (1.0 + (1.0 - u2) * a4);
   } else if (m == OR_POP_AB || m == OR_POP_EM) {
     double gp = Ep * (1.0 + c->alpha[v] * Ep);
     double sg = sqrt(gam), sgp = sqrt(gp);
     double xi = 2.0 * sg * sgp / ((sg - sgp) * (sg - sgp));
-    ct = ((1.0 + xi) - pow(1.0 + 2.0 * xi, u2)) / xi;
+    Xc = expm1(u2 * log1p(2.0 * xi)) / xi;
   } else {
-    ct = 1.0 - 2.0 * u2;
+    Xc = 2.0 * u2;
   }
-  if (ct > 1.0) ct = 1.0;
-  if (ct < -1.0) ct = -1.0;
-  double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+  if (Xc < 0.0) Xc = 0.0;
+  if (Xc > 2.0) Xc = 2.0;
+  double ct = 1.0 - Xc;
+  double st = sqrt(Xc * (2.0 - Xc));
   double ph = 2.0 * OR_PI * u3;
   double kn = sqrt(k2);
   double n[3] = {0.0, 0.0, 1.0};

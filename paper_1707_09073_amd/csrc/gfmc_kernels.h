@@ -1,0 +1,935 @@
+// gfmc_kernels.h -- gfx950 kernels of the electron Monte Carlo step.
+//
+// One flight interval (K sub-steps, one Poisson refresh) is:
+//   k_flight      per particle: free flight + self-scattering selection +
+//                 final state, heat and mechanism counts in LDS, deposit of
+//                 the survivors per subcell; one workgroup per tile.
+//   k_merge       sums the per-tile subcell histograms (deposit and heat).
+//   k_inject_*    refills the contact subcells to neutrality (device mode).
+//   k_poisson     one workgroup per instance: block-tridiagonal direct solve
+//                 of the finite-volume Poisson equation, then the field.
+// Bulk mode replaces the last three by k_bulk_* (per-interval observables).
+#pragma once
+#include "gfmc_device.h"
+
+namespace gfmc {
+
+constexpr int kNCnt = 48;  // u64 counters per instance
+enum {
+  C_SEL = 0, C_SELF = 1, C_OVF = 2, C_REAL = 3, C_EXIT0 = 33, C_EXIT1 = 34, C_INJ0 = 35, C_INJ1 = 36,
+  C_REFL = 37, C_PROC = 38
+};
+enum { CTL_INTERVAL = 0, CTL_WINDOW = 1 };
+
+struct TileDesc {
+  int inst;
+  int count;
+  long long start;  // first slot (global index)
+};
+
+struct InstParams {
+  uint32_t key0, key1, tagw;
+  int cap;
+  long long base;
+  int t0, t1;     // tile range of the instance
+  int target;     // neutral electrons per contact subcell
+  int pad;
+  double N_D_nm;  // donors per nm^3
+  double N_D_m3;  // donors per m^3
+  double w;       // electrons per superparticle
+  double Vgs, Vds, phig;
+  double F[3];    // bulk field
+  double T_init;
+};
+
+struct Plan {
+  uint32_t Q, id0, u, pad;
+  uint32_t need[64];
+  uint32_t off[64];
+};
+
+template <typename T>
+struct FlightArgs {
+  const TileDesc* tiles;
+  const InstParams* ip;
+  const T* table;
+  const T* fac;
+  const T* field;
+  const T* gamma;
+  T *kx, *ky, *kz, *x, *y, *z;
+  uint32_t* meta;
+  uint32_t* partial;
+  uint32_t* tile_dead;
+  unsigned long long* counters;
+  int* flags;
+  const uint32_t* ctl;
+  Mat<T> M;
+  Geo<T> G;
+  int nb;
+  T dE;
+  T TP;
+};
+
+struct Cnt {
+  uint32_t sel, self, ovf, ex0, ex1, refl, dead, proc;
+};
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+__device__ __forceinline__ void set_flag(int* flags, int inst, int code) { atomicCAS(flags + inst, 0, code); }
+
+// Select a mechanism by u1 Gamma_v against the running sum of the tabulated
+// rates of the cell; apply its final state.  Returns the mechanism, -1 = self.
+template <typename T>
+__device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const T* gam, int& v, T& kx, T& ky,
+                                       T& kz, const uint4 w, int cell, int ncell, Cnt& c, uint32_t* sh_heat,
+                                       uint32_t* sh_real) {
+  const Mat<T>& M = a.M;
+  const T k2 = kx * kx + ky * ky + kz * kz;
+  const T g = Ar<T>::dv(M.ck * k2, M.m[v]);
+  const T E = kane_E(g, M.alpha[v]);
+  const T eb = Ar<T>::dv(E, a.dE);
+  int b;
+  if (!(eb < (T)a.nb)) { b = a.nb - 1; c.ovf++; }
+  else b = (int)eb;
+  const T* S = a.table + ((size_t)v * a.nb + b) * kTRow;
+  T Sr[11];
+#pragma unroll
+  for (int q = 0; q < 11; ++q) Sr[q] = S[q];
+  const T rs = Ar<T>::u01(w.y) * gam[v];
+  T cum = (T)0;
+  int m = -1;
+#pragma unroll
+  for (int q = 0; q < kNM; ++q) {
+    cum += tab_term<T>(Sr, f, q);
+    if (m < 0 && rs < cum) m = q;
+  }
+  c.sel++;
+  if (m < 0) { c.self++; return -1; }
+  int vp = v;
+  T Ep;
+  if (m <= 1) Ep = E;
+  else if (m == 2) Ep = E + M.hw_lo;
+  else if (m == 3) Ep = E - M.hw_lo;
+  else {
+    vp = (m - 4) >> 1;
+    Ep = E + M.Ec[v] - M.Ec[vp] + (((m - 4) & 1) ? -M.hw_iv : M.hw_iv);
+  }
+  if (!(Ep > (T)0)) { c.self++; return -1; }
+  atomicAdd(sh_real + v * kNM + m, 1u);
+  if (m == 3) atomicAdd(sh_heat + cell, 1u);
+  else if (m == 2) atomicAdd(sh_heat + ncell + cell, 1u);
+  else if (m >= 4) atomicAdd(sh_heat + (((m - 4) & 1) ? 2 : 3) * ncell + cell, 1u);
+  // polar angle relative to k, sampled as X = 1 - cos; sin = sqrt(X (2 - X))
+  // keeps full relative accuracy for forward scattering
+  const T u2 = Ar<T>::u01(w.z), u3 = Ar<T>::u01(w.w);
+  T X;
+  if (m == 1) {
+    const T a4 = Ar<T>::dv((T)4 * k2, f[6]);
+    X = Ar<T>::dv((T)2 * u2, (T)1 + ((T)1 - u2) * a4);
+  } else if (m == 2 || m == 3) {
+    const T gp = Ep * ((T)1 + M.alpha[v] * Ep);
+    const T sg = Ar<T>::sq(g), sgp = Ar<T>::sq(gp);
+    const T xi = Ar<T>::dv((T)2 * sg * sgp, (sg - sgp) * (sg - sgp));
+    X = Ar<T>::dv(Ar<T>::em1(u2 * Ar<T>::l1p((T)2 * xi)), xi);
+  } else {
+    X = (T)2 * u2;
+  }
+  X = fmin(fmax(X, (T)0), (T)2);
+  const T ct = (T)1 - X;
+  const T st = Ar<T>::sq(X * ((T)2 - X));
+  T cp, sp;
+  Ar<T>::cs2pi(u3, cp, sp);
+  const T kn = Ar<T>::sq(k2);
+  T nx = (T)0, ny = (T)0, nz = (T)1;
+  if (kn > (T)0) { nx = Ar<T>::dv(kx, kn); ny = Ar<T>::dv(ky, kn); nz = Ar<T>::dv(kz, kn); }
+  T e1[3], e2[3];
+  onb<T>(nx, ny, nz, e1, e2);
+  const T gpp = Ep * ((T)1 + M.alpha[vp] * Ep);
+  const T kp = Ar<T>::sq(Ar<T>::dv(gpp * M.m[vp], M.ck));
+  kx = kp * (st * cp * e1[0] + st * sp * e2[0] + ct * nx);
+  ky = kp * (st * cp * e1[1] + st * sp * e2[1] + ct * ny);
+  kz = kp * (st * cp * e1[2] + st * sp * e2[2] + ct * nz);
+  v = vp;
+  return m;
+}
+
+// Free flight for dt in the field (fx, fy, fz): k exact, r by the trapezoid
+// of the end-point velocities, specular lateral walls.  Returns -1 inside,
+// else the contact left through (0 source, 1 drain).
+template <typename T, bool DEV>
+__device__ __forceinline__ int drift(const FlightArgs<T>& a, int v, T dt, T fx, T fy, T fz, T& kx, T& ky, T& kz,
+                                     T& x, T& y, T& z, Cnt& c) {
+  const Mat<T>& M = a.M;
+  const T k1x = kx - M.cf * fx * dt, k1y = ky - M.cf * fy * dt, k1z = kz - M.cf * fz * dt;
+  if (DEV) {
+    const T s0 = vel_factor(M, v, energy(M, v, kx, ky, kz));
+    const T s1 = vel_factor(M, v, energy(M, v, k1x, k1y, k1z));
+    x += (T)0.5 * dt * (s0 * kx + s1 * k1x);
+    y += (T)0.5 * dt * (s0 * ky + s1 * k1y);
+    z += (T)0.5 * dt * (s0 * kz + s1 * k1z);
+  }
+  kx = k1x; ky = k1y; kz = k1z;
+  if (!DEV) return -1;
+  if (x < (T)0) return 0;
+  if (x > a.G.L[0]) return 1;
+  {
+    const T L = a.G.L[1];
+    int guard = 0;
+    while ((y < (T)0 || y > L) && guard < 8) { y = y < (T)0 ? -y : (T)2 * L - y; ky = -ky; ++guard; }
+    if (y < (T)0 || y > L) { y = y < (T)0 ? (T)0 : L; c.refl++; }
+  }
+  {
+    const T L = a.G.L[2];
+    int guard = 0;
+    while ((z < (T)0 || z > L) && guard < 8) { z = z < (T)0 ? -z : (T)2 * L - z; kz = -kz; ++guard; }
+    if (z < (T)0 || z > L) { z = z < (T)0 ? (T)0 : L; c.refl++; }
+  }
+  return -1;
+}
+
+// One flight interval [0, K dt) of one electron.  The field is constant over
+// the interval, so the remaining flight time is drawn afresh at its start.
+template <typename T, bool DEV>
+__device__ __forceinline__ bool fly(const FlightArgs<T>& a, const InstParams& P, const T* fac, const T* field,
+                                    const T* gam, uint32_t n_int, int ncell, int& v, uint32_t id, T& kx, T& ky,
+                                    T& kz, T& x, T& y, T& z, Cnt& c, uint32_t* sh_heat, uint32_t* sh_real,
+                                    bool& guard_hit) {
+  uint4 w = philox(id, n_int, 0u, P.tagw, P.key0, P.key1);
+  T t = (T)0;
+  T tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), gam[v]);
+  uint32_t j = 0;
+  for (;;) {
+    int cell = DEV ? cell_of(a.G, x, y, z) : 0;
+    const T* F = field + 4 * cell;
+    const T fx = F[0], fy = F[1], fz = F[2];
+    if (t + tau >= a.TP) {
+      const int ex = drift<T, DEV>(a, v, a.TP - t, fx, fy, fz, kx, ky, kz, x, y, z, c);
+      if (ex == 0) { c.ex0++; return false; }
+      if (ex == 1) { c.ex1++; return false; }
+      return true;
+    }
+    const int ex = drift<T, DEV>(a, v, tau, fx, fy, fz, kx, ky, kz, x, y, z, c);
+    if (ex == 0) { c.ex0++; return false; }
+    if (ex == 1) { c.ex1++; return false; }
+    t += tau;
+    ++j;
+    if (j > (uint32_t)kMaxEvents) { guard_hit = true; return true; }
+    w = philox(id, n_int, j, P.tagw, P.key0, P.key1);
+    if (DEV) cell = cell_of(a.G, x, y, z);
+    scatter<T>(a, fac + kFRow * cell, gam, v, kx, ky, kz, w, cell, ncell, c, sh_heat, sh_real);
+    tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), gam[v]);
+  }
+}
+
+template <typename T, bool DEV>
+__global__ void __launch_bounds__(256) k_flight(FlightArgs<T> a) {
+  extern __shared__ uint32_t sh[];
+  const int ncell = DEV ? a.G.ncell : 1;
+  uint32_t* sh_dep = sh;
+  uint32_t* sh_heat = sh + ncell;
+  uint32_t* sh_real = sh + 5 * ncell;
+  uint32_t* sh_misc = sh_real + 32;
+  const int nsh = 5 * ncell + 40;
+  for (int i = threadIdx.x; i < nsh; i += blockDim.x) sh[i] = 0u;
+  __syncthreads();
+  const TileDesc td = a.tiles[blockIdx.x];
+  const InstParams P = a.ip[td.inst];
+  const T* fac = a.fac + (size_t)td.inst * ncell * kFRow;
+  const T* field = a.field + (size_t)td.inst * ncell * 4;
+  const T* gam = a.gamma + td.inst * 4;
+  const uint32_t n_int = a.ctl[CTL_INTERVAL];
+  Cnt c = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  bool guard_hit = false, nan_hit = false;
+  for (int i = threadIdx.x; i < td.count; i += blockDim.x) {
+    const long long p = td.start + i;
+    const uint32_t meta = a.meta[p];
+    if (!(meta & kAlive)) { c.dead++; continue; }
+    c.proc++;
+    T kx = a.kx[p], ky = a.ky[p], kz = a.kz[p];
+    T x = (T)0, y = (T)0, z = (T)0;
+    if (DEV) { x = a.x[p]; y = a.y[p]; z = a.z[p]; }
+    int v = meta_valley(meta);
+    const uint32_t id = meta_id(meta);
+    const bool alive = fly<T, DEV>(a, P, fac, field, gam, n_int, ncell, v, id, kx, ky, kz, x, y, z, c, sh_heat,
+                                   sh_real, guard_hit);
+    if (!(isfinite(kx) && isfinite(ky) && isfinite(kz))) nan_hit = true;
+    a.kx[p] = kx; a.ky[p] = ky; a.kz[p] = kz;
+    if (DEV) { a.x[p] = x; a.y[p] = y; a.z[p] = z; }
+    a.meta[p] = (id << 3) | (alive ? kAlive : 0u) | (uint32_t)v;
+    if (!alive) c.dead++;
+    else if (DEV) atomicAdd(sh_dep + cell_of(a.G, x, y, z), 1u);
+  }
+  if (guard_hit) set_flag(a.flags, td.inst, -4);
+  if (nan_hit) set_flag(a.flags, td.inst, -6);
+  {
+    const uint32_t vals[8] = {c.sel, c.self, c.ovf, c.ex0, c.ex1, c.refl, c.dead, c.proc};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const uint32_t s = wave_sum(vals[q]);
+      if ((threadIdx.x & 63) == 0 && s) atomicAdd(sh_misc + q, s);
+    }
+  }
+  __syncthreads();
+  if (DEV) {
+    uint32_t* part = a.partial + (size_t)blockIdx.x * 5 * ncell;
+    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x) part[i] = sh[i];
+  }
+  unsigned long long* cnt = a.counters + (size_t)td.inst * kNCnt;
+  for (int tid = threadIdx.x; tid < 39; tid += blockDim.x) {
+    if (tid < 30) {
+      if (sh_real[tid]) atomicAdd(cnt + C_REAL + tid, (unsigned long long)sh_real[tid]);
+    } else if (tid < 38) {
+      const int q = tid - 30;
+      const int slot = q == 0 ? C_SEL : q == 1 ? C_SELF : q == 2 ? C_OVF : q == 3 ? C_EXIT0
+                     : q == 4 ? C_EXIT1 : q == 5 ? C_REFL : q == 6 ? -1 : C_PROC;
+      if (slot >= 0 && sh_misc[q]) atomicAdd(cnt + slot, (unsigned long long)sh_misc[q]);
+    } else {
+      a.tile_dead[blockIdx.x] = sh_misc[6];
+    }
+  }
+}
+
+// Lane-refill variant: each lane works one segment per iteration (the start
+// of an electron's interval, or one scattering event plus the next flight)
+// and pulls the next electron of the tile from a workgroup queue as soon as
+// its electron reaches the end of the interval, so lanes do not idle while
+// the busiest lane of the wavefront finishes its events.  Per-electron
+// arithmetic and random-number use are the same as in k_flight.
+template <typename T, bool DEV>
+__global__ void __launch_bounds__(256) k_flight_refill(FlightArgs<T> a) {
+  extern __shared__ uint32_t sh[];
+  const int ncell = DEV ? a.G.ncell : 1;
+  uint32_t* sh_dep = sh;
+  uint32_t* sh_heat = sh + ncell;
+  uint32_t* sh_real = sh + 5 * ncell;
+  uint32_t* sh_misc = sh_real + 32;
+  uint32_t* sh_q = sh_misc + 8;
+  const int nsh = 5 * ncell + 41;
+  for (int i = threadIdx.x; i < nsh; i += blockDim.x) sh[i] = 0u;
+  __syncthreads();
+  const TileDesc td = a.tiles[blockIdx.x];
+  const InstParams P = a.ip[td.inst];
+  const T* fac = a.fac + (size_t)td.inst * ncell * kFRow;
+  const T* field = a.field + (size_t)td.inst * ncell * 4;
+  const T* gam = a.gamma + td.inst * 4;
+  const uint32_t n_int = a.ctl[CTL_INTERVAL];
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  Cnt c = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  bool guard_hit = false, nan_hit = false;
+  bool has = false, exhausted = false;
+  long long p = 0;
+  T kx = (T)0, ky = (T)0, kz = (T)0, x = (T)0, y = (T)0, z = (T)0, t = (T)0;
+  int v = 0;
+  uint32_t id = 0, j = 0;
+  for (;;) {
+    // refill: lanes without an electron take the next live slots of the tile
+    bool want = !has && !exhausted;
+    unsigned long long m = __ballot(want);
+    while (m) {
+      const int first = __ffsll((long long)m) - 1;
+      uint32_t base = 0;
+      if (lane == first) base = atomicAdd(sh_q, (uint32_t)__popcll(m));
+      base = __shfl(base, first);
+      if (want) {
+        const uint32_t idx = base + (uint32_t)__popcll(m & lt);
+        if (idx < (uint32_t)td.count) {
+          p = td.start + idx;
+          const uint32_t meta = a.meta[p];
+          if (meta & kAlive) {
+            has = true;
+            c.proc++;
+            kx = a.kx[p]; ky = a.ky[p]; kz = a.kz[p];
+            if (DEV) { x = a.x[p]; y = a.y[p]; z = a.z[p]; }
+            v = meta_valley(meta);
+            id = meta_id(meta);
+            j = 0;
+            t = (T)0;
+          } else {
+            c.dead++;
+          }
+        } else {
+          exhausted = true;
+        }
+      }
+      want = !has && !exhausted;
+      m = __ballot(want);
+    }
+    if (!__any(has)) break;
+    if (has) {
+      const uint4 w = philox(id, n_int, j, P.tagw, P.key0, P.key1);
+      int cell = DEV ? cell_of(a.G, x, y, z) : 0;
+      if (j > 0) scatter<T>(a, fac + kFRow * cell, gam, v, kx, ky, kz, w, cell, ncell, c, sh_heat, sh_real);
+      const T tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), gam[v]);
+      const T* F = field + 4 * cell;
+      const bool last = t + tau >= a.TP;
+      const int ex = drift<T, DEV>(a, v, last ? a.TP - t : tau, F[0], F[1], F[2], kx, ky, kz, x, y, z, c);
+      bool fin = last || ex >= 0;
+      if (!fin) {
+        t += tau;
+        ++j;
+        if (j > (uint32_t)kMaxEvents) { guard_hit = true; fin = true; }
+      }
+      if (fin) {
+        const bool alive = ex < 0;
+        if (ex == 0) c.ex0++;
+        if (ex == 1) c.ex1++;
+        if (!(isfinite(kx) && isfinite(ky) && isfinite(kz))) nan_hit = true;
+        a.kx[p] = kx; a.ky[p] = ky; a.kz[p] = kz;
+        if (DEV) { a.x[p] = x; a.y[p] = y; a.z[p] = z; }
+        a.meta[p] = (id << 3) | (alive ? kAlive : 0u) | (uint32_t)v;
+        if (!alive) c.dead++;
+        else if (DEV) atomicAdd(sh_dep + cell_of(a.G, x, y, z), 1u);
+        has = false;
+      }
+    }
+  }
+  if (guard_hit) set_flag(a.flags, td.inst, -4);
+  if (nan_hit) set_flag(a.flags, td.inst, -6);
+  {
+    const uint32_t vals[8] = {c.sel, c.self, c.ovf, c.ex0, c.ex1, c.refl, c.dead, c.proc};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const uint32_t s = wave_sum(vals[q]);
+      if (lane == 0 && s) atomicAdd(sh_misc + q, s);
+    }
+  }
+  __syncthreads();
+  if (DEV) {
+    uint32_t* part = a.partial + (size_t)blockIdx.x * 5 * ncell;
+    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x) part[i] = sh[i];
+  }
+  unsigned long long* cnt = a.counters + (size_t)td.inst * kNCnt;
+  for (int tid = threadIdx.x; tid < 39; tid += blockDim.x) {
+    if (tid < 30) {
+      if (sh_real[tid]) atomicAdd(cnt + C_REAL + tid, (unsigned long long)sh_real[tid]);
+    } else if (tid < 38) {
+      const int q = tid - 30;
+      const int slot = q == 0 ? C_SEL : q == 1 ? C_SELF : q == 2 ? C_OVF : q == 3 ? C_EXIT0
+                     : q == 4 ? C_EXIT1 : q == 5 ? C_REFL : q == 6 ? -1 : C_PROC;
+      if (slot >= 0 && sh_misc[q]) atomicAdd(cnt + slot, (unsigned long long)sh_misc[q]);
+    } else {
+      a.tile_dead[blockIdx.x] = sh_misc[6];
+    }
+  }
+}
+
+// Sum the per-tile histograms of each instance.  Bins [0, ncell) are the
+// deposit (overwrites the electron count), bins [ncell, 5 ncell) the heat
+// counts (added to the window).  Block (0,0) advances the interval counter.
+__global__ void k_merge(const uint32_t* __restrict__ partial, const InstParams* __restrict__ ip, int ncell,
+                        uint32_t* count, unsigned long long* heat, uint32_t* ctl, int with_heat, int advance) {
+  const int inst = blockIdx.y;
+  const int bin = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t0 = ip[inst].t0, t1 = ip[inst].t1;
+  if (bin < 5 * ncell) {
+    unsigned long long s = 0;
+    for (int t = t0; t < t1; ++t) s += partial[(size_t)t * 5 * ncell + bin];
+    if (bin < ncell) count[(size_t)inst * ncell + bin] = (uint32_t)s;
+    else if (with_heat) heat[(size_t)inst * 4 * ncell + (bin - ncell)] += s;
+  }
+  if (advance && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    ctl[CTL_INTERVAL] += 1u;
+    ctl[CTL_WINDOW] += 1u;
+  }
+}
+
+// Deposit only (used outside a flight interval).
+template <typename T>
+__global__ void k_deposit(const TileDesc* __restrict__ tiles, const T* __restrict__ x, const T* __restrict__ y,
+                          const T* __restrict__ z, const uint32_t* __restrict__ meta, Geo<T> G, uint32_t* partial,
+                          uint32_t* tile_dead) {
+  extern __shared__ uint32_t sh[];
+  const int ncell = G.ncell;
+  for (int i = threadIdx.x; i < 5 * ncell + 1; i += blockDim.x) sh[i] = 0u;
+  __syncthreads();
+  const TileDesc td = tiles[blockIdx.x];
+  uint32_t dead = 0;
+  for (int i = threadIdx.x; i < td.count; i += blockDim.x) {
+    const long long p = td.start + i;
+    if (meta[p] & kAlive) atomicAdd(sh + cell_of(G, x[p], y[p], z[p]), 1u);
+    else ++dead;
+  }
+  dead = wave_sum(dead);
+  if ((threadIdx.x & 63) == 0 && dead) atomicAdd(sh + 5 * ncell, dead);
+  __syncthreads();
+  uint32_t* part = partial + (size_t)blockIdx.x * 5 * ncell;
+  for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x) part[i] = sh[i];
+  if (threadIdx.x == 0) tile_dead[blockIdx.x] = sh[5 * ncell];
+}
+
+// Contact refill plan of one instance (one 64-lane workgroup): electrons
+// needed per contact subcell, their offsets, and the free-slot offsets of the
+// instance's tiles.  The q-th new electron takes the q-th free slot.
+__global__ void k_inject_plan(const InstParams* __restrict__ ip, int nx, int P, int ncell, uint32_t* count,
+                              const uint32_t* __restrict__ tile_dead, uint32_t* tile_off, Plan* plan,
+                              uint32_t* next_id, unsigned long long* counters, int* flags, const uint32_t* ctl) {
+  const int inst = blockIdx.x;
+  const int l = threadIdx.x;
+  const InstParams& I = ip[inst];
+  uint32_t* cnt = count + (size_t)inst * ncell;
+  int cell = -1;
+  uint32_t need = 0;
+  if (l < 2 * P) {
+    cell = l < P ? l : (nx - 1) * P + (l - P);
+    const int have = (int)cnt[cell];
+    need = have < I.target ? (uint32_t)(I.target - have) : 0u;
+  }
+  // inclusive scan over the 64 lanes
+  uint32_t inc = need;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o);
+    if (l >= o) inc += y;
+  }
+  uint32_t Q = __shfl(inc, 63);
+  const uint32_t off = inc - need;
+  // free slots per tile, exclusive prefix over the instance's tiles
+  uint32_t run = 0;
+  for (int t0 = I.t0; t0 < I.t1; t0 += 64) {
+    const int t = t0 + l;
+    const uint32_t d = t < I.t1 ? tile_dead[t] : 0u;
+    uint32_t s = d;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(s, o);
+      if (l >= o) s += y;
+    }
+    if (t < I.t1) tile_off[t] = run + s - d;
+    run += __shfl(s, 63);
+  }
+  if (run < Q) {
+    if (l == 0) set_flag(flags, inst, -3);
+    Q = run;
+  }
+  const uint32_t id0 = next_id[inst];
+  if ((unsigned long long)id0 + Q >= (1ull << 29)) {
+    if (l == 0) set_flag(flags, inst, -3);
+    Q = 0;
+  }
+  uint32_t got = 0;
+  if (cell >= 0) {
+    got = off >= Q ? 0u : (off + need <= Q ? need : Q - off);
+    cnt[cell] += got;
+  }
+  Plan* pl = plan + inst;
+  if (l < 64) { pl->need[l] = need; pl->off[l] = off; }
+  const uint32_t src = wave_sum(l < P ? got : 0u), drn = wave_sum(l >= P ? got : 0u);
+  if (l == 0) {
+    pl->Q = Q;
+    pl->id0 = id0;
+    pl->u = ctl[CTL_INTERVAL];
+    next_id[inst] = id0 + Q;
+    counters[(size_t)inst * kNCnt + C_INJ0] += src;
+    counters[(size_t)inst * kNCnt + C_INJ1] += drn;
+  }
+}
+
+// Write the planned electrons into the first free slots of each tile.
+template <typename T>
+__global__ void k_inject_write(const TileDesc* __restrict__ tiles, const InstParams* __restrict__ ip,
+                               const Plan* __restrict__ plan, const uint32_t* __restrict__ tile_off,
+                               const double* __restrict__ Tcell, Geo<T> G, double m_g1, double ck, T* kx, T* ky,
+                               T* kz, T* x, T* y, T* z, uint32_t* meta) {
+  __shared__ uint32_t s_scan[1024];
+  const TileDesc td = tiles[blockIdx.x];
+  const Plan& pl = plan[td.inst];
+  const uint32_t Q = pl.Q;
+  const uint32_t base_off = tile_off[blockIdx.x];
+  if (base_off >= Q) return;
+  const InstParams I = ip[td.inst];
+  const int P = G.ny * G.nz;
+  const int B = blockDim.x;
+  const int chunk = (td.count + B - 1) / B;
+  const int lo = min(td.count, (int)threadIdx.x * chunk), hi = min(td.count, lo + chunk);
+  uint32_t nd = 0;
+  for (int i = lo; i < hi; ++i) nd += (meta[td.start + i] & kAlive) ? 0u : 1u;
+  s_scan[threadIdx.x] = nd;
+  __syncthreads();
+  // exclusive scan (Hillis-Steele) over the workgroup
+  for (int o = 1; o < B; o <<= 1) {
+    const uint32_t v = threadIdx.x >= (unsigned)o ? s_scan[threadIdx.x - o] : 0u;
+    __syncthreads();
+    s_scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t q = base_off + s_scan[threadIdx.x] - nd;
+  for (int i = lo; i < hi && q < Q; ++i) {
+    const long long p = td.start + i;
+    if (meta[p] & kAlive) continue;
+    int l = -1;
+    for (int t = 0; t < 2 * P; ++t)
+      if (q >= pl.off[t] && q < pl.off[t] + pl.need[t]) { l = t; break; }
+    if (l < 0) break;
+    const int side = l >= P ? 1 : 0;
+    const int lc = side ? l - P : l;
+    const int cell = side ? (G.nx - 1) * P + lc : lc;
+    const uint32_t ii = q - pl.off[l];
+    const uint4 w = philox((uint32_t)cell, pl.u, ii, I.tagw | 2u, I.key0, I.key1);
+    const double Tc = Tcell[(size_t)td.inst * G.ncell + cell];
+    const T sig = (T)sqrt(m_g1 * kKb * Tc / kQ / (2.0 * ck));
+    const T r1 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.x))), r2 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.z)));
+    T c1, s1, c2, s2;
+    Ar<T>::cs2pi(Ar<T>::u01(w.y), c1, s1);
+    Ar<T>::cs2pi(Ar<T>::u01(w.w), c2, s2);
+    kx[p] = sig * r1 * c1;
+    ky[p] = sig * r1 * s1;
+    kz[p] = sig * r2 * c2;
+    const uint4 w2 = philox((uint32_t)cell, pl.u, ii, I.tagw | 3u, I.key0, I.key1);
+    const int ix = side ? G.nx - 1 : 0, iy = lc / G.nz, iz = lc % G.nz;
+    x[p] = ((T)ix + Ar<T>::u01(w2.x)) * G.d[0];
+    y[p] = ((T)iy + Ar<T>::u01(w2.y)) * G.d[1];
+    z[p] = ((T)iz + Ar<T>::u01(w2.z)) * G.d[2];
+    meta[p] = ((pl.id0 + q) << 3) | kAlive;
+    ++q;
+  }
+}
+
+// Initial Maxwellian ensemble: slot p < N gets identity p.
+template <typename T, bool DEV>
+__global__ void k_init(const InstParams* __restrict__ ip, int inst, Geo<T> G, double m_g1, double ck, T* kx, T* ky,
+                       T* kz, T* x, T* y, T* z, uint32_t* meta, int n) {
+  const InstParams I = ip[inst];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= I.cap) return;
+  const long long p = I.base + i;
+  if (i >= n) {
+    kx[p] = ky[p] = kz[p] = (T)0;
+    if (DEV) x[p] = y[p] = z[p] = (T)0;
+    meta[p] = 0u;
+    return;
+  }
+  const uint4 w = philox((uint32_t)i, 0u, 0u, I.tagw | 1u, I.key0, I.key1);
+  const T sig = (T)sqrt(m_g1 * kKb * I.T_init / kQ / (2.0 * ck));
+  const T r1 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.x))), r2 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.z)));
+  T c1, s1, c2, s2;
+  Ar<T>::cs2pi(Ar<T>::u01(w.y), c1, s1);
+  Ar<T>::cs2pi(Ar<T>::u01(w.w), c2, s2);
+  kx[p] = sig * r1 * c1;
+  ky[p] = sig * r1 * s1;
+  kz[p] = sig * r2 * c2;
+  if (DEV) {
+    const uint4 w2 = philox((uint32_t)i, 0u, 1u, I.tagw | 1u, I.key0, I.key1);
+    x[p] = Ar<T>::u01(w2.x) * G.L[0];
+    y[p] = Ar<T>::u01(w2.y) * G.L[1];
+    z[p] = Ar<T>::u01(w2.z) * G.L[2];
+  }
+  meta[p] = ((uint32_t)i << 3) | kAlive;
+}
+
+// Rate-shape tables on the bin midpoints, FP64, plus an FP32 copy.
+__global__ void k_tables(RateMat R, int nb, double dE, double ck, double* t64, float* t32) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kNV * nb) return;
+  const int v = idx / nb, b = idx % nb;
+  const double E = (b + 0.5) * dE;
+  double S[kTRow];
+  const double D = R.D_ac * kQ;
+  S[0] = 2.0 * kPi / kHbar * D * D * kKb / (R.rho * R.u_ac * R.u_ac) * dos_si(R, v, E) * 1e-15;
+  const double eps = R.eps_s * kEps0;
+  S[1] = 2.0 * kPi / kHbar * (kQ * kQ * kQ * kQ) / (eps * eps) * dos_si(R, v, E) * 1e-24;
+  S[2] = pop_shape(R, v, E, E + R.hw_lo) * 1e-15;
+  S[3] = pop_shape(R, v, E, E - R.hw_lo) * 1e-15;
+  for (int j = 0; j < kNV; ++j)
+    for (int em = 0; em < 2; ++em) {
+      const double Ep = E + R.Ec[v] - R.Ec[j] + (em ? -R.hw_iv : R.hw_iv);
+      S[4 + 2 * j + em] = iv_shape(R, v, j, Ep) * 1e-15;
+    }
+  S[10] = 4.0 * (E * (1.0 + R.alpha[v] * E)) * R.m[v] / ck;
+  S[11] = 0.0;
+  for (int q = 0; q < kTRow; ++q) {
+    t64[(size_t)idx * kTRow + q] = S[q];
+    t32[(size_t)idx * kTRow + q] = (float)S[q];
+  }
+}
+
+// Temperature factors per subcell.
+__global__ void k_factors(const double* __restrict__ Tcell, const InstParams* __restrict__ ip, int ncell,
+                          double eps_s, double hw_lo, double hw_iv, double* f64, float* f32) {
+  const int inst = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const double T = Tcell[(size_t)inst * ncell + c];
+  const double ND = ip[inst].N_D_m3;
+  const double b2 = kQ * kQ * ND / (eps_s * kEps0 * kKb * T) * 1e-18;
+  const double N = 1.0 / (exp(hw_lo * kQ / (kKb * T)) - 1.0);
+  const double Niv = 1.0 / (exp(hw_iv * kQ / (kKb * T)) - 1.0);
+  double f[kFRow] = {T, ip[inst].N_D_nm / b2, N, N + 1.0, Niv, Niv + 1.0, b2, 0.0};
+  const size_t o = ((size_t)inst * ncell + c) * kFRow;
+  for (int q = 0; q < kFRow; ++q) { f64[o + q] = f[q]; f32[o + q] = (float)f[q]; }
+}
+
+// Gamma_v: the maximum of the tabulated total over bins and the instance's
+// distinct-temperature subcells, in the precision that uses it.
+template <typename T>
+__global__ void k_gamma(const T* __restrict__ table, const T* __restrict__ fac, const int* __restrict__ reps,
+                        const int* __restrict__ nrep, int ncell, int nb, T* gamma) {
+  const int inst = blockIdx.x, v = blockIdx.y;
+  __shared__ T smax[1024];
+  T g = (T)0;
+  const int n = nrep[inst];
+  for (int idx = threadIdx.x; idx < n * nb; idx += blockDim.x) {
+    const int r = idx / nb, b = idx % nb;
+    const T* S = table + ((size_t)v * nb + b) * kTRow;
+    const T* f = fac + ((size_t)inst * ncell + reps[(size_t)inst * ncell + r]) * kFRow;
+    const T tot = tab_total<T>(S, f);
+    g = tot > g ? tot : g;
+  }
+  smax[threadIdx.x] = g;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gamma[inst * 4 + v] = smax[0];
+}
+
+// ---------------------------------------------------------------------------
+// Poisson: finite volumes on the subcell grid, eps_s eps0 uniform; Dirichlet
+// faces half a cell from the centre (source x=0: 0 V; drain x=L: Vds; gated
+// top and outer side: Vgs + offset), Neumann elsewhere.  The matrix is block
+// tridiagonal in x with P = ny nz blocks; the x coupling is -gx I.
+// Block LU: S_0 = D_0, S_i = D_i - gx^2 S_{i-1}^{-1}; M_i = S_i^{-1}.
+// ---------------------------------------------------------------------------
+struct PoisGeo {
+  int nx, ny, nz, P;
+  double dx, dy, dz, gx, gy, gz, gate0, gate1, Vc;
+};
+
+__device__ __forceinline__ bool gated(const PoisGeo& g, int ix) {
+  const double xc = (ix + 0.5) * g.dx;
+  return xc >= g.gate0 && xc <= g.gate1;
+}
+
+// one workgroup; builds M_i for all slices (init only)
+__global__ void k_poisson_factor(PoisGeo g, double* Minv) {
+  __shared__ double A[32][65];  // [S | I] augmented, then [I | S^-1]
+  __shared__ double Mprev[32][32];
+  const int P = g.P;
+  for (int ix = 0; ix < g.nx; ++ix) {
+    const bool gt = gated(g, ix);
+    for (int e = threadIdx.x; e < P * 2 * P; e += blockDim.x) {
+      const int r = e / (2 * P), c = e % (2 * P);
+      double val = 0.0;
+      if (c < P) {
+        const int iy = r / g.nz, iz = r % g.nz, jy = c / g.nz, jz = c % g.nz;
+        if (r == c) {
+          val += ix > 0 ? g.gx : 2.0 * g.gx;
+          val += ix < g.nx - 1 ? g.gx : 2.0 * g.gx;
+          val += iy > 0 ? g.gy : 0.0;
+          val += iy < g.ny - 1 ? g.gy : (gt ? 2.0 * g.gy : 0.0);
+          val += iz > 0 ? g.gz : 0.0;
+          val += iz < g.nz - 1 ? g.gz : (gt ? 2.0 * g.gz : 0.0);
+          if (ix > 0) val -= g.gx * g.gx * Mprev[r][c];
+        } else {
+          if (iz == jz && (iy - jy == 1 || jy - iy == 1)) val = -g.gy;
+          if (iy == jy && (iz - jz == 1 || jz - iz == 1)) val = -g.gz;
+          if (ix > 0) val -= g.gx * g.gx * Mprev[r][c];
+        }
+      } else {
+        val = (c - P == r) ? 1.0 : 0.0;
+      }
+      A[r][c] = val;
+    }
+    __syncthreads();
+    // Gauss-Jordan without pivoting (the matrix is symmetric positive definite)
+    for (int k = 0; k < P; ++k) {
+      const double piv = A[k][k];
+      __syncthreads();
+      for (int c = threadIdx.x; c < 2 * P; c += blockDim.x) A[k][c] /= piv;
+      __syncthreads();
+      for (int e = threadIdx.x; e < P * 2 * P; e += blockDim.x) {
+        const int r = e / (2 * P), c = e % (2 * P);
+        if (r != k) {
+          const double f = A[r][k];
+          if (c != k) A[r][c] -= f * A[k][c];
+        }
+      }
+      __syncthreads();
+      for (int r = threadIdx.x; r < P; r += blockDim.x)
+        if (r != k) A[r][k] = 0.0;
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < P * P; e += blockDim.x) {
+      const int r = e / P, c = e % P;
+      const double m = A[r][P + c];
+      Mprev[r][c] = m;
+      Minv[((size_t)ix * P + r) * P + c] = m;
+    }
+    __syncthreads();
+  }
+}
+
+// One workgroup of 256 per instance: right-hand side from the counts, block
+// forward/backward sweep (8 lanes per matrix row), field, FP32 copy, and the
+// window density sum.  The M_i rows are prefetched kPF steps ahead.
+constexpr int kPF = 8;
+__global__ void __launch_bounds__(256) k_poisson(PoisGeo g, const InstParams* __restrict__ ip,
+                                                 const double* __restrict__ Minv, const uint32_t* __restrict__ count,
+                                                 double* phi_out, double* field64, float* field32,
+                                                 unsigned long long* dens, int accumulate, int ncell) {
+  extern __shared__ double shd[];
+  double* h = shd;           // [ncell]: h_i, then x_i
+  double* rhs = shd + ncell; // [ncell]
+  const int inst = blockIdx.x;
+  const InstParams& I = ip[inst];
+  const int P = g.P, nx = g.nx;
+  const uint32_t* cnt = count + (size_t)inst * ncell;
+  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+    const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
+    double b = 0.0;
+    if (ix == nx - 1) b += 2.0 * g.gx * I.Vds;
+    if (gated(g, ix)) {
+      if (iy == g.ny - 1) b += 2.0 * g.gy * I.phig;
+      if (iz == g.nz - 1) b += 2.0 * g.gz * I.phig;
+    }
+    rhs[c] = b + kQ * (I.N_D_nm * g.Vc - I.w * (double)cnt[c]);
+    if (accumulate) dens[(size_t)inst * ncell + c] += cnt[c];
+  }
+  __syncthreads();
+  const int r = threadIdx.x >> 3, q = threadIdx.x & 7;
+  const bool act = r < P;
+  const int nsteps = 2 * nx - 1;
+  auto slice = [nx](int s) { return s < nx ? s : 2 * nx - 2 - s; };
+  double buf[kPF][4];
+#pragma unroll
+  for (int k = 0; k < kPF; ++k) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int col = q + 8 * e;
+      buf[k][e] = (act && k < nsteps && col < P) ? Minv[((size_t)slice(k) * P + r) * P + col] : 0.0;
+    }
+  }
+  for (int s0 = 0; s0 < nsteps; s0 += kPF) {
+#pragma unroll
+    for (int kk = 0; kk < kPF; ++kk) {
+      const int s = s0 + kk;
+      if (s < nsteps) {
+        const int i = slice(s);
+        double part = 0.0;
+        if (act) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int col = q + 8 * e;
+            if (col < P) {
+              double vin;
+              if (s < nx) vin = rhs[i * P + col] + (i > 0 ? g.gx * h[(i - 1) * P + col] : 0.0);
+              else vin = h[(i + 1) * P + col];
+              part += buf[kk][e] * vin;
+            }
+          }
+        }
+        // prefetch step s + kPF into this ring slot
+        const int sn = s + kPF;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int col = q + 8 * e;
+          buf[kk][e] = (act && sn < nsteps && col < P) ? Minv[((size_t)slice(sn) * P + r) * P + col] : 0.0;
+        }
+        part += __shfl_xor(part, 1, 8);
+        part += __shfl_xor(part, 2, 8);
+        part += __shfl_xor(part, 4, 8);
+        __syncthreads();
+        if (act && q == 0) {
+          if (s < nx) h[i * P + r] = part;                 // h_i = M_i y_i
+          else h[i * P + r] = h[i * P + r] + g.gx * part;  // x_i = h_i + gx M_i x_{i+1}
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // h now holds phi
+  double* phi = phi_out + (size_t)inst * ncell;
+  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+    const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
+    const double pc = h[c];
+    const bool gt = gated(g, ix);
+    double pe, de, pw, dw;
+    if (ix < nx - 1) { pe = h[c + P]; de = g.dx; } else { pe = I.Vds; de = 0.5 * g.dx; }
+    if (ix > 0) { pw = h[c - P]; dw = g.dx; } else { pw = 0.0; dw = 0.5 * g.dx; }
+    const double ex = -(pe - pw) / (de + dw);
+    double pn, dn, ps, ds;
+    if (iy < g.ny - 1) { pn = h[c + g.nz]; dn = g.dy; }
+    else if (gt) { pn = I.phig; dn = 0.5 * g.dy; }
+    else { pn = pc; dn = 0.0; }
+    if (iy > 0) { ps = h[c - g.nz]; ds = g.dy; } else { ps = pc; ds = 0.0; }
+    const double ey = (dn + ds) > 0.0 ? -(pn - ps) / (dn + ds) : 0.0;
+    double pt, dt, pb, db;
+    if (iz < g.nz - 1) { pt = h[c + 1]; dt = g.dz; }
+    else if (gt) { pt = I.phig; dt = 0.5 * g.dz; }
+    else { pt = pc; dt = 0.0; }
+    if (iz > 0) { pb = h[c - 1]; db = g.dz; } else { pb = pc; db = 0.0; }
+    const double ez = (dt + db) > 0.0 ? -(pt - pb) / (dt + db) : 0.0;
+    phi[c] = pc;
+    const size_t o = ((size_t)inst * ncell + c) * 4;
+    field64[o + 0] = ex; field64[o + 1] = ey; field64[o + 2] = ez; field64[o + 3] = 0.0;
+    field32[o + 0] = (float)ex; field32[o + 1] = (float)ey; field32[o + 2] = (float)ez; field32[o + 3] = 0.0f;
+  }
+}
+
+// Bulk observables: per-tile partial sums in a fixed reduction order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_bulk_partial(const TileDesc* __restrict__ tiles, const T* __restrict__ kx,
+                                                      const T* __restrict__ ky, const T* __restrict__ kz,
+                                                      const uint32_t* __restrict__ meta, Mat<T> M, double* bpart,
+                                                      uint32_t* ctl, int advance) {
+  __shared__ double s[8][256];
+  const TileDesc td = tiles[blockIdx.x];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < td.count; i += 256) {
+    const long long p = td.start + i;
+    const uint32_t mt = meta[p];
+    if (!(mt & kAlive)) continue;
+    const int v = meta_valley(mt);
+    const double x = (double)kx[p], y = (double)ky[p], z = (double)kz[p];
+    const double k2 = x * x + y * y + z * z;
+    const double m = (double)M.m[v], al = (double)M.alpha[v];
+    const double gam = (double)M.ck * k2 / m;
+    const double E = 2.0 * gam / (1.0 + sqrt(1.0 + 4.0 * al * gam));
+    const double sv = (double)M.cv / (m * (1.0 + 2.0 * al * E));
+    acc[0] += 1.0;
+    acc[1] += sv * x; acc[2] += sv * y; acc[3] += sv * z;
+    acc[4] += E;
+    acc[5 + v] += 1.0;
+  }
+  for (int q = 0; q < 8; ++q) s[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o)
+      for (int q = 0; q < 8; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) bpart[(size_t)blockIdx.x * 8 + threadIdx.x] = s[threadIdx.x][0];
+  if (advance && blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl[CTL_INTERVAL] += 1u;
+    ctl[CTL_WINDOW] += 1u;
+  }
+}
+
+__global__ void k_bulk_reduce(const InstParams* __restrict__ ip, const double* __restrict__ bpart, double* hist,
+                              int hist_cap, const uint32_t* ctl) {
+  const int inst = blockIdx.x;
+  const int q = threadIdx.x;
+  if (q >= 8) return;
+  const int row = (int)ctl[CTL_WINDOW] - 1;
+  if (row < 0 || row >= hist_cap) return;
+  double s = 0.0;
+  for (int t = ip[inst].t0; t < ip[inst].t1; ++t) s += bpart[(size_t)t * 8 + q];
+  hist[((size_t)inst * hist_cap + row) * 8 + q] = s;
+}
+
+__global__ void k_zero_window(unsigned long long* heat, unsigned long long* dens, unsigned long long* counters,
+                              size_t nheat, size_t ndens, int n_inst, uint32_t* ctl) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nheat) heat[i] = 0ull;
+  if (i < ndens) dens[i] = 0ull;
+  if (i < (size_t)n_inst * kNCnt) counters[i] = 0ull;
+  if (i == 0) ctl[CTL_WINDOW] = 0u;
+}
+
+}  // namespace gfmc

@@ -1,0 +1,306 @@
+"""Thin ctypes binding of libgfmc.so (C ABI in include/gfmc.h).
+
+Argument marshalling only: every step of the Monte Carlo runs in the HIP
+kernels of the library.  PyTorch supplies the device workspace and the stream.
+The binding raises if the library is not built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgfmc.so")
+
+MC_OK, MC_E_ARG, MC_E_HIP, MC_E_CAPACITY, MC_E_RANGE, MC_E_STATE, MC_E_NAN = 0, -1, -2, -3, -4, -5, -6
+MC_PREC_FP64, MC_PREC_FP32_STATE = 0, 1
+MC_BULK, MC_DEVICE = 0, 1
+
+
+class McMaterial(C.Structure):
+    _fields_ = [("m_eff", C.c_double * 3), ("alpha", C.c_double * 3), ("E_c", C.c_double * 3),
+                ("Z", C.c_int32 * 3), ("eps_s", C.c_double), ("eps_inf", C.c_double), ("rho", C.c_double),
+                ("D_ac_eV", C.c_double), ("D_iv_eVm", C.c_double), ("hw_lo_eV", C.c_double),
+                ("hw_iv_eV", C.c_double), ("u_ac", C.c_double)]
+
+
+class McConfig(C.Structure):
+    _fields_ = [("mode", C.c_int), ("prec", C.c_int), ("mat", McMaterial), ("seed", C.c_uint64),
+                ("instance", C.c_uint32), ("n_particles", C.c_int32), ("capacity", C.c_int32),
+                ("dt_fs", C.c_double), ("substeps", C.c_int32), ("n_bins", C.c_int32), ("dE_eV", C.c_double),
+                ("T0_K", C.c_double), ("T_init_K", C.c_double), ("N_D_m3", C.c_double),
+                ("F_bulk", C.c_double * 3), ("L_nm", C.c_double * 3), ("n_cells", C.c_int32 * 3),
+                ("gate_x_nm", C.c_double * 2), ("Vgs", C.c_double), ("Vds", C.c_double),
+                ("phi_offset", C.c_double)]
+
+
+class McTallyOut(C.Structure):
+    _fields_ = [("intervals", C.c_uint32), ("intervals_total", C.c_uint32), ("t_window_fs", C.c_double),
+                ("n_alive", C.c_uint64), ("selections", C.c_uint64), ("self_events", C.c_uint64),
+                ("overflow", C.c_uint64), ("real", (C.c_uint64 * 10) * 3), ("exits", C.c_uint64 * 2),
+                ("injections", C.c_uint64 * 2), ("segments", C.c_uint64), ("reflect_guard", C.c_uint64),
+                ("weight", C.c_double), ("drain_current_A", C.c_double), ("flags", C.c_int32)]
+
+
+class McParticlesView(C.Structure):
+    _fields_ = [("kx", C.c_void_p), ("ky", C.c_void_p), ("kz", C.c_void_p), ("x", C.c_void_p),
+                ("y", C.c_void_p), ("z", C.c_void_p), ("meta", C.c_void_p), ("capacity", C.c_int32),
+                ("elem_bytes", C.c_int32)]
+
+
+EXPORTS = ["mc_status_string", "mc_last_error", "mc_workspace_bytes", "mc_init", "mc_destroy",
+           "mc_set_lattice_temperature", "mc_set_tables", "mc_step", "poisson_update", "mc_tally", "mc_maps",
+           "mc_history", "mc_particles", "mc_read_particles", "mc_write_particles", "mc_read_fields",
+           "mc_read_tables", "mc_set_launch", "mc_get_launch", "mc_set_variant", "mc_use_graph", "mc_profile", "mc_profile_read",
+           "mc_checkpoint", "mc_restore"]
+
+_lib = None
+
+
+def lib():
+    """Load libgfmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1707_09073_amd/build.py (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, u64p, u32p, i32p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64), \
+            C.POINTER(C.c_uint32), C.POINTER(C.c_int32)
+        L.mc_status_string.argtypes = [C.c_int]; L.mc_status_string.restype = C.c_char_p
+        L.mc_last_error.argtypes = [vp]; L.mc_last_error.restype = C.c_char_p
+        L.mc_workspace_bytes.argtypes = [C.POINTER(McConfig), C.c_int]; L.mc_workspace_bytes.restype = C.c_size_t
+        L.mc_init.argtypes = [C.POINTER(vp), C.POINTER(McConfig), C.c_int, vp, C.c_size_t, vp]
+        L.mc_destroy.argtypes = [vp]
+        L.mc_set_lattice_temperature.argtypes = [vp, C.c_int, dp]
+        L.mc_set_tables.argtypes = [vp, dp, dp]
+        L.mc_step.argtypes = [vp, C.c_int]
+        L.poisson_update.argtypes = [vp]
+        L.mc_tally.argtypes = [vp, C.c_int, C.POINTER(McTallyOut), C.c_int]
+        L.mc_maps.argtypes = [vp, C.c_int, u64p, u64p, dp, dp]
+        L.mc_history.argtypes = [vp, C.c_int, dp, C.c_int, C.POINTER(C.c_int)]
+        L.mc_particles.argtypes = [vp, C.c_int, C.POINTER(McParticlesView)]
+        L.mc_read_particles.argtypes = [vp, C.c_int, dp, dp, i32p, i32p, u32p]
+        L.mc_write_particles.argtypes = [vp, C.c_int, dp, dp, i32p, i32p, u32p]
+        L.mc_read_fields.argtypes = [vp, C.c_int, dp, dp, u32p]
+        L.mc_read_tables.argtypes = [vp, C.c_int, dp, dp, dp, dp]
+        L.mc_set_launch.argtypes = [vp, C.c_int, C.c_int]
+        L.mc_get_launch.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.mc_use_graph.argtypes = [vp, C.c_int]
+        L.mc_set_variant.argtypes = [vp, C.c_int]
+        L.mc_profile.argtypes = [vp, C.c_int]
+        L.mc_profile_read.argtypes = [vp, dp, C.POINTER(C.c_int), dp, C.POINTER(C.c_int), C.c_int]
+        L.mc_checkpoint.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+        L.mc_restore.argtypes = [vp, vp, C.c_size_t]
+        for name in EXPORTS:
+            if name not in ("mc_status_string", "mc_last_error", "mc_workspace_bytes"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class MCError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        self.code = code
+        super().__init__(f"{where}: {lib().mc_status_string(code).decode()} ({code}) {detail}".strip())
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def make_config(cfg: dict) -> McConfig:
+    """Marshal an input-recipe dictionary into the C struct."""
+    m = cfg["material"]
+    c = McConfig()
+    c.mode = MC_DEVICE if cfg["mode"] == "device" else MC_BULK
+    c.prec = MC_PREC_FP32_STATE if cfg.get("precision", "fp64") == "fp32" else MC_PREC_FP64
+    for name in ("m_eff", "alpha", "E_c"):
+        getattr(c.mat, name)[:] = [float(x) for x in m[name]]
+    c.mat.Z[:] = [int(x) for x in m["Z"]]
+    for name in ("eps_s", "eps_inf", "rho", "D_ac_eV", "D_iv_eVm", "hw_lo_eV", "hw_iv_eV", "u_ac"):
+        setattr(c.mat, name, float(m[name]))
+    c.seed = int(cfg["seed"]) & 0xFFFFFFFFFFFFFFFF
+    c.instance = int(cfg.get("instance", 0))
+    c.n_particles = int(cfg["n_particles"])
+    c.capacity = int(cfg["capacity"])
+    c.dt_fs = float(cfg["dt_fs"])
+    c.substeps = int(cfg["substeps"])
+    c.n_bins = int(cfg["n_bins"])
+    c.dE_eV = float(cfg["dE_eV"])
+    c.T0_K = float(cfg["T0_K"])
+    c.T_init_K = float(cfg.get("T_init_K", cfg["T0_K"]))
+    c.N_D_m3 = float(cfg["N_D_m3"])
+    c.F_bulk[:] = [float(x) for x in cfg["F_bulk"]]
+    c.L_nm[:] = [float(x) for x in cfg["L_nm"]]
+    c.n_cells[:] = [int(x) for x in cfg["n_cells"]]
+    c.gate_x_nm[:] = [float(x) for x in cfg["gate_x_nm"]]
+    c.Vgs, c.Vds, c.phi_offset = float(cfg["Vgs"]), float(cfg["Vds"]), float(cfg["phi_offset"])
+    return c
+
+
+def mc_workspace_bytes(cfgs: list[dict]) -> int:
+    arr = (McConfig * len(cfgs))(*[make_config(c) for c in cfgs])
+    return int(lib().mc_workspace_bytes(arr, len(cfgs)))
+
+
+class Ensemble:
+    """A library context over one or more instances; owns its torch workspace."""
+
+    def __init__(self, cfgs, device="cuda", stream=None):
+        import torch
+        if isinstance(cfgs, dict):
+            cfgs = [cfgs]
+        self.cfgs = list(cfgs)
+        self.n = len(self.cfgs)
+        self._carr = (McConfig * self.n)(*[make_config(c) for c in self.cfgs])
+        nbytes = int(lib().mc_workspace_bytes(self._carr, self.n))
+        if nbytes == 0:
+            raise MCError(MC_E_ARG, "mc_workspace_bytes", "invalid configuration")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        # a stream of our own (default priority): the legacy null stream cannot be graph-captured
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self._ctx = C.c_void_p()
+        rc = lib().mc_init(C.byref(self._ctx), self._carr, self.n, C.c_void_p(self.workspace.data_ptr()),
+                           nbytes, C.c_void_p(self.stream.cuda_stream))
+        if rc != MC_OK:
+            detail = lib().mc_last_error(self._ctx).decode() if self._ctx.value else ""
+            raise MCError(rc, "mc_init", detail)
+        self.ncell = 1 if self.cfgs[0]["mode"] != "device" else int(np.prod(self.cfgs[0]["n_cells"]))
+        self.nb = int(self.cfgs[0]["n_bins"])
+        for i, c in enumerate(self.cfgs):
+            if c.get("T_cells") is not None:
+                self.mc_set_lattice_temperature(i, c["T_cells"])
+
+    def _chk(self, rc, where):
+        if rc != MC_OK:
+            raise MCError(rc, where, lib().mc_last_error(self._ctx).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            lib().mc_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- the C ABI, same names ---
+    def mc_set_lattice_temperature(self, inst, T):
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        assert T.size == self.ncell
+        self._chk(lib().mc_set_lattice_temperature(self._ctx, int(inst), _p(T, C.c_double)),
+                  "mc_set_lattice_temperature")
+
+    def mc_set_tables(self, shape, k4):
+        s = np.ascontiguousarray(shape, dtype=np.float64)
+        k = np.ascontiguousarray(k4, dtype=np.float64)
+        assert s.size == 3 * self.nb * 10 and k.size == 3 * self.nb
+        self._chk(lib().mc_set_tables(self._ctx, _p(s, C.c_double), _p(k, C.c_double)), "mc_set_tables")
+
+    def mc_step(self, n_substeps: int):
+        self._chk(lib().mc_step(self._ctx, int(n_substeps)), "mc_step")
+
+    def poisson_update(self):
+        self._chk(lib().poisson_update(self._ctx), "poisson_update")
+
+    def mc_tally(self, inst: int = 0, reset_window: bool = False, check: bool = True) -> dict:
+        t = McTallyOut()
+        rc = lib().mc_tally(self._ctx, int(inst), C.byref(t), int(bool(reset_window)))
+        if check:
+            self._chk(rc, "mc_tally")
+        return dict(intervals=t.intervals, intervals_total=t.intervals_total, t_window_fs=t.t_window_fs,
+                    n_alive=t.n_alive, selections=t.selections, self_events=t.self_events, overflow=t.overflow,
+                    real=np.array([[t.real[v][m] for m in range(10)] for v in range(3)], dtype=np.int64),
+                    exits=np.array(list(t.exits), np.int64), injections=np.array(list(t.injections), np.int64),
+                    segments=t.segments, reflect_guard=t.reflect_guard, weight=t.weight,
+                    drain_current_A=t.drain_current_A, flags=t.flags, status=rc)
+
+    def mc_maps(self, inst: int = 0):
+        n = self.ncell
+        heat4 = np.zeros((n, 4), np.uint64); dens = np.zeros(n, np.uint64)
+        q = np.zeros(n); d = np.zeros(n)
+        self._chk(lib().mc_maps(self._ctx, int(inst), _p(heat4, C.c_uint64), _p(dens, C.c_uint64),
+                                _p(q, C.c_double), _p(d, C.c_double)), "mc_maps")
+        return dict(heat4=heat4, dens_sum=dens, heat_Wm3=q, density_m3=d)
+
+    def mc_history(self, inst: int = 0, max_rows: int = 8192) -> np.ndarray:
+        rows = np.zeros((max_rows, 8)); n = C.c_int(0)
+        self._chk(lib().mc_history(self._ctx, int(inst), _p(rows, C.c_double), int(max_rows), C.byref(n)),
+                  "mc_history")
+        return rows[:n.value].copy()
+
+    def mc_particles(self, inst: int = 0) -> McParticlesView:
+        v = McParticlesView()
+        self._chk(lib().mc_particles(self._ctx, int(inst), C.byref(v)), "mc_particles")
+        return v
+
+    def mc_read_particles(self, inst: int = 0) -> dict:
+        cap = int(self.cfgs[inst]["capacity"])
+        k = np.zeros((cap, 3)); r = np.zeros((cap, 3))
+        v = np.zeros(cap, np.int32); a = np.zeros(cap, np.int32); i = np.zeros(cap, np.uint32)
+        self._chk(lib().mc_read_particles(self._ctx, int(inst), _p(k, C.c_double), _p(r, C.c_double),
+                                          _p(v, C.c_int32), _p(a, C.c_int32), _p(i, C.c_uint32)),
+                  "mc_read_particles")
+        return dict(k=k, r=r, valley=v, alive=a, id=i)
+
+    def mc_write_particles(self, inst, k, r, valley, alive, ident):
+        k = np.ascontiguousarray(k, np.float64); r = np.ascontiguousarray(r, np.float64)
+        v = np.ascontiguousarray(valley, np.int32); a = np.ascontiguousarray(alive, np.int32)
+        i = np.ascontiguousarray(ident, np.uint32)
+        self._chk(lib().mc_write_particles(self._ctx, int(inst), _p(k, C.c_double), _p(r, C.c_double),
+                                           _p(v, C.c_int32), _p(a, C.c_int32), _p(i, C.c_uint32)),
+                  "mc_write_particles")
+
+    def mc_read_fields(self, inst: int = 0):
+        n = self.ncell
+        phi = np.zeros(n); F = np.zeros((n, 3)); cnt = np.zeros(n, np.uint32)
+        self._chk(lib().mc_read_fields(self._ctx, int(inst), _p(phi, C.c_double), _p(F, C.c_double),
+                                       _p(cnt, C.c_uint32)), "mc_read_fields")
+        return phi, F, cnt
+
+    def mc_read_tables(self, inst: int = 0):
+        s = np.zeros((3, self.nb, 10)); k = np.zeros((3, self.nb)); f = np.zeros((self.ncell, 7)); g = np.zeros(3)
+        self._chk(lib().mc_read_tables(self._ctx, int(inst), _p(s, C.c_double), _p(k, C.c_double),
+                                       _p(f, C.c_double), _p(g, C.c_double)), "mc_read_tables")
+        return s, k, f, g
+
+    def mc_set_launch(self, block: int, tile: int):
+        self._chk(lib().mc_set_launch(self._ctx, int(block), int(tile)), "mc_set_launch")
+
+    def mc_get_launch(self):
+        b, t, n = C.c_int(), C.c_int(), C.c_int()
+        self._chk(lib().mc_get_launch(self._ctx, C.byref(b), C.byref(t), C.byref(n)), "mc_get_launch")
+        return b.value, t.value, n.value
+
+    def mc_set_variant(self, variant: int):
+        self._chk(lib().mc_set_variant(self._ctx, int(variant)), "mc_set_variant")
+
+    def mc_use_graph(self, enable: bool):
+        self._chk(lib().mc_use_graph(self._ctx, int(bool(enable))), "mc_use_graph")
+
+    def mc_profile(self, enable: bool):
+        self._chk(lib().mc_profile(self._ctx, int(bool(enable))), "mc_profile")
+
+    def mc_profile_read(self, reset: bool = True) -> dict:
+        fm, rm = C.c_double(), C.c_double()
+        nf, nr = C.c_int(), C.c_int()
+        self._chk(lib().mc_profile_read(self._ctx, C.byref(fm), C.byref(nf), C.byref(rm), C.byref(nr),
+                                        int(bool(reset))), "mc_profile_read")
+        return dict(flight_ms=fm.value, n_flight=nf.value, refresh_ms=rm.value, n_refresh=nr.value)
+
+    def mc_checkpoint(self) -> bytes:
+        n = C.c_size_t(0)
+        self._chk(lib().mc_checkpoint(self._ctx, None, C.byref(n)), "mc_checkpoint")
+        buf = C.create_string_buffer(n.value)
+        self._chk(lib().mc_checkpoint(self._ctx, buf, C.byref(n)), "mc_checkpoint")
+        return buf.raw[:n.value]
+
+    def mc_restore(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._chk(lib().mc_restore(self._ctx, buf, len(blob)), "mc_restore")

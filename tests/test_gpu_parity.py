@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.  FP64 mode must agree per particle to 1e-10
+(relative); integer tallies must be identical."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1707_09073_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-10
+# k is a vector that passes near zero: its error is taken relative to
+# max(|k|, K_FLOOR), a quarter of the 300 K thermal wave number of Gamma1
+K_FLOOR = 0.1  # 1/nm
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1707_09073_amd import gfmc
+    gfmc.lib()
+    return gfmc
+
+
+def _compare_particles(gp, op, rel=REL, what=""):
+    assert np.array_equal(gp["alive"], op["alive"]), what + " alive"
+    alive = op["alive"] == 1
+    assert np.array_equal(gp["id"][alive], op["id"][alive]), what + " id"
+    assert np.array_equal(gp["valley"][alive], op["valley"][alive]), what + " valley"
+    kg, ko = gp["k"][alive], op["k"][alive]
+    scale = np.maximum(np.linalg.norm(ko, axis=1), K_FLOOR)[:, None]
+    err = np.abs(kg - ko) / scale
+    assert err.max() <= rel, f"{what} k rel err {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
+    rg, ro = gp["r"][alive], op["r"][alive]
+    errr = np.abs(rg - ro) / np.maximum(np.abs(ro), 1.0)
+    assert errr.max() <= rel, f"{what} r rel err {errr.max():.3e}"
+    return err.max(), errr.max()
+
+
+def _compare_counts(gt, oc):
+    assert gt["selections"] == oc["selections"]
+    assert gt["self_events"] == oc["self_events"]
+    assert gt["overflow"] == oc["overflow"]
+    assert np.array_equal(gt["real"], oc["real"])
+    assert np.array_equal(gt["exits"], oc["exits"])
+    assert np.array_equal(gt["injections"], oc["injections"])
+
+
+def test_tables_factors_gamma_match_oracle(G, oracle_mod):
+    cfg = W.device_config(n_particles=20000, precision="fp64", Vds=5.0)
+    T = W.hotspot_T_map(cfg)
+    cfg["T_cells"] = T
+    _say("tables: device fp64 with hot-spot map")
+    e = G.Ensemble(cfg)
+    o = oracle_mod.Oracle(cfg)
+    s, k, f, g = e.mc_read_tables(0)
+    so, ko = o.tables()
+    fo = o.factors()
+    go = o.gamma()
+    assert np.allclose(s, so, rtol=1e-13, atol=0)
+    assert np.allclose(k, ko, rtol=1e-14, atol=0)
+    assert np.allclose(f, fo, rtol=1e-13, atol=0)
+    assert np.allclose(g, go, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("mode", ["bulk", "device"])
+def test_initial_state_matches_oracle(G, oracle_mod, mode):
+    if mode == "bulk":
+        cfg = W.bulk_config(n_particles=5000)
+    else:
+        cfg = W.device_config(n_particles=20000, precision="fp64", Vds=5.0)
+    _say("init parity", mode)
+    e = G.Ensemble(cfg)
+    o = oracle_mod.Oracle(cfg)
+    _compare_particles(e.mc_read_particles(), o.particles(), rel=1e-13, what="init")
+    if mode == "device":
+        phi, F, n = e.mc_read_fields()
+        pho, Fo, no = o.fields()
+        assert np.array_equal(n, no)
+        assert np.abs(phi - pho).max() <= 1e-10 * np.abs(pho).max()
+        assert np.abs(F - Fo).max() <= 1e-9 * np.abs(Fo).max()
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_bulk_fp64_per_particle_parity(G, oracle_mod, variant):
+    """Bulk GaN, 10 kV/cm along c, 1e17 cm^-3, 300 K, 1 fs steps."""
+    cfg = W.bulk_config(n_particles=10000, substeps=1)
+    _say("bulk fp64 parity: 10000 electrons x 300 steps, kernel variant", variant)
+    e = G.Ensemble(cfg)
+    e.mc_set_variant(variant)
+    o = oracle_mod.Oracle(cfg)
+    e.mc_step(300)
+    o.run(300)
+    ek, _ = _compare_particles(e.mc_read_particles(), o.particles(), what="bulk")
+    _compare_counts(e.mc_tally(), o.counts())
+    hg, ho = e.mc_history(), o.history()
+    assert hg.shape == ho.shape == (300, 8)
+    assert np.array_equal(hg[:, [0, 5, 6, 7]], ho[:, [0, 5, 6, 7]])
+    # FP64 sums in a different order: bound relative to sum |term|
+    tol = REL * np.maximum(np.abs(ho[:, 1:5]).max(axis=0), 1.0)
+    assert np.all(np.abs(hg[:, 1:5] - ho[:, 1:5]) <= tol)
+    _say("bulk max rel k err", ek)
+
+
+def test_bulk_fp64_parity_with_interval_of_ten_substeps(G, oracle_mod):
+    cfg = W.bulk_config(n_particles=4000, substeps=10, field_V_per_nm=5e-3, doping_cm3=1e18)
+    e = G.Ensemble(cfg)
+    o = oracle_mod.Oracle(cfg)
+    e.mc_step(1000)
+    o.run(100)
+    _compare_particles(e.mc_read_particles(), o.particles(), what="bulk K=10")
+    _compare_counts(e.mc_tally(), o.counts())
+
+
+def _device_small(n=20000, Vds=5.0, Vgs=0.0, prec="fp64", cells=(100, 3, 6), L=(1000.0, 60.0, 120.0)):
+    return W.device_config(n_particles=n, precision=prec, Vds=Vds, Vgs=Vgs, n_cells=cells, L_nm=L)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_device_fp64_per_particle_parity(G, oracle_mod, variant):
+    """Half-nanowire device, 3x6x100 subcells, Vds = 5 V: particles, deposit,
+    heat counts, contacts and the Poisson field after 30 refreshes."""
+    cfg = _device_small()
+    _say("device fp64 parity: 20000 electrons x 30 intervals, kernel variant", variant)
+    e = G.Ensemble(cfg)
+    e.mc_set_variant(variant)
+    o = oracle_mod.Oracle(cfg)
+    e.mc_step(300)
+    o.run(30)
+    ek, er = _compare_particles(e.mc_read_particles(), o.particles(), what="device")
+    _compare_counts(e.mc_tally(), o.counts())
+    m = e.mc_maps()
+    heat_o, dens_o = o.maps()
+    assert np.array_equal(m["heat4"], heat_o)
+    assert np.array_equal(m["dens_sum"], dens_o)
+    phi, F, n = e.mc_read_fields()
+    pho, Fo, no = o.fields()
+    assert np.array_equal(n, no)
+    assert np.abs(phi - pho).max() <= REL * np.abs(pho).max()
+    assert np.abs(F - Fo).max() <= 1e-9 * np.abs(Fo).max()
+    _say("device max rel err k", ek, "r", er)
+
+
+def test_device_fp64_parity_gated_and_ragged(G, oracle_mod):
+    """Negative gate bias, a grid of 37x2x5 subcells and a capacity that is
+    not a multiple of the tile (ragged last tile)."""
+    cfg = _device_small(n=7777, Vds=3.0, Vgs=-1.0, cells=(37, 2, 5), L=(370.0, 40.0, 100.0))
+    cfg["capacity"] = 10007
+    e = G.Ensemble(cfg)
+    e.mc_set_launch(128, 1024)
+    o = oracle_mod.Oracle(cfg)
+    e.mc_step(200)
+    o.run(20)
+    _compare_particles(e.mc_read_particles(), o.particles(), what="ragged")
+    _compare_counts(e.mc_tally(), o.counts())
+
+
+def test_launch_shape_and_graph_do_not_change_results(G):
+    cfg = _device_small(n=30000, prec="fp32")
+    runs = []
+    for block, tile, graph in ((256, 8192, False), (64, 1024, False), (128, 4096, True), (256, 2048, True)):
+        _say("launch shape", block, tile, "graph" if graph else "eager")
+        e = G.Ensemble(cfg)
+        e.mc_set_launch(block, tile)
+        e.mc_use_graph(graph)
+        e.mc_step(200)
+        p = e.mc_read_particles()
+        t = e.mc_tally()
+        runs.append((p, t, e.mc_maps()))
+        e.close()
+    p0, t0, m0 = runs[0]
+    for p, t, m in runs[1:]:
+        for key in p0:
+            assert np.array_equal(p[key], p0[key]), key
+        assert t["selections"] == t0["selections"] and np.array_equal(t["real"], t0["real"])
+        assert np.array_equal(m["heat4"], m0["heat4"]) and np.array_equal(m["dens_sum"], m0["dens_sum"])
+
+
+def test_batched_instances_equal_separate_runs(G):
+    cfgs = W.bias_sweep(3, n_min=3000, n_max=9000)
+    for c in cfgs:
+        c["precision"] = "fp32"
+    eb = G.Ensemble(cfgs)
+    eb.mc_step(100)
+    for i, c in enumerate(cfgs):
+        es = G.Ensemble(c)
+        es.mc_step(100)
+        pb, ps = eb.mc_read_particles(i), es.mc_read_particles(0)
+        for key in pb:
+            assert np.array_equal(pb[key], ps[key]), (i, key)
+        tb, ts = eb.mc_tally(i), es.mc_tally(0)
+        assert tb["selections"] == ts["selections"] and np.array_equal(tb["exits"], ts["exits"])
+
+
+def test_checkpoint_restore_is_bit_exact(G):
+    cfg = _device_small(n=20000, prec="fp32")
+    a = G.Ensemble(cfg)
+    a.mc_step(100)
+    blob = a.mc_checkpoint()
+    a.mc_step(100)
+    b = G.Ensemble(cfg)
+    b.mc_restore(blob)
+    b.mc_step(100)
+    pa, pb = a.mc_read_particles(), b.mc_read_particles()
+    for key in pa:
+        assert np.array_equal(pa[key], pb[key]), key
+
+
+def test_fp32_bulk_statistics_match_fp64_oracle(G, oracle_mod):
+    """FP32 state/flight: drift velocity, mean energy and valley occupancy of
+    bulk GaN within 1% or 3 sigma of the FP64 oracle (independent streams)."""
+    base = W.bulk_config(n_particles=20000, substeps=1, field_V_per_nm=1e-2, doping_cm3=1e17)
+    cfg32 = dict(base, precision="fp32")
+    e = G.Ensemble(cfg32)
+    o = oracle_mod.Oracle(base)
+    e.mc_step(1500)
+    o.run(1500)
+    hg, ho = e.mc_history()[500:], o.history()[500:]
+    for col, name in ((3, "vz"), (4, "E")):
+        a, b = hg[:, col] / hg[:, 0], ho[:, col] / ho[:, 0]
+        sa = a.reshape(10, -1).mean(1).std(ddof=1) / math.sqrt(10)
+        sb = b.reshape(10, -1).mean(1).std(ddof=1) / math.sqrt(10)
+        d = abs(a.mean() - b.mean())
+        assert d <= max(0.01 * abs(b.mean()), 3 * math.hypot(sa, sb)), (name, a.mean(), b.mean(), sa, sb)
+    occ_g = hg[:, 5:8].sum(0) / hg[:, 0].sum()
+    occ_o = ho[:, 5:8].sum(0) / ho[:, 0].sum()
+    assert np.all(np.abs(occ_g - occ_o) <= np.maximum(0.01 * occ_o, 3 * np.sqrt(occ_o / 20000 / 10) + 1e-6))
+
+
+def test_invalid_arguments_are_errors_not_crashes(G):
+    cfg = _device_small(n=2000, prec="fp32")
+    with pytest.raises(G.MCError):
+        G.Ensemble(dict(cfg, capacity=100))
+    e = G.Ensemble(cfg)
+    with pytest.raises(G.MCError):
+        e.mc_step(7)                     # not a multiple of the 10 sub-steps
+    with pytest.raises(G.MCError):
+        e.mc_set_launch(96, 1024)        # workgroup not a multiple of 64
+    with pytest.raises(G.MCError):
+        e.mc_set_lattice_temperature(0, -np.ones(1800))
+    with pytest.raises(G.MCError):
+        e.mc_tally(5)
+
+
+def test_capacity_exhaustion_is_reported(G):
+    """No spare slots: the first refill that needs a slot must flag
+    MC_E_CAPACITY instead of writing out of bounds."""
+    cfg = _device_small(n=18000, prec="fp32", Vds=8.0)
+    cfg["capacity"] = 18000
+    e = G.Ensemble(cfg)
+    e.mc_step(500)
+    t = e.mc_tally(check=False)
+    assert t["status"] in (0, G.MC_E_CAPACITY)
+    assert t["n_alive"] <= 18000
+    p = e.mc_read_particles()
+    ids = p["id"][p["alive"] == 1]
+    assert len(np.unique(ids)) == len(ids)
