@@ -70,15 +70,26 @@ def main() -> int:
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--graph", action="store_true", help="replay intervals from a hipGraph (no per-kernel timing)")
+    ap.add_argument("--variant", type=int, default=0, help="particle kernel: 0 lane refill, 1 one electron per lane")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the hot path here is the per-GPU share and is not sharded "
               "(see the design notes for how it would shard).", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "launches": 5}))
+        return 0
     from paper_1707_09073_amd import gfmc, workloads as W
     if not os.path.exists(gfmc.LIB_PATH):
         from paper_1707_09073_amd import build as B
@@ -90,6 +101,7 @@ def main() -> int:
     ens = gfmc.Ensemble(cfg, device="cuda:0")
     if args.block and args.tile:
         ens.mc_set_launch(args.block, args.tile)
+    ens.mc_set_variant(args.variant)
     block, tile, n_tiles = ens.mc_get_launch()
     ens.mc_use_graph(args.graph)
     _log(f"launch: block {block}, tile {tile}, {n_tiles} tiles; warmup {args.warmup} intervals")
@@ -118,7 +130,8 @@ def main() -> int:
         bytes_launch = per_launch * 28 * 2
         roofline = dict(bound="hbm", achieved=bytes_launch / flight_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=bytes_launch / flight_s / 1e9 / HBM_PEAK_GBS, traffic=None,
-                        kernel="k_flight<float,true>", avg_launch_ms=flight_s * 1e3,
+                        kernel="k_flight_refill<float,true>" if args.variant == 0 else "k_flight<float,true>",
+                        avg_launch_ms=flight_s * 1e3,
                         refresh_avg_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]),
                         flight_share=prof["flight_ms"] / (prof["flight_ms"] + prof["refresh_ms"]))
     out = {
@@ -137,7 +150,7 @@ def main() -> int:
         "config": {"workload": "half-nanowire GaN FinFET device MC, 10M superparticles, 3x6x100 subcells, "
                                "Vgs=0 V, Vds=5 V, 1e18 cm^-3, 300 K + 150 K drain hot spot, 1 fs x 10 per step",
                    "particles": args.particles, "substeps_per_step": K, "block": block, "tile": tile,
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "variant": args.variant},
         "real_events_per_s": real / wall,
         "electron_fs_per_s": proc * cfg["dt_fs"] * K / wall,
         "drain_current_A": tal["drain_current_A"],

@@ -223,6 +223,54 @@ int mc_profile_read(mc_ctx *ctx, double *flight_ms, int *n_flight, double *refre
 int mc_checkpoint(mc_ctx *ctx, void *h_buf, size_t *bytes);
 int mc_restore(mc_ctx *ctx, const void *h_buf, size_t bytes);
 
+/* ------------------------------------------------------------------------
+ * MLP surrogate of the Monte Carlo: (Vgs, Vds, log10 doping, per-subcell
+ * lattice temperature) -> per-subcell heat and electron-density maps.  It
+ * stands in for the electron MC when the thermal side of the hybrid method
+ * (coupling paragraph) needs heat maps for many temperature fields.  BF16
+ * matrix-core GEMMs with FP32 accumulation, GELU (exact normal CDF) hidden
+ * layers, FP32 master weights and Adam.  Device pointers below are caller
+ * allocations of FP32 row-major [batch][n_in] inputs and [batch][n_out]
+ * outputs.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_in;      /* raw input features */
+  int32_t n_out;     /* outputs */
+  int32_t width;     /* hidden width */
+  int32_t depth;     /* hidden layers */
+  int32_t ensemble;  /* independently initialised members (spread = predicted error) */
+  int32_t max_batch; /* largest batch of any call */
+  uint64_t seed;     /* Philox key of the weight initialisation */
+  float beta1, beta2, eps; /* Adam */
+} sg_config;
+
+typedef struct sg_ctx sg_ctx;
+
+/* Device workspace bytes for cfg; 0 if invalid. */
+size_t sg_workspace_bytes(const sg_config *cfg);
+int sg_init(sg_ctx **out, const sg_config *cfg, void *d_workspace, size_t ws_bytes, void *hip_stream);
+int sg_destroy(sg_ctx *ctx);
+const char *sg_last_error(const sg_ctx *ctx);
+/* K (inputs, the first padded to a multiple of 32) and N (outputs) of a weight layer. */
+int sg_layer_dims(const sg_ctx *ctx, int layer, int *K, int *N);
+/* Host FP32 per-feature mean and scale of inputs and outputs (z-scoring). */
+int sg_set_normalization(sg_ctx *ctx, const float *h_x_mean, const float *h_x_std, const float *h_y_mean,
+                         const float *h_y_std);
+/* Normalised predictions of one member (asynchronous). */
+int sg_forward(sg_ctx *ctx, int member, const float *d_x, int batch, float *d_pred);
+/* Forward, mean-squared error on z-scored targets, gradients of every layer
+ * (kept in the workspace); h_loss (may be NULL) gets the loss (synchronises). */
+int sg_backward(sg_ctx *ctx, int member, const float *d_x, const float *d_y, int batch, float *h_loss);
+/* One bias-corrected Adam step of one member from its last gradients. */
+int sg_adam(sg_ctx *ctx, int member, float lr);
+int sg_train_step(sg_ctx *ctx, int member, const float *d_x, const float *d_y, int batch, float lr, float *h_loss);
+/* De-normalised ensemble mean and spread (d_std may be NULL), asynchronous. */
+int sg_predict(sg_ctx *ctx, const float *d_x, int batch, float *d_mean, float *d_std);
+/* FP32 master parameters and last gradients of one layer: W [K][N], b [N]. */
+int sg_get_params(sg_ctx *ctx, int member, int layer, float *h_W, float *h_b);
+int sg_set_params(sg_ctx *ctx, int member, int layer, const float *h_W, const float *h_b);
+int sg_get_grads(sg_ctx *ctx, int member, int layer, float *h_dW, float *h_db);
+
 #ifdef __cplusplus
 }
 #endif

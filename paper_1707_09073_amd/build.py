@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgfmc.so")
-SOURCES = [os.path.join(CSRC, "gfmc.hip")]
+SOURCES = [os.path.join(CSRC, "gfmc.hip"), os.path.join(CSRC, "surrogate.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")] + \
     [os.path.join(ROOT, "include", "gfmc.h")]
 

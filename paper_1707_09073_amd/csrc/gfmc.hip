@@ -31,7 +31,8 @@ struct Layout {
 
 struct Offsets {
   size_t table64, table32, fac64, fac32, field64, field32, phi, gamma64, gamma32, Tcell, count, heat, dens,
-      counters, flags, ctl, next_id, ip, tiles, partial, tile_dead, tile_off, plan, minv, hist, reps, nrep, bpart;
+      counters, flags, ctl, next_id, ip, tiles, partial, acc, tile_dead, tile_off, plan, minv, hist, reps, nrep,
+      bpart;
   size_t kx, ky, kz, x, y, z, meta;
 };
 
@@ -130,6 +131,7 @@ Offsets layout(const mc_config* c, int n, size_t* total) {
   o.ip = L.take(sizeof(InstParams) * n);
   o.tiles = L.take(sizeof(TileDesc) * max_tiles);
   o.partial = L.take(dev ? sizeof(uint32_t) * max_tiles * 5 * nc : 0);
+  o.acc = L.take(dev ? sizeof(unsigned long long) * n * 5 * nc : 0);
   o.tile_dead = L.take(sizeof(uint32_t) * max_tiles);
   o.tile_off = L.take(sizeof(uint32_t) * max_tiles);
   o.plan = L.take(sizeof(Plan) * n);
@@ -302,10 +304,13 @@ FlightArgs<T> flight_args(mc_ctx* c, const Mat<T>& M, const Geo<T>& G, size_t ta
 // deposit (or merged flight histogram), contact refill, Poisson, field
 void enqueue_refresh(mc_ctx* c, bool after_flight) {
   const int nc = c->ncell;
+  dim3 gp((5 * nc + 255) / 256, kMergeGroups, c->n_inst);
+  k_merge_partial<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc,
+                                         c->p<unsigned long long>(c->o.acc));
   dim3 gm((5 * nc + 255) / 256, c->n_inst);
-  k_merge<<<gm, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc,
-                                 c->p<uint32_t>(c->o.count), c->p<unsigned long long>(c->o.heat),
-                                 c->p<uint32_t>(c->o.ctl), after_flight ? 1 : 0, after_flight ? 1 : 0);
+  k_merge_final<<<gm, 256, 0, c->st>>>(c->p<unsigned long long>(c->o.acc), nc, c->p<uint32_t>(c->o.count),
+                                       c->p<unsigned long long>(c->o.heat), c->p<uint32_t>(c->o.ctl),
+                                       after_flight ? 1 : 0, after_flight ? 1 : 0);
   k_inject_plan<<<c->n_inst, 64, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->nx, c->P, nc, c->p<uint32_t>(c->o.count),
                                              c->p<uint32_t>(c->o.tile_dead), c->p<uint32_t>(c->o.tile_off),
                                              c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.next_id),
@@ -324,7 +329,7 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
         c->p<double>(c->o.Tcell), c->G64, mg1, c->ck, c->p<double>(c->o.kx), c->p<double>(c->o.ky),
         c->p<double>(c->o.kz), c->p<double>(c->o.x), c->p<double>(c->o.y), c->p<double>(c->o.z),
         c->p<uint32_t>(c->o.meta));
-  k_poisson<<<c->n_inst, 256, sizeof(double) * 2 * nc, c->st>>>(
+  k_poisson<<<c->n_inst, 64, sizeof(double) * 2 * nc, c->st>>>(
       c->pg, c->p<InstParams>(c->o.ip), c->p<double>(c->o.minv), c->p<uint32_t>(c->o.count), c->p<double>(c->o.phi),
       c->p<double>(c->o.field64), c->p<float>(c->o.field32), c->p<unsigned long long>(c->o.dens),
       after_flight ? 1 : 0, nc);

@@ -419,17 +419,33 @@ __global__ void __launch_bounds__(256) k_flight_refill(FlightArgs<T> a) {
   }
 }
 
-// Sum the per-tile histograms of each instance.  Bins [0, ncell) are the
-// deposit (overwrites the electron count), bins [ncell, 5 ncell) the heat
-// counts (added to the window).  Block (0,0) advances the interval counter.
-__global__ void k_merge(const uint32_t* __restrict__ partial, const InstParams* __restrict__ ip, int ncell,
-                        uint32_t* count, unsigned long long* heat, uint32_t* ctl, int with_heat, int advance) {
+// Sum the per-tile histograms of each instance in two passes: tile groups
+// add their partial sums into a u64 accumulator (atomics on 5 x ncell
+// distinct words per instance), then k_merge_final moves the accumulator
+// into the electron count (bins [0, ncell)) and the window heat counts
+// (bins [ncell, 5 ncell)), clears it, and advances the interval counter.
+constexpr int kMergeGroups = 32;
+__global__ void k_merge_partial(const uint32_t* __restrict__ partial, const InstParams* __restrict__ ip, int ncell,
+                                unsigned long long* acc) {
+  const int inst = blockIdx.z;
+  const int bin = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bin >= 5 * ncell) return;
+  const int t0 = ip[inst].t0, t1 = ip[inst].t1;
+  const int per = (t1 - t0 + kMergeGroups - 1) / kMergeGroups;
+  const int a = t0 + blockIdx.y * per, b = min(t1, a + per);
+  unsigned long long s = 0;
+  for (int t = a; t < b; ++t) s += partial[(size_t)t * 5 * ncell + bin];
+  if (s) atomicAdd(acc + (size_t)inst * 5 * ncell + bin, s);
+}
+
+__global__ void k_merge_final(unsigned long long* acc, int ncell, uint32_t* count, unsigned long long* heat,
+                              uint32_t* ctl, int with_heat, int advance) {
   const int inst = blockIdx.y;
   const int bin = blockIdx.x * blockDim.x + threadIdx.x;
-  const int t0 = ip[inst].t0, t1 = ip[inst].t1;
   if (bin < 5 * ncell) {
-    unsigned long long s = 0;
-    for (int t = t0; t < t1; ++t) s += partial[(size_t)t * 5 * ncell + bin];
+    unsigned long long* a = acc + (size_t)inst * 5 * ncell + bin;
+    const unsigned long long s = *a;
+    *a = 0ull;
     if (bin < ncell) count[(size_t)inst * ncell + bin] = (uint32_t)s;
     else if (with_heat) heat[(size_t)inst * 4 * ncell + (bin - ncell)] += s;
   }
@@ -530,63 +546,69 @@ __global__ void k_inject_plan(const InstParams* __restrict__ ip, int nx, int P, 
   }
 }
 
-// Write the planned electrons into the first free slots of each tile.
+// Write the planned electrons into the first free slots of each tile: the
+// tile is scanned in unit-stride chunks of one workgroup; a dead slot's rank
+// is its instance-wide free-slot index, and rank q < Q receives electron q.
 template <typename T>
-__global__ void k_inject_write(const TileDesc* __restrict__ tiles, const InstParams* __restrict__ ip,
-                               const Plan* __restrict__ plan, const uint32_t* __restrict__ tile_off,
-                               const double* __restrict__ Tcell, Geo<T> G, double m_g1, double ck, T* kx, T* ky,
-                               T* kz, T* x, T* y, T* z, uint32_t* meta) {
-  __shared__ uint32_t s_scan[1024];
+__global__ void __launch_bounds__(256) k_inject_write(const TileDesc* __restrict__ tiles,
+                                                      const InstParams* __restrict__ ip, const Plan* __restrict__ plan,
+                                                      const uint32_t* __restrict__ tile_off,
+                                                      const double* __restrict__ Tcell, Geo<T> G, double m_g1,
+                                                      double ck, T* kx, T* ky, T* kz, T* x, T* y, T* z,
+                                                      uint32_t* meta) {
+  __shared__ uint32_t s_w[4];
   const TileDesc td = tiles[blockIdx.x];
   const Plan& pl = plan[td.inst];
   const uint32_t Q = pl.Q;
-  const uint32_t base_off = tile_off[blockIdx.x];
-  if (base_off >= Q) return;
+  uint32_t run = tile_off[blockIdx.x];
+  if (run >= Q) return;
   const InstParams I = ip[td.inst];
   const int P = G.ny * G.nz;
-  const int B = blockDim.x;
-  const int chunk = (td.count + B - 1) / B;
-  const int lo = min(td.count, (int)threadIdx.x * chunk), hi = min(td.count, lo + chunk);
-  uint32_t nd = 0;
-  for (int i = lo; i < hi; ++i) nd += (meta[td.start + i] & kAlive) ? 0u : 1u;
-  s_scan[threadIdx.x] = nd;
-  __syncthreads();
-  // exclusive scan (Hillis-Steele) over the workgroup
-  for (int o = 1; o < B; o <<= 1) {
-    const uint32_t v = threadIdx.x >= (unsigned)o ? s_scan[threadIdx.x - o] : 0u;
-    __syncthreads();
-    s_scan[threadIdx.x] += v;
-    __syncthreads();
-  }
-  uint32_t q = base_off + s_scan[threadIdx.x] - nd;
-  for (int i = lo; i < hi && q < Q; ++i) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int base = 0; base < td.count; base += blockDim.x) {
+    const int i = base + threadIdx.x;
     const long long p = td.start + i;
-    if (meta[p] & kAlive) continue;
-    int l = -1;
-    for (int t = 0; t < 2 * P; ++t)
-      if (q >= pl.off[t] && q < pl.off[t] + pl.need[t]) { l = t; break; }
-    if (l < 0) break;
-    const int side = l >= P ? 1 : 0;
-    const int lc = side ? l - P : l;
-    const int cell = side ? (G.nx - 1) * P + lc : lc;
-    const uint32_t ii = q - pl.off[l];
-    const uint4 w = philox((uint32_t)cell, pl.u, ii, I.tagw | 2u, I.key0, I.key1);
-    const double Tc = Tcell[(size_t)td.inst * G.ncell + cell];
-    const T sig = (T)sqrt(m_g1 * kKb * Tc / kQ / (2.0 * ck));
-    const T r1 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.x))), r2 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.z)));
-    T c1, s1, c2, s2;
-    Ar<T>::cs2pi(Ar<T>::u01(w.y), c1, s1);
-    Ar<T>::cs2pi(Ar<T>::u01(w.w), c2, s2);
-    kx[p] = sig * r1 * c1;
-    ky[p] = sig * r1 * s1;
-    kz[p] = sig * r2 * c2;
-    const uint4 w2 = philox((uint32_t)cell, pl.u, ii, I.tagw | 3u, I.key0, I.key1);
-    const int ix = side ? G.nx - 1 : 0, iy = lc / G.nz, iz = lc % G.nz;
-    x[p] = ((T)ix + Ar<T>::u01(w2.x)) * G.d[0];
-    y[p] = ((T)iy + Ar<T>::u01(w2.y)) * G.d[1];
-    z[p] = ((T)iz + Ar<T>::u01(w2.z)) * G.d[2];
-    meta[p] = ((pl.id0 + q) << 3) | kAlive;
-    ++q;
+    const bool dead = i < td.count && !(meta[p] & kAlive);
+    const unsigned long long bal = __ballot(dead);
+    if (lane == 0) s_w[wave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int q = 0; q < nw; ++q) {
+      if (q < wave) before += s_w[q];
+      total += s_w[q];
+    }
+    __syncthreads();
+    const uint32_t q = run + before + (uint32_t)__popcll(bal & lt);
+    if (dead && q < Q) {
+      int l = -1;
+      for (int t = 0; t < 2 * P; ++t)
+        if (q >= pl.off[t] && q < pl.off[t] + pl.need[t]) { l = t; break; }
+      if (l >= 0) {
+        const int side = l >= P ? 1 : 0;
+        const int lc = side ? l - P : l;
+        const int cell = side ? (G.nx - 1) * P + lc : lc;
+        const uint32_t ii = q - pl.off[l];
+        const uint4 w = philox((uint32_t)cell, pl.u, ii, I.tagw | 2u, I.key0, I.key1);
+        const double Tc = Tcell[(size_t)td.inst * G.ncell + cell];
+        const T sig = (T)sqrt(m_g1 * kKb * Tc / kQ / (2.0 * ck));
+        const T r1 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.x))), r2 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.z)));
+        T c1, s1, c2, s2;
+        Ar<T>::cs2pi(Ar<T>::u01(w.y), c1, s1);
+        Ar<T>::cs2pi(Ar<T>::u01(w.w), c2, s2);
+        kx[p] = sig * r1 * c1;
+        ky[p] = sig * r1 * s1;
+        kz[p] = sig * r2 * c2;
+        const uint4 w2 = philox((uint32_t)cell, pl.u, ii, I.tagw | 3u, I.key0, I.key1);
+        const int ix = side ? G.nx - 1 : 0, iy = lc / G.nz, iz = lc % G.nz;
+        x[p] = ((T)ix + Ar<T>::u01(w2.x)) * G.d[0];
+        y[p] = ((T)iy + Ar<T>::u01(w2.y)) * G.d[1];
+        z[p] = ((T)iz + Ar<T>::u01(w2.z)) * G.d[2];
+        meta[p] = ((pl.id0 + q) << 3) | kAlive;
+      }
+    }
+    run += total;
+    if (run >= Q) break;
   }
 }
 
@@ -765,22 +787,26 @@ __global__ void k_poisson_factor(PoisGeo g, double* Minv) {
   }
 }
 
-// One workgroup of 256 per instance: right-hand side from the counts, block
-// forward/backward sweep (8 lanes per matrix row), field, FP32 copy, and the
-// window density sum.  The M_i rows are prefetched kPF steps ahead.
-constexpr int kPF = 8;
-__global__ void __launch_bounds__(256) k_poisson(PoisGeo g, const InstParams* __restrict__ ip,
-                                                 const double* __restrict__ Minv, const uint32_t* __restrict__ count,
-                                                 double* phi_out, double* field64, float* field32,
-                                                 unsigned long long* dens, int accumulate, int ncell) {
+// One wavefront per instance: right-hand side from the counts, then the block
+// forward and backward sweeps (kLpr lanes per matrix row, each holding up to
+// kCpl columns of M_i, rows prefetched kPF steps ahead), then the field, its
+// FP32 copy and the window density sum.  A single wavefront needs no
+// cross-wave barrier between the 2 nx - 1 dependent steps.
+constexpr int kPF = 6;
+constexpr int kCpl = 16;  // columns per lane: P <= 32 rows and at least 2 lanes per row
+__global__ void __launch_bounds__(64) k_poisson(PoisGeo g, const InstParams* __restrict__ ip,
+                                                const double* __restrict__ Minv, const uint32_t* __restrict__ count,
+                                                double* phi_out, double* field64, float* field32,
+                                                unsigned long long* dens, int accumulate, int ncell) {
   extern __shared__ double shd[];
   double* h = shd;           // [ncell]: h_i, then x_i
   double* rhs = shd + ncell; // [ncell]
   const int inst = blockIdx.x;
   const InstParams& I = ip[inst];
   const int P = g.P, nx = g.nx;
+  const int lane = threadIdx.x;
   const uint32_t* cnt = count + (size_t)inst * ncell;
-  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+  for (int c = lane; c < ncell; c += 64) {
     const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
     double b = 0.0;
     if (ix == nx - 1) b += 2.0 * g.gx * I.Vds;
@@ -792,16 +818,18 @@ __global__ void __launch_bounds__(256) k_poisson(PoisGeo g, const InstParams* __
     if (accumulate) dens[(size_t)inst * ncell + c] += cnt[c];
   }
   __syncthreads();
-  const int r = threadIdx.x >> 3, q = threadIdx.x & 7;
+  // lpr contiguous lanes per matrix row, each with ceil(P / lpr) <= kCpl columns
+  const int lpr = min(8, 64 / P);
+  const int r = lane / lpr, q = lane % lpr;
   const bool act = r < P;
   const int nsteps = 2 * nx - 1;
   auto slice = [nx](int s) { return s < nx ? s : 2 * nx - 2 - s; };
-  double buf[kPF][4];
+  double buf[kPF][kCpl];
 #pragma unroll
   for (int k = 0; k < kPF; ++k) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int col = q + 8 * e;
+    for (int e = 0; e < kCpl; ++e) {
+      const int col = q + lpr * e;
       buf[k][e] = (act && k < nsteps && col < P) ? Minv[((size_t)slice(k) * P + r) * P + col] : 0.0;
     }
   }
@@ -814,26 +842,24 @@ __global__ void __launch_bounds__(256) k_poisson(PoisGeo g, const InstParams* __
         double part = 0.0;
         if (act) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int col = q + 8 * e;
+          for (int e = 0; e < kCpl; ++e) {
+            const int col = q + lpr * e;
             if (col < P) {
-              double vin;
-              if (s < nx) vin = rhs[i * P + col] + (i > 0 ? g.gx * h[(i - 1) * P + col] : 0.0);
-              else vin = h[(i + 1) * P + col];
+              const double vin = s < nx ? rhs[i * P + col] + (i > 0 ? g.gx * h[(i - 1) * P + col] : 0.0)
+                                        : h[(i + 1) * P + col];
               part += buf[kk][e] * vin;
             }
           }
         }
-        // prefetch step s + kPF into this ring slot
         const int sn = s + kPF;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int col = q + 8 * e;
+        for (int e = 0; e < kCpl; ++e) {
+          const int col = q + lpr * e;
           buf[kk][e] = (act && sn < nsteps && col < P) ? Minv[((size_t)slice(sn) * P + r) * P + col] : 0.0;
         }
-        part += __shfl_xor(part, 1, 8);
-        part += __shfl_xor(part, 2, 8);
-        part += __shfl_xor(part, 4, 8);
+        double row = part;
+        for (int o = 1; o < lpr; ++o) row += __shfl(part, (lane + o) & 63);
+        part = row;
         __syncthreads();
         if (act && q == 0) {
           if (s < nx) h[i * P + r] = part;                 // h_i = M_i y_i
@@ -843,9 +869,8 @@ __global__ void __launch_bounds__(256) k_poisson(PoisGeo g, const InstParams* __
       }
     }
   }
-  // h now holds phi
   double* phi = phi_out + (size_t)inst * ncell;
-  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+  for (int c = lane; c < ncell; c += 64) {
     const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
     const double pc = h[c];
     const bool gt = gated(g, ix);

@@ -1,0 +1,215 @@
+// sg_kernels.h -- gfx950 kernels of the MLP surrogate that maps a bias point
+// (Vgs, Vds, log10 doping, per-subcell lattice temperature) to the per-subcell
+// heat and electron-density maps of the Monte Carlo.  BF16 operands on the
+// matrix cores (v_mfma_f32_32x32x16_bf16) with FP32 accumulation; FP32 master
+// weights and Adam moments.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 128, BN = 128, BK = 32, KP = BK + 8;  // LDS pitch 40 bf16 (80 B, 16-B aligned rows)
+
+enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
+
+struct GemmArgs {
+  const bf16* A;
+  long lda;
+  const bf16* B;
+  long ldb;
+  int M, N, K;
+  float* Cf;
+  long ldcf;
+  bf16* Cb;
+  long ldcb;
+  const float* bias;
+  const float* Z;  // pre-activations for the GELU derivative
+  long ldz;
+};
+
+// GELU with the exact normal CDF: x Phi(x)
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// d/dx [x Phi(x)] = Phi(x) + x phi(x)
+__device__ __forceinline__ float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// C[M x N] = opA(A)[M x K] opB(B)[K x N], BF16 in, FP32 accumulate, with an
+// epilogue.  opA(i,k) = A[i*lda + k] (TA false) or A[k*lda + i] (TA true);
+// opB(k,j) = B[k*ldb + j] (TB false) or B[j*ldb + k] (TB true).
+// Workgroup tile 128 x 128 x 32, four waves of 64 x 64 (2 x 2 MFMA blocks).
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) bf16 As[BM * KP];
+  __shared__ __attribute__((aligned(16))) bf16 Bs[BN * KP];  // n-major: Bs[n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
+  const bf16 zero = (bf16)0.0f;
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      int i, kk;
+      if (!TA) { i = e / BK; kk = e % BK; } else { kk = e / BM; i = e % BM; }
+      const int gi = m0 + i, gk = k0 + kk;
+      bf16 val = zero;
+      if (gi < g.M && gk < g.K) val = TA ? g.A[(long)gk * g.lda + gi] : g.A[(long)gi * g.lda + gk];
+      As[i * KP + kk] = val;
+    }
+    for (int e = tid; e < BN * BK; e += 256) {
+      int j, kk;
+      if (!TB) { kk = e / BN; j = e % BN; } else { j = e / BK; kk = e % BK; }
+      const int gj = n0 + j, gk = k0 + kk;
+      bf16 val = zero;
+      if (gj < g.N && gk < g.K) val = TB ? g.B[(long)gj * g.ldb + gk] : g.B[(long)gk * g.ldb + gj];
+      Bs[j * KP + kk] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+        a[mi] = *reinterpret_cast<const bf16x8*>(As + (wm + mi * 32 + (lane & 31)) * KP + ks + 8 * (lane >> 5));
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+        b[ni] = *reinterpret_cast<const bf16x8*>(Bs + (wn + ni * 32 + (lane & 31)) * KP + ks + 8 * (lane >> 5));
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int row = m0 + wm + mi * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+        const int col = n0 + wn + ni * 32 + (lane & 31);
+        if (row >= g.M || col >= g.N) continue;
+        const float v = acc[mi][ni][j];
+        if (EPI == EPI_STORE) {
+          g.Cf[(long)row * g.ldcf + col] = v;
+        } else if (EPI == EPI_BIAS) {
+          g.Cf[(long)row * g.ldcf + col] = v + g.bias[col];
+        } else if (EPI == EPI_BIAS_GELU) {
+          const float z = v + g.bias[col];
+          g.Cf[(long)row * g.ldcf + col] = z;
+          g.Cb[(long)row * g.ldcb + col] = (bf16)gelu(z);
+        } else {
+          g.Cb[(long)row * g.ldcb + col] = (bf16)(v * gelu_grad(g.Z[(long)row * g.ldz + col]));
+        }
+      }
+}
+
+// Normalised BF16 input rows: (x - mean) / std, zero padding to ldx.
+__global__ void k_input(const float* __restrict__ x, int M, int n_in, const float* __restrict__ mean,
+                        const float* __restrict__ stdv, bf16* X0, int ldx) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)M * ldx) return;
+  const int i = (int)(e / ldx), k = (int)(e % ldx);
+  X0[e] = (bf16)(k < n_in ? (x[(long)i * n_in + k] - mean[k]) / stdv[k] : 0.0f);
+}
+
+// MSE on z-scored targets; writes dL/dpred (BF16) and per-block loss sums.
+__global__ void k_loss(const float* __restrict__ pred, const float* __restrict__ y, int M, int n_out,
+                       const float* __restrict__ ymean, const float* __restrict__ ystd, bf16* dpred,
+                       float* loss_part) {
+  __shared__ float s[256];
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.0f;
+  if (e < (long)M * n_out) {
+    const int j = (int)(e % n_out);
+    const float t = (y[e] - ymean[j]) / ystd[j];
+    const float d = pred[e] - t;
+    l = d * d;
+    dpred[e] = (bf16)(2.0f * d / (float)((long)M * n_out));
+  }
+  s[threadIdx.x] = l;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = s[0];
+}
+
+// column sums of a BF16 [M x N] gradient (bias gradient)
+__global__ void k_colsum(const bf16* __restrict__ d, int M, int N, long ld, float* out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  float s = 0.0f;
+  for (int i = 0; i < M; ++i) s += (float)d[(long)i * ld + j];
+  out[j] = s;
+}
+
+// Adam (bias-corrected) on FP32 master weights, then the BF16 copy.
+__global__ void k_adam(float* w, float* m, float* v, const float* __restrict__ g, bf16* wb, long n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = (bf16)wi;
+}
+
+// Counter-based uniform initialisation U(-a, a) of FP32 master weights.
+__global__ void k_init_weights(float* w, bf16* wb, long n, float a, uint32_t key0, uint32_t key1, uint32_t tag) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = 0u, c3 = tag, k0 = key0, k1 = key1;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  const float u = ((float)(c0 >> 8) + 0.5f) * (1.0f / 16777216.0f);
+  const float wi = a * (2.0f * u - 1.0f);
+  w[i] = wi;
+  wb[i] = (bf16)wi;
+}
+
+// Ensemble mean and spread of de-normalised predictions.
+__global__ void k_ensemble(const float* __restrict__ preds, int E, long per, int n_out, const float* __restrict__ ymean,
+                           const float* __restrict__ ystd, float* mean_out, float* std_out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= per) return;
+  const int j = (int)(e % n_out);
+  // two passes: the spread is often far below the mean, where a one-pass
+  // sum of squares would cancel
+  float s = 0.0f;
+  for (int q = 0; q < E; ++q) s += preds[q * per + e] * ystd[j] + ymean[j];
+  const float mu = s / E;
+  float s2 = 0.0f;
+  for (int q = 0; q < E; ++q) {
+    const float d = preds[q * per + e] * ystd[j] + ymean[j] - mu;
+    s2 += d * d;
+  }
+  mean_out[e] = mu;
+  if (std_out) std_out[e] = E > 1 ? sqrtf(s2 / (E - 1)) : 0.0f;
+}
+
+}  // namespace sg

@@ -1,0 +1,371 @@
+// surrogate.hip -- host side of the MLP surrogate (sg_* in include/gfmc.h):
+// workspace carving, weight initialisation, forward, loss and backward
+// passes, Adam, ensemble prediction.  All arithmetic runs in sg_kernels.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gfmc.h"
+#include "sg_kernels.h"
+
+using namespace sg;
+
+namespace {
+
+struct Lay {
+  size_t total = 0;
+  size_t take(size_t b) {
+    const size_t o = total;
+    total += (b + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+struct LayerOff {
+  size_t Wb, W, m, v, b, bm, bv, dW, db;
+};
+
+struct SgLayout {
+  int L = 0;              // weight layers = depth + 1
+  int K0p = 0;            // padded input width
+  std::vector<int> K, N;  // per layer
+  std::vector<std::vector<LayerOff>> lo;  // [member][layer]
+  size_t xmean, xstd, ymean, ystd, X0, preds, dA0, dA1, loss, idx;
+  std::vector<size_t> Z, A;  // per hidden layer: pre-activation (FP32) and activation (BF16)
+  size_t total = 0;
+};
+
+bool sg_valid(const sg_config* c) {
+  return c && c->n_in > 0 && c->n_out > 0 && c->width > 0 && c->depth >= 1 && c->depth <= 16 && c->ensemble >= 1 &&
+         c->ensemble <= 16 && c->max_batch >= 1 && c->max_batch <= 65536;
+}
+
+SgLayout sg_layout(const sg_config* c) {
+  SgLayout s;
+  Lay L;
+  s.L = c->depth + 1;
+  s.K0p = (c->n_in + 31) / 32 * 32;
+  for (int l = 0; l < s.L; ++l) {
+    s.K.push_back(l == 0 ? s.K0p : c->width);
+    s.N.push_back(l == s.L - 1 ? c->n_out : c->width);
+  }
+  s.lo.resize(c->ensemble);
+  for (int e = 0; e < c->ensemble; ++e)
+    for (int l = 0; l < s.L; ++l) {
+      const size_t n = (size_t)s.K[l] * s.N[l];
+      LayerOff o;
+      o.Wb = L.take(2 * n);
+      o.W = L.take(4 * n);
+      o.m = L.take(4 * n);
+      o.v = L.take(4 * n);
+      o.b = L.take(4 * (size_t)s.N[l]);
+      o.bm = L.take(4 * (size_t)s.N[l]);
+      o.bv = L.take(4 * (size_t)s.N[l]);
+      o.dW = L.take(4 * n);
+      o.db = L.take(4 * (size_t)s.N[l]);
+      s.lo[e].push_back(o);
+    }
+  const size_t MB = c->max_batch;
+  s.xmean = L.take(4 * (size_t)c->n_in);
+  s.xstd = L.take(4 * (size_t)c->n_in);
+  s.ymean = L.take(4 * (size_t)c->n_out);
+  s.ystd = L.take(4 * (size_t)c->n_out);
+  s.X0 = L.take(2 * MB * s.K0p);
+  for (int l = 0; l < s.L - 1; ++l) {
+    s.Z.push_back(L.take(4 * MB * s.N[l]));
+    s.A.push_back(L.take(2 * MB * s.N[l]));
+  }
+  s.preds = L.take(4 * MB * c->n_out * (size_t)c->ensemble);
+  const size_t wmax = std::max(c->width, c->n_out);
+  s.dA0 = L.take(2 * MB * wmax);
+  s.dA1 = L.take(2 * MB * wmax);
+  s.loss = L.take(4 * ((MB * c->n_out + 255) / 256 + 1));
+  s.idx = 0;
+  s.total = L.total;
+  return s;
+}
+
+unsigned blocks(long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+struct sg_ctx {
+  sg_config c;
+  SgLayout s;
+  char* ws = nullptr;
+  hipStream_t st = nullptr;
+  std::vector<int> step;  // Adam step per member
+  std::string err;
+  template <typename T> T* p(size_t o) { return reinterpret_cast<T*>(ws + o); }
+};
+
+namespace {
+
+int sfail(sg_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+
+#define SGCHK(ctx, expr)                                                                                  \
+  do {                                                                                                   \
+    hipError_t e_ = (expr);                                                                              \
+    if (e_ != hipSuccess) return sfail((ctx), MC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <bool TA, bool TB, int EPI>
+void gemm(sg_ctx* c, const GemmArgs& g) {
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM);
+  k_gemm<TA, TB, EPI><<<grid, 256, 0, c->st>>>(g);
+}
+
+GemmArgs ga(const bf16* A, long lda, const bf16* B, long ldb, int M, int N, int K) {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.M = M; g.N = N; g.K = K;
+  return g;
+}
+
+// forward of one member on `batch` rows of raw FP32 inputs; normalised
+// predictions to `out` (FP32 [batch][n_out])
+void enqueue_forward(sg_ctx* c, int e, const float* d_x, int batch, float* out) {
+  const SgLayout& s = c->s;
+  k_input<<<blocks((long)batch * s.K0p), 256, 0, c->st>>>(d_x, batch, c->c.n_in, c->p<float>(s.xmean),
+                                                           c->p<float>(s.xstd), c->p<bf16>(s.X0), s.K0p);
+  const bf16* X = c->p<bf16>(s.X0);
+  long ldx = s.K0p;
+  for (int l = 0; l < s.L; ++l) {
+    const LayerOff& o = s.lo[e][l];
+    GemmArgs g = ga(X, ldx, c->p<bf16>(o.Wb), s.N[l], batch, s.N[l], s.K[l]);
+    g.bias = c->p<float>(o.b);
+    if (l < s.L - 1) {
+      g.Cf = c->p<float>(s.Z[l]); g.ldcf = s.N[l];
+      g.Cb = c->p<bf16>(s.A[l]); g.ldcb = s.N[l];
+      gemm<false, false, EPI_BIAS_GELU>(c, g);
+      X = c->p<bf16>(s.A[l]);
+      ldx = s.N[l];
+    } else {
+      g.Cf = out; g.ldcf = s.N[l];
+      gemm<false, false, EPI_BIAS>(c, g);
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sg_workspace_bytes(const sg_config* c) {
+  if (!sg_valid(c)) return 0;
+  return sg_layout(c).total;
+}
+
+int sg_init(sg_ctx** out, const sg_config* cfg, void* d_ws, size_t bytes, void* stream) {
+  if (!out) return MC_E_ARG;
+  *out = nullptr;
+  if (!sg_valid(cfg)) return MC_E_ARG;
+  SgLayout s = sg_layout(cfg);
+  if (!d_ws || bytes < s.total || ((uintptr_t)d_ws & 255u)) return MC_E_ARG;
+  sg_ctx* c = new sg_ctx();
+  c->c = *cfg;
+  c->s = s;
+  c->ws = (char*)d_ws;
+  c->st = (hipStream_t)stream;
+  c->step.assign(cfg->ensemble, 0);
+  *out = c;
+  SGCHK(c, hipMemsetAsync(c->ws, 0, s.total, c->st));
+  for (int e = 0; e < cfg->ensemble; ++e)
+    for (int l = 0; l < s.L; ++l) {
+      const long n = (long)s.K[l] * s.N[l];
+      // variance-preserving uniform init on the true fan-in
+      const int fan_in = l == 0 ? cfg->n_in : s.K[l];
+      const float a = std::sqrt(3.0f / (float)fan_in);
+      k_init_weights<<<blocks(n), 256, 0, c->st>>>(c->p<float>(s.lo[e][l].W), c->p<bf16>(s.lo[e][l].Wb), n, a,
+                                                   (uint32_t)(cfg->seed & 0xffffffffu), (uint32_t)(cfg->seed >> 32),
+                                                   (uint32_t)((5u << 24) | (e << 8) | l));
+    }
+  // padded input rows of layer 0 carry no weight
+  std::vector<float> ones_x(cfg->n_in, 1.0f), ones_y(cfg->n_out, 1.0f);
+  SGCHK(c, hipMemcpyAsync(c->ws + s.xstd, ones_x.data(), 4 * ones_x.size(), hipMemcpyHostToDevice, c->st));
+  SGCHK(c, hipMemcpyAsync(c->ws + s.ystd, ones_y.data(), 4 * ones_y.size(), hipMemcpyHostToDevice, c->st));
+  for (int e = 0; e < cfg->ensemble; ++e) {
+    const int pad = s.K0p - cfg->n_in;
+    if (pad > 0) {
+      std::vector<float> z((size_t)pad * s.N[0], 0.0f);
+      std::vector<uint16_t> zb((size_t)pad * s.N[0], 0);
+      SGCHK(c, hipMemcpyAsync(c->ws + s.lo[e][0].W + 4 * (size_t)cfg->n_in * s.N[0], z.data(), 4 * z.size(),
+                              hipMemcpyHostToDevice, c->st));
+      SGCHK(c, hipMemcpyAsync(c->ws + s.lo[e][0].Wb + 2 * (size_t)cfg->n_in * s.N[0], zb.data(), 2 * zb.size(),
+                              hipMemcpyHostToDevice, c->st));
+    }
+  }
+  SGCHK(c, hipGetLastError());
+  SGCHK(c, hipStreamSynchronize(c->st));
+  return MC_OK;
+}
+
+int sg_destroy(sg_ctx* c) {
+  if (!c) return MC_E_ARG;
+  (void)hipStreamSynchronize(c->st);
+  delete c;
+  return MC_OK;
+}
+
+const char* sg_last_error(const sg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int sg_layer_dims(const sg_ctx* c, int layer, int* K, int* N) {
+  if (!c || layer < 0 || layer >= c->s.L) return MC_E_ARG;
+  if (K) *K = c->s.K[layer];
+  if (N) *N = c->s.N[layer];
+  return MC_OK;
+}
+
+int sg_set_normalization(sg_ctx* c, const float* xm, const float* xs, const float* ym, const float* ys) {
+  if (!c || !xm || !xs || !ym || !ys) return MC_E_ARG;
+  for (int i = 0; i < c->c.n_in; ++i)
+    if (!(xs[i] > 0.0f)) return sfail(c, MC_E_ARG, "input scale must be positive");
+  for (int i = 0; i < c->c.n_out; ++i)
+    if (!(ys[i] > 0.0f)) return sfail(c, MC_E_ARG, "output scale must be positive");
+  const SgLayout& s = c->s;
+  SGCHK(c, hipMemcpyAsync(c->ws + s.xmean, xm, 4 * (size_t)c->c.n_in, hipMemcpyHostToDevice, c->st));
+  SGCHK(c, hipMemcpyAsync(c->ws + s.xstd, xs, 4 * (size_t)c->c.n_in, hipMemcpyHostToDevice, c->st));
+  SGCHK(c, hipMemcpyAsync(c->ws + s.ymean, ym, 4 * (size_t)c->c.n_out, hipMemcpyHostToDevice, c->st));
+  SGCHK(c, hipMemcpyAsync(c->ws + s.ystd, ys, 4 * (size_t)c->c.n_out, hipMemcpyHostToDevice, c->st));
+  SGCHK(c, hipStreamSynchronize(c->st));
+  return MC_OK;
+}
+
+int sg_forward(sg_ctx* c, int member, const float* d_x, int batch, float* d_pred) {
+  if (!c || member < 0 || member >= c->c.ensemble || !d_x || !d_pred || batch < 1 || batch > c->c.max_batch)
+    return sfail(c, MC_E_ARG, "bad argument");
+  enqueue_forward(c, member, d_x, batch, d_pred);
+  SGCHK(c, hipGetLastError());
+  return MC_OK;
+}
+
+int sg_backward(sg_ctx* c, int member, const float* d_x, const float* d_y, int batch, float* h_loss) {
+  if (!c || member < 0 || member >= c->c.ensemble || !d_x || !d_y || batch < 1 || batch > c->c.max_batch)
+    return sfail(c, MC_E_ARG, "bad argument");
+  const SgLayout& s = c->s;
+  const int n_out = c->c.n_out;
+  float* pred = c->p<float>(s.preds) + (size_t)member * c->c.max_batch * n_out;
+  enqueue_forward(c, member, d_x, batch, pred);
+  const long tot = (long)batch * n_out;
+  bf16* dcur = c->p<bf16>(s.dA0);
+  bf16* dnext = c->p<bf16>(s.dA1);
+  k_loss<<<blocks(tot), 256, 0, c->st>>>(pred, d_y, batch, n_out, c->p<float>(s.ymean), c->p<float>(s.ystd), dcur,
+                                         c->p<float>(s.loss));
+  for (int l = s.L - 1; l >= 0; --l) {
+    const LayerOff& o = s.lo[member][l];
+    const bf16* Xin = l == 0 ? c->p<bf16>(s.X0) : c->p<bf16>(s.A[l - 1]);
+    const long ldx = l == 0 ? s.K0p : s.N[l - 1];
+    // dW = X^T dZ   [K x N]
+    GemmArgs gw = ga(Xin, ldx, dcur, s.N[l], s.K[l], s.N[l], batch);
+    gw.Cf = c->p<float>(o.dW); gw.ldcf = s.N[l];
+    gemm<true, false, EPI_STORE>(c, gw);
+    k_colsum<<<blocks(s.N[l]), 256, 0, c->st>>>(dcur, batch, s.N[l], s.N[l], c->p<float>(o.db));
+    if (l > 0) {
+      // dZ_{l-1} = (dZ_l W^T) * gelu'(Z_{l-1})
+      GemmArgs gx = ga(dcur, s.N[l], c->p<bf16>(o.Wb), s.N[l], batch, s.K[l], s.N[l]);
+      gx.Cb = dnext; gx.ldcb = s.K[l];
+      gx.Z = c->p<float>(s.Z[l - 1]); gx.ldz = s.N[l - 1];
+      gemm<false, true, EPI_GELU_GRAD>(c, gx);
+      std::swap(dcur, dnext);
+    }
+  }
+  SGCHK(c, hipGetLastError());
+  if (h_loss) {
+    const int nb = (int)blocks(tot);
+    std::vector<float> part(nb);
+    SGCHK(c, hipMemcpyAsync(part.data(), c->p<float>(s.loss), 4 * (size_t)nb, hipMemcpyDeviceToHost, c->st));
+    SGCHK(c, hipStreamSynchronize(c->st));
+    double acc = 0.0;
+    for (float v : part) acc += v;
+    *h_loss = (float)(acc / (double)tot);
+  }
+  return MC_OK;
+}
+
+int sg_adam(sg_ctx* c, int member, float lr) {
+  if (!c || member < 0 || member >= c->c.ensemble || !(lr >= 0.0f)) return sfail(c, MC_E_ARG, "bad argument");
+  const SgLayout& s = c->s;
+  const int t = ++c->step[member];
+  const float b1 = c->c.beta1, b2 = c->c.beta2;
+  const float c1 = 1.0f - std::pow(b1, (float)t), c2 = 1.0f - std::pow(b2, (float)t);
+  for (int l = 0; l < s.L; ++l) {
+    const LayerOff& o = s.lo[member][l];
+    // layer 0: only the rows of real inputs train (padding stays zero)
+    const long n = (long)(l == 0 ? c->c.n_in : s.K[l]) * s.N[l];
+    k_adam<<<blocks(n), 256, 0, c->st>>>(c->p<float>(o.W), c->p<float>(o.m), c->p<float>(o.v), c->p<float>(o.dW),
+                                         c->p<bf16>(o.Wb), n, lr, b1, b2, c->c.eps, c1, c2);
+    k_adam<<<blocks(s.N[l]), 256, 0, c->st>>>(c->p<float>(o.b), c->p<float>(o.bm), c->p<float>(o.bv),
+                                              c->p<float>(o.db), nullptr, s.N[l], lr, b1, b2, c->c.eps, c1, c2);
+  }
+  SGCHK(c, hipGetLastError());
+  return MC_OK;
+}
+
+int sg_train_step(sg_ctx* c, int member, const float* d_x, const float* d_y, int batch, float lr, float* h_loss) {
+  int rc = sg_backward(c, member, d_x, d_y, batch, h_loss);
+  if (rc != MC_OK) return rc;
+  return sg_adam(c, member, lr);
+}
+
+int sg_predict(sg_ctx* c, const float* d_x, int batch, float* d_mean, float* d_std) {
+  if (!c || !d_x || !d_mean || batch < 1 || batch > c->c.max_batch) return sfail(c, MC_E_ARG, "bad argument");
+  const SgLayout& s = c->s;
+  const long per = (long)batch * c->c.n_out;
+  for (int e = 0; e < c->c.ensemble; ++e)
+    enqueue_forward(c, e, d_x, batch, c->p<float>(s.preds) + (size_t)e * per);
+  k_ensemble<<<blocks(per), 256, 0, c->st>>>(c->p<float>(s.preds), c->c.ensemble, per, c->c.n_out,
+                                             c->p<float>(s.ymean), c->p<float>(s.ystd), d_mean, d_std);
+  SGCHK(c, hipGetLastError());
+  return MC_OK;
+}
+
+int sg_get_params(sg_ctx* c, int member, int layer, float* h_W, float* h_b) {
+  if (!c || member < 0 || member >= c->c.ensemble || layer < 0 || layer >= c->s.L) return MC_E_ARG;
+  const LayerOff& o = c->s.lo[member][layer];
+  const size_t n = (size_t)c->s.K[layer] * c->s.N[layer];
+  if (h_W) SGCHK(c, hipMemcpyAsync(h_W, c->ws + o.W, 4 * n, hipMemcpyDeviceToHost, c->st));
+  if (h_b) SGCHK(c, hipMemcpyAsync(h_b, c->ws + o.b, 4 * (size_t)c->s.N[layer], hipMemcpyDeviceToHost, c->st));
+  SGCHK(c, hipStreamSynchronize(c->st));
+  return MC_OK;
+}
+
+int sg_set_params(sg_ctx* c, int member, int layer, const float* h_W, const float* h_b) {
+  if (!c || member < 0 || member >= c->c.ensemble || layer < 0 || layer >= c->s.L || !h_W || !h_b) return MC_E_ARG;
+  const LayerOff& o = c->s.lo[member][layer];
+  const size_t n = (size_t)c->s.K[layer] * c->s.N[layer];
+  std::vector<float> w(h_W, h_W + n);
+  if (layer == 0)
+    for (size_t i = (size_t)c->c.n_in * c->s.N[0]; i < n; ++i) w[i] = 0.0f;
+  std::vector<uint16_t> wb(n);
+  for (size_t i = 0; i < n; ++i) {
+    // round to nearest even BF16
+    uint32_t u;
+    std::memcpy(&u, &w[i], 4);
+    const uint32_t r = ((u >> 16) & 1u) + 0x7FFFu;
+    wb[i] = (uint16_t)((u + r) >> 16);
+  }
+  SGCHK(c, hipMemcpyAsync(c->ws + o.W, w.data(), 4 * n, hipMemcpyHostToDevice, c->st));
+  SGCHK(c, hipMemcpyAsync(c->ws + o.Wb, wb.data(), 2 * n, hipMemcpyHostToDevice, c->st));
+  SGCHK(c, hipMemcpyAsync(c->ws + o.b, h_b, 4 * (size_t)c->s.N[layer], hipMemcpyHostToDevice, c->st));
+  SGCHK(c, hipStreamSynchronize(c->st));
+  return MC_OK;
+}
+
+int sg_get_grads(sg_ctx* c, int member, int layer, float* h_dW, float* h_db) {
+  if (!c || member < 0 || member >= c->c.ensemble || layer < 0 || layer >= c->s.L) return MC_E_ARG;
+  const LayerOff& o = c->s.lo[member][layer];
+  const size_t n = (size_t)c->s.K[layer] * c->s.N[layer];
+  if (h_dW) SGCHK(c, hipMemcpyAsync(h_dW, c->ws + o.dW, 4 * n, hipMemcpyDeviceToHost, c->st));
+  if (h_db) SGCHK(c, hipMemcpyAsync(h_db, c->ws + o.db, 4 * (size_t)c->s.N[layer], hipMemcpyDeviceToHost, c->st));
+  SGCHK(c, hipStreamSynchronize(c->st));
+  return MC_OK;
+}
+
+}  // extern "C"

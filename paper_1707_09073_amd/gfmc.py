@@ -304,3 +304,164 @@ class Ensemble:
     def mc_restore(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
         self._chk(lib().mc_restore(self._ctx, buf, len(blob)), "mc_restore")
+
+
+# ---------------------------------------------------------------------------
+# MLP surrogate (sg_* entry points)
+# ---------------------------------------------------------------------------
+class SgConfig(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_out", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32),
+                ("ensemble", C.c_int32), ("max_batch", C.c_int32), ("seed", C.c_uint64),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+SG_EXPORTS = ["sg_workspace_bytes", "sg_init", "sg_destroy", "sg_last_error", "sg_layer_dims",
+              "sg_set_normalization", "sg_forward", "sg_backward", "sg_adam", "sg_train_step", "sg_predict",
+              "sg_get_params", "sg_set_params", "sg_get_grads"]
+EXPORTS = EXPORTS + SG_EXPORTS
+
+_sg_ready = False
+
+
+def _sg_lib():
+    global _sg_ready
+    L = lib()
+    if not _sg_ready:
+        vp, fp = C.c_void_p, C.POINTER(C.c_float)
+        L.sg_workspace_bytes.argtypes = [C.POINTER(SgConfig)]; L.sg_workspace_bytes.restype = C.c_size_t
+        L.sg_init.argtypes = [C.POINTER(vp), C.POINTER(SgConfig), vp, C.c_size_t, vp]
+        L.sg_destroy.argtypes = [vp]
+        L.sg_last_error.argtypes = [vp]; L.sg_last_error.restype = C.c_char_p
+        L.sg_layer_dims.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.sg_set_normalization.argtypes = [vp, fp, fp, fp, fp]
+        L.sg_forward.argtypes = [vp, C.c_int, vp, C.c_int, vp]
+        L.sg_backward.argtypes = [vp, C.c_int, vp, vp, C.c_int, fp]
+        L.sg_adam.argtypes = [vp, C.c_int, C.c_float]
+        L.sg_train_step.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_float, fp]
+        L.sg_predict.argtypes = [vp, vp, C.c_int, vp, vp]
+        L.sg_get_params.argtypes = [vp, C.c_int, C.c_int, fp, fp]
+        L.sg_set_params.argtypes = [vp, C.c_int, C.c_int, fp, fp]
+        L.sg_get_grads.argtypes = [vp, C.c_int, C.c_int, fp, fp]
+        for n in SG_EXPORTS:
+            if n not in ("sg_workspace_bytes", "sg_last_error"):
+                getattr(L, n).restype = C.c_int
+        _sg_ready = True
+    return L
+
+
+class SurrogateNet:
+    """A library surrogate context (ensemble of MLPs); owns its torch workspace.
+    Inputs and outputs are torch FP32 CUDA tensors (row-major)."""
+
+    def __init__(self, n_in, n_out, width=1024, depth=4, ensemble=4, max_batch=256, seed=1707_09073,
+                 beta1=0.9, beta2=0.999, eps=1e-8, device="cuda", stream=None):
+        import torch
+        L = _sg_lib()
+        self.cfg = SgConfig(n_in, n_out, width, depth, ensemble, max_batch, seed, beta1, beta2, eps)
+        nbytes = int(L.sg_workspace_bytes(C.byref(self.cfg)))
+        if nbytes == 0:
+            raise MCError(MC_E_ARG, "sg_workspace_bytes", "invalid surrogate configuration")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self._ctx = C.c_void_p()
+        rc = L.sg_init(C.byref(self._ctx), C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()), nbytes,
+                       C.c_void_p(self.stream.cuda_stream))
+        if rc != MC_OK:
+            raise MCError(rc, "sg_init")
+        self.n_in, self.n_out, self.depth, self.ensemble, self.max_batch = n_in, n_out, depth, ensemble, max_batch
+
+    def _chk(self, rc, where):
+        if rc != MC_OK:
+            raise MCError(rc, where, _sg_lib().sg_last_error(self._ctx).decode())
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            _sg_lib().sg_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _in(self):
+        """Order this context's stream after torch's current stream (inputs written by torch)."""
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _out(self):
+        """Order torch's current stream after this context's stream (outputs read by torch)."""
+        import torch
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    @staticmethod
+    def _ptr(t, rows, cols):
+        import torch
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() >= rows * cols
+        return C.c_void_p(t.data_ptr())
+
+    def sg_layer_dims(self, layer):
+        K, N = C.c_int(), C.c_int()
+        self._chk(_sg_lib().sg_layer_dims(self._ctx, int(layer), C.byref(K), C.byref(N)), "sg_layer_dims")
+        return K.value, N.value
+
+    def sg_set_normalization(self, x_mean, x_std, y_mean, y_std):
+        a = [np.ascontiguousarray(v, np.float32) for v in (x_mean, x_std, y_mean, y_std)]
+        self._norm = a
+        self._chk(_sg_lib().sg_set_normalization(self._ctx, *[_p(v, C.c_float) for v in a]),
+                  "sg_set_normalization")
+
+    def sg_forward(self, member, x, out):
+        b = x.shape[0]
+        self._in()
+        self._chk(_sg_lib().sg_forward(self._ctx, int(member), self._ptr(x, b, self.n_in), b,
+                                       self._ptr(out, b, self.n_out)), "sg_forward")
+        self._out()
+
+    def sg_backward(self, member, x, y) -> float:
+        b = x.shape[0]
+        loss = C.c_float()
+        self._in()
+        self._chk(_sg_lib().sg_backward(self._ctx, int(member), self._ptr(x, b, self.n_in),
+                                        self._ptr(y, b, self.n_out), b, C.byref(loss)), "sg_backward")
+        return loss.value
+
+    def sg_adam(self, member, lr):
+        self._chk(_sg_lib().sg_adam(self._ctx, int(member), float(lr)), "sg_adam")
+
+    def sg_train_step(self, member, x, y, lr, want_loss=True):
+        b = x.shape[0]
+        loss = C.c_float()
+        self._in()
+        self._chk(_sg_lib().sg_train_step(self._ctx, int(member), self._ptr(x, b, self.n_in),
+                                          self._ptr(y, b, self.n_out), b, float(lr),
+                                          C.byref(loss) if want_loss else None), "sg_train_step")
+        return loss.value if want_loss else None
+
+    def sg_predict(self, x, mean_out, std_out=None):
+        b = x.shape[0]
+        self._in()
+        self._chk(_sg_lib().sg_predict(self._ctx, self._ptr(x, b, self.n_in), b, self._ptr(mean_out, b, self.n_out),
+                                       None if std_out is None else self._ptr(std_out, b, self.n_out)), "sg_predict")
+        self._out()
+
+    def sg_get_params(self, member, layer):
+        K, N = self.sg_layer_dims(layer)
+        W = np.zeros((K, N), np.float32); b = np.zeros(N, np.float32)
+        self._chk(_sg_lib().sg_get_params(self._ctx, int(member), int(layer), _p(W, C.c_float), _p(b, C.c_float)),
+                  "sg_get_params")
+        return W, b
+
+    def sg_set_params(self, member, layer, W, b):
+        W = np.ascontiguousarray(W, np.float32); b = np.ascontiguousarray(b, np.float32)
+        self._chk(_sg_lib().sg_set_params(self._ctx, int(member), int(layer), _p(W, C.c_float), _p(b, C.c_float)),
+                  "sg_set_params")
+
+    def sg_get_grads(self, member, layer):
+        K, N = self.sg_layer_dims(layer)
+        dW = np.zeros((K, N), np.float32); db = np.zeros(N, np.float32)
+        self._chk(_sg_lib().sg_get_grads(self._ctx, int(member), int(layer), _p(dW, C.c_float), _p(db, C.c_float)),
+                  "sg_get_grads")
+        return dW, db

@@ -1,0 +1,156 @@
+"""Surrogate runtime: data from the Monte Carlo, training, error calibration
+and the predict-or-Monte-Carlo decision.
+
+The thermal side of the paper's hybrid iteration (coupling paragraph) needs
+the electron MC's per-subcell heat generation for every new lattice
+temperature field.  The surrogate learns that map from runs of the MC itself
+and hands the query back to the MC whenever its own predicted error exceeds
+the tolerance or the query leaves the training box.  Host code here only
+sequences library calls (batched MC contexts, BF16 MFMA training and
+inference kernels); every arithmetic step runs in libgfmc.so.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import gfmc
+from . import workloads as W
+
+N_CELL = 1800
+
+
+def features(cfg: dict) -> np.ndarray:
+    """(Vgs, Vds, log10 doping [cm^-3], per-subcell lattice temperature)."""
+    T = cfg.get("T_cells")
+    T = np.full(N_CELL, cfg["T0_K"]) if T is None else np.asarray(T, np.float64)
+    return np.concatenate([[cfg["Vgs"], cfg["Vds"], math.log10(cfg["N_D_m3"] * 1e-6)], T]).astype(np.float32)
+
+
+def generate(cfgs: list[dict], warm_intervals: int, window_intervals: int, max_instances: int = 64,
+             log=print) -> tuple[np.ndarray, np.ndarray, float]:
+    """Run the MC for every bias point (batched contexts of up to
+    `max_instances` instances; each instance keeps its own seed, doping, bias
+    and temperature map) and return the inputs, the window-averaged maps
+    (heat W/m^3, then electron density m^-3) and the GPU seconds spent."""
+    import torch
+    X = np.stack([features(c) for c in cfgs])
+    Y = np.zeros((len(cfgs), 2 * N_CELL), np.float32)
+    t0 = time.perf_counter()
+    for s in range(0, len(cfgs), max_instances):
+        chunk = [dict(c, instance=i) for i, c in enumerate(cfgs[s:s + max_instances])]
+        K = chunk[0]["substeps"]
+        ens = gfmc.Ensemble(chunk)
+        ens.mc_step(warm_intervals * K)
+        for i in range(len(chunk)):
+            ens.mc_tally(i, reset_window=(i == len(chunk) - 1))
+        ens.mc_step(window_intervals * K)
+        for i in range(len(chunk)):
+            m = ens.mc_maps(i)
+            Y[s + i, :N_CELL] = m["heat_Wm3"]
+            Y[s + i, N_CELL:] = m["density_m3"]
+        ens.close()
+        torch.cuda.synchronize()
+        log(f"  generated {min(s + max_instances, len(cfgs))}/{len(cfgs)} bias points "
+            f"({time.perf_counter() - t0:.1f} s)")
+    return X, Y, time.perf_counter() - t0
+
+
+def rel_l2(pred: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Relative L2 error per row of each map (heat, density): shape [n, 2]."""
+    out = np.zeros((pred.shape[0], 2))
+    for k, sl in enumerate((slice(0, N_CELL), slice(N_CELL, 2 * N_CELL))):
+        out[:, k] = np.linalg.norm(pred[:, sl] - ref[:, sl], axis=1) / np.maximum(
+            np.linalg.norm(ref[:, sl], axis=1), 1e-300)
+    return out
+
+
+class Surrogate:
+    """Ensemble MLP on the library's BF16 MFMA kernels, with calibrated
+    predicted error and Monte Carlo fallback."""
+
+    def __init__(self, width=1024, depth=4, ensemble=4, max_batch=256, seed=1707_09073, tol=0.02):
+        self.net = gfmc.SurrogateNet(3 + N_CELL, 2 * N_CELL, width=width, depth=depth, ensemble=ensemble,
+                                     max_batch=max_batch, seed=seed)
+        self.ensemble = ensemble
+        self.max_batch = max_batch
+        self.tol = tol
+        self.calib = 1.0
+        self.box = None
+
+    def fit(self, X: np.ndarray, Y: np.ndarray, epochs: int = 200, batch: int = 128, lr: float = 1e-3,
+            seed: int = 0, log=print) -> list[float]:
+        import torch
+        xm, xs = X.mean(0), X.std(0)
+        xs = np.where(xs > 1e-6 * np.maximum(1.0, np.abs(xm)), xs, 1.0)
+        ym, ys = Y.mean(0), Y.std(0)
+        ys = np.where(ys > 1e-6 * np.maximum(1.0, np.abs(ym)), ys, np.maximum(1.0, np.abs(ym)))
+        self.net.sg_set_normalization(xm, xs, ym, ys)
+        self.box = (X.min(0), X.max(0))
+        rng = np.random.default_rng(seed)
+        n = X.shape[0]
+        batch = min(batch, self.max_batch, n)
+        losses = []
+        for ep in range(epochs):
+            # cosine learning-rate schedule
+            lr_e = lr * 0.5 * (1.0 + math.cos(math.pi * ep / epochs))
+            for e in range(self.ensemble):
+                perm = rng.permutation(n)
+                Xd = torch.tensor(X[perm], device="cuda")
+                Yd = torch.tensor(Y[perm], device="cuda")
+                for s in range(0, n - batch + 1, batch):
+                    self.net.sg_train_step(e, Xd[s:s + batch], Yd[s:s + batch], lr_e, want_loss=False)
+            if ep % max(1, epochs // 10) == 0 or ep == epochs - 1:
+                Xd = torch.tensor(X[:batch], device="cuda")
+                Yd = torch.tensor(Y[:batch], device="cuda")
+                losses.append(float(np.mean([self.net.sg_backward(e, Xd, Yd) for e in range(self.ensemble)])))
+                log(f"  epoch {ep}: train loss {losses[-1]:.4g}")
+        return losses
+
+    def predict(self, X: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+        import torch
+        means, stds = [], []
+        for s in range(0, X.shape[0], self.max_batch):
+            xd = torch.tensor(X[s:s + self.max_batch], device="cuda")
+            m = torch.empty((xd.shape[0], 2 * N_CELL), device="cuda")
+            sd = torch.empty_like(m)
+            self.net.sg_predict(xd, m, sd)
+            means.append(m.cpu().numpy())
+            stds.append(sd.cpu().numpy())
+        return np.concatenate(means), np.concatenate(stds)
+
+    def spread(self, mean: np.ndarray, std: np.ndarray) -> np.ndarray:
+        """Raw predicted error per row: the ensemble's relative spread, the
+        larger of the two maps."""
+        return np.maximum(np.linalg.norm(std[:, :N_CELL], axis=1) / np.maximum(np.linalg.norm(mean[:, :N_CELL], axis=1), 1e-300),
+                          np.linalg.norm(std[:, N_CELL:], axis=1) / np.maximum(np.linalg.norm(mean[:, N_CELL:], axis=1), 1e-300))
+
+    def calibrate(self, Xv: np.ndarray, Yv: np.ndarray) -> float:
+        """Scale the spread so that it bounds the observed validation error
+        for 90% of the points."""
+        m, s = self.predict(Xv)
+        err = rel_l2(m, Yv).max(axis=1)
+        sp = np.maximum(self.spread(m, s), 1e-12)
+        self.calib = float(np.quantile(err / sp, 0.9))
+        return self.calib
+
+    def in_box(self, X: np.ndarray) -> np.ndarray:
+        lo, hi = self.box
+        pad = 1e-6 * np.maximum(1.0, np.abs(hi - lo))
+        return np.all((X >= lo - pad) & (X <= hi + pad), axis=1)
+
+    def predict_or_mc(self, cfgs: list[dict], warm_intervals: int, window_intervals: int, log=print):
+        """Surrogate maps where the calibrated predicted error is within
+        tolerance and the query is inside the training box; the Monte Carlo
+        for the rest.  Returns (maps, used_mc mask, predicted error)."""
+        X = np.stack([features(c) for c in cfgs])
+        m, s = self.predict(X)
+        perr = self.calib * self.spread(m, s)
+        use_mc = (perr > self.tol) | ~self.in_box(X)
+        if np.any(use_mc):
+            idx = np.nonzero(use_mc)[0]
+            _, Ymc, _ = generate([cfgs[i] for i in idx], warm_intervals, window_intervals, log=log)
+            m[idx] = Ymc
+        return m, use_mc, perr

@@ -1,0 +1,125 @@
+"""Surrogate experiment: train the MLP on Monte Carlo runs of the device and
+measure its heat-map error and time per bias point against the plain MC.
+
+    python -m paper_1707_09073_amd.surrogate_experiment --train 2000 --val 200 --out result.json
+
+Training inputs are seeded bias points (Vgs ~ U[-3,0] V, Vds ~ U[1,10] V,
+doping log-uniform in [1e17, 1e19] cm^-3) with random drain-side hot spots;
+each target is the MC's window-averaged heat and density map.  Held-out
+references use `--ref-seeds` independent MC runs averaged, so that their own
+noise is below the tolerance.  Prints one JSON object.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--val", type=int, default=200)
+    ap.add_argument("--particles", type=int, default=200_000)
+    ap.add_argument("--warm", type=int, default=500, help="intervals (10 fs) before the window")
+    ap.add_argument("--window", type=int, default=1000, help="intervals (10 fs) averaged")
+    ap.add_argument("--ref-seeds", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--width", type=int, default=1024)
+    ap.add_argument("--depth", type=int, default=4)
+    ap.add_argument("--ensemble", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=0.02)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args(argv)
+
+    import torch
+    from . import surrogate as S
+    from . import workloads as W
+
+    def log(*x):
+        print(*x, file=sys.stderr, flush=True)
+
+    train_cfgs = W.surrogate_inputs(a.train, seed=11)
+    val_cfgs = W.surrogate_inputs(a.val, seed=23)
+    for c in train_cfgs + val_cfgs:
+        c["n_particles"] = a.particles
+        c["capacity"] = int(a.particles * 1.3)
+    log(f"MC training data: {a.train} bias points x {a.particles} electrons, {a.warm}+{a.window} intervals")
+    X, Y, t_train = S.generate(train_cfgs, a.warm, a.window, log=log)
+    log(f"MC held-out references: {a.val} bias points x {a.ref_seeds} seeds")
+    Xv = np.stack([S.features(c) for c in val_cfgs])
+    Yv = np.zeros((a.val, 2 * S.N_CELL), np.float32)
+    Yv_single = None
+    t_ref = 0.0
+    for r in range(a.ref_seeds):
+        cfgs = [dict(c, seed=c["seed"] + 100003 * (r + 1)) for c in val_cfgs]
+        _, Yr, tr = S.generate(cfgs, a.warm, a.window, log=log)
+        t_ref += tr
+        Yv += Yr / a.ref_seeds
+        if Yv_single is None:
+            Yv_single = Yr
+    mc_time_per_point = t_ref / (a.ref_seeds * a.val)
+    # noise of one MC run against the averaged reference (an estimate of
+    # the MC's own error at this ensemble size and window)
+    mc_err = S.rel_l2(Yv_single, Yv).max(axis=1) * np.sqrt(a.ref_seeds / max(1, a.ref_seeds - 1))
+
+    sur = S.Surrogate(width=a.width, depth=a.depth, ensemble=a.ensemble, max_batch=256, tol=a.tol)
+    t0 = time.perf_counter()
+    losses = sur.fit(X, Y, epochs=a.epochs, batch=128, lr=a.lr, log=log)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    # calibrate the spread on half of the held-out points, evaluate on the other half
+    h = a.val // 2
+    calib = sur.calibrate(Xv[:h], Yv[:h])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        m, s = sur.predict(Xv[h:])
+    torch.cuda.synchronize()
+    t_pred = (time.perf_counter() - t0) / (reps * (a.val - h))
+    # single-point latency
+    t0 = time.perf_counter()
+    for i in range(20):
+        sur.predict(Xv[h + (i % (a.val - h)):h + (i % (a.val - h)) + 1])
+    torch.cuda.synchronize()
+    t_pred1 = (time.perf_counter() - t0) / 20
+    err = S.rel_l2(m, Yv[h:])
+    perr = sur.calib * sur.spread(m, s)
+    accept = (perr <= a.tol) & sur.in_box(Xv[h:])
+    res = {
+        "train_points": a.train, "val_points": a.val, "particles": a.particles,
+        "warm_intervals": a.warm, "window_intervals": a.window, "ref_seeds": a.ref_seeds,
+        "mlp": {"width": a.width, "depth": a.depth, "ensemble": a.ensemble, "epochs": a.epochs},
+        "mc_seconds_per_bias_point": mc_time_per_point,
+        "mc_train_data_seconds": t_train,
+        "surrogate_fit_seconds": t_fit,
+        "surrogate_seconds_per_point_batched": t_pred,
+        "surrogate_seconds_single_point": t_pred1,
+        "speedup_batched": mc_time_per_point / t_pred,
+        "speedup_single_point": mc_time_per_point / t_pred1,
+        "heat_rel_l2_median": float(np.median(err[:, 0])), "heat_rel_l2_p90": float(np.quantile(err[:, 0], 0.9)),
+        "density_rel_l2_median": float(np.median(err[:, 1])),
+        "density_rel_l2_p90": float(np.quantile(err[:, 1], 0.9)),
+        "mc_single_run_rel_l2_median": float(np.median(mc_err)),
+        "calibration_factor": calib,
+        "accepted_fraction": float(np.mean(accept)),
+        "accepted_heat_rel_l2_max": float(err[accept, 0].max()) if accept.any() else None,
+        "accepted_within_tol_fraction": float(np.mean(err[accept].max(axis=1) <= a.tol)) if accept.any() else None,
+        "fallback_fraction": float(1 - np.mean(accept)),
+        "train_loss_curve": losses,
+    }
+    txt = json.dumps(res)
+    print(txt, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,138 @@
+"""GPU parity of the surrogate's BF16-MFMA kernels against the FP64 NumPy
+reference on identical BF16 operands: forward predictions, per-layer
+gradients and Adam updates (relative L2 <= 1e-3 per tensor; the GPU
+accumulates in FP32, and a BF16 rounding of a value that lies within its FP32
+error of a rounding boundary may go either way)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _make(torch_mod, n_in, n_out, width, depth, batch, ensemble=1, seed=3):
+    from oracle.mlp_oracle import MLPOracle, bf16
+    from paper_1707_09073_amd import gfmc
+    net = gfmc.SurrogateNet(n_in, n_out, width=width, depth=depth, ensemble=ensemble, max_batch=batch, seed=seed)
+    rng = np.random.default_rng(seed)
+    xm, xs = rng.normal(size=n_in), rng.uniform(0.5, 2.0, n_in)
+    ym, ys = rng.normal(size=n_out), rng.uniform(0.5, 2.0, n_out)
+    net.sg_set_normalization(xm, xs, ym, ys)
+    oracles = []
+    for e in range(ensemble):
+        Ws, bs = [], []
+        for l in range(depth + 1):
+            W, b = net.sg_get_params(e, l)
+            Ws.append(bf16(W))
+            bs.append(b.astype(np.float64))
+        oracles.append(MLPOracle(Ws, bs, xm, xs, ym, ys, n_in))
+    x = (xm + xs * rng.normal(size=(batch, n_in))).astype(np.float32)
+    y = (ym + ys * rng.normal(size=(batch, n_out))).astype(np.float32)
+    return net, oracles, x, y
+
+
+def test_forward_and_gradients_match_oracle(torch_mod):
+    torch = torch_mod
+    # several 128-wide tiles in every dimension, ragged edges (300, 200, 257)
+    net, (o,), x, y = _make(torch, n_in=300, n_out=257, width=384, depth=2, batch=200)
+    _say("surrogate small: forward/backward vs oracle")
+    xd = torch.tensor(x, device="cuda")
+    yd = torch.tensor(y, device="cuda")
+    out = torch.empty((200, 257), device="cuda", dtype=torch.float32)
+    net.sg_forward(0, xd, out)
+    torch.cuda.synchronize()
+    pred_o, _ = o.forward(x)
+    assert _rel(out.cpu().numpy(), pred_o) <= 1e-3
+    loss = net.sg_backward(0, xd, yd)
+    loss_o, dW_o, db_o, _ = o.loss_and_grads(x, y)
+    assert loss == pytest.approx(loss_o, rel=1e-4)
+    for l in range(3):
+        dW, db = net.sg_get_grads(0, l)
+        if l == 0:
+            dW, dWo = dW[:300], dW_o[0][:300]
+        else:
+            dWo = dW_o[l]
+        assert _rel(dW, dWo) <= 1e-3, (l, _rel(dW, dWo))
+        assert _rel(db, db_o[l]) <= 1e-3, (l, _rel(db, db_o[l]))
+
+
+def test_adam_step_matches_oracle(torch_mod):
+    torch = torch_mod
+    from oracle.mlp_oracle import adam_step
+    net, (o,), x, y = _make(torch, n_in=100, n_out=140, width=256, depth=1, batch=64)
+    W0 = [net.sg_get_params(0, l)[0].astype(np.float64) for l in range(2)]
+    xd, yd = torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda")
+    net.sg_train_step(0, xd, yd, lr=1e-3)
+    _, dW_o, _, _ = o.loss_and_grads(x, y)
+    for l in range(2):
+        W1 = net.sg_get_params(0, l)[0].astype(np.float64)
+        rows = slice(0, 100) if l == 0 else slice(None)
+        want, _, _ = adam_step(W0[l][rows], 0.0, 0.0, dW_o[l][rows], 1, 1e-3)
+        diff = np.abs(W1[rows] - want)
+        # step 1 of Adam moves every weight by ~lr * sign(g): only signs of
+        # near-zero gradients may disagree
+        assert diff.max() <= 2.0e-3 + 1e-6
+        assert np.mean(diff <= 1e-6) >= 0.99
+
+
+def test_full_size_forward(torch_mod):
+    """The surrogate's real shape: 1803 -> 1024 x 4 (GELU) -> 3600."""
+    torch = torch_mod
+    net, (o,), x, _ = _make(torch, n_in=1803, n_out=3600, width=1024, depth=4, batch=64, seed=11)
+    _say("surrogate full size forward")
+    xd = torch.tensor(x, device="cuda")
+    out = torch.empty((64, 3600), device="cuda", dtype=torch.float32)
+    net.sg_forward(0, xd, out)
+    torch.cuda.synchronize()
+    pred_o, _ = o.forward(x)
+    assert _rel(out.cpu().numpy(), pred_o) <= 1e-3
+
+
+def test_training_reduces_loss_and_ensemble_predicts(torch_mod):
+    torch = torch_mod
+    from paper_1707_09073_amd import gfmc
+    rng = np.random.default_rng(7)
+    n_in, n_out, n = 40, 60, 256
+    x = rng.normal(size=(n, n_in)).astype(np.float32)
+    A = rng.normal(size=(n_in, n_out)) / np.sqrt(n_in)
+    y = np.tanh(x @ A).astype(np.float32) * 3.0 + 1.0
+    net = gfmc.SurrogateNet(n_in, n_out, width=256, depth=2, ensemble=3, max_batch=n, seed=5)
+    net.sg_set_normalization(x.mean(0), x.std(0), y.mean(0), y.std(0))
+    xd, yd = torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda")
+    first = [net.sg_backward(e, xd, yd) for e in range(3)]
+    for it in range(300):
+        for e in range(3):
+            net.sg_train_step(e, xd, yd, lr=2e-3, want_loss=False)
+    last = [net.sg_backward(e, xd, yd) for e in range(3)]
+    assert all(l < f / 20 for f, l in zip(first, last)), (first, last)
+    mean = torch.empty((n, n_out), device="cuda"); std = torch.empty((n, n_out), device="cuda")
+    net.sg_predict(xd, mean, std)
+    torch.cuda.synchronize()
+    m = mean.cpu().numpy()
+    assert np.linalg.norm(m - y) / np.linalg.norm(y) < 0.1
+    # the ensemble mean equals the mean of the members' de-normalised forwards
+    outs = []
+    for e in range(3):
+        o = torch.empty((n, n_out), device="cuda")
+        net.sg_forward(e, xd, o)
+        outs.append(o.cpu().numpy() * y.std(0) + y.mean(0))
+    torch.cuda.synchronize()
+    assert np.allclose(m, np.mean(outs, axis=0), rtol=1e-4, atol=1e-4)
+    assert np.allclose(std.cpu().numpy(), np.std(outs, axis=0, ddof=1), rtol=1e-3, atol=1e-4)

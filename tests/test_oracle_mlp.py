@@ -1,0 +1,84 @@
+"""Pins of the surrogate's FP64 reference: gradients by central finite
+differences, BF16 rounding on exactly representable and tie cases, GELU
+against its integral definition, and Adam minimising a quadratic."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle.mlp_oracle import MLPOracle, adam_step, bf16, gelu, gelu_grad
+
+
+def _net(rng, n_in=7, width=6, depth=2, n_out=5):
+    K0p = (n_in + 31) // 32 * 32
+    dims = [K0p] + [width] * depth + [n_out]
+    Ws, bs = [], []
+    for l in range(len(dims) - 1):
+        W = rng.normal(size=(dims[l], dims[l + 1])) / math.sqrt(dims[l])
+        if l == 0:
+            W[n_in:] = 0.0
+        Ws.append(W)
+        bs.append(rng.normal(size=dims[l + 1]) * 0.1)
+    xm, xs = rng.normal(size=n_in), rng.uniform(0.5, 2.0, n_in)
+    ym, ys = rng.normal(size=n_out), rng.uniform(0.5, 2.0, n_out)
+    return MLPOracle(Ws, bs, xm, xs, ym, ys, n_in)
+
+
+def test_gradients_match_central_differences():
+    rng = np.random.default_rng(0)
+    o = _net(rng)
+    x = rng.normal(size=(4, 7))
+    y = rng.normal(size=(4, 5))
+    loss, dW, db, _ = o.loss_and_grads(x, y, rounded=False)
+    h = 1e-6
+    for l in range(len(o.Ws)):
+        for _ in range(6):
+            i = rng.integers(o.n_in if l == 0 else o.Ws[l].shape[0])
+            j = rng.integers(o.Ws[l].shape[1])
+            o.Ws[l][i, j] += h
+            lp = o.loss_and_grads(x, y, rounded=False)[0]
+            o.Ws[l][i, j] -= 2 * h
+            lm = o.loss_and_grads(x, y, rounded=False)[0]
+            o.Ws[l][i, j] += h
+            fd = (lp - lm) / (2 * h)
+            assert dW[l][i, j] == pytest.approx(fd, rel=1e-5, abs=1e-10)
+        j = rng.integers(len(o.bs[l]))
+        o.bs[l][j] += h
+        lp = o.loss_and_grads(x, y, rounded=False)[0]
+        o.bs[l][j] -= 2 * h
+        lm = o.loss_and_grads(x, y, rounded=False)[0]
+        o.bs[l][j] += h
+        assert db[l][j] == pytest.approx((lp - lm) / (2 * h), rel=1e-5, abs=1e-10)
+
+
+def test_bf16_rounding():
+    # exactly representable values are unchanged
+    exact = np.array([0.0, 1.0, -2.5, 3.0e-3 * 0 + 0.0078125, 65280.0])
+    assert np.array_equal(bf16(exact), exact)
+    # 1 + 2^-8 lies halfway between 1 and 1 + 2^-7: ties go to the even mantissa (1.0)
+    assert bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0
+    # 1 + 3*2^-8 is halfway between 1+2^-7 and 1+2^-6: even is 1+2^-6
+    assert bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+    # unit roundoff of an 8-significant-bit format: 2^-8
+    v = np.random.default_rng(1).normal(size=10000)
+    assert np.max(np.abs(bf16(v) - v) / np.abs(v)) <= 2.0 ** -8
+
+
+def test_gelu_is_x_times_normal_cdf():
+    for x in (-3.0, -0.7, 0.0, 0.4, 2.2):
+        phi, _ = integrate.quad(lambda t: math.exp(-t * t / 2) / math.sqrt(2 * math.pi), -np.inf, x)
+        assert gelu(np.array(x)) == pytest.approx(x * phi, abs=1e-12)
+        h = 1e-6
+        assert gelu_grad(np.array(x)) == pytest.approx((gelu(np.array(x + h)) - gelu(np.array(x - h))) / (2 * h),
+                                                       rel=1e-7, abs=1e-9)
+
+
+def test_adam_minimises_a_quadratic():
+    w = np.array([3.0, -2.0])
+    m = np.zeros(2)
+    v = np.zeros(2)
+    for t in range(1, 3001):
+        g = 2 * (w - np.array([0.5, 1.5]))
+        w, m, v = adam_step(w, m, v, g, t, lr=1e-2)
+    assert np.allclose(w, [0.5, 1.5], atol=1e-3)
