@@ -71,6 +71,7 @@ def main() -> int:
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--graph", action="store_true", help="replay intervals from a hipGraph (no per-kernel timing)")
     ap.add_argument("--variant", type=int, default=0, help="particle kernel: 0 lane refill, 1 one electron per lane")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default (or given) launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration) and exit")
@@ -99,9 +100,15 @@ def main() -> int:
     K = cfg["substeps"]
     _log(f"init: {args.particles} superparticles, capacity {cfg['capacity']}")
     ens = gfmc.Ensemble(cfg, device="cuda:0")
+    ens.mc_set_variant(args.variant)
     if args.block and args.tile:
         ens.mc_set_launch(args.block, args.tile)
-    ens.mc_set_variant(args.variant)
+    elif not args.no_autotune:
+        from paper_1707_09073_amd.autotune import autotune
+        _log("autotuning launch shape")
+        ens.mc_step(10 * K)               # leave the initial transient before timing shapes
+        tuned = autotune(ens, log=_log)
+        args.variant = tuned["variant"]
     block, tile, n_tiles = ens.mc_get_launch()
     ens.mc_use_graph(args.graph)
     _log(f"launch: block {block}, tile {tile}, {n_tiles} tiles; warmup {args.warmup} intervals")

@@ -135,8 +135,9 @@ size_t mc_workspace_bytes(const mc_config *cfgs, int n_instances);
  * per-subcell factors, the self-scattering bounds Gamma_v, the initial
  * Maxwellian ensemble, the Poisson factors and (device mode) the first
  * deposit/injection/Poisson refresh (electron MC paragraph).  MC_E_ARG for
- * capacity < n_particles, dt <= 0, table top < 3 eV, inconsistent instances
- * or a workspace that is too small. */
+ * capacity < n_particles, dt <= 0, table top < 3 eV, inconsistent instances,
+ * a device grid with ny*nz > 32 or more than 4096 subcells, or a workspace
+ * that is too small. */
 int mc_init(mc_ctx **out, const mc_config *cfgs, int n_instances, void *d_workspace, size_t ws_bytes,
             void *hip_stream);
 int mc_destroy(mc_ctx *ctx);
@@ -195,7 +196,7 @@ int mc_read_fields(mc_ctx *ctx, int instance, double *h_phi, double *h_field, ui
  * and Gamma_v [3] (1/fs) of one instance.  Any pointer may be NULL. */
 int mc_read_tables(mc_ctx *ctx, int instance, double *h_shape, double *h_k4, double *h_factors, double *h_gamma);
 
-/* Launch shape of the particle kernel: workgroup size (64..256, multiple of
+/* Launch shape of the particle kernel: workgroup size (64..512, multiple of
  * 64) and tile size (particles per tile, multiple of the workgroup size).
  * Results do not depend on the shape.  MC_E_ARG if unsupported. */
 int mc_set_launch(mc_ctx *ctx, int block, int tile);
@@ -235,8 +236,8 @@ int mc_restore(mc_ctx *ctx, const void *h_buf, size_t bytes);
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t n_in;      /* raw input features */
-  int32_t n_out;     /* outputs */
-  int32_t width;     /* hidden width */
+  int32_t n_out;     /* outputs (multiple of 8) */
+  int32_t width;     /* hidden width (multiple of 8) */
   int32_t depth;     /* hidden layers */
   int32_t ensemble;  /* independently initialised members (spread = predicted error) */
   int32_t max_batch; /* largest batch of any call */

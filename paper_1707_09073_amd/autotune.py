@@ -1,0 +1,72 @@
+"""Launch-shape autotuner for the particle kernel.
+
+Times each candidate (workgroup size, tile size, kernel variant) on the
+context's live state for a few flight intervals with HIP events, restoring a
+checkpoint before every trial and at the end.  Results of the Monte Carlo do
+not depend on the shape, so tuning leaves the simulation exactly where it
+was.  Choices are cached per (mode, precision, instances, total slots).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+DEFAULT_CANDIDATES = [
+    (256, 1024, 0), (256, 2048, 0), (256, 4096, 0), (256, 8192, 0),
+    (512, 2048, 0), (512, 4096, 0), (512, 8192, 0),
+    (128, 2048, 0), (256, 4096, 1),
+]
+
+_cache: dict = {}
+
+
+def _key(ens) -> str:
+    c = ens.cfgs[0]
+    cap = sum(int(x["capacity"]) for x in ens.cfgs)
+    return f"{c['mode']}/{c.get('precision', 'fp64')}/{len(ens.cfgs)}/{cap}"
+
+
+def autotune(ens, candidates=None, trials: int = 3, cache_file: str | None = None, log=None) -> dict:
+    """Pick the fastest launch shape for `ens` (a gfmc.Ensemble) and apply it."""
+    key = _key(ens)
+    if cache_file and os.path.exists(cache_file) and not _cache:
+        try:
+            _cache.update(json.load(open(cache_file)))
+        except (OSError, ValueError):
+            pass
+    if key in _cache:
+        best = _cache[key]
+        ens.mc_set_launch(best["block"], best["tile"])
+        ens.mc_set_variant(best["variant"])
+        return dict(best, cached=True)
+    K = int(ens.cfgs[0]["substeps"])
+    blob = ens.mc_checkpoint()
+    results = []
+    for block, tile, variant in (candidates or DEFAULT_CANDIDATES):
+        ens.mc_restore(blob)
+        try:
+            ens.mc_set_launch(block, tile)
+        except Exception:
+            continue
+        ens.mc_set_variant(variant)
+        ens.mc_profile(True)
+        ens.mc_profile_read(reset=True)
+        ens.mc_step(trials * K)
+        p = ens.mc_profile_read(reset=True)
+        ens.mc_profile(False)
+        ms = (p["flight_ms"] + p["refresh_ms"]) / max(1, p["n_flight"])
+        results.append(dict(block=block, tile=tile, variant=variant, ms_per_interval=ms,
+                            flight_ms=p["flight_ms"] / max(1, p["n_flight"])))
+        if log:
+            log(f"  autotune block {block} tile {tile} variant {variant}: {ms:.3f} ms/interval")
+    best = min(results, key=lambda r: r["ms_per_interval"])
+    ens.mc_restore(blob)
+    ens.mc_set_launch(best["block"], best["tile"])
+    ens.mc_set_variant(best["variant"])
+    _cache[key] = best
+    if cache_file:
+        try:
+            json.dump(_cache, open(cache_file, "w"))
+        except OSError:
+            pass
+    return dict(best, cached=False, trials=results)

@@ -31,8 +31,8 @@ struct Layout {
 
 struct Offsets {
   size_t table64, table32, fac64, fac32, field64, field32, phi, gamma64, gamma32, Tcell, count, heat, dens,
-      counters, flags, ctl, next_id, ip, tiles, partial, acc, tile_dead, tile_off, plan, minv, hist, reps, nrep,
-      bpart;
+      counters, flags, ctl, next_id, ip, tiles, partial, acc, tile_dead, tile_off, plan, minv, ainv, rhs, hist, reps,
+      nrep, bpart;
   size_t kx, ky, kz, x, y, z, meta;
 };
 
@@ -66,6 +66,7 @@ std::string validate(const mc_config* c, int n) {
     if (k.mode == MC_DEVICE) {
       const int P = k.n_cells[1] * k.n_cells[2];
       if (k.n_cells[0] < 2 || k.n_cells[1] < 1 || k.n_cells[2] < 1 || P > 32) return "grid (ny*nz <= 32, nx >= 2)";
+      if ((long long)k.n_cells[0] * P > 4096) return "grid larger than 4096 subcells";
       if (2 * P > 64) return "grid";
       for (int d = 0; d < 3; ++d)
         if (!(k.L_nm[d] > 0.0)) return "domain size";
@@ -138,6 +139,8 @@ Offsets layout(const mc_config* c, int n, size_t* total) {
   o.minv = L.take(dev ? sizeof(double) * c[0].n_cells[0] * (size_t)(c[0].n_cells[1] * c[0].n_cells[2]) *
                             (c[0].n_cells[1] * c[0].n_cells[2])
                       : 0);
+  o.ainv = L.take(dev ? sizeof(double) * (size_t)nc * nc : 0);
+  o.rhs = L.take(dev ? sizeof(double) * (size_t)n * nc : 0);
   o.hist = L.take(dev ? 0 : sizeof(double) * n * kHistCap * 8);
   o.reps = L.take(sizeof(int) * n * nc);
   o.nrep = L.take(sizeof(int) * n);
@@ -318,21 +321,26 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
                                              c->p<uint32_t>(c->o.ctl));
   const double mg1 = c->cfg[0].mat.m_eff[0];
   if (c->f32)
-    k_inject_write<float><<<c->n_tiles, 256, 0, c->st>>>(
+    k_inject_write<float><<<c->n_tiles, 64, 0, c->st>>>(
         c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip), c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
-        c->p<double>(c->o.Tcell), c->G32, mg1, c->ck, c->p<float>(c->o.kx), c->p<float>(c->o.ky),
+        c->p<uint32_t>(c->o.tile_dead), c->p<double>(c->o.Tcell), c->G32, mg1, c->ck, c->p<float>(c->o.kx), c->p<float>(c->o.ky),
         c->p<float>(c->o.kz), c->p<float>(c->o.x), c->p<float>(c->o.y), c->p<float>(c->o.z),
         c->p<uint32_t>(c->o.meta));
   else
-    k_inject_write<double><<<c->n_tiles, 256, 0, c->st>>>(
+    k_inject_write<double><<<c->n_tiles, 64, 0, c->st>>>(
         c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip), c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
-        c->p<double>(c->o.Tcell), c->G64, mg1, c->ck, c->p<double>(c->o.kx), c->p<double>(c->o.ky),
+        c->p<uint32_t>(c->o.tile_dead), c->p<double>(c->o.Tcell), c->G64, mg1, c->ck, c->p<double>(c->o.kx), c->p<double>(c->o.ky),
         c->p<double>(c->o.kz), c->p<double>(c->o.x), c->p<double>(c->o.y), c->p<double>(c->o.z),
         c->p<uint32_t>(c->o.meta));
-  k_poisson<<<c->n_inst, 64, sizeof(double) * 2 * nc, c->st>>>(
-      c->pg, c->p<InstParams>(c->o.ip), c->p<double>(c->o.minv), c->p<uint32_t>(c->o.count), c->p<double>(c->o.phi),
-      c->p<double>(c->o.field64), c->p<float>(c->o.field32), c->p<unsigned long long>(c->o.dens),
-      after_flight ? 1 : 0, nc);
+  dim3 gc((nc + 255) / 256, c->n_inst);
+  k_poisson_rhs<<<gc, 256, 0, c->st>>>(c->pg, c->p<InstParams>(c->o.ip), c->p<uint32_t>(c->o.count),
+                                       c->p<double>(c->o.rhs), c->p<unsigned long long>(c->o.dens),
+                                       after_flight ? 1 : 0, nc);
+  dim3 gv((nc + 3) / 4, c->n_inst);
+  k_poisson_gemv<<<gv, 256, 0, c->st>>>(c->p<double>(c->o.ainv), c->p<double>(c->o.rhs), nc,
+                                        c->p<double>(c->o.phi));
+  k_field<<<gc, 256, 0, c->st>>>(c->pg, c->p<InstParams>(c->o.ip), c->p<double>(c->o.phi), nc,
+                                 c->p<double>(c->o.field64), c->p<float>(c->o.field32));
 }
 
 hipEvent_t prof_event(mc_ctx* c) {
@@ -534,6 +542,8 @@ int mc_init(mc_ctx** out, const mc_config* cfgs, int n, void* d_ws, size_t ws_by
   HIPCHK(c, hipMemcpyAsync(c->ws + o.next_id, nid.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, c->st));
   if (c->dev) {
     k_poisson_factor<<<1, 256, 0, c->st>>>(c->pg, c->p<double>(o.minv));
+    k_poisson_inverse<<<c->ncell, 64, sizeof(double) * 2 * c->ncell, c->st>>>(c->pg, c->p<double>(o.minv), c->ncell,
+                                                                             c->p<double>(o.ainv));
     HIPCHK(c, hipGetLastError());
     *out = c;
     if ((rc = poisson_update(c)) != MC_OK) return rc;
@@ -844,7 +854,7 @@ int mc_read_tables(mc_ctx* c, int inst, double* h_shape, double* h_k4, double* h
 
 int mc_set_launch(mc_ctx* c, int block, int tile) {
   if (!c) return MC_E_ARG;
-  if (block < 64 || block > 256 || block % 64 || tile < min_tile(c->cfg[0]) || tile % block)
+  if (block < 64 || block > 512 || block % 64 || tile < min_tile(c->cfg[0]) || tile % block)
     return fail(c, MC_E_ARG, "unsupported launch shape");
   c->block = block;
   c->tile = tile;

@@ -227,7 +227,7 @@ __device__ __forceinline__ bool fly(const FlightArgs<T>& a, const InstParams& P,
 }
 
 template <typename T, bool DEV>
-__global__ void __launch_bounds__(256) k_flight(FlightArgs<T> a) {
+__global__ void __launch_bounds__(512) k_flight(FlightArgs<T> a) {
   extern __shared__ uint32_t sh[];
   const int ncell = DEV ? a.G.ncell : 1;
   uint32_t* sh_dep = sh;
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(256) k_flight(FlightArgs<T> a) {
 // the busiest lane of the wavefront finishes its events.  Per-electron
 // arithmetic and random-number use are the same as in k_flight.
 template <typename T, bool DEV>
-__global__ void __launch_bounds__(256) k_flight_refill(FlightArgs<T> a) {
+__global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
   extern __shared__ uint32_t sh[];
   const int ncell = DEV ? a.G.ncell : 1;
   uint32_t* sh_dep = sh;
@@ -546,41 +546,53 @@ __global__ void k_inject_plan(const InstParams* __restrict__ ip, int nx, int P, 
   }
 }
 
-// Write the planned electrons into the first free slots of each tile: the
-// tile is scanned in unit-stride chunks of one workgroup; a dead slot's rank
-// is its instance-wide free-slot index, and rank q < Q receives electron q.
+// Write the planned electrons into the first free slots of each tile: one
+// wavefront per tile, each lane owning 8 consecutive slots per step (two
+// 16-byte loads of the meta words), a shuffle prefix scan of the lanes' free
+// counts giving every free slot its instance-wide rank q; rank q < Q receives
+// electron q.  No barriers, and the loads of a step are independent.
 template <typename T>
-__global__ void __launch_bounds__(256) k_inject_write(const TileDesc* __restrict__ tiles,
-                                                      const InstParams* __restrict__ ip, const Plan* __restrict__ plan,
-                                                      const uint32_t* __restrict__ tile_off,
-                                                      const double* __restrict__ Tcell, Geo<T> G, double m_g1,
-                                                      double ck, T* kx, T* ky, T* kz, T* x, T* y, T* z,
-                                                      uint32_t* meta) {
-  __shared__ uint32_t s_w[4];
+__global__ void __launch_bounds__(64) k_inject_write(const TileDesc* __restrict__ tiles,
+                                                     const InstParams* __restrict__ ip, const Plan* __restrict__ plan,
+                                                     const uint32_t* __restrict__ tile_off,
+                                                     const uint32_t* __restrict__ tile_dead,
+                                                     const double* __restrict__ Tcell, Geo<T> G, double m_g1,
+                                                     double ck, T* kx, T* ky, T* kz, T* x, T* y, T* z,
+                                                     uint32_t* meta) {
   const TileDesc td = tiles[blockIdx.x];
   const Plan& pl = plan[td.inst];
   const uint32_t Q = pl.Q;
   uint32_t run = tile_off[blockIdx.x];
-  if (run >= Q) return;
+  if (run >= Q || tile_dead[blockIdx.x] == 0) return;
+  const int lane = threadIdx.x;
   const InstParams I = ip[td.inst];
   const int P = G.ny * G.nz;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  for (int base = 0; base < td.count; base += blockDim.x) {
-    const int i = base + threadIdx.x;
-    const long long p = td.start + i;
-    const bool dead = i < td.count && !(meta[p] & kAlive);
-    const unsigned long long bal = __ballot(dead);
-    if (lane == 0) s_w[wave] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    uint32_t before = 0, total = 0;
-    for (int q = 0; q < nw; ++q) {
-      if (q < wave) before += s_w[q];
-      total += s_w[q];
+  const bool vec = (td.start & 3) == 0;  // 16-byte aligned meta rows
+  for (int b = 0; b < td.count && run < Q; b += 512) {
+    const int i0 = b + 8 * lane;
+    uint32_t m8[8];
+    if (vec && i0 + 8 <= td.count) {
+      const uint4 a = *reinterpret_cast<const uint4*>(meta + td.start + i0);
+      const uint4 c = *reinterpret_cast<const uint4*>(meta + td.start + i0 + 4);
+      m8[0] = a.x; m8[1] = a.y; m8[2] = a.z; m8[3] = a.w; m8[4] = c.x; m8[5] = c.y; m8[6] = c.z; m8[7] = c.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) m8[e] = i0 + e < td.count ? meta[td.start + i0 + e] : kAlive;
     }
-    __syncthreads();
-    const uint32_t q = run + before + (uint32_t)__popcll(bal & lt);
-    if (dead && q < Q) {
+    uint32_t nd = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) nd += (m8[e] & kAlive) ? 0u : 1u;
+    uint32_t inc = nd;  // inclusive scan over the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = __shfl_up(inc, o);
+      if (lane >= o) inc += v;
+    }
+    uint32_t q = run + inc - nd;
+    run += __shfl(inc, 63);
+    for (int e = 0; e < 8 && q < Q; ++e) {
+      if (m8[e] & kAlive) continue;
+      const long long p = td.start + i0 + e;
       int l = -1;
       for (int t = 0; t < 2 * P; ++t)
         if (q >= pl.off[t] && q < pl.off[t] + pl.need[t]) { l = t; break; }
@@ -592,7 +604,8 @@ __global__ void __launch_bounds__(256) k_inject_write(const TileDesc* __restrict
         const uint4 w = philox((uint32_t)cell, pl.u, ii, I.tagw | 2u, I.key0, I.key1);
         const double Tc = Tcell[(size_t)td.inst * G.ncell + cell];
         const T sig = (T)sqrt(m_g1 * kKb * Tc / kQ / (2.0 * ck));
-        const T r1 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.x))), r2 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.z)));
+        const T r1 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.x))),
+                r2 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.z)));
         T c1, s1, c2, s2;
         Ar<T>::cs2pi(Ar<T>::u01(w.y), c1, s1);
         Ar<T>::cs2pi(Ar<T>::u01(w.w), c2, s2);
@@ -606,9 +619,8 @@ __global__ void __launch_bounds__(256) k_inject_write(const TileDesc* __restrict
         z[p] = ((T)iz + Ar<T>::u01(w2.z)) * G.d[2];
         meta[p] = ((pl.id0 + q) << 3) | kAlive;
       }
+      ++q;
     }
-    run += total;
-    if (run >= Q) break;
   }
 }
 
@@ -787,38 +799,15 @@ __global__ void k_poisson_factor(PoisGeo g, double* Minv) {
   }
 }
 
-// One wavefront per instance: right-hand side from the counts, then the block
-// forward and backward sweeps (kLpr lanes per matrix row, each holding up to
-// kCpl columns of M_i, rows prefetched kPF steps ahead), then the field, its
-// FP32 copy and the window density sum.  A single wavefront needs no
-// cross-wave barrier between the 2 nx - 1 dependent steps.
+// Block forward/backward sweep of one right-hand side held in LDS (`rhs`,
+// ncell doubles), by one wavefront: lpr contiguous lanes per matrix row, each
+// with up to kCpl columns of M_i, rows prefetched kPF steps ahead.  Leaves the
+// solution in `h` (LDS, ncell doubles).
 constexpr int kPF = 6;
 constexpr int kCpl = 16;  // columns per lane: P <= 32 rows and at least 2 lanes per row
-__global__ void __launch_bounds__(64) k_poisson(PoisGeo g, const InstParams* __restrict__ ip,
-                                                const double* __restrict__ Minv, const uint32_t* __restrict__ count,
-                                                double* phi_out, double* field64, float* field32,
-                                                unsigned long long* dens, int accumulate, int ncell) {
-  extern __shared__ double shd[];
-  double* h = shd;           // [ncell]: h_i, then x_i
-  double* rhs = shd + ncell; // [ncell]
-  const int inst = blockIdx.x;
-  const InstParams& I = ip[inst];
+__device__ void block_sweep(const PoisGeo& g, const double* __restrict__ Minv, const double* rhs, double* h) {
   const int P = g.P, nx = g.nx;
   const int lane = threadIdx.x;
-  const uint32_t* cnt = count + (size_t)inst * ncell;
-  for (int c = lane; c < ncell; c += 64) {
-    const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
-    double b = 0.0;
-    if (ix == nx - 1) b += 2.0 * g.gx * I.Vds;
-    if (gated(g, ix)) {
-      if (iy == g.ny - 1) b += 2.0 * g.gy * I.phig;
-      if (iz == g.nz - 1) b += 2.0 * g.gz * I.phig;
-    }
-    rhs[c] = b + kQ * (I.N_D_nm * g.Vc - I.w * (double)cnt[c]);
-    if (accumulate) dens[(size_t)inst * ncell + c] += cnt[c];
-  }
-  __syncthreads();
-  // lpr contiguous lanes per matrix row, each with ceil(P / lpr) <= kCpl columns
   const int lpr = min(8, 64 / P);
   const int r = lane / lpr, q = lane % lpr;
   const bool act = r < P;
@@ -859,42 +848,102 @@ __global__ void __launch_bounds__(64) k_poisson(PoisGeo g, const InstParams* __r
         }
         double row = part;
         for (int o = 1; o < lpr; ++o) row += __shfl(part, (lane + o) & 63);
-        part = row;
         __syncthreads();
         if (act && q == 0) {
-          if (s < nx) h[i * P + r] = part;                 // h_i = M_i y_i
-          else h[i * P + r] = h[i * P + r] + g.gx * part;  // x_i = h_i + gx M_i x_{i+1}
+          if (s < nx) h[i * P + r] = row;                 // h_i = M_i y_i
+          else h[i * P + r] = h[i * P + r] + g.gx * row;  // x_i = h_i + gx M_i x_{i+1}
         }
         __syncthreads();
       }
     }
   }
-  double* phi = phi_out + (size_t)inst * ncell;
-  for (int c = lane; c < ncell; c += 64) {
-    const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
-    const double pc = h[c];
-    const bool gt = gated(g, ix);
-    double pe, de, pw, dw;
-    if (ix < nx - 1) { pe = h[c + P]; de = g.dx; } else { pe = I.Vds; de = 0.5 * g.dx; }
-    if (ix > 0) { pw = h[c - P]; dw = g.dx; } else { pw = 0.0; dw = 0.5 * g.dx; }
-    const double ex = -(pe - pw) / (de + dw);
-    double pn, dn, ps, ds;
-    if (iy < g.ny - 1) { pn = h[c + g.nz]; dn = g.dy; }
-    else if (gt) { pn = I.phig; dn = 0.5 * g.dy; }
-    else { pn = pc; dn = 0.0; }
-    if (iy > 0) { ps = h[c - g.nz]; ds = g.dy; } else { ps = pc; ds = 0.0; }
-    const double ey = (dn + ds) > 0.0 ? -(pn - ps) / (dn + ds) : 0.0;
-    double pt, dt, pb, db;
-    if (iz < g.nz - 1) { pt = h[c + 1]; dt = g.dz; }
-    else if (gt) { pt = I.phig; dt = 0.5 * g.dz; }
-    else { pt = pc; dt = 0.0; }
-    if (iz > 0) { pb = h[c - 1]; db = g.dz; } else { pb = pc; db = 0.0; }
-    const double ez = (dt + db) > 0.0 ? -(pt - pb) / (dt + db) : 0.0;
-    phi[c] = pc;
-    const size_t o = ((size_t)inst * ncell + c) * 4;
-    field64[o + 0] = ex; field64[o + 1] = ey; field64[o + 2] = ez; field64[o + 3] = 0.0;
-    field32[o + 0] = (float)ex; field32[o + 1] = (float)ey; field32[o + 2] = (float)ez; field32[o + 3] = 0.0f;
+}
+
+// Dense inverse of the (symmetric) Poisson matrix, one column per
+// wavefront: A^-1 e_j by the block sweep (init only).
+__global__ void __launch_bounds__(64) k_poisson_inverse(PoisGeo g, const double* __restrict__ Minv, int ncell,
+                                                        double* Ainv) {
+  extern __shared__ double shd[];
+  double* h = shd;
+  double* rhs = shd + ncell;
+  const int j = blockIdx.x;
+  for (int c = threadIdx.x; c < ncell; c += 64) rhs[c] = c == j ? 1.0 : 0.0;
+  __syncthreads();
+  block_sweep(g, Minv, rhs, h);
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncell; c += 64) Ainv[(size_t)j * ncell + c] = h[c];
+}
+
+// Right-hand side of the cell balance (coulombs) from the electron counts and
+// the terminal faces; also adds the counts to the window density sum.
+__global__ void k_poisson_rhs(PoisGeo g, const InstParams* __restrict__ ip, const uint32_t* __restrict__ count,
+                              double* rhs_out, unsigned long long* dens, int accumulate, int ncell) {
+  const int inst = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const InstParams& I = ip[inst];
+  const int P = g.P;
+  const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
+  double b = 0.0;
+  if (ix == g.nx - 1) b += 2.0 * g.gx * I.Vds;
+  if (gated(g, ix)) {
+    if (iy == g.ny - 1) b += 2.0 * g.gy * I.phig;
+    if (iz == g.nz - 1) b += 2.0 * g.gz * I.phig;
   }
+  const uint32_t n = count[(size_t)inst * ncell + c];
+  rhs_out[(size_t)inst * ncell + c] = b + kQ * (I.N_D_nm * g.Vc - I.w * (double)n);
+  if (accumulate) dens[(size_t)inst * ncell + c] += n;
+}
+
+// phi = A^-1 rhs: one wavefront per row, unit-stride reads of the
+// (Infinity-Cache-resident) inverse, wavefront reduction.
+__global__ void __launch_bounds__(256) k_poisson_gemv(const double* __restrict__ Ainv,
+                                                      const double* __restrict__ rhs, int ncell, double* phi) {
+  const int inst = blockIdx.y;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= ncell) return;
+  const double* a = Ainv + (size_t)row * ncell;
+  const double* b = rhs + (size_t)inst * ncell;
+  double s = 0.0;
+  for (int j = lane; j < ncell; j += 64) s += a[j] * b[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) phi[(size_t)inst * ncell + row] = s;
+}
+
+// Centred-difference field E = -grad(phi): a Dirichlet neighbour is its face
+// value half a cell away, a Neumann neighbour the cell itself.
+__global__ void k_field(PoisGeo g, const InstParams* __restrict__ ip, const double* __restrict__ phi_all, int ncell,
+                        double* field64, float* field32) {
+  const int inst = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const InstParams& I = ip[inst];
+  const double* h = phi_all + (size_t)inst * ncell;
+  const int P = g.P, nx = g.nx;
+  const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
+  const double pc = h[c];
+  const bool gt = gated(g, ix);
+  double pe, de, pw, dw;
+  if (ix < nx - 1) { pe = h[c + P]; de = g.dx; } else { pe = I.Vds; de = 0.5 * g.dx; }
+  if (ix > 0) { pw = h[c - P]; dw = g.dx; } else { pw = 0.0; dw = 0.5 * g.dx; }
+  const double ex = -(pe - pw) / (de + dw);
+  double pn, dn, ps, ds;
+  if (iy < g.ny - 1) { pn = h[c + g.nz]; dn = g.dy; }
+  else if (gt) { pn = I.phig; dn = 0.5 * g.dy; }
+  else { pn = pc; dn = 0.0; }
+  if (iy > 0) { ps = h[c - g.nz]; ds = g.dy; } else { ps = pc; ds = 0.0; }
+  const double ey = (dn + ds) > 0.0 ? -(pn - ps) / (dn + ds) : 0.0;
+  double pt, dt, pb, db;
+  if (iz < g.nz - 1) { pt = h[c + 1]; dt = g.dz; }
+  else if (gt) { pt = I.phig; dt = 0.5 * g.dz; }
+  else { pt = pc; dt = 0.0; }
+  if (iz > 0) { pb = h[c - 1]; db = g.dz; } else { pb = pc; db = 0.0; }
+  const double ez = (dt + db) > 0.0 ? -(pt - pb) / (dt + db) : 0.0;
+  const size_t o = ((size_t)inst * ncell + c) * 4;
+  field64[o + 0] = ex; field64[o + 1] = ey; field64[o + 2] = ez; field64[o + 3] = 0.0;
+  field32[o + 0] = (float)ex; field32[o + 1] = (float)ey; field32[o + 2] = (float)ez; field32[o + 3] = 0.0f;
 }
 
 // Bulk observables: per-tile partial sums in a fixed reduction order.

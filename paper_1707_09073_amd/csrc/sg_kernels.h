@@ -59,21 +59,56 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
   const bf16 zero = (bf16)0.0f;
   for (int k0 = 0; k0 < g.K; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      int i, kk;
-      if (!TA) { i = e / BK; kk = e % BK; } else { kk = e / BM; i = e % BM; }
-      const int gi = m0 + i, gk = k0 + kk;
-      bf16 val = zero;
-      if (gi < g.M && gk < g.K) val = TA ? g.A[(long)gk * g.lda + gi] : g.A[(long)gi * g.lda + gk];
-      As[i * KP + kk] = val;
-    }
-    for (int e = tid; e < BN * BK; e += 256) {
-      int j, kk;
-      if (!TB) { kk = e / BN; j = e % BN; } else { j = e / BK; kk = e % BK; }
-      const int gj = n0 + j, gk = k0 + kk;
-      bf16 val = zero;
-      if (gj < g.N && gk < g.K) val = TB ? g.B[(long)gj * g.ldb + gk] : g.B[(long)gk * g.ldb + gj];
-      Bs[j * KP + kk] = val;
+    // 512 chunks of 8 consecutive elements along each operand's contiguous
+    // dimension: 16-byte loads where the chunk is in range (leading
+    // dimensions are multiples of 8), element loads at ragged edges
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+      const int ch = tid + 256 * rep;
+      if (!TA) {  // A[i][k]: contiguous in k
+        const int i = ch >> 2, kc = (ch & 3) * 8, gi = m0 + i, gk = k0 + kc;
+        bf16* dst = As + i * KP + kc;
+        if (gi < g.M && gk + 8 <= g.K) {
+          *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(g.A + (long)gi * g.lda + gk);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) dst[e] = (gi < g.M && gk + e < g.K) ? g.A[(long)gi * g.lda + gk + e] : zero;
+        }
+      } else {    // A stored [k][i]: contiguous in i
+        const int kk = ch >> 4, ic = (ch & 15) * 8, gk = k0 + kk, gi = m0 + ic;
+        if (gk < g.K && gi + 8 <= g.M) {
+          const uint4 v = *reinterpret_cast<const uint4*>(g.A + (long)gk * g.lda + gi);
+          const bf16* pv = reinterpret_cast<const bf16*>(&v);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) As[(ic + e) * KP + kk] = pv[e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            As[(ic + e) * KP + kk] = (gk < g.K && gi + e < g.M) ? g.A[(long)gk * g.lda + gi + e] : zero;
+        }
+      }
+      if (!TB) {  // B[k][j]: contiguous in j
+        const int kk = ch >> 4, jc = (ch & 15) * 8, gk = k0 + kk, gj = n0 + jc;
+        if (gk < g.K && gj + 8 <= g.N) {
+          const uint4 v = *reinterpret_cast<const uint4*>(g.B + (long)gk * g.ldb + gj);
+          const bf16* pv = reinterpret_cast<const bf16*>(&v);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) Bs[(jc + e) * KP + kk] = pv[e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            Bs[(jc + e) * KP + kk] = (gk < g.K && gj + e < g.N) ? g.B[(long)gk * g.ldb + gj + e] : zero;
+        }
+      } else {    // B stored [j][k]: contiguous in k
+        const int j = ch >> 2, kc = (ch & 3) * 8, gj = n0 + j, gk = k0 + kc;
+        bf16* dst = Bs + j * KP + kc;
+        if (gj < g.N && gk + 8 <= g.K) {
+          *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(g.B + (long)gj * g.ldb + gk);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) dst[e] = (gj < g.N && gk + e < g.K) ? g.B[(long)gj * g.ldb + gk + e] : zero;
+        }
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -126,19 +161,25 @@ __global__ void k_input(const float* __restrict__ x, int M, int n_in, const floa
   X0[e] = (bf16)(k < n_in ? (x[(long)i * n_in + k] - mean[k]) / stdv[k] : 0.0f);
 }
 
-// MSE on z-scored targets; writes dL/dpred (BF16) and per-block loss sums.
-__global__ void k_loss(const float* __restrict__ pred, const float* __restrict__ y, int M, int n_out,
+// MSE on z-scored targets; writes dL/dpred (BF16, row stride np, zero in the
+// padding columns) and per-block loss sums.
+__global__ void k_loss(const float* __restrict__ pred, const float* __restrict__ y, int M, int n_out, int np,
                        const float* __restrict__ ymean, const float* __restrict__ ystd, bf16* dpred,
                        float* loss_part) {
   __shared__ float s[256];
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   float l = 0.0f;
-  if (e < (long)M * n_out) {
-    const int j = (int)(e % n_out);
-    const float t = (y[e] - ymean[j]) / ystd[j];
-    const float d = pred[e] - t;
-    l = d * d;
-    dpred[e] = (bf16)(2.0f * d / (float)((long)M * n_out));
+  if (e < (long)M * np) {
+    const int i = (int)(e / np), j = (int)(e % np);
+    if (j < n_out) {
+      const long o = (long)i * n_out + j;
+      const float t = (y[o] - ymean[j]) / ystd[j];
+      const float d = pred[o] - t;
+      l = d * d;
+      dpred[e] = (bf16)(2.0f * d / (float)((long)M * n_out));
+    } else {
+      dpred[e] = (bf16)0.0f;
+    }
   }
   s[threadIdx.x] = l;
   __syncthreads();
@@ -180,10 +221,10 @@ __global__ void k_init_weights(float* w, bf16* wb, long n, float a, uint32_t key
   uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = 0u, c3 = tag, k0 = key0, k1 = key1;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
   }
   const float u = ((float)(c0 >> 8) + 0.5f) * (1.0f / 16777216.0f);
@@ -198,18 +239,19 @@ __global__ void k_ensemble(const float* __restrict__ preds, int E, long per, int
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= per) return;
   const int j = (int)(e % n_out);
-  // two passes: the spread is often far below the mean, where a one-pass
-  // sum of squares would cancel
+  // two passes in normalised units: the spread is often far below the mean
+  // (a one-pass sum of squares would cancel), and de-normalised values
+  // (~1e24 for densities in m^-3) would overflow FP32 when squared
   float s = 0.0f;
-  for (int q = 0; q < E; ++q) s += preds[q * per + e] * ystd[j] + ymean[j];
+  for (int q = 0; q < E; ++q) s += preds[q * per + e];
   const float mu = s / E;
   float s2 = 0.0f;
   for (int q = 0; q < E; ++q) {
-    const float d = preds[q * per + e] * ystd[j] + ymean[j] - mu;
+    const float d = preds[q * per + e] - mu;
     s2 += d * d;
   }
-  mean_out[e] = mu;
-  if (std_out) std_out[e] = E > 1 ? sqrtf(s2 / (E - 1)) : 0.0f;
+  mean_out[e] = mu * ystd[j] + ymean[j];
+  if (std_out) std_out[e] = E > 1 ? sqrtf(s2 / (E - 1)) * ystd[j] : 0.0f;
 }
 
 }  // namespace sg

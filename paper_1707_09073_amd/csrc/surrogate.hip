@@ -32,6 +32,7 @@ struct LayerOff {
 struct SgLayout {
   int L = 0;              // weight layers = depth + 1
   int K0p = 0;            // padded input width
+  int Np = 0;             // padded output width (zero weight columns beyond n_out)
   std::vector<int> K, N;  // per layer
   std::vector<std::vector<LayerOff>> lo;  // [member][layer]
   size_t xmean, xstd, ymean, ystd, X0, preds, dA0, dA1, loss, idx;
@@ -40,8 +41,11 @@ struct SgLayout {
 };
 
 bool sg_valid(const sg_config* c) {
-  return c && c->n_in > 0 && c->n_out > 0 && c->width > 0 && c->depth >= 1 && c->depth <= 16 && c->ensemble >= 1 &&
-         c->ensemble <= 16 && c->max_batch >= 1 && c->max_batch <= 65536;
+  // a width that is a multiple of 8 keeps every GEMM row 16-byte aligned
+  // (the input and output widths are padded internally)
+  return c && c->n_in > 0 && c->n_out > 0 && c->width > 0 && c->width % 8 == 0 &&
+         c->depth >= 1 && c->depth <= 16 && c->ensemble >= 1 && c->ensemble <= 16 && c->max_batch >= 1 &&
+         c->max_batch <= 65536;
 }
 
 SgLayout sg_layout(const sg_config* c) {
@@ -49,9 +53,10 @@ SgLayout sg_layout(const sg_config* c) {
   Lay L;
   s.L = c->depth + 1;
   s.K0p = (c->n_in + 31) / 32 * 32;
+  s.Np = (c->n_out + 7) / 8 * 8;
   for (int l = 0; l < s.L; ++l) {
     s.K.push_back(l == 0 ? s.K0p : c->width);
-    s.N.push_back(l == s.L - 1 ? c->n_out : c->width);
+    s.N.push_back(l == s.L - 1 ? s.Np : c->width);
   }
   s.lo.resize(c->ensemble);
   for (int e = 0; e < c->ensemble; ++e)
@@ -80,10 +85,10 @@ SgLayout sg_layout(const sg_config* c) {
     s.A.push_back(L.take(2 * MB * s.N[l]));
   }
   s.preds = L.take(4 * MB * c->n_out * (size_t)c->ensemble);
-  const size_t wmax = std::max(c->width, c->n_out);
+  const size_t wmax = std::max(c->width, s.Np);
   s.dA0 = L.take(2 * MB * wmax);
   s.dA1 = L.take(2 * MB * wmax);
-  s.loss = L.take(4 * ((MB * c->n_out + 255) / 256 + 1));
+  s.loss = L.take(4 * ((MB * s.Np + 255) / 256 + 1));
   s.idx = 0;
   s.total = L.total;
   return s;
@@ -99,6 +104,7 @@ struct sg_ctx {
   char* ws = nullptr;
   hipStream_t st = nullptr;
   std::vector<int> step;  // Adam step per member
+  bool bad_gemm = false;  // a GEMM was refused (misaligned operands)
   std::string err;
   template <typename T> T* p(size_t o) { return reinterpret_cast<T*>(ws + o); }
 };
@@ -118,6 +124,12 @@ int sfail(sg_ctx* c, int code, const std::string& m) {
 
 template <bool TA, bool TB, int EPI>
 void gemm(sg_ctx* c, const GemmArgs& g) {
+  // the 16-byte tile loads need leading dimensions that are multiples of 8
+  // elements and 16-byte aligned operands (all buffers come from the workspace)
+  if ((g.lda & 7) || (g.ldb & 7) || ((uintptr_t)g.A & 15) || ((uintptr_t)g.B & 15)) {
+    c->bad_gemm = true;
+    return;
+  }
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM);
   k_gemm<TA, TB, EPI><<<grid, 256, 0, c->st>>>(g);
 }
@@ -148,7 +160,8 @@ void enqueue_forward(sg_ctx* c, int e, const float* d_x, int batch, float* out) 
       X = c->p<bf16>(s.A[l]);
       ldx = s.N[l];
     } else {
-      g.Cf = out; g.ldcf = s.N[l];
+      g.N = c->c.n_out;  // only the real outputs are written
+      g.Cf = out; g.ldcf = c->c.n_out;
       gemm<false, false, EPI_BIAS>(c, g);
     }
   }
@@ -192,6 +205,23 @@ int sg_init(sg_ctx** out, const sg_config* cfg, void* d_ws, size_t bytes, void* 
   SGCHK(c, hipMemcpyAsync(c->ws + s.xstd, ones_x.data(), 4 * ones_x.size(), hipMemcpyHostToDevice, c->st));
   SGCHK(c, hipMemcpyAsync(c->ws + s.ystd, ones_y.data(), 4 * ones_y.size(), hipMemcpyHostToDevice, c->st));
   for (int e = 0; e < cfg->ensemble; ++e) {
+    const int L1 = s.L - 1;
+    if (s.Np > cfg->n_out) {
+      const size_t n = (size_t)s.K[L1] * s.Np;
+      std::vector<float> w(n);
+      SGCHK(c, hipMemcpyAsync(w.data(), c->ws + s.lo[e][L1].W, 4 * n, hipMemcpyDeviceToHost, c->st));
+      SGCHK(c, hipStreamSynchronize(c->st));
+      std::vector<uint16_t> wb(n);
+      for (size_t i = 0; i < n; ++i) {
+        if ((int)(i % s.Np) >= cfg->n_out) w[i] = 0.0f;
+        uint32_t u;
+        std::memcpy(&u, &w[i], 4);
+        wb[i] = (uint16_t)((u + ((u >> 16) & 1u) + 0x7FFFu) >> 16);
+      }
+      SGCHK(c, hipMemcpyAsync(c->ws + s.lo[e][L1].W, w.data(), 4 * n, hipMemcpyHostToDevice, c->st));
+      SGCHK(c, hipMemcpyAsync(c->ws + s.lo[e][L1].Wb, wb.data(), 2 * n, hipMemcpyHostToDevice, c->st));
+      SGCHK(c, hipStreamSynchronize(c->st));
+    }
     const int pad = s.K0p - cfg->n_in;
     if (pad > 0) {
       std::vector<float> z((size_t)pad * s.N[0], 0.0f);
@@ -219,9 +249,20 @@ const char* sg_last_error(const sg_ctx* c) { return c ? c->err.c_str() : "null c
 int sg_layer_dims(const sg_ctx* c, int layer, int* K, int* N) {
   if (!c || layer < 0 || layer >= c->s.L) return MC_E_ARG;
   if (K) *K = c->s.K[layer];
-  if (N) *N = c->s.N[layer];
+  if (N) *N = layer == c->s.L - 1 ? c->c.n_out : c->s.N[layer];
   return MC_OK;
 }
+
+namespace {
+// copy a [K][Nint] device matrix to a [K][Next] host matrix (Next <= Nint)
+int get_strided(sg_ctx* c, size_t off, int K, int Nint, int Next, float* h) {
+  std::vector<float> t((size_t)K * Nint);
+  SGCHK(c, hipMemcpyAsync(t.data(), c->ws + off, 4 * t.size(), hipMemcpyDeviceToHost, c->st));
+  SGCHK(c, hipStreamSynchronize(c->st));
+  for (int k = 0; k < K; ++k) std::memcpy(h + (size_t)k * Next, t.data() + (size_t)k * Nint, 4 * (size_t)Next);
+  return MC_OK;
+}
+}  // namespace
 
 int sg_set_normalization(sg_ctx* c, const float* xm, const float* xs, const float* ym, const float* ys) {
   if (!c || !xm || !xs || !ym || !ys) return MC_E_ARG;
@@ -243,6 +284,7 @@ int sg_forward(sg_ctx* c, int member, const float* d_x, int batch, float* d_pred
     return sfail(c, MC_E_ARG, "bad argument");
   enqueue_forward(c, member, d_x, batch, d_pred);
   SGCHK(c, hipGetLastError());
+  if (c->bad_gemm) return sfail(c, MC_E_ARG, "GEMM operands not 16-byte aligned");
   return MC_OK;
 }
 
@@ -256,8 +298,8 @@ int sg_backward(sg_ctx* c, int member, const float* d_x, const float* d_y, int b
   const long tot = (long)batch * n_out;
   bf16* dcur = c->p<bf16>(s.dA0);
   bf16* dnext = c->p<bf16>(s.dA1);
-  k_loss<<<blocks(tot), 256, 0, c->st>>>(pred, d_y, batch, n_out, c->p<float>(s.ymean), c->p<float>(s.ystd), dcur,
-                                         c->p<float>(s.loss));
+  k_loss<<<blocks((long)batch * s.Np), 256, 0, c->st>>>(pred, d_y, batch, n_out, s.Np, c->p<float>(s.ymean),
+                                                         c->p<float>(s.ystd), dcur, c->p<float>(s.loss));
   for (int l = s.L - 1; l >= 0; --l) {
     const LayerOff& o = s.lo[member][l];
     const bf16* Xin = l == 0 ? c->p<bf16>(s.X0) : c->p<bf16>(s.A[l - 1]);
@@ -277,8 +319,9 @@ int sg_backward(sg_ctx* c, int member, const float* d_x, const float* d_y, int b
     }
   }
   SGCHK(c, hipGetLastError());
+  if (c->bad_gemm) return sfail(c, MC_E_ARG, "GEMM operands not 16-byte aligned");
   if (h_loss) {
-    const int nb = (int)blocks(tot);
+    const int nb = (int)blocks((long)batch * s.Np);
     std::vector<float> part(nb);
     SGCHK(c, hipMemcpyAsync(part.data(), c->p<float>(s.loss), 4 * (size_t)nb, hipMemcpyDeviceToHost, c->st));
     SGCHK(c, hipStreamSynchronize(c->st));
@@ -323,15 +366,20 @@ int sg_predict(sg_ctx* c, const float* d_x, int batch, float* d_mean, float* d_s
   k_ensemble<<<blocks(per), 256, 0, c->st>>>(c->p<float>(s.preds), c->c.ensemble, per, c->c.n_out,
                                              c->p<float>(s.ymean), c->p<float>(s.ystd), d_mean, d_std);
   SGCHK(c, hipGetLastError());
+  if (c->bad_gemm) return sfail(c, MC_E_ARG, "GEMM operands not 16-byte aligned");
   return MC_OK;
 }
 
 int sg_get_params(sg_ctx* c, int member, int layer, float* h_W, float* h_b) {
   if (!c || member < 0 || member >= c->c.ensemble || layer < 0 || layer >= c->s.L) return MC_E_ARG;
   const LayerOff& o = c->s.lo[member][layer];
-  const size_t n = (size_t)c->s.K[layer] * c->s.N[layer];
-  if (h_W) SGCHK(c, hipMemcpyAsync(h_W, c->ws + o.W, 4 * n, hipMemcpyDeviceToHost, c->st));
-  if (h_b) SGCHK(c, hipMemcpyAsync(h_b, c->ws + o.b, 4 * (size_t)c->s.N[layer], hipMemcpyDeviceToHost, c->st));
+  int N = 0;
+  sg_layer_dims(c, layer, nullptr, &N);
+  if (h_W) {
+    const int rc = get_strided(c, o.W, c->s.K[layer], c->s.N[layer], N, h_W);
+    if (rc != MC_OK) return rc;
+  }
+  if (h_b) SGCHK(c, hipMemcpyAsync(h_b, c->ws + o.b, 4 * (size_t)N, hipMemcpyDeviceToHost, c->st));
   SGCHK(c, hipStreamSynchronize(c->st));
   return MC_OK;
 }
@@ -339,10 +387,16 @@ int sg_get_params(sg_ctx* c, int member, int layer, float* h_W, float* h_b) {
 int sg_set_params(sg_ctx* c, int member, int layer, const float* h_W, const float* h_b) {
   if (!c || member < 0 || member >= c->c.ensemble || layer < 0 || layer >= c->s.L || !h_W || !h_b) return MC_E_ARG;
   const LayerOff& o = c->s.lo[member][layer];
-  const size_t n = (size_t)c->s.K[layer] * c->s.N[layer];
-  std::vector<float> w(h_W, h_W + n);
+  int N = 0;
+  sg_layer_dims(c, layer, nullptr, &N);
+  const int Ni = c->s.N[layer];
+  const size_t n = (size_t)c->s.K[layer] * Ni;
+  std::vector<float> w(n, 0.0f);
+  for (int k = 0; k < c->s.K[layer]; ++k) std::memcpy(w.data() + (size_t)k * Ni, h_W + (size_t)k * N, 4 * (size_t)N);
   if (layer == 0)
     for (size_t i = (size_t)c->c.n_in * c->s.N[0]; i < n; ++i) w[i] = 0.0f;
+  std::vector<float> bb(Ni, 0.0f);
+  std::memcpy(bb.data(), h_b, 4 * (size_t)N);
   std::vector<uint16_t> wb(n);
   for (size_t i = 0; i < n; ++i) {
     // round to nearest even BF16
@@ -353,7 +407,7 @@ int sg_set_params(sg_ctx* c, int member, int layer, const float* h_W, const floa
   }
   SGCHK(c, hipMemcpyAsync(c->ws + o.W, w.data(), 4 * n, hipMemcpyHostToDevice, c->st));
   SGCHK(c, hipMemcpyAsync(c->ws + o.Wb, wb.data(), 2 * n, hipMemcpyHostToDevice, c->st));
-  SGCHK(c, hipMemcpyAsync(c->ws + o.b, h_b, 4 * (size_t)c->s.N[layer], hipMemcpyHostToDevice, c->st));
+  SGCHK(c, hipMemcpyAsync(c->ws + o.b, bb.data(), 4 * (size_t)Ni, hipMemcpyHostToDevice, c->st));
   SGCHK(c, hipStreamSynchronize(c->st));
   return MC_OK;
 }
@@ -361,9 +415,13 @@ int sg_set_params(sg_ctx* c, int member, int layer, const float* h_W, const floa
 int sg_get_grads(sg_ctx* c, int member, int layer, float* h_dW, float* h_db) {
   if (!c || member < 0 || member >= c->c.ensemble || layer < 0 || layer >= c->s.L) return MC_E_ARG;
   const LayerOff& o = c->s.lo[member][layer];
-  const size_t n = (size_t)c->s.K[layer] * c->s.N[layer];
-  if (h_dW) SGCHK(c, hipMemcpyAsync(h_dW, c->ws + o.dW, 4 * n, hipMemcpyDeviceToHost, c->st));
-  if (h_db) SGCHK(c, hipMemcpyAsync(h_db, c->ws + o.db, 4 * (size_t)c->s.N[layer], hipMemcpyDeviceToHost, c->st));
+  int N = 0;
+  sg_layer_dims(c, layer, nullptr, &N);
+  if (h_dW) {
+    const int rc = get_strided(c, o.dW, c->s.K[layer], c->s.N[layer], N, h_dW);
+    if (rc != MC_OK) return rc;
+  }
+  if (h_db) SGCHK(c, hipMemcpyAsync(h_db, c->ws + o.db, 4 * (size_t)N, hipMemcpyDeviceToHost, c->st));
   SGCHK(c, hipStreamSynchronize(c->st));
   return MC_OK;
 }

@@ -60,6 +60,7 @@ def generate(cfgs: list[dict], warm_intervals: int, window_intervals: int, max_i
 
 def rel_l2(pred: np.ndarray, ref: np.ndarray) -> np.ndarray:
     """Relative L2 error per row of each map (heat, density): shape [n, 2]."""
+    pred, ref = np.asarray(pred, np.float64), np.asarray(ref, np.float64)
     out = np.zeros((pred.shape[0], 2))
     for k, sl in enumerate((slice(0, N_CELL), slice(N_CELL, 2 * N_CELL))):
         out[:, k] = np.linalg.norm(pred[:, sl] - ref[:, sl], axis=1) / np.maximum(
@@ -83,9 +84,11 @@ class Surrogate:
     def fit(self, X: np.ndarray, Y: np.ndarray, epochs: int = 200, batch: int = 128, lr: float = 1e-3,
             seed: int = 0, log=print) -> list[float]:
         import torch
-        xm, xs = X.mean(0), X.std(0)
+        # statistics in FP64: densities (~1e24 m^-3) overflow FP32 when squared
+        X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+        xm, xs = X64.mean(0), X64.std(0)
         xs = np.where(xs > 1e-6 * np.maximum(1.0, np.abs(xm)), xs, 1.0)
-        ym, ys = Y.mean(0), Y.std(0)
+        ym, ys = Y64.mean(0), Y64.std(0)
         ys = np.where(ys > 1e-6 * np.maximum(1.0, np.abs(ym)), ys, np.maximum(1.0, np.abs(ym)))
         self.net.sg_set_normalization(xm, xs, ym, ys)
         self.box = (X.min(0), X.max(0))
@@ -124,6 +127,7 @@ class Surrogate:
     def spread(self, mean: np.ndarray, std: np.ndarray) -> np.ndarray:
         """Raw predicted error per row: the ensemble's relative spread, the
         larger of the two maps."""
+        mean, std = np.asarray(mean, np.float64), np.asarray(std, np.float64)
         return np.maximum(np.linalg.norm(std[:, :N_CELL], axis=1) / np.maximum(np.linalg.norm(mean[:, :N_CELL], axis=1), 1e-300),
                           np.linalg.norm(std[:, N_CELL:], axis=1) / np.maximum(np.linalg.norm(mean[:, N_CELL:], axis=1), 1e-300))
 
