@@ -31,7 +31,7 @@ struct Layout {
 
 struct Offsets {
   size_t table64, table32, fac64, fac32, field64, field32, phi, gamma64, gamma32, Tcell, count, heat, dens,
-      counters, flags, ctl, next_id, ip, tiles, partial, acc, tile_dead, tile_off, plan, minv, ainv, rhs, hist, reps,
+      counters, flags, ctl, next_id, ip, tiles, partial, acc, tile_dead, tile_off, plan, slots, minv, ainv, rhs, hist, reps,
       nrep, bpart;
   size_t kx, ky, kz, x, y, z, meta;
 };
@@ -136,6 +136,7 @@ Offsets layout(const mc_config* c, int n, size_t* total) {
   o.tile_dead = L.take(sizeof(uint32_t) * max_tiles);
   o.tile_off = L.take(sizeof(uint32_t) * max_tiles);
   o.plan = L.take(sizeof(Plan) * n);
+  o.slots = L.take(dev ? sizeof(uint32_t) * cap : 0);  // contact-refill slot list
   o.minv = L.take(dev ? sizeof(double) * c[0].n_cells[0] * (size_t)(c[0].n_cells[1] * c[0].n_cells[2]) *
                             (c[0].n_cells[1] * c[0].n_cells[2])
                       : 0);
@@ -169,6 +170,7 @@ struct mc_ctx {
   Offsets o;
   int nb = 0, ncell = 1, nx = 1, ny = 1, nz = 1, P = 1;
   int block = 256, tile = 0, n_tiles = 0;
+  unsigned inj_blocks = 0;  // refill grid: covers the most electrons one instance can need
   size_t total_cap = 0;
   std::vector<long long> base;
   std::vector<InstParams> ip;
@@ -319,19 +321,26 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
                                              c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.next_id),
                                              c->p<unsigned long long>(c->o.counters), c->p<int>(c->o.flags),
                                              c->p<uint32_t>(c->o.ctl));
+  k_inject_slots<<<c->n_tiles, 256, 0, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip),
+                                                c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
+                                                c->p<uint32_t>(c->o.tile_dead), c->p<uint32_t>(c->o.meta),
+                                                c->p<uint32_t>(c->o.slots));
   const double mg1 = c->cfg[0].mat.m_eff[0];
-  if (c->f32)
-    k_inject_write<float><<<c->n_tiles, 64, 0, c->st>>>(
-        c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip), c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
-        c->p<uint32_t>(c->o.tile_dead), c->p<double>(c->o.Tcell), c->G32, mg1, c->ck, c->p<float>(c->o.kx), c->p<float>(c->o.ky),
-        c->p<float>(c->o.kz), c->p<float>(c->o.x), c->p<float>(c->o.y), c->p<float>(c->o.z),
-        c->p<uint32_t>(c->o.meta));
-  else
-    k_inject_write<double><<<c->n_tiles, 64, 0, c->st>>>(
-        c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip), c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
-        c->p<uint32_t>(c->o.tile_dead), c->p<double>(c->o.Tcell), c->G64, mg1, c->ck, c->p<double>(c->o.kx), c->p<double>(c->o.ky),
-        c->p<double>(c->o.kz), c->p<double>(c->o.x), c->p<double>(c->o.y), c->p<double>(c->o.z),
-        c->p<uint32_t>(c->o.meta));
+  if (c->inj_blocks > 0) {
+    dim3 gi(c->inj_blocks, c->n_inst);
+    if (c->f32)
+      k_inject_fill<float><<<gi, 256, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->p<Plan>(c->o.plan),
+                                                  c->p<uint32_t>(c->o.slots), c->p<double>(c->o.Tcell), c->G32, mg1,
+                                                  c->ck, c->p<float>(c->o.kx), c->p<float>(c->o.ky),
+                                                  c->p<float>(c->o.kz), c->p<float>(c->o.x), c->p<float>(c->o.y),
+                                                  c->p<float>(c->o.z), c->p<uint32_t>(c->o.meta));
+    else
+      k_inject_fill<double><<<gi, 256, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->p<Plan>(c->o.plan),
+                                                   c->p<uint32_t>(c->o.slots), c->p<double>(c->o.Tcell), c->G64, mg1,
+                                                   c->ck, c->p<double>(c->o.kx), c->p<double>(c->o.ky),
+                                                   c->p<double>(c->o.kz), c->p<double>(c->o.x), c->p<double>(c->o.y),
+                                                   c->p<double>(c->o.z), c->p<uint32_t>(c->o.meta));
+  }
   dim3 gc((nc + 255) / 256, c->n_inst);
   k_poisson_rhs<<<gc, 256, 0, c->st>>>(c->pg, c->p<InstParams>(c->o.ip), c->p<uint32_t>(c->o.count),
                                        c->p<double>(c->o.rhs), c->p<unsigned long long>(c->o.dens),
@@ -487,6 +496,14 @@ int mc_init(mc_ctx** out, const mc_config* cfgs, int n, void* d_ws, size_t ws_by
     for (int q = 0; q < c->ncell; ++q) c->Tcell[i][q] = k.T0_K;
   }
   c->total_cap = (size_t)base;
+  if (c->dev) {
+    // an instance places at most 2P*target electrons (all contact subcells
+    // empty) and never more than its free slots
+    long long qmax = 0;
+    for (int i = 0; i < n; ++i)
+      qmax = std::max(qmax, std::min<long long>(cfgs[i].capacity, 2LL * c->P * std::max(0, c->ip[i].target)));
+    c->inj_blocks = (unsigned)((qmax + 255) / 256);
+  }
   int rc;
   HIPCHK(c, hipMemsetAsync(c->ws, 0, need, c->st));
   if ((rc = upload_tiles(c)) != MC_OK) { *out = c; return rc; }

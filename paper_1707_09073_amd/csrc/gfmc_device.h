@@ -65,6 +65,8 @@ template <> struct Ar<double> {
   __device__ static double em1(double x) { return expm1(x); }
   __device__ static double l1p(double x) { return log1p(x); }
   __device__ static double fl(double x) { return floor(x); }
+  // position -> cell coordinate: a correctly rounded division in FP64
+  __device__ static double cs(double x, double d, double) { return x / d; }
 };
 template <> struct Ar<float> {
   // 23 random bits so that (w + 1/2) 2^-23 is exact and lies in (0, 1)
@@ -85,7 +87,28 @@ template <> struct Ar<float> {
   // log(1 + x) for x >= 0 (the argument here is 2 xi >> 0)
   __device__ static float l1p(float x) { return __builtin_amdgcn_logf(1.0f + x) * 0.693147180559945f; }
   __device__ static float fl(float x) { return floorf(x); }
+  __device__ static float cs(float x, float, float inv_d) { return x * inv_d; }
 };
+
+// Row loads of 16-byte vectors (rows are 16-byte aligned).
+template <typename T, int N>
+__device__ __forceinline__ void load_row(const T* p, T* out);
+template <int N>
+__device__ __forceinline__ void load_row(const float* p, float* out) {
+#pragma unroll
+  for (int i = 0; i < N / 4; ++i) {
+    const float4 v = reinterpret_cast<const float4*>(p)[i];
+    out[4 * i] = v.x; out[4 * i + 1] = v.y; out[4 * i + 2] = v.z; out[4 * i + 3] = v.w;
+  }
+}
+template <int N>
+__device__ __forceinline__ void load_row(const double* p, double* out) {
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const double2 v = reinterpret_cast<const double2*>(p)[i];
+    out[2 * i] = v.x; out[2 * i + 1] = v.y;
+  }
+}
 
 // Material constants in MC units, one precision.
 template <typename T>
@@ -125,9 +148,9 @@ __device__ __forceinline__ T vel_factor(const Mat<T>& M, int v, T E) {
 template <typename T>
 __device__ __forceinline__ int cell_of(const Geo<T>& G, T x, T y, T z) {
   // clamp in floating point first so non-finite input still lands in range
-  T fx = Ar<T>::fl(Ar<T>::dv(x, G.d[0]));
-  T fy = Ar<T>::fl(Ar<T>::dv(y, G.d[1]));
-  T fz = Ar<T>::fl(Ar<T>::dv(z, G.d[2]));
+  T fx = Ar<T>::fl(Ar<T>::cs(x, G.d[0], G.inv_d[0]));
+  T fy = Ar<T>::fl(Ar<T>::cs(y, G.d[1], G.inv_d[1]));
+  T fz = Ar<T>::fl(Ar<T>::cs(z, G.d[2], G.inv_d[2]));
   fx = fmin(fmax(fx, (T)0), (T)(G.nx - 1));
   fy = fmin(fmax(fy, (T)0), (T)(G.ny - 1));
   fz = fmin(fmax(fz, (T)0), (T)(G.nz - 1));

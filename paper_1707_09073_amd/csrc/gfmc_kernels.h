@@ -294,6 +294,122 @@ __global__ void __launch_bounds__(512) k_flight(FlightArgs<T> a) {
   }
 }
 
+// Scattering with the electron's kinetic energy E already known (kept by the
+// lane between drift and scatter instead of being recomputed from k).  Table,
+// factor and field rows are read as 16-byte vectors.  Real events of valley
+// Gamma1 are counted in the lane's registers (rc), the rare upper-valley
+// events by LDS atomics.  Returns the mechanism (-1 self) and updates E.
+template <typename T>
+__device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* frow, const T* gam, int& v, T& kx, T& ky,
+                                         T& kz, T& E, const uint4 w, int cell, int ncell, Cnt& c, uint32_t* sh_heat,
+                                         uint32_t* sh_real, uint32_t* rc) {
+  const Mat<T>& M = a.M;
+  const T eb = Ar<T>::dv(E, a.dE);
+  int b;
+  if (!(eb < (T)a.nb)) { b = a.nb - 1; c.ovf++; }
+  else b = (int)eb;
+  T Sr[kTRow], f[kFRow];
+  load_row<kTRow>(a.table + ((size_t)v * a.nb + b) * kTRow, Sr);
+  load_row<kFRow>(frow, f);
+  const T rs = Ar<T>::u01(w.y) * gam[v];
+  T cum = (T)0;
+  int m = -1;
+#pragma unroll
+  for (int q = 0; q < kNM; ++q) {
+    cum += tab_term<T>(Sr, f, q);
+    if (m < 0 && rs < cum) m = q;
+  }
+  c.sel++;
+  if (m < 0) { c.self++; return -1; }
+  int vp = v;
+  T Ep;
+  if (m <= 1) Ep = E;
+  else if (m == 2) Ep = E + M.hw_lo;
+  else if (m == 3) Ep = E - M.hw_lo;
+  else {
+    vp = (m - 4) >> 1;
+    Ep = E + M.Ec[v] - M.Ec[vp] + (((m - 4) & 1) ? -M.hw_iv : M.hw_iv);
+  }
+  if (!(Ep > (T)0)) { c.self++; return -1; }
+  if (v == 0) {
+#pragma unroll
+    for (int q = 0; q < kNM; ++q) rc[q] += (m == q) ? 1u : 0u;
+  } else {
+    atomicAdd(sh_real + v * kNM + m, 1u);
+  }
+  if (m == 3) atomicAdd(sh_heat + cell, 1u);
+  else if (m == 2) atomicAdd(sh_heat + ncell + cell, 1u);
+  else if (m >= 4) atomicAdd(sh_heat + (((m - 4) & 1) ? 2 : 3) * ncell + cell, 1u);
+  const T k2 = kx * kx + ky * ky + kz * kz;
+  const T g = E * ((T)1 + M.alpha[v] * E);
+  const T u2 = Ar<T>::u01(w.z), u3 = Ar<T>::u01(w.w);
+  T X;
+  if (m == 1) {
+    const T a4 = Ar<T>::dv((T)4 * k2, f[6]);
+    X = Ar<T>::dv((T)2 * u2, (T)1 + ((T)1 - u2) * a4);
+  } else if (m == 2 || m == 3) {
+    const T gp = Ep * ((T)1 + M.alpha[v] * Ep);
+    const T sg = Ar<T>::sq(g), sgp = Ar<T>::sq(gp);
+    const T xi = Ar<T>::dv((T)2 * sg * sgp, (sg - sgp) * (sg - sgp));
+    X = Ar<T>::dv(Ar<T>::em1(u2 * Ar<T>::l1p((T)2 * xi)), xi);
+  } else {
+    X = (T)2 * u2;
+  }
+  X = fmin(fmax(X, (T)0), (T)2);
+  const T ct = (T)1 - X;
+  const T st = Ar<T>::sq(X * ((T)2 - X));
+  T cp, sp;
+  Ar<T>::cs2pi(u3, cp, sp);
+  const T kn = Ar<T>::sq(k2);
+  T nx = (T)0, ny = (T)0, nz = (T)1;
+  if (kn > (T)0) { nx = Ar<T>::dv(kx, kn); ny = Ar<T>::dv(ky, kn); nz = Ar<T>::dv(kz, kn); }
+  T e1[3], e2[3];
+  onb<T>(nx, ny, nz, e1, e2);
+  const T gpp = Ep * ((T)1 + M.alpha[vp] * Ep);
+  const T kp = Ar<T>::sq(Ar<T>::dv(gpp * M.m[vp], M.ck));
+  kx = kp * (st * cp * e1[0] + st * sp * e2[0] + ct * nx);
+  ky = kp * (st * cp * e1[1] + st * sp * e2[1] + ct * ny);
+  kz = kp * (st * cp * e1[2] + st * sp * e2[2] + ct * nz);
+  v = vp;
+  E = Ep;
+  return m;
+}
+
+// Free flight with the energy E of the initial k known; on return E is the
+// energy of the final k (needed by the next scattering).
+template <typename T, bool DEV>
+__device__ __forceinline__ int drift_e(const FlightArgs<T>& a, int v, T dt, T fx, T fy, T fz, T& kx, T& ky, T& kz,
+                                       T& x, T& y, T& z, T& E, Cnt& c) {
+  const Mat<T>& M = a.M;
+  const T k1x = kx - M.cf * fx * dt, k1y = ky - M.cf * fy * dt, k1z = kz - M.cf * fz * dt;
+  const T E1 = energy(M, v, k1x, k1y, k1z);
+  if (DEV) {
+    const T s0 = vel_factor(M, v, E);
+    const T s1 = vel_factor(M, v, E1);
+    x += (T)0.5 * dt * (s0 * kx + s1 * k1x);
+    y += (T)0.5 * dt * (s0 * ky + s1 * k1y);
+    z += (T)0.5 * dt * (s0 * kz + s1 * k1z);
+  }
+  kx = k1x; ky = k1y; kz = k1z;
+  E = E1;
+  if (!DEV) return -1;
+  if (x < (T)0) return 0;
+  if (x > a.G.L[0]) return 1;
+  {
+    const T L = a.G.L[1];
+    int guard = 0;
+    while ((y < (T)0 || y > L) && guard < 8) { y = y < (T)0 ? -y : (T)2 * L - y; ky = -ky; ++guard; }
+    if (y < (T)0 || y > L) { y = y < (T)0 ? (T)0 : L; c.refl++; }
+  }
+  {
+    const T L = a.G.L[2];
+    int guard = 0;
+    while ((z < (T)0 || z > L) && guard < 8) { z = z < (T)0 ? -z : (T)2 * L - z; kz = -kz; ++guard; }
+    if (z < (T)0 || z > L) { z = z < (T)0 ? (T)0 : L; c.refl++; }
+  }
+  return -1;
+}
+
 // Lane-refill variant: each lane works one segment per iteration (the start
 // of an electron's interval, or one scattering event plus the next flight)
 // and pulls the next electron of the tile from a workgroup queue as soon as
@@ -324,9 +440,12 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
   bool guard_hit = false, nan_hit = false;
   bool has = false, exhausted = false;
   long long p = 0;
-  T kx = (T)0, ky = (T)0, kz = (T)0, x = (T)0, y = (T)0, z = (T)0, t = (T)0;
+  T kx = (T)0, ky = (T)0, kz = (T)0, x = (T)0, y = (T)0, z = (T)0, t = (T)0, E = (T)0;
   int v = 0;
   uint32_t id = 0, j = 0;
+  uint32_t rc[kNM];
+#pragma unroll
+  for (int q = 0; q < kNM; ++q) rc[q] = 0u;
   for (;;) {
     // refill: lanes without an electron take the next live slots of the tile
     bool want = !has && !exhausted;
@@ -350,6 +469,7 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
             id = meta_id(meta);
             j = 0;
             t = (T)0;
+            E = energy(a.M, v, kx, ky, kz);
           } else {
             c.dead++;
           }
@@ -364,11 +484,12 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
     if (has) {
       const uint4 w = philox(id, n_int, j, P.tagw, P.key0, P.key1);
       int cell = DEV ? cell_of(a.G, x, y, z) : 0;
-      if (j > 0) scatter<T>(a, fac + kFRow * cell, gam, v, kx, ky, kz, w, cell, ncell, c, sh_heat, sh_real);
+      if (j > 0) scatter_e<T>(a, fac + kFRow * cell, gam, v, kx, ky, kz, E, w, cell, ncell, c, sh_heat, sh_real, rc);
       const T tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), gam[v]);
-      const T* F = field + 4 * cell;
+      T F[4];
+      load_row<4>(field + 4 * cell, F);
       const bool last = t + tau >= a.TP;
-      const int ex = drift<T, DEV>(a, v, last ? a.TP - t : tau, F[0], F[1], F[2], kx, ky, kz, x, y, z, c);
+      const int ex = drift_e<T, DEV>(a, v, last ? a.TP - t : tau, F[0], F[1], F[2], kx, ky, kz, x, y, z, E, c);
       bool fin = last || ex >= 0;
       if (!fin) {
         t += tau;
@@ -397,6 +518,11 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
     for (int q = 0; q < 8; ++q) {
       const uint32_t s = wave_sum(vals[q]);
       if (lane == 0 && s) atomicAdd(sh_misc + q, s);
+    }
+#pragma unroll
+    for (int q = 0; q < kNM; ++q) {
+      const uint32_t s = wave_sum(rc[q]);
+      if (lane == 0 && s) atomicAdd(sh_real + q, s);
     }
   }
   __syncthreads();
@@ -546,82 +672,125 @@ __global__ void k_inject_plan(const InstParams* __restrict__ ip, int nx, int P, 
   }
 }
 
-// Write the planned electrons into the first free slots of each tile: one
-// wavefront per tile, each lane owning 8 consecutive slots per step (two
-// 16-byte loads of the meta words), a shuffle prefix scan of the lanes' free
-// counts giving every free slot its instance-wide rank q; rank q < Q receives
-// electron q.  No barriers, and the loads of a step are independent.
-template <typename T>
-__global__ void __launch_bounds__(64) k_inject_write(const TileDesc* __restrict__ tiles,
-                                                     const InstParams* __restrict__ ip, const Plan* __restrict__ plan,
-                                                     const uint32_t* __restrict__ tile_off,
-                                                     const uint32_t* __restrict__ tile_dead,
-                                                     const double* __restrict__ Tcell, Geo<T> G, double m_g1,
-                                                     double ck, T* kx, T* ky, T* kz, T* x, T* y, T* z,
-                                                     uint32_t* meta) {
+// Free-slot ranks of one tile (one 256-lane workgroup, 16 consecutive slots
+// per lane and step): a block prefix scan of the lanes' free counts gives
+// every free slot its instance-wide rank q, and the slot of rank q < Q is
+// written to position q of the instance's slot list (relative slot index).
+// Tiles whose first rank is already >= Q, or that hold no free slot, exit.
+__global__ void __launch_bounds__(256) k_inject_slots(const TileDesc* __restrict__ tiles,
+                                                      const InstParams* __restrict__ ip,
+                                                      const Plan* __restrict__ plan,
+                                                      const uint32_t* __restrict__ tile_off,
+                                                      const uint32_t* __restrict__ tile_dead,
+                                                      const uint32_t* __restrict__ meta, uint32_t* slot_list) {
+  __shared__ uint32_t s_wave[4];
   const TileDesc td = tiles[blockIdx.x];
-  const Plan& pl = plan[td.inst];
-  const uint32_t Q = pl.Q;
+  const uint32_t Q = plan[td.inst].Q;
   uint32_t run = tile_off[blockIdx.x];
   if (run >= Q || tile_dead[blockIdx.x] == 0) return;
-  const int lane = threadIdx.x;
-  const InstParams I = ip[td.inst];
-  const int P = G.ny * G.nz;
+  const long long base = ip[td.inst].base;
+  uint32_t* list = slot_list + base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool vec = (td.start & 3) == 0;  // 16-byte aligned meta rows
-  for (int b = 0; b < td.count && run < Q; b += 512) {
-    const int i0 = b + 8 * lane;
-    uint32_t m8[8];
-    if (vec && i0 + 8 <= td.count) {
-      const uint4 a = *reinterpret_cast<const uint4*>(meta + td.start + i0);
-      const uint4 c = *reinterpret_cast<const uint4*>(meta + td.start + i0 + 4);
-      m8[0] = a.x; m8[1] = a.y; m8[2] = a.z; m8[3] = a.w; m8[4] = c.x; m8[5] = c.y; m8[6] = c.z; m8[7] = c.w;
+  for (int b = 0; b < td.count && run < Q; b += 256 * 16) {
+    const int i0 = b + 16 * (int)threadIdx.x;
+    const uint32_t* mp = meta + td.start + i0;
+    uint32_t freem = 0;  // bit e: slot i0 + e is free
+    if (vec && i0 + 16 <= td.count) {
+      uint4 v[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) v[h] = reinterpret_cast<const uint4*>(mp)[h];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        freem |= ((v[h].x & kAlive) ? 0u : 1u) << (4 * h);
+        freem |= ((v[h].y & kAlive) ? 0u : 1u) << (4 * h + 1);
+        freem |= ((v[h].z & kAlive) ? 0u : 1u) << (4 * h + 2);
+        freem |= ((v[h].w & kAlive) ? 0u : 1u) << (4 * h + 3);
+      }
     } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) m8[e] = i0 + e < td.count ? meta[td.start + i0 + e] : kAlive;
+      for (int e = 0; e < 16; ++e)
+        if (i0 + e < td.count && !(mp[e] & kAlive)) freem |= 1u << e;
     }
-    uint32_t nd = 0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) nd += (m8[e] & kAlive) ? 0u : 1u;
+    const uint32_t nd = (uint32_t)__popc(freem);
     uint32_t inc = nd;  // inclusive scan over the wavefront
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t v = __shfl_up(inc, o);
-      if (lane >= o) inc += v;
+      const uint32_t y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
     }
-    uint32_t q = run + inc - nd;
-    run += __shfl(inc, 63);
-    for (int e = 0; e < 8 && q < Q; ++e) {
-      if (m8[e] & kAlive) continue;
-      const long long p = td.start + i0 + e;
-      int l = -1;
-      for (int t = 0; t < 2 * P; ++t)
-        if (q >= pl.off[t] && q < pl.off[t] + pl.need[t]) { l = t; break; }
-      if (l >= 0) {
-        const int side = l >= P ? 1 : 0;
-        const int lc = side ? l - P : l;
-        const int cell = side ? (G.nx - 1) * P + lc : lc;
-        const uint32_t ii = q - pl.off[l];
-        const uint4 w = philox((uint32_t)cell, pl.u, ii, I.tagw | 2u, I.key0, I.key1);
-        const double Tc = Tcell[(size_t)td.inst * G.ncell + cell];
-        const T sig = (T)sqrt(m_g1 * kKb * Tc / kQ / (2.0 * ck));
-        const T r1 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.x))),
-                r2 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.z)));
-        T c1, s1, c2, s2;
-        Ar<T>::cs2pi(Ar<T>::u01(w.y), c1, s1);
-        Ar<T>::cs2pi(Ar<T>::u01(w.w), c2, s2);
-        kx[p] = sig * r1 * c1;
-        ky[p] = sig * r1 * s1;
-        kz[p] = sig * r2 * c2;
-        const uint4 w2 = philox((uint32_t)cell, pl.u, ii, I.tagw | 3u, I.key0, I.key1);
-        const int ix = side ? G.nx - 1 : 0, iy = lc / G.nz, iz = lc % G.nz;
-        x[p] = ((T)ix + Ar<T>::u01(w2.x)) * G.d[0];
-        y[p] = ((T)iy + Ar<T>::u01(w2.y)) * G.d[1];
-        z[p] = ((T)iz + Ar<T>::u01(w2.z)) * G.d[2];
-        meta[p] = ((pl.id0 + q) << 3) | kAlive;
-      }
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t t = s_wave[w];
+      before += w < wave ? t : 0u;
+      total += t;
+    }
+    uint32_t q = run + before + inc - nd;
+    while (freem && q < Q) {
+      const int e = __ffs(freem) - 1;
+      freem &= freem - 1;
+      list[q] = (uint32_t)(td.start + i0 + e - base);
       ++q;
     }
+    run += total;
+    __syncthreads();  // s_wave is rewritten by the next step
   }
+}
+
+// Contact refill (one thread per new electron q < Q of instance blockIdx.y):
+// its contact subcell is the first whose cumulative need exceeds q, its
+// wave vector a Maxwellian at that subcell's lattice temperature and its
+// position uniform in the subcell, drawn from the counter (subcell,
+// interval, index within the subcell); it takes slot list[q] and the
+// identity next_id + q.
+template <typename T>
+__global__ void __launch_bounds__(256) k_inject_fill(const InstParams* __restrict__ ip,
+                                                     const Plan* __restrict__ plan,
+                                                     const uint32_t* __restrict__ slot_list,
+                                                     const double* __restrict__ Tcell, Geo<T> G, double m_g1,
+                                                     double ck, T* kx, T* ky, T* kz, T* x, T* y, T* z,
+                                                     uint32_t* meta) {
+  __shared__ uint32_t s_end[64];
+  const int inst = blockIdx.y;
+  const Plan& pl = plan[inst];
+  const uint32_t Q = pl.Q;
+  const uint32_t q0 = blockIdx.x * 256u;
+  if (q0 >= Q) return;
+  const int P = G.ny * G.nz, n2 = 2 * P;
+  if (threadIdx.x < 64) s_end[threadIdx.x] = pl.off[threadIdx.x] + pl.need[threadIdx.x];
+  __syncthreads();
+  const uint32_t q = q0 + threadIdx.x;
+  if (q >= Q) return;
+  int lo = 0, hi = n2 - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (s_end[mid] > q) hi = mid; else lo = mid + 1;
+  }
+  const int l = lo;
+  const InstParams I = ip[inst];
+  const long long p = I.base + slot_list[I.base + q];
+  const int side = l >= P ? 1 : 0;
+  const int lc = side ? l - P : l;
+  const int cell = side ? (G.nx - 1) * P + lc : lc;
+  const uint32_t ii = q - pl.off[l];
+  const uint4 w = philox((uint32_t)cell, pl.u, ii, I.tagw | 2u, I.key0, I.key1);
+  const double Tc = Tcell[(size_t)inst * G.ncell + cell];
+  const T sig = (T)sqrt(m_g1 * kKb * Tc / kQ / (2.0 * ck));
+  const T r1 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.x))), r2 = Ar<T>::sq((T)-2 * Ar<T>::ln(Ar<T>::u01(w.z)));
+  T c1, s1, c2, s2;
+  Ar<T>::cs2pi(Ar<T>::u01(w.y), c1, s1);
+  Ar<T>::cs2pi(Ar<T>::u01(w.w), c2, s2);
+  kx[p] = sig * r1 * c1;
+  ky[p] = sig * r1 * s1;
+  kz[p] = sig * r2 * c2;
+  const uint4 w2 = philox((uint32_t)cell, pl.u, ii, I.tagw | 3u, I.key0, I.key1);
+  const int ix = side ? G.nx - 1 : 0, iy = lc / G.nz, iz = lc % G.nz;
+  x[p] = ((T)ix + Ar<T>::u01(w2.x)) * G.d[0];
+  y[p] = ((T)iy + Ar<T>::u01(w2.y)) * G.d[1];
+  z[p] = ((T)iz + Ar<T>::u01(w2.z)) * G.d[2];
+  meta[p] = ((pl.id0 + q) << 3) | kAlive;
 }
 
 // Initial Maxwellian ensemble: slot p < N gets identity p.

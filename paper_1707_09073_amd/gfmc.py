@@ -426,6 +426,7 @@ class SurrogateNet:
         self._in()
         self._chk(_sg_lib().sg_backward(self._ctx, int(member), self._ptr(x, b, self.n_in),
                                         self._ptr(y, b, self.n_out), b, C.byref(loss)), "sg_backward")
+        self._out()
         return loss.value
 
     def sg_adam(self, member, lr):
@@ -438,6 +439,9 @@ class SurrogateNet:
         self._chk(_sg_lib().sg_train_step(self._ctx, int(member), self._ptr(x, b, self.n_in),
                                           self._ptr(y, b, self.n_out), b, float(lr),
                                           C.byref(loss) if want_loss else None), "sg_train_step")
+        # the caller's x and y may be freed (and their memory handed out
+        # again on torch's stream) as soon as this returns
+        self._out()
         return loss.value if want_loss else None
 
     def sg_predict(self, x, mean_out, std_out=None):
