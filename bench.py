@@ -25,8 +25,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "electron scatter+flight events/s per MI355X; surrogate vs MC heat-map time @2% err"
 HBM_PEAK_GBS = 8000.0
-# FP32 lane-ops per second: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (no packed math)
+# VALU issue peak in lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz (one non-packed FP32 or integer operation per lane and cycle; the
+# build disables packed FP32 math)
 ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+# Per-segment figures of the particle kernel from its rocprofv3 counter passes
+# (profiles/k_flight_refill_device1e7_counters.md), valid for the kernel
+# sources whose digest is given: VALU lane-instructions issued per free-flight
+# segment (SQ_INSTS_VALU x 64 / segments) and HBM bytes per segment
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a 1 GiB device copy).
+KERNEL_COUNTERS = {"sources_digest": "eb1943372ce3d5bc", "valu_lane_ops_per_segment": 151.5,
+                   "hbm_bytes_per_segment": 9.32, "profile": "profiles/k_flight_refill_device1e7_counters.md"}
+
+
+def _kernel_digest() -> str:
+    import hashlib
+    h = []
+    for f in ("gfmc_kernels.h", "gfmc_device.h"):
+        with open(os.path.join(ROOT, "paper_1707_09073_amd", "csrc", f), "rb") as fh:
+            h.append(hashlib.sha256(fh.read()).hexdigest())
+    return hashlib.sha256("".join(h).encode()).hexdigest()[:16]
 
 
 def _log(*a):
@@ -61,6 +80,66 @@ def cpu_baseline(n_intervals: int = 3) -> dict:
                         f"approximated by the final alive count)"))
 
 
+def sweep64(args) -> dict:
+    """Batched bias sweep: 64 device instances (uneven ensembles of 20k-500k
+    electrons, FP32 state) in one context, one launch per kernel per interval
+    replayed from a hipGraph, against the same 64 bias points run one after
+    another as separate contexts."""
+    import torch
+    from paper_1707_09073_amd import gfmc, workloads as W
+    cfgs = W.bias_sweep(64)
+    K = cfgs[0]["substeps"]
+    n_tot = sum(c["n_particles"] for c in cfgs)
+    _log(f"sweep: 64 instances, {n_tot} electrons in total")
+    ens = gfmc.Ensemble(cfgs, device="cuda:0")
+    ens.mc_step(10 * K)
+    if args.block and args.tile:
+        ens.mc_set_launch(args.block, args.tile)
+    elif not args.no_autotune:
+        from paper_1707_09073_amd.autotune import autotune
+        autotune(ens, log=_log)
+    block, tile, n_tiles = ens.mc_get_launch()
+    # per-kernel split from a few profiled intervals (eager launches)
+    ens.mc_profile(True)
+    ens.mc_profile_read(reset=True)
+    ens.mc_step(10 * K)
+    prof = ens.mc_profile_read(reset=True)
+    ens.mc_profile(False)
+    ens.mc_use_graph(True)
+    ens.mc_step(args.warmup * K)
+    for i in range(64):
+        ens.mc_tally(i, reset_window=(i == 63))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.mc_step(args.steps * K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    segs = sum(ens.mc_tally(i)["segments"] for i in range(64))
+    ens.close()
+    del ens
+    torch.cuda.synchronize()
+    # the same bias points as 64 separate contexts, run back to back
+    sep_steps = max(1, args.steps // 4)
+    sep_wall, sep_segs = 0.0, 0
+    for i, c in enumerate(cfgs):
+        e = gfmc.Ensemble(c, device="cuda:0")
+        e.mc_step(10 * K)
+        e.mc_use_graph(True)
+        e.mc_step(2 * K)
+        e.mc_tally(reset_window=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e.mc_step(sep_steps * K)
+        torch.cuda.synchronize()
+        sep_wall += time.perf_counter() - t0
+        sep_segs += e.mc_tally()["segments"]
+        e.close()
+    return dict(value=segs / wall, ms_per_step=wall / args.steps * 1e3, n_tot=n_tot, block=block, tile=tile,
+                n_tiles=n_tiles, separate_value=sep_segs / sep_wall, separate_steps=sep_steps,
+                flight_ms=prof["flight_ms"] / max(1, prof["n_flight"]),
+                refresh_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +152,8 @@ def main() -> int:
     ap.add_argument("--variant", type=int, default=0, help="particle kernel: 0 lane refill, 1 one electron per lane")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default (or given) launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["device1e7", "sweep64"], default="device1e7",
+                    help="device1e7: one 10M-electron device (the headline); sweep64: 64-instance batched sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration) and exit")
     args = ap.parse_args()
@@ -96,6 +177,20 @@ def main() -> int:
         from paper_1707_09073_amd import build as B
         B.build(force=True)
     torch.cuda.set_device(0)
+    if args.workload == "sweep64":
+        r = sweep64(args)
+        print(json.dumps({
+            "metric": METRIC, "value": r["value"], "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "batched bias sweep: 64 half-nanowire device instances, Vgs U[-3,0] V, "
+                                   "Vds U[1,10] V, doping log-uniform 1e17-1e19 cm^-3, 20k-500k electrons each, "
+                                   "one hipGraph replay per interval", "electrons": r["n_tot"],
+                       "block": r["block"], "tile": r["tile"], "tiles": r["n_tiles"]},
+            "separate_contexts_events_per_s": r["separate_value"], "separate_steps": r["separate_steps"],
+            "batched_over_separate": r["value"] / r["separate_value"],
+            "flight_avg_ms": r["flight_ms"], "refresh_avg_ms": r["refresh_ms"]}), flush=True)
+        return 0
     cfg = W.large_device_config(n_particles=args.particles)
     K = cfg["substeps"]
     _log(f"init: {args.particles} superparticles, capacity {cfg['capacity']}")
@@ -131,16 +226,32 @@ def main() -> int:
 
     roofline = None
     if prof and prof["n_flight"]:
+        # the particle kernel (one launch per interval), timed by HIP events on its stream
         flight_s = prof["flight_ms"] / prof["n_flight"] * 1e-3
+        segs_launch = segments / prof["n_flight"]
         per_launch = proc / prof["n_flight"]
-        # algorithmic HBM bytes per launch: the SoA state (6 x FP32 + u32 meta) read and written once
-        bytes_launch = per_launch * 28 * 2
-        roofline = dict(bound="hbm", achieved=bytes_launch / flight_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=bytes_launch / flight_s / 1e9 / HBM_PEAK_GBS, traffic=None,
-                        kernel="k_flight_refill<float,true>" if args.variant == 0 else "k_flight<float,true>",
-                        avg_launch_ms=flight_s * 1e3,
-                        refresh_avg_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]),
-                        flight_share=prof["flight_ms"] / (prof["flight_ms"] + prof["refresh_ms"]))
+        fresh = _kernel_digest() == KERNEL_COUNTERS["sources_digest"] and args.variant == 0
+        ops = KERNEL_COUNTERS["valu_lane_ops_per_segment"] * segs_launch
+        achieved = ops / flight_s / 1e12
+        # the state stream the fused interval must move: 6 x FP32 + u32 meta per
+        # electron, read and written once per launch
+        state_bytes = per_launch * 28 * 2
+        roofline = dict(
+            bound="alu", achieved=achieved, peak=ALU_PEAK_LANE_OPS / 1e12, unit="TOP/s",
+            frac=achieved / (ALU_PEAK_LANE_OPS / 1e12),
+            traffic=KERNEL_COUNTERS["hbm_bytes_per_segment"] * segs_launch if fresh else None,
+            counters_current=fresh,
+            kernel="k_flight_refill<float,true>" if args.variant == 0 else "k_flight<float,true>",
+            ops_per_segment=KERNEL_COUNTERS["valu_lane_ops_per_segment"], segments_per_launch=segs_launch,
+            avg_launch_ms=flight_s * 1e3,
+            refresh_avg_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]),
+            flight_share=prof["flight_ms"] / (prof["flight_ms"] + prof["refresh_ms"]),
+            hbm_state_stream=dict(achieved=state_bytes / flight_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                                  frac=state_bytes / flight_s / 1e9 / HBM_PEAK_GBS),
+            hbm_per_substep_model=dict(achieved=per_launch * K * 56 / flight_s / 1e9, peak=HBM_PEAK_GBS,
+                                       unit="GB/s", frac=per_launch * K * 56 / flight_s / 1e9 / HBM_PEAK_GBS,
+                                       note="56 B per electron per 1 fs sub-step, as if the state crossed "
+                                            "HBM every sub-step; the kernel fuses the 10 sub-steps"))
     out = {
         "metric": METRIC,
         "value": value,

@@ -880,6 +880,13 @@ void or_set_particles(or_ctx *X, const double *k, const double *r, const int32_t
   for (int p = 0; p < cap; ++p) { X->valley[p] = valley[p]; X->alive[p] = alive[p]; }
   memcpy(X->id, id, sizeof(uint32_t) * cap);
 }
+/* Resume hook: the number of intervals done (the interval index of the
+ * flight streams and of the contact refill) and the next free identity, so
+ * that a state taken from elsewhere continues on the same streams. */
+void or_set_progress(or_ctx *X, int n_done, uint32_t next_id) {
+  X->n_done = n_done;
+  X->next_id = next_id;
+}
 void or_get_fields(const or_ctx *X, double *phi, double *field, uint32_t *count) {
   memcpy(phi, X->phi, sizeof(double) * X->ncell);
   memcpy(field, X->field, sizeof(double) * 3 * X->ncell);

@@ -85,6 +85,7 @@ def lib():
         L.or_factors.argtypes = [C.c_void_p, dp]
         L.or_get_particles.argtypes = [C.c_void_p, dp, dp, i32p, i32p, u32p]
         L.or_set_particles.argtypes = [C.c_void_p, dp, dp, i32p, i32p, u32p]
+        L.or_set_progress.argtypes = [C.c_void_p, C.c_int, C.c_uint32]
         L.or_get_fields.argtypes = [C.c_void_p, dp, dp, u32p]
         L.or_get_counts.argtypes = [C.c_void_p, u64p]
         L.or_get_maps.argtypes = [C.c_void_p, u64p, u64p]
@@ -242,6 +243,10 @@ class Oracle:
         i = np.ascontiguousarray(ident, dtype=np.uint32)
         lib().or_set_particles(self._h, _p(k, C.c_double), _p(r, C.c_double), _p(v, C.c_int32),
                                _p(a, C.c_int32), _p(i, C.c_uint32))
+
+    def set_progress(self, n_done: int, next_id: int):
+        """Continue from interval `n_done` with identities from `next_id`."""
+        lib().or_set_progress(self._h, int(n_done), int(next_id))
 
     def fields(self):
         phi = np.zeros(self.ncell); F = np.zeros((self.ncell, 3)); n = np.zeros(self.ncell, np.uint32)

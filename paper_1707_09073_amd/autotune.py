@@ -11,8 +11,12 @@ from __future__ import annotations
 import json
 import os
 
+# (workgroup size, tile size, kernel variant).  Tile sizes step finely
+# because the last round of resident workgroups is partly idle: the best
+# tile is one whose tile count is just under a multiple of the resident count.
 DEFAULT_CANDIDATES = [
-    (256, 1024, 0), (256, 2048, 0), (256, 4096, 0), (256, 8192, 0),
+    (256, 1536, 0), (256, 2048, 0), (256, 2560, 0), (256, 3072, 0), (256, 4096, 0),
+    (256, 5120, 0), (256, 6144, 0), (256, 8192, 0),
     (512, 2048, 0), (512, 4096, 0), (512, 8192, 0),
     (128, 2048, 0), (256, 4096, 1),
 ]

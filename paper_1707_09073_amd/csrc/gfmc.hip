@@ -316,7 +316,7 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
   k_merge_final<<<gm, 256, 0, c->st>>>(c->p<unsigned long long>(c->o.acc), nc, c->p<uint32_t>(c->o.count),
                                        c->p<unsigned long long>(c->o.heat), c->p<uint32_t>(c->o.ctl),
                                        after_flight ? 1 : 0, after_flight ? 1 : 0);
-  k_inject_plan<<<c->n_inst, 64, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->nx, c->P, nc, c->p<uint32_t>(c->o.count),
+  k_inject_plan<<<c->n_inst, kPlanThreads, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->nx, c->P, nc, c->p<uint32_t>(c->o.count),
                                              c->p<uint32_t>(c->o.tile_dead), c->p<uint32_t>(c->o.tile_off),
                                              c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.next_id),
                                              c->p<unsigned long long>(c->o.counters), c->p<int>(c->o.flags),
@@ -345,9 +345,16 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
   k_poisson_rhs<<<gc, 256, 0, c->st>>>(c->pg, c->p<InstParams>(c->o.ip), c->p<uint32_t>(c->o.count),
                                        c->p<double>(c->o.rhs), c->p<unsigned long long>(c->o.dens),
                                        after_flight ? 1 : 0, nc);
-  dim3 gv((nc + 3) / 4, c->n_inst);
-  k_poisson_gemv<<<gv, 256, 0, c->st>>>(c->p<double>(c->o.ainv), c->p<double>(c->o.rhs), nc,
-                                        c->p<double>(c->o.phi));
+  if (c->n_inst == 1) {
+    dim3 gv((nc + 3) / 4, 1);
+    k_poisson_gemv<<<gv, 256, 0, c->st>>>(c->p<double>(c->o.ainv), c->p<double>(c->o.rhs), nc,
+                                          c->p<double>(c->o.phi));
+  } else {
+    const int rows = (nc + kPgR - 1) / kPgR;
+    dim3 gg((rows + 3) / 4, (c->n_inst + kPgG - 1) / kPgG);
+    k_poisson_gemm<<<gg, 256, 0, c->st>>>(c->p<double>(c->o.ainv), c->p<double>(c->o.rhs), nc, c->n_inst,
+                                          c->p<double>(c->o.phi));
+  }
   k_field<<<gc, 256, 0, c->st>>>(c->pg, c->p<InstParams>(c->o.ip), c->p<double>(c->o.phi), nc,
                                  c->p<double>(c->o.field64), c->p<float>(c->o.field32));
 }
@@ -362,7 +369,7 @@ hipEvent_t prof_event(mc_ctx* c) {
 }
 
 void enqueue_interval(mc_ctx* c) {
-  const size_t lds = sizeof(uint32_t) * (5 * c->ncell + 41);
+  const size_t lds = sizeof(uint32_t) * flight_lds_words(c->ncell);
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (c->profile) {
     e0 = prof_event(c); e1 = prof_event(c); e2 = prof_event(c);
@@ -871,7 +878,7 @@ int mc_read_tables(mc_ctx* c, int inst, double* h_shape, double* h_k4, double* h
 
 int mc_set_launch(mc_ctx* c, int block, int tile) {
   if (!c) return MC_E_ARG;
-  if (block < 64 || block > 512 || block % 64 || tile < min_tile(c->cfg[0]) || tile % block)
+  if (block < 64 || block > 512 || block % 64 || tile < min_tile(c->cfg[0]) || tile > kMaxTile || tile % block)
     return fail(c, MC_E_ARG, "unsupported launch shape");
   c->block = block;
   c->tile = tile;

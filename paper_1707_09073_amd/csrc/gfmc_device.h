@@ -127,6 +127,13 @@ struct Geo {
   T L[3], d[3], inv_d[3];
 };
 
+// Per-valley constant for a lane's runtime valley index, by selects: an
+// array of the kernel arguments indexed at run time would be a memory load.
+template <typename T>
+__device__ __forceinline__ T pick3(const T (&a)[3], int v) {
+  return v == 0 ? a[0] : (v == 1 ? a[1] : a[2]);
+}
+
 // Kane: E from gamma = E (1 + a E), positive root, finite at a = 0.
 template <typename T>
 __device__ __forceinline__ T kane_E(T gam, T a) {
@@ -136,13 +143,13 @@ __device__ __forceinline__ T kane_E(T gam, T a) {
 template <typename T>
 __device__ __forceinline__ T energy(const Mat<T>& M, int v, T kx, T ky, T kz) {
   const T k2 = kx * kx + ky * ky + kz * kz;
-  return kane_E(Ar<T>::dv(M.ck * k2, M.m[v]), M.alpha[v]);
+  return kane_E(Ar<T>::dv(M.ck * k2, pick3(M.m, v)), pick3(M.alpha, v));
 }
 
 // group-velocity factor: v = s k with s = hbar / (m (1 + 2 a E)), nm/fs per 1/nm
 template <typename T>
 __device__ __forceinline__ T vel_factor(const Mat<T>& M, int v, T E) {
-  return Ar<T>::dv(M.cv, M.m[v] * ((T)1 + (T)2 * M.alpha[v] * E));
+  return Ar<T>::dv(M.cv, pick3(M.m, v) * ((T)1 + (T)2 * pick3(M.alpha, v) * E));
 }
 
 template <typename T>

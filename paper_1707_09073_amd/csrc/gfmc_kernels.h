@@ -85,13 +85,13 @@ __device__ __forceinline__ void set_flag(int* flags, int inst, int code) { atomi
 // Select a mechanism by u1 Gamma_v against the running sum of the tabulated
 // rates of the cell; apply its final state.  Returns the mechanism, -1 = self.
 template <typename T>
-__device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const T* gam, int& v, T& kx, T& ky,
+__device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const T (&gam)[3], int& v, T& kx, T& ky,
                                        T& kz, const uint4 w, int cell, int ncell, Cnt& c, uint32_t* sh_heat,
                                        uint32_t* sh_real) {
   const Mat<T>& M = a.M;
   const T k2 = kx * kx + ky * ky + kz * kz;
-  const T g = Ar<T>::dv(M.ck * k2, M.m[v]);
-  const T E = kane_E(g, M.alpha[v]);
+  const T g = Ar<T>::dv(M.ck * k2, pick3(M.m, v));
+  const T E = kane_E(g, pick3(M.alpha, v));
   const T eb = Ar<T>::dv(E, a.dE);
   int b;
   if (!(eb < (T)a.nb)) { b = a.nb - 1; c.ovf++; }
@@ -100,7 +100,7 @@ __device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const
   T Sr[11];
 #pragma unroll
   for (int q = 0; q < 11; ++q) Sr[q] = S[q];
-  const T rs = Ar<T>::u01(w.y) * gam[v];
+  const T rs = Ar<T>::u01(w.y) * pick3(gam, v);
   T cum = (T)0;
   int m = -1;
 #pragma unroll
@@ -117,7 +117,7 @@ __device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const
   else if (m == 3) Ep = E - M.hw_lo;
   else {
     vp = (m - 4) >> 1;
-    Ep = E + M.Ec[v] - M.Ec[vp] + (((m - 4) & 1) ? -M.hw_iv : M.hw_iv);
+    Ep = E + pick3(M.Ec, v) - pick3(M.Ec, vp) + (((m - 4) & 1) ? -M.hw_iv : M.hw_iv);
   }
   if (!(Ep > (T)0)) { c.self++; return -1; }
   atomicAdd(sh_real + v * kNM + m, 1u);
@@ -132,7 +132,7 @@ __device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const
     const T a4 = Ar<T>::dv((T)4 * k2, f[6]);
     X = Ar<T>::dv((T)2 * u2, (T)1 + ((T)1 - u2) * a4);
   } else if (m == 2 || m == 3) {
-    const T gp = Ep * ((T)1 + M.alpha[v] * Ep);
+    const T gp = Ep * ((T)1 + pick3(M.alpha, v) * Ep);
     const T sg = Ar<T>::sq(g), sgp = Ar<T>::sq(gp);
     const T xi = Ar<T>::dv((T)2 * sg * sgp, (sg - sgp) * (sg - sgp));
     X = Ar<T>::dv(Ar<T>::em1(u2 * Ar<T>::l1p((T)2 * xi)), xi);
@@ -149,8 +149,8 @@ __device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const
   if (kn > (T)0) { nx = Ar<T>::dv(kx, kn); ny = Ar<T>::dv(ky, kn); nz = Ar<T>::dv(kz, kn); }
   T e1[3], e2[3];
   onb<T>(nx, ny, nz, e1, e2);
-  const T gpp = Ep * ((T)1 + M.alpha[vp] * Ep);
-  const T kp = Ar<T>::sq(Ar<T>::dv(gpp * M.m[vp], M.ck));
+  const T gpp = Ep * ((T)1 + pick3(M.alpha, vp) * Ep);
+  const T kp = Ar<T>::sq(Ar<T>::dv(gpp * pick3(M.m, vp), M.ck));
   kx = kp * (st * cp * e1[0] + st * sp * e2[0] + ct * nx);
   ky = kp * (st * cp * e1[1] + st * sp * e2[1] + ct * ny);
   kz = kp * (st * cp * e1[2] + st * sp * e2[2] + ct * nz);
@@ -196,12 +196,12 @@ __device__ __forceinline__ int drift(const FlightArgs<T>& a, int v, T dt, T fx, 
 // the interval, so the remaining flight time is drawn afresh at its start.
 template <typename T, bool DEV>
 __device__ __forceinline__ bool fly(const FlightArgs<T>& a, const InstParams& P, const T* fac, const T* field,
-                                    const T* gam, uint32_t n_int, int ncell, int& v, uint32_t id, T& kx, T& ky,
+                                    const T (&gam)[3], uint32_t n_int, int ncell, int& v, uint32_t id, T& kx, T& ky,
                                     T& kz, T& x, T& y, T& z, Cnt& c, uint32_t* sh_heat, uint32_t* sh_real,
                                     bool& guard_hit) {
   uint4 w = philox(id, n_int, 0u, P.tagw, P.key0, P.key1);
   T t = (T)0;
-  T tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), gam[v]);
+  T tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), pick3(gam, v));
   uint32_t j = 0;
   for (;;) {
     int cell = DEV ? cell_of(a.G, x, y, z) : 0;
@@ -222,8 +222,24 @@ __device__ __forceinline__ bool fly(const FlightArgs<T>& a, const InstParams& P,
     w = philox(id, n_int, j, P.tagw, P.key0, P.key1);
     if (DEV) cell = cell_of(a.G, x, y, z);
     scatter<T>(a, fac + kFRow * cell, gam, v, kx, ky, kz, w, cell, ncell, c, sh_heat, sh_real);
-    tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), gam[v]);
+    tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), pick3(gam, v));
   }
+}
+
+// LDS histogram of one tile: the electron deposit packed two subcells per
+// word (16-bit halves; a tile holds at most kMaxTile slots, so a half never
+// carries), then the four heat counters per subcell, the per-mechanism
+// counters of the upper valleys (32 words), the event counters (8) and the
+// refill queue head (1).  Packing the deposit keeps the histogram under
+// 32 KB, so five 256-lane workgroups fit one CU.
+constexpr int kMaxTile = 65535;
+__host__ __device__ constexpr int dep_words(int ncell) { return (ncell + 1) / 2; }
+__host__ __device__ constexpr int flight_lds_words(int ncell) { return dep_words(ncell) + 4 * ncell + 41; }
+__device__ __forceinline__ void dep_add(uint32_t* dep, int cell) {
+  atomicAdd(dep + (cell >> 1), 1u << (16 * (cell & 1)));
+}
+__device__ __forceinline__ uint32_t dep_get(const uint32_t* dep, int cell) {
+  return (dep[cell >> 1] >> (16 * (cell & 1))) & 0xffffu;
 }
 
 template <typename T, bool DEV>
@@ -231,17 +247,18 @@ __global__ void __launch_bounds__(512) k_flight(FlightArgs<T> a) {
   extern __shared__ uint32_t sh[];
   const int ncell = DEV ? a.G.ncell : 1;
   uint32_t* sh_dep = sh;
-  uint32_t* sh_heat = sh + ncell;
-  uint32_t* sh_real = sh + 5 * ncell;
+  uint32_t* sh_heat = sh + dep_words(ncell);
+  uint32_t* sh_real = sh_heat + 4 * ncell;
   uint32_t* sh_misc = sh_real + 32;
-  const int nsh = 5 * ncell + 40;
+  const int nsh = flight_lds_words(ncell);
   for (int i = threadIdx.x; i < nsh; i += blockDim.x) sh[i] = 0u;
   __syncthreads();
   const TileDesc td = a.tiles[blockIdx.x];
   const InstParams P = a.ip[td.inst];
   const T* fac = a.fac + (size_t)td.inst * ncell * kFRow;
   const T* field = a.field + (size_t)td.inst * ncell * 4;
-  const T* gam = a.gamma + td.inst * 4;
+  const T* gp = a.gamma + td.inst * 4;
+  const T gam[3] = {gp[0], gp[1], gp[2]};  // workgroup-uniform
   const uint32_t n_int = a.ctl[CTL_INTERVAL];
   Cnt c = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
   bool guard_hit = false, nan_hit = false;
@@ -262,7 +279,7 @@ __global__ void __launch_bounds__(512) k_flight(FlightArgs<T> a) {
     if (DEV) { a.x[p] = x; a.y[p] = y; a.z[p] = z; }
     a.meta[p] = (id << 3) | (alive ? kAlive : 0u) | (uint32_t)v;
     if (!alive) c.dead++;
-    else if (DEV) atomicAdd(sh_dep + cell_of(a.G, x, y, z), 1u);
+    else if (DEV) dep_add(sh_dep, cell_of(a.G, x, y, z));
   }
   if (guard_hit) set_flag(a.flags, td.inst, -4);
   if (nan_hit) set_flag(a.flags, td.inst, -6);
@@ -277,7 +294,8 @@ __global__ void __launch_bounds__(512) k_flight(FlightArgs<T> a) {
   __syncthreads();
   if (DEV) {
     uint32_t* part = a.partial + (size_t)blockIdx.x * 5 * ncell;
-    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x) part[i] = sh[i];
+    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x)
+      part[i] = i < ncell ? dep_get(sh_dep, i) : sh_heat[i - ncell];
   }
   unsigned long long* cnt = a.counters + (size_t)td.inst * kNCnt;
   for (int tid = threadIdx.x; tid < 39; tid += blockDim.x) {
@@ -300,18 +318,11 @@ __global__ void __launch_bounds__(512) k_flight(FlightArgs<T> a) {
 // Gamma1 are counted in the lane's registers (rc), the rare upper-valley
 // events by LDS atomics.  Returns the mechanism (-1 self) and updates E.
 template <typename T>
-__device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* frow, const T* gam, int& v, T& kx, T& ky,
-                                         T& kz, T& E, const uint4 w, int cell, int ncell, Cnt& c, uint32_t* sh_heat,
-                                         uint32_t* sh_real, uint32_t* rc) {
+__device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* Sr, const T* f, const T (&gam)[3], int& v,
+                                         T& kx, T& ky, T& kz, T& E, const uint4 w, int cell, int ncell, Cnt& c,
+                                         uint32_t* sh_heat, uint32_t* sh_real, uint32_t* rc) {
   const Mat<T>& M = a.M;
-  const T eb = Ar<T>::dv(E, a.dE);
-  int b;
-  if (!(eb < (T)a.nb)) { b = a.nb - 1; c.ovf++; }
-  else b = (int)eb;
-  T Sr[kTRow], f[kFRow];
-  load_row<kTRow>(a.table + ((size_t)v * a.nb + b) * kTRow, Sr);
-  load_row<kFRow>(frow, f);
-  const T rs = Ar<T>::u01(w.y) * gam[v];
+  const T rs = Ar<T>::u01(w.y) * pick3(gam, v);
   T cum = (T)0;
   int m = -1;
 #pragma unroll
@@ -328,7 +339,7 @@ __device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* frow, 
   else if (m == 3) Ep = E - M.hw_lo;
   else {
     vp = (m - 4) >> 1;
-    Ep = E + M.Ec[v] - M.Ec[vp] + (((m - 4) & 1) ? -M.hw_iv : M.hw_iv);
+    Ep = E + pick3(M.Ec, v) - pick3(M.Ec, vp) + (((m - 4) & 1) ? -M.hw_iv : M.hw_iv);
   }
   if (!(Ep > (T)0)) { c.self++; return -1; }
   if (v == 0) {
@@ -341,14 +352,14 @@ __device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* frow, 
   else if (m == 2) atomicAdd(sh_heat + ncell + cell, 1u);
   else if (m >= 4) atomicAdd(sh_heat + (((m - 4) & 1) ? 2 : 3) * ncell + cell, 1u);
   const T k2 = kx * kx + ky * ky + kz * kz;
-  const T g = E * ((T)1 + M.alpha[v] * E);
+  const T g = E * ((T)1 + pick3(M.alpha, v) * E);
   const T u2 = Ar<T>::u01(w.z), u3 = Ar<T>::u01(w.w);
   T X;
   if (m == 1) {
     const T a4 = Ar<T>::dv((T)4 * k2, f[6]);
     X = Ar<T>::dv((T)2 * u2, (T)1 + ((T)1 - u2) * a4);
   } else if (m == 2 || m == 3) {
-    const T gp = Ep * ((T)1 + M.alpha[v] * Ep);
+    const T gp = Ep * ((T)1 + pick3(M.alpha, v) * Ep);
     const T sg = Ar<T>::sq(g), sgp = Ar<T>::sq(gp);
     const T xi = Ar<T>::dv((T)2 * sg * sgp, (sg - sgp) * (sg - sgp));
     X = Ar<T>::dv(Ar<T>::em1(u2 * Ar<T>::l1p((T)2 * xi)), xi);
@@ -365,14 +376,29 @@ __device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* frow, 
   if (kn > (T)0) { nx = Ar<T>::dv(kx, kn); ny = Ar<T>::dv(ky, kn); nz = Ar<T>::dv(kz, kn); }
   T e1[3], e2[3];
   onb<T>(nx, ny, nz, e1, e2);
-  const T gpp = Ep * ((T)1 + M.alpha[vp] * Ep);
-  const T kp = Ar<T>::sq(Ar<T>::dv(gpp * M.m[vp], M.ck));
+  const T gpp = Ep * ((T)1 + pick3(M.alpha, vp) * Ep);
+  const T kp = Ar<T>::sq(Ar<T>::dv(gpp * pick3(M.m, vp), M.ck));
   kx = kp * (st * cp * e1[0] + st * sp * e2[0] + ct * nx);
   ky = kp * (st * cp * e1[1] + st * sp * e2[1] + ct * ny);
   kz = kp * (st * cp * e1[2] + st * sp * e2[2] + ct * nz);
   v = vp;
   E = Ep;
   return m;
+}
+
+// Specular reflection at the walls 0 and L of one axis: the first reflection
+// by selects, further ones (a flight longer than the width) in a rare loop,
+// a position still outside after 8 reflections clamped and counted.
+template <typename T>
+__device__ __forceinline__ void reflect(T L, T& y, T& ky, Cnt& c) {
+  const bool lo = y < (T)0, hi = y > L;
+  y = lo ? -y : (hi ? (T)2 * L - y : y);
+  ky = (lo || hi) ? -ky : ky;
+  if (y < (T)0 || y > L) {
+    int guard = 1;
+    while ((y < (T)0 || y > L) && guard < 8) { y = y < (T)0 ? -y : (T)2 * L - y; ky = -ky; ++guard; }
+    if (y < (T)0 || y > L) { y = y < (T)0 ? (T)0 : L; c.refl++; }
+  }
 }
 
 // Free flight with the energy E of the initial k known; on return E is the
@@ -395,18 +421,8 @@ __device__ __forceinline__ int drift_e(const FlightArgs<T>& a, int v, T dt, T fx
   if (!DEV) return -1;
   if (x < (T)0) return 0;
   if (x > a.G.L[0]) return 1;
-  {
-    const T L = a.G.L[1];
-    int guard = 0;
-    while ((y < (T)0 || y > L) && guard < 8) { y = y < (T)0 ? -y : (T)2 * L - y; ky = -ky; ++guard; }
-    if (y < (T)0 || y > L) { y = y < (T)0 ? (T)0 : L; c.refl++; }
-  }
-  {
-    const T L = a.G.L[2];
-    int guard = 0;
-    while ((z < (T)0 || z > L) && guard < 8) { z = z < (T)0 ? -z : (T)2 * L - z; kz = -kz; ++guard; }
-    if (z < (T)0 || z > L) { z = z < (T)0 ? (T)0 : L; c.refl++; }
-  }
+  reflect<T>(a.G.L[1], y, ky, c);
+  reflect<T>(a.G.L[2], z, kz, c);
   return -1;
 }
 
@@ -421,18 +437,19 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
   extern __shared__ uint32_t sh[];
   const int ncell = DEV ? a.G.ncell : 1;
   uint32_t* sh_dep = sh;
-  uint32_t* sh_heat = sh + ncell;
-  uint32_t* sh_real = sh + 5 * ncell;
+  uint32_t* sh_heat = sh + dep_words(ncell);
+  uint32_t* sh_real = sh_heat + 4 * ncell;
   uint32_t* sh_misc = sh_real + 32;
   uint32_t* sh_q = sh_misc + 8;
-  const int nsh = 5 * ncell + 41;
+  const int nsh = flight_lds_words(ncell);
   for (int i = threadIdx.x; i < nsh; i += blockDim.x) sh[i] = 0u;
   __syncthreads();
   const TileDesc td = a.tiles[blockIdx.x];
   const InstParams P = a.ip[td.inst];
   const T* fac = a.fac + (size_t)td.inst * ncell * kFRow;
   const T* field = a.field + (size_t)td.inst * ncell * 4;
-  const T* gam = a.gamma + td.inst * 4;
+  const T* gp = a.gamma + td.inst * 4;
+  const T gam[3] = {gp[0], gp[1], gp[2]};  // workgroup-uniform
   const uint32_t n_int = a.ctl[CTL_INTERVAL];
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = (1ull << lane) - 1ull;
@@ -482,12 +499,25 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
     }
     if (!__any(has)) break;
     if (has) {
-      const uint4 w = philox(id, n_int, j, P.tagw, P.key0, P.key1);
-      int cell = DEV ? cell_of(a.G, x, y, z) : 0;
-      if (j > 0) scatter_e<T>(a, fac + kFRow * cell, gam, v, kx, ky, kz, E, w, cell, ncell, c, sh_heat, sh_real, rc);
-      const T tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), gam[v]);
-      T F[4];
+      // the rate-table row (pre-event valley and energy bin), the cell's
+      // factor row and its field: loads issued before the random numbers,
+      // whose arithmetic then covers their latency (the position does not
+      // change in an event, so the field row serves the flight after it)
+      const int cell = DEV ? cell_of(a.G, x, y, z) : 0;
+      const T eb = Ar<T>::dv(E, a.dE);
+      const bool ovf = !(eb < (T)a.nb);
+      const int bin = (int)fmin(eb, (T)(a.nb - 1));  // NaN -> last bin
+      T Sr[kTRow], f[kFRow], F[4];
+      load_row<kTRow>(a.table + ((size_t)v * a.nb + bin) * kTRow, Sr);
+      load_row<kFRow>(fac + kFRow * cell, f);
       load_row<4>(field + 4 * cell, F);
+      __builtin_amdgcn_sched_barrier(0);  // keep the loads above the generator
+      const uint4 w = philox(id, n_int, j, P.tagw, P.key0, P.key1);
+      if (j > 0) {
+        if (ovf) c.ovf++;
+        scatter_e<T>(a, Sr, f, gam, v, kx, ky, kz, E, w, cell, ncell, c, sh_heat, sh_real, rc);
+      }
+      const T tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), pick3(gam, v));
       const bool last = t + tau >= a.TP;
       const int ex = drift_e<T, DEV>(a, v, last ? a.TP - t : tau, F[0], F[1], F[2], kx, ky, kz, x, y, z, E, c);
       bool fin = last || ex >= 0;
@@ -505,7 +535,7 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
         if (DEV) { a.x[p] = x; a.y[p] = y; a.z[p] = z; }
         a.meta[p] = (id << 3) | (alive ? kAlive : 0u) | (uint32_t)v;
         if (!alive) c.dead++;
-        else if (DEV) atomicAdd(sh_dep + cell_of(a.G, x, y, z), 1u);
+        else if (DEV) dep_add(sh_dep, cell_of(a.G, x, y, z));
         has = false;
       }
     }
@@ -528,7 +558,8 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
   __syncthreads();
   if (DEV) {
     uint32_t* part = a.partial + (size_t)blockIdx.x * 5 * ncell;
-    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x) part[i] = sh[i];
+    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x)
+      part[i] = i < ncell ? dep_get(sh_dep, i) : sh_heat[i - ncell];
   }
   unsigned long long* cnt = a.counters + (size_t)td.inst * kNCnt;
   for (int tid = threadIdx.x; tid < 39; tid += blockDim.x) {
@@ -605,15 +636,49 @@ __global__ void k_deposit(const TileDesc* __restrict__ tiles, const T* __restric
   if (threadIdx.x == 0) tile_dead[blockIdx.x] = sh[5 * ncell];
 }
 
-// Contact refill plan of one instance (one 64-lane workgroup): electrons
-// needed per contact subcell, their offsets, and the free-slot offsets of the
-// instance's tiles.  The q-th new electron takes the q-th free slot.
-__global__ void k_inject_plan(const InstParams* __restrict__ ip, int nx, int P, int ncell, uint32_t* count,
-                              const uint32_t* __restrict__ tile_dead, uint32_t* tile_off, Plan* plan,
-                              uint32_t* next_id, unsigned long long* counters, int* flags, const uint32_t* ctl) {
+// Contact refill plan of one instance (one workgroup of kPlanThreads): the
+// free-slot offsets of the instance's tiles (block-wide exclusive scan, each
+// lane owning a contiguous run of tiles), then, in wavefront 0, the
+// electrons needed per contact subcell and their offsets.  The q-th new
+// electron takes the q-th free slot.
+constexpr int kPlanThreads = 1024;
+__global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* __restrict__ ip, int nx, int P,
+                                                              int ncell, uint32_t* count,
+                                                              const uint32_t* __restrict__ tile_dead,
+                                                              uint32_t* tile_off, Plan* plan, uint32_t* next_id,
+                                                              unsigned long long* counters, int* flags,
+                                                              const uint32_t* ctl) {
+  __shared__ uint32_t s_wave[kPlanThreads / 64];
   const int inst = blockIdx.x;
-  const int l = threadIdx.x;
+  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
   const InstParams& I = ip[inst];
+  // free slots per tile, exclusive prefix over the instance's tiles
+  const int nt = I.t1 - I.t0;
+  const int per = (nt + kPlanThreads - 1) / kPlanThreads;
+  const int ta = I.t0 + tid * per, tb = min(I.t1, ta + per);
+  uint32_t mine = 0;
+  for (int t = ta; t < tb; ++t) mine += tile_dead[t];
+  uint32_t inc = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o);
+    if (l >= o) inc += y;
+  }
+  if (l == 63) s_wave[wv] = inc;
+  __syncthreads();
+  uint32_t before = 0, run = 0;
+#pragma unroll
+  for (int w = 0; w < kPlanThreads / 64; ++w) {
+    const uint32_t t = s_wave[w];
+    before += w < wv ? t : 0u;
+    run += t;
+  }
+  uint32_t o = before + inc - mine;
+  for (int t = ta; t < tb; ++t) {
+    tile_off[t] = o;
+    o += tile_dead[t];
+  }
+  if (wv != 0) return;
   uint32_t* cnt = count + (size_t)inst * ncell;
   int cell = -1;
   uint32_t need = 0;
@@ -623,28 +688,14 @@ __global__ void k_inject_plan(const InstParams* __restrict__ ip, int nx, int P, 
     need = have < I.target ? (uint32_t)(I.target - have) : 0u;
   }
   // inclusive scan over the 64 lanes
-  uint32_t inc = need;
+  uint32_t ninc = need;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(inc, o);
-    if (l >= o) inc += y;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(ninc, d);
+    if (l >= d) ninc += y;
   }
-  uint32_t Q = __shfl(inc, 63);
-  const uint32_t off = inc - need;
-  // free slots per tile, exclusive prefix over the instance's tiles
-  uint32_t run = 0;
-  for (int t0 = I.t0; t0 < I.t1; t0 += 64) {
-    const int t = t0 + l;
-    const uint32_t d = t < I.t1 ? tile_dead[t] : 0u;
-    uint32_t s = d;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(s, o);
-      if (l >= o) s += y;
-    }
-    if (t < I.t1) tile_off[t] = run + s - d;
-    run += __shfl(s, 63);
-  }
+  uint32_t Q = __shfl(ninc, 63);
+  const uint32_t off = ninc - need;
   if (run < Q) {
     if (l == 0) set_flag(flags, inst, -3);
     Q = run;
@@ -660,7 +711,8 @@ __global__ void k_inject_plan(const InstParams* __restrict__ ip, int nx, int P, 
     cnt[cell] += got;
   }
   Plan* pl = plan + inst;
-  if (l < 64) { pl->need[l] = need; pl->off[l] = off; }
+  pl->need[l] = need;
+  pl->off[l] = off;
   const uint32_t src = wave_sum(l < P ? got : 0u), drn = wave_sum(l >= P ? got : 0u);
   if (l == 0) {
     pl->Q = Q;
@@ -1065,7 +1117,17 @@ __global__ void k_poisson_rhs(PoisGeo g, const InstParams* __restrict__ ip, cons
 }
 
 // phi = A^-1 rhs: one wavefront per row, unit-stride reads of the
-// (Infinity-Cache-resident) inverse, wavefront reduction.
+// (Infinity-Cache-resident) inverse.  Every output is summed in one fixed
+// order -- lane l accumulates the products of columns j = l (mod 64) in
+// ascending j with fused multiply-adds, then a butterfly over the lanes --
+// which k_poisson_gemm repeats exactly, so a batched context gives the same
+// potential as a context of one instance.
+__device__ __forceinline__ double lane_butterfly(double s) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  return s;
+}
+
 __global__ void __launch_bounds__(256) k_poisson_gemv(const double* __restrict__ Ainv,
                                                       const double* __restrict__ rhs, int ncell, double* phi) {
   const int inst = blockIdx.y;
@@ -1075,10 +1137,56 @@ __global__ void __launch_bounds__(256) k_poisson_gemv(const double* __restrict__
   const double* a = Ainv + (size_t)row * ncell;
   const double* b = rhs + (size_t)inst * ncell;
   double s = 0.0;
-  for (int j = lane; j < ncell; j += 64) s += a[j] * b[j];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  for (int j = lane; j < ncell; j += 64) s = fma(a[j], b[j], s);
+  s = lane_butterfly(s);
   if (lane == 0) phi[(size_t)inst * ncell + row] = s;
+}
+
+// Many instances: Phi = A^-1 [rhs_0 ... rhs_n-1], register-blocked over
+// kPgR rows and kPgG instances per wavefront, so each column element of the
+// inverse is read once per kPgG instances; same summation order as
+// k_poisson_gemv.
+constexpr int kPgR = 4, kPgG = 8;
+__global__ void __launch_bounds__(256) k_poisson_gemm(const double* __restrict__ Ainv,
+                                                      const double* __restrict__ rhs, int ncell, int n_inst,
+                                                      double* phi) {
+  const int lane = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * kPgR;
+  const int i0 = blockIdx.y * kPgG;
+  if (row0 >= ncell) return;
+  double s[kPgR][kPgG];
+#pragma unroll
+  for (int r = 0; r < kPgR; ++r)
+#pragma unroll
+    for (int g = 0; g < kPgG; ++g) s[r][g] = 0.0;
+  const double* arow[kPgR];
+  const double* bcol[kPgG];
+#pragma unroll
+  for (int r = 0; r < kPgR; ++r) arow[r] = Ainv + (size_t)min(row0 + r, ncell - 1) * ncell;
+#pragma unroll
+  for (int g = 0; g < kPgG; ++g) bcol[g] = rhs + (size_t)min(i0 + g, n_inst - 1) * ncell;
+  for (int j = lane; j < ncell; j += 64) {
+    double av[kPgR], bv[kPgG];
+#pragma unroll
+    for (int r = 0; r < kPgR; ++r) av[r] = arow[r][j];
+#pragma unroll
+    for (int g = 0; g < kPgG; ++g) bv[g] = bcol[g][j];
+#pragma unroll
+    for (int r = 0; r < kPgR; ++r)
+#pragma unroll
+      for (int g = 0; g < kPgG; ++g) s[r][g] = fma(av[r], bv[g], s[r][g]);
+  }
+#pragma unroll
+  for (int r = 0; r < kPgR; ++r)
+#pragma unroll
+    for (int g = 0; g < kPgG; ++g) s[r][g] = lane_butterfly(s[r][g]);
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < kPgR; ++r)
+#pragma unroll
+      for (int g = 0; g < kPgG; ++g)
+        if (row0 + r < ncell && i0 + g < n_inst) phi[(size_t)(i0 + g) * ncell + row0 + r] = s[r][g];
+  }
 }
 
 // Centred-difference field E = -grad(phi): a Dirichlet neighbour is its face

@@ -254,4 +254,109 @@ __global__ void k_ensemble(const float* __restrict__ preds, int E, long per, int
   if (std_out) std_out[e] = E > 1 ? sqrtf(s2 / (E - 1)) * ystd[j] : 0.0f;
 }
 
+// ---------------------------------------------------------------------------
+// Small-batch inference (M <= kSmallM rows): each layer is a stream over its
+// BF16 weights, so it runs as a split-K GEMV across all ensemble members in
+// one launch (grid: column blocks x K splits x members; one wavefront per
+// workgroup, 8 consecutive columns per lane read as one 16-byte load), with
+// FP32 partial sums per split and a second kernel that adds the splits in a
+// fixed order and applies the bias (and GELU) epilogue.
+constexpr int kSmallM = 8;
+constexpr int kGvCols = 512;   // columns per wavefront
+constexpr int kGvMaxSplit = 64;
+constexpr int kMaxMembers = 16;
+
+struct GemvArgs {
+  const bf16* X;   // [member][M][ldx] (xse = 0: one input shared by all members)
+  long ldx, xse;
+  const bf16* W[kMaxMembers];  // [K][ldw] per member
+  long ldw;
+  int M, N, K, S;
+  float* P;        // partials [member][S][M][N]
+};
+
+__device__ __forceinline__ void bf16x8_to_f32(const uint4 v, float* f) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    f[2 * i] = __uint_as_float(w[i] << 16);
+    f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+
+template <int MT>
+__global__ void __launch_bounds__(64) k_gemv(GemvArgs g) {
+  const int e = blockIdx.z, s = blockIdx.y;
+  const int n = blockIdx.x * kGvCols + 8 * (int)threadIdx.x;
+  const int kc = (g.K + g.S - 1) / g.S, k0 = s * kc, k1 = min(g.K, k0 + kc);
+  const bf16* __restrict__ W = g.W[e];
+  const bf16* __restrict__ X = g.X + (long)e * g.xse;
+  float acc[MT][8];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[m][j] = 0.0f;
+  if (n >= g.N) return;  // N is a multiple of 8: a lane owns 8 columns or none
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    uint4 wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) wv[u] = *reinterpret_cast<const uint4*>(W + (long)(k + u) * g.ldw + n);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      float wf[8];
+      bf16x8_to_f32(wv[u], wf);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const float xm = m < g.M ? (float)X[(long)m * g.ldx + k + u] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[m][j] = fmaf(xm, wf[j], acc[m][j]);
+      }
+    }
+  }
+  for (; k < k1; ++k) {
+    float wf[8];
+    bf16x8_to_f32(*reinterpret_cast<const uint4*>(W + (long)k * g.ldw + n), wf);
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const float xm = m < g.M ? (float)X[(long)m * g.ldx + k] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[m][j] = fmaf(xm, wf[j], acc[m][j]);
+    }
+  }
+  float* P = g.P + ((long)e * g.S + s) * g.M * g.N;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    if (m >= g.M) break;
+    float4* d = reinterpret_cast<float4*>(P + (long)m * g.N + n);
+    d[0] = make_float4(acc[m][0], acc[m][1], acc[m][2], acc[m][3]);
+    d[1] = make_float4(acc[m][4], acc[m][5], acc[m][6], acc[m][7]);
+  }
+}
+
+struct GemvReduceArgs {
+  const float* P;  // [member][S][M][N]
+  int S, M, N, n_valid, E;
+  const float* bias[kMaxMembers];
+  float* outf;     // last layer: FP32 [member][M][ldo] (members ofs_e apart)
+  bf16* outb;      // hidden layer: BF16 GELU activations [member][M][ldo]
+  long ldo, ofs_e;
+};
+
+template <bool LAST>
+__global__ void k_gemv_reduce(GemvReduceArgs r) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)r.M * r.n_valid;
+  if (idx >= per * r.E) return;
+  const int e = (int)(idx / per);
+  const long rem = idx % per;
+  const int m = (int)(rem / r.n_valid), n = (int)(rem % r.n_valid);
+  const float* P = r.P + (long)e * r.S * r.M * r.N + (long)m * r.N + n;
+  float acc = 0.0f;
+  for (int s = 0; s < r.S; ++s) acc += P[(long)s * r.M * r.N];
+  const float z = acc + r.bias[e][n];
+  if (LAST) r.outf[e * r.ofs_e + (long)m * r.ldo + n] = z;
+  else r.outb[e * r.ofs_e + (long)m * r.ldo + n] = (bf16)gelu(z);
+}
+
 }  // namespace sg

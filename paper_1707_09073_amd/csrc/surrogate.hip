@@ -36,6 +36,8 @@ struct SgLayout {
   std::vector<int> K, N;  // per layer
   std::vector<std::vector<LayerOff>> lo;  // [member][layer]
   size_t xmean, xstd, ymean, ystd, X0, preds, dA0, dA1, loss, idx;
+  int msmall = 0;          // rows of the small-batch inference path
+  size_t Asm, gvp;         // its activations [2][member][msmall][width] and split partials
   std::vector<size_t> Z, A;  // per hidden layer: pre-activation (FP32) and activation (BF16)
   size_t total = 0;
 };
@@ -44,7 +46,7 @@ bool sg_valid(const sg_config* c) {
   // a width that is a multiple of 8 keeps every GEMM row 16-byte aligned
   // (the input and output widths are padded internally)
   return c && c->n_in > 0 && c->n_out > 0 && c->width > 0 && c->width % 8 == 0 &&
-         c->depth >= 1 && c->depth <= 16 && c->ensemble >= 1 && c->ensemble <= 16 && c->max_batch >= 1 &&
+         c->depth >= 1 && c->depth <= 16 && c->ensemble >= 1 && c->ensemble <= kMaxMembers && c->max_batch >= 1 &&
          c->max_batch <= 65536;
 }
 
@@ -89,6 +91,9 @@ SgLayout sg_layout(const sg_config* c) {
   s.dA0 = L.take(2 * MB * wmax);
   s.dA1 = L.take(2 * MB * wmax);
   s.loss = L.take(4 * ((MB * s.Np + 255) / 256 + 1));
+  s.msmall = (int)std::min<size_t>(kSmallM, MB);
+  s.Asm = L.take(2 * 2 * (size_t)c->ensemble * s.msmall * c->width);
+  s.gvp = L.take(4 * (size_t)c->ensemble * kGvMaxSplit * s.msmall * wmax);
   s.idx = 0;
   s.total = L.total;
   return s;
@@ -163,6 +168,54 @@ void enqueue_forward(sg_ctx* c, int e, const float* d_x, int batch, float* out) 
       g.N = c->c.n_out;  // only the real outputs are written
       g.Cf = out; g.ldcf = c->c.n_out;
       gemm<false, false, EPI_BIAS>(c, g);
+    }
+  }
+}
+
+// Small-batch forward of every member (batch <= msmall): split-K GEMV per
+// layer over all members, then the ordered split sum with the epilogue.
+// Normalised predictions to preds [member][batch][n_out].
+void enqueue_forward_small(sg_ctx* c, const float* d_x, int batch, float* preds) {
+  const SgLayout& s = c->s;
+  const int E = c->c.ensemble, width = c->c.width;
+  k_input<<<blocks((long)batch * s.K0p), 256, 0, c->st>>>(d_x, batch, c->c.n_in, c->p<float>(s.xmean),
+                                                           c->p<float>(s.xstd), c->p<bf16>(s.X0), s.K0p);
+  const size_t abuf = (size_t)E * s.msmall * width;  // one activation buffer, all members
+  int cur = -1;
+  for (int l = 0; l < s.L; ++l) {
+    const bool last = l == s.L - 1;
+    GemvArgs g;
+    std::memset(&g, 0, sizeof(g));
+    if (l == 0) {
+      g.X = c->p<bf16>(s.X0); g.ldx = s.K0p; g.xse = 0;
+    } else {
+      g.X = c->p<bf16>(s.Asm) + (size_t)cur * abuf; g.ldx = width; g.xse = (long)s.msmall * width;
+    }
+    for (int e = 0; e < E; ++e) g.W[e] = c->p<bf16>(s.lo[e][l].Wb);
+    g.ldw = s.N[l];
+    g.M = batch; g.N = s.N[l]; g.K = s.K[l];
+    const int ncb = (g.N + kGvCols - 1) / kGvCols;
+    // about a thousand wavefronts per launch, at least 4 rows per split
+    g.S = std::max(1, std::min({kGvMaxSplit, 1024 / (ncb * E), g.K / 4}));
+    g.P = c->p<float>(s.gvp);
+    dim3 grid(ncb, g.S, E);
+    if (batch <= 1) k_gemv<1><<<grid, 64, 0, c->st>>>(g);
+    else if (batch <= 2) k_gemv<2><<<grid, 64, 0, c->st>>>(g);
+    else if (batch <= 4) k_gemv<4><<<grid, 64, 0, c->st>>>(g);
+    else k_gemv<8><<<grid, 64, 0, c->st>>>(g);
+    GemvReduceArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.P = g.P; r.S = g.S; r.M = batch; r.N = g.N; r.E = E;
+    for (int e = 0; e < E; ++e) r.bias[e] = c->p<float>(s.lo[e][l].b);
+    if (last) {
+      r.n_valid = c->c.n_out; r.outf = preds; r.ldo = c->c.n_out; r.ofs_e = (long)batch * c->c.n_out;
+      k_gemv_reduce<true><<<blocks((long)E * batch * r.n_valid), 256, 0, c->st>>>(r);
+    } else {
+      const int nxt = cur == 0 ? 1 : 0;
+      r.n_valid = g.N; r.outb = c->p<bf16>(s.Asm) + (size_t)nxt * abuf; r.ldo = width;
+      r.ofs_e = (long)s.msmall * width;
+      k_gemv_reduce<false><<<blocks((long)E * batch * r.n_valid), 256, 0, c->st>>>(r);
+      cur = nxt;
     }
   }
 }
@@ -361,8 +414,12 @@ int sg_predict(sg_ctx* c, const float* d_x, int batch, float* d_mean, float* d_s
   if (!c || !d_x || !d_mean || batch < 1 || batch > c->c.max_batch) return sfail(c, MC_E_ARG, "bad argument");
   const SgLayout& s = c->s;
   const long per = (long)batch * c->c.n_out;
-  for (int e = 0; e < c->c.ensemble; ++e)
-    enqueue_forward(c, e, d_x, batch, c->p<float>(s.preds) + (size_t)e * per);
+  if (batch <= s.msmall) {
+    enqueue_forward_small(c, d_x, batch, c->p<float>(s.preds));
+  } else {
+    for (int e = 0; e < c->c.ensemble; ++e)
+      enqueue_forward(c, e, d_x, batch, c->p<float>(s.preds) + (size_t)e * per);
+  }
   k_ensemble<<<blocks(per), 256, 0, c->st>>>(c->p<float>(s.preds), c->c.ensemble, per, c->c.n_out,
                                              c->p<float>(s.ymean), c->p<float>(s.ystd), d_mean, d_std);
   SGCHK(c, hipGetLastError());

@@ -68,12 +68,50 @@ def rel_l2(pred: np.ndarray, ref: np.ndarray) -> np.ndarray:
     return out
 
 
+# Target encoding.  Across bias points and doping the maps span orders of
+# magnitude, while the accuracy asked for is relative per map: each map is
+# learned as its unit-norm shape (1800 values) and the logarithm of its norm,
+# so that a squared error in the shape is a relative error of the map.
+N_ENC = 2 * N_CELL + 2
+LOGNORM_WEIGHT = 10.0  # the two log-norms' scale is divided by this (loss weight 100)
+
+
+def encode(Y: np.ndarray) -> np.ndarray:
+    Y = np.asarray(Y, np.float64)
+    out = np.zeros((Y.shape[0], N_ENC))
+    for k, sl in enumerate((slice(0, N_CELL), slice(N_CELL, 2 * N_CELL))):
+        nrm = np.maximum(np.linalg.norm(Y[:, sl], axis=1), 1e-300)
+        out[:, sl] = Y[:, sl] / nrm[:, None]
+        out[:, 2 * N_CELL + k] = np.log(nrm)
+    return out
+
+
+def decode(T: np.ndarray) -> np.ndarray:
+    T = np.asarray(T, np.float64)
+    Y = np.zeros((T.shape[0], 2 * N_CELL))
+    for k, sl in enumerate((slice(0, N_CELL), slice(N_CELL, 2 * N_CELL))):
+        Y[:, sl] = T[:, sl] * np.exp(T[:, 2 * N_CELL + k])[:, None]
+    return Y
+
+
+def encoded_spread(mean: np.ndarray, std: np.ndarray) -> np.ndarray:
+    """Raw predicted relative error per row from the ensemble spread of the
+    encoded outputs: shape spread over shape norm combined with the spread
+    of the log-norm, the larger of the two maps."""
+    mean, std = np.asarray(mean, np.float64), np.asarray(std, np.float64)
+    out = np.zeros(mean.shape[0])
+    for k, sl in enumerate((slice(0, N_CELL), slice(N_CELL, 2 * N_CELL))):
+        rs = np.linalg.norm(std[:, sl], axis=1) / np.maximum(np.linalg.norm(mean[:, sl], axis=1), 1e-300)
+        out = np.maximum(out, np.hypot(rs, std[:, 2 * N_CELL + k]))
+    return out
+
+
 class Surrogate:
     """Ensemble MLP on the library's BF16 MFMA kernels, with calibrated
     predicted error and Monte Carlo fallback."""
 
     def __init__(self, width=1024, depth=4, ensemble=4, max_batch=256, seed=1707_09073, tol=0.02):
-        self.net = gfmc.SurrogateNet(3 + N_CELL, 2 * N_CELL, width=width, depth=depth, ensemble=ensemble,
+        self.net = gfmc.SurrogateNet(3 + N_CELL, N_ENC, width=width, depth=depth, ensemble=ensemble,
                                      max_batch=max_batch, seed=seed)
         self.ensemble = ensemble
         self.max_batch = max_batch
@@ -84,60 +122,60 @@ class Surrogate:
     def fit(self, X: np.ndarray, Y: np.ndarray, epochs: int = 200, batch: int = 128, lr: float = 1e-3,
             seed: int = 0, log=print) -> list[float]:
         import torch
-        # statistics in FP64: densities (~1e24 m^-3) overflow FP32 when squared
-        X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+        T = encode(Y)
+        # statistics in FP64 (densities ~1e24 m^-3 would overflow FP32 squared)
+        X64 = X.astype(np.float64)
         xm, xs = X64.mean(0), X64.std(0)
         xs = np.where(xs > 1e-6 * np.maximum(1.0, np.abs(xm)), xs, 1.0)
-        ym, ys = Y64.mean(0), Y64.std(0)
-        ys = np.where(ys > 1e-6 * np.maximum(1.0, np.abs(ym)), ys, np.maximum(1.0, np.abs(ym)))
+        ym, ys = T.mean(0), T.std(0)
+        ys = np.where(ys > 1e-9, ys, 1.0)
+        ys[2 * N_CELL:] /= LOGNORM_WEIGHT
         self.net.sg_set_normalization(xm, xs, ym, ys)
         self.box = (X.min(0), X.max(0))
         rng = np.random.default_rng(seed)
         n = X.shape[0]
         batch = min(batch, self.max_batch, n)
+        Td = torch.tensor(T.astype(np.float32), device="cuda")
+        Xd_all = torch.tensor(X, device="cuda")
         losses = []
         for ep in range(epochs):
             # cosine learning-rate schedule
             lr_e = lr * 0.5 * (1.0 + math.cos(math.pi * ep / epochs))
             for e in range(self.ensemble):
-                perm = rng.permutation(n)
-                Xd = torch.tensor(X[perm], device="cuda")
-                Yd = torch.tensor(Y[perm], device="cuda")
+                perm = torch.tensor(rng.permutation(n), device="cuda")
+                Xd, Yd = Xd_all[perm], Td[perm]
                 for s in range(0, n - batch + 1, batch):
                     self.net.sg_train_step(e, Xd[s:s + batch], Yd[s:s + batch], lr_e, want_loss=False)
             if ep % max(1, epochs // 10) == 0 or ep == epochs - 1:
-                Xd = torch.tensor(X[:batch], device="cuda")
-                Yd = torch.tensor(Y[:batch], device="cuda")
-                losses.append(float(np.mean([self.net.sg_backward(e, Xd, Yd) for e in range(self.ensemble)])))
+                losses.append(float(np.mean([self.net.sg_backward(e, Xd_all[:batch], Td[:batch])
+                                             for e in range(self.ensemble)])))
                 log(f"  epoch {ep}: train loss {losses[-1]:.4g}")
         return losses
 
-    def predict(self, X: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    def predict_encoded(self, X: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
         import torch
         means, stds = [], []
         for s in range(0, X.shape[0], self.max_batch):
             xd = torch.tensor(X[s:s + self.max_batch], device="cuda")
-            m = torch.empty((xd.shape[0], 2 * N_CELL), device="cuda")
+            m = torch.empty((xd.shape[0], N_ENC), device="cuda")
             sd = torch.empty_like(m)
             self.net.sg_predict(xd, m, sd)
             means.append(m.cpu().numpy())
             stds.append(sd.cpu().numpy())
         return np.concatenate(means), np.concatenate(stds)
 
-    def spread(self, mean: np.ndarray, std: np.ndarray) -> np.ndarray:
-        """Raw predicted error per row: the ensemble's relative spread, the
-        larger of the two maps."""
-        mean, std = np.asarray(mean, np.float64), np.asarray(std, np.float64)
-        return np.maximum(np.linalg.norm(std[:, :N_CELL], axis=1) / np.maximum(np.linalg.norm(mean[:, :N_CELL], axis=1), 1e-300),
-                          np.linalg.norm(std[:, N_CELL:], axis=1) / np.maximum(np.linalg.norm(mean[:, N_CELL:], axis=1), 1e-300))
+    def predict(self, X: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+        """Maps (heat W/m^3, density m^-3) and the raw predicted relative
+        error of each row."""
+        m, s = self.predict_encoded(X)
+        return decode(m), encoded_spread(m, s)
 
     def calibrate(self, Xv: np.ndarray, Yv: np.ndarray) -> float:
         """Scale the spread so that it bounds the observed validation error
         for 90% of the points."""
-        m, s = self.predict(Xv)
-        err = rel_l2(m, Yv).max(axis=1)
-        sp = np.maximum(self.spread(m, s), 1e-12)
-        self.calib = float(np.quantile(err / sp, 0.9))
+        maps, sp = self.predict(Xv)
+        err = rel_l2(maps, Yv).max(axis=1)
+        self.calib = float(np.quantile(err / np.maximum(sp, 1e-12), 0.9))
         return self.calib
 
     def in_box(self, X: np.ndarray) -> np.ndarray:
@@ -150,11 +188,11 @@ class Surrogate:
         tolerance and the query is inside the training box; the Monte Carlo
         for the rest.  Returns (maps, used_mc mask, predicted error)."""
         X = np.stack([features(c) for c in cfgs])
-        m, s = self.predict(X)
-        perr = self.calib * self.spread(m, s)
+        maps, sp = self.predict(X)
+        perr = self.calib * sp
         use_mc = (perr > self.tol) | ~self.in_box(X)
         if np.any(use_mc):
             idx = np.nonzero(use_mc)[0]
             _, Ymc, _ = generate([cfgs[i] for i in idx], warm_intervals, window_intervals, log=log)
-            m[idx] = Ymc
-        return m, use_mc, perr
+            maps[idx] = Ymc
+        return maps, use_mc, perr

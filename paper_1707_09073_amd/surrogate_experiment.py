@@ -79,7 +79,7 @@ def main(argv=None) -> int:
     t0 = time.perf_counter()
     reps = 20
     for _ in range(reps):
-        m, s = sur.predict(Xv[h:])
+        m, sp = sur.predict(Xv[h:])
     torch.cuda.synchronize()
     t_pred = (time.perf_counter() - t0) / (reps * (a.val - h))
     # single-point latency
@@ -89,7 +89,7 @@ def main(argv=None) -> int:
     torch.cuda.synchronize()
     t_pred1 = (time.perf_counter() - t0) / 20
     err = S.rel_l2(m, Yv[h:])
-    perr = sur.calib * sur.spread(m, s)
+    perr = sur.calib * sp
     accept = (perr <= a.tol) & sur.in_box(Xv[h:])
     res = {
         "train_points": a.train, "val_points": a.val, "particles": a.particles,

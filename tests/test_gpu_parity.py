@@ -295,3 +295,13 @@ def test_fp32_device_statistics_match_fp64_oracle(G, oracle_mod):
     hg, ho = e.mc_maps()["heat4"].astype(float), o.maps()[0].astype(float)
     net_g, net_o = (hg[:, 0] - hg[:, 1]).sum(), (ho[:, 0] - ho[:, 1]).sum()
     assert abs(net_g - net_o) <= 0.03 * abs(net_o) + 3 * math.sqrt(hg[:, :2].sum() + ho[:, :2].sum())
+    # the heat map along the channel: net LO-phonon emission per slice of 18
+    # subcells, within 1% or 3 sigma (counting noise of both runs) in at
+    # least 98 of the 100 slices and within 5 sigma in all
+    P = cfg["n_cells"][1] * cfg["n_cells"][2]
+    col_g = (hg[:, 0] - hg[:, 1]).reshape(-1, P).sum(axis=1)
+    col_o = (ho[:, 0] - ho[:, 1]).reshape(-1, P).sum(axis=1)
+    sig = np.sqrt(hg[:, :2].sum(axis=1).reshape(-1, P).sum(axis=1) + ho[:, :2].sum(axis=1).reshape(-1, P).sum(axis=1))
+    dev = np.abs(col_g - col_o)
+    ok = (dev <= 0.01 * np.abs(col_o)) | (dev <= 3 * sig)
+    assert ok.sum() >= 98 and np.all(dev <= np.maximum(0.01 * np.abs(col_o), 5 * sig)), (ok.sum(), dev / sig)

@@ -136,3 +136,34 @@ def test_training_reduces_loss_and_ensemble_predicts(torch_mod):
     torch.cuda.synchronize()
     assert np.allclose(m, np.mean(outs, axis=0), rtol=1e-4, atol=1e-4)
     assert np.allclose(std.cpu().numpy(), np.std(outs, axis=0, ddof=1), rtol=1e-3, atol=1e-4)
+
+
+@pytest.mark.parametrize("shape", [
+    # ragged widths (not multiples of the 512-column GEMV block), 3 members
+    dict(n_in=300, n_out=257, width=384, depth=2, ensemble=3, seed=13),
+    # the surrogate's real shape: 1803 -> 1024 x 4 (GELU) -> 3600, 4 members
+    dict(n_in=1803, n_out=3600, width=1024, depth=4, ensemble=4, seed=17),
+])
+def test_small_batch_predict_matches_oracle_and_gemm_path(torch_mod, shape):
+    """sg_predict at batch <= 8 takes the split-K GEMV path; its ensemble mean
+    and spread match the oracle's, and the rows agree with the MFMA path."""
+    torch = torch_mod
+    n_out, E = shape["n_out"], shape["ensemble"]
+    net, oracles, x, _ = _make(torch, shape["n_in"], n_out, shape["width"], shape["depth"], batch=16,
+                               ensemble=E, seed=shape["seed"])
+    _say(f"surrogate small-batch predict {shape}")
+    ym, ys = net._norm[2].astype(np.float64), net._norm[3].astype(np.float64)
+    outs = np.stack([o.forward(x)[0] * ys + ym for o in oracles])
+    mean_o, std_o = outs.mean(0), outs.std(0, ddof=1)
+    xd = torch.tensor(x, device="cuda")
+    big_m = torch.empty((16, n_out), device="cuda"); big_s = torch.empty_like(big_m)
+    net.sg_predict(xd, big_m, big_s)  # batch 16: MFMA path
+    big_m, big_s = big_m.cpu().numpy(), big_s.cpu().numpy()
+    for lo, hi in [(0, 1), (1, 3), (3, 7), (7, 15), (15, 16)]:
+        m = torch.empty((hi - lo, n_out), device="cuda"); s = torch.empty_like(m)
+        net.sg_predict(xd[lo:hi].contiguous(), m, s)
+        m, s = m.cpu().numpy(), s.cpu().numpy()
+        assert _rel(m, mean_o[lo:hi]) <= 1e-3, (lo, hi, _rel(m, mean_o[lo:hi]))
+        assert _rel(s, std_o[lo:hi]) <= 2e-2, (lo, hi, _rel(s, std_o[lo:hi]))
+        assert _rel(m, big_m[lo:hi]) <= 1e-3
+        assert _rel(s, big_s[lo:hi]) <= 2e-2
