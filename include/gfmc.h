@@ -243,6 +243,7 @@ typedef struct {
   int32_t max_batch; /* largest batch of any call */
   uint64_t seed;     /* Philox key of the weight initialisation */
   float beta1, beta2, eps; /* Adam */
+  float weight_decay;      /* decoupled (AdamW) decay of the weights, not the biases; 0 = plain Adam */
 } sg_config;
 
 typedef struct sg_ctx sg_ctx;

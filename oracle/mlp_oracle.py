@@ -81,9 +81,10 @@ class MLPOracle:
         return loss, dWs, dbs, pred
 
 
-def adam_step(w, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
-    """One bias-corrected Adam step (Kingma & Ba), returns (w, m, v)."""
+def adam_step(w, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
+    """One bias-corrected Adam step (Kingma & Ba) with decoupled weight decay
+    wd (Loshchilov & Hutter; wd = 0 is plain Adam), returns (w, m, v)."""
     m = b1 * m + (1 - b1) * g
     v = b2 * v + (1 - b2) * g * g
-    w = w - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+    w = w - lr * ((m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps) + wd * w)
     return w, m, v

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace gfmc {
 
 // CODATA 2018, SI
@@ -127,11 +129,19 @@ struct Geo {
   T L[3], d[3], inv_d[3];
 };
 
-// Per-valley constant for a lane's runtime valley index, by selects: an
-// array of the kernel arguments indexed at run time would be a memory load.
+// Per-valley constant for a lane's runtime valley index.  Written as bit
+// masks so that it compiles to v_cndmask: an array of the kernel arguments
+// indexed at run time is a memory load, and a ternary chain on the valley
+// becomes divergent branches.
 template <typename T>
 __device__ __forceinline__ T pick3(const T (&a)[3], int v) {
-  return v == 0 ? a[0] : (v == 1 ? a[1] : a[2]);
+  typedef typename std::conditional<sizeof(T) == 8, unsigned long long, unsigned int>::type U;
+  const U x0 = __builtin_bit_cast(U, a[0]), x1 = __builtin_bit_cast(U, a[1]);
+  U r = __builtin_bit_cast(U, a[2]);
+  const U m0 = (U)0 - (U)(v == 0), m1 = (U)0 - (U)(v == 1);
+  r = (x1 & m1) | (r & ~m1);
+  r = (x0 & m0) | (r & ~m0);
+  return __builtin_bit_cast(T, r);
 }
 
 // Kane: E from gamma = E (1 + a E), positive root, finite at a = 0.

@@ -121,9 +121,12 @@ __device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const
   }
   if (!(Ep > (T)0)) { c.self++; return -1; }
   atomicAdd(sh_real + v * kNM + m, 1u);
-  if (m == 3) atomicAdd(sh_heat + cell, 1u);
-  else if (m == 2) atomicAdd(sh_heat + ncell + cell, 1u);
-  else if (m >= 4) atomicAdd(sh_heat + (((m - 4) & 1) ? 2 : 3) * ncell + cell, 1u);
+  {
+    // heat slot: 0 LO emission, 1 LO absorption, 2 intervalley emission,
+    // 3 intervalley absorption; none for the elastic mechanisms
+    const int hs = m == 3 ? 0 : (m == 2 ? 1 : (m >= 4 ? (((m - 4) & 1) ? 2 : 3) : -1));
+    if (hs >= 0) atomicAdd(sh_heat + hs * ncell + cell, 1u);
+  }
   // polar angle relative to k, sampled as X = 1 - cos; sin = sqrt(X (2 - X))
   // keeps full relative accuracy for forward scattering
   const T u2 = Ar<T>::u01(w.z), u3 = Ar<T>::u01(w.w);
@@ -348,9 +351,12 @@ __device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* Sr, co
   } else {
     atomicAdd(sh_real + v * kNM + m, 1u);
   }
-  if (m == 3) atomicAdd(sh_heat + cell, 1u);
-  else if (m == 2) atomicAdd(sh_heat + ncell + cell, 1u);
-  else if (m >= 4) atomicAdd(sh_heat + (((m - 4) & 1) ? 2 : 3) * ncell + cell, 1u);
+  {
+    // heat slot: 0 LO emission, 1 LO absorption, 2 intervalley emission,
+    // 3 intervalley absorption; none for the elastic mechanisms
+    const int hs = m == 3 ? 0 : (m == 2 ? 1 : (m >= 4 ? (((m - 4) & 1) ? 2 : 3) : -1));
+    if (hs >= 0) atomicAdd(sh_heat + hs * ncell + cell, 1u);
+  }
   const T k2 = kx * kx + ky * ky + kz * kz;
   const T g = E * ((T)1 + pick3(M.alpha, v) * E);
   const T u2 = Ar<T>::u01(w.z), u3 = Ar<T>::u01(w.w);
@@ -476,12 +482,17 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
         const uint32_t idx = base + (uint32_t)__popcll(m & lt);
         if (idx < (uint32_t)td.count) {
           p = td.start + idx;
+          // the state is loaded together with the meta word (one memory
+          // round trip per slot; a free slot's stale state is discarded)
           const uint32_t meta = a.meta[p];
+          const T lkx = a.kx[p], lky = a.ky[p], lkz = a.kz[p];
+          T lx = (T)0, ly = (T)0, lz = (T)0;
+          if (DEV) { lx = a.x[p]; ly = a.y[p]; lz = a.z[p]; }
           if (meta & kAlive) {
             has = true;
             c.proc++;
-            kx = a.kx[p]; ky = a.ky[p]; kz = a.kz[p];
-            if (DEV) { x = a.x[p]; y = a.y[p]; z = a.z[p]; }
+            kx = lkx; ky = lky; kz = lkz;
+            x = lx; y = ly; z = lz;
             v = meta_valley(meta);
             id = meta_id(meta);
             j = 0;

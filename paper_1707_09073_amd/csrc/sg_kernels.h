@@ -199,9 +199,10 @@ __global__ void k_colsum(const bf16* __restrict__ d, int M, int N, long ld, floa
   out[j] = s;
 }
 
-// Adam (bias-corrected) on FP32 master weights, then the BF16 copy.
+// Adam (bias-corrected) on FP32 master weights with decoupled weight decay
+// wd (Loshchilov & Hutter), then the BF16 copy.
 __global__ void k_adam(float* w, float* m, float* v, const float* __restrict__ g, bf16* wb, long n, float lr,
-                       float b1, float b2, float eps, float c1, float c2) {
+                       float b1, float b2, float eps, float c1, float c2, float wd) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -209,7 +210,7 @@ __global__ void k_adam(float* w, float* m, float* v, const float* __restrict__ g
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  const float wi = w[i] - lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * w[i]);
   w[i] = wi;
   if (wb) wb[i] = (bf16)wi;
 }

@@ -45,7 +45,7 @@ struct SgLayout {
 bool sg_valid(const sg_config* c) {
   // a width that is a multiple of 8 keeps every GEMM row 16-byte aligned
   // (the input and output widths are padded internally)
-  return c && c->n_in > 0 && c->n_out > 0 && c->width > 0 && c->width % 8 == 0 &&
+  return c && c->n_in > 0 && c->n_out > 0 && c->width > 0 && c->width % 8 == 0 && c->weight_decay >= 0.0f &&
          c->depth >= 1 && c->depth <= 16 && c->ensemble >= 1 && c->ensemble <= kMaxMembers && c->max_batch >= 1 &&
          c->max_batch <= 65536;
 }
@@ -396,9 +396,9 @@ int sg_adam(sg_ctx* c, int member, float lr) {
     // layer 0: only the rows of real inputs train (padding stays zero)
     const long n = (long)(l == 0 ? c->c.n_in : s.K[l]) * s.N[l];
     k_adam<<<blocks(n), 256, 0, c->st>>>(c->p<float>(o.W), c->p<float>(o.m), c->p<float>(o.v), c->p<float>(o.dW),
-                                         c->p<bf16>(o.Wb), n, lr, b1, b2, c->c.eps, c1, c2);
+                                         c->p<bf16>(o.Wb), n, lr, b1, b2, c->c.eps, c1, c2, c->c.weight_decay);
     k_adam<<<blocks(s.N[l]), 256, 0, c->st>>>(c->p<float>(o.b), c->p<float>(o.bm), c->p<float>(o.bv),
-                                              c->p<float>(o.db), nullptr, s.N[l], lr, b1, b2, c->c.eps, c1, c2);
+                                              c->p<float>(o.db), nullptr, s.N[l], lr, b1, b2, c->c.eps, c1, c2, 0.0f);
   }
   SGCHK(c, hipGetLastError());
   return MC_OK;

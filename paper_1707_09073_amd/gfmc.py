@@ -312,7 +312,7 @@ class Ensemble:
 class SgConfig(C.Structure):
     _fields_ = [("n_in", C.c_int32), ("n_out", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32),
                 ("ensemble", C.c_int32), ("max_batch", C.c_int32), ("seed", C.c_uint64),
-                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("weight_decay", C.c_float)]
 
 
 SG_EXPORTS = ["sg_workspace_bytes", "sg_init", "sg_destroy", "sg_last_error", "sg_layer_dims",
@@ -354,10 +354,10 @@ class SurrogateNet:
     Inputs and outputs are torch FP32 CUDA tensors (row-major)."""
 
     def __init__(self, n_in, n_out, width=1024, depth=4, ensemble=4, max_batch=256, seed=1707_09073,
-                 beta1=0.9, beta2=0.999, eps=1e-8, device="cuda", stream=None):
+                 beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, device="cuda", stream=None):
         import torch
         L = _sg_lib()
-        self.cfg = SgConfig(n_in, n_out, width, depth, ensemble, max_batch, seed, beta1, beta2, eps)
+        self.cfg = SgConfig(n_in, n_out, width, depth, ensemble, max_batch, seed, beta1, beta2, eps, weight_decay)
         nbytes = int(L.sg_workspace_bytes(C.byref(self.cfg)))
         if nbytes == 0:
             raise MCError(MC_E_ARG, "sg_workspace_bytes", "invalid surrogate configuration")

@@ -73,7 +73,8 @@ def rel_l2(pred: np.ndarray, ref: np.ndarray) -> np.ndarray:
 # learned as its unit-norm shape (1800 values) and the logarithm of its norm,
 # so that a squared error in the shape is a relative error of the map.
 N_ENC = 2 * N_CELL + 2
-LOGNORM_WEIGHT = 10.0  # the two log-norms' scale is divided by this (loss weight 100)
+# the two log-norms' scale is divided by this in the loss (loss weight = square)
+LOGNORM_WEIGHT = 10.0
 
 
 def encode(Y: np.ndarray) -> np.ndarray:
@@ -110,9 +111,15 @@ class Surrogate:
     """Ensemble MLP on the library's BF16 MFMA kernels, with calibrated
     predicted error and Monte Carlo fallback."""
 
-    def __init__(self, width=1024, depth=4, ensemble=4, max_batch=256, seed=1707_09073, tol=0.02):
+    def __init__(self, width=1024, depth=4, ensemble=4, max_batch=256, seed=1707_09073, tol=0.02,
+                 weight_decay=0.0, lognorm_weight=LOGNORM_WEIGHT, shared_scale=False):
         self.net = gfmc.SurrogateNet(3 + N_CELL, N_ENC, width=width, depth=depth, ensemble=ensemble,
-                                     max_batch=max_batch, seed=seed)
+                                     max_batch=max_batch, seed=seed, weight_decay=weight_decay)
+        self.lognorm_weight = lognorm_weight
+        # shared_scale: one scale per map for its shape block and log-norm
+        # (divided by lognorm_weight), so that the loss follows the maps'
+        # relative L2 errors instead of per-cell z-scores
+        self.shared_scale = shared_scale
         self.ensemble = ensemble
         self.max_batch = max_batch
         self.tol = tol
@@ -129,7 +136,12 @@ class Surrogate:
         xs = np.where(xs > 1e-6 * np.maximum(1.0, np.abs(xm)), xs, 1.0)
         ym, ys = T.mean(0), T.std(0)
         ys = np.where(ys > 1e-9, ys, 1.0)
-        ys[2 * N_CELL:] /= LOGNORM_WEIGHT
+        if self.shared_scale:
+            for k, sl in enumerate((slice(0, N_CELL), slice(N_CELL, 2 * N_CELL))):
+                s_map = float(np.sqrt(np.mean(T[:, sl].var(axis=0))))
+                ys[sl] = s_map
+                ys[2 * N_CELL + k] = s_map
+        ys[2 * N_CELL:] /= self.lognorm_weight
         self.net.sg_set_normalization(xm, xs, ym, ys)
         self.box = (X.min(0), X.max(0))
         rng = np.random.default_rng(seed)

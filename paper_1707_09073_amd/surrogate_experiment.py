@@ -32,6 +32,8 @@ def main(argv=None) -> int:
     ap.add_argument("--depth", type=int, default=4)
     ap.add_argument("--ensemble", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--weight-decay", type=float, default=0.0)
+    ap.add_argument("--lognorm-weight", type=float, default=10.0)
     ap.add_argument("--tol", type=float, default=0.02)
     ap.add_argument("--out", default="")
     a = ap.parse_args(argv)
@@ -67,7 +69,8 @@ def main(argv=None) -> int:
     # the MC's own error at this ensemble size and window)
     mc_err = S.rel_l2(Yv_single, Yv).max(axis=1) * np.sqrt(a.ref_seeds / max(1, a.ref_seeds - 1))
 
-    sur = S.Surrogate(width=a.width, depth=a.depth, ensemble=a.ensemble, max_batch=256, tol=a.tol)
+    sur = S.Surrogate(width=a.width, depth=a.depth, ensemble=a.ensemble, max_batch=256, tol=a.tol,
+                      weight_decay=a.weight_decay, lognorm_weight=a.lognorm_weight)
     t0 = time.perf_counter()
     losses = sur.fit(X, Y, epochs=a.epochs, batch=128, lr=a.lr, log=log)
     torch.cuda.synchronize()
@@ -94,7 +97,8 @@ def main(argv=None) -> int:
     res = {
         "train_points": a.train, "val_points": a.val, "particles": a.particles,
         "warm_intervals": a.warm, "window_intervals": a.window, "ref_seeds": a.ref_seeds,
-        "mlp": {"width": a.width, "depth": a.depth, "ensemble": a.ensemble, "epochs": a.epochs},
+        "mlp": {"width": a.width, "depth": a.depth, "ensemble": a.ensemble, "epochs": a.epochs, "lr": a.lr,
+                "weight_decay": a.weight_decay, "lognorm_weight": a.lognorm_weight},
         "mc_seconds_per_bias_point": mc_time_per_point,
         "mc_train_data_seconds": t_train,
         "surrogate_fit_seconds": t_fit,

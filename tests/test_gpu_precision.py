@@ -1,0 +1,115 @@
+"""Precision split on the 200k-electron half-nanowire device over 20 ps: the
+FP32-state GPU path and the FP64 GPU path against the FP64 oracle, per
+observable, each within 1% or 3 sigma.  Sigma is the standard error of the
+mean of 5 blocks of 2 ps of each run, combined in quadrature; the runs use
+the same seeds but diverge chaotically after a few hundred events, so they
+are statistically independent over the window.  Printed as a table.
+
+Observables over a 10 ps window after 10 ps of warm-up: drain current, net
+LO-phonon heat, net intervalley heat, scattering selections per electron,
+the U and Gamma3 valley fractions of the final ensemble (binomial sigma),
+and the electron-density and heat profiles along the channel (per slice of
+18 subcells; within 1% or 3 sigma in at least 95 of the 100 slices)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1707_09073_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N, WARM, BLOCK, NBLK = 200_000, 1000, 200, 5
+QE = 1.602176634e-19
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _block(counts, heat4, dens, w, t_s, n_int, P):
+    """Per-block scalar observables and profiles from integer tallies."""
+    h = heat4.astype(np.int64)
+    net_lo = float(h[:, 0].sum() - h[:, 1].sum())
+    net_iv = float(h[:, 2].sum() - h[:, 3].sum())
+    i_d = QE * w * float(counts["exits"][1] - counts["injections"][1]) / t_s
+    h_prof = (h[:, 0] - h[:, 1]).reshape(-1, P).sum(axis=1).astype(np.float64)
+    n_prof = dens.astype(np.float64).reshape(-1, P).sum(axis=1) / n_int
+    return dict(I_D=i_d, net_LO=net_lo, net_IV=net_iv, selections=float(counts["selections"]) / N), h_prof, n_prof
+
+
+def _run_gpu(G, cfg):
+    e = G.Ensemble(cfg)
+    K = cfg["substeps"]
+    e.mc_step(WARM * K)
+    P = cfg["n_cells"][1] * cfg["n_cells"][2]
+    out = []
+    for _ in range(NBLK):
+        e.mc_tally(reset_window=True)
+        e.mc_step(BLOCK * K)
+        t = e.mc_tally()
+        m = e.mc_maps()
+        out.append(_block(t, m["heat4"], m["dens_sum"], t["weight"], t["t_window_fs"] * 1e-15, t["intervals"], P))
+    p = e.mc_read_particles()
+    return out, p["valley"][p["alive"] == 1]
+
+
+def _run_oracle(O, cfg):
+    o = O.Oracle(dict(cfg, precision="fp64"))
+    o.run(WARM)
+    P = cfg["n_cells"][1] * cfg["n_cells"][2]
+    t_s = BLOCK * cfg["substeps"] * cfg["dt_fs"] * 1e-15
+    out = []
+    for _ in range(NBLK):
+        o.reset_window()
+        before = o.counts()
+        o.run(BLOCK)
+        after = o.counts()
+        c = {k: after[k] - before[k] for k in ("selections", "exits", "injections")}
+        heat, dens = o.maps()
+        out.append(_block(c, heat, dens, o.weight, t_s, BLOCK, P))
+    p = o.particles()
+    return out, p["valley"][p["alive"] == 1]
+
+
+def _ms(x):
+    x = np.asarray(x, np.float64)
+    return x.mean(axis=0), x.std(axis=0, ddof=1) / math.sqrt(x.shape[0])
+
+
+def test_fp32_and_fp64_gpu_against_fp64_oracle_per_observable(oracle_mod):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1707_09073_amd import gfmc as G
+    cfg = W.device_config(n_particles=N, precision="fp64")
+    cfg["T_cells"] = W.hotspot_T_map(cfg)
+    _say(f"precision: {N} electrons, {WARM} + {NBLK}x{BLOCK} intervals of 10 fs; oracle first")
+    ref, vref = _run_oracle(oracle_mod, cfg)
+    runs = {"gpu_fp64": _run_gpu(G, cfg), "gpu_fp32": _run_gpu(G, dict(cfg, precision="fp32"))}
+    rows = []
+    for name, (blocks, vals) in runs.items():
+        for key in ("I_D", "net_LO", "net_IV", "selections"):
+            mo, so = _ms([b[0][key] for b in ref])
+            mg, sg = _ms([b[0][key] for b in blocks])
+            s = math.hypot(so, sg)
+            rows.append((name, key, mg, mo, (mg - mo) / abs(mo), s / abs(mo), abs(mg - mo) <= max(0.01 * abs(mo), 3 * s)))
+        for v, vname in ((1, "U fraction"), (2, "Gamma3 fraction")):
+            fo, fg = np.mean(vref == v), np.mean(vals == v)
+            s = math.sqrt(fo * (1 - fo) / vref.size + fg * (1 - fg) / vals.size)
+            rows.append((name, vname, fg, fo, (fg - fo) / max(fo, 1e-12), s / max(fo, 1e-12),
+                         abs(fg - fo) <= max(0.01 * fo, 3 * s)))
+        for idx, label in ((1, "heat profile"), (2, "density profile")):
+            mo, so = _ms([b[idx] for b in ref])
+            mg, sg = _ms([b[idx] for b in blocks])
+            s = np.hypot(so, sg)
+            dev = np.abs(mg - mo)
+            ok = (dev <= 0.01 * np.abs(mo)) | (dev <= 3 * s)
+            rel = float(np.linalg.norm(mg - mo) / np.linalg.norm(mo))
+            rel_s = float(np.linalg.norm(s) / np.linalg.norm(mo))
+            rows.append((name, label + " L2", rel, float(ok.mean()), rel, rel_s, ok.mean() >= 0.95))
+    _say(f"{'path':9s} {'observable':20s} {'value':>12s} {'oracle':>12s} {'rel diff':>9s} {'rel sigma':>9s} ok")
+    for r in rows:
+        _say(f"{r[0]:9s} {r[1]:20s} {r[2]:12.5g} {r[3]:12.5g} {r[4]:9.4f} {r[5]:9.4f} {r[6]}")
+    assert all(r[6] for r in rows), [r for r in rows if not r[6]]

@@ -27,10 +27,11 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _make(torch_mod, n_in, n_out, width, depth, batch, ensemble=1, seed=3):
+def _make(torch_mod, n_in, n_out, width, depth, batch, ensemble=1, seed=3, weight_decay=0.0):
     from oracle.mlp_oracle import MLPOracle, bf16
     from paper_1707_09073_amd import gfmc
-    net = gfmc.SurrogateNet(n_in, n_out, width=width, depth=depth, ensemble=ensemble, max_batch=batch, seed=seed)
+    net = gfmc.SurrogateNet(n_in, n_out, width=width, depth=depth, ensemble=ensemble, max_batch=batch, seed=seed,
+                            weight_decay=weight_decay)
     rng = np.random.default_rng(seed)
     xm, xs = rng.normal(size=n_in), rng.uniform(0.5, 2.0, n_in)
     ym, ys = rng.normal(size=n_out), rng.uniform(0.5, 2.0, n_out)
@@ -73,10 +74,11 @@ def test_forward_and_gradients_match_oracle(torch_mod):
         assert _rel(db, db_o[l]) <= 1e-3, (l, _rel(db, db_o[l]))
 
 
-def test_adam_step_matches_oracle(torch_mod):
+@pytest.mark.parametrize("wd", [0.0, 0.5])
+def test_adam_step_matches_oracle(torch_mod, wd):
     torch = torch_mod
     from oracle.mlp_oracle import adam_step
-    net, (o,), x, y = _make(torch, n_in=100, n_out=140, width=256, depth=1, batch=64)
+    net, (o,), x, y = _make(torch, n_in=100, n_out=140, width=256, depth=1, batch=64, weight_decay=wd)
     W0 = [net.sg_get_params(0, l)[0].astype(np.float64) for l in range(2)]
     xd, yd = torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda")
     net.sg_train_step(0, xd, yd, lr=1e-3)
@@ -84,7 +86,7 @@ def test_adam_step_matches_oracle(torch_mod):
     for l in range(2):
         W1 = net.sg_get_params(0, l)[0].astype(np.float64)
         rows = slice(0, 100) if l == 0 else slice(None)
-        want, _, _ = adam_step(W0[l][rows], 0.0, 0.0, dW_o[l][rows], 1, 1e-3)
+        want, _, _ = adam_step(W0[l][rows], 0.0, 0.0, dW_o[l][rows], 1, 1e-3, wd=wd)
         diff = np.abs(W1[rows] - want)
         # step 1 of Adam moves every weight by ~lr * sign(g): only signs of
         # near-zero gradients may disagree

@@ -82,3 +82,20 @@ def test_adam_minimises_a_quadratic():
         g = 2 * (w - np.array([0.5, 1.5]))
         w, m, v = adam_step(w, m, v, g, t, lr=1e-2)
     assert np.allclose(w, [0.5, 1.5], atol=1e-3)
+
+
+def test_decoupled_weight_decay():
+    """With zero gradients the decoupled decay alone acts: w_t = w_0 (1 - lr wd)^t.
+    With a quadratic loss toward a, the decay pulls the end point from a
+    toward 0 (same sign as a, smaller magnitude)."""
+    w0 = np.array([1.5, -0.25])
+    w, m, v = w0.copy(), np.zeros(2), np.zeros(2)
+    for t in range(1, 101):
+        w, m, v = adam_step(w, m, v, np.zeros(2), t, lr=1e-2, wd=0.5)
+    assert np.allclose(w, w0 * (1 - 1e-2 * 0.5) ** 100, rtol=1e-12)
+    # a decayed quadratic fit ends between 0 and the undecayed optimum
+    a = np.array([0.5, 1.5])
+    w, m, v = np.array([3.0, -2.0]), np.zeros(2), np.zeros(2)
+    for t in range(1, 5001):
+        w, m, v = adam_step(w, m, v, 2 * (w - a), t, lr=1e-3, wd=0.1)
+    assert np.all(np.abs(w) < np.abs(a)) and np.all(w * a > 0)
