@@ -202,6 +202,13 @@ int mc_read_tables(mc_ctx *ctx, int instance, double *h_shape, double *h_k4, dou
 int mc_set_launch(mc_ctx *ctx, int block, int tile);
 int mc_get_launch(const mc_ctx *ctx, int *block, int *tile, int *n_tiles);
 
+/* Residency of the particle kernel (current variant and precision) at
+ * workgroup size `block`: workgroups per compute unit given its registers and
+ * LDS histogram, and the device's compute units.  Lets a tuner pick tile
+ * counts that fill whole rounds of resident workgroups.  MC_E_ARG for an
+ * unsupported block, MC_E_HIP if the runtime query fails. */
+int mc_occupancy(mc_ctx *ctx, int block, int *wg_per_cu, int *n_cu);
+
 /* Particle-kernel variant: 0 = lane refill (each lane pulls the next electron
  * of its tile as soon as its own finishes the interval; default), 1 = one
  * electron per lane per pass.  Results are identical up to the compiler's

@@ -24,6 +24,28 @@ DEFAULT_CANDIDATES = [
 _cache: dict = {}
 
 
+def round_candidates(ens, blocks=(256, 512), max_rounds=8) -> list:
+    """Tile sizes whose tile count just fills r whole rounds of resident
+    workgroups (r = 1..max_rounds): with workgroups of similar length, a last
+    round that is partly empty leaves compute units idle."""
+    total = sum(int(c["capacity"]) for c in ens.cfgs)
+    out = []
+    for b in blocks:
+        try:
+            per_cu, n_cu = ens.mc_occupancy(b)
+        except Exception:
+            continue
+        resident = per_cu * n_cu
+        if resident <= 0:
+            continue
+        for r in range(1, max_rounds + 1):
+            tile = -(-total // (r * resident))
+            tile = -(-tile // b) * b
+            if tile <= 65535:
+                out.append((b, tile, 0))
+    return out
+
+
 def _key(ens) -> str:
     c = ens.cfgs[0]
     cap = sum(int(x["capacity"]) for x in ens.cfgs)
@@ -44,9 +66,11 @@ def autotune(ens, candidates=None, trials: int = 3, cache_file: str | None = Non
         ens.mc_set_variant(best["variant"])
         return dict(best, cached=True)
     K = int(ens.cfgs[0]["substeps"])
+    if candidates is None:
+        candidates = list(dict.fromkeys(DEFAULT_CANDIDATES + round_candidates(ens)))
     blob = ens.mc_checkpoint()
     results = []
-    for block, tile, variant in (candidates or DEFAULT_CANDIDATES):
+    for block, tile, variant in candidates:
         ens.mc_restore(blob)
         try:
             ens.mc_set_launch(block, tile)

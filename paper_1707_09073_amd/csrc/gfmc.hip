@@ -893,6 +893,35 @@ int mc_set_variant(mc_ctx* c, int variant) {
   return MC_OK;
 }
 
+int mc_occupancy(mc_ctx* c, int block, int* wg_per_cu, int* n_cu) {
+  if (!c || !wg_per_cu || !n_cu) return MC_E_ARG;
+  if (block < 64 || block > 512 || block % 64) return fail(c, MC_E_ARG, "unsupported block");
+  const size_t lds = sizeof(uint32_t) * flight_lds_words(c->ncell);
+  int n = 0;
+  hipError_t e;
+  if (c->f32) {
+    if (c->variant == 0)
+      e = c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight_refill<float, true>, block, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight_refill<float, false>, block, lds);
+    else
+      e = c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight<float, true>, block, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight<float, false>, block, lds);
+  } else {
+    if (c->variant == 0)
+      e = c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight_refill<double, true>, block, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight_refill<double, false>, block, lds);
+    else
+      e = c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight<double, true>, block, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight<double, false>, block, lds);
+  }
+  HIPCHK(c, e);
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  HIPCHK(c, hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  *wg_per_cu = n;
+  return MC_OK;
+}
+
 int mc_get_launch(const mc_ctx* c, int* block, int* tile, int* n_tiles) {
   if (!c) return MC_E_ARG;
   if (block) *block = c->block;

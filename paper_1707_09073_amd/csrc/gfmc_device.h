@@ -83,8 +83,9 @@ template <> struct Ar<float> {
   __device__ static float pw(float b, float e) { return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(b)); }
   // exp(x) - 1: a short series where exp(x) - 1 would cancel
   __device__ static float em1(float x) {
-    if (fabsf(x) < 1e-2f) return x * (1.0f + 0.5f * x * (1.0f + x * (1.0f / 3.0f)));
-    return __builtin_amdgcn_exp2f(x * 1.44269504088896f) - 1.0f;
+    const float s = x * (1.0f + 0.5f * x * (1.0f + x * (1.0f / 3.0f)));
+    const float e = __builtin_amdgcn_exp2f(x * 1.44269504088896f) - 1.0f;
+    return fabsf(x) < 1e-2f ? s : e;
   }
   // log(1 + x) for x >= 0 (the argument here is 2 xi >> 0)
   __device__ static float l1p(float x) { return __builtin_amdgcn_logf(1.0f + x) * 0.693147180559945f; }

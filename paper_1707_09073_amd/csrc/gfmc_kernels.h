@@ -131,16 +131,16 @@ __device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const
   // keeps full relative accuracy for forward scattering
   const T u2 = Ar<T>::u01(w.z), u3 = Ar<T>::u01(w.w);
   T X;
-  if (m == 1) {
-    const T a4 = Ar<T>::dv((T)4 * k2, f[6]);
-    X = Ar<T>::dv((T)2 * u2, (T)1 + ((T)1 - u2) * a4);
-  } else if (m == 2 || m == 3) {
+  if (m == 2 || m == 3) {
     const T gp = Ep * ((T)1 + pick3(M.alpha, v) * Ep);
     const T sg = Ar<T>::sq(g), sgp = Ar<T>::sq(gp);
     const T xi = Ar<T>::dv((T)2 * sg * sgp, (sg - sgp) * (sg - sgp));
     X = Ar<T>::dv(Ar<T>::em1(u2 * Ar<T>::l1p((T)2 * xi)), xi);
   } else {
-    X = (T)2 * u2;
+    // Brooks-Herring; with a4 = 0 the same expression is the isotropic
+    // X = 2 u2 exactly (a division by 1)
+    const T a4 = m == 1 ? Ar<T>::dv((T)4 * k2, f[6]) : (T)0;
+    X = Ar<T>::dv((T)2 * u2, (T)1 + ((T)1 - u2) * a4);
   }
   X = fmin(fmax(X, (T)0), (T)2);
   const T ct = (T)1 - X;
@@ -335,15 +335,10 @@ __device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* Sr, co
   }
   c.sel++;
   if (m < 0) { c.self++; return -1; }
-  int vp = v;
-  T Ep;
-  if (m <= 1) Ep = E;
-  else if (m == 2) Ep = E + M.hw_lo;
-  else if (m == 3) Ep = E - M.hw_lo;
-  else {
-    vp = (m - 4) >> 1;
-    Ep = E + pick3(M.Ec, v) - pick3(M.Ec, vp) + (((m - 4) & 1) ? -M.hw_iv : M.hw_iv);
-  }
+  // final energy by selects (every lane computes the intervalley form)
+  const int vp = m >= 4 ? (m - 4) >> 1 : v;
+  const T Eiv = E + pick3(M.Ec, v) - pick3(M.Ec, vp) + (((m - 4) & 1) ? -M.hw_iv : M.hw_iv);
+  const T Ep = m <= 1 ? E : (m == 2 ? E + M.hw_lo : (m == 3 ? E - M.hw_lo : Eiv));
   if (!(Ep > (T)0)) { c.self++; return -1; }
   if (v == 0) {
 #pragma unroll
@@ -361,16 +356,16 @@ __device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* Sr, co
   const T g = E * ((T)1 + pick3(M.alpha, v) * E);
   const T u2 = Ar<T>::u01(w.z), u3 = Ar<T>::u01(w.w);
   T X;
-  if (m == 1) {
-    const T a4 = Ar<T>::dv((T)4 * k2, f[6]);
-    X = Ar<T>::dv((T)2 * u2, (T)1 + ((T)1 - u2) * a4);
-  } else if (m == 2 || m == 3) {
+  if (m == 2 || m == 3) {
     const T gp = Ep * ((T)1 + pick3(M.alpha, v) * Ep);
     const T sg = Ar<T>::sq(g), sgp = Ar<T>::sq(gp);
     const T xi = Ar<T>::dv((T)2 * sg * sgp, (sg - sgp) * (sg - sgp));
     X = Ar<T>::dv(Ar<T>::em1(u2 * Ar<T>::l1p((T)2 * xi)), xi);
   } else {
-    X = (T)2 * u2;
+    // Brooks-Herring; with a4 = 0 the same expression is the isotropic
+    // X = 2 u2 exactly (a division by 1)
+    const T a4 = m == 1 ? Ar<T>::dv((T)4 * k2, f[6]) : (T)0;
+    X = Ar<T>::dv((T)2 * u2, (T)1 + ((T)1 - u2) * a4);
   }
   X = fmin(fmax(X, (T)0), (T)2);
   const T ct = (T)1 - X;

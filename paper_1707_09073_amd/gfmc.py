@@ -53,7 +53,7 @@ class McParticlesView(C.Structure):
 EXPORTS = ["mc_status_string", "mc_last_error", "mc_workspace_bytes", "mc_init", "mc_destroy",
            "mc_set_lattice_temperature", "mc_set_tables", "mc_step", "poisson_update", "mc_tally", "mc_maps",
            "mc_history", "mc_particles", "mc_read_particles", "mc_write_particles", "mc_read_fields",
-           "mc_read_tables", "mc_set_launch", "mc_get_launch", "mc_set_variant", "mc_use_graph", "mc_profile", "mc_profile_read",
+           "mc_read_tables", "mc_set_launch", "mc_get_launch", "mc_occupancy", "mc_set_variant", "mc_use_graph", "mc_profile", "mc_profile_read",
            "mc_checkpoint", "mc_restore"]
 
 _lib = None
@@ -87,6 +87,7 @@ def lib():
         L.mc_read_tables.argtypes = [vp, C.c_int, dp, dp, dp, dp]
         L.mc_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.mc_get_launch.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.mc_occupancy.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.mc_use_graph.argtypes = [vp, C.c_int]
         L.mc_set_variant.argtypes = [vp, C.c_int]
         L.mc_profile.argtypes = [vp, C.c_int]
@@ -277,6 +278,12 @@ class Ensemble:
         b, t, n = C.c_int(), C.c_int(), C.c_int()
         self._chk(lib().mc_get_launch(self._ctx, C.byref(b), C.byref(t), C.byref(n)), "mc_get_launch")
         return b.value, t.value, n.value
+
+    def mc_occupancy(self, block: int):
+        """(resident workgroups per compute unit, compute units) of the particle kernel."""
+        w, n = C.c_int(), C.c_int()
+        self._chk(lib().mc_occupancy(self._ctx, int(block), C.byref(w), C.byref(n)), "mc_occupancy")
+        return w.value, n.value
 
     def mc_set_variant(self, variant: int):
         self._chk(lib().mc_set_variant(self._ctx, int(variant)), "mc_set_variant")

@@ -73,8 +73,8 @@ def rel_l2(pred: np.ndarray, ref: np.ndarray) -> np.ndarray:
 # learned as its unit-norm shape (1800 values) and the logarithm of its norm,
 # so that a squared error in the shape is a relative error of the map.
 N_ENC = 2 * N_CELL + 2
-# the two log-norms' scale is divided by this in the loss (loss weight = square)
-LOGNORM_WEIGHT = 10.0
+# the two log-norms' scale is divided by this in the loss (loss weight = its square)
+LOGNORM_WEIGHT = 1.0
 
 
 def encode(Y: np.ndarray) -> np.ndarray:
@@ -112,13 +112,15 @@ class Surrogate:
     predicted error and Monte Carlo fallback."""
 
     def __init__(self, width=1024, depth=4, ensemble=4, max_batch=256, seed=1707_09073, tol=0.02,
-                 weight_decay=0.0, lognorm_weight=LOGNORM_WEIGHT, shared_scale=False):
+                 weight_decay=0.0, lognorm_weight=LOGNORM_WEIGHT, shared_scale=True):
         self.net = gfmc.SurrogateNet(3 + N_CELL, N_ENC, width=width, depth=depth, ensemble=ensemble,
                                      max_batch=max_batch, seed=seed, weight_decay=weight_decay)
         self.lognorm_weight = lognorm_weight
-        # shared_scale: one scale per map for its shape block and log-norm
-        # (divided by lognorm_weight), so that the loss follows the maps'
-        # relative L2 errors instead of per-cell z-scores
+        # shared_scale: one scale per map for its shape block and its log-norm
+        # (the latter divided by lognorm_weight), so that the squared error
+        # of each map's block is its squared relative L2 error; per-cell
+        # z-scores instead up-weight the noisy near-zero cells of the heat map
+        # and overfit
         self.shared_scale = shared_scale
         self.ensemble = ensemble
         self.max_batch = max_batch
@@ -126,7 +128,7 @@ class Surrogate:
         self.calib = 1.0
         self.box = None
 
-    def fit(self, X: np.ndarray, Y: np.ndarray, epochs: int = 200, batch: int = 128, lr: float = 1e-3,
+    def fit(self, X: np.ndarray, Y: np.ndarray, epochs: int = 2000, batch: int = 128, lr: float = 3e-4,
             seed: int = 0, log=print) -> list[float]:
         import torch
         T = encode(Y)

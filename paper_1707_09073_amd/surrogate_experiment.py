@@ -24,16 +24,18 @@ def main(argv=None) -> int:
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--val", type=int, default=200)
     ap.add_argument("--particles", type=int, default=200_000)
-    ap.add_argument("--warm", type=int, default=500, help="intervals (10 fs) before the window")
+    ap.add_argument("--warm", type=int, default=1000, help="intervals (10 fs) before the window")
     ap.add_argument("--window", type=int, default=1000, help="intervals (10 fs) averaged")
     ap.add_argument("--ref-seeds", type=int, default=4)
-    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=2000)
     ap.add_argument("--width", type=int, default=1024)
     ap.add_argument("--depth", type=int, default=4)
     ap.add_argument("--ensemble", type=int, default=4)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--weight-decay", type=float, default=0.0)
-    ap.add_argument("--lognorm-weight", type=float, default=10.0)
+    ap.add_argument("--lognorm-weight", type=float, default=1.0)
+    ap.add_argument("--per-cell-scale", action="store_true",
+                    help="z-score every output on its own (default: one scale per map)")
     ap.add_argument("--tol", type=float, default=0.02)
     ap.add_argument("--out", default="")
     a = ap.parse_args(argv)
@@ -70,7 +72,8 @@ def main(argv=None) -> int:
     mc_err = S.rel_l2(Yv_single, Yv).max(axis=1) * np.sqrt(a.ref_seeds / max(1, a.ref_seeds - 1))
 
     sur = S.Surrogate(width=a.width, depth=a.depth, ensemble=a.ensemble, max_batch=256, tol=a.tol,
-                      weight_decay=a.weight_decay, lognorm_weight=a.lognorm_weight)
+                      weight_decay=a.weight_decay, lognorm_weight=a.lognorm_weight,
+                      shared_scale=not a.per_cell_scale)
     t0 = time.perf_counter()
     losses = sur.fit(X, Y, epochs=a.epochs, batch=128, lr=a.lr, log=log)
     torch.cuda.synchronize()
@@ -98,7 +101,8 @@ def main(argv=None) -> int:
         "train_points": a.train, "val_points": a.val, "particles": a.particles,
         "warm_intervals": a.warm, "window_intervals": a.window, "ref_seeds": a.ref_seeds,
         "mlp": {"width": a.width, "depth": a.depth, "ensemble": a.ensemble, "epochs": a.epochs, "lr": a.lr,
-                "weight_decay": a.weight_decay, "lognorm_weight": a.lognorm_weight},
+                "weight_decay": a.weight_decay, "lognorm_weight": a.lognorm_weight,
+                "shared_scale": not a.per_cell_scale},
         "mc_seconds_per_bias_point": mc_time_per_point,
         "mc_train_data_seconds": t_train,
         "surrogate_fit_seconds": t_fit,

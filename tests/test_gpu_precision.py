@@ -1,7 +1,7 @@
 """Precision split on the 200k-electron half-nanowire device over 20 ps: the
 FP32-state GPU path and the FP64 GPU path against the FP64 oracle, per
 observable, each within 1% or 3 sigma.  Sigma is the standard error of the
-mean of 5 blocks of 2 ps of each run, combined in quadrature; the runs use
+mean of 10 blocks of 1 ps of each run, combined in quadrature; the runs use
 the same seeds but diverge chaotically after a few hundred events, so they
 are statistically independent over the window.  Printed as a table.
 
@@ -20,7 +20,7 @@ from paper_1707_09073_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-N, WARM, BLOCK, NBLK = 200_000, 1000, 200, 5
+N, WARM, BLOCK, NBLK = 200_000, 1000, 100, 10
 QE = 1.602176634e-19
 
 
@@ -108,8 +108,8 @@ def test_fp32_and_fp64_gpu_against_fp64_oracle_per_observable(oracle_mod):
             ok = (dev <= 0.01 * np.abs(mo)) | (dev <= 3 * s)
             rel = float(np.linalg.norm(mg - mo) / np.linalg.norm(mo))
             rel_s = float(np.linalg.norm(s) / np.linalg.norm(mo))
-            rows.append((name, label + " L2", rel, float(ok.mean()), rel, rel_s, ok.mean() >= 0.95))
-    _say(f"{'path':9s} {'observable':20s} {'value':>12s} {'oracle':>12s} {'rel diff':>9s} {'rel sigma':>9s} ok")
+            rows.append((name, f"{label} L2 ({int(ok.sum())}/100)", rel, float("nan"), rel, rel_s, ok.mean() >= 0.95))
+    _say(f"{'path':9s} {'observable':28s} {'value':>12s} {'oracle':>12s} {'rel diff':>9s} {'rel sigma':>9s} ok")
     for r in rows:
-        _say(f"{r[0]:9s} {r[1]:20s} {r[2]:12.5g} {r[3]:12.5g} {r[4]:9.4f} {r[5]:9.4f} {r[6]}")
+        _say(f"{r[0]:9s} {r[1]:28s} {r[2]:12.5g} {r[3]:12.5g} {r[4]:9.4f} {r[5]:9.4f} {r[6]}")
     assert all(r[6] for r in rows), [r for r in rows if not r[6]]
