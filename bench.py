@@ -35,7 +35,7 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # sources whose digest is given: VALU lane-instructions issued per free-flight
 # segment (SQ_INSTS_VALU x 64 / segments) and HBM bytes per segment
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a 1 GiB device copy).
-KERNEL_COUNTERS = {"sources_digest": "a2b06d2a55f939f2", "valu_lane_ops_per_segment": 161.6,
+KERNEL_COUNTERS = {"sources_digest": "699133ea30806f40", "valu_lane_ops_per_segment": 153.0,
                    "hbm_bytes_per_segment": 9.75, "profile": "profiles/k_flight_refill_device1e7_counters.md"}
 
 

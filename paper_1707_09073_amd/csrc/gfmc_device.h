@@ -33,14 +33,22 @@ __device__ __forceinline__ uint32_t meta_id(uint32_t m) { return m >> 3; }
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11).  Counter (c0..c3), key (k0, k1).
 // ---------------------------------------------------------------------------
+// The key (k0, k1) must be the same in every lane of the wavefront (every
+// caller passes the instance seed).  The key schedule then stays in scalar
+// registers and is recomputed with scalar adds at each call: the empty asm
+// below keeps the compiler from hoisting the 20 round keys out of the
+// callers' loops, which overflowed the scalar registers and spilled them.
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                         uint32_t k1) {
+  asm volatile("" : "+s"(k0), "+s"(k1));
   // one 32x32 -> 64-bit product per multiplier (v_mad_u64_u32 gives both halves)
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    // three-input XOR in one v_bitop3_b32 (truth table 0x96)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96),
+                   n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
     c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
   }

@@ -97,6 +97,17 @@ def main(argv=None) -> int:
     err = S.rel_l2(m, Yv[h:])
     perr = sur.calib * sp
     accept = (perr <= a.tol) & sur.in_box(Xv[h:])
+    # accuracy / time trade-off of the hybrid (surrogate where the calibrated
+    # predicted error is within tolerance, Monte Carlo elsewhere)
+    tradeoff = []
+    for tol in (0.02, 0.05, 0.10):
+        acc = (perr <= tol) & sur.in_box(Xv[h:])
+        t_hyb = acc.mean() * t_pred1 + (1 - acc.mean()) * mc_time_per_point
+        emax = err[acc].max(axis=1) if acc.any() else np.zeros(0)
+        tradeoff.append({"tol": tol, "accepted_fraction": float(acc.mean()),
+                         "accepted_within_tol_fraction": float(np.mean(emax <= tol)) if acc.any() else None,
+                         "hybrid_seconds_per_point": float(t_hyb),
+                         "hybrid_speedup": float(mc_time_per_point / t_hyb)})
     res = {
         "train_points": a.train, "val_points": a.val, "particles": a.particles,
         "warm_intervals": a.warm, "window_intervals": a.window, "ref_seeds": a.ref_seeds,
@@ -119,6 +130,7 @@ def main(argv=None) -> int:
         "accepted_heat_rel_l2_max": float(err[accept, 0].max()) if accept.any() else None,
         "accepted_within_tol_fraction": float(np.mean(err[accept].max(axis=1) <= a.tol)) if accept.any() else None,
         "fallback_fraction": float(1 - np.mean(accept)),
+        "tradeoff": tradeoff,
         "train_loss_curve": losses,
     }
     txt = json.dumps(res)
