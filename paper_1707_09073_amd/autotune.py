@@ -17,14 +17,14 @@ import os
 DEFAULT_CANDIDATES = [
     (256, 1536, 0), (256, 2048, 0), (256, 2560, 0), (256, 3072, 0), (256, 4096, 0),
     (256, 5120, 0), (256, 6144, 0), (256, 8192, 0),
-    (512, 2048, 0), (512, 4096, 0), (512, 8192, 0),
+    (512, 2048, 0), (512, 4096, 0), (512, 8192, 0), (384, 3072, 0), (384, 6144, 0),
     (128, 2048, 0), (256, 4096, 1),
 ]
 
 _cache: dict = {}
 
 
-def round_candidates(ens, blocks=(256, 512), max_rounds=8) -> list:
+def round_candidates(ens, blocks=(256, 384, 512), max_rounds=8) -> list:
     """Tile sizes whose tile count just fills r whole rounds of resident
     workgroups (r = 1..max_rounds): with workgroups of similar length, a last
     round that is partly empty leaves compute units idle."""
