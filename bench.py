@@ -30,21 +30,28 @@ HBM_PEAK_GBS = 8000.0
 # build disables packed FP32 math)
 ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
-# Per-segment figures of the particle kernel from its rocprofv3 counter passes
-# (profiles/k_flight_refill_device1e7_counters.md), valid for the kernel
-# sources whose digest is given: VALU lane-instructions issued per free-flight
-# segment (SQ_INSTS_VALU x 64 / segments) and HBM bytes per segment
-# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a 1 GiB device copy).
-KERNEL_COUNTERS = {"sources_digest": "699133ea30806f40", "valu_lane_ops_per_segment": 153.0,
-                   "hbm_bytes_per_segment": 9.75, "profile": "profiles/k_flight_refill_device1e7_counters.md"}
+# Per-segment figures of each particle-kernel variant from its rocprofv3
+# counter passes (the profile named), valid for the kernel sources whose
+# digest is given: VALU lane-instructions issued per free-flight segment
+# (SQ_INSTS_VALU x 64 / segments) and HBM bytes per segment (FETCH_SIZE x
+# 2.000 + WRITE_SIZE x 1.000, scales from a 1 GiB device copy).
+KERNELS = {0: "k_flight_refill<float,true>", 1: "k_flight<float,true>", 2: "k_flight_persist<float,true>"}
+KERNEL_COUNTERS = {
+    0: {"sources_digest": "699133ea30806f40", "valu_lane_ops_per_segment": 153.0, "hbm_bytes_per_segment": 9.75,
+        "profile": "profiles/k_flight_refill_device1e7_counters.md"},
+}
 
 
 def _kernel_digest() -> str:
+    """Digest of the particle-kernel sources with comments and blank lines
+    removed (a comment edit does not invalidate the counters)."""
     import hashlib
+    import re
     h = []
     for f in ("gfmc_kernels.h", "gfmc_device.h"):
-        with open(os.path.join(ROOT, "paper_1707_09073_amd", "csrc", f), "rb") as fh:
-            h.append(hashlib.sha256(fh.read()).hexdigest())
+        with open(os.path.join(ROOT, "paper_1707_09073_amd", "csrc", f)) as fh:
+            code = [re.sub(r"//.*$", "", line).rstrip() for line in fh]
+        h.append(hashlib.sha256("\n".join(l for l in code if l.strip()).encode()).hexdigest())
     return hashlib.sha256("".join(h).encode()).hexdigest()[:16]
 
 
@@ -149,7 +156,8 @@ def main() -> int:
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--graph", action="store_true", help="replay intervals from a hipGraph (no per-kernel timing)")
-    ap.add_argument("--variant", type=int, default=0, help="particle kernel: 0 lane refill, 1 one electron per lane")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="particle kernel: 0 lane refill per tile, 1 one electron per lane, 2 persistent")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default (or given) launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["device1e7", "sweep64"], default="device1e7",
@@ -230,8 +238,9 @@ def main() -> int:
         flight_s = prof["flight_ms"] / prof["n_flight"] * 1e-3
         segs_launch = segments / prof["n_flight"]
         per_launch = proc / prof["n_flight"]
-        fresh = _kernel_digest() == KERNEL_COUNTERS["sources_digest"] and args.variant == 0
-        ops = KERNEL_COUNTERS["valu_lane_ops_per_segment"] * segs_launch
+        kc = KERNEL_COUNTERS.get(args.variant, KERNEL_COUNTERS[0])
+        fresh = _kernel_digest() == kc["sources_digest"] and args.variant in KERNEL_COUNTERS
+        ops = kc["valu_lane_ops_per_segment"] * segs_launch
         achieved = ops / flight_s / 1e12
         # the state stream the fused interval must move: 6 x FP32 + u32 meta per
         # electron, read and written once per launch
@@ -239,10 +248,10 @@ def main() -> int:
         roofline = dict(
             bound="alu", achieved=achieved, peak=ALU_PEAK_LANE_OPS / 1e12, unit="TOP/s",
             frac=achieved / (ALU_PEAK_LANE_OPS / 1e12),
-            traffic=KERNEL_COUNTERS["hbm_bytes_per_segment"] * segs_launch if fresh else None,
+            traffic=kc["hbm_bytes_per_segment"] * segs_launch if fresh else None,
             counters_current=fresh,
-            kernel="k_flight_refill<float,true>" if args.variant == 0 else "k_flight<float,true>",
-            ops_per_segment=KERNEL_COUNTERS["valu_lane_ops_per_segment"], segments_per_launch=segs_launch,
+            kernel=KERNELS[args.variant],
+            ops_per_segment=kc["valu_lane_ops_per_segment"], segments_per_launch=segs_launch,
             avg_launch_ms=flight_s * 1e3,
             refresh_avg_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]),
             flight_share=prof["flight_ms"] / (prof["flight_ms"] + prof["refresh_ms"]),

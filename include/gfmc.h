@@ -196,9 +196,13 @@ int mc_read_fields(mc_ctx *ctx, int instance, double *h_phi, double *h_field, ui
  * and Gamma_v [3] (1/fs) of one instance.  Any pointer may be NULL. */
 int mc_read_tables(mc_ctx *ctx, int instance, double *h_shape, double *h_k4, double *h_factors, double *h_gamma);
 
-/* Launch shape of the particle kernel: workgroup size (64..512, multiple of
- * 64) and tile size (particles per tile, multiple of the workgroup size).
- * Results do not depend on the shape.  MC_E_ARG if unsupported. */
+/* Launch shape of the particle kernel: workgroup size (64..1024, multiple of
+ * 64; above 512 only for variant 2, else mc_step returns MC_E_ARG) and tile
+ * size (particles per tile, multiple of the workgroup size).
+ * Variants 0 and 1 launch one workgroup per tile; variant 2 launches as many
+ * workgroups as the GPU holds at once and uses the tiles only for the contact
+ * refill's free-slot counts.  Results do not depend on the shape.  MC_E_ARG
+ * if unsupported.  n_tiles reports the tiles, not the variant-2 grid. */
 int mc_set_launch(mc_ctx *ctx, int block, int tile);
 int mc_get_launch(const mc_ctx *ctx, int *block, int *tile, int *n_tiles);
 
@@ -211,8 +215,14 @@ int mc_occupancy(mc_ctx *ctx, int block, int *wg_per_cu, int *n_cu);
 
 /* Particle-kernel variant: 0 = lane refill (each lane pulls the next electron
  * of its tile as soon as its own finishes the interval; default), 1 = one
- * electron per lane per pass.  Results are identical up to the compiler's
- * floating-point contraction choices in each variant.  MC_E_ARG otherwise. */
+ * electron per lane per pass, 2 = persistent (as many workgroups as the GPU
+ * holds at once, each bound to one instance in proportion to its slots and
+ * owning every nw-th chunk of 256 slots of it, so each samples the whole slot
+ * range and the launch is balanced however the live electrons are spread over
+ * the slots).  Results are identical up to the compiler's floating-point
+ * contraction choices in each variant (variants 0 and 2 share the
+ * per-electron code).  MC_E_ARG for another value, MC_E_HIP if the occupancy
+ * query for variant 2 fails. */
 int mc_set_variant(mc_ctx *ctx, int variant);
 
 /* Replay each interval from a captured hipGraph (1) or launch eagerly (0). */

@@ -32,7 +32,7 @@ struct Layout {
 struct Offsets {
   size_t table64, table32, fac64, fac32, field64, field32, phi, gamma64, gamma32, Tcell, count, heat, dens,
       counters, flags, ctl, next_id, ip, tiles, partial, acc, tile_dead, tile_off, plan, slots, minv, ainv, rhs, hist, reps,
-      nrep, bpart;
+      nrep, bpart, wg_inst;
   size_t kx, ky, kz, x, y, z, meta;
 };
 
@@ -135,6 +135,7 @@ Offsets layout(const mc_config* c, int n, size_t* total) {
   o.acc = L.take(dev ? sizeof(unsigned long long) * n * 5 * nc : 0);
   o.tile_dead = L.take(sizeof(uint32_t) * max_tiles);
   o.tile_off = L.take(sizeof(uint32_t) * max_tiles);
+  o.wg_inst = L.take(sizeof(int) * max_tiles);
   o.plan = L.take(sizeof(Plan) * n);
   o.slots = L.take(dev ? sizeof(uint32_t) * cap : 0);  // contact-refill slot list
   o.minv = L.take(dev ? sizeof(double) * c[0].n_cells[0] * (size_t)(c[0].n_cells[1] * c[0].n_cells[2]) *
@@ -170,6 +171,8 @@ struct mc_ctx {
   Offsets o;
   int nb = 0, ncell = 1, nx = 1, ny = 1, nz = 1, P = 1;
   int block = 256, tile = 0, n_tiles = 0;
+  int max_tiles = 0;        // tiles at the smallest tile size: partial histograms the workspace holds
+  int n_wg = 0, chunk = 256;  // persistent kernel: workgroups, slots per chunk
   unsigned inj_blocks = 0;  // refill grid: covers the most electrons one instance can need
   size_t total_cap = 0;
   std::vector<long long> base;
@@ -183,7 +186,7 @@ struct mc_ctx {
   double ck = 0.0;
   bool use_graph = false;
   hipGraphExec_t gexec = nullptr;
-  int variant = 0;  // 0: lane refill, 1: one electron per lane
+  int variant = 0;  // 0: lane refill, 1: one electron per lane, 2: persistent
   bool profile = false;
   std::vector<hipEvent_t> ev_pool;   // triples: before flight, after flight, after refresh
   size_t ev_used = 0;
@@ -235,12 +238,51 @@ void mats(mc_ctx* c) {
   }
 }
 
+int flight_occupancy(mc_ctx* c, int variant, int block, int* wg_per_cu, int* n_cu);
+
+// Tiles of the current tile size, and for the persistent kernel the chunks of
+// each instance (chunks never straddle a tile) and its share of the
+// workgroups the GPU holds at once (at least one each, in proportion to the
+// chunks, at most one per chunk).
 int upload_tiles(mc_ctx* c) {
   TilePlan tp = make_tiles(c->cfg.data(), c->n_inst, c->tile);
   c->n_tiles = (int)tp.tiles.size();
-  for (int i = 0; i < c->n_inst; ++i) { c->ip[i].t0 = tp.t0[i]; c->ip[i].t1 = tp.t1[i]; }
+  const int cpt = (c->tile + c->chunk - 1) / c->chunk;
+  long long tot = 0;
+  for (int i = 0; i < c->n_inst; ++i) {
+    InstParams& I = c->ip[i];
+    I.t0 = tp.t0[i];
+    I.t1 = tp.t1[i];
+    const int nt = I.t1 - I.t0, last = I.cap - (nt - 1) * c->tile;
+    I.nchunk = (nt - 1) * cpt + (last + c->chunk - 1) / c->chunk;
+    tot += I.nchunk;
+  }
+  int wg = c->n_inst;
+  if (c->variant == 2) {
+    int per = 0, ncu = 0, rc;
+    if ((rc = flight_occupancy(c, 2, c->block, &per, &ncu)) != MC_OK) return rc;
+    if (per < 1) return fail(c, MC_E_ARG, "persistent kernel does not fit this workgroup size");
+    wg = std::max(c->n_inst, std::min(per * ncu, c->max_tiles));
+  }
+  // no workgroup may own more than kMaxTile slots (16-bit packed deposit)
+  const int max_chunks = kMaxTile / c->chunk;
+  std::vector<int> wg_inst;
+  for (int i = 0; i < c->n_inst; ++i) {
+    InstParams& I = c->ip[i];
+    long long share = 1 + (long long)(wg - c->n_inst) * I.nchunk / std::max(1LL, tot);
+    share = std::max<long long>(share, (I.nchunk + max_chunks - 1) / max_chunks);
+    I.w0 = (int)wg_inst.size();
+    I.w1 = I.w0 + (int)std::min<long long>(share, I.nchunk);
+    wg_inst.resize(I.w1, i);
+  }
+  if ((int)wg_inst.size() > c->max_tiles) return fail(c, MC_E_ARG, "persistent grid exceeds the partial histograms");
+  c->n_wg = (int)wg_inst.size();
   HIPCHK(c, hipMemcpyAsync(c->ws + c->o.tiles, tp.tiles.data(), sizeof(TileDesc) * tp.tiles.size(),
                            hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->o.wg_inst, wg_inst.data(), sizeof(int) * wg_inst.size(), hipMemcpyHostToDevice,
+                           c->st));
+  // free-slot counts start from zero under the new tiling
+  HIPCHK(c, hipMemsetAsync(c->ws + c->o.tile_dead, 0, sizeof(uint32_t) * c->max_tiles, c->st));
   HIPCHK(c, hipMemcpyAsync(c->ws + c->o.ip, c->ip.data(), sizeof(InstParams) * c->n_inst, hipMemcpyHostToDevice,
                            c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -298,6 +340,9 @@ FlightArgs<T> flight_args(mc_ctx* c, const Mat<T>& M, const Geo<T>& G, size_t ta
   a.counters = c->p<unsigned long long>(c->o.counters);
   a.flags = c->p<int>(c->o.flags);
   a.ctl = c->p<uint32_t>(c->o.ctl);
+  a.wg_inst = c->p<int>(c->o.wg_inst);
+  a.tile = c->tile;
+  a.chunk = c->chunk;
   a.M = M;
   a.G = G;
   a.nb = c->nb;
@@ -311,6 +356,7 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
   const int nc = c->ncell;
   dim3 gp((5 * nc + 255) / 256, kMergeGroups, c->n_inst);
   k_merge_partial<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc,
+                                         after_flight && c->variant == 2 ? 1 : 0,
                                          c->p<unsigned long long>(c->o.acc));
   dim3 gm((5 * nc + 255) / 256, c->n_inst);
   k_merge_final<<<gm, 256, 0, c->st>>>(c->p<unsigned long long>(c->o.acc), nc, c->p<uint32_t>(c->o.count),
@@ -368,33 +414,63 @@ hipEvent_t prof_event(mc_ctx* c) {
   return c->ev_pool[c->ev_used++];
 }
 
+size_t flight_lds_bytes(const mc_ctx* c, int variant) {
+  (void)variant;  // every lane-refill variant keeps the same LDS histogram
+  return sizeof(uint32_t) * flight_lds_words(c->ncell);
+}
+
+template <typename T>
+void launch_flight(mc_ctx* c, const FlightArgs<T>& a) {
+  const size_t lds = flight_lds_bytes(c, c->variant);
+  if (c->variant == 2) {
+    if (c->dev) k_flight_persist<T, true><<<c->n_wg, c->block, lds, c->st>>>(a);
+    else k_flight_persist<T, false><<<c->n_wg, c->block, lds, c->st>>>(a);
+  } else if (c->variant == 0) {
+    if (c->dev) k_flight_refill<T, true><<<c->n_tiles, c->block, lds, c->st>>>(a);
+    else k_flight_refill<T, false><<<c->n_tiles, c->block, lds, c->st>>>(a);
+  } else {
+    if (c->dev) k_flight<T, true><<<c->n_tiles, c->block, lds, c->st>>>(a);
+    else k_flight<T, false><<<c->n_tiles, c->block, lds, c->st>>>(a);
+  }
+}
+
+template <typename T>
+hipError_t occupancy_of(const mc_ctx* c, int variant, int block, int* n) {
+  const size_t lds = flight_lds_bytes(c, variant);
+  if (variant == 2)
+    return c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_flight_persist<T, true>, block, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_flight_persist<T, false>, block, lds);
+  if (variant == 0)
+    return c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_flight_refill<T, true>, block, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_flight_refill<T, false>, block, lds);
+  return c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_flight<T, true>, block, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_flight<T, false>, block, lds);
+}
+
+// Workgroups of the particle kernel (variant, precision of the context) that
+// one compute unit holds at once, and the compute units of the current device.
+int flight_occupancy(mc_ctx* c, int variant, int block, int* wg_per_cu, int* n_cu) {
+  int n = 0;
+  HIPCHK(c, c->f32 ? occupancy_of<float>(c, variant, block, &n) : occupancy_of<double>(c, variant, block, &n));
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  HIPCHK(c, hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  *wg_per_cu = n;
+  return MC_OK;
+}
+
 void enqueue_interval(mc_ctx* c) {
-  const size_t lds = sizeof(uint32_t) * flight_lds_words(c->ncell);
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (c->profile) {
     e0 = prof_event(c); e1 = prof_event(c); e2 = prof_event(c);
     if (e0) (void)hipEventRecord(e0, c->st);
   }
-  if (c->f32) {
-    FlightArgs<float> a = flight_args<float>(c, c->M32, c->G32, c->o.table32, c->o.fac32, c->o.field32, c->o.gamma32);
-    if (c->variant == 0) {
-      if (c->dev) k_flight_refill<float, true><<<c->n_tiles, c->block, lds, c->st>>>(a);
-      else k_flight_refill<float, false><<<c->n_tiles, c->block, lds, c->st>>>(a);
-    } else {
-      if (c->dev) k_flight<float, true><<<c->n_tiles, c->block, lds, c->st>>>(a);
-      else k_flight<float, false><<<c->n_tiles, c->block, lds, c->st>>>(a);
-    }
-  } else {
-    FlightArgs<double> a =
-        flight_args<double>(c, c->M64, c->G64, c->o.table64, c->o.fac64, c->o.field64, c->o.gamma64);
-    if (c->variant == 0) {
-      if (c->dev) k_flight_refill<double, true><<<c->n_tiles, c->block, lds, c->st>>>(a);
-      else k_flight_refill<double, false><<<c->n_tiles, c->block, lds, c->st>>>(a);
-    } else {
-      if (c->dev) k_flight<double, true><<<c->n_tiles, c->block, lds, c->st>>>(a);
-      else k_flight<double, false><<<c->n_tiles, c->block, lds, c->st>>>(a);
-    }
-  }
+  if (c->f32)
+    launch_flight<float>(c, flight_args<float>(c, c->M32, c->G32, c->o.table32, c->o.fac32, c->o.field32,
+                                               c->o.gamma32));
+  else
+    launch_flight<double>(c, flight_args<double>(c, c->M64, c->G64, c->o.table64, c->o.fac64, c->o.field64,
+                                                 c->o.gamma64));
   if (e1) (void)hipEventRecord(e1, c->st);
   if (c->dev) {
     enqueue_refresh(c, true);
@@ -474,6 +550,7 @@ int mc_init(mc_ctx** out, const mc_config* cfgs, int n, void* d_ws, size_t ws_by
   c->ncell = c->nx * c->ny * c->nz;
   c->tile = c->dev ? 8192 : 1024;
   c->block = 256;
+  c->max_tiles = (int)make_tiles(cfgs, n, min_tile(cfgs[0])).tiles.size();
   mats(c);
   // per-instance parameters
   long long base = 0;
@@ -617,6 +694,8 @@ int mc_step(mc_ctx* c, int n_substeps) {
   const int K = c->cfg[0].substeps;
   if (n_substeps < 0 || n_substeps % K) return fail(c, MC_E_ARG, "n_substeps must be a multiple of substeps");
   const int n = n_substeps / K;
+  if (c->block > 512 && c->variant != 2)
+    return fail(c, MC_E_ARG, "workgroups of more than 512 lanes need the persistent variant");
   if (n == 0) return MC_OK;
   if (c->use_graph && !c->profile) {
     if (!c->gexec) {
@@ -878,7 +957,7 @@ int mc_read_tables(mc_ctx* c, int inst, double* h_shape, double* h_k4, double* h
 
 int mc_set_launch(mc_ctx* c, int block, int tile) {
   if (!c) return MC_E_ARG;
-  if (block < 64 || block > 512 || block % 64 || tile < min_tile(c->cfg[0]) || tile > kMaxTile || tile % block)
+  if (block < 64 || block > 1024 || block % 64 || tile < min_tile(c->cfg[0]) || tile > kMaxTile || tile % block)
     return fail(c, MC_E_ARG, "unsupported launch shape");
   c->block = block;
   c->tile = tile;
@@ -887,39 +966,16 @@ int mc_set_launch(mc_ctx* c, int block, int tile) {
 }
 
 int mc_set_variant(mc_ctx* c, int variant) {
-  if (!c || variant < 0 || variant > 1) return fail(c, MC_E_ARG, "unknown kernel variant");
+  if (!c || variant < 0 || variant > 2) return fail(c, MC_E_ARG, "unknown kernel variant");
   c->variant = variant;
   drop_graph(c);
-  return MC_OK;
+  return upload_tiles(c);
 }
 
 int mc_occupancy(mc_ctx* c, int block, int* wg_per_cu, int* n_cu) {
   if (!c || !wg_per_cu || !n_cu) return MC_E_ARG;
-  if (block < 64 || block > 512 || block % 64) return fail(c, MC_E_ARG, "unsupported block");
-  const size_t lds = sizeof(uint32_t) * flight_lds_words(c->ncell);
-  int n = 0;
-  hipError_t e;
-  if (c->f32) {
-    if (c->variant == 0)
-      e = c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight_refill<float, true>, block, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight_refill<float, false>, block, lds);
-    else
-      e = c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight<float, true>, block, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight<float, false>, block, lds);
-  } else {
-    if (c->variant == 0)
-      e = c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight_refill<double, true>, block, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight_refill<double, false>, block, lds);
-    else
-      e = c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight<double, true>, block, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_flight<double, false>, block, lds);
-  }
-  HIPCHK(c, e);
-  int dev = 0;
-  HIPCHK(c, hipGetDevice(&dev));
-  HIPCHK(c, hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  *wg_per_cu = n;
-  return MC_OK;
+  if (block < 64 || block > 1024 || block % 64) return fail(c, MC_E_ARG, "unsupported block");
+  return flight_occupancy(c, c->variant, block, wg_per_cu, n_cu);
 }
 
 int mc_get_launch(const mc_ctx* c, int* block, int* tile, int* n_tiles) {

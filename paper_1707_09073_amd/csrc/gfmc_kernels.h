@@ -1,14 +1,23 @@
 // gfmc_kernels.h -- gfx950 kernels of the electron Monte Carlo step.
 //
 // One flight interval (K sub-steps, one Poisson refresh) is:
-//   k_flight      per particle: free flight + self-scattering selection +
-//                 final state, heat and mechanism counts in LDS, deposit of
-//                 the survivors per subcell; one workgroup per tile.
-//   k_merge       sums the per-tile subcell histograms (deposit and heat).
-//   k_inject_*    refills the contact subcells to neutrality (device mode).
-//   k_poisson     one workgroup per instance: block-tridiagonal direct solve
-//                 of the finite-volume Poisson equation, then the field.
-// Bulk mode replaces the last three by k_bulk_* (per-interval observables).
+//   k_flight_refill  per lane-slot: free flight + self-scattering selection
+//                    for K sub-steps, lanes refilled from an LDS queue of the
+//                    tile's particles; mechanism counts, heat and the deposit
+//                    of the survivors per subcell kept in LDS, written per
+//                    tile (k_flight: one particle per thread, same physics;
+//                    k_flight_persist: resident workgroups, each working
+//                    every nw-th chunk of its instance's slots).
+//   k_merge_*        sums the per-tile subcell histograms (deposit and heat).
+//   k_inject_*       refills the contact subcells to neutrality (device mode):
+//                    per-instance plan, slot list, one thread per electron.
+//   k_poisson_rhs    charge balance per cell with the terminal faces, then
+//   k_poisson_gemv/gemm  the potential from the dense inverse of the
+//                    finite-volume Poisson matrix (built once at init by
+//                    k_poisson_factor + k_poisson_inverse), then
+//   k_field          the cell-centred field.
+// Bulk mode replaces deposit, injection and Poisson by k_bulk_* (per-interval
+// observables).
 #pragma once
 #include "gfmc_device.h"
 
@@ -33,7 +42,8 @@ struct InstParams {
   long long base;
   int t0, t1;     // tile range of the instance
   int target;     // neutral electrons per contact subcell
-  int pad;
+  int w0, w1;     // persistent kernel: workgroups of the instance
+  int nchunk;     // persistent kernel: slot chunks of the instance
   double N_D_nm;  // donors per nm^3
   double N_D_m3;  // donors per m^3
   double w;       // electrons per superparticle
@@ -63,6 +73,8 @@ struct FlightArgs {
   unsigned long long* counters;
   int* flags;
   const uint32_t* ctl;
+  const int* wg_inst;  // persistent kernel: instance of each workgroup
+  int tile, chunk;     // persistent kernel: tile and chunk sizes (slots)
   Mat<T> M;
   Geo<T> G;
   int nb;
@@ -427,6 +439,136 @@ __device__ __forceinline__ int drift_e(const FlightArgs<T>& a, int v, T dt, T fx
   return -1;
 }
 
+// The electron a lane is working on in the lane-refill kernels.
+template <typename T>
+struct LaneE {
+  T kx, ky, kz, x, y, z, t, E;
+  int v;
+  uint32_t id, j;
+  long long p;  // slot
+};
+
+// Load slot p (the state together with the meta word: one memory round trip
+// per slot; a free slot's stale state is discarded).  Returns whether the
+// slot holds a live electron, which then becomes the lane's electron.
+template <typename T, bool DEV>
+__device__ __forceinline__ bool take_slot(const FlightArgs<T>& a, long long p, LaneE<T>& L, Cnt& c) {
+  const uint32_t meta = a.meta[p];
+  const T lkx = a.kx[p], lky = a.ky[p], lkz = a.kz[p];
+  T lx = (T)0, ly = (T)0, lz = (T)0;
+  if (DEV) { lx = a.x[p]; ly = a.y[p]; lz = a.z[p]; }
+  if (!(meta & kAlive)) { c.dead++; return false; }
+  c.proc++;
+  L.p = p;
+  L.kx = lkx; L.ky = lky; L.kz = lkz;
+  L.x = lx; L.y = ly; L.z = lz;
+  L.v = meta_valley(meta);
+  L.id = meta_id(meta);
+  L.j = 0;
+  L.t = (T)0;
+  L.E = energy(a.M, L.v, L.kx, L.ky, L.kz);
+  return true;
+}
+
+// One segment of the lane's electron: the scattering event that ends the
+// previous flight (none at the start of the interval, j = 0), then the flight
+// to the next selection or to the end of the interval.  The rate-table row
+// (pre-event valley and energy bin), the cell's factor row and its field are
+// issued before the random numbers, whose arithmetic then covers their
+// latency (the position does not change in an event, so the field row serves
+// the flight after it).  Returns -2 while the interval goes on, -1 at its end
+// (or at the event guard), 0 or 1 when the electron left through the source
+// or drain contact.
+template <typename T, bool DEV>
+__device__ __forceinline__ int lane_segment(const FlightArgs<T>& a, const InstParams& P, const T* fac,
+                                            const T* field, const T (&gam)[3], uint32_t n_int, int ncell,
+                                            LaneE<T>& L, Cnt& c, uint32_t* sh_heat, uint32_t* sh_real, uint32_t* rc,
+                                            bool& guard_hit) {
+  const int cell = DEV ? cell_of(a.G, L.x, L.y, L.z) : 0;
+  const T eb = Ar<T>::dv(L.E, a.dE);
+  const bool ovf = !(eb < (T)a.nb);
+  const int bin = (int)fmin(eb, (T)(a.nb - 1));  // NaN -> last bin
+  T Sr[kTRow], f[kFRow], F[4];
+  load_row<kTRow>(a.table + ((size_t)L.v * a.nb + bin) * kTRow, Sr);
+  load_row<kFRow>(fac + kFRow * cell, f);
+  load_row<4>(field + 4 * cell, F);
+  __builtin_amdgcn_sched_barrier(0);  // keep the loads above the generator
+  const uint4 w = philox(L.id, n_int, L.j, P.tagw, P.key0, P.key1);
+  if (L.j > 0) {
+    if (ovf) c.ovf++;
+    scatter_e<T>(a, Sr, f, gam, L.v, L.kx, L.ky, L.kz, L.E, w, cell, ncell, c, sh_heat, sh_real, rc);
+  }
+  const T tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), pick3(gam, L.v));
+  const bool last = L.t + tau >= a.TP;
+  const int ex = drift_e<T, DEV>(a, L.v, last ? a.TP - L.t : tau, F[0], F[1], F[2], L.kx, L.ky, L.kz, L.x, L.y,
+                                 L.z, L.E, c);
+  if (ex >= 0) return ex;
+  if (last) return -1;
+  L.t += tau;
+  ++L.j;
+  if (L.j > (uint32_t)kMaxEvents) { guard_hit = true; return -1; }
+  return -2;
+}
+
+// Write the lane's electron back at the end of its interval (ex as returned
+// by lane_segment) and deposit it in its subcell if it is still inside.
+template <typename T, bool DEV>
+__device__ __forceinline__ void retire(const FlightArgs<T>& a, const LaneE<T>& L, int ex, Cnt& c, uint32_t* sh_dep,
+                                       bool packed_dep, bool& nan_hit) {
+  const bool alive = ex < 0;
+  c.ex0 += (uint32_t)(ex == 0);  // as adds: a pair of guarded increments is merged into an indexed one in scratch
+  c.ex1 += (uint32_t)(ex == 1);
+  if (!(isfinite(L.kx) && isfinite(L.ky) && isfinite(L.kz))) nan_hit = true;
+  const long long p = L.p;
+  a.kx[p] = L.kx; a.ky[p] = L.ky; a.kz[p] = L.kz;
+  if (DEV) { a.x[p] = L.x; a.y[p] = L.y; a.z[p] = L.z; }
+  a.meta[p] = (L.id << 3) | (alive ? kAlive : 0u) | (uint32_t)L.v;
+  if (!alive) c.dead++;
+  else if (DEV) {
+    const int cell = cell_of(a.G, L.x, L.y, L.z);
+    if (packed_dep) dep_add(sh_dep, cell);
+    else atomicAdd(sh_dep + cell, 1u);
+  }
+}
+
+// Workgroup end of the lane-refill kernels: per-lane counters summed into LDS,
+// then the workgroup's histogram written to its partial (deposit unpacked when
+// packed) and the event counters added to the instance's totals.
+template <bool DEV>
+__device__ __forceinline__ void flush_workgroup(const Cnt& c, const uint32_t* rc, uint32_t* sh_dep, bool packed_dep,
+                                                uint32_t* sh_heat, uint32_t* sh_real, uint32_t* sh_misc, int ncell,
+                                                uint32_t* part, unsigned long long* cnt, uint32_t* tile_dead_out) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t vals[8] = {c.sel, c.self, c.ovf, c.ex0, c.ex1, c.refl, c.dead, c.proc};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t s = wave_sum(vals[q]);
+    if (lane == 0 && s) atomicAdd(sh_misc + q, s);
+  }
+#pragma unroll
+  for (int q = 0; q < kNM; ++q) {
+    const uint32_t s = wave_sum(rc[q]);
+    if (lane == 0 && s) atomicAdd(sh_real + q, s);
+  }
+  __syncthreads();
+  if (DEV) {
+    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x)
+      part[i] = i < ncell ? (packed_dep ? dep_get(sh_dep, i) : sh_dep[i]) : sh_heat[i - ncell];
+  }
+  for (int tid = threadIdx.x; tid < 39; tid += blockDim.x) {
+    if (tid < 30) {
+      if (sh_real[tid]) atomicAdd(cnt + C_REAL + tid, (unsigned long long)sh_real[tid]);
+    } else if (tid < 38) {
+      const int q = tid - 30;
+      const int slot = q == 0 ? C_SEL : q == 1 ? C_SELF : q == 2 ? C_OVF : q == 3 ? C_EXIT0
+                     : q == 4 ? C_EXIT1 : q == 5 ? C_REFL : q == 6 ? -1 : C_PROC;
+      if (slot >= 0 && sh_misc[q]) atomicAdd(cnt + slot, (unsigned long long)sh_misc[q]);
+    } else if (tile_dead_out) {
+      *tile_dead_out = sh_misc[6];
+    }
+  }
+}
+
 // Lane-refill variant: each lane works one segment per iteration (the start
 // of an electron's interval, or one scattering event plus the next flight)
 // and pulls the next electron of the tile from a workgroup queue as soon as
@@ -457,10 +599,7 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
   Cnt c = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
   bool guard_hit = false, nan_hit = false;
   bool has = false, exhausted = false;
-  long long p = 0;
-  T kx = (T)0, ky = (T)0, kz = (T)0, x = (T)0, y = (T)0, z = (T)0, t = (T)0, E = (T)0;
-  int v = 0;
-  uint32_t id = 0, j = 0;
+  LaneE<T> L = {};
   uint32_t rc[kNM];
 #pragma unroll
   for (int q = 0; q < kNM; ++q) rc[q] = 0u;
@@ -475,125 +614,140 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
       base = __shfl(base, first);
       if (want) {
         const uint32_t idx = base + (uint32_t)__popcll(m & lt);
-        if (idx < (uint32_t)td.count) {
-          p = td.start + idx;
-          // the state is loaded together with the meta word (one memory
-          // round trip per slot; a free slot's stale state is discarded)
-          const uint32_t meta = a.meta[p];
-          const T lkx = a.kx[p], lky = a.ky[p], lkz = a.kz[p];
-          T lx = (T)0, ly = (T)0, lz = (T)0;
-          if (DEV) { lx = a.x[p]; ly = a.y[p]; lz = a.z[p]; }
-          if (meta & kAlive) {
-            has = true;
-            c.proc++;
-            kx = lkx; ky = lky; kz = lkz;
-            x = lx; y = ly; z = lz;
-            v = meta_valley(meta);
-            id = meta_id(meta);
-            j = 0;
-            t = (T)0;
-            E = energy(a.M, v, kx, ky, kz);
-          } else {
-            c.dead++;
-          }
-        } else {
-          exhausted = true;
-        }
+        if (idx < (uint32_t)td.count) has = take_slot<T, DEV>(a, td.start + idx, L, c);
+        else exhausted = true;
       }
       want = !has && !exhausted;
       m = __ballot(want);
     }
     if (!__any(has)) break;
     if (has) {
-      // the rate-table row (pre-event valley and energy bin), the cell's
-      // factor row and its field: loads issued before the random numbers,
-      // whose arithmetic then covers their latency (the position does not
-      // change in an event, so the field row serves the flight after it)
-      const int cell = DEV ? cell_of(a.G, x, y, z) : 0;
-      const T eb = Ar<T>::dv(E, a.dE);
-      const bool ovf = !(eb < (T)a.nb);
-      const int bin = (int)fmin(eb, (T)(a.nb - 1));  // NaN -> last bin
-      T Sr[kTRow], f[kFRow], F[4];
-      load_row<kTRow>(a.table + ((size_t)v * a.nb + bin) * kTRow, Sr);
-      load_row<kFRow>(fac + kFRow * cell, f);
-      load_row<4>(field + 4 * cell, F);
-      __builtin_amdgcn_sched_barrier(0);  // keep the loads above the generator
-      const uint4 w = philox(id, n_int, j, P.tagw, P.key0, P.key1);
-      if (j > 0) {
-        if (ovf) c.ovf++;
-        scatter_e<T>(a, Sr, f, gam, v, kx, ky, kz, E, w, cell, ncell, c, sh_heat, sh_real, rc);
-      }
-      const T tau = Ar<T>::dv(-Ar<T>::ln(Ar<T>::u01(w.x)), pick3(gam, v));
-      const bool last = t + tau >= a.TP;
-      const int ex = drift_e<T, DEV>(a, v, last ? a.TP - t : tau, F[0], F[1], F[2], kx, ky, kz, x, y, z, E, c);
-      bool fin = last || ex >= 0;
-      if (!fin) {
-        t += tau;
-        ++j;
-        if (j > (uint32_t)kMaxEvents) { guard_hit = true; fin = true; }
-      }
-      if (fin) {
-        const bool alive = ex < 0;
-        if (ex == 0) c.ex0++;
-        if (ex == 1) c.ex1++;
-        if (!(isfinite(kx) && isfinite(ky) && isfinite(kz))) nan_hit = true;
-        a.kx[p] = kx; a.ky[p] = ky; a.kz[p] = kz;
-        if (DEV) { a.x[p] = x; a.y[p] = y; a.z[p] = z; }
-        a.meta[p] = (id << 3) | (alive ? kAlive : 0u) | (uint32_t)v;
-        if (!alive) c.dead++;
-        else if (DEV) dep_add(sh_dep, cell_of(a.G, x, y, z));
+      const int r = lane_segment<T, DEV>(a, P, fac, field, gam, n_int, ncell, L, c, sh_heat, sh_real, rc, guard_hit);
+      if (r > -2) {
+        retire<T, DEV>(a, L, r, c, sh_dep, true, nan_hit);
         has = false;
       }
     }
   }
   if (guard_hit) set_flag(a.flags, td.inst, -4);
   if (nan_hit) set_flag(a.flags, td.inst, -6);
-  {
-    const uint32_t vals[8] = {c.sel, c.self, c.ovf, c.ex0, c.ex1, c.refl, c.dead, c.proc};
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const uint32_t s = wave_sum(vals[q]);
-      if (lane == 0 && s) atomicAdd(sh_misc + q, s);
-    }
-#pragma unroll
-    for (int q = 0; q < kNM; ++q) {
-      const uint32_t s = wave_sum(rc[q]);
-      if (lane == 0 && s) atomicAdd(sh_real + q, s);
-    }
-  }
-  __syncthreads();
-  if (DEV) {
-    uint32_t* part = a.partial + (size_t)blockIdx.x * 5 * ncell;
-    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x)
-      part[i] = i < ncell ? dep_get(sh_dep, i) : sh_heat[i - ncell];
-  }
-  unsigned long long* cnt = a.counters + (size_t)td.inst * kNCnt;
-  for (int tid = threadIdx.x; tid < 39; tid += blockDim.x) {
-    if (tid < 30) {
-      if (sh_real[tid]) atomicAdd(cnt + C_REAL + tid, (unsigned long long)sh_real[tid]);
-    } else if (tid < 38) {
-      const int q = tid - 30;
-      const int slot = q == 0 ? C_SEL : q == 1 ? C_SELF : q == 2 ? C_OVF : q == 3 ? C_EXIT0
-                     : q == 4 ? C_EXIT1 : q == 5 ? C_REFL : q == 6 ? -1 : C_PROC;
-      if (slot >= 0 && sh_misc[q]) atomicAdd(cnt + slot, (unsigned long long)sh_misc[q]);
-    } else {
-      a.tile_dead[blockIdx.x] = sh_misc[6];
-    }
-  }
+  flush_workgroup<DEV>(c, rc, sh_dep, true, sh_heat, sh_real, sh_misc, ncell,
+                       a.partial + (size_t)blockIdx.x * 5 * ncell, a.counters + (size_t)td.inst * kNCnt,
+                       a.tile_dead + blockIdx.x);
 }
 
-// Sum the per-tile histograms of each instance in two passes: tile groups
-// add their partial sums into a u64 accumulator (atomics on 5 x ncell
+// Persistent variant: as many workgroups as the GPU holds at once, each bound
+// to one instance (a.wg_inst; w1 - w0 of them per instance, in proportion to
+// its slots).  The instance's slots are cut into chunks of at most a.chunk
+// consecutive slots that never straddle a tile; workgroup r of the instance
+// owns chunks r, r + nw, r + 2 nw, ..., so every workgroup samples the whole
+// slot range evenly and holds about the same number of live electrons however
+// they are spread over the slots (the contact refill fills the lowest free
+// slots, so live electrons gather at the front).  Its wavefronts take the
+// workgroup's chunks one at a time from an LDS counter and refill their lanes
+// from the current chunk.  No global queue: nothing to reset between
+// launches.  One histogram per workgroup, laid out as in k_flight_refill (the
+// host gives every instance enough workgroups that none owns more than
+// kMaxTile slots, so the packed deposit cannot carry).  Free slots are added to the tile's
+// count by atomics, once per chunk and once per electron that leaves (the
+// refill plan clears the counts after reading them).  Per-electron arithmetic
+// and random-number use are those of k_flight_refill.
+template <typename T, bool DEV>
+__global__ void __launch_bounds__(1024) k_flight_persist(FlightArgs<T> a) {
+  extern __shared__ uint32_t sh[];
+  const int ncell = DEV ? a.G.ncell : 1;
+  uint32_t* sh_dep = sh;
+  uint32_t* sh_heat = sh + dep_words(ncell);
+  uint32_t* sh_real = sh_heat + 4 * ncell;
+  uint32_t* sh_misc = sh_real + 32;
+  uint32_t* sh_claim = sh_misc + 8;
+  const int nsh = flight_lds_words(ncell);
+  for (int i = threadIdx.x; i < nsh; i += blockDim.x) sh[i] = 0u;
+  __syncthreads();
+  const int inst = a.wg_inst[blockIdx.x];
+  const InstParams P = a.ip[inst];
+  const T* fac = a.fac + (size_t)inst * ncell * kFRow;
+  const T* field = a.field + (size_t)inst * ncell * 4;
+  const T* gp = a.gamma + inst * 4;
+  const T gam[3] = {gp[0], gp[1], gp[2]};  // workgroup-uniform
+  const uint32_t n_int = a.ctl[CTL_INTERVAL];
+  const int r = (int)blockIdx.x - P.w0, nw = P.w1 - P.w0;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const int cpt = (a.tile + a.chunk - 1) / a.chunk;  // chunks per tile
+  Cnt c = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  bool guard_hit = false, nan_hit = false;
+  bool has = false;
+  // wavefront-uniform: no chunks left, current chunk [cpos, cend) of tile
+  // ctile, free slots met in it so far
+  bool exhausted = false;
+  int cpos = 0, cend = 0, ctile = 0;
+  uint32_t dacc = 0;
+  int ltile = 0;  // tile of the lane's electron
+  LaneE<T> L = {};
+  uint32_t rc[kNM];
+#pragma unroll
+  for (int q = 0; q < kNM; ++q) rc[q] = 0u;
+  for (;;) {
+    bool want = !has && !exhausted;
+    unsigned long long m = __ballot(want);
+    while (m) {
+      if (cpos >= cend) {
+        if (DEV && lane == 0 && dacc) atomicAdd(a.tile_dead + ctile, dacc);
+        dacc = 0;
+        uint32_t i = 0;
+        if (lane == 0) i = atomicAdd(sh_claim, 1u);
+        i = __builtin_amdgcn_readfirstlane(i);
+        const uint32_t k = (uint32_t)r + i * (uint32_t)nw;  // < nchunk + nw: no wrap
+        if (k >= (uint32_t)P.nchunk) { exhausted = true; break; }
+        const int t = (int)(k / (uint32_t)cpt), sub = (int)(k % (uint32_t)cpt);
+        cpos = t * a.tile + sub * a.chunk;
+        cend = min(cpos + a.chunk, min((t + 1) * a.tile, P.cap));
+        ctile = P.t0 + t;
+      }
+      const int n = __popcll(m);
+      const int take = min(n, cend - cpos);
+      const int rank = __popcll(m & lt);
+      bool live = false;
+      if (want && rank < take) {
+        live = take_slot<T, DEV>(a, P.base + cpos + rank, L, c);
+        has = live;
+        ltile = ctile;
+      }
+      if (DEV) dacc += (uint32_t)__popcll(__ballot(want && rank < take && !live));
+      cpos += take;
+      want = !has;
+      m = __ballot(want);
+    }
+    if (!__any(has)) break;
+    if (has) {
+      const int rr = lane_segment<T, DEV>(a, P, fac, field, gam, n_int, ncell, L, c, sh_heat, sh_real, rc, guard_hit);
+      if (rr > -2) {
+        retire<T, DEV>(a, L, rr, c, sh_dep, true, nan_hit);
+        if (DEV && rr >= 0) atomicAdd(a.tile_dead + ltile, 1u);
+        has = false;
+      }
+    }
+  }
+  if (guard_hit) set_flag(a.flags, inst, -4);
+  if (nan_hit) set_flag(a.flags, inst, -6);
+  flush_workgroup<DEV>(c, rc, sh_dep, true, sh_heat, sh_real, sh_misc, ncell,
+                       a.partial + (size_t)blockIdx.x * 5 * ncell, a.counters + (size_t)inst * kNCnt, nullptr);
+}
+
+// Sum the per-tile (or, after the persistent kernel, per-workgroup)
+// histograms of each instance in two passes: groups of them add their partial
+// sums into a u64 accumulator (atomics on 5 x ncell
 // distinct words per instance), then k_merge_final moves the accumulator
 // into the electron count (bins [0, ncell)) and the window heat counts
 // (bins [ncell, 5 ncell)), clears it, and advances the interval counter.
 constexpr int kMergeGroups = 32;
 __global__ void k_merge_partial(const uint32_t* __restrict__ partial, const InstParams* __restrict__ ip, int ncell,
-                                unsigned long long* acc) {
+                                int by_wg, unsigned long long* acc) {
   const int inst = blockIdx.z;
   const int bin = blockIdx.x * blockDim.x + threadIdx.x;
   if (bin >= 5 * ncell) return;
-  const int t0 = ip[inst].t0, t1 = ip[inst].t1;
+  const int t0 = by_wg ? ip[inst].w0 : ip[inst].t0, t1 = by_wg ? ip[inst].w1 : ip[inst].t1;
   const int per = (t1 - t0 + kMergeGroups - 1) / kMergeGroups;
   const int a = t0 + blockIdx.y * per, b = min(t1, a + per);
   unsigned long long s = 0;
@@ -735,17 +889,20 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
 // every free slot its instance-wide rank q, and the slot of rank q < Q is
 // written to position q of the instance's slot list (relative slot index).
 // Tiles whose first rank is already >= Q, or that hold no free slot, exit.
+// Every tile's free count is cleared here once read.
 __global__ void __launch_bounds__(256) k_inject_slots(const TileDesc* __restrict__ tiles,
                                                       const InstParams* __restrict__ ip,
                                                       const Plan* __restrict__ plan,
-                                                      const uint32_t* __restrict__ tile_off,
-                                                      const uint32_t* __restrict__ tile_dead,
+                                                      const uint32_t* __restrict__ tile_off, uint32_t* tile_dead,
                                                       const uint32_t* __restrict__ meta, uint32_t* slot_list) {
   __shared__ uint32_t s_wave[4];
   const TileDesc td = tiles[blockIdx.x];
   const uint32_t Q = plan[td.inst].Q;
   uint32_t run = tile_off[blockIdx.x];
-  if (run >= Q || tile_dead[blockIdx.x] == 0) return;
+  const uint32_t ndead = tile_dead[blockIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0) tile_dead[blockIdx.x] = 0u;  // the persistent kernel adds to it
+  if (run >= Q || ndead == 0) return;
   const long long base = ip[td.inst].base;
   uint32_t* list = slot_list + base;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

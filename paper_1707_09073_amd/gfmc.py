@@ -286,6 +286,9 @@ class Ensemble:
         return w.value, n.value
 
     def mc_set_variant(self, variant: int):
+        """Particle kernel: 0 lane refill per tile, 1 one electron per lane,
+        2 persistent (resident workgroups, each working every nw-th slot chunk
+        of its instance)."""
         self._chk(lib().mc_set_variant(self._ctx, int(variant)), "mc_set_variant")
 
     def mc_use_graph(self, enable: bool):

@@ -90,7 +90,7 @@ def test_initial_state_matches_oracle(G, oracle_mod, mode):
         assert np.abs(F - Fo).max() <= 1e-9 * np.abs(Fo).max()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_bulk_fp64_per_particle_parity(G, oracle_mod, variant):
     """Bulk GaN, 10 kV/cm along c, 1e17 cm^-3, 300 K, 1 fs steps."""
     cfg = W.bulk_config(n_particles=10000, substeps=1)
@@ -129,7 +129,7 @@ def _device_small(n=20000, Vds=5.0, Vgs=0.0, prec="fp64", cells=(100, 3, 6), L=(
     return W.device_config(n_particles=n, precision=prec, Vds=Vds, Vgs=Vgs, n_cells=cells, L_nm=L)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_device_fp64_per_particle_parity(G, oracle_mod, variant):
     """Half-nanowire device, 3x6x100 subcells, Vds = 5 V: particles, deposit,
     heat counts, contacts and the Poisson field after 30 refreshes."""
@@ -154,13 +154,16 @@ def test_device_fp64_per_particle_parity(G, oracle_mod, variant):
     _say("device max rel err k", ek, "r", er)
 
 
-def test_device_fp64_parity_gated_and_ragged(G, oracle_mod):
+@pytest.mark.parametrize("variant", [0, 2])
+def test_device_fp64_parity_gated_and_ragged(G, oracle_mod, variant):
     """Negative gate bias, a grid of 37x2x5 subcells and a capacity that is
-    not a multiple of the tile (ragged last tile)."""
+    not a multiple of the tile (ragged last tile, and for the persistent
+    queue a ragged last chunk)."""
     cfg = _device_small(n=7777, Vds=3.0, Vgs=-1.0, cells=(37, 2, 5), L=(370.0, 40.0, 100.0))
     cfg["capacity"] = 10007
     e = G.Ensemble(cfg)
     e.mc_set_launch(128, 1024)
+    e.mc_set_variant(variant)
     o = oracle_mod.Oracle(cfg)
     e.mc_step(200)
     o.run(20)
@@ -171,10 +174,13 @@ def test_device_fp64_parity_gated_and_ragged(G, oracle_mod):
 def test_launch_shape_and_graph_do_not_change_results(G):
     cfg = _device_small(n=30000, prec="fp32")
     runs = []
-    for block, tile, graph in ((256, 8192, False), (64, 1024, False), (128, 4096, True), (256, 2048, True)):
-        _say("launch shape", block, tile, "graph" if graph else "eager")
+    for block, tile, graph, variant in ((256, 8192, False, 0), (64, 1024, False, 0), (128, 4096, True, 0),
+                                        (256, 2048, True, 0), (64, 1024, False, 2), (320, 4160, False, 2),
+                                        (512, 4096, True, 2), (1024, 4096, False, 2)):
+        _say("launch shape", block, tile, "graph" if graph else "eager", "variant", variant)
         e = G.Ensemble(cfg)
         e.mc_set_launch(block, tile)
+        e.mc_set_variant(variant)
         e.mc_use_graph(graph)
         e.mc_step(200)
         p = e.mc_read_particles()
@@ -189,11 +195,16 @@ def test_launch_shape_and_graph_do_not_change_results(G):
         assert np.array_equal(m["heat4"], m0["heat4"]) and np.array_equal(m["dens_sum"], m0["dens_sum"])
 
 
-def test_batched_instances_equal_separate_runs(G):
+@pytest.mark.parametrize("variant", [0, 2])
+def test_batched_instances_equal_separate_runs(G, variant):
+    """Three bias points in one context equal three separate runs, per
+    particle; with the persistent queue each instance has its own share of
+    the workgroups and its own queue."""
     cfgs = W.bias_sweep(3, n_min=3000, n_max=9000)
     for c in cfgs:
         c["precision"] = "fp32"
     eb = G.Ensemble(cfgs)
+    eb.mc_set_variant(variant)
     eb.mc_step(100)
     for i, c in enumerate(cfgs):
         es = G.Ensemble(c)
@@ -249,18 +260,24 @@ def test_invalid_arguments_are_errors_not_crashes(G):
         e.mc_step(7)                     # not a multiple of the 10 sub-steps
     with pytest.raises(G.MCError):
         e.mc_set_launch(96, 1024)        # workgroup not a multiple of 64
+    e.mc_set_launch(1024, 4096)          # 1024 lanes: the persistent variant only
+    with pytest.raises(G.MCError):
+        e.mc_step(10)
+    e.mc_set_launch(256, 4096)
     with pytest.raises(G.MCError):
         e.mc_set_lattice_temperature(0, -np.ones(1800))
     with pytest.raises(G.MCError):
         e.mc_tally(5)
 
 
-def test_capacity_exhaustion_is_reported(G):
+@pytest.mark.parametrize("variant", [0, 2])
+def test_capacity_exhaustion_is_reported(G, variant):
     """No spare slots: the first refill that needs a slot must flag
     MC_E_CAPACITY instead of writing out of bounds."""
     cfg = _device_small(n=18000, prec="fp32", Vds=8.0)
     cfg["capacity"] = 18000
     e = G.Ensemble(cfg)
+    e.mc_set_variant(variant)
     e.mc_step(500)
     t = e.mc_tally(check=False)
     assert t["status"] in (0, G.MC_E_CAPACITY)
