@@ -197,7 +197,8 @@ int mc_read_fields(mc_ctx *ctx, int instance, double *h_phi, double *h_field, ui
 int mc_read_tables(mc_ctx *ctx, int instance, double *h_shape, double *h_k4, double *h_factors, double *h_gamma);
 
 /* Launch shape of the particle kernel: workgroup size (64..1024, multiple of
- * 64; above 512 only for variant 2, else mc_step returns MC_E_ARG) and tile
+ * 64; above 512 only for FP32 state and variants 0 and 2, else mc_step
+ * returns MC_E_ARG) and tile
  * size (particles per tile, multiple of the workgroup size).
  * Variants 0 and 1 launch one workgroup per tile; variant 2 launches as many
  * workgroups as the GPU holds at once and uses the tiles only for the contact

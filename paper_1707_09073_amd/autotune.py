@@ -24,6 +24,9 @@ DEFAULT_CANDIDATES = [
     (128, 2048, 0), (256, 4096, 1),
     (1024, 4096, 2), (1024, 8192, 2), (512, 4096, 2),
 ]
+# FP32 state only: 1024-lane workgroups (16 wavefronts sharing one refill
+# queue; FP64 state needs more registers than they leave each lane)
+FP32_CANDIDATES = [(1024, 10240, 0), (1024, 13312, 0), (1024, 20480, 0)]
 
 _cache: dict = {}
 
@@ -71,7 +74,12 @@ def autotune(ens, candidates=None, trials: int = 3, cache_file: str | None = Non
         return dict(best, cached=True)
     K = int(ens.cfgs[0]["substeps"])
     if candidates is None:
-        candidates = list(dict.fromkeys(DEFAULT_CANDIDATES + round_candidates(ens)))
+        fp32 = ens.cfgs[0].get("precision", "fp64") == "fp32"
+        blocks = (256, 384, 512, 1024) if fp32 else (256, 384, 512)
+        candidates = DEFAULT_CANDIDATES + (FP32_CANDIDATES if fp32 else [])
+        candidates = list(dict.fromkeys(candidates + round_candidates(ens, blocks=blocks)))
+        if not fp32:
+            candidates = [c for c in candidates if c[0] <= 512]
     blob = ens.mc_checkpoint()
     results = []
     for block, tile, variant in candidates:

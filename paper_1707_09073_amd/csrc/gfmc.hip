@@ -694,8 +694,8 @@ int mc_step(mc_ctx* c, int n_substeps) {
   const int K = c->cfg[0].substeps;
   if (n_substeps < 0 || n_substeps % K) return fail(c, MC_E_ARG, "n_substeps must be a multiple of substeps");
   const int n = n_substeps / K;
-  if (c->block > 512 && c->variant != 2)
-    return fail(c, MC_E_ARG, "workgroups of more than 512 lanes need the persistent variant");
+  if (c->block > 512 && (c->variant == 1 || !c->f32))
+    return fail(c, MC_E_ARG, "workgroups of more than 512 lanes need FP32 state and a lane-refill variant");
   if (n == 0) return MC_OK;
   if (c->use_graph && !c->profile) {
     if (!c->gexec) {

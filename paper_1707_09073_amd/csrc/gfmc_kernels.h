@@ -575,8 +575,13 @@ __device__ __forceinline__ void flush_workgroup(const Cnt& c, const uint32_t* rc
 // its electron reaches the end of the interval, so lanes do not idle while
 // the busiest lane of the wavefront finishes its events.  Per-electron
 // arithmetic and random-number use are the same as in k_flight.
+// Workgroups of up to 1024 lanes for FP32 state; FP64 state needs more than
+// the 128 registers a 1024-lane workgroup leaves each lane, so 512 at most.
+template <typename T>
+__host__ __device__ constexpr int max_flight_block() { return sizeof(T) == 4 ? 1024 : 512; }
+
 template <typename T, bool DEV>
-__global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
+__global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightArgs<T> a) {
   extern __shared__ uint32_t sh[];
   const int ncell = DEV ? a.G.ncell : 1;
   uint32_t* sh_dep = sh;
@@ -653,7 +658,7 @@ __global__ void __launch_bounds__(512) k_flight_refill(FlightArgs<T> a) {
 // refill plan clears the counts after reading them).  Per-electron arithmetic
 // and random-number use are those of k_flight_refill.
 template <typename T, bool DEV>
-__global__ void __launch_bounds__(1024) k_flight_persist(FlightArgs<T> a) {
+__global__ void __launch_bounds__(max_flight_block<T>()) k_flight_persist(FlightArgs<T> a) {
   extern __shared__ uint32_t sh[];
   const int ncell = DEV ? a.G.ncell : 1;
   uint32_t* sh_dep = sh;

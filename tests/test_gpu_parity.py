@@ -176,7 +176,7 @@ def test_launch_shape_and_graph_do_not_change_results(G):
     runs = []
     for block, tile, graph, variant in ((256, 8192, False, 0), (64, 1024, False, 0), (128, 4096, True, 0),
                                         (256, 2048, True, 0), (64, 1024, False, 2), (320, 4160, False, 2),
-                                        (512, 4096, True, 2), (1024, 4096, False, 2)):
+                                        (512, 4096, True, 2), (1024, 4096, False, 2), (1024, 8192, True, 0)):
         _say("launch shape", block, tile, "graph" if graph else "eager", "variant", variant)
         e = G.Ensemble(cfg)
         e.mc_set_launch(block, tile)
@@ -260,9 +260,11 @@ def test_invalid_arguments_are_errors_not_crashes(G):
         e.mc_step(7)                     # not a multiple of the 10 sub-steps
     with pytest.raises(G.MCError):
         e.mc_set_launch(96, 1024)        # workgroup not a multiple of 64
-    e.mc_set_launch(1024, 4096)          # 1024 lanes: the persistent variant only
+    e.mc_set_launch(1024, 4096)          # 1024 lanes: not for the one-electron-per-lane variant
+    e.mc_set_variant(1)
     with pytest.raises(G.MCError):
         e.mc_step(10)
+    e.mc_set_variant(0)
     e.mc_set_launch(256, 4096)
     with pytest.raises(G.MCError):
         e.mc_set_lattice_temperature(0, -np.ones(1800))
