@@ -756,6 +756,7 @@ __global__ void k_merge_partial(const uint32_t* __restrict__ partial, const Inst
   const int per = (t1 - t0 + kMergeGroups - 1) / kMergeGroups;
   const int a = t0 + blockIdx.y * per, b = min(t1, a + per);
   unsigned long long s = 0;
+#pragma unroll 8
   for (int t = a; t < b; ++t) s += partial[(size_t)t * 5 * ncell + bin];
   if (s) atomicAdd(acc + (size_t)inst * 5 * ncell + bin, s);
 }
@@ -1305,6 +1306,9 @@ __global__ void __launch_bounds__(256) k_poisson_gemv(const double* __restrict__
   const double* a = Ainv + (size_t)row * ncell;
   const double* b = rhs + (size_t)inst * ncell;
   double s = 0.0;
+  // unrolled so the loads of several columns are in flight at once; the
+  // sums stay in column order
+#pragma unroll 8
   for (int j = lane; j < ncell; j += 64) s = fma(a[j], b[j], s);
   s = lane_butterfly(s);
   if (lane == 0) phi[(size_t)inst * ncell + row] = s;
