@@ -62,7 +62,7 @@ def test_round_candidates_fill_whole_rounds():
         n_tiles = -(-13_000_000 // tile)
         r = -(-n_tiles // resident)          # rounds of resident workgroups
         # the last round is full up to the rounding of the tile to the block
-        assert r <= 8 and n_tiles >= r * resident * tile / (tile + block) - 1
+        assert r <= 8 and n_tiles >= r * resident * (tile - block - 1) / tile
 
 
 def test_fp64_contexts_never_try_1024_lane_workgroups():
