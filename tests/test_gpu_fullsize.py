@@ -1,5 +1,7 @@
 """Parity at the headline size: the 10-million-electron half-nanowire device
-with the drain-end hot spot, at a launch shape of the benchmark's tuner.
+with the drain-end hot spot, at launch shapes of the benchmark's tuner (FP64
+state: 256-lane workgroups; FP32 state: the benchmark's 1024-lane lane-refill
+shape and the persistent variant).
 
 FP64: after a few intervals on the GPU, the oracle takes the GPU's state
 (particles, the deposit from which it solves its own Poisson field, the
@@ -24,7 +26,8 @@ pytestmark = pytest.mark.gpu
 REL = 1e-10
 K_FLOOR = 0.1  # 1/nm, as in the smaller parity tests
 QE = 1.602176634e-19
-BLOCK, TILE = 256, 4096
+BLOCK, TILE = 256, 4096                   # FP64 state
+FP32_SHAPES = [(1024, 20480, 0), (1024, 8192, 2)]
 
 
 def _say(*a):
@@ -89,12 +92,14 @@ def test_full_size_fp64_interval_matches_oracle(G, oracle_mod):
     assert np.array_equal(cnt1, o.fields()[2])
 
 
-def test_full_size_fp32_invariants(G):
+@pytest.mark.parametrize("block,tile,variant", FP32_SHAPES)
+def test_full_size_fp32_invariants(G, block, tile, variant):
     cfg = W.large_device_config()
     K = cfg["substeps"]
-    _say(f"full size fp32 invariants: {cfg['n_particles']} electrons, launch {BLOCK}/{TILE}")
+    _say(f"full size fp32 invariants: {cfg['n_particles']} electrons, launch {block}/{tile}, variant {variant}")
     e = G.Ensemble(cfg)
-    e.mc_set_launch(BLOCK, TILE)
+    e.mc_set_launch(block, tile)
+    e.mc_set_variant(variant)
     e.mc_step(20 * K)
     t = e.mc_tally()
     assert t["flags"] == 0
