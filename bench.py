@@ -37,7 +37,7 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # 2.000 + WRITE_SIZE x 1.000, scales from a 1 GiB device copy).
 KERNELS = {0: "k_flight_refill<float,true>", 1: "k_flight<float,true>", 2: "k_flight_persist<float,true>"}
 KERNEL_COUNTERS = {
-    0: {"sources_digest": "47088e44e1cb7075", "valu_lane_ops_per_segment": 153.2, "hbm_bytes_per_segment": 9.63,
+    0: {"sources_digest": "d97c2dabc3f82965", "valu_lane_ops_per_segment": 153.2, "hbm_bytes_per_segment": 9.63,
         "profile": "profiles/k_flight_refill_device1e7_counters.md"},
 }
 
@@ -59,9 +59,10 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_intervals: int = 3) -> dict:
+def cpu_baseline(n_intervals: int = 40) -> dict:
     """The FP64 CPU reference on the same workload, timed on the host cores
-    for its first few flight intervals after initialisation."""
+    for its first flight intervals after initialisation (about 10 s of work
+    on 16 cores)."""
     from oracle import emc_oracle
     from paper_1707_09073_amd import workloads as W
     emc_oracle.build()
@@ -72,19 +73,21 @@ def cpu_baseline(n_intervals: int = 3) -> dict:
     o = emc_oracle.Oracle(cfg)
     t_init = time.perf_counter() - t0
     o.reset_window()
+    import numpy as np
+    alive0 = int(np.count_nonzero(o.particles()["alive"]))
     t0 = time.perf_counter()
     o.run(n_intervals, threads)
     dt = time.perf_counter() - t0
     c = o.counts()
-    # alive electrons x sub-steps + selections, as for the GPU
-    import numpy as np
-    alive = int(np.count_nonzero(o.particles()["alive"]))
-    segs = alive * cfg["substeps"] * n_intervals + c["selections"]
+    # alive electrons x sub-steps + selections, as for the GPU (the live count
+    # taken as the mean of its values before and after the sample)
+    alive1 = int(np.count_nonzero(o.particles()["alive"]))
+    segs = 0.5 * (alive0 + alive1) * cfg["substeps"] * n_intervals + c["selections"]
     return dict(value=segs / dt, unit="events/s", cores=threads, kind="oracle",
                 sample=(f"same 1e7-superparticle device workload in FP64, first {n_intervals} flight intervals "
                         f"({n_intervals * cfg['substeps']} fs) after initialisation; {dt:.1f} s timed, "
                         f"init {t_init:.1f} s untimed; segments counted as on the GPU (alive x sub-steps "
-                        f"approximated by the final alive count)"))
+                        f"with the live count averaged over the sample)"))
 
 
 def sweep64(args) -> dict:
