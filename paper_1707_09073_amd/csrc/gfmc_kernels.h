@@ -1337,6 +1337,8 @@ __global__ void __launch_bounds__(256) k_poisson_gemm(const double* __restrict__
   for (int r = 0; r < kPgR; ++r) arow[r] = Ainv + (size_t)min(row0 + r, ncell - 1) * ncell;
 #pragma unroll
   for (int g = 0; g < kPgG; ++g) bcol[g] = rhs + (size_t)min(i0 + g, n_inst - 1) * ncell;
+  // unrolled so several columns' loads are in flight; each sum stays in column order
+#pragma unroll 4
   for (int j = lane; j < ncell; j += 64) {
     double av[kPgR], bv[kPgG];
 #pragma unroll

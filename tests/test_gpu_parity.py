@@ -171,6 +171,39 @@ def test_device_fp64_parity_gated_and_ragged(G, oracle_mod, variant):
     _compare_counts(e.mc_tally(), o.counts())
 
 
+@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("n,field", [(1, 5e-3), (63, 5e-3), (65, 5e-3), (65, 0.0)])
+def test_tiny_bulk_ensembles_match_oracle(G, oracle_mod, n, field, variant):
+    """Degenerate sizes: one electron, one electron fewer or more than a
+    wavefront (ragged refill rounds and chunks), and zero field."""
+    cfg = W.bulk_config(n_particles=n, substeps=10, field_V_per_nm=field)
+    _say("tiny bulk", n, "electrons, field", field, "variant", variant)
+    e = G.Ensemble(cfg)
+    e.mc_set_variant(variant)
+    o = oracle_mod.Oracle(cfg)
+    e.mc_step(200)
+    o.run(20)
+    _compare_particles(e.mc_read_particles(), o.particles(), what=f"bulk n={n}")
+    _compare_counts(e.mc_tally(), o.counts())
+
+
+@pytest.mark.parametrize("variant", [0, 2])
+def test_sparse_device_matches_oracle(G, oracle_mod, variant):
+    """One superparticle per subcell on average (the contact refill then tops
+    each contact subcell up to about one electron)."""
+    cfg = _device_small(n=1800, Vds=2.0)
+    e = G.Ensemble(cfg)
+    e.mc_set_variant(variant)
+    o = oracle_mod.Oracle(cfg)
+    e.mc_step(200)
+    o.run(20)
+    _compare_particles(e.mc_read_particles(), o.particles(), what="sparse device")
+    _compare_counts(e.mc_tally(), o.counts())
+    m = e.mc_maps()
+    heat_o, dens_o = o.maps()
+    assert np.array_equal(m["heat4"], heat_o) and np.array_equal(m["dens_sum"], dens_o)
+
+
 def test_launch_shape_and_graph_do_not_change_results(G):
     cfg = _device_small(n=30000, prec="fp32")
     runs = []
