@@ -43,8 +43,10 @@ KERNEL_COUNTERS = {
 
 
 def _kernel_digest() -> str:
-    """Digest of the particle-kernel sources with comments and blank lines
-    removed (a comment edit does not invalidate the counters)."""
+    """Digest of the particle-kernel sources (the kernels and the device
+    arithmetic they use; the refresh kernels live in a header of their own)
+    with comments and blank lines removed, so that a comment edit does not
+    invalidate the counters."""
     import hashlib
     import re
     h = []

@@ -13,6 +13,7 @@
 
 #include "../../include/gfmc.h"
 #include "gfmc_kernels.h"
+#include "gfmc_refresh.h"
 
 using namespace gfmc;
 
