@@ -1,7 +1,7 @@
 """Surrogate experiment: train the MLP on Monte Carlo runs of the device and
 measure its heat-map error and time per bias point against the plain MC.
 
-    python -m paper_1707_09073_amd.surrogate_experiment --train 9000 --val 200 --out result.json
+    python -m paper_1707_09073_amd.surrogate_experiment --train 12000 --val 200 --out result.json
 
 Training inputs are seeded bias points (Vgs ~ U[-3,0] V, Vds ~ U[1,10] V,
 doping log-uniform in [1e17, 1e19] cm^-3) with random drain-side hot spots;
@@ -21,13 +21,13 @@ import numpy as np
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=9000)
+    ap.add_argument("--train", type=int, default=12000)
     ap.add_argument("--val", type=int, default=200)
     ap.add_argument("--particles", type=int, default=200_000)
     ap.add_argument("--warm", type=int, default=1000, help="intervals (10 fs) before the window")
     ap.add_argument("--window", type=int, default=1000, help="intervals (10 fs) averaged")
     ap.add_argument("--ref-seeds", type=int, default=4)
-    ap.add_argument("--epochs", type=int, default=1000)
+    ap.add_argument("--epochs", type=int, default=800)
     ap.add_argument("--width", type=int, default=1024)
     ap.add_argument("--depth", type=int, default=4)
     ap.add_argument("--ensemble", type=int, default=4)
