@@ -92,6 +92,50 @@ def cpu_baseline(n_intervals: int = 40) -> dict:
                         f"with the live count averaged over the sample)"))
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense BF16 MFMA, MI355X
+
+
+def surrogate_mlp(args) -> dict:
+    """The surrogate's dense layers at a large batch: one member of the
+    1803 -> 1024 x 4 -> 3600 MLP (BF16 MFMA, FP32 accumulation), the forward
+    pass and the training step (forward, backward, Adam) timed with HIP events
+    on the surrogate's stream."""
+    import numpy as np
+    import torch
+    from paper_1707_09073_amd import gfmc
+    from paper_1707_09073_amd.surrogate import N_CELL, N_ENC
+    N_IN = 3 + N_CELL
+    B = args.sg_batch
+    net = gfmc.SurrogateNet(N_IN, N_ENC, width=1024, depth=4, ensemble=1, max_batch=B)
+    g = torch.Generator(device="cuda:0").manual_seed(7)
+    x = torch.randn(B, N_IN, device="cuda:0", generator=g)
+    y = torch.randn(B, N_ENC, device="cuda:0", generator=g)
+    net.sg_set_normalization(np.zeros(N_IN), np.ones(N_IN), np.zeros(N_ENC), np.ones(N_ENC))
+    out = torch.empty(B, N_ENC, device="cuda:0")
+    dims = [net.sg_layer_dims(l) for l in range(5)]
+    dims[0] = (N_IN, dims[0][1])  # algorithmic flops: the unpadded input width
+    flops_fwd = 2.0 * B * sum(k * n for k, n in dims)
+    # backward: dX and dW per layer (dX skipped for the first layer)
+    flops_bwd = 2.0 * B * (2 * sum(k * n for k, n in dims) - dims[0][0] * dims[0][1])
+    res = {}
+    for name, fn, flops in (("forward", lambda: net.sg_forward(0, x, out), flops_fwd),
+                            ("train_step", lambda: net.sg_train_step(0, x, y, 1e-4, want_loss=False),
+                             flops_fwd + flops_bwd)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(net.stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(net.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        res[name] = dict(ms=ms, tflops=flops / (ms * 1e-3) / 1e12)
+    net.close()
+    return dict(batch=B, dims=dims, flops_forward=flops_fwd, flops_backward=flops_bwd, **res)
+
+
 def sweep64(args) -> dict:
     """Batched bias sweep: 64 device instances (uneven ensembles of 20k-500k
     electrons, FP32 state) in one context, one launch per kernel per interval
@@ -165,7 +209,8 @@ def main() -> int:
                     help="particle kernel: 0 lane refill per tile, 1 one electron per lane, 2 persistent")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default (or given) launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["device1e7", "sweep64"], default="device1e7",
+    ap.add_argument("--sg-batch", type=int, default=4096, help="batch of the surrogate workload")
+    ap.add_argument("--workload", choices=["device1e7", "sweep64", "surrogate"], default="device1e7",
                     help="device1e7: one 10M-electron device (the headline); sweep64: 64-instance batched sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration) and exit")
@@ -190,6 +235,20 @@ def main() -> int:
         from paper_1707_09073_amd import build as B
         B.build(force=True)
     torch.cuda.set_device(0)
+    if args.workload == "surrogate":
+        r = surrogate_mlp(args)
+        fw = r["forward"]
+        print(json.dumps({
+            "metric": "surrogate MLP throughput (BF16 MFMA, FP32 accumulation)", "value": fw["tflops"],
+            "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": fw["ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "surrogate MLP 1803 -> 1024 x 4 -> 3600, one member, forward at batch "
+                                   f"{r['batch']}", "batch": r["batch"]},
+            "train_step": r["train_step"],
+            "roofline": {"bound": "mfma", "achieved": fw["tflops"], "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": fw["tflops"] / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                         "flops_per_forward": r["flops_forward"]}}), flush=True)
+        return 0
     if args.workload == "sweep64":
         r = sweep64(args)
         print(json.dumps({

@@ -13,7 +13,13 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 128, BN = 128, BK = 32, KP = BK + 8;  // LDS pitch 40 bf16 (80 B, 16-B aligned rows)
+constexpr int BM = 128, BN = 128, BK = 64, KP = BK + 8;  // LDS pitch 72 bf16 (144 B, 16-B aligned rows)
+
+// LDS position of the 8-element k-chunk c (0..7) of tile row r: chunks are
+// permuted within the row by r / 8, so that the 2-byte stores of a transposed
+// operand (lanes 8 rows apart) fall into different banks; a chunk stays
+// contiguous for the 16-byte fragment reads.
+__device__ __forceinline__ int lds_at(int r, int c) { return r * KP + ((c ^ ((r >> 3) & 7)) << 3); }
 
 enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
 
@@ -39,10 +45,24 @@ __device__ __forceinline__ float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
 
+// Eight consecutive BF16 of row r, columns c .. c+7, of a [R x C] matrix with
+// leading dimension ld (a multiple of 8): one 16-byte load when the chunk is
+// inside, element loads with zero fill at ragged edges.
+__device__ __forceinline__ uint4 load_chunk(const bf16* p, long ld, int r, int c, int R, int C) {
+  if (r < R && c + 8 <= C) return *reinterpret_cast<const uint4*>(p + (long)r * ld + c);
+  uint4 v;
+  bf16* e = reinterpret_cast<bf16*>(&v);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) e[q] = (r < R && c + q < C) ? p[(long)r * ld + c + q] : (bf16)0.0f;
+  return v;
+}
+
 // C[M x N] = opA(A)[M x K] opB(B)[K x N], BF16 in, FP32 accumulate, with an
 // epilogue.  opA(i,k) = A[i*lda + k] (TA false) or A[k*lda + i] (TA true);
 // opB(k,j) = B[k*ldb + j] (TB false) or B[j*ldb + k] (TB true).
-// Workgroup tile 128 x 128 x 32, four waves of 64 x 64 (2 x 2 MFMA blocks).
+// Workgroup tile 128 x 128 x 64, four waves of 64 x 64 (2 x 2 MFMA blocks).
+// The next K slab is loaded into registers while the matrix cores work on
+// the current one from LDS (LDS holds A as [i][k] and B as [j][k]).
 template <bool TA, bool TB, int EPI>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) bf16 As[BM * KP];
@@ -57,75 +77,88 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
-  const bf16 zero = (bf16)0.0f;
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-    // 512 chunks of 8 consecutive elements along each operand's contiguous
-    // dimension: 16-byte loads where the chunk is in range (leading
-    // dimensions are multiples of 8), element loads at ragged edges
+  // 1024 chunks of 8 elements per operand and slab, four per thread, along
+  // each operand's contiguous dimension
+  uint4 ra[4], rb[4];
+  auto fetch_fast = [&](int k0) {  // every chunk of the slab in range
 #pragma unroll
-    for (int rep = 0; rep < 2; ++rep) {
+    for (int rep = 0; rep < 4; ++rep) {
       const int ch = tid + 256 * rep;
-      if (!TA) {  // A[i][k]: contiguous in k
-        const int i = ch >> 2, kc = (ch & 3) * 8, gi = m0 + i, gk = k0 + kc;
-        bf16* dst = As + i * KP + kc;
-        if (gi < g.M && gk + 8 <= g.K) {
-          *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(g.A + (long)gi * g.lda + gk);
-        } else {
+      ra[rep] = !TA ? *reinterpret_cast<const uint4*>(g.A + (long)(m0 + (ch >> 3)) * g.lda + k0 + (ch & 7) * 8)
+                    : *reinterpret_cast<const uint4*>(g.A + (long)(k0 + (ch >> 4)) * g.lda + m0 + (ch & 15) * 8);
+      rb[rep] = TB ? *reinterpret_cast<const uint4*>(g.B + (long)(n0 + (ch >> 3)) * g.ldb + k0 + (ch & 7) * 8)
+                   : *reinterpret_cast<const uint4*>(g.B + (long)(k0 + (ch >> 4)) * g.ldb + n0 + (ch & 15) * 8);
+    }
+  };
+  auto fetch_checked = [&](int k0) {  // ragged edges: zero fill
 #pragma unroll
-          for (int e = 0; e < 8; ++e) dst[e] = (gi < g.M && gk + e < g.K) ? g.A[(long)gi * g.lda + gk + e] : zero;
-        }
-      } else {    // A stored [k][i]: contiguous in i
-        const int kk = ch >> 4, ic = (ch & 15) * 8, gk = k0 + kk, gi = m0 + ic;
-        if (gk < g.K && gi + 8 <= g.M) {
-          const uint4 v = *reinterpret_cast<const uint4*>(g.A + (long)gk * g.lda + gi);
-          const bf16* pv = reinterpret_cast<const bf16*>(&v);
+    for (int rep = 0; rep < 4; ++rep) {
+      const int ch = tid + 256 * rep;
+      ra[rep] = !TA ? load_chunk(g.A, g.lda, m0 + (ch >> 3), k0 + (ch & 7) * 8, g.M, g.K)
+                    : load_chunk(g.A, g.lda, k0 + (ch >> 4), m0 + (ch & 15) * 8, g.K, g.M);
+      rb[rep] = TB ? load_chunk(g.B, g.ldb, n0 + (ch >> 3), k0 + (ch & 7) * 8, g.N, g.K)
+                   : load_chunk(g.B, g.ldb, k0 + (ch >> 4), n0 + (ch & 15) * 8, g.K, g.N);
+    }
+  };
+  auto stash = [&]() {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) As[(ic + e) * KP + kk] = pv[e];
-        } else {
+    for (int rep = 0; rep < 4; ++rep) {
+      const int ch = tid + 256 * rep;
+      if (!TA) {
+        *reinterpret_cast<uint4*>(As + lds_at(ch >> 3, ch & 7)) = ra[rep];
+      } else {
+        const bf16* pv = reinterpret_cast<const bf16*>(&ra[rep]);
+        const int kk = ch >> 4, ic = (ch & 15) * 8;
 #pragma unroll
-          for (int e = 0; e < 8; ++e)
-            As[(ic + e) * KP + kk] = (gk < g.K && gi + e < g.M) ? g.A[(long)gk * g.lda + gi + e] : zero;
-        }
+        for (int e = 0; e < 8; ++e) As[lds_at(ic + e, kk >> 3) + (kk & 7)] = pv[e];
       }
-      if (!TB) {  // B[k][j]: contiguous in j
-        const int kk = ch >> 4, jc = (ch & 15) * 8, gk = k0 + kk, gj = n0 + jc;
-        if (gk < g.K && gj + 8 <= g.N) {
-          const uint4 v = *reinterpret_cast<const uint4*>(g.B + (long)gk * g.ldb + gj);
-          const bf16* pv = reinterpret_cast<const bf16*>(&v);
+      if (TB) {
+        *reinterpret_cast<uint4*>(Bs + lds_at(ch >> 3, ch & 7)) = rb[rep];
+      } else {
+        const bf16* pv = reinterpret_cast<const bf16*>(&rb[rep]);
+        const int kk = ch >> 4, jc = (ch & 15) * 8;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) Bs[(jc + e) * KP + kk] = pv[e];
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            Bs[(jc + e) * KP + kk] = (gk < g.K && gj + e < g.N) ? g.B[(long)gk * g.ldb + gj + e] : zero;
-        }
-      } else {    // B stored [j][k]: contiguous in k
-        const int j = ch >> 2, kc = (ch & 3) * 8, gj = n0 + j, gk = k0 + kc;
-        bf16* dst = Bs + j * KP + kc;
-        if (gj < g.N && gk + 8 <= g.K) {
-          *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(g.B + (long)gj * g.ldb + gk);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) dst[e] = (gj < g.N && gk + e < g.K) ? g.B[(long)gj * g.ldb + gk + e] : zero;
-        }
+        for (int e = 0; e < 8; ++e) Bs[lds_at(jc + e, kk >> 3) + (kk & 7)] = pv[e];
       }
     }
-    __syncthreads();
+  };
+  auto mma = [&]() {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
       bf16x8 a[2], b[2];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
-        a[mi] = *reinterpret_cast<const bf16x8*>(As + (wm + mi * 32 + (lane & 31)) * KP + ks + 8 * (lane >> 5));
+        a[mi] = *reinterpret_cast<const bf16x8*>(As + lds_at(wm + mi * 32 + (lane & 31), (ks >> 3) + (lane >> 5)));
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni)
-        b[ni] = *reinterpret_cast<const bf16x8*>(Bs + (wn + ni * 32 + (lane & 31)) * KP + ks + 8 * (lane >> 5));
+        b[ni] = *reinterpret_cast<const bf16x8*>(Bs + lds_at(wn + ni * 32 + (lane & 31), (ks >> 3) + (lane >> 5)));
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
+  };
+  // Interior workgroups (rows and columns in range) run the whole slabs with
+  // plain 16-byte loads, the next slab's loads in flight during the current
+  // slab's matrix-core work; the ragged last slab, and every slab of an edge
+  // workgroup, take the checked loads.
+  const int kfull = (m0 + BM <= g.M && n0 + BN <= g.N) ? (g.K / BK) * BK : 0;
+  if (kfull > 0) {
+    fetch_fast(0);
+    for (int k0 = 0; k0 < kfull; k0 += BK) {
+      stash();
+      __syncthreads();
+      if (k0 + BK < kfull) fetch_fast(k0 + BK);
+      mma();
+      __syncthreads();
+    }
+  }
+  for (int k0 = kfull; k0 < g.K; k0 += BK) {
+    fetch_checked(k0);
+    stash();
+    __syncthreads();
+    mma();
     __syncthreads();
   }
 #pragma unroll
@@ -190,13 +223,29 @@ __global__ void k_loss(const float* __restrict__ pred, const float* __restrict__
   if (threadIdx.x == 0) loss_part[blockIdx.x] = s[0];
 }
 
-// column sums of a BF16 [M x N] gradient (bias gradient)
-__global__ void k_colsum(const bf16* __restrict__ d, int M, int N, long ld, float* out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
+// Column sums of a BF16 [M x N] gradient (bias gradient): one workgroup of
+// kCsRows x 64 lanes per 64 columns; lane group r sums rows r, r + kCsRows,
+// ... (independent loads, unrolled), and the groups' sums are added in group
+// order, so the result does not depend on timing.
+constexpr int kCsRows = 16;
+__global__ void __launch_bounds__(64 * kCsRows) k_colsum(const bf16* __restrict__ d, int M, int N, long ld,
+                                                          float* out) {
+  __shared__ float part[kCsRows][64];
+  const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
   float s = 0.0f;
-  for (int i = 0; i < M; ++i) s += (float)d[(long)i * ld + j];
-  out[j] = s;
+  if (j < N) {
+#pragma unroll 8
+    for (int i = r; i < M; i += kCsRows) s += (float)d[(long)i * ld + j];
+  }
+  part[r][c] = s;
+  __syncthreads();
+  if (r == 0 && j < N) {
+    float t = 0.0f;
+#pragma unroll
+    for (int g = 0; g < kCsRows; ++g) t += part[g][c];
+    out[j] = t;
+  }
 }
 
 // Adam (bias-corrected) on FP32 master weights with decoupled weight decay

@@ -361,7 +361,7 @@ int sg_backward(sg_ctx* c, int member, const float* d_x, const float* d_y, int b
     GemmArgs gw = ga(Xin, ldx, dcur, s.N[l], s.K[l], s.N[l], batch);
     gw.Cf = c->p<float>(o.dW); gw.ldcf = s.N[l];
     gemm<true, false, EPI_STORE>(c, gw);
-    k_colsum<<<blocks(s.N[l]), 256, 0, c->st>>>(dcur, batch, s.N[l], s.N[l], c->p<float>(o.db));
+    k_colsum<<<blocks(s.N[l], 64), 64 * kCsRows, 0, c->st>>>(dcur, batch, s.N[l], s.N[l], c->p<float>(o.db));
     if (l > 0) {
       // dZ_{l-1} = (dZ_l W^T) * gelu'(Z_{l-1})
       GemmArgs gx = ga(dcur, s.N[l], c->p<bf16>(o.Wb), s.N[l], batch, s.K[l], s.N[l]);
