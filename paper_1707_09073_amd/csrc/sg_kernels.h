@@ -13,7 +13,7 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 128, BN = 128, BK = 64, KP = BK + 8;  // LDS pitch 72 bf16 (144 B, 16-B aligned rows)
+constexpr int BK = 64, KP = BK + 8;  // LDS pitch 72 bf16 (144 B, 16-B aligned rows)
 
 // LDS position of the 8-element k-chunk c (0..7) of tile row r: chunks are
 // permuted within the row by r / 8, so that the 2-byte stores of a transposed
@@ -60,55 +60,60 @@ __device__ __forceinline__ uint4 load_chunk(const bf16* p, long ld, int r, int c
 // C[M x N] = opA(A)[M x K] opB(B)[K x N], BF16 in, FP32 accumulate, with an
 // epilogue.  opA(i,k) = A[i*lda + k] (TA false) or A[k*lda + i] (TA true);
 // opB(k,j) = B[k*ldb + j] (TB false) or B[j*ldb + k] (TB true).
-// Workgroup tile 128 x 128 x 64, four waves of 64 x 64 (2 x 2 MFMA blocks).
-// The next K slab is loaded into registers while the matrix cores work on
-// the current one from LDS (LDS holds A as [i][k] and B as [j][k]).
-template <bool TA, bool TB, int EPI>
+// Workgroup tile 2 TM x 2 TM x 64, four waves of TM x TM (TM = 64: 2 x 2
+// MFMA blocks each; TM = 32: one), TM = 32 for products whose 128 x 128
+// tiles would leave compute units idle.  The next K slab is loaded into
+// registers while the matrix cores work on the current one from LDS (LDS
+// holds A as [i][k] and B as [j][k]).
+template <bool TA, bool TB, int EPI, int TM>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  constexpr int BM = 2 * TM, BN = 2 * TM, MB = TM / 32, NCH = BM * 8 / 256;
   __shared__ __attribute__((aligned(16))) bf16 As[BM * KP];
   __shared__ __attribute__((aligned(16))) bf16 Bs[BN * KP];  // n-major: Bs[n][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  f32x16 acc[2][2];
+  const int wm = (wave >> 1) * TM, wn = (wave & 1) * TM;
+  f32x16 acc[MB][MB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < MB; ++b)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
-  // 1024 chunks of 8 elements per operand and slab, four per thread, along
-  // each operand's contiguous dimension
-  uint4 ra[4], rb[4];
+  // BM x 8 chunks of 8 elements per operand and slab, NCH per thread, along
+  // each operand's contiguous dimension (a row of 64 k is 8 chunks; a row of
+  // BM elements is BM / 8)
+  constexpr int RS = BM / 8;  // chunks per row of the transposed operands
+  uint4 ra[NCH], rb[NCH];
   auto fetch_fast = [&](int k0) {  // every chunk of the slab in range
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
+    for (int rep = 0; rep < NCH; ++rep) {
       const int ch = tid + 256 * rep;
       ra[rep] = !TA ? *reinterpret_cast<const uint4*>(g.A + (long)(m0 + (ch >> 3)) * g.lda + k0 + (ch & 7) * 8)
-                    : *reinterpret_cast<const uint4*>(g.A + (long)(k0 + (ch >> 4)) * g.lda + m0 + (ch & 15) * 8);
+                    : *reinterpret_cast<const uint4*>(g.A + (long)(k0 + ch / RS) * g.lda + m0 + (ch % RS) * 8);
       rb[rep] = TB ? *reinterpret_cast<const uint4*>(g.B + (long)(n0 + (ch >> 3)) * g.ldb + k0 + (ch & 7) * 8)
-                   : *reinterpret_cast<const uint4*>(g.B + (long)(k0 + (ch >> 4)) * g.ldb + n0 + (ch & 15) * 8);
+                   : *reinterpret_cast<const uint4*>(g.B + (long)(k0 + ch / RS) * g.ldb + n0 + (ch % RS) * 8);
     }
   };
   auto fetch_checked = [&](int k0) {  // ragged edges: zero fill
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
+    for (int rep = 0; rep < NCH; ++rep) {
       const int ch = tid + 256 * rep;
       ra[rep] = !TA ? load_chunk(g.A, g.lda, m0 + (ch >> 3), k0 + (ch & 7) * 8, g.M, g.K)
-                    : load_chunk(g.A, g.lda, k0 + (ch >> 4), m0 + (ch & 15) * 8, g.K, g.M);
+                    : load_chunk(g.A, g.lda, k0 + ch / RS, m0 + (ch % RS) * 8, g.K, g.M);
       rb[rep] = TB ? load_chunk(g.B, g.ldb, n0 + (ch >> 3), k0 + (ch & 7) * 8, g.N, g.K)
-                   : load_chunk(g.B, g.ldb, k0 + (ch >> 4), n0 + (ch & 15) * 8, g.K, g.N);
+                   : load_chunk(g.B, g.ldb, k0 + ch / RS, n0 + (ch % RS) * 8, g.K, g.N);
     }
   };
   auto stash = [&]() {
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
+    for (int rep = 0; rep < NCH; ++rep) {
       const int ch = tid + 256 * rep;
       if (!TA) {
         *reinterpret_cast<uint4*>(As + lds_at(ch >> 3, ch & 7)) = ra[rep];
       } else {
         const bf16* pv = reinterpret_cast<const bf16*>(&ra[rep]);
-        const int kk = ch >> 4, ic = (ch & 15) * 8;
+        const int kk = ch / RS, ic = (ch % RS) * 8;
 #pragma unroll
         for (int e = 0; e < 8; ++e) As[lds_at(ic + e, kk >> 3) + (kk & 7)] = pv[e];
       }
@@ -116,7 +121,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         *reinterpret_cast<uint4*>(Bs + lds_at(ch >> 3, ch & 7)) = rb[rep];
       } else {
         const bf16* pv = reinterpret_cast<const bf16*>(&rb[rep]);
-        const int kk = ch >> 4, jc = (ch & 15) * 8;
+        const int kk = ch / RS, jc = (ch % RS) * 8;
 #pragma unroll
         for (int e = 0; e < 8; ++e) Bs[lds_at(jc + e, kk >> 3) + (kk & 7)] = pv[e];
       }
@@ -125,17 +130,17 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   auto mma = [&]() {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
-      bf16x8 a[2], b[2];
+      bf16x8 a[MB], b[MB];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < MB; ++mi)
         a[mi] = *reinterpret_cast<const bf16x8*>(As + lds_at(wm + mi * 32 + (lane & 31), (ks >> 3) + (lane >> 5)));
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
+      for (int ni = 0; ni < MB; ++ni)
         b[ni] = *reinterpret_cast<const bf16x8*>(Bs + lds_at(wn + ni * 32 + (lane & 31), (ks >> 3) + (lane >> 5)));
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
+        for (int ni = 0; ni < MB; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
   };
@@ -162,9 +167,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     __syncthreads();
   }
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+    for (int ni = 0; ni < MB; ++ni)
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int row = m0 + wm + mi * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);

@@ -135,8 +135,16 @@ void gemm(sg_ctx* c, const GemmArgs& g) {
     c->bad_gemm = true;
     return;
   }
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM);
-  k_gemm<TA, TB, EPI><<<grid, 256, 0, c->st>>>(g);
+  // 128 x 128 tiles unless they would give fewer than two workgroups per
+  // compute unit (256 on the MI355X); 64 x 64 tiles then
+  const long big = (long)((g.N + 127) / 128) * ((g.M + 127) / 128);
+  if (big >= 512) {
+    dim3 grid((g.N + 127) / 128, (g.M + 127) / 128);
+    k_gemm<TA, TB, EPI, 64><<<grid, 256, 0, c->st>>>(g);
+  } else {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    k_gemm<TA, TB, EPI, 32><<<grid, 256, 0, c->st>>>(g);
+  }
 }
 
 GemmArgs ga(const bf16* A, long lda, const bf16* B, long ldb, int M, int N, int K) {
