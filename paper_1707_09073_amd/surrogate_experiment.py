@@ -27,7 +27,7 @@ def main(argv=None) -> int:
     ap.add_argument("--warm", type=int, default=1000, help="intervals (10 fs) before the window")
     ap.add_argument("--window", type=int, default=1000, help="intervals (10 fs) averaged")
     ap.add_argument("--ref-seeds", type=int, default=4)
-    ap.add_argument("--epochs", type=int, default=800)
+    ap.add_argument("--epochs", type=int, default=1400)
     ap.add_argument("--width", type=int, default=1024)
     ap.add_argument("--depth", type=int, default=4)
     ap.add_argument("--ensemble", type=int, default=4)
