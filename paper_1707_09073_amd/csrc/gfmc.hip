@@ -35,6 +35,7 @@ struct Offsets {
       counters, flags, ctl, next_id, ip, tiles, partial, acc, tile_dead, tile_off, plan, slots, minv, ainv, rhs, hist, reps,
       nrep, bpart, wg_inst;
   size_t kx, ky, kz, x, y, z, meta;
+  size_t skx, sky, skz, sx, sy, sz, smeta;  // compaction scratch (device mode)
 };
 
 bool same_shared(const mc_config& a, const mc_config& b) {
@@ -156,6 +157,13 @@ Offsets layout(const mc_config* c, int n, size_t* total) {
   o.y = L.take(dev ? es * cap : 0);
   o.z = L.take(dev ? es * cap : 0);
   o.meta = L.take(sizeof(uint32_t) * cap);
+  o.skx = L.take(dev ? es * cap : 0);
+  o.sky = L.take(dev ? es * cap : 0);
+  o.skz = L.take(dev ? es * cap : 0);
+  o.sx = L.take(dev ? es * cap : 0);
+  o.sy = L.take(dev ? es * cap : 0);
+  o.sz = L.take(dev ? es * cap : 0);
+  o.smeta = L.take(dev ? sizeof(uint32_t) * cap : 0);
   *total = L.total;
   return o;
 }
@@ -173,6 +181,7 @@ struct mc_ctx {
   int nb = 0, ncell = 1, nx = 1, ny = 1, nz = 1, P = 1;
   int block = 256, tile = 0, n_tiles = 0;
   int max_tiles = 0;        // tiles at the smallest tile size: partial histograms the workspace holds
+  long long max_cap = 0;    // largest instance capacity
   int n_wg = 0, chunk = 256;  // persistent kernel: workgroups, slots per chunk
   unsigned inj_blocks = 0;  // refill grid: covers the most electrons one instance can need
   size_t total_cap = 0;
@@ -352,6 +361,28 @@ FlightArgs<T> flight_args(mc_ctx* c, const Mat<T>& M, const Geo<T>& G, size_t ta
   return a;
 }
 
+template <typename T>
+StateArrays<T> state_arrays(mc_ctx* c, bool scratch) {
+  const Offsets& o = c->o;
+  StateArrays<T> a;
+  a.kx = c->p<T>(scratch ? o.skx : o.kx); a.ky = c->p<T>(scratch ? o.sky : o.ky); a.kz = c->p<T>(scratch ? o.skz : o.kz);
+  a.x = c->p<T>(scratch ? o.sx : o.x); a.y = c->p<T>(scratch ? o.sy : o.y); a.z = c->p<T>(scratch ? o.sz : o.z);
+  a.meta = c->p<uint32_t>(scratch ? o.smeta : o.meta);
+  return a;
+}
+
+// Stable compaction of the instances whose plan asks for it (the kernels of
+// the other instances return at once).
+template <typename T>
+void enqueue_compaction(mc_ctx* c) {
+  const StateArrays<T> st = state_arrays<T>(c, false), scr = state_arrays<T>(c, true);
+  k_compact_scatter<T><<<c->n_tiles, 256, 0, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip),
+                                                       c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
+                                                       c->p<uint32_t>(c->o.tile_dead), st, scr);
+  dim3 g((unsigned)((c->max_cap + 255) / 256), c->n_inst);
+  k_compact_finish<T><<<g, 256, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->p<Plan>(c->o.plan), st, scr);
+}
+
 // deposit (or merged flight histogram), contact refill, Poisson, field
 void enqueue_refresh(mc_ctx* c, bool after_flight) {
   const int nc = c->ncell;
@@ -363,11 +394,15 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
   k_merge_final<<<gm, 256, 0, c->st>>>(c->p<unsigned long long>(c->o.acc), nc, c->p<uint32_t>(c->o.count),
                                        c->p<unsigned long long>(c->o.heat), c->p<uint32_t>(c->o.ctl),
                                        after_flight ? 1 : 0, after_flight ? 1 : 0);
-  k_inject_plan<<<c->n_inst, kPlanThreads, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->nx, c->P, nc, c->p<uint32_t>(c->o.count),
+  k_inject_plan<<<c->n_inst, kPlanThreads, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->p<TileDesc>(c->o.tiles),
+                                                       c->p<uint32_t>(c->o.meta), c->nx, c->P, nc,
+                                                       c->p<uint32_t>(c->o.count),
                                              c->p<uint32_t>(c->o.tile_dead), c->p<uint32_t>(c->o.tile_off),
                                              c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.next_id),
                                              c->p<unsigned long long>(c->o.counters), c->p<int>(c->o.flags),
                                              c->p<uint32_t>(c->o.ctl));
+  if (c->f32) enqueue_compaction<float>(c);
+  else enqueue_compaction<double>(c);
   k_inject_slots<<<c->n_tiles, 256, 0, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip),
                                                 c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
                                                 c->p<uint32_t>(c->o.tile_dead), c->p<uint32_t>(c->o.meta),
@@ -552,6 +587,7 @@ int mc_init(mc_ctx** out, const mc_config* cfgs, int n, void* d_ws, size_t ws_by
   c->tile = c->dev ? 8192 : 1024;
   c->block = 256;
   c->max_tiles = (int)make_tiles(cfgs, n, min_tile(cfgs[0])).tiles.size();
+  for (int i = 0; i < n; ++i) c->max_cap = std::max<long long>(c->max_cap, cfgs[i].capacity);
   mats(c);
   // per-instance parameters
   long long base = 0;

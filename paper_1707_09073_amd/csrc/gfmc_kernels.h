@@ -57,6 +57,9 @@ struct InstParams {
 
 struct Plan {
   uint32_t Q, id0, u, pad;
+  uint32_t alive;    // live electrons of the instance before the refill
+  uint32_t compact;  // 1: compact the instance's slots in this refresh
+  uint32_t pad2[2];
   uint32_t need[64];
   uint32_t off[64];
 };

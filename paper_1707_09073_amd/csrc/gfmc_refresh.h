@@ -75,13 +75,17 @@ __global__ void k_deposit(const TileDesc* __restrict__ tiles, const T* __restric
 // electrons needed per contact subcell and their offsets.  The q-th new
 // electron takes the q-th free slot.
 constexpr int kPlanThreads = 1024;
-__global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* __restrict__ ip, int nx, int P,
+__global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* __restrict__ ip,
+                                                              const TileDesc* __restrict__ tiles,
+                                                              const uint32_t* __restrict__ meta, int nx, int P,
                                                               int ncell, uint32_t* count,
                                                               const uint32_t* __restrict__ tile_dead,
                                                               uint32_t* tile_off, Plan* plan, uint32_t* next_id,
                                                               unsigned long long* counters, int* flags,
                                                               const uint32_t* ctl) {
   __shared__ uint32_t s_wave[kPlanThreads / 64];
+  __shared__ uint32_t s_holes[kPlanThreads / 64];
+  __shared__ int s_edge;
   const int inst = blockIdx.x;
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
   const InstParams& I = ip[inst];
@@ -111,7 +115,31 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
     tile_off[t] = o;
     o += tile_dead[t];
   }
+  // free slots below the live count: holes a compaction would close (the
+  // free slots of the tiles wholly below it, plus those of the tile it falls
+  // in, counted slot by slot, so the count does not depend on the tiling)
+  const uint32_t alive = (uint32_t)I.cap - run;
+  if (tid == 0) s_edge = -1;
+  __syncthreads();
+  uint32_t holes = 0;
+  for (int t = ta; t < tb; ++t) {
+    const long long s0 = tiles[t].start - I.base;
+    if (s0 + tiles[t].count <= (long long)alive) holes += tile_dead[t];
+    else if (s0 < (long long)alive) s_edge = t;  // one tile holds the position
+  }
+  __syncthreads();
+  if (s_edge >= 0) {
+    const long long s0 = tiles[s_edge].start;
+    const int n = (int)((long long)alive - (s0 - I.base));
+    for (int i = tid; i < n; i += kPlanThreads) holes += (meta[s0 + i] & kAlive) ? 0u : 1u;
+  }
+  holes = wave_sum(holes);
+  if (l == 0) s_holes[wv] = holes;
+  __syncthreads();
   if (wv != 0) return;
+  holes = 0;
+#pragma unroll
+  for (int w = 0; w < kPlanThreads / 64; ++w) holes += s_holes[w];
   uint32_t* cnt = count + (size_t)inst * ncell;
   int cell = -1;
   uint32_t need = 0;
@@ -151,9 +179,95 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
     pl->Q = Q;
     pl->id0 = id0;
     pl->u = ctl[CTL_INTERVAL];
+    pl->alive = alive;
+    pl->compact = (unsigned long long)holes * 32u > alive ? 1u : 0u;
     next_id[inst] = id0 + Q;
     counters[(size_t)inst * kNCnt + C_INJ0] += src;
     counters[(size_t)inst * kNCnt + C_INJ1] += drn;
+  }
+}
+
+// Stable compaction of an instance's slots (device mode), in a refresh where k_inject_plan
+// found the free slots below the live count above 1/32 of the live
+// electrons: every live electron keeps its order and moves to the slot of its
+// rank among the live ones, and the free slots become the tail.  Electrons
+// carry their identity, so the move changes no result; it keeps the particle
+// kernel's tiles dense (holes cost it extra refill rounds).
+// Pass 1, one 256-lane workgroup per tile, 256 consecutive slots per step:
+// ranks from the tile's live prefix (its start minus the free slots before
+// it, from k_inject_plan) and a block scan of the live flags; the state goes
+// to the scratch arrays at that rank; the tile's free-slot count and offset
+// are rewritten for the compacted layout.
+template <typename T>
+struct StateArrays {
+  T *kx, *ky, *kz, *x, *y, *z;
+  uint32_t* meta;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_compact_scatter(const TileDesc* __restrict__ tiles,
+                                                         const InstParams* __restrict__ ip,
+                                                         const Plan* __restrict__ plan, uint32_t* tile_off,
+                                                         uint32_t* tile_dead, StateArrays<T> src,
+                                                         StateArrays<T> dst) {
+  __shared__ uint32_t s_wave[4];
+  const TileDesc td = tiles[blockIdx.x];
+  const Plan& pl = plan[td.inst];
+  if (!pl.compact) return;
+  const long long base = ip[td.inst].base;
+  const uint32_t s0 = (uint32_t)(td.start - base), alive = pl.alive;
+  uint32_t run = s0 - tile_off[blockIdx.x];  // live slots before this tile
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int b = 0; b < td.count; b += 256) {
+    const int i = b + (int)threadIdx.x;
+    const long long p = td.start + i;
+    const uint32_t m = i < td.count ? src.meta[p] : 0u;
+    const bool live = (m & kAlive) != 0;
+    const unsigned long long bal = __ballot(live);
+    if (lane == 0) s_wave[wave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      before += w < wave ? s_wave[w] : 0u;
+      total += s_wave[w];
+    }
+    const long long q = base + run + before + (uint32_t)__popcll(bal & lt);
+    if (live && q < base + ip[td.inst].cap) {  // the bound always holds: tile counts match the flags
+      dst.meta[q] = m;
+      dst.kx[q] = src.kx[p]; dst.ky[q] = src.ky[p]; dst.kz[q] = src.kz[p];
+      dst.x[q] = src.x[p]; dst.y[q] = src.y[p]; dst.z[q] = src.z[p];
+    }
+    run += total;
+    __syncthreads();  // s_wave is rewritten by the next step
+  }
+  if (threadIdx.x == 0) {
+    const uint32_t c = (uint32_t)td.count;
+    const uint32_t live_after = alive > s0 ? min(c, alive - s0) : 0u;
+    tile_dead[blockIdx.x] = c - live_after;
+    tile_off[blockIdx.x] = s0 > alive ? s0 - alive : 0u;
+  }
+}
+
+// Pass 2, one thread per slot of instance blockIdx.y: the compacted state
+// back from the scratch arrays, the tail marked free.
+template <typename T>
+__global__ void k_compact_finish(const InstParams* __restrict__ ip, const Plan* __restrict__ plan,
+                                 StateArrays<T> st, StateArrays<T> scr) {
+  const int inst = blockIdx.y;
+  const Plan& pl = plan[inst];
+  if (!pl.compact) return;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const InstParams& I = ip[inst];
+  if (i >= I.cap) return;
+  const long long p = I.base + i;
+  if (i < (long long)pl.alive) {
+    st.meta[p] = scr.meta[p];
+    st.kx[p] = scr.kx[p]; st.ky[p] = scr.ky[p]; st.kz[p] = scr.kz[p];
+    st.x[p] = scr.x[p]; st.y[p] = scr.y[p]; st.z[p] = scr.z[p];
+  } else {
+    st.meta[p] = 0u;
   }
 }
 

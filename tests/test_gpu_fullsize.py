@@ -30,6 +30,12 @@ BLOCK, TILE = 256, 4096                   # FP64 state
 FP32_SHAPES = [(1024, 20480, 0), (1024, 8192, 2)]
 
 
+def _by_id(p):
+    alive = p["alive"] == 1
+    order = np.argsort(p["id"][alive], kind="stable")
+    return {key: p[key][alive][order] for key in ("id", "valley", "k", "r")}
+
+
 def _say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
@@ -72,15 +78,15 @@ def test_full_size_fp64_interval_matches_oracle(G, oracle_mod):
     e.mc_step(K)
     o.run(1)
     gp, op = e.mc_read_particles(), o.particles()
-    assert np.array_equal(gp["alive"], op["alive"])
-    alive = op["alive"] == 1
-    assert np.array_equal(gp["id"][alive], op["id"][alive])
-    assert np.array_equal(gp["valley"][alive], op["valley"][alive])
-    ko = op["k"][alive]
-    errk = np.abs(gp["k"][alive] - ko) / np.maximum(np.linalg.norm(ko, axis=1), K_FLOOR)[:, None]
-    ro = op["r"][alive]
-    errr = np.abs(gp["r"][alive] - ro) / np.maximum(np.abs(ro), 1.0)
-    _say(f"full size fp64: {int(alive.sum())} electrons, max rel err k {errk.max():.2e} r {errr.max():.2e}")
+    # electrons matched by identity: the GPU may compact its slots in a refresh
+    g, q = _by_id(gp), _by_id(op)
+    assert np.array_equal(g["id"], q["id"])
+    assert np.array_equal(g["valley"], q["valley"])
+    ko = q["k"]
+    errk = np.abs(g["k"] - ko) / np.maximum(np.linalg.norm(ko, axis=1), K_FLOOR)[:, None]
+    ro = q["r"]
+    errr = np.abs(g["r"] - ro) / np.maximum(np.abs(ro), 1.0)
+    _say(f"full size fp64: {g['id'].size} electrons, max rel err k {errk.max():.2e} r {errr.max():.2e}")
     assert errk.max() <= REL and errr.max() <= REL
     t1 = e.mc_tally()
     c_after = o.counts()

@@ -31,19 +31,27 @@ def G():
     return gfmc
 
 
+def _by_id(p):
+    """Live electrons ordered by identity (the GPU may compact its slots, so
+    an electron's slot carries no meaning; its identity does)."""
+    alive = p["alive"] == 1
+    order = np.argsort(p["id"][alive], kind="stable")
+    return {key: p[key][alive][order] for key in ("id", "valley", "k", "r")}
+
+
 def _compare_particles(gp, op, rel=REL, what=""):
-    assert np.array_equal(gp["alive"], op["alive"]), what + " alive"
-    alive = op["alive"] == 1
-    assert np.array_equal(gp["id"][alive], op["id"][alive]), what + " id"
-    assert np.array_equal(gp["valley"][alive], op["valley"][alive]), what + " valley"
-    kg, ko = gp["k"][alive], op["k"][alive]
+    g, o = _by_id(gp), _by_id(op)
+    assert g["id"].size == o["id"].size, what + " live count"
+    assert np.array_equal(g["id"], o["id"]), what + " id"
+    assert np.array_equal(g["valley"], o["valley"]), what + " valley"
+    kg, ko = g["k"], o["k"]
     scale = np.maximum(np.linalg.norm(ko, axis=1), K_FLOOR)[:, None]
     err = np.abs(kg - ko) / scale
-    assert err.max() <= rel, f"{what} k rel err {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
-    rg, ro = gp["r"][alive], op["r"][alive]
+    assert err.max(initial=0.0) <= rel, f"{what} k rel err {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
+    rg, ro = g["r"], o["r"]
     errr = np.abs(rg - ro) / np.maximum(np.abs(ro), 1.0)
-    assert errr.max() <= rel, f"{what} r rel err {errr.max():.3e}"
-    return err.max(), errr.max()
+    assert errr.max(initial=0.0) <= rel, f"{what} r rel err {errr.max():.3e}"
+    return err.max(initial=0.0), errr.max(initial=0.0)
 
 
 def _compare_counts(gt, oc):
@@ -202,6 +210,42 @@ def test_sparse_device_matches_oracle(G, oracle_mod, variant):
     m = e.mc_maps()
     heat_o, dens_o = o.maps()
     assert np.array_equal(m["heat4"], heat_o) and np.array_equal(m["dens_sum"], dens_o)
+
+
+@pytest.mark.parametrize("variant", [0, 2])
+def test_compaction_closes_holes_and_keeps_order(G, oracle_mod, variant):
+    """The live electrons spread over the whole capacity (holes between them)
+    on both sides; after one interval the GPU has compacted its slots: every
+    live electron in a dense prefix, the survivors in their former order, the
+    new electrons behind them, and the physics equal to the oracle's (which
+    keeps its own slot layout) electron by electron."""
+    cfg = _device_small(n=20000)
+    e = G.Ensemble(cfg)
+    e.mc_set_variant(variant)
+    o = oracle_mod.Oracle(cfg)
+    p = e.mc_read_particles()
+    cap = p["alive"].size
+    live = np.nonzero(p["alive"] == 1)[0]
+    spread = (np.arange(live.size) * cap) // live.size
+    q = {key: np.zeros_like(p[key]) for key in p}
+    for key in p:
+        q[key][spread] = p[key][live]
+    e.mc_write_particles(0, q["k"], q["r"], q["valley"], q["alive"], q["id"])
+    o.set_particles(q["k"], q["r"], q["valley"], q["alive"], q["id"])
+    e.mc_step(10)
+    o.run(1)
+    g = e.mc_read_particles()
+    _compare_particles(g, o.particles(), what="compaction")
+    _compare_counts(e.mc_tally(), o.counts())
+    alive = g["alive"] == 1
+    n_alive = int(alive.sum())
+    assert np.array_equal(np.nonzero(alive)[0], np.arange(n_alive)), "live electrons form a dense prefix"
+    ids = g["id"][:n_alive]
+    old = np.isin(ids, p["id"][live])
+    n_old = int(old.sum())
+    assert np.all(old[:n_old]) and not np.any(old[n_old:]), "survivors first, new electrons behind them"
+    before = q["id"][spread]
+    assert np.array_equal(ids[:n_old], before[np.isin(before, ids[:n_old])]), "survivors keep their order"
 
 
 def test_launch_shape_and_graph_do_not_change_results(G):
