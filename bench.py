@@ -270,16 +270,19 @@ def main() -> int:
     ens.mc_set_variant(args.variant)
     if args.block and args.tile:
         ens.mc_set_launch(args.block, args.tile)
-    elif not args.no_autotune:
+    _log(f"warmup {args.warmup} intervals")
+    ens.mc_step(args.warmup * K)
+    if not (args.block and args.tile) and not args.no_autotune:
+        # tuned on the state the timed window starts from (the live
+        # population and its layout in the slots change over the first
+        # picoseconds); every trial restarts from a checkpoint of it
         from paper_1707_09073_amd.autotune import autotune
         _log("autotuning launch shape")
-        ens.mc_step(10 * K)               # leave the initial transient before timing shapes
         tuned = autotune(ens, log=_log)
         args.variant = tuned["variant"]
     block, tile, n_tiles = ens.mc_get_launch()
     ens.mc_use_graph(args.graph)
-    _log(f"launch: block {block}, tile {tile}, {n_tiles} tiles; warmup {args.warmup} intervals")
-    ens.mc_step(args.warmup * K)
+    _log(f"launch: block {block}, tile {tile}, {n_tiles} tiles, variant {args.variant}")
     ens.mc_tally(reset_window=True)
     ens.mc_profile(not args.graph)
     torch.cuda.synchronize()
