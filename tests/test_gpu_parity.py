@@ -253,7 +253,8 @@ def test_launch_shape_and_graph_do_not_change_results(G):
     runs = []
     for block, tile, graph, variant in ((256, 8192, False, 0), (64, 1024, False, 0), (128, 4096, True, 0),
                                         (256, 2048, True, 0), (64, 1024, False, 2), (320, 4160, False, 2),
-                                        (512, 4096, True, 2), (1024, 4096, False, 2), (1024, 8192, True, 0)):
+                                        (512, 4096, True, 2), (1024, 4096, False, 2), (1024, 8192, True, 0),
+                                        (512, 5120, False, 0)):
         _say("launch shape", block, tile, "graph" if graph else "eager", "variant", variant)
         e = G.Ensemble(cfg)
         e.mc_set_launch(block, tile)
