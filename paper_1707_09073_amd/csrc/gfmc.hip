@@ -379,17 +379,28 @@ void enqueue_compaction(mc_ctx* c) {
   k_compact_scatter<T><<<c->n_tiles, 256, 0, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip),
                                                        c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
                                                        c->p<uint32_t>(c->o.tile_dead), st, scr);
-  dim3 g((unsigned)((c->max_cap + 255) / 256), c->n_inst);
+  // a bounded grid that strides over the slots: most refreshes compact
+  // nothing, and then every workgroup only reads the plan
+  dim3 g((unsigned)std::min<long long>((c->max_cap + 255) / 256, 2048), c->n_inst);
   k_compact_finish<T><<<g, 256, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->p<Plan>(c->o.plan), st, scr);
 }
 
 // deposit (or merged flight histogram), contact refill, Poisson, field
 void enqueue_refresh(mc_ctx* c, bool after_flight) {
   const int nc = c->ncell;
-  dim3 gp((5 * nc + 255) / 256, kMergeGroups, c->n_inst);
-  k_merge_partial<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc,
-                                         after_flight && c->variant == 2 ? 1 : 0,
-                                         c->p<unsigned long long>(c->o.acc));
+  const int by_wg = after_flight && c->variant == 2 ? 1 : 0;
+  if ((5 * nc) % 4 == 0) {
+    // groups of about 16 histograms, at most 64 per instance
+    int span = 1;
+    for (const InstParams& I : c->ip) span = std::max(span, by_wg ? I.w1 - I.w0 : I.t1 - I.t0);
+    dim3 gp((5 * nc / 4 + 255) / 256, std::min(64, (span + 15) / 16), c->n_inst);
+    k_merge_partial4<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc, by_wg,
+                                            c->p<unsigned long long>(c->o.acc));
+  } else {
+    dim3 gp((5 * nc + 255) / 256, kMergeGroups, c->n_inst);
+    k_merge_partial<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc, by_wg,
+                                           c->p<unsigned long long>(c->o.acc));
+  }
   dim3 gm((5 * nc + 255) / 256, c->n_inst);
   k_merge_final<<<gm, 256, 0, c->st>>>(c->p<unsigned long long>(c->o.acc), nc, c->p<uint32_t>(c->o.count),
                                        c->p<unsigned long long>(c->o.heat), c->p<uint32_t>(c->o.ctl),
