@@ -379,10 +379,8 @@ void enqueue_compaction(mc_ctx* c) {
   k_compact_scatter<T><<<c->n_tiles, 256, 0, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip),
                                                        c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
                                                        c->p<uint32_t>(c->o.tile_dead), st, scr);
-  // a bounded grid that strides over the slots: most refreshes compact
-  // nothing, and then every workgroup only reads the plan
-  dim3 g((unsigned)std::min<long long>((c->max_cap + 255) / 256, 2048), c->n_inst);
-  k_compact_finish<T><<<g, 256, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->p<Plan>(c->o.plan), st, scr);
+  k_compact_finish<T><<<c->n_tiles, 256, 0, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip),
+                                                      c->p<Plan>(c->o.plan), st, scr);
 }
 
 // deposit (or merged flight histogram), contact refill, Poisson, field
@@ -443,10 +441,12 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
     k_poisson_gemv<<<gv, 256, 0, c->st>>>(c->p<double>(c->o.ainv), c->p<double>(c->o.rhs), nc,
                                           c->p<double>(c->o.phi));
   } else {
-    const int rows = (nc + kPgR - 1) / kPgR;
-    dim3 gg((rows + 3) / 4, (c->n_inst + kPgG - 1) / kPgG);
-    k_poisson_gemm<<<gg, 256, 0, c->st>>>(c->p<double>(c->o.ainv), c->p<double>(c->o.rhs), nc, c->n_inst,
-                                          c->p<double>(c->o.phi));
+    // 4 rows x 8 instances per wavefront: 2 rows x 16 instances halves the
+    // passes over the inverse but doubles the loads of the right-hand sides,
+    // and was slower (73 against 57 us for 64 instances)
+    dim3 gg(((nc + 3) / 4 + 3) / 4, (c->n_inst + 7) / 8);
+    k_poisson_gemm<4, 8, 4><<<gg, 256, 0, c->st>>>(c->p<double>(c->o.ainv), c->p<double>(c->o.rhs), nc, c->n_inst,
+                                                   c->p<double>(c->o.phi));
   }
   k_field<<<gc, 256, 0, c->st>>>(c->pg, c->p<InstParams>(c->o.ip), c->p<double>(c->o.phi), nc,
                                  c->p<double>(c->o.field64), c->p<float>(c->o.field32));

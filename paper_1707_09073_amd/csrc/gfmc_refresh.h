@@ -276,20 +276,21 @@ __global__ void __launch_bounds__(256) k_compact_scatter(const TileDesc* __restr
   }
 }
 
-// Pass 2, one thread per slot of instance blockIdx.y: the compacted state
-// back from the scratch arrays, the tail marked free.
+// Pass 2, one workgroup per tile: the tile's slots of a compacting instance
+// take back the compacted state from the scratch arrays (slots below the live
+// count) or are marked free; tiles of other instances return at once.
 template <typename T>
-__global__ void k_compact_finish(const InstParams* __restrict__ ip, const Plan* __restrict__ plan,
-                                 StateArrays<T> st, StateArrays<T> scr) {
-  const int inst = blockIdx.y;
-  const Plan& pl = plan[inst];
+__global__ void __launch_bounds__(256) k_compact_finish(const TileDesc* __restrict__ tiles,
+                                                        const InstParams* __restrict__ ip,
+                                                        const Plan* __restrict__ plan, StateArrays<T> st,
+                                                        StateArrays<T> scr) {
+  const TileDesc td = tiles[blockIdx.x];
+  const Plan& pl = plan[td.inst];
   if (!pl.compact) return;
-  const InstParams& I = ip[inst];
-  const long long alive = (long long)pl.alive;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < I.cap;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long p = I.base + i;
-    if (i < alive) {
+  const long long alive_end = ip[td.inst].base + (long long)pl.alive;
+  for (int i = threadIdx.x; i < td.count; i += blockDim.x) {
+    const long long p = td.start + i;
+    if (p < alive_end) {
       st.meta[p] = scr.meta[p];
       st.kx[p] = scr.kx[p]; st.ky[p] = scr.ky[p]; st.kz[p] = scr.kz[p];
       st.x[p] = scr.x[p]; st.y[p] = scr.y[p]; st.z[p] = scr.z[p];
@@ -723,51 +724,50 @@ __global__ void __launch_bounds__(256) k_poisson_gemv(const double* __restrict__
   if (lane == 0) phi[(size_t)inst * ncell + row] = s;
 }
 
-// Many instances: Phi = A^-1 [rhs_0 ... rhs_n-1], register-blocked over
-// kPgR rows and kPgG instances per wavefront, so each column element of the
-// inverse is read once per kPgG instances; same summation order as
-// k_poisson_gemv.
-constexpr int kPgR = 4, kPgG = 8;
+// Many instances: Phi = A^-1 [rhs_0 ... rhs_n-1], register-blocked over R
+// rows and G instances per wavefront, so each column element of the inverse
+// is read once per G instances; same summation order as k_poisson_gemv.
+template <int R, int G, int U>
 __global__ void __launch_bounds__(256) k_poisson_gemm(const double* __restrict__ Ainv,
                                                       const double* __restrict__ rhs, int ncell, int n_inst,
                                                       double* phi) {
   const int lane = threadIdx.x & 63;
-  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * kPgR;
-  const int i0 = blockIdx.y * kPgG;
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * R;
+  const int i0 = blockIdx.y * G;
   if (row0 >= ncell) return;
-  double s[kPgR][kPgG];
+  double s[R][G];
 #pragma unroll
-  for (int r = 0; r < kPgR; ++r)
+  for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int g = 0; g < kPgG; ++g) s[r][g] = 0.0;
-  const double* arow[kPgR];
-  const double* bcol[kPgG];
+    for (int g = 0; g < G; ++g) s[r][g] = 0.0;
+  const double* arow[R];
+  const double* bcol[G];
 #pragma unroll
-  for (int r = 0; r < kPgR; ++r) arow[r] = Ainv + (size_t)min(row0 + r, ncell - 1) * ncell;
+  for (int r = 0; r < R; ++r) arow[r] = Ainv + (size_t)min(row0 + r, ncell - 1) * ncell;
 #pragma unroll
-  for (int g = 0; g < kPgG; ++g) bcol[g] = rhs + (size_t)min(i0 + g, n_inst - 1) * ncell;
+  for (int g = 0; g < G; ++g) bcol[g] = rhs + (size_t)min(i0 + g, n_inst - 1) * ncell;
   // unrolled so several columns' loads are in flight; each sum stays in column order
-#pragma unroll 4
+#pragma unroll U
   for (int j = lane; j < ncell; j += 64) {
-    double av[kPgR], bv[kPgG];
+    double av[R], bv[G];
 #pragma unroll
-    for (int r = 0; r < kPgR; ++r) av[r] = arow[r][j];
+    for (int r = 0; r < R; ++r) av[r] = arow[r][j];
 #pragma unroll
-    for (int g = 0; g < kPgG; ++g) bv[g] = bcol[g][j];
+    for (int g = 0; g < G; ++g) bv[g] = bcol[g][j];
 #pragma unroll
-    for (int r = 0; r < kPgR; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int g = 0; g < kPgG; ++g) s[r][g] = fma(av[r], bv[g], s[r][g]);
+      for (int g = 0; g < G; ++g) s[r][g] = fma(av[r], bv[g], s[r][g]);
   }
 #pragma unroll
-  for (int r = 0; r < kPgR; ++r)
+  for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int g = 0; g < kPgG; ++g) s[r][g] = lane_butterfly(s[r][g]);
+    for (int g = 0; g < G; ++g) s[r][g] = lane_butterfly(s[r][g]);
   if (lane == 0) {
 #pragma unroll
-    for (int r = 0; r < kPgR; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int g = 0; g < kPgG; ++g)
+      for (int g = 0; g < G; ++g)
         if (row0 + r < ncell && i0 + g < n_inst) phi[(size_t)(i0 + g) * ncell + row0 + r] = s[r][g];
   }
 }

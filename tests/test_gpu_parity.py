@@ -273,12 +273,13 @@ def test_launch_shape_and_graph_do_not_change_results(G):
         assert np.array_equal(m["heat4"], m0["heat4"]) and np.array_equal(m["dens_sum"], m0["dens_sum"])
 
 
-@pytest.mark.parametrize("variant", [0, 2])
-def test_batched_instances_equal_separate_runs(G, variant):
-    """Three bias points in one context equal three separate runs, per
-    particle; with the persistent queue each instance has its own share of
-    the workgroups and its own queue."""
-    cfgs = W.bias_sweep(3, n_min=3000, n_max=9000)
+@pytest.mark.parametrize("n_inst,variant", [(3, 0), (3, 2), (18, 0)])
+def test_batched_instances_equal_separate_runs(G, n_inst, variant):
+    """Bias points in one context equal separate runs, per particle; with the
+    persistent queue each instance has its own share of the workgroups and
+    its own queue.  The batched Poisson product blocks 8 instances per
+    wavefront (18: two full groups and a ragged one)."""
+    cfgs = W.bias_sweep(n_inst, n_min=3000, n_max=9000)
     for c in cfgs:
         c["precision"] = "fp32"
     eb = G.Ensemble(cfgs)
