@@ -237,8 +237,10 @@ int mc_profile(mc_ctx *ctx, int enable);
 int mc_profile_read(mc_ctx *ctx, double *flight_ms, int *n_flight, double *refresh_ms, int *n_refresh, int reset);
 
 /* Bytes and contents of a checkpoint (particle state, counters, tallies,
- * fields); restoring into a context built from the same configurations
- * continues bit-identically. */
+ * fields, refill plans); restoring into a context built from the same
+ * configurations continues bit-identically.  A checkpoint starts with a
+ * format word: mc_restore rejects (MC_E_ARG) one written by a library whose
+ * workspace image differs, or one of another context's size. */
 int mc_checkpoint(mc_ctx *ctx, void *h_buf, size_t *bytes);
 int mc_restore(mc_ctx *ctx, const void *h_buf, size_t bytes);
 

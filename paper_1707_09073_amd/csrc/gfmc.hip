@@ -351,6 +351,7 @@ FlightArgs<T> flight_args(mc_ctx* c, const Mat<T>& M, const Geo<T>& G, size_t ta
   a.flags = c->p<int>(c->o.flags);
   a.ctl = c->p<uint32_t>(c->o.ctl);
   a.wg_inst = c->p<int>(c->o.wg_inst);
+  a.plan = c->p<Plan>(c->o.plan);
   a.tile = c->tile;
   a.chunk = c->chunk;
   a.M = M;
@@ -387,17 +388,19 @@ void enqueue_compaction(mc_ctx* c) {
 void enqueue_refresh(mc_ctx* c, bool after_flight) {
   const int nc = c->ncell;
   const int by_wg = after_flight && c->variant == 2 ? 1 : 0;
+  // after the lane-refill kernel, only the tiles below the bound of slots in use
+  const Plan* hw_plan = after_flight && c->variant == 0 && c->dev ? c->p<Plan>(c->o.plan) : nullptr;
   if ((5 * nc) % 4 == 0) {
     // groups of about 16 histograms, at most 64 per instance
     int span = 1;
     for (const InstParams& I : c->ip) span = std::max(span, by_wg ? I.w1 - I.w0 : I.t1 - I.t0);
     dim3 gp((5 * nc / 4 + 255) / 256, std::min(64, (span + 15) / 16), c->n_inst);
     k_merge_partial4<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc, by_wg,
-                                            c->p<unsigned long long>(c->o.acc));
+                                            hw_plan, c->tile, c->p<unsigned long long>(c->o.acc));
   } else {
     dim3 gp((5 * nc + 255) / 256, kMergeGroups, c->n_inst);
     k_merge_partial<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc, by_wg,
-                                           c->p<unsigned long long>(c->o.acc));
+                                           hw_plan, c->tile, c->p<unsigned long long>(c->o.acc));
   }
   dim3 gm((5 * nc + 255) / 256, c->n_inst);
   k_merge_final<<<gm, 256, 0, c->st>>>(c->p<unsigned long long>(c->o.acc), nc, c->p<uint32_t>(c->o.count),
@@ -687,6 +690,8 @@ int mc_init(mc_ctx** out, const mc_config* cfgs, int n, void* d_ws, size_t ws_by
                                                        cfgs[i].n_particles);
     }
   }
+  // the initial electrons fill the slots [0, N) of each instance
+  for (int i = 0; i < n; ++i) k_set_hw<<<1, 64, 0, c->st>>>(c->p<Plan>(o.plan), i, (uint32_t)cfgs[i].n_particles);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(c->ws + o.next_id, nid.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, c->st));
   if (c->dev) {
@@ -949,6 +954,10 @@ int mc_write_particles(mc_ctx* c, int inst, const double* h_k, const double* h_r
     meta[i] = (h_id[i] << 3) | (h_alive[i] ? kAlive : 0u) | (uint32_t)h_valley[i];
   }
   HIPCHK(c, hipMemcpy(c->p<uint32_t>(c->o.meta) + b, meta.data(), sizeof(uint32_t) * cap, hipMemcpyHostToDevice));
+  // live electrons may now lie anywhere in the instance's slots
+  k_set_hw<<<1, 64, 0, c->st>>>(c->p<Plan>(c->o.plan), inst, (uint32_t)cap);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->st));
   return MC_OK;
 }
 
@@ -1067,18 +1076,23 @@ int mc_profile_read(mc_ctx* c, double* flight_ms, int* n_flight, double* refresh
   return MC_OK;
 }
 
-// checkpoint = the whole workspace image (particles, counters, tallies,
-// fields, tables) plus the host-side temperature maps
+// checkpoint = a format word, the workspace size, the whole workspace image
+// (particles, counters, tallies, fields, tables, refill plans) and the
+// host-side temperature maps.  The format word changes whenever the meaning
+// of the workspace image does.
+constexpr uint64_t kCheckpointFormat = 0x67666d6300000002ull;  // "gfmc", 2: plans carry the slots in use
+
 int mc_checkpoint(mc_ctx* c, void* h_buf, size_t* bytes) {
   if (!c || !bytes) return MC_E_ARG;
   size_t need = 0;
   layout(c->cfg.data(), c->n_inst, &need);
   const size_t tbytes = sizeof(double) * (size_t)c->n_inst * c->ncell;
-  const size_t total = sizeof(uint64_t) + need + tbytes;
+  const size_t total = 2 * sizeof(uint64_t) + need + tbytes;
   if (!h_buf) { *bytes = total; return MC_OK; }
   if (*bytes < total) return fail(c, MC_E_ARG, "checkpoint buffer too small");
   HIPCHK(c, hipStreamSynchronize(c->st));
-  char* b = (char*)h_buf;
+  std::memcpy(h_buf, &kCheckpointFormat, sizeof(uint64_t));
+  char* b = (char*)h_buf + sizeof(uint64_t);
   const uint64_t n64 = need;
   std::memcpy(b, &n64, sizeof(n64));
   HIPCHK(c, hipMemcpy(b + sizeof(n64), c->ws, need, hipMemcpyDeviceToHost));
@@ -1094,10 +1108,14 @@ int mc_restore(mc_ctx* c, const void* h_buf, size_t bytes) {
   size_t need = 0;
   layout(c->cfg.data(), c->n_inst, &need);
   const size_t tbytes = sizeof(double) * (size_t)c->n_inst * c->ncell;
-  uint64_t n64 = 0;
-  std::memcpy(&n64, h_buf, sizeof(n64));
+  uint64_t fmt = 0, n64 = 0;
+  if (bytes < 2 * sizeof(uint64_t)) return fail(c, MC_E_ARG, "checkpoint does not match");
+  std::memcpy(&fmt, h_buf, sizeof(fmt));
+  if (fmt != kCheckpointFormat) return fail(c, MC_E_ARG, "checkpoint from another library version");
+  const char* b = (const char*)h_buf + sizeof(uint64_t);
+  bytes -= sizeof(uint64_t);
+  std::memcpy(&n64, b, sizeof(n64));
   if (n64 != need || bytes < sizeof(n64) + need + tbytes) return fail(c, MC_E_ARG, "checkpoint does not match");
-  const char* b = (const char*)h_buf;
   HIPCHK(c, hipStreamSynchronize(c->st));
   // keep the launch-shape-dependent tile table of this context
   const int blk = c->block, tl = c->tile;

@@ -59,7 +59,8 @@ struct Plan {
   uint32_t Q, id0, u, pad;
   uint32_t alive;    // live electrons of the instance before the refill
   uint32_t compact;  // 1: compact the instance's slots in this refresh
-  uint32_t pad2[2];
+  uint32_t hw;       // slots in use (relative): every live electron lies below it
+  uint32_t pad2;
   uint32_t need[64];
   uint32_t off[64];
 };
@@ -79,6 +80,7 @@ struct FlightArgs {
   unsigned long long* counters;
   int* flags;
   const uint32_t* ctl;
+  const Plan* plan;     // lane-refill kernel (device mode): slots in use per instance
   const int* wg_inst;  // persistent kernel: instance of each workgroup
   int tile, chunk;     // persistent kernel: tile and chunk sizes (slots)
   Mat<T> M;
@@ -557,7 +559,7 @@ __device__ __forceinline__ void flush_workgroup(const Cnt& c, const uint32_t* rc
     if (lane == 0 && s) atomicAdd(sh_real + q, s);
   }
   __syncthreads();
-  if (DEV) {
+  if (DEV && part) {
     for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x)
       part[i] = i < ncell ? (packed_dep ? dep_get(sh_dep, i) : sh_dep[i]) : sh_heat[i - ncell];
   }
@@ -605,9 +607,17 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
   const T* gp = a.gamma + td.inst * 4;
   const T gam[3] = {gp[0], gp[1], gp[2]};  // workgroup-uniform
   const uint32_t n_int = a.ctl[CTL_INTERVAL];
+  // slots of the tile below the instance's bound of slots in use; those
+  // above it are free and only counted
+  uint32_t lim = (uint32_t)td.count;
+  if (DEV) {
+    const uint32_t hw = a.plan[td.inst].hw, rel = (uint32_t)(td.start - P.base);
+    lim = hw > rel ? min(lim, hw - rel) : 0u;
+  }
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = (1ull << lane) - 1ull;
   Cnt c = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  if (threadIdx.x == 0) c.dead = (uint32_t)td.count - lim;
   bool guard_hit = false, nan_hit = false;
   bool has = false, exhausted = false;
   LaneE<T> L = {};
@@ -625,7 +635,7 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
       base = __shfl(base, first);
       if (want) {
         const uint32_t idx = base + (uint32_t)__popcll(m & lt);
-        if (idx < (uint32_t)td.count) has = take_slot<T, DEV>(a, td.start + idx, L, c);
+        if (idx < lim) has = take_slot<T, DEV>(a, td.start + idx, L, c);
         else exhausted = true;
       }
       want = !has && !exhausted;
@@ -642,9 +652,11 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
   }
   if (guard_hit) set_flag(a.flags, td.inst, -4);
   if (nan_hit) set_flag(a.flags, td.inst, -6);
+  // a tile wholly above the bound holds no electron: its histogram is not
+  // written, and the merge stops at the bound
   flush_workgroup<DEV>(c, rc, sh_dep, true, sh_heat, sh_real, sh_misc, ncell,
-                       a.partial + (size_t)blockIdx.x * 5 * ncell, a.counters + (size_t)td.inst * kNCnt,
-                       a.tile_dead + blockIdx.x);
+                       lim > 0 ? a.partial + (size_t)blockIdx.x * 5 * ncell : nullptr,
+                       a.counters + (size_t)td.inst * kNCnt, a.tile_dead + blockIdx.x);
 }
 
 // Persistent variant: as many workgroups as the GPU holds at once, each bound

@@ -14,12 +14,23 @@ namespace gfmc {
 // into the electron count (bins [0, ncell)) and the window heat counts
 // (bins [ncell, 5 ncell)), clears it, and advances the interval counter.
 constexpr int kMergeGroups = 32;
+
+// End of an instance's histograms to merge: all of its workgroups or tiles,
+// or, given the bound of slots in use and the tile size (plan non-null, after
+// the lane-refill kernel, which writes no histogram for a tile wholly above
+// the bound), the tiles that reach below the bound.
+__device__ __forceinline__ int merge_end(const InstParams& I, int by_wg, const Plan* plan, int inst, int tile) {
+  if (by_wg) return I.w1;
+  if (!plan) return I.t1;
+  const long long nt = ((long long)plan[inst].hw + tile - 1) / tile;
+  return (int)min((long long)I.t1, (long long)I.t0 + nt);
+}
 __global__ void k_merge_partial(const uint32_t* __restrict__ partial, const InstParams* __restrict__ ip, int ncell,
-                                int by_wg, unsigned long long* acc) {
+                                int by_wg, const Plan* __restrict__ plan, int tile, unsigned long long* acc) {
   const int inst = blockIdx.z;
   const int bin = blockIdx.x * blockDim.x + threadIdx.x;
   if (bin >= 5 * ncell) return;
-  const int t0 = by_wg ? ip[inst].w0 : ip[inst].t0, t1 = by_wg ? ip[inst].w1 : ip[inst].t1;
+  const int t0 = by_wg ? ip[inst].w0 : ip[inst].t0, t1 = merge_end(ip[inst], by_wg, plan, inst, tile);
   const int per = (t1 - t0 + kMergeGroups - 1) / kMergeGroups;
   const int a = t0 + blockIdx.y * per, b = min(t1, a + per);
   unsigned long long s = 0;
@@ -32,12 +43,12 @@ __global__ void k_merge_partial(const uint32_t* __restrict__ partial, const Inst
 // multiple of 4 (every histogram then starts on a 16-byte boundary); the
 // launch picks the number of groups (gridDim.y).
 __global__ void k_merge_partial4(const uint32_t* __restrict__ partial, const InstParams* __restrict__ ip, int ncell,
-                                 int by_wg, unsigned long long* acc) {
+                                 int by_wg, const Plan* __restrict__ plan, int tile, unsigned long long* acc) {
   const int inst = blockIdx.z;
   const int nq = 5 * ncell / 4;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
-  const int t0 = by_wg ? ip[inst].w0 : ip[inst].t0, t1 = by_wg ? ip[inst].w1 : ip[inst].t1;
+  const int t0 = by_wg ? ip[inst].w0 : ip[inst].t0, t1 = merge_end(ip[inst], by_wg, plan, inst, tile);
   const int per = (t1 - t0 + (int)gridDim.y - 1) / (int)gridDim.y;
   const int a = t0 + blockIdx.y * per, b = min(t1, a + per);
   const uint4* src = reinterpret_cast<const uint4*>(partial) + q;
@@ -206,11 +217,22 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
     pl->id0 = id0;
     pl->u = ctl[CTL_INTERVAL];
     pl->alive = alive;
-    pl->compact = (unsigned long long)holes * 32u > alive ? 1u : 0u;
+    const uint32_t compact = (unsigned long long)holes * 32u > alive ? 1u : 0u;
+    pl->compact = compact;
+    // new slots in use: after a compaction the live electrons fill [0, alive)
+    // and the new ones follow them; otherwise the Q lowest free slots take
+    // the new ones, so the bound grows only past alive + Q
+    pl->hw = compact ? alive + Q : max(min(pl->hw, (uint32_t)I.cap), alive + Q);
     next_id[inst] = id0 + Q;
     counters[(size_t)inst * kNCnt + C_INJ0] += src;
     counters[(size_t)inst * kNCnt + C_INJ1] += drn;
   }
+}
+
+// Bound of slots in use of one instance, set by the host where it knows it
+// (initial ensemble) or cannot (particles written from the host: capacity).
+__global__ void k_set_hw(Plan* plan, int inst, uint32_t hw) {
+  if (threadIdx.x == 0) plan[inst].hw = hw;
 }
 
 // Stable compaction of an instance's slots (device mode), in a refresh where k_inject_plan

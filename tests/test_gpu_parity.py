@@ -307,6 +307,14 @@ def test_checkpoint_restore_is_bit_exact(G):
     pa, pb = a.mc_read_particles(), b.mc_read_particles()
     for key in pa:
         assert np.array_equal(pa[key], pb[key]), key
+    # a checkpoint of another format, or truncated, is refused and leaves the context usable
+    bad = bytearray(blob)
+    bad[0] ^= 1
+    with pytest.raises(G.MCError):
+        b.mc_restore(bytes(bad))
+    with pytest.raises(G.MCError):
+        b.mc_restore(blob[: len(blob) // 2])
+    b.mc_step(10)
 
 
 def test_fp32_bulk_statistics_match_fp64_oracle(G, oracle_mod):
