@@ -372,16 +372,19 @@ StateArrays<T> state_arrays(mc_ctx* c, bool scratch) {
   return a;
 }
 
-// Stable compaction of the instances whose plan asks for it (the kernels of
-// the other instances return at once).
+// Stable compaction of the instances whose plan asks for it (the tiles of
+// the other instances return at once): the gather into the scratch arrays,
+// then, per tile, the copy back and the free-slot list.
 template <typename T>
-void enqueue_compaction(mc_ctx* c) {
+void enqueue_compaction_and_slots(mc_ctx* c) {
   const StateArrays<T> st = state_arrays<T>(c, false), scr = state_arrays<T>(c, true);
   k_compact_scatter<T><<<c->n_tiles, 256, 0, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip),
                                                        c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
                                                        c->p<uint32_t>(c->o.tile_dead), st, scr);
-  k_compact_finish<T><<<c->n_tiles, 256, 0, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip),
-                                                      c->p<Plan>(c->o.plan), st, scr);
+  k_inject_slots<T><<<c->n_tiles, 256, 0, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip),
+                                                    c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
+                                                    c->p<uint32_t>(c->o.tile_dead), st, scr,
+                                                    c->p<uint32_t>(c->o.slots));
 }
 
 // deposit (or merged flight histogram), contact refill, Poisson, field
@@ -402,23 +405,17 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
     k_merge_partial<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc, by_wg,
                                            hw_plan, c->tile, c->p<unsigned long long>(c->o.acc));
   }
-  dim3 gm((5 * nc + 255) / 256, c->n_inst);
-  k_merge_final<<<gm, 256, 0, c->st>>>(c->p<unsigned long long>(c->o.acc), nc, c->p<uint32_t>(c->o.count),
-                                       c->p<unsigned long long>(c->o.heat), c->p<uint32_t>(c->o.ctl),
-                                       after_flight ? 1 : 0, after_flight ? 1 : 0);
-  k_inject_plan<<<c->n_inst, kPlanThreads, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->p<TileDesc>(c->o.tiles),
-                                                       c->p<uint32_t>(c->o.meta), c->nx, c->P, nc,
-                                                       c->p<uint32_t>(c->o.count),
-                                             c->p<uint32_t>(c->o.tile_dead), c->p<uint32_t>(c->o.tile_off),
-                                             c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.next_id),
-                                             c->p<unsigned long long>(c->o.counters), c->p<int>(c->o.flags),
-                                             c->p<uint32_t>(c->o.ctl));
-  if (c->f32) enqueue_compaction<float>(c);
-  else enqueue_compaction<double>(c);
-  k_inject_slots<<<c->n_tiles, 256, 0, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<InstParams>(c->o.ip),
-                                                c->p<Plan>(c->o.plan), c->p<uint32_t>(c->o.tile_off),
-                                                c->p<uint32_t>(c->o.tile_dead), c->p<uint32_t>(c->o.meta),
-                                                c->p<uint32_t>(c->o.slots));
+  // merged counts and heat, refill plan and Poisson right-hand side: one
+  // workgroup per instance
+  const int af = after_flight ? 1 : 0;
+  k_inject_plan<<<c->n_inst, kPlanThreads, 0, c->st>>>(
+      c->p<InstParams>(c->o.ip), c->p<TileDesc>(c->o.tiles), c->p<uint32_t>(c->o.meta), c->pg, nc,
+      c->p<unsigned long long>(c->o.acc), c->p<uint32_t>(c->o.count), c->p<unsigned long long>(c->o.heat), af,
+      c->p<uint32_t>(c->o.tile_dead), c->p<uint32_t>(c->o.tile_off), c->p<Plan>(c->o.plan),
+      c->p<uint32_t>(c->o.next_id), c->p<unsigned long long>(c->o.counters), c->p<int>(c->o.flags),
+      c->p<uint32_t>(c->o.ctl), c->p<double>(c->o.rhs), c->p<unsigned long long>(c->o.dens));
+  if (c->f32) enqueue_compaction_and_slots<float>(c);
+  else enqueue_compaction_and_slots<double>(c);
   const double mg1 = c->cfg[0].mat.m_eff[0];
   if (c->inj_blocks > 0) {
     dim3 gi(c->inj_blocks, c->n_inst);
@@ -436,9 +433,6 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
                                                    c->p<double>(c->o.z), c->p<uint32_t>(c->o.meta));
   }
   dim3 gc((nc + 255) / 256, c->n_inst);
-  k_poisson_rhs<<<gc, 256, 0, c->st>>>(c->pg, c->p<InstParams>(c->o.ip), c->p<uint32_t>(c->o.count),
-                                       c->p<double>(c->o.rhs), c->p<unsigned long long>(c->o.dens),
-                                       after_flight ? 1 : 0, nc);
   if (c->n_inst == 1) {
     dim3 gv((nc + 3) / 4, 1);
     k_poisson_gemv<<<gv, 256, 0, c->st>>>(c->p<double>(c->o.ainv), c->p<double>(c->o.rhs), nc,
@@ -452,7 +446,7 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
                                                    c->p<double>(c->o.phi));
   }
   k_field<<<gc, 256, 0, c->st>>>(c->pg, c->p<InstParams>(c->o.ip), c->p<double>(c->o.phi), nc,
-                                 c->p<double>(c->o.field64), c->p<float>(c->o.field32));
+                                 c->p<double>(c->o.field64), c->p<float>(c->o.field32), c->p<uint32_t>(c->o.ctl), af);
 }
 
 hipEvent_t prof_event(mc_ctx* c) {

@@ -7,6 +7,32 @@
 
 namespace gfmc {
 
+// Subcell grid of the Poisson problem (the discretisation is described with
+// the Poisson kernels below).
+struct PoisGeo {
+  int nx, ny, nz, P;
+  double dx, dy, dz, gx, gy, gz, gate0, gate1, Vc;
+};
+
+__device__ __forceinline__ bool gated(const PoisGeo& g, int ix) {
+  const double xc = (ix + 0.5) * g.dx;
+  return xc >= g.gate0 && xc <= g.gate1;
+}
+
+// Right-hand side of the balance of cell c (coulombs) holding n electrons:
+// the terminal faces' Dirichlet terms plus the doping minus the electrons.
+__device__ __forceinline__ double rhs_cell(const PoisGeo& g, const InstParams& I, int c, uint32_t n) {
+  const int P = g.P;
+  const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
+  double b = 0.0;
+  if (ix == g.nx - 1) b += 2.0 * g.gx * I.Vds;
+  if (gated(g, ix)) {
+    if (iy == g.ny - 1) b += 2.0 * g.gy * I.phig;
+    if (iz == g.nz - 1) b += 2.0 * g.gz * I.phig;
+  }
+  return b + kQ * (I.N_D_nm * g.Vc - I.w * (double)n);
+}
+
 // Sum the per-tile (or, after the persistent kernel, per-workgroup)
 // histograms of each instance in two passes: groups of them add their partial
 // sums into a u64 accumulator (atomics on 5 x ncell
@@ -65,23 +91,6 @@ __global__ void k_merge_partial4(const uint32_t* __restrict__ partial, const Ins
   if (s3) atomicAdd(d + 3, s3);
 }
 
-__global__ void k_merge_final(unsigned long long* acc, int ncell, uint32_t* count, unsigned long long* heat,
-                              uint32_t* ctl, int with_heat, int advance) {
-  const int inst = blockIdx.y;
-  const int bin = blockIdx.x * blockDim.x + threadIdx.x;
-  if (bin < 5 * ncell) {
-    unsigned long long* a = acc + (size_t)inst * 5 * ncell + bin;
-    const unsigned long long s = *a;
-    *a = 0ull;
-    if (bin < ncell) count[(size_t)inst * ncell + bin] = (uint32_t)s;
-    else if (with_heat) heat[(size_t)inst * 4 * ncell + (bin - ncell)] += s;
-  }
-  if (advance && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    ctl[CTL_INTERVAL] += 1u;
-    ctl[CTL_WINDOW] += 1u;
-  }
-}
-
 // Deposit only (used outside a flight interval).
 template <typename T>
 __global__ void k_deposit(const TileDesc* __restrict__ tiles, const T* __restrict__ x, const T* __restrict__ y,
@@ -114,18 +123,32 @@ __global__ void k_deposit(const TileDesc* __restrict__ tiles, const T* __restric
 constexpr int kPlanThreads = 1024;
 __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* __restrict__ ip,
                                                               const TileDesc* __restrict__ tiles,
-                                                              const uint32_t* __restrict__ meta, int nx, int P,
-                                                              int ncell, uint32_t* count,
+                                                              const uint32_t* __restrict__ meta, PoisGeo g,
+                                                              int ncell, unsigned long long* acc, uint32_t* count,
+                                                              unsigned long long* heat, int after_flight,
                                                               const uint32_t* __restrict__ tile_dead,
                                                               uint32_t* tile_off, Plan* plan, uint32_t* next_id,
                                                               unsigned long long* counters, int* flags,
-                                                              const uint32_t* ctl) {
+                                                              const uint32_t* ctl, double* rhs_out,
+                                                              unsigned long long* dens) {
   __shared__ uint32_t s_wave[kPlanThreads / 64];
   __shared__ uint32_t s_holes[kPlanThreads / 64];
   __shared__ int s_edge;
   const int inst = blockIdx.x;
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
   const InstParams& I = ip[inst];
+  const int nx = g.nx, P = g.P;
+  // the merged histogram: electron counts per subcell and, after a flight,
+  // the window's heat counts; the accumulator is cleared for the next merge
+  {
+    unsigned long long* a = acc + (size_t)inst * 5 * ncell;
+    for (int bin = tid; bin < 5 * ncell; bin += kPlanThreads) {
+      const unsigned long long v = a[bin];
+      a[bin] = 0ull;
+      if (bin < ncell) count[(size_t)inst * ncell + bin] = (uint32_t)v;
+      else if (after_flight) heat[(size_t)inst * 4 * ncell + (bin - ncell)] += v;
+    }
+  }
   // free slots per tile, exclusive prefix over the instance's tiles
   const int nt = I.t1 - I.t0;
   const int per = (nt + kPlanThreads - 1) / kPlanThreads;
@@ -173,59 +196,69 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
   holes = wave_sum(holes);
   if (l == 0) s_holes[wv] = holes;
   __syncthreads();
-  if (wv != 0) return;
-  holes = 0;
+  if (wv == 0) {
+    holes = 0;
 #pragma unroll
-  for (int w = 0; w < kPlanThreads / 64; ++w) holes += s_holes[w];
-  uint32_t* cnt = count + (size_t)inst * ncell;
-  int cell = -1;
-  uint32_t need = 0;
-  if (l < 2 * P) {
-    cell = l < P ? l : (nx - 1) * P + (l - P);
-    const int have = (int)cnt[cell];
-    need = have < I.target ? (uint32_t)(I.target - have) : 0u;
-  }
-  // inclusive scan over the 64 lanes
-  uint32_t ninc = need;
+    for (int w = 0; w < kPlanThreads / 64; ++w) holes += s_holes[w];
+    uint32_t* cnt = count + (size_t)inst * ncell;
+    int cell = -1;
+    uint32_t need = 0;
+    if (l < 2 * P) {
+      cell = l < P ? l : (nx - 1) * P + (l - P);
+      const int have = (int)cnt[cell];
+      need = have < I.target ? (uint32_t)(I.target - have) : 0u;
+    }
+    // inclusive scan over the 64 lanes
+    uint32_t ninc = need;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(ninc, d);
-    if (l >= d) ninc += y;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(ninc, d);
+      if (l >= d) ninc += y;
+    }
+    uint32_t Q = __shfl(ninc, 63);
+    const uint32_t off = ninc - need;
+    if (run < Q) {
+      if (l == 0) set_flag(flags, inst, -3);
+      Q = run;
+    }
+    const uint32_t id0 = next_id[inst];
+    if ((unsigned long long)id0 + Q >= (1ull << 29)) {
+      if (l == 0) set_flag(flags, inst, -3);
+      Q = 0;
+    }
+    uint32_t got = 0;
+    if (cell >= 0) {
+      got = off >= Q ? 0u : (off + need <= Q ? need : Q - off);
+      cnt[cell] += got;
+    }
+    Plan* pl = plan + inst;
+    pl->need[l] = need;
+    pl->off[l] = off;
+    const uint32_t src = wave_sum(l < P ? got : 0u), drn = wave_sum(l >= P ? got : 0u);
+    if (l == 0) {
+      pl->Q = Q;
+      pl->id0 = id0;
+      pl->u = ctl[CTL_INTERVAL] + (after_flight ? 1u : 0u);  // k_field advances the counter
+      pl->alive = alive;
+      const uint32_t compact = (unsigned long long)holes * 32u > alive ? 1u : 0u;
+      pl->compact = compact;
+      // new slots in use: after a compaction the live electrons fill [0, alive)
+      // and the new ones follow them; otherwise the Q lowest free slots take
+      // the new ones, so the bound grows only past alive + Q
+      pl->hw = compact ? alive + Q : max(min(pl->hw, (uint32_t)I.cap), alive + Q);
+      next_id[inst] = id0 + Q;
+      counters[(size_t)inst * kNCnt + C_INJ0] += src;
+      counters[(size_t)inst * kNCnt + C_INJ1] += drn;
+    }
   }
-  uint32_t Q = __shfl(ninc, 63);
-  const uint32_t off = ninc - need;
-  if (run < Q) {
-    if (l == 0) set_flag(flags, inst, -3);
-    Q = run;
-  }
-  const uint32_t id0 = next_id[inst];
-  if ((unsigned long long)id0 + Q >= (1ull << 29)) {
-    if (l == 0) set_flag(flags, inst, -3);
-    Q = 0;
-  }
-  uint32_t got = 0;
-  if (cell >= 0) {
-    got = off >= Q ? 0u : (off + need <= Q ? need : Q - off);
-    cnt[cell] += got;
-  }
-  Plan* pl = plan + inst;
-  pl->need[l] = need;
-  pl->off[l] = off;
-  const uint32_t src = wave_sum(l < P ? got : 0u), drn = wave_sum(l >= P ? got : 0u);
-  if (l == 0) {
-    pl->Q = Q;
-    pl->id0 = id0;
-    pl->u = ctl[CTL_INTERVAL];
-    pl->alive = alive;
-    const uint32_t compact = (unsigned long long)holes * 32u > alive ? 1u : 0u;
-    pl->compact = compact;
-    // new slots in use: after a compaction the live electrons fill [0, alive)
-    // and the new ones follow them; otherwise the Q lowest free slots take
-    // the new ones, so the bound grows only past alive + Q
-    pl->hw = compact ? alive + Q : max(min(pl->hw, (uint32_t)I.cap), alive + Q);
-    next_id[inst] = id0 + Q;
-    counters[(size_t)inst * kNCnt + C_INJ0] += src;
-    counters[(size_t)inst * kNCnt + C_INJ1] += drn;
+  // right-hand side of the Poisson problem from the counts, the contact
+  // subcells' new electrons included; after a flight the counts also add to
+  // the window's density sum
+  __syncthreads();
+  for (int c = tid; c < ncell; c += kPlanThreads) {
+    const uint32_t n = count[(size_t)inst * ncell + c];
+    rhs_out[(size_t)inst * ncell + c] = rhs_cell(g, I, c, n);
+    if (after_flight) dens[(size_t)inst * ncell + c] += n;
   }
 }
 
@@ -298,44 +331,40 @@ __global__ void __launch_bounds__(256) k_compact_scatter(const TileDesc* __restr
   }
 }
 
-// Pass 2, one workgroup per tile: the tile's slots of a compacting instance
-// take back the compacted state from the scratch arrays (slots below the live
-// count) or are marked free; tiles of other instances return at once.
-template <typename T>
-__global__ void __launch_bounds__(256) k_compact_finish(const TileDesc* __restrict__ tiles,
-                                                        const InstParams* __restrict__ ip,
-                                                        const Plan* __restrict__ plan, StateArrays<T> st,
-                                                        StateArrays<T> scr) {
-  const TileDesc td = tiles[blockIdx.x];
-  const Plan& pl = plan[td.inst];
-  if (!pl.compact) return;
-  const long long alive_end = ip[td.inst].base + (long long)pl.alive;
-  for (int i = threadIdx.x; i < td.count; i += blockDim.x) {
-    const long long p = td.start + i;
-    if (p < alive_end) {
-      st.meta[p] = scr.meta[p];
-      st.kx[p] = scr.kx[p]; st.ky[p] = scr.ky[p]; st.kz[p] = scr.kz[p];
-      st.x[p] = scr.x[p]; st.y[p] = scr.y[p]; st.z[p] = scr.z[p];
-    } else {
-      st.meta[p] = 0u;
-    }
-  }
-}
-
 // Free-slot ranks of one tile (one 256-lane workgroup, 16 consecutive slots
-// per lane and step): a block prefix scan of the lanes' free counts gives
-// every free slot its instance-wide rank q, and the slot of rank q < Q is
-// written to position q of the instance's slot list (relative slot index).
-// Tiles whose first rank is already >= Q, or that hold no free slot, exit.
-// Every tile's free count is cleared here once read.
+// per lane and step), after the tile's part of a compaction if its instance
+// compacts in this refresh: a block prefix scan of the lanes' free counts
+// gives every free slot its instance-wide rank q, and the slot of rank q < Q
+// is written to position q of the instance's slot list (relative slot index).
+// Tiles whose first rank is already >= Q, or that hold no free slot, stop
+// there.  Every tile's free count is cleared here once read.
+template <typename T>
 __global__ void __launch_bounds__(256) k_inject_slots(const TileDesc* __restrict__ tiles,
                                                       const InstParams* __restrict__ ip,
                                                       const Plan* __restrict__ plan,
                                                       const uint32_t* __restrict__ tile_off, uint32_t* tile_dead,
-                                                      const uint32_t* __restrict__ meta, uint32_t* slot_list) {
+                                                      StateArrays<T> st, StateArrays<T> scr, uint32_t* slot_list) {
   __shared__ uint32_t s_wave[4];
   const TileDesc td = tiles[blockIdx.x];
-  const uint32_t Q = plan[td.inst].Q;
+  const Plan& pl = plan[td.inst];
+  const uint32_t Q = pl.Q;
+  if (pl.compact) {
+    // second pass of a compaction: the tile's slots take back the compacted
+    // state (below the live count) or are marked free
+    const long long alive_end = ip[td.inst].base + (long long)pl.alive;
+    for (int i = threadIdx.x; i < td.count; i += blockDim.x) {
+      const long long p = td.start + i;
+      if (p < alive_end) {
+        st.meta[p] = scr.meta[p];
+        st.kx[p] = scr.kx[p]; st.ky[p] = scr.ky[p]; st.kz[p] = scr.kz[p];
+        st.x[p] = scr.x[p]; st.y[p] = scr.y[p]; st.z[p] = scr.z[p];
+      } else {
+        st.meta[p] = 0u;
+      }
+    }
+    __syncthreads();  // the free-slot scan below reads these meta words
+  }
+  const uint32_t* meta = st.meta;
   uint32_t run = tile_off[blockIdx.x];
   const uint32_t ndead = tile_dead[blockIdx.x];
   __syncthreads();
@@ -552,16 +581,6 @@ __global__ void k_gamma(const T* __restrict__ table, const T* __restrict__ fac, 
 // tridiagonal in x with P = ny nz blocks; the x coupling is -gx I.
 // Block LU: S_0 = D_0, S_i = D_i - gx^2 S_{i-1}^{-1}; M_i = S_i^{-1}.
 // ---------------------------------------------------------------------------
-struct PoisGeo {
-  int nx, ny, nz, P;
-  double dx, dy, dz, gx, gy, gz, gate0, gate1, Vc;
-};
-
-__device__ __forceinline__ bool gated(const PoisGeo& g, int ix) {
-  const double xc = (ix + 0.5) * g.dx;
-  return xc >= g.gate0 && xc <= g.gate1;
-}
-
 // one workgroup; builds M_i for all slices (init only)
 __global__ void k_poisson_factor(PoisGeo g, double* Minv) {
   __shared__ double A[32][65];  // [S | I] augmented, then [I | S^-1]
@@ -696,27 +715,6 @@ __global__ void __launch_bounds__(64) k_poisson_inverse(PoisGeo g, const double*
   for (int c = threadIdx.x; c < ncell; c += 64) Ainv[(size_t)j * ncell + c] = h[c];
 }
 
-// Right-hand side of the cell balance (coulombs) from the electron counts and
-// the terminal faces; also adds the counts to the window density sum.
-__global__ void k_poisson_rhs(PoisGeo g, const InstParams* __restrict__ ip, const uint32_t* __restrict__ count,
-                              double* rhs_out, unsigned long long* dens, int accumulate, int ncell) {
-  const int inst = blockIdx.y;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const InstParams& I = ip[inst];
-  const int P = g.P;
-  const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
-  double b = 0.0;
-  if (ix == g.nx - 1) b += 2.0 * g.gx * I.Vds;
-  if (gated(g, ix)) {
-    if (iy == g.ny - 1) b += 2.0 * g.gy * I.phig;
-    if (iz == g.nz - 1) b += 2.0 * g.gz * I.phig;
-  }
-  const uint32_t n = count[(size_t)inst * ncell + c];
-  rhs_out[(size_t)inst * ncell + c] = b + kQ * (I.N_D_nm * g.Vc - I.w * (double)n);
-  if (accumulate) dens[(size_t)inst * ncell + c] += n;
-}
-
 // phi = A^-1 rhs: one wavefront per row, unit-stride reads of the
 // (Infinity-Cache-resident) inverse.  Every output is summed in one fixed
 // order -- lane l accumulates the products of columns j = l (mod 64) in
@@ -797,9 +795,14 @@ __global__ void __launch_bounds__(256) k_poisson_gemm(const double* __restrict__
 // Centred-difference field E = -grad(phi): a Dirichlet neighbour is its face
 // value half a cell away, a Neumann neighbour the cell itself.
 __global__ void k_field(PoisGeo g, const InstParams* __restrict__ ip, const double* __restrict__ phi_all, int ncell,
-                        double* field64, float* field32) {
+                        double* field64, float* field32, uint32_t* ctl, int advance) {
   const int inst = blockIdx.y;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  // the interval is complete: the refill plan has read the counter
+  if (advance && c == 0 && inst == 0) {
+    ctl[CTL_INTERVAL] += 1u;
+    ctl[CTL_WINDOW] += 1u;
+  }
   if (c >= ncell) return;
   const InstParams& I = ip[inst];
   const double* h = phi_all + (size_t)inst * ncell;
