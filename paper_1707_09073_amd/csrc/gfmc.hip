@@ -405,10 +405,11 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
     k_merge_partial<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc, by_wg,
                                            hw_plan, c->tile, c->p<unsigned long long>(c->o.acc));
   }
-  // merged counts and heat, refill plan and Poisson right-hand side: one
-  // workgroup per instance
+  // merged counts and heat, refill plan and Poisson right-hand side:
+  // workgroup 0 of each instance plans the refill, the others take the bins
   const int af = after_flight ? 1 : 0;
-  k_inject_plan<<<c->n_inst, kPlanThreads, 0, c->st>>>(
+  dim3 gpl(1 + (5 * nc + kPlanThreads - 1) / kPlanThreads, c->n_inst);
+  k_inject_plan<<<gpl, kPlanThreads, 0, c->st>>>(
       c->p<InstParams>(c->o.ip), c->p<TileDesc>(c->o.tiles), c->p<uint32_t>(c->o.meta), c->pg, nc,
       c->p<unsigned long long>(c->o.acc), c->p<uint32_t>(c->o.count), c->p<unsigned long long>(c->o.heat), af,
       c->p<uint32_t>(c->o.tile_dead), c->p<uint32_t>(c->o.tile_off), c->p<Plan>(c->o.plan),

@@ -115,11 +115,15 @@ __global__ void k_deposit(const TileDesc* __restrict__ tiles, const T* __restric
   if (threadIdx.x == 0) tile_dead[blockIdx.x] = sh[5 * ncell];
 }
 
-// Contact refill plan of one instance (one workgroup of kPlanThreads): the
-// free-slot offsets of the instance's tiles (block-wide exclusive scan, each
-// lane owning a contiguous run of tiles), then, in wavefront 0, the
-// electrons needed per contact subcell and their offsets.  The q-th new
-// electron takes the q-th free slot.
+// The refresh after the histogram merge, per instance (grid y).  Workgroup 0
+// plans the contact refill: the free-slot offsets of the instance's tiles
+// (block-wide exclusive scan, each lane owning a contiguous run of tiles),
+// the exact count of holes below the live count, then, in wavefront 0, the
+// electrons needed per contact subcell and their offsets (the q-th new
+// electron takes the q-th free slot), and the contact subcells' counts and
+// Poisson right-hand side with their new electrons.  The other workgroups
+// move the rest of the merged histogram into the counts, right-hand side,
+// density and heat sums.
 constexpr int kPlanThreads = 1024;
 __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* __restrict__ ip,
                                                               const TileDesc* __restrict__ tiles,
@@ -134,20 +138,29 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
   __shared__ uint32_t s_wave[kPlanThreads / 64];
   __shared__ uint32_t s_holes[kPlanThreads / 64];
   __shared__ int s_edge;
-  const int inst = blockIdx.x;
+  const int inst = blockIdx.y;
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
   const InstParams& I = ip[inst];
   const int nx = g.nx, P = g.P;
-  // the merged histogram: electron counts per subcell and, after a flight,
-  // the window's heat counts; the accumulator is cleared for the next merge
-  {
-    unsigned long long* a = acc + (size_t)inst * 5 * ncell;
-    for (int bin = tid; bin < 5 * ncell; bin += kPlanThreads) {
-      const unsigned long long v = a[bin];
-      a[bin] = 0ull;
-      if (bin < ncell) count[(size_t)inst * ncell + bin] = (uint32_t)v;
-      else if (after_flight) heat[(size_t)inst * 4 * ncell + (bin - ncell)] += v;
+  if (blockIdx.x > 0) {
+    // the other workgroups: one bin of the merged histogram per thread, the
+    // accumulator cleared for the next merge.  A subcell's count and its
+    // Poisson right-hand side (after a flight also its density sum); a heat
+    // bin added to the window.  The contact subcells are left to workgroup 0.
+    const int bin = (blockIdx.x - 1) * kPlanThreads + tid;
+    if (bin >= 5 * ncell || (bin < ncell && (bin < P || bin >= ncell - P))) return;
+    unsigned long long* a = acc + (size_t)inst * 5 * ncell + bin;
+    const unsigned long long v = *a;
+    *a = 0ull;
+    if (bin < ncell) {
+      const uint32_t n = (uint32_t)v;
+      count[(size_t)inst * ncell + bin] = n;
+      rhs_out[(size_t)inst * ncell + bin] = rhs_cell(g, I, bin, n);
+      if (after_flight) dens[(size_t)inst * ncell + bin] += n;
+    } else if (after_flight) {
+      heat[(size_t)inst * 4 * ncell + (bin - ncell)] += v;
     }
+    return;
   }
   // free slots per tile, exclusive prefix over the instance's tiles
   const int nt = I.t1 - I.t0;
@@ -200,13 +213,15 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
     holes = 0;
 #pragma unroll
     for (int w = 0; w < kPlanThreads / 64; ++w) holes += s_holes[w];
-    uint32_t* cnt = count + (size_t)inst * ncell;
+    // contact subcells: their merged counts straight from the accumulator
+    unsigned long long* a = acc + (size_t)inst * 5 * ncell;
     int cell = -1;
-    uint32_t need = 0;
+    uint32_t need = 0, have = 0;
     if (l < 2 * P) {
       cell = l < P ? l : (nx - 1) * P + (l - P);
-      const int have = (int)cnt[cell];
-      need = have < I.target ? (uint32_t)(I.target - have) : 0u;
+      have = (uint32_t)a[cell];
+      a[cell] = 0ull;
+      need = (int)have < I.target ? (uint32_t)(I.target - (int)have) : 0u;
     }
     // inclusive scan over the 64 lanes
     uint32_t ninc = need;
@@ -228,8 +243,14 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
     }
     uint32_t got = 0;
     if (cell >= 0) {
+      // count, right-hand side and density sum of the contact subcell with
+      // its new electrons
       got = off >= Q ? 0u : (off + need <= Q ? need : Q - off);
-      cnt[cell] += got;
+      const uint32_t n = have + got;
+      const size_t o = (size_t)inst * ncell + cell;
+      count[o] = n;
+      rhs_out[o] = rhs_cell(g, I, cell, n);
+      if (after_flight) dens[o] += n;
     }
     Plan* pl = plan + inst;
     pl->need[l] = need;
@@ -250,15 +271,6 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
       counters[(size_t)inst * kNCnt + C_INJ0] += src;
       counters[(size_t)inst * kNCnt + C_INJ1] += drn;
     }
-  }
-  // right-hand side of the Poisson problem from the counts, the contact
-  // subcells' new electrons included; after a flight the counts also add to
-  // the window's density sum
-  __syncthreads();
-  for (int c = tid; c < ncell; c += kPlanThreads) {
-    const uint32_t n = count[(size_t)inst * ncell + c];
-    rhs_out[(size_t)inst * ncell + c] = rhs_cell(g, I, c, n);
-    if (after_flight) dens[(size_t)inst * ncell + c] += n;
   }
 }
 
