@@ -11,10 +11,15 @@
 //                    k_flight_persist: resident workgroups, each working
 //                    every nw-th chunk of its instance's slots).
 // then, in gfmc_refresh.h:
-//   k_merge_*        sums the per-tile subcell histograms (deposit and heat).
-//   k_inject_*       refills the contact subcells to neutrality (device mode):
-//                    per-instance plan, slot list, one thread per electron.
-//   k_poisson_rhs    charge balance per cell with the terminal faces, then
+//   k_merge_partial* sums the per-tile subcell histograms (deposit and heat)
+//                    of the tiles below each instance's bound of slots in use.
+//   k_inject_plan    moves the sums into the counts and heat, plans the
+//                    refill of the contact subcells to neutrality (device
+//                    mode) and forms the Poisson right-hand side (charge
+//                    balance per cell with the terminal faces);
+//   k_compact_scatter, k_inject_slots, k_inject_fill  compact the slots when
+//                    holes have gathered, list the free slots, and create one
+//                    electron per thread;
 //   k_poisson_gemv/gemm  the potential from the dense inverse of the
 //                    finite-volume Poisson matrix (built once at init by
 //                    k_poisson_factor + k_poisson_inverse), then

@@ -35,10 +35,10 @@ __device__ __forceinline__ double rhs_cell(const PoisGeo& g, const InstParams& I
 
 // Sum the per-tile (or, after the persistent kernel, per-workgroup)
 // histograms of each instance in two passes: groups of them add their partial
-// sums into a u64 accumulator (atomics on 5 x ncell
-// distinct words per instance), then k_merge_final moves the accumulator
-// into the electron count (bins [0, ncell)) and the window heat counts
-// (bins [ncell, 5 ncell)), clears it, and advances the interval counter.
+// sums into a u64 accumulator (atomics on 5 x ncell distinct words per
+// instance), then k_inject_plan moves the accumulator into the electron
+// count (bins [0, ncell)) and the window heat counts (bins [ncell, 5 ncell))
+// and clears it; k_field advances the interval counter.
 constexpr int kMergeGroups = 32;
 
 // End of an instance's histograms to merge: all of its workgroups or tiles,
