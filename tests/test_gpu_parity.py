@@ -273,6 +273,32 @@ def test_launch_shape_and_graph_do_not_change_results(G):
         assert np.array_equal(m["heat4"], m0["heat4"]) and np.array_equal(m["dens_sum"], m0["dens_sum"])
 
 
+
+def test_shape_and_variant_changes_mid_run_do_not_change_results(G):
+    """Launch shape and kernel variant changed every 20 intervals (as the
+    autotuner does between its trials) give the same electrons, slot by
+    slot, and the same tallies and maps as one shape throughout: the bound
+    of slots in use, the compaction decisions and the free-slot counts carry
+    over from one tiling and kernel to the next."""
+    cfg = _device_small(n=30000, prec="fp32")
+    a = G.Ensemble(cfg)
+    a.mc_set_launch(512, 5120)
+    a.mc_step(600)
+    b = G.Ensemble(cfg)
+    for block, tile, variant in ((256, 2048, 2), (1024, 8192, 0), (512, 4096, 0)):
+        _say("mid-run shape", block, tile, "variant", variant)
+        b.mc_set_launch(block, tile)
+        b.mc_set_variant(variant)
+        b.mc_step(200)
+    pa, pb = a.mc_read_particles(), b.mc_read_particles()
+    for key in pa:
+        assert np.array_equal(pa[key], pb[key]), key
+    ta, tb = a.mc_tally(), b.mc_tally()
+    assert ta["selections"] == tb["selections"] and np.array_equal(ta["real"], tb["real"])
+    assert np.array_equal(ta["exits"], tb["exits"])
+    ma, mb = a.mc_maps(), b.mc_maps()
+    assert np.array_equal(ma["heat4"], mb["heat4"]) and np.array_equal(ma["dens_sum"], mb["dens_sum"])
+
 @pytest.mark.parametrize("n_inst,variant", [(3, 0), (3, 2), (18, 0)])
 def test_batched_instances_equal_separate_runs(G, n_inst, variant):
     """Bias points in one context equal separate runs, per particle; with the
