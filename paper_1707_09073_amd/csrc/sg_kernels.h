@@ -13,12 +13,18 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int BK = 64, KP = BK + 8;  // LDS pitch 72 bf16 (144 B, 16-B aligned rows)
+// Depth of the K slabs staged in LDS: 128 for the 64 x 64 workgroup tiles
+// (each global round trip then feeds twice the matrix-core work of a 64-deep
+// slab, at 128 registers per lane and 35 KB of LDS per workgroup), 64 for the
+// 128 x 128 tiles (128-deep slabs would need 280 registers per lane: one
+// wavefront per SIMD).  Rows of a slab are padded by 8 elements (16 bytes).
+template <int TM> constexpr int slab_depth() { return TM == 32 ? 128 : 64; }
 
-// LDS position of the 8-element k-chunk c (0..7) of tile row r: chunks are
-// permuted within the row by r / 8, so that the 2-byte stores of a transposed
-// operand (lanes 8 rows apart) fall into different banks; a chunk stays
-// contiguous for the 16-byte fragment reads.
+// LDS position of the 8-element k-chunk c (0..CPR-1) of tile row r: chunks
+// are permuted within groups of 8 of the row by r / 8, so that the 2-byte
+// stores of a transposed operand (lanes 8 rows apart) fall into different
+// banks; a chunk stays contiguous for the 16-byte fragment reads.
+template <int KP>
 __device__ __forceinline__ int lds_at(int r, int c) { return r * KP + ((c ^ ((r >> 3) & 7)) << 3); }
 
 enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
@@ -67,7 +73,8 @@ __device__ __forceinline__ uint4 load_chunk(const bf16* p, long ld, int r, int c
 // holds A as [i][k] and B as [j][k]).
 template <bool TA, bool TB, int EPI, int TM>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-  constexpr int BM = 2 * TM, BN = 2 * TM, MB = TM / 32, NCH = BM * 8 / 256;
+  constexpr int BK = slab_depth<TM>(), KP = BK + 8, CPR = BK / 8;
+  constexpr int BM = 2 * TM, BN = 2 * TM, MB = TM / 32, NCH = BM * CPR / 256;
   __shared__ __attribute__((aligned(16))) bf16 As[BM * KP];
   __shared__ __attribute__((aligned(16))) bf16 Bs[BN * KP];  // n-major: Bs[n][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -80,8 +87,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     for (int b = 0; b < MB; ++b)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
-  // BM x 8 chunks of 8 elements per operand and slab, NCH per thread, along
-  // each operand's contiguous dimension (a row of 64 k is 8 chunks; a row of
+  // BM x CPR chunks of 8 elements per operand and slab, NCH per thread, along
+  // each operand's contiguous dimension (a row of BK k is CPR chunks; a row of
   // BM elements is BM / 8)
   constexpr int RS = BM / 8;  // chunks per row of the transposed operands
   uint4 ra[NCH], rb[NCH];
@@ -89,9 +96,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
     for (int rep = 0; rep < NCH; ++rep) {
       const int ch = tid + 256 * rep;
-      ra[rep] = !TA ? *reinterpret_cast<const uint4*>(g.A + (long)(m0 + (ch >> 3)) * g.lda + k0 + (ch & 7) * 8)
+      ra[rep] = !TA ? *reinterpret_cast<const uint4*>(g.A + (long)(m0 + ch / CPR) * g.lda + k0 + (ch % CPR) * 8)
                     : *reinterpret_cast<const uint4*>(g.A + (long)(k0 + ch / RS) * g.lda + m0 + (ch % RS) * 8);
-      rb[rep] = TB ? *reinterpret_cast<const uint4*>(g.B + (long)(n0 + (ch >> 3)) * g.ldb + k0 + (ch & 7) * 8)
+      rb[rep] = TB ? *reinterpret_cast<const uint4*>(g.B + (long)(n0 + ch / CPR) * g.ldb + k0 + (ch % CPR) * 8)
                    : *reinterpret_cast<const uint4*>(g.B + (long)(k0 + ch / RS) * g.ldb + n0 + (ch % RS) * 8);
     }
   };
@@ -99,9 +106,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
     for (int rep = 0; rep < NCH; ++rep) {
       const int ch = tid + 256 * rep;
-      ra[rep] = !TA ? load_chunk(g.A, g.lda, m0 + (ch >> 3), k0 + (ch & 7) * 8, g.M, g.K)
+      ra[rep] = !TA ? load_chunk(g.A, g.lda, m0 + ch / CPR, k0 + (ch % CPR) * 8, g.M, g.K)
                     : load_chunk(g.A, g.lda, k0 + ch / RS, m0 + (ch % RS) * 8, g.K, g.M);
-      rb[rep] = TB ? load_chunk(g.B, g.ldb, n0 + (ch >> 3), k0 + (ch & 7) * 8, g.N, g.K)
+      rb[rep] = TB ? load_chunk(g.B, g.ldb, n0 + ch / CPR, k0 + (ch % CPR) * 8, g.N, g.K)
                    : load_chunk(g.B, g.ldb, k0 + ch / RS, n0 + (ch % RS) * 8, g.K, g.N);
     }
   };
@@ -110,20 +117,20 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     for (int rep = 0; rep < NCH; ++rep) {
       const int ch = tid + 256 * rep;
       if (!TA) {
-        *reinterpret_cast<uint4*>(As + lds_at(ch >> 3, ch & 7)) = ra[rep];
+        *reinterpret_cast<uint4*>(As + lds_at<KP>(ch / CPR, ch % CPR)) = ra[rep];
       } else {
         const bf16* pv = reinterpret_cast<const bf16*>(&ra[rep]);
         const int kk = ch / RS, ic = (ch % RS) * 8;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) As[lds_at(ic + e, kk >> 3) + (kk & 7)] = pv[e];
+        for (int e = 0; e < 8; ++e) As[lds_at<KP>(ic + e, kk >> 3) + (kk & 7)] = pv[e];
       }
       if (TB) {
-        *reinterpret_cast<uint4*>(Bs + lds_at(ch >> 3, ch & 7)) = rb[rep];
+        *reinterpret_cast<uint4*>(Bs + lds_at<KP>(ch / CPR, ch % CPR)) = rb[rep];
       } else {
         const bf16* pv = reinterpret_cast<const bf16*>(&rb[rep]);
         const int kk = ch / RS, jc = (ch % RS) * 8;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[lds_at(jc + e, kk >> 3) + (kk & 7)] = pv[e];
+        for (int e = 0; e < 8; ++e) Bs[lds_at<KP>(jc + e, kk >> 3) + (kk & 7)] = pv[e];
       }
     }
   };
@@ -133,10 +140,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       bf16x8 a[MB], b[MB];
 #pragma unroll
       for (int mi = 0; mi < MB; ++mi)
-        a[mi] = *reinterpret_cast<const bf16x8*>(As + lds_at(wm + mi * 32 + (lane & 31), (ks >> 3) + (lane >> 5)));
+        a[mi] = *reinterpret_cast<const bf16x8*>(As + lds_at<KP>(wm + mi * 32 + (lane & 31), (ks >> 3) + (lane >> 5)));
 #pragma unroll
       for (int ni = 0; ni < MB; ++ni)
-        b[ni] = *reinterpret_cast<const bf16x8*>(Bs + lds_at(wn + ni * 32 + (lane & 31), (ks >> 3) + (lane >> 5)));
+        b[ni] = *reinterpret_cast<const bf16x8*>(Bs + lds_at<KP>(wn + ni * 32 + (lane & 31), (ks >> 3) + (lane >> 5)));
 #pragma unroll
       for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
@@ -267,6 +274,25 @@ __global__ void k_adam(float* w, float* m, float* v, const float* __restrict__ g
   const float wi = w[i] - lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * w[i]);
   w[i] = wi;
   if (wb) wb[i] = (bf16)wi;
+}
+
+// N-major copy of a BF16 weight matrix: out[c][r] = in[r][c] for in R x C
+// (row-major), through 32 x 32 LDS tiles (blockDim 32 x 8).  The forward
+// products read their weights N-major, so that both operands of the GEMM are
+// staged with 16-byte LDS stores along K.
+__global__ void __launch_bounds__(256) k_transpose_bf16(const uint16_t* __restrict__ in, int R, int C,
+                                                        uint16_t* __restrict__ out) {
+  __shared__ uint16_t t[32][34];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int r = r0 + i, col = c0 + threadIdx.x;
+    if (r < R && col < C) t[i][threadIdx.x] = in[(long)r * C + col];
+  }
+  __syncthreads();
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int col = c0 + i, r = r0 + threadIdx.x;
+    if (col < C && r < R) out[(long)col * R + r] = t[threadIdx.x][i];
+  }
 }
 
 // Counter-based uniform initialisation U(-a, a) of FP32 master weights.

@@ -26,7 +26,7 @@ struct Lay {
 };
 
 struct LayerOff {
-  size_t Wb, W, m, v, b, bm, bv, dW, db;
+  size_t Wb, Wt, W, m, v, b, bm, bv, dW, db;  // Wb: BF16 [K][N]; Wt: its N-major copy [N][K]
 };
 
 struct SgLayout {
@@ -66,6 +66,7 @@ SgLayout sg_layout(const sg_config* c) {
       const size_t n = (size_t)s.K[l] * s.N[l];
       LayerOff o;
       o.Wb = L.take(2 * n);
+      o.Wt = L.take(2 * n);
       o.W = L.take(4 * n);
       o.m = L.take(4 * n);
       o.v = L.take(4 * n);
@@ -147,6 +148,14 @@ void gemm(sg_ctx* c, const GemmArgs& g) {
   }
 }
 
+// The N-major copy of a layer's BF16 weights, after every change of them.
+void enqueue_wt(sg_ctx* c, int e, int l) {
+  const SgLayout& s = c->s;
+  const LayerOff& o = s.lo[e][l];
+  dim3 grid((s.N[l] + 31) / 32, (s.K[l] + 31) / 32);
+  k_transpose_bf16<<<grid, dim3(32, 8), 0, c->st>>>(c->p<uint16_t>(o.Wb), s.K[l], s.N[l], c->p<uint16_t>(o.Wt));
+}
+
 GemmArgs ga(const bf16* A, long lda, const bf16* B, long ldb, int M, int N, int K) {
   GemmArgs g;
   std::memset(&g, 0, sizeof(g));
@@ -164,18 +173,18 @@ void enqueue_forward(sg_ctx* c, int e, const float* d_x, int batch, float* out) 
   long ldx = s.K0p;
   for (int l = 0; l < s.L; ++l) {
     const LayerOff& o = s.lo[e][l];
-    GemmArgs g = ga(X, ldx, c->p<bf16>(o.Wb), s.N[l], batch, s.N[l], s.K[l]);
+    GemmArgs g = ga(X, ldx, c->p<bf16>(o.Wt), s.K[l], batch, s.N[l], s.K[l]);  // weights N-major
     g.bias = c->p<float>(o.b);
     if (l < s.L - 1) {
       g.Cf = c->p<float>(s.Z[l]); g.ldcf = s.N[l];
       g.Cb = c->p<bf16>(s.A[l]); g.ldcb = s.N[l];
-      gemm<false, false, EPI_BIAS_GELU>(c, g);
+      gemm<false, true, EPI_BIAS_GELU>(c, g);
       X = c->p<bf16>(s.A[l]);
       ldx = s.N[l];
     } else {
       g.N = c->c.n_out;  // only the real outputs are written
       g.Cf = out; g.ldcf = c->c.n_out;
-      gemm<false, false, EPI_BIAS>(c, g);
+      gemm<false, true, EPI_BIAS>(c, g);
     }
   }
 }
@@ -293,6 +302,8 @@ int sg_init(sg_ctx** out, const sg_config* cfg, void* d_ws, size_t bytes, void* 
                               hipMemcpyHostToDevice, c->st));
     }
   }
+  for (int e = 0; e < cfg->ensemble; ++e)
+    for (int l = 0; l < s.L; ++l) enqueue_wt(c, e, l);
   SGCHK(c, hipGetLastError());
   SGCHK(c, hipStreamSynchronize(c->st));
   return MC_OK;
@@ -407,6 +418,7 @@ int sg_adam(sg_ctx* c, int member, float lr) {
                                          c->p<bf16>(o.Wb), n, lr, b1, b2, c->c.eps, c1, c2, c->c.weight_decay);
     k_adam<<<blocks(s.N[l]), 256, 0, c->st>>>(c->p<float>(o.b), c->p<float>(o.bm), c->p<float>(o.bv),
                                               c->p<float>(o.db), nullptr, s.N[l], lr, b1, b2, c->c.eps, c1, c2, 0.0f);
+    enqueue_wt(c, member, l);
   }
   SGCHK(c, hipGetLastError());
   return MC_OK;
@@ -473,6 +485,8 @@ int sg_set_params(sg_ctx* c, int member, int layer, const float* h_W, const floa
   SGCHK(c, hipMemcpyAsync(c->ws + o.W, w.data(), 4 * n, hipMemcpyHostToDevice, c->st));
   SGCHK(c, hipMemcpyAsync(c->ws + o.Wb, wb.data(), 2 * n, hipMemcpyHostToDevice, c->st));
   SGCHK(c, hipMemcpyAsync(c->ws + o.b, bb.data(), 4 * (size_t)Ni, hipMemcpyHostToDevice, c->st));
+  enqueue_wt(c, member, layer);
+  SGCHK(c, hipGetLastError());
   SGCHK(c, hipStreamSynchronize(c->st));
   return MC_OK;
 }
