@@ -345,7 +345,7 @@ FlightArgs<T> flight_args(mc_ctx* c, const Mat<T>& M, const Geo<T>& G, size_t ta
   a.kx = c->p<T>(c->o.kx); a.ky = c->p<T>(c->o.ky); a.kz = c->p<T>(c->o.kz);
   a.x = c->p<T>(c->o.x); a.y = c->p<T>(c->o.y); a.z = c->p<T>(c->o.z);
   a.meta = c->p<uint32_t>(c->o.meta);
-  a.partial = c->p<uint32_t>(c->o.partial);
+  a.acc = c->p<unsigned long long>(c->o.acc);
   a.tile_dead = c->p<uint32_t>(c->o.tile_dead);
   a.counters = c->p<unsigned long long>(c->o.counters);
   a.flags = c->p<int>(c->o.flags);
@@ -390,20 +390,21 @@ void enqueue_compaction_and_slots(mc_ctx* c) {
 // deposit (or merged flight histogram), contact refill, Poisson, field
 void enqueue_refresh(mc_ctx* c, bool after_flight) {
   const int nc = c->ncell;
-  const int by_wg = after_flight && c->variant == 2 ? 1 : 0;
-  // after the lane-refill kernel, only the tiles below the bound of slots in use
-  const Plan* hw_plan = after_flight && c->variant == 0 && c->dev ? c->p<Plan>(c->o.plan) : nullptr;
-  if ((5 * nc) % 4 == 0) {
-    // groups of about 16 histograms, at most 64 per instance
-    int span = 1;
-    for (const InstParams& I : c->ip) span = std::max(span, by_wg ? I.w1 - I.w0 : I.t1 - I.t0);
-    dim3 gp((5 * nc / 4 + 255) / 256, std::min(64, (span + 15) / 16), c->n_inst);
-    k_merge_partial4<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc, by_wg,
-                                            hw_plan, c->tile, c->p<unsigned long long>(c->o.acc));
-  } else {
-    dim3 gp((5 * nc + 255) / 256, kMergeGroups, c->n_inst);
-    k_merge_partial<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc, by_wg,
-                                           hw_plan, c->tile, c->p<unsigned long long>(c->o.acc));
+  // after a flight the particle kernel has filled the accumulator; after a
+  // deposit the tile histograms are summed into it
+  if (!after_flight) {
+    if ((5 * nc) % 4 == 0) {
+      // groups of about 16 histograms, at most 64 per instance
+      int span = 1;
+      for (const InstParams& I : c->ip) span = std::max(span, I.t1 - I.t0);
+      dim3 gp((5 * nc / 4 + 255) / 256, std::min(64, (span + 15) / 16), c->n_inst);
+      k_merge_partial4<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc,
+                                              c->p<unsigned long long>(c->o.acc));
+    } else {
+      dim3 gp((5 * nc + 255) / 256, kMergeGroups, c->n_inst);
+      k_merge_partial<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc,
+                                             c->p<unsigned long long>(c->o.acc));
+    }
   }
   // merged counts and heat, refill plan and Poisson right-hand side:
   // workgroup 0 of each instance plans the refill, the others take the bins

@@ -6,13 +6,12 @@
 //   k_flight_refill  per lane-slot: free flight + self-scattering selection
 //                    for K sub-steps, lanes refilled from an LDS queue of the
 //                    tile's particles; mechanism counts, heat and the deposit
-//                    of the survivors per subcell kept in LDS, written per
-//                    tile (k_flight: one particle per thread, same physics;
+//                    of the survivors per subcell kept in LDS and added to
+//                    the instance's sums at the end of the workgroup
+//                    (k_flight: one particle per thread, same physics;
 //                    k_flight_persist: resident workgroups, each working
 //                    every nw-th chunk of its instance's slots).
 // then, in gfmc_refresh.h:
-//   k_merge_partial* sums the per-tile subcell histograms (deposit and heat)
-//                    of the tiles below each instance's bound of slots in use.
 //   k_inject_plan    moves the sums into the counts and heat, plans the
 //                    refill of the contact subcells to neutrality (device
 //                    mode) and forms the Poisson right-hand side (charge
@@ -80,7 +79,7 @@ struct FlightArgs {
   const T* gamma;
   T *kx, *ky, *kz, *x, *y, *z;
   uint32_t* meta;
-  uint32_t* partial;
+  unsigned long long* acc;  // device mode: the interval's histogram sums, [instance][5 ncell]
   uint32_t* tile_dead;
   unsigned long long* counters;
   int* flags;
@@ -321,9 +320,11 @@ __global__ void __launch_bounds__(512) k_flight(FlightArgs<T> a) {
   }
   __syncthreads();
   if (DEV) {
-    uint32_t* part = a.partial + (size_t)blockIdx.x * 5 * ncell;
-    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x)
-      part[i] = i < ncell ? dep_get(sh_dep, i) : sh_heat[i - ncell];
+    unsigned long long* h = a.acc + (size_t)td.inst * 5 * ncell;
+    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x) {
+      const uint32_t v = i < ncell ? dep_get(sh_dep, i) : sh_heat[i - ncell];
+      if (v) atomicAdd(h + i, (unsigned long long)v);
+    }
   }
   unsigned long long* cnt = a.counters + (size_t)td.inst * kNCnt;
   for (int tid = threadIdx.x; tid < 39; tid += blockDim.x) {
@@ -545,12 +546,14 @@ __device__ __forceinline__ void retire(const FlightArgs<T>& a, const LaneE<T>& L
 }
 
 // Workgroup end of the lane-refill kernels: per-lane counters summed into LDS,
-// then the workgroup's histogram written to its partial (deposit unpacked when
-// packed) and the event counters added to the instance's totals.
+// then the nonzero bins of the workgroup's histogram (deposit unpacked when
+// packed) added to the instance's sums by 64-bit atomics, exact in any order,
+// and the event counters added to the instance's totals.
 template <bool DEV>
 __device__ __forceinline__ void flush_workgroup(const Cnt& c, const uint32_t* rc, uint32_t* sh_dep, bool packed_dep,
                                                 uint32_t* sh_heat, uint32_t* sh_real, uint32_t* sh_misc, int ncell,
-                                                uint32_t* part, unsigned long long* cnt, uint32_t* tile_dead_out) {
+                                                unsigned long long* hist, unsigned long long* cnt,
+                                                uint32_t* tile_dead_out) {
   const int lane = threadIdx.x & 63;
   const uint32_t vals[8] = {c.sel, c.self, c.ovf, c.ex0, c.ex1, c.refl, c.dead, c.proc};
 #pragma unroll
@@ -564,9 +567,11 @@ __device__ __forceinline__ void flush_workgroup(const Cnt& c, const uint32_t* rc
     if (lane == 0 && s) atomicAdd(sh_real + q, s);
   }
   __syncthreads();
-  if (DEV && part) {
-    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x)
-      part[i] = i < ncell ? (packed_dep ? dep_get(sh_dep, i) : sh_dep[i]) : sh_heat[i - ncell];
+  if (DEV && hist) {
+    for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x) {
+      const uint32_t v = i < ncell ? (packed_dep ? dep_get(sh_dep, i) : sh_dep[i]) : sh_heat[i - ncell];
+      if (v) atomicAdd(hist + i, (unsigned long long)v);
+    }
   }
   for (int tid = threadIdx.x; tid < 39; tid += blockDim.x) {
     if (tid < 30) {
@@ -657,10 +662,9 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
   }
   if (guard_hit) set_flag(a.flags, td.inst, -4);
   if (nan_hit) set_flag(a.flags, td.inst, -6);
-  // a tile wholly above the bound holds no electron: its histogram is not
-  // written, and the merge stops at the bound
+  // a tile wholly above the bound holds no electron and adds nothing
   flush_workgroup<DEV>(c, rc, sh_dep, true, sh_heat, sh_real, sh_misc, ncell,
-                       lim > 0 ? a.partial + (size_t)blockIdx.x * 5 * ncell : nullptr,
+                       lim > 0 ? a.acc + (size_t)td.inst * 5 * ncell : nullptr,
                        a.counters + (size_t)td.inst * kNCnt, a.tile_dead + blockIdx.x);
 }
 
@@ -674,9 +678,9 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
 // slots, so live electrons gather at the front).  Its wavefronts take the
 // workgroup's chunks one at a time from an LDS counter and refill their lanes
 // from the current chunk.  No global queue: nothing to reset between
-// launches.  One histogram per workgroup, laid out as in k_flight_refill (the
-// host gives every instance enough workgroups that none owns more than
-// kMaxTile slots, so the packed deposit cannot carry).  Free slots are added to the tile's
+// launches.  One LDS histogram per workgroup, as in k_flight_refill (the host
+// gives every instance enough workgroups that none owns more than kMaxTile
+// slots, so the packed deposit cannot carry).  Free slots are added to the tile's
 // count by atomics, once per chunk and once per electron that leaves (the
 // refill plan clears the counts after reading them).  Per-electron arithmetic
 // and random-number use are those of k_flight_refill.
@@ -759,8 +763,8 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_persist(Flight
   }
   if (guard_hit) set_flag(a.flags, inst, -4);
   if (nan_hit) set_flag(a.flags, inst, -6);
-  flush_workgroup<DEV>(c, rc, sh_dep, true, sh_heat, sh_real, sh_misc, ncell,
-                       a.partial + (size_t)blockIdx.x * 5 * ncell, a.counters + (size_t)inst * kNCnt, nullptr);
+  flush_workgroup<DEV>(c, rc, sh_dep, true, sh_heat, sh_real, sh_misc, ncell, a.acc + (size_t)inst * 5 * ncell,
+                       a.counters + (size_t)inst * kNCnt, nullptr);
 }
 
 }  // namespace gfmc

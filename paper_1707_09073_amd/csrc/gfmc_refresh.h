@@ -33,30 +33,21 @@ __device__ __forceinline__ double rhs_cell(const PoisGeo& g, const InstParams& I
   return b + kQ * (I.N_D_nm * g.Vc - I.w * (double)n);
 }
 
-// Sum the per-tile (or, after the persistent kernel, per-workgroup)
-// histograms of each instance in two passes: groups of them add their partial
-// sums into a u64 accumulator (atomics on 5 x ncell distinct words per
-// instance), then k_inject_plan moves the accumulator into the electron
-// count (bins [0, ncell)) and the window heat counts (bins [ncell, 5 ncell))
-// and clears it; k_field advances the interval counter.
+// The flight kernels add their workgroup histograms to a u64 accumulator per
+// instance themselves.  Outside a flight (the deposit of a new or rewritten
+// ensemble), k_deposit writes one histogram per tile and these kernels sum
+// them: groups of tiles add their partial sums into the accumulator (atomics
+// on 5 x ncell distinct words per instance).  k_inject_plan then moves the
+// accumulator into the electron count (bins [0, ncell)) and the window heat
+// counts (bins [ncell, 5 ncell)) and clears it; k_field advances the interval
+// counter.
 constexpr int kMergeGroups = 32;
-
-// End of an instance's histograms to merge: all of its workgroups or tiles,
-// or, given the bound of slots in use and the tile size (plan non-null, after
-// the lane-refill kernel, which writes no histogram for a tile wholly above
-// the bound), the tiles that reach below the bound.
-__device__ __forceinline__ int merge_end(const InstParams& I, int by_wg, const Plan* plan, int inst, int tile) {
-  if (by_wg) return I.w1;
-  if (!plan) return I.t1;
-  const long long nt = ((long long)plan[inst].hw + tile - 1) / tile;
-  return (int)min((long long)I.t1, (long long)I.t0 + nt);
-}
 __global__ void k_merge_partial(const uint32_t* __restrict__ partial, const InstParams* __restrict__ ip, int ncell,
-                                int by_wg, const Plan* __restrict__ plan, int tile, unsigned long long* acc) {
+                                unsigned long long* acc) {
   const int inst = blockIdx.z;
   const int bin = blockIdx.x * blockDim.x + threadIdx.x;
   if (bin >= 5 * ncell) return;
-  const int t0 = by_wg ? ip[inst].w0 : ip[inst].t0, t1 = merge_end(ip[inst], by_wg, plan, inst, tile);
+  const int t0 = ip[inst].t0, t1 = ip[inst].t1;
   const int per = (t1 - t0 + kMergeGroups - 1) / kMergeGroups;
   const int a = t0 + blockIdx.y * per, b = min(t1, a + per);
   unsigned long long s = 0;
@@ -69,12 +60,12 @@ __global__ void k_merge_partial(const uint32_t* __restrict__ partial, const Inst
 // multiple of 4 (every histogram then starts on a 16-byte boundary); the
 // launch picks the number of groups (gridDim.y).
 __global__ void k_merge_partial4(const uint32_t* __restrict__ partial, const InstParams* __restrict__ ip, int ncell,
-                                 int by_wg, const Plan* __restrict__ plan, int tile, unsigned long long* acc) {
+                                 unsigned long long* acc) {
   const int inst = blockIdx.z;
   const int nq = 5 * ncell / 4;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
-  const int t0 = by_wg ? ip[inst].w0 : ip[inst].t0, t1 = merge_end(ip[inst], by_wg, plan, inst, tile);
+  const int t0 = ip[inst].t0, t1 = ip[inst].t1;
   const int per = (t1 - t0 + (int)gridDim.y - 1) / (int)gridDim.y;
   const int a = t0 + blockIdx.y * per, b = min(t1, a + per);
   const uint4* src = reinterpret_cast<const uint4*>(partial) + q;
