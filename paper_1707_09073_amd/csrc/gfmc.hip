@@ -32,7 +32,7 @@ struct Layout {
 
 struct Offsets {
   size_t table64, table32, fac64, fac32, field64, field32, phi, gamma64, gamma32, Tcell, count, heat, dens,
-      counters, flags, ctl, next_id, ip, tiles, partial, acc, tile_dead, tile_off, plan, slots, minv, ainv, rhs, hist, reps,
+      counters, flags, ctl, next_id, ip, tiles, acc, tile_dead, tile_off, plan, slots, minv, ainv, rhs, hist, reps,
       nrep, bpart, wg_inst;
   size_t kx, ky, kz, x, y, z, meta;
   size_t skx, sky, skz, sx, sy, sz, smeta;  // compaction scratch (device mode)
@@ -133,7 +133,6 @@ Offsets layout(const mc_config* c, int n, size_t* total) {
   o.next_id = L.take(sizeof(uint32_t) * n);
   o.ip = L.take(sizeof(InstParams) * n);
   o.tiles = L.take(sizeof(TileDesc) * max_tiles);
-  o.partial = L.take(dev ? sizeof(uint32_t) * max_tiles * 5 * nc : 0);
   o.acc = L.take(dev ? sizeof(unsigned long long) * n * 5 * nc : 0);
   o.tile_dead = L.take(sizeof(uint32_t) * max_tiles);
   o.tile_off = L.take(sizeof(uint32_t) * max_tiles);
@@ -180,7 +179,7 @@ struct mc_ctx {
   Offsets o;
   int nb = 0, ncell = 1, nx = 1, ny = 1, nz = 1, P = 1;
   int block = 256, tile = 0, n_tiles = 0;
-  int max_tiles = 0;        // tiles at the smallest tile size: partial histograms the workspace holds
+  int max_tiles = 0;        // tiles at the smallest tile size: per-tile entries the workspace holds
   long long max_cap = 0;    // largest instance capacity
   int n_wg = 0, chunk = 256;  // persistent kernel: workgroups, slots per chunk
   unsigned inj_blocks = 0;  // refill grid: covers the most electrons one instance can need
@@ -285,7 +284,7 @@ int upload_tiles(mc_ctx* c) {
     I.w1 = I.w0 + (int)std::min<long long>(share, I.nchunk);
     wg_inst.resize(I.w1, i);
   }
-  if ((int)wg_inst.size() > c->max_tiles) return fail(c, MC_E_ARG, "persistent grid exceeds the partial histograms");
+  if ((int)wg_inst.size() > c->max_tiles) return fail(c, MC_E_ARG, "persistent grid exceeds the workgroup table");
   c->n_wg = (int)wg_inst.size();
   HIPCHK(c, hipMemcpyAsync(c->ws + c->o.tiles, tp.tiles.data(), sizeof(TileDesc) * tp.tiles.size(),
                            hipMemcpyHostToDevice, c->st));
@@ -390,22 +389,6 @@ void enqueue_compaction_and_slots(mc_ctx* c) {
 // deposit (or merged flight histogram), contact refill, Poisson, field
 void enqueue_refresh(mc_ctx* c, bool after_flight) {
   const int nc = c->ncell;
-  // after a flight the particle kernel has filled the accumulator; after a
-  // deposit the tile histograms are summed into it
-  if (!after_flight) {
-    if ((5 * nc) % 4 == 0) {
-      // groups of about 16 histograms, at most 64 per instance
-      int span = 1;
-      for (const InstParams& I : c->ip) span = std::max(span, I.t1 - I.t0);
-      dim3 gp((5 * nc / 4 + 255) / 256, std::min(64, (span + 15) / 16), c->n_inst);
-      k_merge_partial4<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc,
-                                              c->p<unsigned long long>(c->o.acc));
-    } else {
-      dim3 gp((5 * nc + 255) / 256, kMergeGroups, c->n_inst);
-      k_merge_partial<<<gp, 256, 0, c->st>>>(c->p<uint32_t>(c->o.partial), c->p<InstParams>(c->o.ip), nc,
-                                             c->p<unsigned long long>(c->o.acc));
-    }
-  }
   // merged counts and heat, refill plan and Poisson right-hand side:
   // workgroup 0 of each instance plans the refill, the others take the bins
   const int af = after_flight ? 1 : 0;
@@ -773,13 +756,13 @@ int poisson_update(mc_ctx* c) {
   if (c->f32)
     k_deposit<float><<<c->n_tiles, 256, lds, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<float>(c->o.x),
                                                      c->p<float>(c->o.y), c->p<float>(c->o.z),
-                                                     c->p<uint32_t>(c->o.meta), c->G32, c->p<uint32_t>(c->o.partial),
-                                                     c->p<uint32_t>(c->o.tile_dead));
+                                                     c->p<uint32_t>(c->o.meta), c->G32,
+                                                     c->p<unsigned long long>(c->o.acc), c->p<uint32_t>(c->o.tile_dead));
   else
     k_deposit<double><<<c->n_tiles, 256, lds, c->st>>>(c->p<TileDesc>(c->o.tiles), c->p<double>(c->o.x),
                                                       c->p<double>(c->o.y), c->p<double>(c->o.z),
                                                       c->p<uint32_t>(c->o.meta), c->G64,
-                                                      c->p<uint32_t>(c->o.partial), c->p<uint32_t>(c->o.tile_dead));
+                                                      c->p<unsigned long long>(c->o.acc), c->p<uint32_t>(c->o.tile_dead));
   enqueue_refresh(c, false);
   HIPCHK(c, hipGetLastError());
   return MC_OK;
@@ -1076,7 +1059,7 @@ int mc_profile_read(mc_ctx* c, double* flight_ms, int* n_flight, double* refresh
 // (particles, counters, tallies, fields, tables, refill plans) and the
 // host-side temperature maps.  The format word changes whenever the meaning
 // of the workspace image does.
-constexpr uint64_t kCheckpointFormat = 0x67666d6300000002ull;  // "gfmc", 2: plans carry the slots in use
+constexpr uint64_t kCheckpointFormat = 0x67666d6300000003ull;  // "gfmc", 3: no per-tile histograms
 
 int mc_checkpoint(mc_ctx* c, void* h_buf, size_t* bytes) {
   if (!c || !bytes) return MC_E_ARG;

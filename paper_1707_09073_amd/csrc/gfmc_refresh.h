@@ -1,5 +1,5 @@
-// gfmc_refresh.h -- gfx950 kernels around the particle kernel: the merge of
-// the tile histograms, the contact refill, the Poisson refresh and field,
+// gfmc_refresh.h -- gfx950 kernels around the particle kernel: the summed
+// subcell histograms, the contact refill, the Poisson refresh and field,
 // the set-up kernels (rate tables, per-subcell factors, Gamma_v, the initial
 // ensemble, the dense Poisson inverse) and the bulk-mode observables.
 #pragma once
@@ -33,60 +33,18 @@ __device__ __forceinline__ double rhs_cell(const PoisGeo& g, const InstParams& I
   return b + kQ * (I.N_D_nm * g.Vc - I.w * (double)n);
 }
 
-// The flight kernels add their workgroup histograms to a u64 accumulator per
-// instance themselves.  Outside a flight (the deposit of a new or rewritten
-// ensemble), k_deposit writes one histogram per tile and these kernels sum
-// them: groups of tiles add their partial sums into the accumulator (atomics
-// on 5 x ncell distinct words per instance).  k_inject_plan then moves the
-// accumulator into the electron count (bins [0, ncell)) and the window heat
-// counts (bins [ncell, 5 ncell)) and clears it; k_field advances the interval
-// counter.
-constexpr int kMergeGroups = 32;
-__global__ void k_merge_partial(const uint32_t* __restrict__ partial, const InstParams* __restrict__ ip, int ncell,
-                                unsigned long long* acc) {
-  const int inst = blockIdx.z;
-  const int bin = blockIdx.x * blockDim.x + threadIdx.x;
-  if (bin >= 5 * ncell) return;
-  const int t0 = ip[inst].t0, t1 = ip[inst].t1;
-  const int per = (t1 - t0 + kMergeGroups - 1) / kMergeGroups;
-  const int a = t0 + blockIdx.y * per, b = min(t1, a + per);
-  unsigned long long s = 0;
-#pragma unroll 8
-  for (int t = a; t < b; ++t) s += partial[(size_t)t * 5 * ncell + bin];
-  if (s) atomicAdd(acc + (size_t)inst * 5 * ncell + bin, s);
-}
-
-// The same sums, four bins per lane with 16-byte loads, for 5 x ncell a
-// multiple of 4 (every histogram then starts on a 16-byte boundary); the
-// launch picks the number of groups (gridDim.y).
-__global__ void k_merge_partial4(const uint32_t* __restrict__ partial, const InstParams* __restrict__ ip, int ncell,
-                                 unsigned long long* acc) {
-  const int inst = blockIdx.z;
-  const int nq = 5 * ncell / 4;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
-  const int t0 = ip[inst].t0, t1 = ip[inst].t1;
-  const int per = (t1 - t0 + (int)gridDim.y - 1) / (int)gridDim.y;
-  const int a = t0 + blockIdx.y * per, b = min(t1, a + per);
-  const uint4* src = reinterpret_cast<const uint4*>(partial) + q;
-  unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll 8
-  for (int t = a; t < b; ++t) {
-    const uint4 v = src[(size_t)t * nq];
-    s0 += v.x; s1 += v.y; s2 += v.z; s3 += v.w;
-  }
-  unsigned long long* d = acc + (size_t)inst * 5 * ncell + 4 * q;
-  if (s0) atomicAdd(d, s0);
-  if (s1) atomicAdd(d + 1, s1);
-  if (s2) atomicAdd(d + 2, s2);
-  if (s3) atomicAdd(d + 3, s3);
-}
-
-// Deposit only (used outside a flight interval).
+// Every kernel that counts electrons or heat per subcell (the flight kernels,
+// k_deposit outside a flight) keeps a histogram per workgroup in LDS and adds
+// its nonzero bins to a u64 accumulator per instance by atomics: integer
+// sums, the same in any order.  k_inject_plan then moves the accumulator into
+// the electron count (bins [0, ncell)) and the window heat counts (bins
+// [ncell, 5 ncell)) and clears it; k_field advances the interval counter.
+// Deposit only (used outside a flight interval): live electrons per subcell
+// into the instance's accumulator, free slots per tile.
 template <typename T>
 __global__ void k_deposit(const TileDesc* __restrict__ tiles, const T* __restrict__ x, const T* __restrict__ y,
-                          const T* __restrict__ z, const uint32_t* __restrict__ meta, Geo<T> G, uint32_t* partial,
-                          uint32_t* tile_dead) {
+                          const T* __restrict__ z, const uint32_t* __restrict__ meta, Geo<T> G,
+                          unsigned long long* acc, uint32_t* tile_dead) {
   extern __shared__ uint32_t sh[];
   const int ncell = G.ncell;
   for (int i = threadIdx.x; i < 5 * ncell + 1; i += blockDim.x) sh[i] = 0u;
@@ -101,19 +59,20 @@ __global__ void k_deposit(const TileDesc* __restrict__ tiles, const T* __restric
   dead = wave_sum(dead);
   if ((threadIdx.x & 63) == 0 && dead) atomicAdd(sh + 5 * ncell, dead);
   __syncthreads();
-  uint32_t* part = partial + (size_t)blockIdx.x * 5 * ncell;
-  for (int i = threadIdx.x; i < 5 * ncell; i += blockDim.x) part[i] = sh[i];
+  unsigned long long* h = acc + (size_t)td.inst * 5 * ncell;
+  for (int i = threadIdx.x; i < ncell; i += blockDim.x)
+    if (sh[i]) atomicAdd(h + i, (unsigned long long)sh[i]);
   if (threadIdx.x == 0) tile_dead[blockIdx.x] = sh[5 * ncell];
 }
 
-// The refresh after the histogram merge, per instance (grid y).  Workgroup 0
+// The refresh after the histograms are summed, per instance (grid y).  Workgroup 0
 // plans the contact refill: the free-slot offsets of the instance's tiles
 // (block-wide exclusive scan, each lane owning a contiguous run of tiles),
 // the exact count of holes below the live count, then, in wavefront 0, the
 // electrons needed per contact subcell and their offsets (the q-th new
 // electron takes the q-th free slot), and the contact subcells' counts and
 // Poisson right-hand side with their new electrons.  The other workgroups
-// move the rest of the merged histogram into the counts, right-hand side,
+// move the rest of the summed histogram into the counts, right-hand side,
 // density and heat sums.
 constexpr int kPlanThreads = 1024;
 __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* __restrict__ ip,
@@ -134,8 +93,8 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
   const InstParams& I = ip[inst];
   const int nx = g.nx, P = g.P;
   if (blockIdx.x > 0) {
-    // the other workgroups: one bin of the merged histogram per thread, the
-    // accumulator cleared for the next merge.  A subcell's count and its
+    // the other workgroups: one bin of the summed histogram per thread, the
+    // accumulator cleared for the next interval.  A subcell's count and its
     // Poisson right-hand side (after a flight also its density sum); a heat
     // bin added to the window.  The contact subcells are left to workgroup 0.
     const int bin = (blockIdx.x - 1) * kPlanThreads + tid;
@@ -204,7 +163,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
     holes = 0;
 #pragma unroll
     for (int w = 0; w < kPlanThreads / 64; ++w) holes += s_holes[w];
-    // contact subcells: their merged counts straight from the accumulator
+    // contact subcells: their summed counts straight from the accumulator
     unsigned long long* a = acc + (size_t)inst * 5 * ncell;
     int cell = -1;
     uint32_t need = 0, have = 0;
