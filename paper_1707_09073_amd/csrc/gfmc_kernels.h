@@ -680,7 +680,8 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
 // from the current chunk.  No global queue: nothing to reset between
 // launches.  One LDS histogram per workgroup, as in k_flight_refill (the host
 // gives every instance enough workgroups that none owns more than kMaxTile
-// slots, so the packed deposit cannot carry).  Free slots are added to the tile's
+// slots, so the packed deposit cannot carry).  The part of a chunk at or above
+// the bound of slots in use is counted free without being read.  Free slots are added to the tile's
 // count by atomics, once per chunk and once per electron that leaves (the
 // refill plan clears the counts after reading them).  Per-electron arithmetic
 // and random-number use are those of k_flight_refill.
@@ -707,6 +708,9 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_persist(Flight
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = (1ull << lane) - 1ull;
   const int cpt = (a.tile + a.chunk - 1) / a.chunk;  // chunks per tile
+  // slots at or above the instance's bound of slots in use are free: they
+  // are counted, not read
+  const int hw = DEV ? (int)min(a.plan[inst].hw, (uint32_t)P.cap) : P.cap;
   Cnt c = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
   bool guard_hit = false, nan_hit = false;
   bool has = false;
@@ -736,6 +740,10 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_persist(Flight
         cpos = t * a.tile + sub * a.chunk;
         cend = min(cpos + a.chunk, min((t + 1) * a.tile, P.cap));
         ctile = P.t0 + t;
+        if (cend > hw) {
+          if (DEV && lane == 0) atomicAdd(a.tile_dead + ctile, (uint32_t)(cend - max(cpos, hw)));
+          cend = max(cpos, hw);
+        }
       }
       const int n = __popcll(m);
       const int take = min(n, cend - cpos);
