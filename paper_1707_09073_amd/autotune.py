@@ -20,7 +20,7 @@ import os
 DEFAULT_CANDIDATES = [
     (256, 1536, 0), (256, 2048, 0), (256, 2560, 0), (256, 3072, 0), (256, 4096, 0),
     (256, 5120, 0), (256, 6144, 0), (256, 8192, 0),
-    (512, 2048, 0), (512, 4096, 0), (512, 8192, 0), (384, 3072, 0), (384, 6144, 0),
+    (512, 2048, 0), (512, 2560, 0), (512, 3072, 0), (512, 4096, 0), (512, 8192, 0), (384, 3072, 0), (384, 6144, 0),
     (128, 2048, 0), (256, 4096, 1),
     (1024, 4096, 2), (1024, 8192, 2), (512, 4096, 2),
 ]
@@ -59,7 +59,7 @@ def _key(ens) -> str:
     return f"{c['mode']}/{c.get('precision', 'fp64')}/{len(ens.cfgs)}/{cap}"
 
 
-def autotune(ens, candidates=None, trials: int = 3, cache_file: str | None = None, log=None) -> dict:
+def autotune(ens, candidates=None, trials: int = 5, cache_file: str | None = None, log=None) -> dict:
     """Pick the fastest launch shape for `ens` (a gfmc.Ensemble) and apply it."""
     key = _key(ens)
     if cache_file and os.path.exists(cache_file) and not _cache:
