@@ -202,6 +202,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=500, help="timed flight intervals (10 fs each)")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--particles", type=int, default=10_000_000)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
+                    help="particle state precision (tallies and the Poisson solve are FP64 either way)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--graph", action="store_true", help="replay intervals from a hipGraph (no per-kernel timing)")
@@ -264,6 +266,8 @@ def main() -> int:
             "flight_avg_ms": r["flight_ms"], "refresh_avg_ms": r["refresh_ms"]}), flush=True)
         return 0
     cfg = W.large_device_config(n_particles=args.particles)
+    cfg["precision"] = args.precision
+    f32 = args.precision == "fp32"
     K = cfg["substeps"]
     _log(f"init: {args.particles} superparticles, capacity {cfg['capacity']}")
     ens = gfmc.Ensemble(cfg, device="cuda:0")
@@ -300,7 +304,18 @@ def main() -> int:
     _log(f"wall {wall:.3f} s, segments {segments}, selections {tal['selections']}, real {real}")
 
     roofline = None
-    if prof and prof["n_flight"]:
+    if prof and prof["n_flight"] and not f32:
+        # FP64 state: the particle kernel is timed, but its per-segment counters
+        # were taken for FP32 state only
+        flight_s = prof["flight_ms"] / prof["n_flight"] * 1e-3
+        roofline = dict(
+            bound="alu", achieved=None, peak=ALU_PEAK_LANE_OPS / 1e12, unit="TOP/s", frac=None, traffic=None,
+            counters_current=False, kernel=KERNELS[args.variant].replace("<float", "<double"),
+            note="per-segment counters exist for FP32 state only",
+            segments_per_launch=segments / prof["n_flight"], avg_launch_ms=flight_s * 1e3,
+            refresh_avg_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]),
+            flight_share=prof["flight_ms"] / (prof["flight_ms"] + prof["refresh_ms"]))
+    elif prof and prof["n_flight"]:
         # the particle kernel (one launch per interval), timed by HIP events on its stream
         flight_s = prof["flight_ms"] / prof["n_flight"] * 1e-3
         segs_launch = segments / prof["n_flight"]
@@ -339,12 +354,12 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if f32 else "f64",
         "data": "synthetic",
         "config": {"workload": "half-nanowire GaN FinFET device MC, 10M superparticles, 3x6x100 subcells, "
                                "Vgs=0 V, Vds=5 V, 1e18 cm^-3, 300 K + 150 K drain hot spot, 1 fs x 10 per step",
                    "particles": args.particles, "substeps_per_step": K, "block": block, "tile": tile,
-                   "graph": bool(args.graph), "variant": args.variant},
+                   "graph": bool(args.graph), "variant": args.variant, "precision": args.precision},
         "real_events_per_s": real / wall,
         "electron_fs_per_s": proc * cfg["dt_fs"] * K / wall,
         "drain_current_A": tal["drain_current_A"],
