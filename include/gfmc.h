@@ -183,7 +183,10 @@ int mc_history(mc_ctx *ctx, int instance, double *h_rows, int max_rows, int *n_r
 int mc_particles(mc_ctx *ctx, int instance, mc_particles_view *out);
 
 /* Copy one instance's particles to / from host arrays of `capacity` entries:
- * k[cap][3], r[cap][3] (FP64), valley, alive (int32), id (uint32). */
+ * k[cap][3], r[cap][3] (FP64), valley, alive (int32), id (uint32).  After a
+ * write the live electrons may sit in any slot: the particle kernel scans all
+ * of the instance's slots until a refresh compacts them (results do not
+ * depend on the slots; electrons are identified by id). */
 int mc_read_particles(mc_ctx *ctx, int instance, double *h_k, double *h_r, int32_t *h_valley, int32_t *h_alive,
                       uint32_t *h_id);
 int mc_write_particles(mc_ctx *ctx, int instance, const double *h_k, const double *h_r, const int32_t *h_valley,
