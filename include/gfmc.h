@@ -210,6 +210,10 @@ int mc_read_tables(mc_ctx *ctx, int instance, double *h_shape, double *h_k4, dou
 int mc_set_launch(mc_ctx *ctx, int block, int tile);
 int mc_get_launch(const mc_ctx *ctx, int *block, int *tile, int *n_tiles);
 
+/* Subcells of the context's grid (nx * ny * nz in device mode, 1 in bulk
+ * mode): the length of every per-subcell array of the API. */
+int mc_get_ncell(const mc_ctx *ctx, int *ncell);
+
 /* Residency of the particle kernel (current variant and precision) at
  * workgroup size `block`: workgroups per compute unit given its registers and
  * LDS histogram, and the device's compute units.  Lets a tuner pick tile
@@ -295,6 +299,39 @@ int sg_predict(sg_ctx *ctx, const float *d_x, int batch, float *d_mean, float *d
 int sg_get_params(sg_ctx *ctx, int member, int layer, float *h_W, float *h_b);
 int sg_set_params(sg_ctx *ctx, int member, int layer, const float *h_W, const float *h_b);
 int sg_get_grads(sg_ctx *ctx, int member, int layer, float *h_dW, float *h_db);
+
+/* One query of sg_predict_or_mc (host memory). */
+typedef struct {
+  const float *h_x;        /* raw features [n_in]: Vgs, Vds, log10 doping (cm^-3), lattice T per subcell */
+  const float *h_box_lo;   /* training box [n_in] of the features; both NULL: no box check */
+  const float *h_box_hi;
+  float calib;             /* calibration factor applied to the ensemble spread */
+  float tol;               /* largest predicted relative error the surrogate may answer with */
+  int32_t warm_substeps;   /* Monte Carlo fallback: sub-steps before the averaging window (>= 0) */
+  int32_t window_substeps; /* sub-steps averaged (>= 1); both multiples of the context's interval */
+} sg_query;
+
+/* The surrogate's answer where it can vouch for it, the Monte Carlo's
+ * elsewhere (coupling paragraph: heat maps for the thermal side).
+ * The network's outputs are read as the encoding [heat shape (ncell),
+ * density shape (ncell), log heat norm, log density norm], so n_out =
+ * 2 ncell + 2; each map is its unit-norm shape times the exponential of its
+ * log-norm.  The predicted relative error is calib x the ensemble spread:
+ * per map the spread of the shape over the norm of its mean, combined in
+ * quadrature with the spread of the log-norm, the larger of the two maps.
+ * When it exceeds tol, or the features leave the training box, the Monte
+ * Carlo runs on instance `instance` of `mc`, which the caller set up for the
+ * same bias point (doping, voltages, temperature map): warm_substeps
+ * sub-steps, a window reset (of the whole context), window_substeps
+ * sub-steps; every instance of `mc` advances.  h_maps [2 ncell] receives
+ * heat (W/m^3) then electron density (m^-3); h_pred_err (may be NULL) the
+ * predicted error; used_mc (may be NULL) 1 if the Monte Carlo answered.
+ * Synchronises both contexts' streams.  MC_E_ARG for bad arguments, an
+ * output width that is not such an encoding, a missing `mc` when the
+ * Monte Carlo is needed, or a grid of `mc` that differs from ncell; the
+ * status of the Monte Carlo calls otherwise. */
+int sg_predict_or_mc(sg_ctx *ctx, mc_ctx *mc, int instance, const sg_query *query, double *h_maps,
+                     float *h_pred_err, int *used_mc);
 
 #ifdef __cplusplus
 }

@@ -1022,6 +1022,12 @@ int mc_get_launch(const mc_ctx* c, int* block, int* tile, int* n_tiles) {
   return MC_OK;
 }
 
+int mc_get_ncell(const mc_ctx* c, int* ncell) {
+  if (!c || !ncell) return MC_E_ARG;
+  *ncell = c->ncell;
+  return MC_OK;
+}
+
 int mc_use_graph(mc_ctx* c, int enable) {
   if (!c) return MC_E_ARG;
   c->use_graph = enable != 0;

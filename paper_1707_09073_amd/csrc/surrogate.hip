@@ -36,6 +36,7 @@ struct SgLayout {
   std::vector<int> K, N;  // per layer
   std::vector<std::vector<LayerOff>> lo;  // [member][layer]
   size_t xmean, xstd, ymean, ystd, X0, preds, dA0, dA1, loss, idx;
+  size_t qx, qm, qs;        // one query of sg_predict_or_mc: features, mean, spread
   int msmall = 0;          // rows of the small-batch inference path
   size_t Asm, gvp;         // its activations [2][member][msmall][width] and split partials
   std::vector<size_t> Z, A;  // per hidden layer: pre-activation (FP32) and activation (BF16)
@@ -95,6 +96,9 @@ SgLayout sg_layout(const sg_config* c) {
   s.msmall = (int)std::min<size_t>(kSmallM, MB);
   s.Asm = L.take(2 * 2 * (size_t)c->ensemble * s.msmall * c->width);
   s.gvp = L.take(4 * (size_t)c->ensemble * kGvMaxSplit * s.msmall * wmax);
+  s.qx = L.take(4 * (size_t)c->n_in);
+  s.qm = L.take(4 * (size_t)c->n_out);
+  s.qs = L.take(4 * (size_t)c->n_out);
   s.idx = 0;
   s.total = L.total;
   return s;
@@ -445,6 +449,56 @@ int sg_predict(sg_ctx* c, const float* d_x, int batch, float* d_mean, float* d_s
   SGCHK(c, hipGetLastError());
   if (c->bad_gemm) return sfail(c, MC_E_ARG, "GEMM operands not 16-byte aligned");
   return MC_OK;
+}
+
+int sg_predict_or_mc(sg_ctx* c, mc_ctx* mc, int instance, const sg_query* q, double* h_maps, float* h_pred_err,
+                     int* used_mc) {
+  if (!c || !q || !q->h_x || !h_maps || !(q->calib >= 0.0f)) return sfail(c, MC_E_ARG, "bad argument");
+  const int n_in = c->c.n_in, n_out = c->c.n_out;
+  if (n_out < 4 || (n_out - 2) % 2)
+    return sfail(c, MC_E_ARG, "outputs are not [shape, shape, log-norm, log-norm] of two maps");
+  const int nc = (n_out - 2) / 2;
+  const SgLayout& s = c->s;
+  SGCHK(c, hipMemcpyAsync(c->ws + s.qx, q->h_x, 4 * (size_t)n_in, hipMemcpyHostToDevice, c->st));
+  int rc = sg_predict(c, c->p<float>(s.qx), 1, c->p<float>(s.qm), c->p<float>(s.qs));
+  if (rc != MC_OK) return rc;
+  std::vector<float> m(n_out), sd(n_out);
+  SGCHK(c, hipMemcpyAsync(m.data(), c->ws + s.qm, 4 * (size_t)n_out, hipMemcpyDeviceToHost, c->st));
+  SGCHK(c, hipMemcpyAsync(sd.data(), c->ws + s.qs, 4 * (size_t)n_out, hipMemcpyDeviceToHost, c->st));
+  SGCHK(c, hipStreamSynchronize(c->st));
+  // decoded maps and the spread of each: shape spread over shape norm, in
+  // quadrature with the log-norm spread; the larger map's
+  double spread = 0.0;
+  for (int k = 0; k < 2; ++k) {
+    double nm = 0.0, ns = 0.0;
+    for (int i = 0; i < nc; ++i) {
+      nm += (double)m[k * nc + i] * m[k * nc + i];
+      ns += (double)sd[k * nc + i] * sd[k * nc + i];
+    }
+    spread = std::max(spread, std::hypot(std::sqrt(ns) / std::max(std::sqrt(nm), 1e-300), (double)sd[2 * nc + k]));
+    const double scale = std::exp((double)m[2 * nc + k]);
+    for (int i = 0; i < nc; ++i) h_maps[k * nc + i] = (double)m[k * nc + i] * scale;
+  }
+  const double perr = (double)q->calib * spread;
+  bool inside = true;
+  if (q->h_box_lo && q->h_box_hi)
+    for (int j = 0; j < n_in; ++j) {
+      const double lo = q->h_box_lo[j], hi = q->h_box_hi[j], pad = 1e-6 * std::max(1.0, std::fabs(hi - lo));
+      if (!(q->h_x[j] >= lo - pad && q->h_x[j] <= hi + pad)) inside = false;
+    }
+  const bool fall = !(perr <= (double)q->tol) || !inside;  // a NaN error falls back too
+  if (h_pred_err) *h_pred_err = (float)perr;
+  if (used_mc) *used_mc = fall ? 1 : 0;
+  if (!fall) return MC_OK;
+  int mnc = 0;
+  if (!mc || mc_get_ncell(mc, &mnc) != MC_OK) return sfail(c, MC_E_ARG, "the Monte Carlo is needed: no context given");
+  if (mnc != nc) return sfail(c, MC_E_ARG, "the Monte Carlo context's grid differs from the surrogate's maps");
+  if (q->warm_substeps < 0 || q->window_substeps < 1) return sfail(c, MC_E_ARG, "bad Monte Carlo window");
+  if ((rc = mc_step(mc, q->warm_substeps)) != MC_OK) return rc;
+  mc_tally_out t;
+  if ((rc = mc_tally(mc, instance, &t, 1)) != MC_OK) return rc;
+  if ((rc = mc_step(mc, q->window_substeps)) != MC_OK) return rc;
+  return mc_maps(mc, instance, nullptr, nullptr, h_maps, h_maps + nc);
 }
 
 int sg_get_params(sg_ctx* c, int member, int layer, float* h_W, float* h_b) {

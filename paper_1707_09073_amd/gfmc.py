@@ -53,7 +53,7 @@ class McParticlesView(C.Structure):
 EXPORTS = ["mc_status_string", "mc_last_error", "mc_workspace_bytes", "mc_init", "mc_destroy",
            "mc_set_lattice_temperature", "mc_set_tables", "mc_step", "poisson_update", "mc_tally", "mc_maps",
            "mc_history", "mc_particles", "mc_read_particles", "mc_write_particles", "mc_read_fields",
-           "mc_read_tables", "mc_set_launch", "mc_get_launch", "mc_occupancy", "mc_set_variant", "mc_use_graph", "mc_profile", "mc_profile_read",
+           "mc_read_tables", "mc_set_launch", "mc_get_launch", "mc_get_ncell", "mc_occupancy", "mc_set_variant", "mc_use_graph", "mc_profile", "mc_profile_read",
            "mc_checkpoint", "mc_restore"]
 
 _lib = None
@@ -87,6 +87,7 @@ def lib():
         L.mc_read_tables.argtypes = [vp, C.c_int, dp, dp, dp, dp]
         L.mc_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.mc_get_launch.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.mc_get_ncell.argtypes = [vp, C.POINTER(C.c_int)]
         L.mc_occupancy.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.mc_use_graph.argtypes = [vp, C.c_int]
         L.mc_set_variant.argtypes = [vp, C.c_int]
@@ -279,6 +280,11 @@ class Ensemble:
         self._chk(lib().mc_get_launch(self._ctx, C.byref(b), C.byref(t), C.byref(n)), "mc_get_launch")
         return b.value, t.value, n.value
 
+    def mc_get_ncell(self) -> int:
+        n = C.c_int()
+        self._chk(lib().mc_get_ncell(self._ctx, C.byref(n)), "mc_get_ncell")
+        return n.value
+
     def mc_occupancy(self, block: int):
         """(resident workgroups per compute unit, compute units) of the particle kernel."""
         w, n = C.c_int(), C.c_int()
@@ -325,9 +331,14 @@ class SgConfig(C.Structure):
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("weight_decay", C.c_float)]
 
 
+class SgQuery(C.Structure):
+    _fields_ = [("h_x", C.c_void_p), ("h_box_lo", C.c_void_p), ("h_box_hi", C.c_void_p), ("calib", C.c_float),
+                ("tol", C.c_float), ("warm_substeps", C.c_int32), ("window_substeps", C.c_int32)]
+
+
 SG_EXPORTS = ["sg_workspace_bytes", "sg_init", "sg_destroy", "sg_last_error", "sg_layer_dims",
               "sg_set_normalization", "sg_forward", "sg_backward", "sg_adam", "sg_train_step", "sg_predict",
-              "sg_get_params", "sg_set_params", "sg_get_grads"]
+              "sg_get_params", "sg_set_params", "sg_get_grads", "sg_predict_or_mc"]
 EXPORTS = EXPORTS + SG_EXPORTS
 
 _sg_ready = False
@@ -352,6 +363,8 @@ def _sg_lib():
         L.sg_get_params.argtypes = [vp, C.c_int, C.c_int, fp, fp]
         L.sg_set_params.argtypes = [vp, C.c_int, C.c_int, fp, fp]
         L.sg_get_grads.argtypes = [vp, C.c_int, C.c_int, fp, fp]
+        L.sg_predict_or_mc.argtypes = [vp, vp, C.c_int, C.POINTER(SgQuery), C.POINTER(C.c_double), fp,
+                                       C.POINTER(C.c_int)]
         for n in SG_EXPORTS:
             if n not in ("sg_workspace_bytes", "sg_last_error"):
                 getattr(L, n).restype = C.c_int
@@ -453,6 +466,28 @@ class SurrogateNet:
         # again on torch's stream) as soon as this returns
         self._out()
         return loss.value if want_loss else None
+
+    def sg_predict_or_mc(self, x, calib: float, tol: float, ens=None, instance: int = 0, warm_substeps: int = 0,
+                         window_substeps: int = 1, box=None):
+        """One query (host FP32 features): the maps [2 ncell] (heat W/m^3, then
+        density m^-3), the predicted relative error, and whether the Monte
+        Carlo context `ens` (set up for the same bias point) answered."""
+        x = np.ascontiguousarray(x, np.float32)
+        assert x.size == self.n_in
+        lo = hi = None
+        if box is not None:
+            lo = np.ascontiguousarray(box[0], np.float32)
+            hi = np.ascontiguousarray(box[1], np.float32)
+            assert lo.size == self.n_in and hi.size == self.n_in
+        q = SgQuery(x.ctypes.data, None if lo is None else lo.ctypes.data, None if hi is None else hi.ctypes.data,
+                    float(calib), float(tol), int(warm_substeps), int(window_substeps))
+        maps = np.zeros(self.n_out - 2)
+        perr, used = C.c_float(), C.c_int()
+        self._in()
+        self._chk(_sg_lib().sg_predict_or_mc(self._ctx, None if ens is None else ens._ctx, int(instance), C.byref(q),
+                                             maps.ctypes.data_as(C.POINTER(C.c_double)), C.byref(perr),
+                                             C.byref(used)), "sg_predict_or_mc")
+        return maps, perr.value, bool(used.value)
 
     def sg_predict(self, x, mean_out, std_out=None):
         b = x.shape[0]

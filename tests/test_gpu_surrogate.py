@@ -169,3 +169,74 @@ def test_small_batch_predict_matches_oracle_and_gemm_path(torch_mod, shape):
         assert _rel(s, std_o[lo:hi]) <= 2e-2, (lo, hi, _rel(s, std_o[lo:hi]))
         assert _rel(m, big_m[lo:hi]) <= 1e-3
         assert _rel(s, big_s[lo:hi]) <= 2e-2
+
+
+def test_predict_or_mc_answers_from_surrogate_or_monte_carlo(torch_mod):
+    """sg_predict_or_mc on a 37 x 2 x 5 device grid.  Within tolerance and the
+    training box: the maps decoded from sg_predict's ensemble mean and the
+    predicted error (calibration x spread), both formed here on the host.
+    Outside the box, or beyond the tolerance: the Monte Carlo of the given
+    context, equal to the same runs through the mc_* calls.  A missing
+    context, or one of another grid, is refused when the Monte Carlo is
+    needed."""
+    from paper_1707_09073_amd import gfmc, workloads as W
+    torch = torch_mod
+    cells, L = (37, 2, 5), (370.0, 40.0, 100.0)
+    nc = cells[0] * cells[1] * cells[2]
+    cfg = W.device_config(n_particles=7777, precision="fp32", Vds=3.0, Vgs=-1.0, n_cells=cells, L_nm=L)
+    K = cfg["substeps"]
+    n_in, n_out = 3 + nc, 2 * nc + 2
+    net = gfmc.SurrogateNet(n_in, n_out, width=64, depth=2, ensemble=3, max_batch=8, seed=5)
+    rng = np.random.default_rng(5)
+    xm = np.concatenate([[-1.0, 3.0, 18.0], np.full(nc, 300.0)])
+    xs = np.concatenate([[1.0, 2.0, 0.5], np.full(nc, 20.0)])
+    ym = np.zeros(n_out)
+    ym[-2:] = [10.0, 20.0]  # log-norms of the two maps
+    ys = np.full(n_out, 0.05)
+    ys[-2:] = 0.1
+    net.sg_set_normalization(xm, xs, ym, ys)
+    x = (xm + 0.1 * xs * rng.normal(size=n_in)).astype(np.float32)
+    _say("predict_or_mc: surrogate answer")
+    xd = torch.tensor(x[None], device="cuda")
+    m = torch.empty((1, n_out), device="cuda")
+    sd = torch.empty_like(m)
+    net.sg_predict(xd, m, sd)
+    m = m.cpu().numpy()[0].astype(np.float64)
+    sd = sd.cpu().numpy()[0].astype(np.float64)
+    ref_maps = np.concatenate([m[:nc] * np.exp(m[2 * nc]), m[nc:2 * nc] * np.exp(m[2 * nc + 1])])
+    spread = max(np.hypot(np.linalg.norm(sd[k * nc:(k + 1) * nc]) / np.linalg.norm(m[k * nc:(k + 1) * nc]),
+                          sd[2 * nc + k]) for k in range(2))
+    calib = 1.7
+    maps, perr, used = net.sg_predict_or_mc(x, calib, tol=1e30)
+    assert not used
+    assert _rel(maps, ref_maps) <= 1e-6
+    assert abs(perr - calib * spread) <= 1e-5 * calib * spread
+    _say("predict_or_mc: outside the training box")
+    ens, ref = gfmc.Ensemble(cfg), gfmc.Ensemble(cfg)
+    assert ens.mc_get_ncell() == nc
+    box = (x + 1.0, x + 2.0)  # every feature lies below the box
+    maps, _, used = net.sg_predict_or_mc(x, calib, tol=1e30, ens=ens, warm_substeps=5 * K, window_substeps=5 * K,
+                                         box=box)
+    assert used
+    ref.mc_step(5 * K)
+    ref.mc_tally(0, reset_window=True)
+    ref.mc_step(5 * K)
+    r = ref.mc_maps(0)
+    assert np.array_equal(maps[:nc], r["heat_Wm3"]) and np.array_equal(maps[nc:], r["density_m3"])
+    _say("predict_or_mc: beyond the tolerance")
+    maps, perr, used = net.sg_predict_or_mc(x, calib, tol=0.0, ens=ens, warm_substeps=0, window_substeps=3 * K)
+    assert used and perr > 0.0
+    ref.mc_tally(0, reset_window=True)
+    ref.mc_step(3 * K)
+    r = ref.mc_maps(0)
+    assert np.array_equal(maps[:nc], r["heat_Wm3"]) and np.array_equal(maps[nc:], r["density_m3"])
+    _say("predict_or_mc: refused contexts")
+    with pytest.raises(gfmc.MCError):
+        net.sg_predict_or_mc(x, calib, tol=0.0)
+    other = gfmc.Ensemble(W.device_config(n_particles=4000, precision="fp32", n_cells=(20, 2, 2),
+                                          L_nm=(200.0, 20.0, 20.0)))
+    with pytest.raises(gfmc.MCError):
+        net.sg_predict_or_mc(x, calib, tol=0.0, ens=other, window_substeps=K)
+    for e in (ens, ref, other):
+        e.close()
+    net.close()
