@@ -110,10 +110,22 @@ typedef struct {
   uint64_t *dens_sum;  /* [cell] */
   or_counts tot;
   uint32_t win_intervals;
-  /* bulk history: rows of 8 doubles */
+  /* per-interval history, rows of 8 doubles (layout differs by mode; see
+   * record_bulk and record_device) */
   double *hist;
   int hist_cap, hist_len;
   int err_capacity, err_nan;
+  /* energy carried through the contacts (device mode): the total energy
+   * (kinetic plus valley minimum, eV) of each electron that left in the
+   * current interval, per slot, summed in slot order after the interval */
+  double *eexit;
+  signed char *xside; /* contact left through in this interval, -1 none */
+  double e_exit[2], e_inj[2]; /* window sums, eV, source and drain */
+  double *ework;              /* per slot: kinetic energy gained in free flight this interval, eV */
+  double e_work;              /* window sum of ework, eV */
+  double *eabs;               /* per slot: energy gained in phonon absorptions this interval, eV */
+  double e_abs;               /* window sum of eabs, eV */
+  double e_ens0;              /* ensemble total energy at the window start, eV */
 } or_ctx;
 
 /* ------------------------------------------------------------------ */
@@ -617,6 +629,17 @@ static int scatter(const or_ctx *X, double k[3], int *pv, int cell, const uint32
   return m;
 }
 
+double or_ensemble_energy(const or_ctx *X);
+
+/* total energy of an electron: kinetic (Kane) plus its valley minimum, eV */
+static double total_energy(const or_ctx *X, const double k[3], int v) { return energy_of_k(X, k, v) + X->c.E_c[v]; }
+
+/* an electron of slot p left through contact `side` with valley v */
+static void note_exit(or_ctx *X, int p, int side, int v) {
+  X->eexit[p] = total_energy(X, X->k + 3 * p, v);
+  X->xside[p] = (signed char)side;
+}
+
 /* One flight interval [0, K dt) of particle p (the field is constant over an
  * interval, so the remaining flight time is drawn afresh at its start; the
  * Poisson process of rate Gamma_v is memoryless). */
@@ -627,27 +650,38 @@ static void fly(or_ctx *X, int p, uint32_t n_int, or_counts *tl, uint64_t *heat)
   uint32_t idp = X->id[p];
   uint32_t w[4];
   uint32_t j = 0;
+  double work = 0.0;     /* kinetic energy gained in the field over the flights, eV */
+  double absorbed = 0.0; /* energy gained in phonon absorptions, eV */
   rng(X, idp, n_int, 0u, 0u, w);
   double t = 0.0;
   double tau = -log(u01(w[0])) / X->gamma[v];
   for (;;) {
     int cell = cell_of(X, r);
     const double *F = X->c.mode == 1 ? X->field + 3 * cell : X->c.F_bulk;
+    double e0 = energy_of_k(X, k, v);
     if (t + tau >= TP) {
       int ex = drift(X, k, r, v, TP - t, F, tl);
-      if (ex >= 0) { X->alive[p] = 0; tl->exits[ex]++; }
+      work += energy_of_k(X, k, v) - e0;
+      if (ex >= 0) { X->alive[p] = 0; tl->exits[ex]++; note_exit(X, p, ex, v); }
       break;
     }
     int ex = drift(X, k, r, v, tau, F, tl);
-    if (ex >= 0) { X->alive[p] = 0; tl->exits[ex]++; break; }
+    work += energy_of_k(X, k, v) - e0;
+    if (ex >= 0) { X->alive[p] = 0; tl->exits[ex]++; note_exit(X, p, ex, v); break; }
     t += tau;
     ++j;
     rng(X, idp, n_int, j, 0u, w);
     cell = cell_of(X, r);
-    scatter(X, k, &v, cell, w, tl, heat);
+    double et = total_energy(X, k, v);
+    int m = scatter(X, k, &v, cell, w, tl, heat);
+    /* energy taken from absorbed phonons, from the electron's own energy
+     * change (independent of the event counts) */
+    if (m == OR_POP_AB || (m >= OR_IV0 && ((m - OR_IV0) & 1) == 0)) absorbed += total_energy(X, k, v) - et;
     tau = -log(u01(w[0])) / X->gamma[v];
   }
   X->valley[p] = v;
+  X->ework[p] = work;
+  X->eabs[p] = absorbed;
   if (!(isfinite(k[0]) && isfinite(k[1]) && isfinite(k[2]))) X->err_nan = 1;
 }
 
@@ -698,6 +732,7 @@ static void inject(or_ctx *X, uint32_t u) {
         X->valley[slot] = 0;
         X->alive[slot] = 1;
         X->id[slot] = X->next_id + q;
+        X->e_inj[side] += total_energy(X, X->k + 3 * slot, 0);
         ++q;
         X->count[cell]++;
         X->tot.injections[side]++;
@@ -750,10 +785,17 @@ or_ctx *or_create(const or_config *cfg, const double *T_cells) {
   X->dens_sum = calloc(X->ncell, sizeof(uint64_t));
   X->hist_cap = 1 << 16;
   X->hist = calloc((size_t)X->hist_cap * 8, sizeof(double));
+  X->eexit = calloc(cap, sizeof(double));
+  X->ework = calloc(cap, sizeof(double));
+  X->eabs = calloc(cap, sizeof(double));
+  X->xside = malloc(cap);
+  memset(X->xside, -1, cap);
   build_tables(X);
   cell_factors(X);
   compute_gamma(X);
   init_particles(X);
+  /* the window starts before the first contact refill, which it counts */
+  X->e_ens0 = or_ensemble_energy(X);
   if (cfg->mode == 1) {
     poisson_setup(X);
     or_poisson_update(X);
@@ -767,6 +809,7 @@ void or_destroy(or_ctx *X) {
   free(X->k); free(X->r); free(X->valley); free(X->alive); free(X->id);
   free(X->phi); free(X->field); free(X->bc_rhs); free(X->Lband); free(X->count);
   free(X->heat); free(X->dens_sum); free(X->hist);
+  free(X->eexit); free(X->xside); free(X->ework); free(X->eabs);
   free(X);
 }
 
@@ -785,6 +828,42 @@ static void record_bulk(or_ctx *X) {
     row[5 + v] += 1.0;
   }
   X->hist_len++;
+}
+
+/* Device-mode row after each refresh: the window's cumulative exits and
+ * injections (source, drain), the electrons present, the mean potential (V)
+ * and the root-mean-square field magnitude (V/nm) over the subcells, and the
+ * number of intervals done.  The drain current and the field are the two
+ * quantities whose constancy marks the steady state (electron MC
+ * paragraph). */
+static void record_device(or_ctx *X) {
+  if (X->hist_len >= X->hist_cap) return;
+  double *row = X->hist + (size_t)X->hist_len * 8;
+  double n = 0.0, sphi = 0.0, sf2 = 0.0;
+  for (int i = 0; i < X->ncell; ++i) {
+    n += (double)X->count[i];
+    sphi += X->phi[i];
+    const double *F = X->field + 3 * i;
+    sf2 += F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+  }
+  row[0] = (double)X->tot.exits[0];
+  row[1] = (double)X->tot.exits[1];
+  row[2] = (double)X->tot.injections[0];
+  row[3] = (double)X->tot.injections[1];
+  row[4] = n;
+  row[5] = sphi / X->ncell;
+  row[6] = sqrt(sf2 / X->ncell);
+  row[7] = (double)X->n_done;
+  X->hist_len++;
+}
+
+/* total energy (kinetic plus valley minimum, eV) of the live electrons,
+ * summed in slot order */
+double or_ensemble_energy(const or_ctx *X) {
+  double e = 0.0;
+  for (int p = 0; p < X->c.capacity; ++p)
+    if (X->alive[p]) e += total_energy(X, X->k + 3 * p, X->valley[p]);
+  return e;
 }
 
 /* Advance n_intervals flight intervals (each K sub-steps), with a deposit,
@@ -814,16 +893,31 @@ int or_run(or_ctx *X, int n_intervals, int n_threads) {
 #endif
       fly(X, p, n_int, tl + t, heat[t]);
     }
+    /* integer counts merged after every interval (any order gives the same
+     * sums); exit energies in slot order, before the refill reuses slots */
+    for (int t = 0; t < nt; ++t) {
+      add_counts(&X->tot, tl + t);
+      memset(tl + t, 0, sizeof(or_counts));
+    }
+    for (int p = 0; p < cap; ++p) {
+      X->e_work += X->ework[p];
+      X->e_abs += X->eabs[p];
+      X->ework[p] = X->eabs[p] = 0.0;
+      if (X->xside[p] >= 0) {
+        X->e_exit[(int)X->xside[p]] += X->eexit[p];
+        X->xside[p] = -1;
+      }
+    }
     X->n_done++;
     if (X->c.mode == 0) record_bulk(X);
     else {
       or_poisson_update(X);
       for (int i = 0; i < X->ncell; ++i) X->dens_sum[i] += X->count[i];
+      record_device(X);
     }
     X->win_intervals++;
   }
   for (int t = 0; t < nt; ++t) {
-    add_counts(&X->tot, tl + t);
     for (size_t i = 0; i < (size_t)X->ncell * 4; ++i) X->heat[i] += heat[t][i];
     free(heat[t]);
   }
@@ -838,6 +932,8 @@ void or_reset_window(or_ctx *X) {
   memset(X->dens_sum, 0, sizeof(uint64_t) * X->ncell);
   X->win_intervals = 0;
   X->hist_len = 0;
+  X->e_exit[0] = X->e_exit[1] = X->e_inj[0] = X->e_inj[1] = X->e_work = X->e_abs = 0.0;
+  X->e_ens0 = or_ensemble_energy(X);
 }
 
 void or_set_temperature(or_ctx *X, const double *T_cells) {
@@ -910,6 +1006,128 @@ int or_history(const or_ctx *X, double *rows, int max_rows) {
   int n = X->hist_len < max_rows ? X->hist_len : max_rows;
   memcpy(rows, X->hist, sizeof(double) * 8 * n);
   return n;
+}
+
+/* ------------------------------------------------------------------ */
+/* Observables of the averaging window (electron MC paragraph: heat     */
+/* counted per subcell, the steady state reached once current and field */
+/* stop changing; the thermal-resistance passage: emitted phonon energy) */
+/* ------------------------------------------------------------------ */
+enum { OR_STEADY_BLOCKS = 10 };
+
+/* Steady-state test of one per-interval series s[0..m): the last 2h values
+ * (h = m/2) form two halves; each half's mean and its standard error come
+ * from 10 batch means of h/10 consecutive values.  Steady (1) when the two
+ * means differ by at most 3 combined standard errors, 0 otherwise, -1 when
+ * a half holds fewer than 10 values.  out = {mean1, mean2, se1, se2}. */
+int or_steady_test(const double *s, int m, double out[4]) {
+  int h = m / 2, b = h / OR_STEADY_BLOCKS;
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  if (b < 1) return -1;
+  for (int half = 0; half < 2; ++half) {
+    int start = m - 2 * h + half * h;
+    double bm[OR_STEADY_BLOCKS], mu = 0.0;
+    for (int j = 0; j < OR_STEADY_BLOCKS; ++j) {
+      double a = 0.0;
+      for (int i = 0; i < b; ++i) a += s[start + j * b + i];
+      bm[j] = a / b;
+      mu += bm[j];
+    }
+    mu /= OR_STEADY_BLOCKS;
+    double var = 0.0;
+    for (int j = 0; j < OR_STEADY_BLOCKS; ++j) var += (bm[j] - mu) * (bm[j] - mu);
+    out[half] = mu;
+    out[2 + half] = sqrt(var / (OR_STEADY_BLOCKS * (OR_STEADY_BLOCKS - 1.0)));
+  }
+  return fabs(out[0] - out[1]) <= 3.0 * sqrt(out[2] * out[2] + out[3] * out[3]) ? 1 : 0;
+}
+
+typedef struct {
+  int intervals;
+  double t_window_s;
+  /* device mode */
+  double I_D, I_S;           /* A: e w (exits - injections) / t at the drain and source contacts */
+  double P_heat_W, P_emit_W; /* net phonon emission and emission only (E_Emit / t), whole domain */
+  double E_out_J[2], E_in_J[2]; /* total energy carried out of / into the domain, source and drain */
+  double dE_ens_J;           /* change of the ensemble's total energy over the window */
+  double W_field_J;          /* kinetic energy the electrons gained in free flight (work of the field) */
+  double E_abs_J;            /* energy the electrons took from absorbed phonons */
+  /* bulk mode */
+  double v_drift_ms[3], mean_E_eV, valley_frac[3];
+  /* steady state of the two series (device: drain current per interval, rms
+   * field; bulk: mean v_z per interval, mean energy) */
+  double half_mean[2][2], half_se[2][2];
+  int steady; /* 1 both steady, 0 either not, -1 window too short */
+} or_obs;
+
+/* Per-subcell maps of the window: net phonon-emission power density and
+ * emission-only power density (W/m^3), electron density (1/m^3). */
+void or_power_maps(const or_ctx *X, double *q_net, double *q_emit, double *dens_m3) {
+  double t = X->win_intervals * X->c.substeps * X->c.dt_fs * 1e-15;
+  double vc = X->Vc * 1e-27, hlo = X->c.hw_lo_eV, hiv = X->c.hw_iv_eV;
+  for (int i = 0; i < X->ncell; ++i) {
+    const uint64_t *h = X->heat + 4 * i; /* LO emit, LO absorb, iv emit, iv absorb */
+    double e_net = hlo * ((double)h[0] - (double)h[1]) + hiv * ((double)h[2] - (double)h[3]);
+    double e_em = hlo * (double)h[0] + hiv * (double)h[2];
+    if (q_net) q_net[i] = t > 0.0 ? X->w * OR_QE * e_net / (vc * t) : 0.0;
+    if (q_emit) q_emit[i] = t > 0.0 ? X->w * OR_QE * e_em / (vc * t) : 0.0;
+    if (dens_m3) dens_m3[i] = X->win_intervals ? X->w * (double)X->dens_sum[i] / X->win_intervals / vc : 0.0;
+  }
+}
+
+void or_observables(const or_ctx *X, or_obs *o) {
+  memset(o, 0, sizeof(*o));
+  int m = X->hist_len;
+  double TP = X->c.substeps * X->c.dt_fs * 1e-15;
+  o->intervals = (int)X->win_intervals;
+  o->t_window_s = X->win_intervals * TP;
+  double *s1 = calloc(m > 0 ? m : 1, sizeof(double)), *s2 = calloc(m > 0 ? m : 1, sizeof(double));
+  if (X->c.mode == 1) {
+    double t = o->t_window_s, wq = X->w * OR_QE;
+    const or_counts *c = &X->tot;
+    if (t > 0.0) {
+      o->I_D = wq * ((double)c->exits[1] - (double)c->injections[1]) / t;
+      o->I_S = wq * ((double)c->exits[0] - (double)c->injections[0]) / t;
+      double en = 0.0, ee = 0.0;
+      for (int i = 0; i < X->ncell; ++i) {
+        const uint64_t *h = X->heat + 4 * i;
+        en += X->c.hw_lo_eV * ((double)h[0] - (double)h[1]) + X->c.hw_iv_eV * ((double)h[2] - (double)h[3]);
+        ee += X->c.hw_lo_eV * (double)h[0] + X->c.hw_iv_eV * (double)h[2];
+      }
+      o->P_heat_W = wq * en / t;
+      o->P_emit_W = wq * ee / t;
+    }
+    for (int sd = 0; sd < 2; ++sd) { o->E_out_J[sd] = wq * X->e_exit[sd]; o->E_in_J[sd] = wq * X->e_inj[sd]; }
+    o->dE_ens_J = wq * (or_ensemble_energy(X) - X->e_ens0);
+    o->W_field_J = wq * X->e_work;
+    o->E_abs_J = wq * X->e_abs;
+    /* per-interval drain current from the cumulative counts of the rows */
+    for (int n = 0; n < m; ++n) {
+      const double *r = X->hist + 8 * (size_t)n, *q = n > 0 ? X->hist + 8 * (size_t)(n - 1) : NULL;
+      double dex = r[1] - (q ? q[1] : 0.0), dinj = r[3] - (q ? q[3] : 0.0);
+      s1[n] = wq * (dex - dinj) / TP;
+      s2[n] = r[6];
+    }
+  } else {
+    for (int n = 0; n < m; ++n) {
+      const double *r = X->hist + 8 * (size_t)n;
+      double na = r[0] > 0.0 ? r[0] : 1.0;
+      for (int d = 0; d < 3; ++d) o->v_drift_ms[d] += r[1 + d] / na * 1e6 / m; /* nm/fs -> m/s */
+      o->mean_E_eV += r[4] / na / m;
+      for (int v = 0; v < 3; ++v) o->valley_frac[v] += r[5 + v] / na / m;
+      s1[n] = r[3] / na * 1e6;
+      s2[n] = r[4] / na;
+    }
+  }
+  double a[4], b[4];
+  int f1 = or_steady_test(s1, m, a), f2 = or_steady_test(s2, m, b);
+  for (int h = 0; h < 2; ++h) {
+    o->half_mean[0][h] = a[h]; o->half_se[0][h] = a[2 + h];
+    o->half_mean[1][h] = b[h]; o->half_se[1][h] = b[2 + h];
+  }
+  o->steady = (f1 < 0 || f2 < 0) ? -1 : (f1 && f2);
+  free(s1);
+  free(s2);
 }
 
 /* Solve the device Poisson problem for an arbitrary charge per cell (C);

@@ -35,6 +35,16 @@ class OrConfig(C.Structure):
     ]
 
 
+class OrObs(C.Structure):
+    _fields_ = [
+        ("intervals", C.c_int), ("pad", C.c_int), ("t_window_s", C.c_double),
+        ("I_D", C.c_double), ("I_S", C.c_double), ("P_heat_W", C.c_double), ("P_emit_W", C.c_double),
+        ("E_out_J", C.c_double * 2), ("E_in_J", C.c_double * 2), ("dE_ens_J", C.c_double), ("W_field_J", C.c_double), ("E_abs_J", C.c_double),
+        ("v_drift_ms", C.c_double * 3), ("mean_E_eV", C.c_double), ("valley_frac", C.c_double * 3),
+        ("half_mean", C.c_double * 4), ("half_se", C.c_double * 4), ("steady", C.c_int),
+    ]
+
+
 def build(force: bool = False) -> str:
     """Compile the reference with gcc (plain -O2: no fast-math, no FMA contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -95,6 +105,12 @@ def lib():
         L.or_sample_selection.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_uint32, C.c_int, u64p]
         L.or_scatter_once.argtypes = [C.c_void_p, dp, i32p, C.c_int, u32p]
         L.or_scatter_once.restype = C.c_int
+        L.or_steady_test.argtypes = [dp, C.c_int, dp]
+        L.or_steady_test.restype = C.c_int
+        L.or_power_maps.argtypes = [C.c_void_p, dp, dp, dp]
+        L.or_observables.argtypes = [C.c_void_p, C.POINTER(OrObs)]
+        L.or_ensemble_energy.argtypes = [C.c_void_p]
+        L.or_ensemble_energy.restype = C.c_double
         _lib = L
     return _lib
 
@@ -152,6 +168,15 @@ def rate(cfg: dict, valley: int, mech: int, E_eV: float, T: float) -> float:
 def dos(cfg: dict, valley: int, E_eV: float) -> float:
     c = make_config(cfg)
     return lib().or_dos(C.byref(c), int(valley), float(E_eV))
+
+
+def steady_test(series) -> tuple[int, np.ndarray]:
+    """Steady-state test of a per-interval series: (flag, [mean1, mean2,
+    se1, se2]) for the two halves of its last 2*(m//2) values."""
+    a = np.ascontiguousarray(series, dtype=np.float64)
+    out = np.zeros(4)
+    f = lib().or_steady_test(_p(a, C.c_double), int(a.size), _p(out, C.c_double))
+    return f, out
 
 
 def onb(n):
@@ -271,6 +296,26 @@ class Oracle:
         rows = np.zeros((max_rows, 8))
         n = lib().or_history(self._h, _p(rows, C.c_double), int(max_rows))
         return rows[:n].copy()
+
+    def power_maps(self):
+        """Window maps: net and emission-only phonon power density (W/m^3),
+        electron density (1/m^3)."""
+        qn, qe, n = np.zeros(self.ncell), np.zeros(self.ncell), np.zeros(self.ncell)
+        lib().or_power_maps(self._h, _p(qn, C.c_double), _p(qe, C.c_double), _p(n, C.c_double))
+        return qn, qe, n
+
+    def observables(self) -> dict:
+        o = OrObs()
+        lib().or_observables(self._h, C.byref(o))
+        return dict(intervals=o.intervals, t_window_s=o.t_window_s, I_D=o.I_D, I_S=o.I_S,
+                    P_heat_W=o.P_heat_W, P_emit_W=o.P_emit_W, E_out_J=np.array(o.E_out_J[:]),
+                    E_in_J=np.array(o.E_in_J[:]), dE_ens_J=o.dE_ens_J, W_field_J=o.W_field_J, E_abs_J=o.E_abs_J, v_drift_ms=np.array(o.v_drift_ms[:]),
+                    mean_E_eV=o.mean_E_eV, valley_frac=np.array(o.valley_frac[:]),
+                    half_mean=np.array(o.half_mean[:]).reshape(2, 2), half_se=np.array(o.half_se[:]).reshape(2, 2),
+                    steady=o.steady)
+
+    def ensemble_energy_eV(self) -> float:
+        return lib().or_ensemble_energy(self._h)
 
     def poisson_solve(self, charge_C):
         q = np.ascontiguousarray(charge_C, dtype=np.float64)
