@@ -88,3 +88,48 @@ def adam_step(w, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
     v = b2 * v + (1 - b2) * g * g
     w = w - lr * ((m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps) + wd * w)
     return w, m, v
+
+
+# ---------------------------------------------------------------------------
+# Predict-or-Monte-Carlo decision (the surrogate's answer for the thermal side
+# of the hybrid iteration, coupling paragraph).  The network's outputs are the
+# encoding [heat shape (ncell), density shape (ncell), log heat norm, log
+# density norm]; definitions as documented for the library's entry point.
+# ---------------------------------------------------------------------------
+def ensemble_mean_spread(preds):
+    """Mean and sample standard deviation (divisor members - 1) over the
+    first axis (members) of de-normalised predictions [E, batch, n_out]."""
+    p = np.asarray(preds, np.float64)
+    if p.shape[0] < 2:
+        return p.mean(0), np.zeros(p.shape[1:])
+    return p.mean(0), p.std(0, ddof=1)
+
+
+def decode_maps(mean, ncell):
+    """Per-subcell heat and density maps [batch, 2 ncell] from the mean
+    encoding: each map is its shape times exp(its log-norm)."""
+    m = np.atleast_2d(np.asarray(mean, np.float64))
+    out = np.empty((m.shape[0], 2 * ncell))
+    for k in range(2):
+        out[:, k * ncell:(k + 1) * ncell] = m[:, k * ncell:(k + 1) * ncell] * np.exp(m[:, 2 * ncell + k])[:, None]
+    return out
+
+
+def predicted_error(mean, spread, ncell, calib):
+    """calib x the larger over the two maps of hypot(|spread of the shape| /
+    |mean shape|, spread of the log-norm), norms over the subcells."""
+    m = np.atleast_2d(np.asarray(mean, np.float64))
+    s = np.atleast_2d(np.asarray(spread, np.float64))
+    err = np.zeros(m.shape[0])
+    for k in range(2):
+        sl = slice(k * ncell, (k + 1) * ncell)
+        rel = np.linalg.norm(s[:, sl], axis=1) / np.maximum(np.linalg.norm(m[:, sl], axis=1), 1e-300)
+        err = np.maximum(err, np.hypot(rel, s[:, 2 * ncell + k]))
+    return calib * err
+
+
+def inside_box(x, lo, hi):
+    """Every feature within [lo, hi] widened by 1e-6 max(1, hi - lo)."""
+    x, lo, hi = (np.asarray(a, np.float64) for a in (x, lo, hi))
+    pad = 1e-6 * np.maximum(1.0, np.abs(hi - lo))
+    return bool(np.all((x >= lo - pad) & (x <= hi + pad)))

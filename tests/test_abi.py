@@ -52,6 +52,8 @@ int main(void) {
          sizeof(mc_particles_view), offsetof(mc_config, seed));
   printf("%zu %zu %zu %zu\n", offsetof(mc_config, n_cells), offsetof(mc_config, Vds),
          offsetof(mc_tally_out, real), offsetof(mc_tally_out, flags));
+  printf("%zu %zu %zu %zu\n", sizeof(mc_observables_out), offsetof(mc_observables_out, drift_velocity_ms),
+         offsetof(mc_observables_out, half_se), offsetof(mc_observables_out, steady));
   return 0;
 }
 """
@@ -63,7 +65,9 @@ int main(void) {
         out = subprocess.check_output([exe]).decode().split()
     want = [C.sizeof(gfmc.McMaterial), C.sizeof(gfmc.McConfig), C.sizeof(gfmc.McTallyOut),
             C.sizeof(gfmc.McParticlesView), gfmc.McConfig.seed.offset, gfmc.McConfig.n_cells.offset,
-            gfmc.McConfig.Vds.offset, gfmc.McTallyOut.real.offset, gfmc.McTallyOut.flags.offset]
+            gfmc.McConfig.Vds.offset, gfmc.McTallyOut.real.offset, gfmc.McTallyOut.flags.offset,
+            C.sizeof(gfmc.McObservablesOut), gfmc.McObservablesOut.drift_velocity_ms.offset,
+            gfmc.McObservablesOut.half_se.offset, gfmc.McObservablesOut.steady.offset]
     assert [int(x) for x in out] == want
 
 

@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 from scipy import integrate
 
-from oracle.mlp_oracle import MLPOracle, adam_step, bf16, gelu, gelu_grad
+from oracle.mlp_oracle import (MLPOracle, adam_step, bf16, decode_maps, ensemble_mean_spread, gelu, gelu_grad,
+                               inside_box, predicted_error)
 
 
 def _net(rng, n_in=7, width=6, depth=2, n_out=5):
@@ -99,3 +100,67 @@ def test_decoupled_weight_decay():
     for t in range(1, 5001):
         w, m, v = adam_step(w, m, v, 2 * (w - a), t, lr=1e-3, wd=0.1)
     assert np.all(np.abs(w) < np.abs(a)) and np.all(w * a > 0)
+
+
+def test_adam_first_two_steps_closed_form():
+    """Kingma & Ba's bias correction makes the first step lr g / (|g| + eps)
+    whatever the gradient's scale; a second step with the same gradient
+    repeats it, one with the opposite gradient moves back by
+    lr (1 - b1) / (1 + b1) g / (|g| + eps) (m_2 = -(1 - b1)^2 g,
+    v_2 = (1 - b2^2) g^2).  A missing or shifted correction changes both."""
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for g0 in (1e-6, 3e-3, 1.0, -250.0, 4e5):
+        g = np.array([g0])
+        w1, m, v = adam_step(np.zeros(1), np.zeros(1), np.zeros(1), g, 1, lr, b1, b2, eps)
+        unit = g / (np.abs(g) + eps)
+        assert w1[0] == pytest.approx(-lr * unit[0], rel=1e-9)
+        w2, _, _ = adam_step(w1, m, v, g, 2, lr, b1, b2, eps)
+        assert w2[0] - w1[0] == pytest.approx(-lr * unit[0], rel=1e-9)
+        w2, _, _ = adam_step(w1, m, v, -g, 2, lr, b1, b2, eps)
+        assert w2[0] - w1[0] == pytest.approx(lr * (1 - b1) / (1 + b1) * unit[0], rel=1e-9)
+
+
+def test_decode_inverts_the_map_encoding():
+    """A map encoded as (its unit-norm shape, log of its norm) decodes to
+    itself, for maps spanning many orders of magnitude."""
+    rng = np.random.default_rng(3)
+    nc = 37
+    heat = rng.gamma(2.0, 1.0, (3, nc)) * np.array([[1e9], [1e14], [3e16]])
+    dens = rng.uniform(0.2, 1.0, (3, nc)) * 1e24
+    enc = np.zeros((3, 2 * nc + 2))
+    for k, Y in enumerate((heat, dens)):
+        n = np.linalg.norm(Y, axis=1)
+        enc[:, k * nc:(k + 1) * nc] = Y / n[:, None]
+        enc[:, 2 * nc + k] = np.log(n)
+    out = decode_maps(enc, nc)
+    assert np.allclose(out[:, :nc], heat, rtol=1e-13, atol=0)
+    assert np.allclose(out[:, nc:], dens, rtol=1e-13, atol=0)
+
+
+def test_predicted_error_closed_forms():
+    """Two members whose shapes are s +- d and log-norms l +- e: the sample
+    spread is sqrt(2)|d| and sqrt(2)|e|, so the predicted error of a map is
+    calib hypot(sqrt(2)|d| / |s|, sqrt(2)|e|); identical members give 0."""
+    nc = 50
+    rng = np.random.default_rng(8)
+    s = rng.normal(size=(2, nc)); s /= np.linalg.norm(s, axis=1)[:, None]
+    d = [0.01 * rng.normal(size=nc), 0.03 * rng.normal(size=nc)]
+    e = [0.002, 0.0005]
+    base = np.concatenate([s[0], s[1], [1.0, 2.0]])
+    delta = np.concatenate([d[0], d[1], e])
+    mean, spread = ensemble_mean_spread(np.stack([base + delta, base - delta])[:, None, :])
+    assert np.allclose(mean[0], base, rtol=0, atol=1e-15)
+    assert np.allclose(spread[0], math.sqrt(2) * np.abs(delta), rtol=1e-12)
+    want = max(math.hypot(math.sqrt(2) * np.linalg.norm(d[k]) / np.linalg.norm(s[k]), math.sqrt(2) * e[k])
+               for k in range(2))
+    assert predicted_error(mean, spread, nc, 1.7)[0] == pytest.approx(1.7 * want, rel=1e-12)
+    m0, s0 = ensemble_mean_spread(np.stack([base, base, base])[:, None, :])
+    assert predicted_error(m0, s0, nc, 3.0)[0] < 1e-15
+
+
+def test_training_box():
+    lo, hi = np.array([0.0, -3.0, 17.0]), np.array([1.0, 0.0, 19.0])
+    assert inside_box([0.5, -1.0, 18.0], lo, hi)
+    assert inside_box([1.0 + 5e-7, -3.0, 19.0], lo, hi)          # within the 1e-6 widening
+    assert not inside_box([1.0 + 2e-6, -3.0, 19.0], lo, hi)
+    assert not inside_box([0.5, 0.1, 18.0], lo, hi)

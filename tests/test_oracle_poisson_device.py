@@ -122,3 +122,70 @@ def test_biased_device_drives_current_and_heats_near_drain(oracle_mod):
     net = (heat[:, 0].astype(float) - heat[:, 1]).reshape(50, 18).sum(1)
     assert net.sum() > 0
     assert net[25:].sum() > net[:25].sum()                               # dissipation grows towards the drain
+
+
+def _gated_manufactured(oracle_mod, nx, ny, nz):
+    """Gate over the whole channel, every terminal at 0 V: the Dirichlet faces
+    are the source, the drain, the top and the outer side; y = 0 and z = 0
+    are Neumann.  phi = A sin(pi x / L) cos(pi y / 2 Ly) cos(pi z / 2 Lz)
+    meets all of them, and -eps lap(phi) = eps lam phi."""
+    L, Ly, Lz = 200.0, 60.0, 120.0
+    cfg = W.device_config(n_particles=nx * ny * nz, precision="fp64", Vds=0.0, Vgs=0.0, n_cells=(nx, ny, nz),
+                          L_nm=(L, Ly, Lz))
+    cfg["gate_x_nm"] = [0.0, L]
+    o = oracle_mod.Oracle(cfg)
+    A = 0.4
+    eps = cfg["material"]["eps_s"] * EPS0 * 1e-9
+    lam = math.pi ** 2 * (1 / L ** 2 + 1 / (4 * Ly ** 2) + 1 / (4 * Lz ** 2))
+    dx, dy, dz = L / nx, Ly / ny, Lz / nz
+    # exact cell integrals of the separable source
+    ix = np.arange(nx) * dx
+    Ix = (L / math.pi) * (np.cos(math.pi * ix / L) - np.cos(math.pi * (ix + dx) / L))
+    iy = np.arange(ny) * dy
+    Iy = (2 * Ly / math.pi) * (np.sin(math.pi * (iy + dy) / (2 * Ly)) - np.sin(math.pi * iy / (2 * Ly)))
+    iz = np.arange(nz) * dz
+    Iz = (2 * Lz / math.pi) * (np.sin(math.pi * (iz + dz) / (2 * Lz)) - np.sin(math.pi * iz / (2 * Lz)))
+    q = eps * lam * A * (Ix[:, None, None] * Iy[None, :, None] * Iz[None, None, :]).ravel()
+    phi, F = o.poisson_solve(q)
+    xc, yc, zc = ix + dx / 2, iy + dy / 2, iz + dz / 2
+    X, Y, Z = np.meshgrid(xc, yc, zc, indexing="ij")
+    exact = A * np.sin(math.pi * X / L) * np.cos(math.pi * Y / (2 * Ly)) * np.cos(math.pi * Z / (2 * Lz))
+    dphidy = -A * (math.pi / (2 * Ly)) * np.sin(math.pi * X / L) * np.sin(math.pi * Y / (2 * Ly)) * \
+        np.cos(math.pi * Z / (2 * Lz))
+    dphidz = -A * (math.pi / (2 * Lz)) * np.sin(math.pi * X / L) * np.cos(math.pi * Y / (2 * Ly)) * \
+        np.sin(math.pi * Z / (2 * Lz))
+    Fr = F.reshape(nx, ny, nz, 3)
+    err_phi = np.abs(phi.reshape(nx, ny, nz) - exact).max() / A
+    # field in the cells along the gated faces (outer side, top), where a
+    # Dirichlet neighbour sits half a cell away
+    err_fy = np.abs(Fr[:, -1, :, 1] + dphidy[:, -1, :]).max() / np.abs(dphidy).max()
+    err_fz = np.abs(Fr[:, :, -1, 2] + dphidz[:, :, -1]).max() / np.abs(dphidz).max()
+    return err_phi, err_fy, err_fz
+
+
+def test_gated_faces_manufactured_solution(oracle_mod):
+    """Second-order potential and a converging field at the gated faces: a
+    wrong gate-face coefficient in the matrix or the right-hand side, or a
+    wrong half-cell distance in the field, stops the convergence."""
+    e = [_gated_manufactured(oracle_mod, 10 * s, 3 * s, 6 * s) for s in (1, 2, 4)]
+    phi = [x[0] for x in e]
+    assert all(3.5 < phi[i] / phi[i + 1] < 4.5 for i in range(2)), phi
+    assert phi[-1] < 2e-3
+    for j in (1, 2):
+        f = [x[j] for x in e]
+        assert all(f[i] / f[i + 1] > 1.8 for i in range(2)), f
+        assert f[-1] < 0.05, f
+
+
+def test_gated_superposition_and_bounds(oracle_mod):
+    """No charge, gate over the whole channel: the potential of (V_ds, V_gs)
+    is the sum of those of (V_ds, 0) and (0, V_gs), and lies between the
+    lowest and highest terminal potential."""
+    cfg = W.device_config(n_particles=1800, precision="fp64", Vds=0.7, Vgs=-0.4, n_cells=(20, 3, 6),
+                          L_nm=(200.0, 60.0, 120.0))
+    cfg["gate_x_nm"] = [0.0, 200.0]
+    a = oracle_mod.Oracle(dict(cfg, Vgs=0.0)).poisson_solve(np.zeros(360))[0]
+    b = oracle_mod.Oracle(dict(cfg, Vds=0.0)).poisson_solve(np.zeros(360))[0]
+    ab = oracle_mod.Oracle(cfg).poisson_solve(np.zeros(360))[0]
+    assert np.allclose(ab, a + b, rtol=0, atol=1e-13)
+    assert np.all(ab <= 0.7 + 1e-13) and np.all(ab >= -0.4 - 1e-13)
