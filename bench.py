@@ -8,9 +8,15 @@ One step = one flight interval: 10 sub-steps of 1 fs of free flight and
 scattering for every electron, then the subcell deposit, the contact refill
 and the Poisson refresh.  The default run times 500 steps (5 ps).
 
-Prints one JSON line.  The metric counts free-flight segments (one per
-electron per sub-step plus one per scattering selection, real or self) per
-second; real scattering events/s and electron-fs/s are reported beside it.
+Prints one JSON line.  The metric counts free-flight segments as a
+sub-step-at-a-time Monte Carlo would fly them (one per electron per 1 fs
+sub-step plus one per scattering selection, real or self) per second.  The
+kernel fuses the ten sub-steps of an interval and draws each electron's
+flight afresh only at the interval start, so the flights it actually flies
+(one per electron per interval plus one per selection) are reported beside
+the metric as flights_per_s, with real scattering events/s and
+electron-fs/s.  The roofline is the algorithmic HBM stream of the particle
+kernel: each live electron's state read and written once per interval.
 """
 from __future__ import annotations
 
@@ -38,7 +44,7 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 KERNELS = {0: "k_flight_refill<float,true>", 1: "k_flight<float,true>", 2: "k_flight_persist<float,true>"}
 KERNEL_COUNTERS = {
     0: {"sources_digest": "fc22754904390b71", "valu_lane_ops_per_segment": 173.2, "hbm_bytes_per_segment": 8.76,
-        "profile": "profiles/k_flight_refill_device1e7_counters.md"},
+        "active_lane_fraction": 0.46, "profile": "profiles/k_flight_refill_device1e7_counters.md"},
 }
 
 
@@ -304,45 +310,38 @@ def main() -> int:
     _log(f"wall {wall:.3f} s, segments {segments}, selections {tal['selections']}, real {real}")
 
     roofline = None
-    if prof and prof["n_flight"] and not f32:
-        # FP64 state: the particle kernel is timed, but its per-segment counters
-        # were taken for FP32 state only
+    if prof and prof["n_flight"]:
+        # the particle kernel (one launch per interval), timed by HIP events on
+        # the library's stream.  Algorithmic bytes: the fused interval must read
+        # and write each live electron's state once per launch (six coordinates
+        # and the meta word: 28 B each way in FP32 state, 52 B in FP64)
         flight_s = prof["flight_ms"] / prof["n_flight"] * 1e-3
-        roofline = dict(
-            bound="alu", achieved=None, peak=ALU_PEAK_LANE_OPS / 1e12, unit="TOP/s", frac=None, traffic=None,
-            counters_current=False, kernel=KERNELS[args.variant].replace("<float", "<double"),
-            note="per-segment counters exist for FP32 state only",
-            segments_per_launch=segments / prof["n_flight"], avg_launch_ms=flight_s * 1e3,
-            refresh_avg_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]),
-            flight_share=prof["flight_ms"] / (prof["flight_ms"] + prof["refresh_ms"]))
-    elif prof and prof["n_flight"]:
-        # the particle kernel (one launch per interval), timed by HIP events on its stream
-        flight_s = prof["flight_ms"] / prof["n_flight"] * 1e-3
-        segs_launch = segments / prof["n_flight"]
         per_launch = proc / prof["n_flight"]
-        kc = KERNEL_COUNTERS.get(args.variant, KERNEL_COUNTERS[0])
-        fresh = _kernel_digest() == kc["sources_digest"] and args.variant in KERNEL_COUNTERS
-        ops = kc["valu_lane_ops_per_segment"] * segs_launch
-        achieved = ops / flight_s / 1e12
-        # the state stream the fused interval must move: 6 x FP32 + u32 meta per
-        # electron, read and written once per launch
-        state_bytes = per_launch * 28 * 2
+        state_b = (28 if f32 else 52) * 2
+        achieved = per_launch * state_b / flight_s / 1e9
+        kc = KERNEL_COUNTERS.get(args.variant) if f32 else None
+        fresh = bool(kc) and _kernel_digest() == kc["sources_digest"]
+        segs_launch = segments / prof["n_flight"]
         roofline = dict(
-            bound="alu", achieved=achieved, peak=ALU_PEAK_LANE_OPS / 1e12, unit="TOP/s",
-            frac=achieved / (ALU_PEAK_LANE_OPS / 1e12),
+            bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
             traffic=kc["hbm_bytes_per_segment"] * segs_launch if fresh else None,
-            counters_current=fresh,
-            kernel=KERNELS[args.variant],
-            ops_per_segment=kc["valu_lane_ops_per_segment"], segments_per_launch=segs_launch,
-            avg_launch_ms=flight_s * 1e3,
+            kernel=KERNELS[args.variant] if f32 else KERNELS[args.variant].replace("<float", "<double"),
+            algorithmic_bytes_per_launch=per_launch * state_b, bytes_per_electron_interval=state_b,
+            electrons_per_launch=per_launch, avg_launch_ms=flight_s * 1e3,
             refresh_avg_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]),
             flight_share=prof["flight_ms"] / (prof["flight_ms"] + prof["refresh_ms"]),
-            hbm_state_stream=dict(achieved=state_bytes / flight_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
-                                  frac=state_bytes / flight_s / 1e9 / HBM_PEAK_GBS),
-            hbm_per_substep_model=dict(achieved=per_launch * K * 56 / flight_s / 1e9, peak=HBM_PEAK_GBS,
-                                       unit="GB/s", frac=per_launch * K * 56 / flight_s / 1e9 / HBM_PEAK_GBS,
-                                       note="56 B per electron per 1 fs sub-step, as if the state crossed "
-                                            "HBM every sub-step; the kernel fuses the 10 sub-steps"))
+            counters_current=fresh,
+            note="the kernel is bound by VALU issue, not by HBM: the ten sub-steps of an interval run in "
+                 "registers, so the state crosses HBM once per interval")
+        if fresh:
+            ops = kc["valu_lane_ops_per_segment"] * segs_launch
+            roofline["valu_issue"] = dict(
+                lane_instructions_per_launch=ops, achieved=ops / flight_s / 1e12, peak=ALU_PEAK_LANE_OPS / 1e12,
+                unit="T lane-instr/s", frac_issue=ops / flight_s / ALU_PEAK_LANE_OPS,
+                active_lane_fraction=kc.get("active_lane_fraction"),
+                frac_useful=(ops * kc["active_lane_fraction"] / flight_s / ALU_PEAK_LANE_OPS
+                             if kc.get("active_lane_fraction") else None),
+                profile=kc["profile"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -360,6 +359,7 @@ def main() -> int:
                                "Vgs=0 V, Vds=5 V, 1e18 cm^-3, 300 K + 150 K drain hot spot, 1 fs x 10 per step",
                    "particles": args.particles, "substeps_per_step": K, "block": block, "tile": tile,
                    "graph": bool(args.graph), "variant": args.variant, "precision": args.precision},
+        "flights_per_s": (proc + tal["selections"]) / wall,
         "real_events_per_s": real / wall,
         "electron_fs_per_s": proc * cfg["dt_fs"] * K / wall,
         "drain_current_A": tal["drain_current_A"],

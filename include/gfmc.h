@@ -168,29 +168,80 @@ int mc_tally(mc_ctx *ctx, int instance, mc_tally_out *h_out, int reset_window);
 
 /* Window maps of one instance: h_heat4 [ncell][4] phonon counts (LO emit, LO
  * absorb, intervalley emit, intervalley absorb), h_dens_sum [ncell] electron
- * counts summed over the window's refreshes, and the derived FP64 maps
- * h_heat_Wm3 (net phonon-emission power density) and h_density_m3.  Any
- * pointer may be NULL. */
+ * counts summed over the window's refreshes, and the derived FP64 maps:
+ * h_heat_Wm3 the net phonon-emission power density w e (hw_LO (em - ab) +
+ * hw_iv (em - ab)) / (V_c t_window), h_density_m3 the mean electron density
+ * w <count> / V_c, h_emit_Wm3 the emission-only power density (the emitted
+ * phonon energy of the thermal-resistance passage, per volume and time).
+ * Heat is counted per subcell (electron MC paragraph).  Any pointer may be
+ * NULL.  Synchronises the stream. */
 int mc_maps(mc_ctx *ctx, int instance, uint64_t *h_heat4, uint64_t *h_dens_sum, double *h_heat_Wm3,
-            double *h_density_m3);
+            double *h_density_m3, double *h_emit_Wm3);
 
-/* Bulk mode: per-interval rows (n_alive, sum vx, sum vy, sum vz, sum E,
- * N_Gamma1, N_U, N_Gamma3) recorded at each interval end, since the last
- * window reset. */
+/* Per-interval history rows (8 doubles each) since the last window reset,
+ * at most 8192.
+ * Bulk mode, at each interval end: live electrons, sum vx, sum vy, sum vz
+ * (nm/fs), sum of kinetic energies (eV), electrons in Gamma1, U, Gamma3.
+ * Device mode, after each refresh: the window's cumulative source exits,
+ * drain exits, source injections and drain injections, the electrons present
+ * after the refill, the mean potential (V) and the root-mean-square field
+ * magnitude (V/nm) over the subcells, the intervals done since mc_init.
+ * h_rows may be NULL (count only).  Synchronises the stream. */
 int mc_history(mc_ctx *ctx, int instance, double *h_rows, int max_rows, int *n_rows);
+
+/* Observables of one instance over the current window, computed on the host
+ * from the window's counts and history rows (electron MC paragraph: heat
+ * counted per subcell, steady state once current and field no longer
+ * change; the thermal-resistance passage: the emitted phonon energy). */
+typedef struct {
+  uint32_t intervals;          /* intervals in the window */
+  double t_window_fs;
+  /* device mode */
+  double drain_current_A;      /* e w (drain exits - drain injections) / t_window */
+  double source_current_A;     /* e w (source exits - source injections) / t_window (negative when
+                                  electrons enter at the source) */
+  double heat_W;               /* net phonon-emission power over the domain */
+  double emit_W;               /* emission-only power (emitted phonon energy / t_window) */
+  /* bulk mode: window means of the per-interval ensemble averages */
+  double drift_velocity_ms[3]; /* mean electron velocity, m/s */
+  double mean_energy_eV;       /* mean kinetic energy */
+  double valley_fraction[3];   /* Gamma1, U, Gamma3 */
+  /* steady state.  Two per-interval series: device mode the drain current and
+   * the rms field, bulk mode the mean v_z and the mean kinetic energy.  The
+   * last 2h intervals of the window (h = intervals / 2) form two halves;
+   * each half's mean and its standard error come from 10 batch means. */
+  double half_mean[2][2];      /* [series][half] */
+  double half_se[2][2];
+  int32_t steady;              /* 1: both series' half means within 3 combined standard errors; 0: not;
+                                  -1: a half holds fewer than 10 intervals */
+} mc_observables_out;
+
+/* Returns MC_OK, the first sticky device error of the instance (after
+ * filling *out), or MC_E_ARG / MC_E_HIP.  Synchronises the stream. */
+int mc_observables(mc_ctx *ctx, int instance, mc_observables_out *out);
 
 /* Device pointers of one instance's particle state (for in-place readers). */
 int mc_particles(mc_ctx *ctx, int instance, mc_particles_view *out);
 
 /* Copy one instance's particles to / from host arrays of `capacity` entries:
- * k[cap][3], r[cap][3] (FP64), valley, alive (int32), id (uint32).  After a
- * write the live electrons may sit in any slot: the particle kernel scans all
- * of the instance's slots until a refresh compacts them (results do not
- * depend on the slots; electrons are identified by id). */
+ * k[cap][3], r[cap][3] (FP64; r ignored and may be NULL in bulk mode),
+ * valley, alive (int32), id (uint32).  Both are ordered after the work already
+ * enqueued on the context's stream and complete before returning.  A write
+ * checks every entry first (identity below 2^29, valley 0..2) and returns
+ * MC_E_ARG without changing anything if one is bad.  After a write the live
+ * electrons may sit in any slot: the particle kernel scans all of the
+ * instance's slots until a refresh compacts them (results do not depend on
+ * the slots; electrons are identified by id). */
 int mc_read_particles(mc_ctx *ctx, int instance, double *h_k, double *h_r, int32_t *h_valley, int32_t *h_alive,
                       uint32_t *h_id);
 int mc_write_particles(mc_ctx *ctx, int instance, const double *h_k, const double *h_r, const int32_t *h_valley,
                        const int32_t *h_alive, const uint32_t *h_id);
+
+/* The configuration an instance was created with, and its current
+ * per-subcell lattice temperature (ncell doubles).  MC_E_ARG for a bad
+ * instance or pointer. */
+int mc_get_config(const mc_ctx *ctx, int instance, mc_config *out);
+int mc_get_lattice_temperature(const mc_ctx *ctx, int instance, double *h_T_cells);
 
 /* Potential, field and electron counts of the last refresh (ncell entries). */
 int mc_read_fields(mc_ctx *ctx, int instance, double *h_phi, double *h_field, uint32_t *h_count);
@@ -263,7 +314,7 @@ int mc_restore(mc_ctx *ctx, const void *h_buf, size_t bytes);
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t n_in;      /* raw input features */
-  int32_t n_out;     /* outputs (multiple of 8) */
+  int32_t n_out;     /* outputs (any positive count; padded internally to a multiple of 8) */
   int32_t width;     /* hidden width (multiple of 8) */
   int32_t depth;     /* hidden layers */
   int32_t ensemble;  /* independently initialised members (spread = predicted error) */
@@ -290,10 +341,16 @@ int sg_forward(sg_ctx *ctx, int member, const float *d_x, int batch, float *d_pr
 /* Forward, mean-squared error on z-scored targets, gradients of every layer
  * (kept in the workspace); h_loss (may be NULL) gets the loss (synchronises). */
 int sg_backward(sg_ctx *ctx, int member, const float *d_x, const float *d_y, int batch, float *h_loss);
-/* One bias-corrected Adam step of one member from its last gradients. */
+/* One bias-corrected Adam step of one member from its last gradients
+ * (Kingma & Ba: m and v moments, each divided by 1 - beta^t at step t). */
 int sg_adam(sg_ctx *ctx, int member, float lr);
+/* sg_backward then sg_adam for one member: the members of the ensemble are
+ * trained independently (each on its own batches), which is what makes
+ * their spread a measure of the error. */
 int sg_train_step(sg_ctx *ctx, int member, const float *d_x, const float *d_y, int batch, float lr, float *h_loss);
-/* De-normalised ensemble mean and spread (d_std may be NULL), asynchronous. */
+/* De-normalised ensemble mean and spread of every output (d_std may be NULL;
+ * sample standard deviation over the members), asynchronous.  The spread is
+ * per output; sg_predict_or_mc reduces it to one predicted relative error. */
 int sg_predict(sg_ctx *ctx, const float *d_x, int batch, float *d_mean, float *d_std);
 /* FP32 master parameters and last gradients of one layer: W [K][N], b [N]. */
 int sg_get_params(sg_ctx *ctx, int member, int layer, float *h_W, float *h_b);
@@ -316,20 +373,25 @@ typedef struct {
  * The network's outputs are read as the encoding [heat shape (ncell),
  * density shape (ncell), log heat norm, log density norm], so n_out =
  * 2 ncell + 2; each map is its unit-norm shape times the exponential of its
- * log-norm.  The predicted relative error is calib x the ensemble spread:
- * per map the spread of the shape over the norm of its mean, combined in
- * quadrature with the spread of the log-norm, the larger of the two maps.
- * When it exceeds tol, or the features leave the training box, the Monte
- * Carlo runs on instance `instance` of `mc`, which the caller set up for the
- * same bias point (doping, voltages, temperature map): warm_substeps
- * sub-steps, a window reset (of the whole context), window_substeps
- * sub-steps; every instance of `mc` advances.  h_maps [2 ncell] receives
- * heat (W/m^3) then electron density (m^-3); h_pred_err (may be NULL) the
- * predicted error; used_mc (may be NULL) 1 if the Monte Carlo answered.
- * Synchronises both contexts' streams.  MC_E_ARG for bad arguments, an
- * output width that is not such an encoding, a missing `mc` when the
- * Monte Carlo is needed, or a grid of `mc` that differs from ncell; the
- * status of the Monte Carlo calls otherwise. */
+ * log-norm (decoded from the ensemble mean).  The spread of an output is
+ * the sample standard deviation over the members (divisor members - 1).
+ * The predicted relative error is calib x the larger, over the two maps, of
+ * hypot(|spread of the shape| / |mean shape|, spread of the log-norm)
+ * (|.| the Euclidean norm over the ncell subcells).
+ * When it exceeds tol, or the features leave the training box (each feature
+ * within [lo, hi] widened by 1e-6 max(1, hi - lo)), the Monte Carlo runs on
+ * instance `instance` of `mc`, which must be set up for the same point: the
+ * same grid, Vgs, Vds, log10 doping and per-subcell temperature as the
+ * features (relative 1e-5), else MC_E_ARG.  It runs warm_substeps sub-steps,
+ * a window reset (of the whole context) and window_substeps sub-steps;
+ * every instance of `mc` advances.  h_maps [2 ncell] receives heat (W/m^3,
+ * the net map of mc_maps) then electron density (m^-3); h_pred_err (may be
+ * NULL) the predicted error; used_mc (may be NULL) 1 if the Monte Carlo
+ * answered.  Synchronises both contexts' streams.  Returns MC_OK; MC_E_ARG
+ * for bad arguments, an output width that is not such an encoding, a
+ * missing or mismatched `mc` when the Monte Carlo is needed; otherwise the
+ * status of the Monte Carlo calls, including a sticky device error raised
+ * during the window (the maps are then still filled). */
 int sg_predict_or_mc(sg_ctx *ctx, mc_ctx *mc, int instance, const sg_query *query, double *h_maps,
                      float *h_pred_err, int *used_mc);
 

@@ -19,8 +19,6 @@ using namespace gfmc;
 
 namespace {
 
-constexpr int kHistCap = 8192;
-
 struct Layout {
   size_t total = 0;
   size_t take(size_t bytes) {
@@ -144,7 +142,7 @@ Offsets layout(const mc_config* c, int n, size_t* total) {
                       : 0);
   o.ainv = L.take(dev ? sizeof(double) * (size_t)nc * nc : 0);
   o.rhs = L.take(dev ? sizeof(double) * (size_t)n * nc : 0);
-  o.hist = L.take(dev ? 0 : sizeof(double) * n * kHistCap * 8);
+  o.hist = L.take(sizeof(double) * n * kHistCap * 8);
   o.reps = L.take(sizeof(int) * n * nc);
   o.nrep = L.take(sizeof(int) * n);
   o.bpart = L.take(dev ? 0 : sizeof(double) * max_tiles * 8);
@@ -398,7 +396,8 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
       c->p<unsigned long long>(c->o.acc), c->p<uint32_t>(c->o.count), c->p<unsigned long long>(c->o.heat), af,
       c->p<uint32_t>(c->o.tile_dead), c->p<uint32_t>(c->o.tile_off), c->p<Plan>(c->o.plan),
       c->p<uint32_t>(c->o.next_id), c->p<unsigned long long>(c->o.counters), c->p<int>(c->o.flags),
-      c->p<uint32_t>(c->o.ctl), c->p<double>(c->o.rhs), c->p<unsigned long long>(c->o.dens));
+      c->p<uint32_t>(c->o.ctl), c->p<double>(c->o.rhs), c->p<unsigned long long>(c->o.dens),
+      c->p<double>(c->o.hist));
   if (c->f32) enqueue_compaction_and_slots<float>(c);
   else enqueue_compaction_and_slots<double>(c);
   const double mg1 = c->cfg[0].mat.m_eff[0];
@@ -431,7 +430,8 @@ void enqueue_refresh(mc_ctx* c, bool after_flight) {
                                                    c->p<double>(c->o.phi));
   }
   k_field<<<gc, 256, 0, c->st>>>(c->pg, c->p<InstParams>(c->o.ip), c->p<double>(c->o.phi), nc,
-                                 c->p<double>(c->o.field64), c->p<float>(c->o.field32), c->p<uint32_t>(c->o.ctl), af);
+                                 c->p<double>(c->o.field64), c->p<float>(c->o.field32), c->p<uint32_t>(c->o.ctl), af,
+                                 c->p<Plan>(c->o.plan), c->p<double>(c->o.hist));
 }
 
 hipEvent_t prof_event(mc_ctx* c) {
@@ -816,7 +816,8 @@ int mc_tally(mc_ctx* c, int inst, mc_tally_out* out, int reset_window) {
   return flag;
 }
 
-int mc_maps(mc_ctx* c, int inst, uint64_t* h_heat4, uint64_t* h_dens, double* h_heat_Wm3, double* h_dens_m3) {
+int mc_maps(mc_ctx* c, int inst, uint64_t* h_heat4, uint64_t* h_dens, double* h_heat_Wm3, double* h_dens_m3,
+            double* h_emit_Wm3) {
   if (!c || inst < 0 || inst >= c->n_inst) return fail(c, MC_E_ARG, "bad argument");
   const int nc = c->ncell;
   std::vector<unsigned long long> heat((size_t)4 * nc), dens(nc);
@@ -843,23 +844,115 @@ int mc_maps(mc_ctx* c, int inst, uint64_t* h_heat4, uint64_t* h_dens, double* h_
       h_heat_Wm3[q] = tw > 0 ? w * kQ * (m.hw_lo_eV * (em_lo - ab_lo) + m.hw_iv_eV * (em_iv - ab_iv)) / (Vc_m3 * tw)
                              : 0.0;
     if (h_dens_m3) h_dens_m3[q] = ctl[CTL_WINDOW] ? w * (double)dens[q] / ctl[CTL_WINDOW] / Vc_m3 : 0.0;
+    if (h_emit_Wm3)
+      h_emit_Wm3[q] = tw > 0 ? w * kQ * (m.hw_lo_eV * em_lo + m.hw_iv_eV * em_iv) / (Vc_m3 * tw) : 0.0;
   }
   return MC_OK;
 }
 
 int mc_history(mc_ctx* c, int inst, double* h_rows, int max_rows, int* n_rows) {
-  if (!c || inst < 0 || inst >= c->n_inst || !n_rows) return fail(c, MC_E_ARG, "bad argument");
+  if (!c || inst < 0 || inst >= c->n_inst || !n_rows || max_rows < 0) return fail(c, MC_E_ARG, "bad argument");
   *n_rows = 0;
-  if (c->dev) return MC_OK;
   uint32_t ctl[16];
   HIPCHK(c, hipMemcpyAsync(ctl, c->p<uint32_t>(c->o.ctl), sizeof(ctl), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  int n = std::min<int>((int)ctl[CTL_WINDOW], std::min(kHistCap, max_rows));
-  if (n > 0 && h_rows)
-    HIPCHK(c, hipMemcpy(h_rows, c->p<double>(c->o.hist) + (size_t)inst * kHistCap * 8, sizeof(double) * 8 * n,
-                        hipMemcpyDeviceToHost));
+  const int n = std::min<int>((int)ctl[CTL_WINDOW], std::min(kHistCap, max_rows));
+  if (n > 0 && h_rows) {
+    HIPCHK(c, hipMemcpyAsync(h_rows, c->p<double>(c->o.hist) + (size_t)inst * kHistCap * 8, sizeof(double) * 8 * n,
+                             hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+  }
   *n_rows = n;
   return MC_OK;
+}
+
+namespace {
+
+// Two-halves test of one per-interval series: the last 2h values (h = m/2)
+// split in halves, each half's mean and standard error from 10 batch means
+// of h/10 consecutive values; steady when the means differ by no more than
+// three combined standard errors.  -1 when a half has fewer than 10 values.
+int halves_steady(const std::vector<double>& s, double mean[2], double se[2]) {
+  constexpr int kBlocks = 10;
+  const int m = (int)s.size(), h = m / 2, b = h / kBlocks;
+  mean[0] = mean[1] = se[0] = se[1] = 0.0;
+  if (b < 1) return -1;
+  for (int half = 0; half < 2; ++half) {
+    const int first = m - 2 * h + half * h;
+    double bm[kBlocks];
+    double mu = 0.0;
+    for (int j = 0; j < kBlocks; ++j) {
+      double acc = 0.0;
+      for (int i = first + j * b; i < first + (j + 1) * b; ++i) acc += s[i];
+      bm[j] = acc / b;
+      mu += bm[j];
+    }
+    mu /= kBlocks;
+    double ss = 0.0;
+    for (int j = 0; j < kBlocks; ++j) ss += (bm[j] - mu) * (bm[j] - mu);
+    mean[half] = mu;
+    se[half] = std::sqrt(ss / (kBlocks * (kBlocks - 1.0)));
+  }
+  return std::fabs(mean[0] - mean[1]) <= 3.0 * std::hypot(se[0], se[1]) ? 1 : 0;
+}
+
+}  // namespace
+
+int mc_observables(mc_ctx* c, int inst, mc_observables_out* out) {
+  if (!c || inst < 0 || inst >= c->n_inst || !out) return fail(c, MC_E_ARG, "bad argument");
+  std::memset(out, 0, sizeof(*out));
+  int n = 0, rc;
+  std::vector<double> rows((size_t)kHistCap * 8);
+  if ((rc = mc_history(c, inst, rows.data(), kHistCap, &n)) != MC_OK) return rc;
+  mc_tally_out t;
+  std::memset(&t, 0, sizeof(t));
+  rc = mc_tally(c, inst, &t, 0);
+  if (rc != MC_OK && rc != t.flags) return rc;  // a runtime failure, not a sticky device flag
+  const double TP = c->cfg[0].dt_fs * c->cfg[0].substeps * 1e-15;  // s
+  out->intervals = t.intervals;
+  out->t_window_fs = t.t_window_fs;
+  std::vector<double> s1(n), s2(n);
+  if (c->dev) {
+    const double qw = kQ * c->ip[inst].w, tw = t.t_window_fs * 1e-15;
+    if (tw > 0.0) {
+      out->drain_current_A = qw * ((double)t.exits[1] - (double)t.injections[1]) / tw;
+      out->source_current_A = qw * ((double)t.exits[0] - (double)t.injections[0]) / tw;
+    }
+    std::vector<uint64_t> heat4((size_t)4 * c->ncell);
+    if ((rc = mc_maps(c, inst, heat4.data(), nullptr, nullptr, nullptr, nullptr)) != MC_OK) return rc;
+    const mc_material& m = c->cfg[0].mat;
+    double net = 0.0, emit = 0.0;  // eV
+    for (int q = 0; q < c->ncell; ++q) {
+      const uint64_t* h = heat4.data() + 4 * q;
+      net += m.hw_lo_eV * ((double)h[0] - (double)h[1]) + m.hw_iv_eV * ((double)h[2] - (double)h[3]);
+      emit += m.hw_lo_eV * (double)h[0] + m.hw_iv_eV * (double)h[2];
+    }
+    if (tw > 0.0) {
+      out->heat_W = qw * net / tw;
+      out->emit_W = qw * emit / tw;
+    }
+    // drain current of each interval from the window's cumulative counts
+    for (int i = 0; i < n; ++i) {
+      const double* r = rows.data() + 8 * (size_t)i;
+      const double ex0 = i ? r[1 - 8] : 0.0, in0 = i ? r[3 - 8] : 0.0;
+      s1[i] = qw * ((r[1] - ex0) - (r[3] - in0)) / TP;
+      s2[i] = r[6];
+    }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      const double* r = rows.data() + 8 * (size_t)i;
+      const double na = r[0] > 0.0 ? r[0] : 1.0;
+      for (int d = 0; d < 3; ++d) out->drift_velocity_ms[d] += r[1 + d] / na * 1e6 / n;  // nm/fs -> m/s
+      out->mean_energy_eV += r[4] / na / n;
+      for (int v = 0; v < 3; ++v) out->valley_fraction[v] += r[5 + v] / na / n;
+      s1[i] = r[3] / na * 1e6;
+      s2[i] = r[4] / na;
+    }
+  }
+  const int f1 = halves_steady(s1, out->half_mean[0], out->half_se[0]);
+  const int f2 = halves_steady(s2, out->half_mean[1], out->half_se[1]);
+  out->steady = (f1 < 0 || f2 < 0) ? -1 : (f1 == 1 && f2 == 1 ? 1 : 0);
+  return t.flags;
 }
 
 int mc_particles(mc_ctx* c, int inst, mc_particles_view* out) {
@@ -916,27 +1009,49 @@ int mc_write_particles(mc_ctx* c, int inst, const double* h_k, const double* h_r
   const int cap = c->cfg[inst].capacity;
   const long long b = c->ip[inst].base;
   const size_t es = c->f32 ? 4 : 8;
-  const size_t offs[6] = {c->o.kx, c->o.ky, c->o.kz, c->o.x, c->o.y, c->o.z};
-  std::vector<char> buf(es * cap);
-  for (int d = 0; d < 6; ++d) {
-    if (d >= 3 && !c->dev) continue;
-    for (int i = 0; i < cap; ++i) {
-      const double val = d < 3 ? h_k[3 * i + d] : h_r[3 * i + d - 3];
-      if (c->f32) ((float*)buf.data())[i] = (float)val;
-      else ((double*)buf.data())[i] = val;
-    }
-    HIPCHK(c, hipMemcpy(c->ws + offs[d] + es * b, buf.data(), es * cap, hipMemcpyHostToDevice));
-  }
+  // every input is checked before anything is copied: a rejected write
+  // leaves the instance as it was
   std::vector<uint32_t> meta(cap);
   for (int i = 0; i < cap; ++i) {
     if (h_id[i] >= (1u << 29) || h_valley[i] < 0 || h_valley[i] > 2) return fail(c, MC_E_ARG, "bad particle");
     meta[i] = (h_id[i] << 3) | (h_alive[i] ? kAlive : 0u) | (uint32_t)h_valley[i];
   }
-  HIPCHK(c, hipMemcpy(c->p<uint32_t>(c->o.meta) + b, meta.data(), sizeof(uint32_t) * cap, hipMemcpyHostToDevice));
+  const size_t offs[6] = {c->o.kx, c->o.ky, c->o.kz, c->o.x, c->o.y, c->o.z};
+  std::vector<char> buf[6];
+  for (int d = 0; d < 6; ++d) {
+    if (d >= 3 && !c->dev) continue;
+    buf[d].resize(es * cap);
+    for (int i = 0; i < cap; ++i) {
+      const double val = d < 3 ? h_k[3 * i + d] : h_r[3 * i + d - 3];
+      if (c->f32) ((float*)buf[d].data())[i] = (float)val;
+      else ((double*)buf[d].data())[i] = val;
+    }
+  }
+  // the copies are ordered after every kernel already enqueued on the
+  // context's stream (a write right after an asynchronous mc_step waits for
+  // it) and complete before the call returns
+  for (int d = 0; d < 6; ++d) {
+    if (d >= 3 && !c->dev) continue;
+    HIPCHK(c, hipMemcpyAsync(c->ws + offs[d] + es * b, buf[d].data(), es * cap, hipMemcpyHostToDevice, c->st));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->p<uint32_t>(c->o.meta) + b, meta.data(), sizeof(uint32_t) * cap, hipMemcpyHostToDevice,
+                           c->st));
   // live electrons may now lie anywhere in the instance's slots
   k_set_hw<<<1, 64, 0, c->st>>>(c->p<Plan>(c->o.plan), inst, (uint32_t)cap);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->st));
+  return MC_OK;
+}
+
+int mc_get_config(const mc_ctx* c, int inst, mc_config* out) {
+  if (!c || inst < 0 || inst >= c->n_inst || !out) return MC_E_ARG;
+  *out = c->cfg[inst];
+  return MC_OK;
+}
+
+int mc_get_lattice_temperature(const mc_ctx* c, int inst, double* h_T) {
+  if (!c || inst < 0 || inst >= c->n_inst || !h_T) return MC_E_ARG;
+  std::memcpy(h_T, c->Tcell[inst].data(), sizeof(double) * c->ncell);
   return MC_OK;
 }
 

@@ -36,6 +36,15 @@ enum {
   C_REFL = 37, C_PROC = 38
 };
 enum { CTL_INTERVAL = 0, CTL_WINDOW = 1 };
+constexpr uint32_t kNoRow = 0xffffffffu;
+// Per-interval history rows, 8 doubles each, per instance.  Bulk mode: live
+// electrons, sum of vx, vy, vz (nm/fs), sum of kinetic energies (eV),
+// electrons in Gamma1, U, Gamma3.  Device mode (after each refresh): the
+// window's cumulative source exits, drain exits, source injections and drain
+// injections, the electrons present after the refill, the mean potential (V)
+// and the root-mean-square field magnitude (V/nm) over the subcells, and the
+// intervals done since initialisation.
+constexpr int kHistCap = 8192;
 
 struct TileDesc {
   int inst;
@@ -64,7 +73,7 @@ struct Plan {
   uint32_t alive;    // live electrons of the instance before the refill
   uint32_t compact;  // 1: compact the instance's slots in this refresh
   uint32_t hw;       // slots in use (relative): every live electron lies below it
-  uint32_t pad2;
+  uint32_t row;      // history row of this refresh (device mode, after a flight), else kNoRow
   uint32_t need[64];
   uint32_t off[64];
 };

@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
                                                               uint32_t* tile_off, Plan* plan, uint32_t* next_id,
                                                               unsigned long long* counters, int* flags,
                                                               const uint32_t* ctl, double* rhs_out,
-                                                              unsigned long long* dens) {
+                                                              unsigned long long* dens, double* hist) {
   __shared__ uint32_t s_wave[kPlanThreads / 64];
   __shared__ uint32_t s_holes[kPlanThreads / 64];
   __shared__ int s_edge;
@@ -218,8 +218,22 @@ __global__ void __launch_bounds__(kPlanThreads) k_inject_plan(const InstParams* 
       // the new ones, so the bound grows only past alive + Q
       pl->hw = compact ? alive + Q : max(min(pl->hw, (uint32_t)I.cap), alive + Q);
       next_id[inst] = id0 + Q;
-      counters[(size_t)inst * kNCnt + C_INJ0] += src;
-      counters[(size_t)inst * kNCnt + C_INJ1] += drn;
+      unsigned long long* cn = counters + (size_t)inst * kNCnt;
+      cn[C_INJ0] += src;
+      cn[C_INJ1] += drn;
+      // history row of an interval: the window's contact counts and the
+      // electrons present; k_field adds the potential and field
+      const uint32_t row = ctl[CTL_WINDOW];
+      pl->row = (after_flight && row < (uint32_t)kHistCap) ? row : kNoRow;
+      if (pl->row != kNoRow) {
+        double* h = hist + ((size_t)inst * kHistCap + row) * 8;
+        h[0] = (double)cn[C_EXIT0];
+        h[1] = (double)cn[C_EXIT1];
+        h[2] = (double)cn[C_INJ0];
+        h[3] = (double)cn[C_INJ1];
+        h[4] = (double)(alive + Q);
+        h[7] = (double)(ctl[CTL_INTERVAL] + 1u);
+      }
     }
   }
 }
@@ -756,18 +770,11 @@ __global__ void __launch_bounds__(256) k_poisson_gemm(const double* __restrict__
 
 // Centred-difference field E = -grad(phi): a Dirichlet neighbour is its face
 // value half a cell away, a Neumann neighbour the cell itself.
-__global__ void k_field(PoisGeo g, const InstParams* __restrict__ ip, const double* __restrict__ phi_all, int ncell,
-                        double* field64, float* field32, uint32_t* ctl, int advance) {
-  const int inst = blockIdx.y;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  // the interval is complete: the refill plan has read the counter
-  if (advance && c == 0 && inst == 0) {
-    ctl[CTL_INTERVAL] += 1u;
-    ctl[CTL_WINDOW] += 1u;
-  }
-  if (c >= ncell) return;
-  const InstParams& I = ip[inst];
-  const double* h = phi_all + (size_t)inst * ncell;
+// Cell-centred field E = -grad(phi) of subcell c (V/nm): centred
+// differences; a Dirichlet neighbour (source, drain, gated face) is its face
+// value half a cell away, a Neumann neighbour is the cell itself.
+__device__ __forceinline__ void cell_field(const PoisGeo& g, const InstParams& I, const double* h, int c,
+                                           double& ex, double& ey, double& ez) {
   const int P = g.P, nx = g.nx;
   const int ix = c / P, l = c % P, iy = l / g.nz, iz = l % g.nz;
   const double pc = h[c];
@@ -775,19 +782,68 @@ __global__ void k_field(PoisGeo g, const InstParams* __restrict__ ip, const doub
   double pe, de, pw, dw;
   if (ix < nx - 1) { pe = h[c + P]; de = g.dx; } else { pe = I.Vds; de = 0.5 * g.dx; }
   if (ix > 0) { pw = h[c - P]; dw = g.dx; } else { pw = 0.0; dw = 0.5 * g.dx; }
-  const double ex = -(pe - pw) / (de + dw);
+  ex = -(pe - pw) / (de + dw);
   double pn, dn, ps, ds;
   if (iy < g.ny - 1) { pn = h[c + g.nz]; dn = g.dy; }
   else if (gt) { pn = I.phig; dn = 0.5 * g.dy; }
   else { pn = pc; dn = 0.0; }
   if (iy > 0) { ps = h[c - g.nz]; ds = g.dy; } else { ps = pc; ds = 0.0; }
-  const double ey = (dn + ds) > 0.0 ? -(pn - ps) / (dn + ds) : 0.0;
+  ey = (dn + ds) > 0.0 ? -(pn - ps) / (dn + ds) : 0.0;
   double pt, dt, pb, db;
   if (iz < g.nz - 1) { pt = h[c + 1]; dt = g.dz; }
   else if (gt) { pt = I.phig; dt = 0.5 * g.dz; }
   else { pt = pc; dt = 0.0; }
   if (iz > 0) { pb = h[c - 1]; db = g.dz; } else { pb = pc; db = 0.0; }
-  const double ez = (dt + db) > 0.0 ? -(pt - pb) / (dt + db) : 0.0;
+  ez = (dt + db) > 0.0 ? -(pt - pb) / (dt + db) : 0.0;
+}
+
+// The field of every subcell (one per thread).  After a flight workgroup 0
+// of each instance also completes the interval's history row with the mean
+// potential and the root-mean-square field over all subcells (a fixed-order
+// reduction), and one thread advances the interval counters.
+__global__ void __launch_bounds__(256) k_field(PoisGeo g, const InstParams* __restrict__ ip,
+                                               const double* __restrict__ phi_all, int ncell, double* field64,
+                                               float* field32, uint32_t* ctl, int advance,
+                                               const Plan* __restrict__ plan, double* hist) {
+  __shared__ double s_red[2][4];
+  const int inst = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const InstParams& I = ip[inst];
+  const double* h = phi_all + (size_t)inst * ncell;
+  if (advance && blockIdx.x == 0) {
+    const uint32_t row = plan[inst].row;
+    if (row != kNoRow) {
+      double sp = 0.0, sf = 0.0;
+      for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
+        double ex, ey, ez;
+        cell_field(g, I, h, q, ex, ey, ez);
+        sp += h[q];
+        sf += ex * ex + ey * ey + ez * ez;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        sp += __shfl_xor(sp, o);
+        sf += __shfl_xor(sf, o);
+      }
+      if ((threadIdx.x & 63) == 0) { s_red[0][threadIdx.x >> 6] = sp; s_red[1][threadIdx.x >> 6] = sf; }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += s_red[0][w]; b += s_red[1][w]; }
+        double* r = hist + ((size_t)inst * kHistCap + row) * 8;
+        r[5] = a / ncell;
+        r[6] = sqrt(b / ncell);
+      }
+    }
+  }
+  // the interval is complete: the refill plan has read the counter
+  if (advance && c == 0 && inst == 0) {
+    ctl[CTL_INTERVAL] += 1u;
+    ctl[CTL_WINDOW] += 1u;
+  }
+  if (c >= ncell) return;
+  double ex, ey, ez;
+  cell_field(g, I, h, c, ex, ey, ez);
   const size_t o = ((size_t)inst * ncell + c) * 4;
   field64[o + 0] = ex; field64[o + 1] = ey; field64[o + 2] = ez; field64[o + 3] = 0.0;
   field32[o + 0] = (float)ex; field32[o + 1] = (float)ey; field32[o + 2] = (float)ez; field32[o + 3] = 0.0f;

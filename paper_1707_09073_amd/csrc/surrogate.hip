@@ -490,15 +490,29 @@ int sg_predict_or_mc(sg_ctx* c, mc_ctx* mc, int instance, const sg_query* q, dou
   if (h_pred_err) *h_pred_err = (float)perr;
   if (used_mc) *used_mc = fall ? 1 : 0;
   if (!fall) return MC_OK;
+  if (!mc) return sfail(c, MC_E_ARG, "the Monte Carlo is needed: no context given");
+  // the instance must be set up for the queried point: same grid, voltages,
+  // doping and lattice temperature (features are FP32: relative 1e-5)
+  mc_config mcfg;
   int mnc = 0;
-  if (!mc || mc_get_ncell(mc, &mnc) != MC_OK) return sfail(c, MC_E_ARG, "the Monte Carlo is needed: no context given");
+  if (mc_get_config(mc, instance, &mcfg) != MC_OK || mc_get_ncell(mc, &mnc) != MC_OK)
+    return sfail(c, MC_E_ARG, "bad Monte Carlo instance");
   if (mnc != nc) return sfail(c, MC_E_ARG, "the Monte Carlo context's grid differs from the surrogate's maps");
+  if (n_in != 3 + nc) return sfail(c, MC_E_ARG, "features are not (Vgs, Vds, log10 doping, T per subcell)");
+  std::vector<double> T(nc);
+  if (mc_get_lattice_temperature(mc, instance, T.data()) != MC_OK) return sfail(c, MC_E_ARG, "bad Monte Carlo instance");
+  auto near = [](double a, double b) { return std::fabs(a - b) <= 1e-5 * std::max(1.0, std::fabs(b)); };
+  bool same = near(mcfg.Vgs, q->h_x[0]) && near(mcfg.Vds, q->h_x[1]) && near(std::log10(mcfg.N_D_m3 * 1e-6), q->h_x[2]);
+  for (int i = 0; i < nc && same; ++i) same = near(T[i], q->h_x[3 + i]);
+  if (!same) return sfail(c, MC_E_ARG, "the Monte Carlo instance is set up for another bias point or temperature map");
   if (q->warm_substeps < 0 || q->window_substeps < 1) return sfail(c, MC_E_ARG, "bad Monte Carlo window");
   if ((rc = mc_step(mc, q->warm_substeps)) != MC_OK) return rc;
   mc_tally_out t;
   if ((rc = mc_tally(mc, instance, &t, 1)) != MC_OK) return rc;
   if ((rc = mc_step(mc, q->window_substeps)) != MC_OK) return rc;
-  return mc_maps(mc, instance, nullptr, nullptr, h_maps, h_maps + nc);
+  if ((rc = mc_maps(mc, instance, nullptr, nullptr, h_maps, h_maps + nc, nullptr)) != MC_OK) return rc;
+  // a sticky device error raised during the window (the maps are filled)
+  return mc_tally(mc, instance, &t, 0);
 }
 
 int sg_get_params(sg_ctx* c, int member, int layer, float* h_W, float* h_b) {

@@ -44,6 +44,14 @@ class McTallyOut(C.Structure):
                 ("weight", C.c_double), ("drain_current_A", C.c_double), ("flags", C.c_int32)]
 
 
+class McObservablesOut(C.Structure):
+    _fields_ = [("intervals", C.c_uint32), ("t_window_fs", C.c_double), ("drain_current_A", C.c_double),
+                ("source_current_A", C.c_double), ("heat_W", C.c_double), ("emit_W", C.c_double),
+                ("drift_velocity_ms", C.c_double * 3), ("mean_energy_eV", C.c_double),
+                ("valley_fraction", C.c_double * 3), ("half_mean", C.c_double * 4), ("half_se", C.c_double * 4),
+                ("steady", C.c_int32)]
+
+
 class McParticlesView(C.Structure):
     _fields_ = [("kx", C.c_void_p), ("ky", C.c_void_p), ("kz", C.c_void_p), ("x", C.c_void_p),
                 ("y", C.c_void_p), ("z", C.c_void_p), ("meta", C.c_void_p), ("capacity", C.c_int32),
@@ -52,8 +60,8 @@ class McParticlesView(C.Structure):
 
 EXPORTS = ["mc_status_string", "mc_last_error", "mc_workspace_bytes", "mc_init", "mc_destroy",
            "mc_set_lattice_temperature", "mc_set_tables", "mc_step", "poisson_update", "mc_tally", "mc_maps",
-           "mc_history", "mc_particles", "mc_read_particles", "mc_write_particles", "mc_read_fields",
-           "mc_read_tables", "mc_set_launch", "mc_get_launch", "mc_get_ncell", "mc_occupancy", "mc_set_variant", "mc_use_graph", "mc_profile", "mc_profile_read",
+           "mc_history", "mc_observables", "mc_particles", "mc_read_particles", "mc_write_particles", "mc_read_fields",
+           "mc_read_tables", "mc_get_config", "mc_get_lattice_temperature", "mc_set_launch", "mc_get_launch", "mc_get_ncell", "mc_occupancy", "mc_set_variant", "mc_use_graph", "mc_profile", "mc_profile_read",
            "mc_checkpoint", "mc_restore"]
 
 _lib = None
@@ -78,13 +86,16 @@ def lib():
         L.mc_step.argtypes = [vp, C.c_int]
         L.poisson_update.argtypes = [vp]
         L.mc_tally.argtypes = [vp, C.c_int, C.POINTER(McTallyOut), C.c_int]
-        L.mc_maps.argtypes = [vp, C.c_int, u64p, u64p, dp, dp]
+        L.mc_maps.argtypes = [vp, C.c_int, u64p, u64p, dp, dp, dp]
+        L.mc_observables.argtypes = [vp, C.c_int, C.POINTER(McObservablesOut)]
         L.mc_history.argtypes = [vp, C.c_int, dp, C.c_int, C.POINTER(C.c_int)]
         L.mc_particles.argtypes = [vp, C.c_int, C.POINTER(McParticlesView)]
         L.mc_read_particles.argtypes = [vp, C.c_int, dp, dp, i32p, i32p, u32p]
         L.mc_write_particles.argtypes = [vp, C.c_int, dp, dp, i32p, i32p, u32p]
         L.mc_read_fields.argtypes = [vp, C.c_int, dp, dp, u32p]
         L.mc_read_tables.argtypes = [vp, C.c_int, dp, dp, dp, dp]
+        L.mc_get_config.argtypes = [vp, C.c_int, C.POINTER(McConfig)]
+        L.mc_get_lattice_temperature.argtypes = [vp, C.c_int, dp]
         L.mc_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.mc_get_launch.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.mc_get_ncell.argtypes = [vp, C.POINTER(C.c_int)]
@@ -226,10 +237,22 @@ class Ensemble:
     def mc_maps(self, inst: int = 0):
         n = self.ncell
         heat4 = np.zeros((n, 4), np.uint64); dens = np.zeros(n, np.uint64)
-        q = np.zeros(n); d = np.zeros(n)
+        q = np.zeros(n); d = np.zeros(n); e = np.zeros(n)
         self._chk(lib().mc_maps(self._ctx, int(inst), _p(heat4, C.c_uint64), _p(dens, C.c_uint64),
-                                _p(q, C.c_double), _p(d, C.c_double)), "mc_maps")
-        return dict(heat4=heat4, dens_sum=dens, heat_Wm3=q, density_m3=d)
+                                _p(q, C.c_double), _p(d, C.c_double), _p(e, C.c_double)), "mc_maps")
+        return dict(heat4=heat4, dens_sum=dens, heat_Wm3=q, density_m3=d, emit_Wm3=e)
+
+    def mc_observables(self, inst: int = 0, check: bool = True) -> dict:
+        o = McObservablesOut()
+        rc = lib().mc_observables(self._ctx, int(inst), C.byref(o))
+        if check:
+            self._chk(rc, "mc_observables")
+        return dict(intervals=o.intervals, t_window_fs=o.t_window_fs, drain_current_A=o.drain_current_A,
+                    source_current_A=o.source_current_A, heat_W=o.heat_W, emit_W=o.emit_W,
+                    drift_velocity_ms=np.array(o.drift_velocity_ms[:]), mean_energy_eV=o.mean_energy_eV,
+                    valley_fraction=np.array(o.valley_fraction[:]),
+                    half_mean=np.array(o.half_mean[:]).reshape(2, 2), half_se=np.array(o.half_se[:]).reshape(2, 2),
+                    steady=o.steady, status=rc)
 
     def mc_history(self, inst: int = 0, max_rows: int = 8192) -> np.ndarray:
         rows = np.zeros((max_rows, 8)); n = C.c_int(0)
@@ -271,6 +294,17 @@ class Ensemble:
         self._chk(lib().mc_read_tables(self._ctx, int(inst), _p(s, C.c_double), _p(k, C.c_double),
                                        _p(f, C.c_double), _p(g, C.c_double)), "mc_read_tables")
         return s, k, f, g
+
+    def mc_get_config(self, inst: int = 0) -> McConfig:
+        c = McConfig()
+        self._chk(lib().mc_get_config(self._ctx, int(inst), C.byref(c)), "mc_get_config")
+        return c
+
+    def mc_get_lattice_temperature(self, inst: int = 0) -> np.ndarray:
+        T = np.zeros(self.ncell)
+        self._chk(lib().mc_get_lattice_temperature(self._ctx, int(inst), _p(T, C.c_double)),
+                  "mc_get_lattice_temperature")
+        return T
 
     def mc_set_launch(self, block: int, tile: int):
         self._chk(lib().mc_set_launch(self._ctx, int(block), int(tile)), "mc_set_launch")

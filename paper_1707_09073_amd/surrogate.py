@@ -5,9 +5,15 @@ The thermal side of the paper's hybrid iteration (coupling paragraph) needs
 the electron MC's per-subcell heat generation for every new lattice
 temperature field.  The surrogate learns that map from runs of the MC itself
 and hands the query back to the MC whenever its own predicted error exceeds
-the tolerance or the query leaves the training box.  Host code here only
-sequences library calls (batched MC contexts, BF16 MFMA training and
-inference kernels); every arithmetic step runs in libgfmc.so.
+the tolerance or the query leaves the training box.  The Monte Carlo runs
+and the network's forward, backward and Adam steps run in libgfmc.so
+(batched MC contexts, BF16 MFMA kernels).  Around them this module does the
+batch bookkeeping in NumPy on the host: the target encoding (unit shape and
+log-norm per map) and its decoding, the predicted error from the ensemble
+spread, its calibration on held-out points, the training-box check and the
+data statistics for z-scoring.  The decoding and the predicted error follow
+the same definitions as the library's one-query entry point
+sg_predict_or_mc, and are checked against the oracle's.
 """
 from __future__ import annotations
 

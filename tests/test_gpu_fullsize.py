@@ -137,3 +137,41 @@ def test_full_size_fp32_invariants(G, block, tile, variant):
         assert r[:, d].min() >= 0.0 and r[:, d].max() <= cfg["L_nm"][d]
     _say(f"full size fp32: {n_alive} alive, {t['selections']} selections, drain current "
          f"{t['drain_current_A']:.3e} A")
+
+
+def test_full_size_fp32_heat_map_matches_oracle(G, oracle_mod):
+    """The benchmark's precision at its size: FP32 state for 1e7 electrons
+    at the benchmark's launch shape, 20 intervals from the initial ensemble,
+    against the FP64 oracle run on the same workload with another seed (two
+    independent samples).  The 1800-subcell net heat map agrees cell by cell
+    within 1% or 3 sigma (counting noise of both runs), with at most 1% of
+    the cells beyond 3 sigma, none beyond 5, and chi-square per cell within
+    three standard deviations of 1; the net drain exits within 1% or three
+    times a conservative counting sigma (exits plus injections of both)."""
+    cfg = W.large_device_config()
+    K = cfg["substeps"]
+    _say(f"full size fp32 heat map vs oracle: {cfg['n_particles']} electrons, 20 intervals")
+    e = G.Ensemble(cfg)
+    e.mc_set_launch(512, 3584)
+    e.mc_step(20 * K)
+    t = e.mc_tally()
+    hg = e.mc_maps()["heat4"].astype(float)
+    e.close()
+    ref = dict(cfg, precision="fp64", seed=cfg["seed"] + 17)
+    _say("full size fp32 heat map: oracle, 20 intervals")
+    o = oracle_mod.Oracle(ref)
+    o.run(20)
+    ho = o.maps()[0].astype(float)
+    c = o.counts()
+    net_g = hg[:, 0] - hg[:, 1] + hg[:, 2] - hg[:, 3]
+    net_o = ho[:, 0] - ho[:, 1] + ho[:, 2] - ho[:, 3]
+    z = (net_g - net_o) / np.sqrt(np.maximum(hg.sum(axis=1) + ho.sum(axis=1), 1.0))
+    ok = (np.abs(net_g - net_o) <= 0.01 * np.abs(net_o)) | (np.abs(z) <= 3.0)
+    _say(f"full size heat map: chi2/cell {np.mean(z * z):.3f}, max |z| {np.abs(z).max():.2f}, "
+         f"{int((~ok).sum())} cells out")
+    assert ok.mean() >= 0.99 and np.abs(z).max() <= 5.0
+    assert np.mean(z * z) <= 1 + 3 * np.sqrt(2 / z.size)
+    nd_g = float(t["exits"][1]) - float(t["injections"][1])
+    nd_o = float(c["exits"][1]) - float(c["injections"][1])
+    sig = np.sqrt(t["exits"][1] + t["injections"][1] + c["exits"][1] + c["injections"][1])
+    assert abs(nd_g - nd_o) <= max(0.01 * abs(nd_o), 3 * sig), (nd_g, nd_o, sig)

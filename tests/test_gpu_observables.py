@@ -1,0 +1,234 @@
+"""GPU parity of the window observables and of the cases the per-electron
+parity tests do not reach: the derived maps, currents, powers, history rows
+and steady-state test against the oracle; the 2000-step bulk run; a batched
+context against one oracle per instance; energies above the table top; a
+non-finite electron; a particle write right after an asynchronous step."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1707_09073_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-10
+K_FLOOR = 0.1
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1707_09073_amd import gfmc
+    gfmc.lib()
+    return gfmc
+
+
+def _by_id(p):
+    alive = p["alive"] == 1
+    order = np.argsort(p["id"][alive], kind="stable")
+    return {key: p[key][alive][order] for key in ("id", "valley", "k", "r")}
+
+
+def _compare_particles(gp, op, what=""):
+    g, o = _by_id(gp), _by_id(op)
+    assert np.array_equal(g["id"], o["id"]), what + " id"
+    assert np.array_equal(g["valley"], o["valley"]), what + " valley"
+    err = np.abs(g["k"] - o["k"]) / np.maximum(np.linalg.norm(o["k"], axis=1), K_FLOOR)[:, None]
+    assert err.max(initial=0.0) <= REL, f"{what} k rel err {err.max():.3e}"
+    errr = np.abs(g["r"] - o["r"]) / np.maximum(np.abs(o["r"]), 1.0)
+    assert errr.max(initial=0.0) <= REL, f"{what} r rel err {errr.max():.3e}"
+
+
+def _compare_counts(gt, oc):
+    assert gt["selections"] == oc["selections"]
+    assert gt["self_events"] == oc["self_events"]
+    assert gt["overflow"] == oc["overflow"]
+    assert np.array_equal(gt["real"], oc["real"])
+    assert np.array_equal(gt["exits"], oc["exits"])
+    assert np.array_equal(gt["injections"], oc["injections"])
+
+
+def test_device_observables_match_oracle(G, oracle_mod):
+    """Gated device at Vds = 3 V, Vgs = -0.5 V, FP64: after 8 warm-up
+    intervals, a 22-interval window.  The derived maps (net and emission-only
+    power density, electron density), drain and source current, net and
+    emitted power, the history rows and the steady-state verdict equal the
+    oracle's: the counts behind them are identical, so the derived values
+    agree to rounding (1e-12); the potential and field columns to the
+    Poisson parity (1e-9)."""
+    cfg = W.device_config(n_particles=20000, precision="fp64", Vds=3.0, Vgs=-0.5)
+    _say("device observables: 20000 electrons, 8 + 22 intervals")
+    e = G.Ensemble(cfg)
+    o = oracle_mod.Oracle(cfg)
+    e.mc_step(80)
+    o.run(8)
+    e.mc_tally(reset_window=True)
+    o.reset_window()
+    e.mc_step(220)
+    o.run(22)
+    _compare_counts(e.mc_tally(), o.counts())
+    m = e.mc_maps()
+    qn, qe, n = o.power_maps()
+    for key, ref in (("heat_Wm3", qn), ("emit_Wm3", qe), ("density_m3", n)):
+        scale = np.abs(ref).max()
+        assert scale > 0, key
+        assert np.abs(m[key] - ref).max() <= 1e-12 * scale, key
+    ob, oo = e.mc_observables(), o.observables()
+    assert ob["intervals"] == oo["intervals"] == 22
+    assert ob["t_window_fs"] == pytest.approx(oo["t_window_s"] * 1e15, rel=1e-14)
+    for a, b in (("drain_current_A", "I_D"), ("source_current_A", "I_S"), ("heat_W", "P_heat_W"),
+                 ("emit_W", "P_emit_W")):
+        assert ob[a] == pytest.approx(oo[b], rel=1e-12, abs=1e-30), a
+    assert ob["drain_current_A"] > 0 and ob["heat_W"] > 0 and ob["emit_W"] > ob["heat_W"]
+    hg, ho = e.mc_history(), o.history()
+    assert hg.shape == ho.shape == (22, 8)
+    assert np.array_equal(hg[:, [0, 1, 2, 3, 4, 7]], ho[:, [0, 1, 2, 3, 4, 7]])
+    assert np.abs(hg[:, 5] - ho[:, 5]).max() <= 1e-9 * np.abs(ho[:, 5]).max()
+    assert np.abs(hg[:, 6] - ho[:, 6]).max() <= 1e-9 * np.abs(ho[:, 6]).max()
+    assert ob["steady"] == oo["steady"] and ob["steady"] in (0, 1)
+    assert np.allclose(ob["half_mean"][0], oo["half_mean"][0], rtol=1e-12)
+    assert np.allclose(ob["half_se"][0], oo["half_se"][0], rtol=1e-9)
+    assert np.allclose(ob["half_mean"][1], oo["half_mean"][1], rtol=1e-9)
+
+
+def test_bulk_config1_full_run_observables(G, oracle_mod):
+    """The bulk run at its full length: 10,000 electrons, 10 kV/cm, 1e17
+    cm^-3, 300 K, 2,000 steps of 1 fs, FP64.  Over steps 1001-2000 the drift
+    velocity, the mean energy and the valley occupancy agree with the
+    oracle's within 1% or 3 standard errors (rounding differences separate
+    the trajectories after some hundred events, so the two runs are compared
+    as samples), and both runs pass the steady-state test."""
+    cfg = W.bulk_config(n_particles=10000, substeps=1)
+    _say("bulk config 1: 10000 electrons x 2000 steps")
+    e = G.Ensemble(cfg)
+    o = oracle_mod.Oracle(cfg)
+    e.mc_step(1000)
+    o.run(1000)
+    e.mc_tally(reset_window=True)
+    o.reset_window()
+    e.mc_step(1000)
+    o.run(1000)
+    ob, oo = e.mc_observables(), o.observables()
+    assert ob["steady"] == 1 and oo["steady"] == 1
+    hg, ho = e.mc_history(), o.history()
+    assert hg.shape == ho.shape == (1000, 8)
+    for col, a, b in ((3, ob["drift_velocity_ms"][2], oo["v_drift_ms"][2]),
+                      (4, ob["mean_energy_eV"], oo["mean_E_eV"])):
+        sa = (hg[:, col] / hg[:, 0]).reshape(10, -1).mean(1).std(ddof=1) / math.sqrt(10)
+        sb = (ho[:, col] / ho[:, 0]).reshape(10, -1).mean(1).std(ddof=1) / math.sqrt(10)
+        scale = 1e6 if col == 3 else 1.0
+        assert abs(a - b) <= max(0.01 * abs(b), 3 * scale * math.hypot(sa, sb)), (col, a, b, sa, sb)
+    assert oo["v_drift_ms"][2] < 0                       # electrons drift against the field along c
+    for v in range(3):
+        a, b = ob["valley_fraction"][v], oo["valley_fraction"][v]
+        assert abs(a - b) <= max(0.01 * b, 3 * math.sqrt(max(b, 1e-12) / 10000 / 10) + 1e-9), (v, a, b)
+    assert ob["valley_fraction"].sum() == pytest.approx(1.0, rel=1e-12)
+
+
+def test_batched_instances_match_one_oracle_each(G, oracle_mod):
+    """Three bias points in one FP64 context, each with its own seed, bias,
+    doping, ensemble size and instance index (which enters every random
+    stream), against three oracles: per electron 1e-10, tallies exact."""
+    cfgs = []
+    for i, (vgs, vds, dop, n, seed) in enumerate(((0.0, 4.0, 1e18, 9000, 101), (-1.5, 2.0, 3e17, 6500, 202),
+                                                  (-0.5, 7.0, 2e18, 12000, 303))):
+        c = W.device_config(n_particles=n, precision="fp64", Vgs=vgs, Vds=vds, doping_cm3=dop, seed=seed)
+        c["instance"] = 7 + 5 * i
+        cfgs.append(c)
+    _say("batched fp64: 3 instances vs 3 oracles")
+    e = G.Ensemble(cfgs)
+    e.mc_step(200)
+    for i, c in enumerate(cfgs):
+        o = oracle_mod.Oracle(c)
+        o.run(20)
+        _compare_particles(e.mc_read_particles(i), o.particles(), what=f"instance {i}")
+        _compare_counts(e.mc_tally(i), o.counts())
+        m = e.mc_maps(i)
+        heat, dens = o.maps()
+        assert np.array_equal(m["heat4"], heat) and np.array_equal(m["dens_sum"], dens)
+        phi, _, cnt = e.mc_read_fields(i)
+        pho, _, no = o.fields()
+        assert np.array_equal(cnt, no)
+        assert np.abs(phi - pho).max() <= REL * np.abs(pho).max()
+
+
+@pytest.mark.parametrize("variant", [0, 2])
+def test_energies_above_the_table_top(G, oracle_mod, variant):
+    """500 kV/cm: a few percent of the selections find the electron above the
+    3 eV table top (clamped to the last bin and counted).  Electrons and
+    every count, overflow included, equal the oracle's."""
+    cfg = W.bulk_config(n_particles=4000, substeps=10, field_V_per_nm=5e-2)
+    e = G.Ensemble(cfg)
+    e.mc_set_variant(variant)
+    o = oracle_mod.Oracle(cfg)
+    e.mc_step(200)
+    o.run(20)
+    t, c = e.mc_tally(), o.counts()
+    assert c["overflow"] > 1000
+    _compare_counts(t, c)
+    _compare_particles(e.mc_read_particles(), o.particles(), what="overflow")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_non_finite_electron_is_flagged(G, oracle_mod, prec):
+    """An electron written with a NaN wave vector: the step completes, the
+    instance's sticky flag reads MC_E_NAN, and in bulk mode (no coupling
+    between electrons) every other electron is unaffected."""
+    cfg = W.bulk_config(n_particles=3000, substeps=10, precision=prec)
+    e = G.Ensemble(cfg)
+    p = e.mc_read_particles()
+    p["k"][17] = np.nan
+    e.mc_write_particles(0, p["k"], p["r"], p["valley"], p["alive"], p["id"])
+    e.mc_step(50)
+    t = e.mc_tally(check=False)
+    assert t["status"] == G.MC_E_NAN and t["flags"] == G.MC_E_NAN
+    if prec == "fp64":
+        o = oracle_mod.Oracle(cfg)
+        q = o.particles()
+        q["alive"][17] = 0
+        o.set_particles(q["k"], q["r"], q["valley"], q["alive"], q["id"])
+        o.run(5)
+        g = e.mc_read_particles()
+        g["alive"][17] = 0
+        _compare_particles(g, o.particles(), what="others")
+
+
+def test_write_right_after_an_asynchronous_step(G):
+    """A particle write issued while the context's stream still runs the
+    kernels of a step waits for them: the result equals the same sequence
+    with a synchronising read in between."""
+    cfg = W.device_config(n_particles=30000, precision="fp32", Vds=5.0)
+    a, b = G.Ensemble(cfg), G.Ensemble(cfg)
+    a.mc_step(100)
+    p = a.mc_read_particles()                 # synchronises
+    p["k"] *= 1.01                            # a state the step itself would not produce
+    for e in (a, b):
+        if e is b:
+            b.mc_step(100)                    # still running when the write is issued
+        e.mc_write_particles(0, p["k"], p["r"], p["valley"], p["alive"], p["id"])
+        e.mc_step(100)
+    pa, pb = a.mc_read_particles(), b.mc_read_particles()
+    for key in pa:
+        assert np.array_equal(pa[key], pb[key]), key
+
+
+def test_rejected_write_changes_nothing(G):
+    cfg = W.bulk_config(n_particles=2000, substeps=10)
+    e = G.Ensemble(cfg)
+    before = e.mc_read_particles()
+    bad = {k: v.copy() for k, v in before.items()}
+    bad["k"] += 1.0
+    bad["valley"][1999] = 3                   # invalid: the whole write is refused
+    with pytest.raises(G.MCError):
+        e.mc_write_particles(0, bad["k"], bad["r"], bad["valley"], bad["alive"], bad["id"])
+    after = e.mc_read_particles()
+    for key in before:
+        assert np.array_equal(before[key], after[key]), key

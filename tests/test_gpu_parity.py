@@ -402,38 +402,63 @@ def test_capacity_exhaustion_is_reported(G, variant):
     assert len(np.unique(ids)) == len(ids)
 
 
+def _heat_map_agreement(hg, ho, rel=0.01):
+    """Per-subcell net phonon emission (LO plus intervalley, equal phonon
+    energies) of two independent runs.  The variance of a cell's net count
+    is taken as its emission plus absorption count (Poisson; the measured
+    dispersion of two oracle runs with different seeds is 0.8 of it).
+    Returns the per-cell deviations in units of sigma and whether each cell
+    lies within rel or 3 sigma."""
+    net_g = hg[:, 0] - hg[:, 1] + hg[:, 2] - hg[:, 3]
+    net_o = ho[:, 0] - ho[:, 1] + ho[:, 2] - ho[:, 3]
+    var = hg.sum(axis=1) + ho.sum(axis=1)
+    z = (net_g - net_o) / np.sqrt(np.maximum(var, 1.0))
+    ok = (np.abs(net_g - net_o) <= rel * np.abs(net_o)) | (np.abs(z) <= 3.0)
+    return z, ok
+
+
 def test_fp32_device_statistics_match_fp64_oracle(G, oracle_mod):
-    """FP32 state/flight in device mode (hot-spot temperature map): scattering
-    selections, real events per mechanism class, exits and the net heat of
-    the FP32 path agree with the FP64 oracle within 2% (independent random
-    streams; 2e5 electrons x 20 intervals)."""
-    cfg = W.device_config(n_particles=200000, precision="fp32")
-    cfg["T_cells"] = W.hotspot_T_map(cfg)
-    _say("fp32 device statistics vs oracle")
-    e = G.Ensemble(cfg)
-    _, _, _, g32 = e.mc_read_tables()
-    o = oracle_mod.Oracle(dict(cfg, precision="fp64"))
-    assert np.allclose(g32, o.gamma(), rtol=1e-6)
-    e.mc_tally(reset_window=True)
-    o.reset_window()
-    e.mc_step(200)
+    """FP32 state/flight in device mode (hot-spot temperature map, 2e5
+    electrons, 20 intervals from the initial ensemble) against the FP64
+    oracle, as independent samples: the GPU runs six replicas on other seeds.
+    Selections, real events per mechanism class, drain exits and injections
+    and the net LO heat agree within 1% or 3 sigma (sigma from the replicas'
+    spread); the 1800-subcell net heat map agrees cell by cell within 1% or
+    3 sigma (counting noise) with the expected share of 3-sigma excursions:
+    at most 1% of the cells beyond, none beyond 5 sigma, and chi-square per
+    cell within three standard deviations of 1."""
+    base = W.device_config(n_particles=200000, precision="fp64")
+    base["T_cells"] = W.hotspot_T_map(base)
+    _say("fp32 device statistics vs oracle: 6 GPU replicas")
+    o = oracle_mod.Oracle(base)
     o.run(20)
-    t, c = e.mc_tally(), o.counts()
-    for a, b, name in ((t["selections"], c["selections"], "selections"),
-                       (t["real"][:, 0].sum(), c["real"][:, 0].sum(), "acoustic"),
-                       (t["real"][:, 1].sum(), c["real"][:, 1].sum(), "impurity"),
-                       (t["real"][:, 2:4].sum(), c["real"][:, 2:4].sum(), "polar optical")):
-        assert abs(a - b) <= 0.02 * b, (name, a, b)
-    hg, ho = e.mc_maps()["heat4"].astype(float), o.maps()[0].astype(float)
-    net_g, net_o = (hg[:, 0] - hg[:, 1]).sum(), (ho[:, 0] - ho[:, 1]).sum()
-    assert abs(net_g - net_o) <= 0.03 * abs(net_o) + 3 * math.sqrt(hg[:, :2].sum() + ho[:, :2].sum())
-    # the heat map along the channel: net LO-phonon emission per slice of 18
-    # subcells, within 1% or 3 sigma (counting noise of both runs) in at
-    # least 98 of the 100 slices and within 5 sigma in all
-    P = cfg["n_cells"][1] * cfg["n_cells"][2]
-    col_g = (hg[:, 0] - hg[:, 1]).reshape(-1, P).sum(axis=1)
-    col_o = (ho[:, 0] - ho[:, 1]).reshape(-1, P).sum(axis=1)
-    sig = np.sqrt(hg[:, :2].sum(axis=1).reshape(-1, P).sum(axis=1) + ho[:, :2].sum(axis=1).reshape(-1, P).sum(axis=1))
-    dev = np.abs(col_g - col_o)
-    ok = (dev <= 0.01 * np.abs(col_o)) | (dev <= 3 * sig)
-    assert ok.sum() >= 98 and np.all(dev <= np.maximum(0.01 * np.abs(col_o), 5 * sig)), (ok.sum(), dev / sig)
+    c = o.counts()
+    ho = o.maps()[0].astype(float)
+    R = 6
+    stats, maps = [], []
+    for r in range(R):
+        cfg = dict(base, precision="fp32", seed=base["seed"] + 1000 + r)
+        e = G.Ensemble(cfg)
+        if r == 0:
+            _, _, _, g32 = e.mc_read_tables()
+            assert np.allclose(g32, o.gamma(), rtol=1e-6)
+        e.mc_step(200)
+        t = e.mc_tally()
+        h = e.mc_maps()["heat4"].astype(float)
+        stats.append([t["selections"], t["real"][:, 0].sum(), t["real"][:, 1].sum(), t["real"][:, 2:4].sum(),
+                      t["real"][:, 4:].sum(), t["exits"][1], t["injections"][1], (h[:, 0] - h[:, 1]).sum()])
+        maps.append(h)
+        e.close()
+    stats = np.array(stats, float)
+    ref = np.array([c["selections"], c["real"][:, 0].sum(), c["real"][:, 1].sum(), c["real"][:, 2:4].sum(),
+                    c["real"][:, 4:].sum(), c["exits"][1], c["injections"][1], (ho[:, 0] - ho[:, 1]).sum()], float)
+    names = ["selections", "acoustic", "impurity", "polar optical", "intervalley", "drain exits",
+             "drain injections", "net LO heat"]
+    g, sg = stats.mean(0), stats.std(0, ddof=1)
+    for k, name in enumerate(names):
+        bar = max(0.01 * abs(ref[k]), 3 * sg[k] * math.sqrt(1 + 1 / R))
+        assert abs(g[k] - ref[k]) <= bar, (name, g[k], ref[k], sg[k])
+    z, ok = _heat_map_agreement(maps[0], ho)
+    _say(f"heat map: chi2/cell {np.mean(z * z):.3f}, max |z| {np.abs(z).max():.2f}, {int((~ok).sum())} cells out")
+    assert ok.mean() >= 0.99 and np.abs(z).max() <= 5.0
+    assert np.mean(z * z) <= 1 + 3 * math.sqrt(2 / z.size)

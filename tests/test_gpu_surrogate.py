@@ -171,23 +171,49 @@ def test_small_batch_predict_matches_oracle_and_gemm_path(torch_mod, shape):
         assert _rel(s, big_s[lo:hi]) <= 2e-2
 
 
+def test_large_batch_output_layer_matches_oracle(torch_mod):
+    """Batch 4096 through 1803 -> 1024 -> 3600: the output layer has 32 x 29
+    tiles of 128 x 128, enough for the 128 x 128 workgroup tile (the hidden
+    layer, 32 x 8 tiles, takes the 64 x 64 one), in the forward product and
+    in the backward products of the training step."""
+    torch = torch_mod
+    net, (o,), x, y = _make(torch, n_in=1803, n_out=3600, width=1024, depth=1, batch=4096, seed=23)
+    _say("surrogate batch 4096: forward and gradients vs oracle")
+    xd, yd = torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda")
+    out = torch.empty((4096, 3600), device="cuda", dtype=torch.float32)
+    net.sg_forward(0, xd, out)
+    torch.cuda.synchronize()
+    loss_o, dW_o, db_o, pred_o = o.loss_and_grads(x, y)
+    assert _rel(out.cpu().numpy(), pred_o) <= 1e-3
+    loss = net.sg_backward(0, xd, yd)
+    assert loss == pytest.approx(loss_o, rel=1e-4)
+    for l in range(2):
+        dW, db = net.sg_get_grads(0, l)
+        dWo = dW_o[l][:1803] if l == 0 else dW_o[l]
+        dW = dW[:1803] if l == 0 else dW
+        assert _rel(dW, dWo) <= 1e-3, (l, _rel(dW, dWo))
+        assert _rel(db, db_o[l]) <= 1e-3, (l, _rel(db, db_o[l]))
+
+
 def test_predict_or_mc_answers_from_surrogate_or_monte_carlo(torch_mod):
-    """sg_predict_or_mc on a 37 x 2 x 5 device grid.  Within tolerance and the
-    training box: the maps decoded from sg_predict's ensemble mean and the
-    predicted error (calibration x spread), both formed here on the host.
-    Outside the box, or beyond the tolerance: the Monte Carlo of the given
-    context, equal to the same runs through the mc_* calls.  A missing
-    context, or one of another grid, is refused when the Monte Carlo is
-    needed."""
+    """sg_predict_or_mc on a 37 x 2 x 5 device grid, against the oracle: each
+    member's forward by the MLP oracle on the same BF16 weights, the
+    ensemble mean and spread, the decoded maps and the predicted error by the
+    oracle's decode.  Within tolerance and the training box the surrogate
+    answers with those maps (1e-3, the BF16 bar; the spread, a difference of
+    members, to 2e-2).  Outside the box, or beyond the tolerance: the Monte
+    Carlo of the given context, equal to the same runs through the mc_*
+    calls.  A missing context, one of another grid, or one set up for
+    another bias point is refused when the Monte Carlo is needed."""
+    from oracle.mlp_oracle import MLPOracle, bf16, decode_maps, ensemble_mean_spread, predicted_error
     from paper_1707_09073_amd import gfmc, workloads as W
     torch = torch_mod
     cells, L = (37, 2, 5), (370.0, 40.0, 100.0)
     nc = cells[0] * cells[1] * cells[2]
     cfg = W.device_config(n_particles=7777, precision="fp32", Vds=3.0, Vgs=-1.0, n_cells=cells, L_nm=L)
     K = cfg["substeps"]
-    n_in, n_out = 3 + nc, 2 * nc + 2
-    net = gfmc.SurrogateNet(n_in, n_out, width=64, depth=2, ensemble=3, max_batch=8, seed=5)
-    rng = np.random.default_rng(5)
+    n_in, n_out, E = 3 + nc, 2 * nc + 2, 3
+    net = gfmc.SurrogateNet(n_in, n_out, width=64, depth=2, ensemble=E, max_batch=8, seed=5)
     xm = np.concatenate([[-1.0, 3.0, 18.0], np.full(nc, 300.0)])
     xs = np.concatenate([[1.0, 2.0, 0.5], np.full(nc, 20.0)])
     ym = np.zeros(n_out)
@@ -195,22 +221,31 @@ def test_predict_or_mc_answers_from_surrogate_or_monte_carlo(torch_mod):
     ys = np.full(n_out, 0.05)
     ys[-2:] = 0.1
     net.sg_set_normalization(xm, xs, ym, ys)
-    x = (xm + 0.1 * xs * rng.normal(size=n_in)).astype(np.float32)
-    _say("predict_or_mc: surrogate answer")
+    # the features of the context's bias point: Vgs, Vds, log10 doping (cm^-3), T per subcell
+    x = np.concatenate([[cfg["Vgs"], cfg["Vds"], np.log10(cfg["N_D_m3"] * 1e-6)], np.full(nc, cfg["T0_K"])])
+    x = x.astype(np.float32)
+    _say("predict_or_mc: surrogate answer vs the oracle")
+    members = []
+    for e in range(E):
+        Ws, bs = zip(*[net.sg_get_params(e, l) for l in range(3)])
+        o = MLPOracle([bf16(w) for w in Ws], [b.astype(np.float64) for b in bs], xm, xs, ym, ys, n_in)
+        members.append(o.forward(x[None])[0] * net._norm[3].astype(np.float64) + net._norm[2].astype(np.float64))
+    mean_o, spread_o = ensemble_mean_spread(np.stack(members))
+    calib = 1.7
+    maps_o = decode_maps(mean_o, nc)[0]
+    perr_o = predicted_error(mean_o, spread_o, nc, calib)[0]
+    maps, perr, used = net.sg_predict_or_mc(x, calib, tol=1e30)
+    assert not used
+    assert _rel(maps[:nc], maps_o[:nc]) <= 1e-3 and _rel(maps[nc:], maps_o[nc:]) <= 1e-3
+    assert perr == pytest.approx(perr_o, rel=2e-2)
+    # and exactly the decoding of sg_predict's own mean and spread
     xd = torch.tensor(x[None], device="cuda")
     m = torch.empty((1, n_out), device="cuda")
     sd = torch.empty_like(m)
     net.sg_predict(xd, m, sd)
-    m = m.cpu().numpy()[0].astype(np.float64)
-    sd = sd.cpu().numpy()[0].astype(np.float64)
-    ref_maps = np.concatenate([m[:nc] * np.exp(m[2 * nc]), m[nc:2 * nc] * np.exp(m[2 * nc + 1])])
-    spread = max(np.hypot(np.linalg.norm(sd[k * nc:(k + 1) * nc]) / np.linalg.norm(m[k * nc:(k + 1) * nc]),
-                          sd[2 * nc + k]) for k in range(2))
-    calib = 1.7
-    maps, perr, used = net.sg_predict_or_mc(x, calib, tol=1e30)
-    assert not used
-    assert _rel(maps, ref_maps) <= 1e-6
-    assert abs(perr - calib * spread) <= 1e-5 * calib * spread
+    m, sd = m.cpu().numpy().astype(np.float64), sd.cpu().numpy().astype(np.float64)
+    assert _rel(maps, decode_maps(m, nc)[0]) <= 1e-6
+    assert perr == pytest.approx(predicted_error(m, sd, nc, calib)[0], rel=1e-5)
     _say("predict_or_mc: outside the training box")
     ens, ref = gfmc.Ensemble(cfg), gfmc.Ensemble(cfg)
     assert ens.mc_get_ncell() == nc
@@ -237,6 +272,16 @@ def test_predict_or_mc_answers_from_surrogate_or_monte_carlo(torch_mod):
                                           L_nm=(200.0, 20.0, 20.0)))
     with pytest.raises(gfmc.MCError):
         net.sg_predict_or_mc(x, calib, tol=0.0, ens=other, window_substeps=K)
-    for e in (ens, ref, other):
+    wrong_bias = gfmc.Ensemble(dict(cfg, Vds=4.0))
+    with pytest.raises(gfmc.MCError):
+        net.sg_predict_or_mc(x, calib, tol=0.0, ens=wrong_bias, window_substeps=K)
+    with pytest.raises(gfmc.MCError):
+        net.sg_predict_or_mc(x, calib, tol=0.0, ens=ens, instance=1, window_substeps=K)
+    T = np.full(nc, 300.0)
+    T[5] = 310.0
+    hot = gfmc.Ensemble(dict(cfg, T_cells=T))
+    with pytest.raises(gfmc.MCError):
+        net.sg_predict_or_mc(x, calib, tol=0.0, ens=hot, window_substeps=K)
+    for e in (ens, ref, other, wrong_bias, hot):
         e.close()
     net.close()

@@ -46,3 +46,15 @@ def test_rel_l2_and_features():
     assert f[0] == np.float32(cfg["Vgs"]) and f[1] == np.float32(cfg["Vds"])
     assert math.isclose(f[2], math.log10(cfg["N_D_m3"] * 1e-6), rel_tol=1e-6)
     assert np.allclose(f[3:], cfg["T_cells"], rtol=1e-6)
+
+
+def test_host_decode_and_spread_equal_the_oracle():
+    """The batched runtime decodes maps and predicted errors on the host;
+    both equal the oracle's definitions (the ones the library's one-query
+    entry point follows)."""
+    from oracle.mlp_oracle import decode_maps, predicted_error
+    rng = np.random.default_rng(4)
+    mean = S.encode(rng.uniform(1.0, 5.0, (6, 2 * S.N_CELL)) * np.array([[1e12] * S.N_CELL + [1e24] * S.N_CELL]))
+    spread = np.abs(rng.normal(0.0, 0.01, mean.shape))
+    assert np.allclose(S.decode(mean), decode_maps(mean, S.N_CELL), rtol=1e-13, atol=0)
+    assert np.allclose(S.encoded_spread(mean, spread), predicted_error(mean, spread, S.N_CELL, 1.0), rtol=1e-13)
