@@ -128,7 +128,7 @@ def test_bulk_config1_full_run_observables(G, oracle_mod):
         assert abs(a - b) <= max(0.01 * abs(b), 3 * scale * math.hypot(sa, sb)), (col, a, b, sa, sb)
     assert oo["v_drift_ms"][2] < 0                       # electrons drift against the field along c
     for v in range(3):
-        a, b = ob["valley_fraction"][v], oo["valley_fraction"][v]
+        a, b = ob["valley_fraction"][v], oo["valley_frac"][v]
         assert abs(a - b) <= max(0.01 * b, 3 * math.sqrt(max(b, 1e-12) / 10000 / 10) + 1e-9), (v, a, b)
     assert ob["valley_fraction"].sum() == pytest.approx(1.0, rel=1e-12)
 

@@ -214,7 +214,9 @@ def test_predict_or_mc_answers_from_surrogate_or_monte_carlo(torch_mod):
     K = cfg["substeps"]
     n_in, n_out, E = 3 + nc, 2 * nc + 2, 3
     net = gfmc.SurrogateNet(n_in, n_out, width=64, depth=2, ensemble=E, max_batch=8, seed=5)
-    xm = np.concatenate([[-1.0, 3.0, 18.0], np.full(nc, 300.0)])
+    # normalisation centred away from the queried point, so that the members'
+    # different weights give different answers
+    xm = np.concatenate([[-0.5, 4.0, 17.5], 290.0 + 5.0 * np.sin(np.arange(nc))])
     xs = np.concatenate([[1.0, 2.0, 0.5], np.full(nc, 20.0)])
     ym = np.zeros(n_out)
     ym[-2:] = [10.0, 20.0]  # log-norms of the two maps
