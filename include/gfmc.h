@@ -352,6 +352,21 @@ int sg_train_step(sg_ctx *ctx, int member, const float *d_x, const float *d_y, i
  * sample standard deviation over the members), asynchronous.  The spread is
  * per output; sg_predict_or_mc reduces it to one predicted relative error. */
 int sg_predict(sg_ctx *ctx, const float *d_x, int batch, float *d_mean, float *d_std);
+/* sg_predict for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid it): the same
+ * small-batch kernels, with their scratch (normalised inputs, activations,
+ * split partial sums, the members' predictions) in a static 8 MiB device
+ * array of the library instead of the context's workspace.  Each GPU holds
+ * its own array until the process ends (its address is taken once per
+ * device at sg_init); every call on a GPU shares it, so calls that overlap
+ * on one GPU race.  Nothing in it needs clearing: each call writes what it
+ * reads.  batch 1..8 (and at most the context's max_batch); MC_E_ARG for a
+ * larger batch or a network whose scratch would not fit (the split count
+ * shrinks to fit before that: 4 members of 1024 wide with 3602 outputs fit at
+ * batch 8).  Results equal sg_predict's up to the order of the split sums.
+ * Allocates nothing; asynchronous on the context's stream. */
+int sg_predict_static(sg_ctx *ctx, const float *d_x, int batch, float *d_mean, float *d_std);
+
 /* FP32 master parameters and last gradients of one layer: W [K][N], b [N]. */
 int sg_get_params(sg_ctx *ctx, int member, int layer, float *h_W, float *h_b);
 int sg_set_params(sg_ctx *ctx, int member, int layer, const float *h_W, const float *h_b);

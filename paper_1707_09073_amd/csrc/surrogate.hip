@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -115,6 +117,7 @@ struct sg_ctx {
   hipStream_t st = nullptr;
   std::vector<int> step;  // Adam step per member
   bool bad_gemm = false;  // a GEMM was refused (misaligned operands)
+  int dev = 0;            // device current at sg_init
   std::string err;
   template <typename T> T* p(size_t o) { return reinterpret_cast<T*>(ws + o); }
 };
@@ -193,14 +196,26 @@ void enqueue_forward(sg_ctx* c, int e, const float* d_x, int batch, float* out) 
   }
 }
 
+// Scratch of the small-batch forward: normalised BF16 inputs [batch][K0p],
+// two activation buffers [2][member][msmall][width], split partials
+// [member][S][batch][N] with S at most max_split, and the members'
+// normalised predictions [member][batch][n_out].
+struct SmallScratch {
+  bf16* X0;
+  bf16* Asm;
+  float* P;
+  float* preds;
+  int max_split;
+};
+
 // Small-batch forward of every member (batch <= msmall): split-K GEMV per
 // layer over all members, then the ordered split sum with the epilogue.
-// Normalised predictions to preds [member][batch][n_out].
-void enqueue_forward_small(sg_ctx* c, const float* d_x, int batch, float* preds) {
+// Normalised predictions to sc.preds [member][batch][n_out].
+void enqueue_forward_small(sg_ctx* c, const float* d_x, int batch, const SmallScratch& sc) {
   const SgLayout& s = c->s;
   const int E = c->c.ensemble, width = c->c.width;
   k_input<<<blocks((long)batch * s.K0p), 256, 0, c->st>>>(d_x, batch, c->c.n_in, c->p<float>(s.xmean),
-                                                           c->p<float>(s.xstd), c->p<bf16>(s.X0), s.K0p);
+                                                           c->p<float>(s.xstd), sc.X0, s.K0p);
   const size_t abuf = (size_t)E * s.msmall * width;  // one activation buffer, all members
   int cur = -1;
   for (int l = 0; l < s.L; ++l) {
@@ -208,17 +223,17 @@ void enqueue_forward_small(sg_ctx* c, const float* d_x, int batch, float* preds)
     GemvArgs g;
     std::memset(&g, 0, sizeof(g));
     if (l == 0) {
-      g.X = c->p<bf16>(s.X0); g.ldx = s.K0p; g.xse = 0;
+      g.X = sc.X0; g.ldx = s.K0p; g.xse = 0;
     } else {
-      g.X = c->p<bf16>(s.Asm) + (size_t)cur * abuf; g.ldx = width; g.xse = (long)s.msmall * width;
+      g.X = sc.Asm + (size_t)cur * abuf; g.ldx = width; g.xse = (long)s.msmall * width;
     }
     for (int e = 0; e < E; ++e) g.W[e] = c->p<bf16>(s.lo[e][l].Wb);
     g.ldw = s.N[l];
     g.M = batch; g.N = s.N[l]; g.K = s.K[l];
     const int ncb = (g.N + kGvCols - 1) / kGvCols;
     // about a thousand wavefronts per launch, at least 4 rows per split
-    g.S = std::max(1, std::min({kGvMaxSplit, 1024 / (ncb * E), g.K / 4}));
-    g.P = c->p<float>(s.gvp);
+    g.S = std::max(1, std::min({sc.max_split, 1024 / (ncb * E), g.K / 4}));
+    g.P = sc.P;
     dim3 grid(ncb, g.S, E);
     if (batch <= 1) k_gemv<1><<<grid, 64, 0, c->st>>>(g);
     else if (batch <= 2) k_gemv<2><<<grid, 64, 0, c->st>>>(g);
@@ -229,17 +244,47 @@ void enqueue_forward_small(sg_ctx* c, const float* d_x, int batch, float* preds)
     r.P = g.P; r.S = g.S; r.M = batch; r.N = g.N; r.E = E;
     for (int e = 0; e < E; ++e) r.bias[e] = c->p<float>(s.lo[e][l].b);
     if (last) {
-      r.n_valid = c->c.n_out; r.outf = preds; r.ldo = c->c.n_out; r.ofs_e = (long)batch * c->c.n_out;
+      r.n_valid = c->c.n_out; r.outf = sc.preds; r.ldo = c->c.n_out; r.ofs_e = (long)batch * c->c.n_out;
       k_gemv_reduce<true><<<blocks((long)E * batch * r.n_valid), 256, 0, c->st>>>(r);
     } else {
       const int nxt = cur == 0 ? 1 : 0;
-      r.n_valid = g.N; r.outb = c->p<bf16>(s.Asm) + (size_t)nxt * abuf; r.ldo = width;
+      r.n_valid = g.N; r.outb = sc.Asm + (size_t)nxt * abuf; r.ldo = width;
       r.ofs_e = (long)s.msmall * width;
       k_gemv_reduce<false><<<blocks((long)E * batch * r.n_valid), 256, 0, c->st>>>(r);
       cur = nxt;
     }
   }
 }
+
+SmallScratch workspace_scratch(sg_ctx* c) {
+  const SgLayout& s = c->s;
+  return SmallScratch{c->p<bf16>(s.X0), c->p<bf16>(s.Asm), c->p<float>(s.gvp), c->p<float>(s.preds), kGvMaxSplit};
+}
+
+// The allocation-free small-batch predictor's scratch: one array per GPU,
+// held until the process ends, shared by every call on that GPU.  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// device that is current (the array's name is a host-side stand-in).
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char sg_static_scratch[kStaticScratchBytes];
+std::mutex g_static_mu;
+std::map<int, unsigned char*> g_static_ptr;  // device -> address of its sg_static_scratch
+
+// Address of the static scratch on device `dev` (current), looked up once per
+// device.
+hipError_t static_scratch_of(int dev, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  auto it = g_static_ptr.find(dev);
+  if (it != g_static_ptr.end()) { *out = it->second; return hipSuccess; }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(sg_static_scratch));
+  if (e != hipSuccess) return e;
+  g_static_ptr[dev] = (unsigned char*)ptr;
+  *out = (unsigned char*)ptr;
+  return hipSuccess;
+}
+
+size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -263,6 +308,11 @@ int sg_init(sg_ctx** out, const sg_config* cfg, void* d_ws, size_t bytes, void* 
   c->st = (hipStream_t)stream;
   c->step.assign(cfg->ensemble, 0);
   *out = c;
+  SGCHK(c, hipGetDevice(&c->dev));
+  {
+    unsigned char* scr = nullptr;  // the allocation-free predictor's scratch on this device
+    SGCHK(c, static_scratch_of(c->dev, &scr));
+  }
   SGCHK(c, hipMemsetAsync(c->ws, 0, s.total, c->st));
   for (int e = 0; e < cfg->ensemble; ++e)
     for (int l = 0; l < s.L; ++l) {
@@ -439,7 +489,7 @@ int sg_predict(sg_ctx* c, const float* d_x, int batch, float* d_mean, float* d_s
   const SgLayout& s = c->s;
   const long per = (long)batch * c->c.n_out;
   if (batch <= s.msmall) {
-    enqueue_forward_small(c, d_x, batch, c->p<float>(s.preds));
+    enqueue_forward_small(c, d_x, batch, workspace_scratch(c));
   } else {
     for (int e = 0; e < c->c.ensemble; ++e)
       enqueue_forward(c, e, d_x, batch, c->p<float>(s.preds) + (size_t)e * per);
@@ -448,6 +498,34 @@ int sg_predict(sg_ctx* c, const float* d_x, int batch, float* d_mean, float* d_s
                                              c->p<float>(s.ymean), c->p<float>(s.ystd), d_mean, d_std);
   SGCHK(c, hipGetLastError());
   if (c->bad_gemm) return sfail(c, MC_E_ARG, "GEMM operands not 16-byte aligned");
+  return MC_OK;
+}
+
+int sg_predict_static(sg_ctx* c, const float* d_x, int batch, float* d_mean, float* d_std) {
+  if (!c || !d_x || !d_mean || batch < 1 || batch > c->s.msmall) return sfail(c, MC_E_ARG, "bad argument");
+  const SgLayout& s = c->s;
+  const int E = c->c.ensemble;
+  unsigned char* base = nullptr;
+  SGCHK(c, static_scratch_of(c->dev, &base));
+  const size_t b_x0 = up256(2 * (size_t)batch * s.K0p);
+  const size_t b_asm = up256(2 * 2 * (size_t)E * s.msmall * c->c.width);
+  const size_t b_pred = up256(4 * (size_t)E * batch * c->c.n_out);
+  const size_t nmax = (size_t)std::max(c->c.width, s.Np);
+  const size_t per_split = 4 * (size_t)E * batch * nmax;  // partials of one K split, widest layer
+  const size_t fixed = b_x0 + b_asm + b_pred;
+  if (fixed + per_split > kStaticScratchBytes)
+    return sfail(c, MC_E_ARG, "the network's small-batch scratch exceeds the static 8 MiB");
+  SmallScratch sc;
+  sc.X0 = (bf16*)base;
+  sc.Asm = (bf16*)(base + b_x0);
+  sc.preds = (float*)(base + b_x0 + b_asm);
+  sc.P = (float*)(base + fixed);
+  sc.max_split = (int)std::min<size_t>(kGvMaxSplit, (kStaticScratchBytes - fixed) / per_split);
+  enqueue_forward_small(c, d_x, batch, sc);
+  const long per = (long)batch * c->c.n_out;
+  k_ensemble<<<blocks(per), 256, 0, c->st>>>(sc.preds, E, per, c->c.n_out, c->p<float>(s.ymean),
+                                             c->p<float>(s.ystd), d_mean, d_std);
+  SGCHK(c, hipGetLastError());
   return MC_OK;
 }
 

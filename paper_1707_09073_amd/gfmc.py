@@ -371,7 +371,7 @@ class SgQuery(C.Structure):
 
 
 SG_EXPORTS = ["sg_workspace_bytes", "sg_init", "sg_destroy", "sg_last_error", "sg_layer_dims",
-              "sg_set_normalization", "sg_forward", "sg_backward", "sg_adam", "sg_train_step", "sg_predict",
+              "sg_set_normalization", "sg_forward", "sg_backward", "sg_adam", "sg_train_step", "sg_predict", "sg_predict_static",
               "sg_get_params", "sg_set_params", "sg_get_grads", "sg_predict_or_mc"]
 EXPORTS = EXPORTS + SG_EXPORTS
 
@@ -394,6 +394,7 @@ def _sg_lib():
         L.sg_adam.argtypes = [vp, C.c_int, C.c_float]
         L.sg_train_step.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_float, fp]
         L.sg_predict.argtypes = [vp, vp, C.c_int, vp, vp]
+        L.sg_predict_static.argtypes = [vp, vp, C.c_int, vp, vp]
         L.sg_get_params.argtypes = [vp, C.c_int, C.c_int, fp, fp]
         L.sg_set_params.argtypes = [vp, C.c_int, C.c_int, fp, fp]
         L.sg_get_grads.argtypes = [vp, C.c_int, C.c_int, fp, fp]
@@ -528,6 +529,17 @@ class SurrogateNet:
         self._in()
         self._chk(_sg_lib().sg_predict(self._ctx, self._ptr(x, b, self.n_in), b, self._ptr(mean_out, b, self.n_out),
                                        None if std_out is None else self._ptr(std_out, b, self.n_out)), "sg_predict")
+        self._out()
+
+    def sg_predict_static(self, x, mean_out, std_out=None):
+        """sg_predict for batch <= 8 with the library's static scratch (no
+        device allocation inside the call)."""
+        b = x.shape[0]
+        self._in()
+        self._chk(_sg_lib().sg_predict_static(self._ctx, self._ptr(x, b, self.n_in), b,
+                                              self._ptr(mean_out, b, self.n_out),
+                                              None if std_out is None else self._ptr(std_out, b, self.n_out)),
+                  "sg_predict_static")
         self._out()
 
     def sg_get_params(self, member, layer):
