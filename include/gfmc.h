@@ -152,18 +152,35 @@ int mc_set_lattice_temperature(mc_ctx *ctx, int instance, const double *h_T_cell
  * 4k^2 at bin midpoints [3][n_bins]) and rebuild Gamma_v. */
 int mc_set_tables(mc_ctx *ctx, const double *h_shape, const double *h_k4);
 
-/* Advance every instance by n_substeps sub-steps (a multiple of `substeps`):
- * per interval, free flight and scattering with heat counts, then in device
- * mode deposit, contact injection and Poisson refresh. */
+/* Advance every instance by n_substeps sub-steps (a multiple of `substeps`)
+ * (electron MC paragraph: free flight under the local field in the Kane
+ * bands, scattering chosen by self-scattering among impurity, polar-optical,
+ * acoustic and intervalley rates, the electron-phonon energy exchange counted
+ * per subcell, the Poisson refresh).  Per interval: free flight and
+ * scattering with heat counts for every live electron, then in device mode
+ * the subcell deposit, the contact refill and the Poisson refresh.
+ * Asynchronous on the context's stream; MC_E_ARG for a count that is not a
+ * multiple of `substeps` or an unsupported launch shape, MC_E_HIP if a
+ * launch or the graph capture fails.  Faults inside the kernels (event
+ * guard, non-finite state, exhausted capacity) become sticky per-instance
+ * flags that mc_tally returns. */
 int mc_step(mc_ctx *ctx, int n_substeps);
 
 /* Deposit electrons per subcell, refill the contact subcells to neutrality,
  * solve the Poisson equation and refresh the field, for all instances
- * (device mode; done after every interval by mc_step). */
+ * (electron MC paragraph: the field follows from the terminal voltages and
+ * the electron concentration counted in the subcells).  Device mode only
+ * (MC_OK and nothing done in bulk mode); done after every interval by
+ * mc_step.  Asynchronous; MC_E_HIP if a launch fails. */
 int poisson_update(mc_ctx *ctx);
 
-/* Copy the window tallies of one instance; reset_window != 0 starts a new
- * window afterwards.  Returns the first sticky device error, if any. */
+/* Copy the window tallies of one instance (electron MC paragraph: the
+ * events behind the heat counted per subcell and the contact currents) into
+ * the caller's h_out; reset_window != 0 starts a new window of every
+ * instance afterwards (counts, maps and history rows).  Synchronises the
+ * stream.  Returns MC_OK or the first sticky device error of the instance
+ * (h_out filled either way), MC_E_ARG for a bad instance or pointer,
+ * MC_E_HIP for a failed copy. */
 int mc_tally(mc_ctx *ctx, int instance, mc_tally_out *h_out, int reset_window);
 
 /* Window maps of one instance: h_heat4 [ncell][4] phonon counts (LO emit, LO
@@ -220,7 +237,10 @@ typedef struct {
  * filling *out), or MC_E_ARG / MC_E_HIP.  Synchronises the stream. */
 int mc_observables(mc_ctx *ctx, int instance, mc_observables_out *out);
 
-/* Device pointers of one instance's particle state (for in-place readers). */
+/* Device pointers of one instance's particle state, the per-electron (k, r,
+ * valley) ensemble of the electron MC paragraph, for in-place readers on the
+ * context's stream.  The pointers stay owned by the workspace and valid
+ * until mc_destroy; MC_E_ARG for a bad instance or pointer. */
 int mc_particles(mc_ctx *ctx, int instance, mc_particles_view *out);
 
 /* Copy one instance's particles to / from host arrays of `capacity` entries:
@@ -294,11 +314,20 @@ int mc_use_graph(mc_ctx *ctx, int enable);
 int mc_profile(mc_ctx *ctx, int enable);
 int mc_profile_read(mc_ctx *ctx, double *flight_ms, int *n_flight, double *refresh_ms, int *n_refresh, int reset);
 
-/* Bytes and contents of a checkpoint (particle state, counters, tallies,
- * fields, refill plans); restoring into a context built from the same
- * configurations continues bit-identically.  A checkpoint starts with a
- * format word: mc_restore rejects (MC_E_ARG) one written by a library whose
- * workspace image differs, or one of another context's size. */
+/* Checkpoint of the Monte Carlo state that evolves (electron MC paragraph:
+ * the ensemble and its window tallies): particles, counters, tallies and
+ * history, potential and field, refill plans, the interval counters and the
+ * lattice temperatures.  With h_buf NULL, *bytes receives the size;
+ * otherwise h_buf (caller-owned, *bytes long) receives the checkpoint and
+ * *bytes its length (MC_E_ARG if too small).  Restoring into a context built
+ * from the same configurations continues bit-identically: the checkpoint
+ * carries the rate tables, factors and self-scattering bounds with the
+ * temperatures; set-up products (the Poisson inverse) and per-interval
+ * scratch stay the restoring context's own, and it keeps its launch shape.
+ * A checkpoint starts
+ * with a format word: mc_restore rejects (MC_E_ARG) one written by a
+ * library whose layout differs, or one of another context's size.  Both
+ * synchronise the stream. */
 int mc_checkpoint(mc_ctx *ctx, void *h_buf, size_t *bytes);
 int mc_restore(mc_ctx *ctx, const void *h_buf, size_t bytes);
 

@@ -21,9 +21,16 @@ namespace {
 
 struct Layout {
   size_t total = 0;
+  std::vector<std::pair<size_t, size_t>> kept;  // regions a checkpoint carries: (offset, bytes)
   size_t take(size_t bytes) {
     const size_t off = total;
     total += (bytes + 255) & ~(size_t)255;
+    return off;
+  }
+  // a region of evolving state (carried by checkpoints)
+  size_t keep(size_t bytes) {
+    const size_t off = take(bytes);
+    if (bytes) kept.emplace_back(off, bytes);
     return off;
   }
 };
@@ -34,6 +41,7 @@ struct Offsets {
       nrep, bpart, wg_inst;
   size_t kx, ky, kz, x, y, z, meta;
   size_t skx, sky, skz, sx, sy, sz, smeta;  // compaction scratch (device mode)
+  std::vector<std::pair<size_t, size_t>> kept;  // evolving state: the regions a checkpoint carries
 };
 
 bool same_shared(const mc_config& a, const mc_config& b) {
@@ -112,48 +120,50 @@ Offsets layout(const mc_config* c, int n, size_t* total) {
   size_t cap = 0;
   for (int i = 0; i < n; ++i) cap += (size_t)c[i].capacity;
   const size_t max_tiles = make_tiles(c, n, min_tile(c[0])).tiles.size();
-  o.table64 = L.take(sizeof(double) * 3 * nb * kTRow);
-  o.table32 = L.take(sizeof(float) * 3 * nb * kTRow);
-  o.fac64 = L.take(sizeof(double) * n * nc * kFRow);
-  o.fac32 = L.take(sizeof(float) * n * nc * kFRow);
-  o.field64 = L.take(sizeof(double) * n * nc * 4);
-  o.field32 = L.take(sizeof(float) * n * nc * 4);
-  o.phi = L.take(sizeof(double) * n * nc);
-  o.gamma64 = L.take(sizeof(double) * n * 4);
-  o.gamma32 = L.take(sizeof(float) * n * 4);
-  o.Tcell = L.take(sizeof(double) * n * nc);
-  o.count = L.take(sizeof(uint32_t) * n * nc);
-  o.heat = L.take(sizeof(unsigned long long) * n * nc * 4);
-  o.dens = L.take(sizeof(unsigned long long) * n * nc);
-  o.counters = L.take(sizeof(unsigned long long) * n * kNCnt);
-  o.flags = L.take(sizeof(int) * n);
-  o.ctl = L.take(sizeof(uint32_t) * 16);
-  o.next_id = L.take(sizeof(uint32_t) * n);
+  // keep(): state that evolves or that the caller may replace (tables); the
+  // rest is rebuilt at set-up or rewritten within every interval
+  o.table64 = L.keep(sizeof(double) * 3 * nb * kTRow);
+  o.table32 = L.keep(sizeof(float) * 3 * nb * kTRow);
+  o.fac64 = L.keep(sizeof(double) * n * nc * kFRow);
+  o.fac32 = L.keep(sizeof(float) * n * nc * kFRow);
+  o.field64 = L.keep(sizeof(double) * n * nc * 4);
+  o.field32 = L.keep(sizeof(float) * n * nc * 4);
+  o.phi = L.keep(sizeof(double) * n * nc);
+  o.gamma64 = L.keep(sizeof(double) * n * 4);
+  o.gamma32 = L.keep(sizeof(float) * n * 4);
+  o.Tcell = L.keep(sizeof(double) * n * nc);
+  o.count = L.keep(sizeof(uint32_t) * n * nc);
+  o.heat = L.keep(sizeof(unsigned long long) * n * nc * 4);
+  o.dens = L.keep(sizeof(unsigned long long) * n * nc);
+  o.counters = L.keep(sizeof(unsigned long long) * n * kNCnt);
+  o.flags = L.keep(sizeof(int) * n);
+  o.ctl = L.keep(sizeof(uint32_t) * 16);
+  o.next_id = L.keep(sizeof(uint32_t) * n);
   o.ip = L.take(sizeof(InstParams) * n);
   o.tiles = L.take(sizeof(TileDesc) * max_tiles);
-  o.acc = L.take(dev ? sizeof(unsigned long long) * n * 5 * nc : 0);
+  o.acc = L.keep(dev ? sizeof(unsigned long long) * n * 5 * nc : 0);
   o.tile_dead = L.take(sizeof(uint32_t) * max_tiles);
   o.tile_off = L.take(sizeof(uint32_t) * max_tiles);
   o.wg_inst = L.take(sizeof(int) * max_tiles);
-  o.plan = L.take(sizeof(Plan) * n);
+  o.plan = L.keep(sizeof(Plan) * n);
   o.slots = L.take(dev ? sizeof(uint32_t) * cap : 0);  // contact-refill slot list
   o.minv = L.take(dev ? sizeof(double) * c[0].n_cells[0] * (size_t)(c[0].n_cells[1] * c[0].n_cells[2]) *
                             (c[0].n_cells[1] * c[0].n_cells[2])
                       : 0);
   o.ainv = L.take(dev ? sizeof(double) * (size_t)nc * nc : 0);
   o.rhs = L.take(dev ? sizeof(double) * (size_t)n * nc : 0);
-  o.hist = L.take(sizeof(double) * n * kHistCap * 8);
-  o.reps = L.take(sizeof(int) * n * nc);
-  o.nrep = L.take(sizeof(int) * n);
+  o.hist = L.keep(sizeof(double) * n * kHistCap * 8);
+  o.reps = L.keep(sizeof(int) * n * nc);
+  o.nrep = L.keep(sizeof(int) * n);
   o.bpart = L.take(dev ? 0 : sizeof(double) * max_tiles * 8);
   const size_t es = f32 ? 4 : 8;
-  o.kx = L.take(es * cap);
-  o.ky = L.take(es * cap);
-  o.kz = L.take(es * cap);
-  o.x = L.take(dev ? es * cap : 0);
-  o.y = L.take(dev ? es * cap : 0);
-  o.z = L.take(dev ? es * cap : 0);
-  o.meta = L.take(sizeof(uint32_t) * cap);
+  o.kx = L.keep(es * cap);
+  o.ky = L.keep(es * cap);
+  o.kz = L.keep(es * cap);
+  o.x = L.keep(dev ? es * cap : 0);
+  o.y = L.keep(dev ? es * cap : 0);
+  o.z = L.keep(dev ? es * cap : 0);
+  o.meta = L.keep(sizeof(uint32_t) * cap);
   o.skx = L.take(dev ? es * cap : 0);
   o.sky = L.take(dev ? es * cap : 0);
   o.skz = L.take(dev ? es * cap : 0);
@@ -161,6 +171,7 @@ Offsets layout(const mc_config* c, int n, size_t* total) {
   o.sy = L.take(dev ? es * cap : 0);
   o.sz = L.take(dev ? es * cap : 0);
   o.smeta = L.take(dev ? sizeof(uint32_t) * cap : 0);
+  o.kept = L.kept;
   *total = L.total;
   return o;
 }
@@ -1176,37 +1187,49 @@ int mc_profile_read(mc_ctx* c, double* flight_ms, int* n_flight, double* refresh
   return MC_OK;
 }
 
-// checkpoint = a format word, the workspace size, the whole workspace image
-// (particles, counters, tallies, fields, tables, refill plans) and the
-// host-side temperature maps.  The format word changes whenever the meaning
-// of the workspace image does.
-constexpr uint64_t kCheckpointFormat = 0x67666d6300000003ull;  // "gfmc", 3: no per-tile histograms
+// checkpoint = a format word, the byte count of the evolving state, the
+// regions of the workspace that hold it (in layout order) and the host-side
+// temperature maps.  Set-up products (the Poisson inverse), the tiling and
+// the per-interval scratch (compaction copy, slot list, histogram merge,
+// right-hand side) are not carried: the restoring context has its own and
+// rewrites the rest.  The format word changes whenever the meaning of the
+// carried state does.
+constexpr uint64_t kCheckpointFormat = 0x67666d6300000004ull;  // "gfmc", 4: evolving regions only
+
+namespace {
+size_t kept_bytes(const Offsets& o) {
+  size_t b = 0;
+  for (const auto& r : o.kept) b += r.second;
+  return b;
+}
+}  // namespace
 
 int mc_checkpoint(mc_ctx* c, void* h_buf, size_t* bytes) {
   if (!c || !bytes) return MC_E_ARG;
-  size_t need = 0;
-  layout(c->cfg.data(), c->n_inst, &need);
+  const size_t need = kept_bytes(c->o);
   const size_t tbytes = sizeof(double) * (size_t)c->n_inst * c->ncell;
   const size_t total = 2 * sizeof(uint64_t) + need + tbytes;
   if (!h_buf) { *bytes = total; return MC_OK; }
   if (*bytes < total) return fail(c, MC_E_ARG, "checkpoint buffer too small");
-  HIPCHK(c, hipStreamSynchronize(c->st));
   std::memcpy(h_buf, &kCheckpointFormat, sizeof(uint64_t));
   char* b = (char*)h_buf + sizeof(uint64_t);
   const uint64_t n64 = need;
   std::memcpy(b, &n64, sizeof(n64));
-  HIPCHK(c, hipMemcpy(b + sizeof(n64), c->ws, need, hipMemcpyDeviceToHost));
+  char* d = b + sizeof(n64);
+  for (const auto& r : c->o.kept) {
+    HIPCHK(c, hipMemcpyAsync(d, c->ws + r.first, r.second, hipMemcpyDeviceToHost, c->st));
+    d += r.second;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->st));
   for (int i = 0; i < c->n_inst; ++i)
-    std::memcpy(b + sizeof(n64) + need + sizeof(double) * (size_t)i * c->ncell, c->Tcell[i].data(),
-                sizeof(double) * c->ncell);
+    std::memcpy(d + sizeof(double) * (size_t)i * c->ncell, c->Tcell[i].data(), sizeof(double) * c->ncell);
   *bytes = total;
   return MC_OK;
 }
 
 int mc_restore(mc_ctx* c, const void* h_buf, size_t bytes) {
   if (!c || !h_buf) return MC_E_ARG;
-  size_t need = 0;
-  layout(c->cfg.data(), c->n_inst, &need);
+  const size_t need = kept_bytes(c->o);
   const size_t tbytes = sizeof(double) * (size_t)c->n_inst * c->ncell;
   uint64_t fmt = 0, n64 = 0;
   if (bytes < 2 * sizeof(uint64_t)) return fail(c, MC_E_ARG, "checkpoint does not match");
@@ -1216,13 +1239,16 @@ int mc_restore(mc_ctx* c, const void* h_buf, size_t bytes) {
   bytes -= sizeof(uint64_t);
   std::memcpy(&n64, b, sizeof(n64));
   if (n64 != need || bytes < sizeof(n64) + need + tbytes) return fail(c, MC_E_ARG, "checkpoint does not match");
-  HIPCHK(c, hipStreamSynchronize(c->st));
   // keep the launch-shape-dependent tile table of this context
   const int blk = c->block, tl = c->tile;
-  HIPCHK(c, hipMemcpy(c->ws, b + sizeof(n64), need, hipMemcpyHostToDevice));
+  const char* d = b + sizeof(n64);
+  for (const auto& r : c->o.kept) {
+    HIPCHK(c, hipMemcpyAsync(c->ws + r.first, d, r.second, hipMemcpyHostToDevice, c->st));
+    d += r.second;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->st));
   for (int i = 0; i < c->n_inst; ++i)
-    std::memcpy(c->Tcell[i].data(), b + sizeof(n64) + need + sizeof(double) * (size_t)i * c->ncell,
-                sizeof(double) * c->ncell);
+    std::memcpy(c->Tcell[i].data(), d + sizeof(double) * (size_t)i * c->ncell, sizeof(double) * c->ncell);
   drop_graph(c);
   return mc_set_launch(c, blk, tl);
 }
