@@ -13,6 +13,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "emc_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "phonon_mc_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 NV, NM, NF = 3, 10, 7
@@ -45,12 +46,59 @@ class OrObs(C.Structure):
     ]
 
 
+class OrPhConfig(C.Structure):
+    _fields_ = [("L_nm", C.c_double * 3), ("n_cells", C.c_int * 3), ("face", C.c_int * 6), ("n_bins", C.c_int),
+                ("seed", C.c_uint64), ("instance", C.c_uint32), ("max_events", C.c_int)]
+
+
+class OrPhCounts(C.Structure):
+    _fields_ = [("scatterings", C.c_uint64), ("wall_specular", C.c_uint64), ("wall_diffuse", C.c_uint64),
+                ("absorbed", C.c_uint64 * 6), ("dropped", C.c_uint64), ("path_nm", C.c_double)]
+
+
+FACE = {"specular": 0, "diffuse": 1, "isothermal": 2}
+
+
+def phonon_mc(cfg: dict, q_cell, v_ms, inv_tau, C_bin, n_packets: int, threads: int = 0) -> dict:
+    """Steady-state phonon packets of the wire domain (see phonon_mc_oracle.c):
+    cfg has L_nm, n_cells, faces (six of 'specular', 'diffuse', 'isothermal'
+    for x0 x1 y0 y1 z0 z1), seed, instance, max_events; q_cell the power per
+    subcell (W); per frequency bin the group velocity (m/s), relaxation rate
+    (1/s) and heat capacity (J/(m^3 K)).  Returns the time packets spent per
+    subcell (fs), the temperature rise per subcell (K) and the counts."""
+    c = OrPhConfig()
+    c.L_nm[:] = [float(x) for x in cfg["L_nm"]]
+    c.n_cells[:] = [int(x) for x in cfg["n_cells"]]
+    c.face[:] = [FACE[f] for f in cfg["faces"]]
+    v = np.ascontiguousarray(np.asarray(v_ms, np.float64) * 1e-6)            # nm/fs
+    tau = np.ascontiguousarray(1e15 / np.asarray(inv_tau, np.float64))         # fs
+    Cb = np.asarray(C_bin, np.float64)
+    c.n_bins = int(v.size)
+    c.seed = int(cfg["seed"]) & 0xFFFFFFFFFFFFFFFF
+    c.instance = int(cfg.get("instance", 0))
+    c.max_events = int(cfg.get("max_events", 1 << 20))
+    emit = Cb * np.asarray(inv_tau, np.float64)
+    cum = np.ascontiguousarray(np.cumsum(emit))   # in bin order
+    q = np.ascontiguousarray(q_cell, np.float64)
+    nc = int(np.prod(cfg["n_cells"]))
+    t = np.zeros(nc)
+    cnt = OrPhCounts()
+    lib().or_ph_run(C.byref(c), _p(q, C.c_double), _p(v, C.c_double), _p(tau, C.c_double), _p(cum, C.c_double),
+                    int(n_packets), int(threads), _p(t, C.c_double), C.byref(cnt))
+    P = float(q.sum())
+    Vc = np.prod(np.asarray(cfg["L_nm"], float) / np.asarray(cfg["n_cells"], float)) * 1e-27
+    dT = P * t * 1e-15 / n_packets / (Cb.sum() * Vc)
+    return dict(t_fs=t, dT=dT, scatterings=int(cnt.scatterings), wall_specular=int(cnt.wall_specular),
+                wall_diffuse=int(cnt.wall_diffuse), absorbed=np.array(cnt.absorbed[:], np.int64),
+                dropped=int(cnt.dropped), path_nm=cnt.path_nm)
+
+
 def build(force: bool = False) -> str:
     """Compile the reference with gcc (plain -O2: no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-                               "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
+                               "-Wno-unused-function", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -111,6 +159,7 @@ def lib():
         L.or_observables.argtypes = [C.c_void_p, C.POINTER(OrObs)]
         L.or_ensemble_energy.argtypes = [C.c_void_p]
         L.or_ensemble_energy.restype = C.c_double
+        L.or_ph_run.argtypes = [C.POINTER(OrPhConfig), dp, dp, dp, dp, C.c_long, C.c_int, dp, C.POINTER(OrPhCounts)]
         _lib = L
     return _lib
 
