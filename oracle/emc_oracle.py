@@ -83,14 +83,15 @@ def phonon_mc(cfg: dict, q_cell, v_ms, inv_tau, C_bin, n_packets: int, threads: 
     nc = int(np.prod(cfg["n_cells"]))
     t = np.zeros(nc)
     cnt = OrPhCounts()
+    pk = np.zeros(int(n_packets), np.uint32)
     lib().or_ph_run(C.byref(c), _p(q, C.c_double), _p(v, C.c_double), _p(tau, C.c_double), _p(cum, C.c_double),
-                    int(n_packets), int(threads), _p(t, C.c_double), C.byref(cnt))
+                    int(n_packets), int(threads), _p(t, C.c_double), C.byref(cnt), _p(pk, C.c_uint32))
     P = float(q.sum())
     Vc = np.prod(np.asarray(cfg["L_nm"], float) / np.asarray(cfg["n_cells"], float)) * 1e-27
     dT = P * t * 1e-15 / n_packets / (Cb.sum() * Vc)
     return dict(t_fs=t, dT=dT, scatterings=int(cnt.scatterings), wall_specular=int(cnt.wall_specular),
                 wall_diffuse=int(cnt.wall_diffuse), absorbed=np.array(cnt.absorbed[:], np.int64),
-                dropped=int(cnt.dropped), path_nm=cnt.path_nm)
+                dropped=int(cnt.dropped), path_nm=cnt.path_nm, packet_scatterings=pk)
 
 
 def build(force: bool = False) -> str:
@@ -159,7 +160,8 @@ def lib():
         L.or_observables.argtypes = [C.c_void_p, C.POINTER(OrObs)]
         L.or_ensemble_energy.argtypes = [C.c_void_p]
         L.or_ensemble_energy.restype = C.c_double
-        L.or_ph_run.argtypes = [C.POINTER(OrPhConfig), dp, dp, dp, dp, C.c_long, C.c_int, dp, C.POINTER(OrPhCounts)]
+        L.or_ph_run.argtypes = [C.POINTER(OrPhConfig), dp, dp, dp, dp, C.c_long, C.c_int, dp, C.POINTER(OrPhCounts),
+                                u32p]
         _lib = L
     return _lib
 

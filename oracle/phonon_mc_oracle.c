@@ -54,7 +54,7 @@ typedef struct {
   int n_bins;
   uint64_t seed;
   uint32_t instance;
-  int max_events; /* per packet; a packet that reaches it is counted and dropped */
+  int max_events; /* scatterings plus wall reflections per packet; a packet past it is counted and dropped */
 } or_ph_config;
 
 typedef struct {
@@ -92,9 +92,11 @@ static void iso_dir(double u1, double u2, double d[3]) {
 /* Run n_packets packets of the source `q_cell` (W per subcell, the power of
  * each subcell) with the bin tables v (nm/fs), cumulative re-emission weights
  * (C_b / tau_b, summed in bin order) and tau (fs).  Adds each subcell's
- * packet time (fs) to t_cell and the event counts to cnt. */
+ * packet time (fs) to t_cell and the event counts to cnt; pk_events (may be
+ * NULL) receives each packet's number of scatterings. */
 void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs, const double *tau_fs,
-               const double *cum_emit, long n_packets, int n_threads, double *t_cell, or_ph_counts *cnt) {
+               const double *cum_emit, long n_packets, int n_threads, double *t_cell, or_ph_counts *cnt,
+               uint32_t *pk_events) {
   const int nx = c->n_cells[0], ny = c->n_cells[1], nz = c->n_cells[2], nc = nx * ny * nz, nb = c->n_bins;
   const double d[3] = {c->L_nm[0] / nx, c->L_nm[1] / ny, c->L_nm[2] / nz};
   const int nn[3] = {nx, ny, nz};
@@ -131,6 +133,7 @@ void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs
     iso_dir(u01(w[1]), u01(w[2]), dir);
     double left = -log(u01(w[3])) * tau_fs[b] * v_nmfs[b]; /* free path to the next scattering, nm */
     uint32_t ev = 0, hits = 0;
+    long events = 0; /* scatterings and wall reflections, against the guard */
     for (;;) {
       /* distance to the next cell boundary along each axis */
       double tmin = left;
@@ -152,8 +155,8 @@ void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs
       left -= tmin;
       if (ax < 0) {
         /* scattering: a new bin and direction, a new free path */
+        if (++events > c->max_events) { C->dropped++; break; }
         ++ev;
-        if ((int)ev > c->max_events) { C->dropped++; break; }
         C->scatterings++;
         hits = 0;
         ph_rng(c, (uint32_t)pk, ev, 0u, w);
@@ -169,6 +172,7 @@ void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs
       if (nxt >= 0 && nxt < nn[ax]) { ic[ax] = nxt; continue; }
       const int f = 2 * ax + up;
       if (c->face[f] == PH_ISOTHERMAL) { C->absorbed[f]++; break; }
+      if (++events > c->max_events) { C->dropped++; break; }
       if (c->face[f] == PH_SPECULAR) {
         C->wall_specular++;
         dir[ax] = -dir[ax];
@@ -184,6 +188,7 @@ void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs
         dir[a2] = st * sin(ph);
       }
     }
+    if (pk_events) pk_events[pk] = ev;
   }
   for (int th = 0; th < nt; ++th) {
     for (int i = 0; i < nc; ++i) t_cell[i] += tt[(size_t)th * nc + i];

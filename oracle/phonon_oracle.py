@@ -127,8 +127,9 @@ def transmissivity(m1: dict, m2: dict, w):
     """Eq. (2) with three identical branches on each side: the sums over
     branches cancel, and v D = q^2 / (2 pi^2)."""
     w = np.asarray(w, float)
-    a = np.where(w < m1["w_max"], vg_of_w(m1, w) * dos(m1, w), 0.0)
-    b = np.where(w < m2["w_max"], vg_of_w(m2, w) * dos(m2, w), 0.0)
+    with np.errstate(invalid="ignore"):   # v D at or above a band top is masked out
+        a = np.where(w < m1["w_max"], vg_of_w(m1, w) * dos(m1, w), 0.0)
+        b = np.where(w < m2["w_max"], vg_of_w(m2, w) * dos(m2, w), 0.0)
     return np.where(a + b > 0.0, b / np.where(a + b > 0.0, a + b, 1.0), 0.0)
 
 

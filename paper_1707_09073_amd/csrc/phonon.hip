@@ -1,0 +1,523 @@
+// phonon.hip -- the phonon side of the hybrid method on gfx950: bin tables
+// of the sine-dispersion acoustic branches with their relaxation times
+// (phonon paragraph, Table II) and the scattering by free electrons of
+// Eq. (1); the diffuse-mismatch transmissivity of Eq. (2) and the interface
+// resistance of Eq. (3); and the steady-state phonon packet Monte Carlo of
+// the wire domain (phonon and coupling paragraphs).  C ABI in
+// include/gfph.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "../../include/gfph.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kHbar = 1.054571817e-34;
+constexpr double kKb = 1.380649e-23;
+constexpr double kQe = 1.602176634e-19;
+constexpr double kM0 = 9.1093837015e-31;
+
+// ---------------------------------------------------------------------------
+// Bin tables
+// ---------------------------------------------------------------------------
+
+// Group velocity (m/s) and density of states per branch and volume of the
+// sine dispersion omega = w_max sin(pi q / 2 q0) at omega.
+__device__ inline void sine_branch(const ph_material& m, double w, double& q, double& vg, double& dos) {
+  const double s = fmin(w / m.w_max, 1.0);
+  q = 2.0 * m.q0 / kPi * asin(s);
+  vg = kPi / (2.0 * m.q0) * m.w_max * sqrt(fmax(0.0, (1.0 - s) * (1.0 + s)));
+  dos = q * q / (2.0 * kPi * kPi * vg);
+}
+
+// d f_BE / dT = x / (T 4 sinh^2(x / 2)), x = hbar omega / k_B T
+__device__ inline double bose_dT(double w, double T) {
+  const double x = kHbar * w / (kKb * T);
+  const double sh = sinh(0.5 * x);
+  return x / (T * 4.0 * sh * sh);
+}
+
+// ln(1 + e^y) without overflow
+__device__ inline double softplus(double y) { return y > 0.0 ? y + log1p(exp(-y)) : log1p(exp(y)); }
+
+// Eq. (1): the braces rewritten as softplus(c - x) - softplus(-c - x), which
+// equals hbar omega / k_B T - ln((1 + e^(x + c)) / (1 + e^(x - c))) with
+// c = hbar omega / 2 k_B T and x the electron-energy offset of the equation.
+__device__ inline double inv_tau_e(double w, double T, double EF_eV, const ph_electrons& e) {
+  const double m = e.m_dos * kM0, Da = e.D_a_eV * kQe, kT = kKb * T;
+  const double half = 0.5 * m * e.v_g * e.v_g;
+  const double pref = Da * Da * m * m * m * e.v_g / (4.0 * kPi * kHbar * kHbar * kHbar * kHbar * e.rho) * kT / half;
+  const double x = (half - EF_eV * kQe) / kT + kHbar * kHbar * w * w / (8.0 * m * e.v_g * e.v_g * kT);
+  const double c = kHbar * w / (2.0 * kT);
+  return pref * (softplus(c - x) - softplus(-c - x));
+}
+
+// Fermi level of a parabolic band: n = N_c F_1/2(eta) with
+// F_1/2(eta) = (2/sqrt(pi)) int_0^inf sqrt(e) / (1 + e^(e - eta)) de, written
+// with e = t^2 as (4/sqrt(pi)) int_0^inf t^2 / (1 + e^(t^2 - eta)) dt and
+// summed by the composite Simpson rule over t in [0, sqrt(max(eta,0) + 50)]
+// (8192 intervals, spread over the workgroup's threads).  Bisection on eta.
+constexpr int kFdThreads = 256;
+__global__ void __launch_bounds__(kFdThreads) k_fermi_level(double n_m3, double m_dos, double T, double* out) {
+  __shared__ double red[kFdThreads / 64];
+  __shared__ double s_eta;
+  const double Nc = 2.0 * pow(m_dos * kM0 * kKb * T / (2.0 * kPi * kHbar * kHbar), 1.5);
+  const double ef0 = kHbar * kHbar * pow(3.0 * kPi * kPi * n_m3, 2.0 / 3.0) / (2.0 * m_dos * kM0) / (kKb * T);
+  double lo = fmin(-60.0, log(n_m3 / Nc) - 10.0), hi = fmax(200.0, 2.0 * ef0 + 10.0);
+  constexpr int kIntervals = 8192;
+  for (int it = 0; it < 200 && hi - lo > 1e-13 * fmax(1.0, fabs(hi)); ++it) {
+    const double eta = 0.5 * (lo + hi);
+    const double top = sqrt(fmax(eta, 0.0) + 50.0), h = top / kIntervals;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i <= kIntervals; i += kFdThreads) {
+      const double t = i * h;
+      const double f = t * t / (1.0 + exp(fmin(t * t - eta, 700.0)));
+      const double wgt = (i == 0 || i == kIntervals) ? 1.0 : ((i & 1) ? 4.0 : 2.0);
+      acc += wgt * f;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < kFdThreads / 64; ++w) s += red[w];
+      const double F = 4.0 / sqrt(kPi) * s * h / 3.0;
+      s_eta = Nc * F > n_m3 ? 1.0 : -1.0;
+    }
+    __syncthreads();
+    if (s_eta > 0.0) hi = eta;
+    else lo = eta;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = 0.5 * (lo + hi) * kKb * T / kQe;
+}
+
+// One thread per bin: omega, group velocity (m/s), heat capacity of the bin
+// for the three branches (J/(m^3 K)) and relaxation rate (1/s), stored
+// [4][n_bins].
+__global__ void k_ph_tables(ph_material m, int use_e, ph_electrons e, const double* __restrict__ EF, double T, int nb,
+                            double* out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const double dw = m.w_max / nb, w = (b + 0.5) * dw;
+  double q, vg, dos;
+  sine_branch(m, w, q, vg, dos);
+  double it = m.A * w * w * w * w + m.B1 * w * w * T * exp(-m.B2 / T);
+  if (use_e) it += inv_tau_e(w, T, *EF, e);
+  out[b] = w;
+  out[nb + b] = vg;
+  out[2 * nb + b] = 3.0 * kHbar * w * bose_dT(w, T) * dos * dw;
+  out[3 * nb + b] = it;
+}
+
+// Eq. (2) on the bins of material 1 and the sums of Eq. (3) and of the bulk
+// conductivity, one workgroup: tau_12 per bin (optional), then
+// sum v_1 C_1 tau_12 / 4 and sum C_1 v_1^2 tau_1 / 3 in a fixed order.
+__global__ void __launch_bounds__(256) k_ph_interface(ph_material m1, ph_material m2, const double* __restrict__ tab1,
+                                                      int nb, double* tau12_out, double* sums) {
+  __shared__ double red[2][4];
+  double a = 0.0, k = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const double w = tab1[b];
+    double q1, v1, d1, q2, v2, d2;
+    sine_branch(m1, w, q1, v1, d1);
+    double t12 = 0.0;
+    if (w < m2.w_max) {
+      sine_branch(m2, w, q2, v2, d2);
+      // three identical branches on each side
+      const double s1 = 3.0 * v1 * d1, s2 = 3.0 * v2 * d2;
+      t12 = s2 / (s1 + s2);
+    }
+    if (tau12_out) tau12_out[b] = t12;
+    const double vb = tab1[nb + b], Cb = tab1[2 * nb + b], itb = tab1[3 * nb + b];
+    a += vb * Cb * t12;
+    k += Cb * vb * vb / itb;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    k += __shfl_xor(k, o);
+  }
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = a; red[1][threadIdx.x >> 6] = k; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sk = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { sa += red[0][w]; sk += red[1][w]; }
+    sums[0] = sa / 4.0;
+    sums[1] = sk / 3.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phonon packet Monte Carlo
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                        uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ double uo(uint32_t w) {
+#pragma clang fp contract(off)
+  return ((double)w + 0.5) * (1.0 / 4294967296.0);
+}
+
+// first i with u * cum[n-1] < cum[i]
+__device__ __forceinline__ int draw_cum(const double* cum, int n, double u) {
+#pragma clang fp contract(off)
+  const double x = u * cum[n - 1];
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (x < cum[mid]) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void iso(double u1, double u2, double d[3]) {
+#pragma clang fp contract(off)
+  const double mu = 2.0 * u1 - 1.0, s = sqrt(fmax(0.0, 1.0 - mu * mu)), ph = 2.0 * kPi * u2;
+  d[0] = s * cos(ph);
+  d[1] = s * sin(ph);
+  d[2] = mu;
+}
+
+enum { CT_SCAT = 0, CT_SPEC = 1, CT_DIFF = 2, CT_ABS0 = 3, CT_DROP = 9, CT_N = 10 };
+
+struct PhArgs {
+  double L[3], d[3];
+  int n[3], face[6], ncell, nb, max_events;
+  uint32_t k0, k1, tag;
+  long long n_packets;
+  const double* cum_cell;  // [ncell] cumulative power in subcell order
+  const double* tab;       // [4][nb] bin tables
+  const double* cum_emit;  // [nb] cumulative C_b / tau_b in bin order
+  double* t_cell;          // [ncell] packet time per subcell, fs (atomic sums)
+  uint32_t* pk_scat;       // [n_packets] scatterings of each packet (may be null)
+  unsigned long long* counts;  // [CT_N]
+  unsigned long long* next;    // packet counter of the launch
+};
+
+// Set-up of a run: cumulative source and re-emission weights (one thread
+// each, in order), the packet counter and the tallies cleared.
+__global__ void k_ph_setup(const double* __restrict__ q, int ncell, const double* __restrict__ tab, int nb,
+                           double* cum_cell, double* cum_emit, double* t_cell, unsigned long long* counts,
+                           unsigned long long* next, double* sums) {
+#pragma clang fp contract(off)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double a = 0.0;
+    for (int i = 0; i < ncell; ++i) { a += q[i]; cum_cell[i] = a; }
+    sums[0] = a;  // total power, W
+    double e = 0.0, cv = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      e += tab[2 * nb + b] * tab[3 * nb + b];
+      cum_emit[b] = e;
+      cv += tab[2 * nb + b];
+    }
+    sums[1] = cv;  // volumetric heat capacity, J/(m^3 K)
+    for (int i = 0; i < CT_N; ++i) counts[i] = 0ull;
+    *next = 0ull;
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += gridDim.x * blockDim.x) t_cell[i] = 0.0;
+}
+
+// One packet per lane at a time: when a lane's packet ends it takes the next
+// packet index from the launch's counter (64 at a time per wavefront), so
+// lanes do not idle while the longest packet of their wavefront runs.  The
+// bin tables and re-emission weights sit in LDS; each workgroup keeps its
+// packet times per subcell in LDS and adds them to the global sums at the
+// end (FP64 atomic adds: the order of the sums varies at rounding level).
+constexpr int kPhBlock = 256;
+constexpr int kPhChunk = 256;  // packet indices a wavefront claims at a time
+__global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
+  // separate multiplies and adds, as the FP64 reference rounds them: the
+  // packet's path (and which boundary or face it meets first) then follows
+  // the reference's arithmetic
+#pragma clang fp contract(off)
+  extern __shared__ double shd[];
+  double* s_v = shd;                 // nm/fs
+  double* s_tau = s_v + a.nb;        // fs
+  double* s_cum = s_tau + a.nb;
+  double* s_t = s_cum + a.nb;        // [ncell]
+  for (int b = threadIdx.x; b < a.nb; b += blockDim.x) {
+    s_v[b] = a.tab[a.nb + b] * 1e-6;
+    s_tau[b] = 1e15 / a.tab[3 * a.nb + b];
+    s_cum[b] = a.cum_emit[b];
+  }
+  for (int i = threadIdx.x; i < a.ncell; i += blockDim.x) s_t[i] = 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int ny = a.n[1], nz = a.n[2];
+  unsigned long long cnt[CT_N];
+#pragma unroll
+  for (int i = 0; i < CT_N; ++i) cnt[i] = 0ull;
+  bool has = false;
+  long long pk = 0;
+  double r[3] = {0, 0, 0}, dir[3] = {0, 0, 1}, left = 0.0;
+  int ic[3] = {0, 0, 0}, b = 0;
+  uint32_t ev = 0, hits = 0;
+  long long events = 0;
+  // wavefront-uniform chunk [cpos, cend) of packet indices claimed from the
+  // launch's counter kPhChunk at a time; exhausted once the counter passes
+  // the last packet
+  long long cpos = 0, cend = 0;
+  bool exhausted = false;
+  for (;;) {
+    // refill: lanes without a packet take the next indices of the chunk
+    unsigned long long want = __ballot(!has && !exhausted);
+    while (want) {
+      if (cpos >= cend) {
+        const int first = __ffsll((long long)want) - 1;
+        unsigned long long base = 0;
+        if (lane == first) base = atomicAdd(a.next, (unsigned long long)kPhChunk);
+        base = __shfl(base, first);
+        if ((long long)base >= a.n_packets) { exhausted = true; break; }
+        cpos = (long long)base;
+        cend = cpos + kPhChunk < a.n_packets ? cpos + kPhChunk : a.n_packets;
+      }
+      const long long take = min((long long)__popcll(want), cend - cpos);
+      const long long rank = __popcll(want & ((1ull << lane) - 1ull));
+      if (((want >> lane) & 1ull) && rank < take) {
+        pk = cpos + rank;
+        uint4 w = philox((uint32_t)pk, 0u, 0u, a.tag, a.k0, a.k1);
+        const int cell = draw_cum(a.cum_cell, a.ncell, uo(w.x));
+        ic[0] = cell / (ny * nz); ic[1] = (cell / nz) % ny; ic[2] = cell % nz;
+        r[0] = (ic[0] + uo(w.y)) * a.d[0];
+        r[1] = (ic[1] + uo(w.z)) * a.d[1];
+        r[2] = (ic[2] + uo(w.w)) * a.d[2];
+        w = philox((uint32_t)pk, 0u, 1u, a.tag, a.k0, a.k1);
+        b = draw_cum(s_cum, a.nb, uo(w.x));
+        iso(uo(w.y), uo(w.z), dir);
+        left = -log(uo(w.w)) * s_tau[b] * s_v[b];
+        ev = 0; hits = 0; events = 0;
+        has = true;
+      }
+      cpos += take;
+      want = __ballot(!has && !exhausted);
+    }
+    if (!__any(has)) break;
+    if (!has) continue;
+    // one step: to the nearest cell boundary, or to the scattering point
+    double tmin = left;
+    int ax = -1;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (dir[q] > 0.0) {
+        const double s = ((ic[q] + 1) * a.d[q] - r[q]) / dir[q];
+        if (s < tmin) { tmin = s; ax = q; }
+      } else if (dir[q] < 0.0) {
+        const double s = (ic[q] * a.d[q] - r[q]) / dir[q];
+        if (s < tmin) { tmin = s; ax = q; }
+      }
+    }
+    if (tmin < 0.0) tmin = 0.0;
+    const int cc = (ic[0] * ny + ic[1]) * nz + ic[2];
+    unsafeAtomicAdd(s_t + cc, tmin / s_v[b]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r[q] += tmin * dir[q];
+    left -= tmin;
+    if (ax < 0) {
+      if (++events > a.max_events) {
+        cnt[CT_DROP]++;
+        if (a.pk_scat) a.pk_scat[pk] = ev;
+        has = false;
+        continue;
+      }
+      ++ev;
+      cnt[CT_SCAT]++;
+      hits = 0;
+      const uint4 w = philox((uint32_t)pk, ev, 0u, a.tag, a.k0, a.k1);
+      b = draw_cum(s_cum, a.nb, uo(w.x));
+      iso(uo(w.y), uo(w.z), dir);
+      left = -log(uo(w.w)) * s_tau[b] * s_v[b];
+      continue;
+    }
+    const bool up = dir[ax] > 0.0;
+    r[ax] = (ic[ax] + (up ? 1 : 0)) * a.d[ax];
+    const int nxt = ic[ax] + (up ? 1 : -1);
+    if (nxt >= 0 && nxt < a.n[ax]) { ic[ax] = nxt; continue; }
+    const int f = 2 * ax + (up ? 1 : 0);
+    if (a.face[f] == PH_ISOTHERMAL) {
+      cnt[CT_ABS0 + f]++;
+      if (a.pk_scat) a.pk_scat[pk] = ev;
+      has = false;
+      continue;
+    }
+    if (++events > a.max_events) {
+      cnt[CT_DROP]++;
+      if (a.pk_scat) a.pk_scat[pk] = ev;
+      has = false;
+      continue;
+    }
+    if (a.face[f] == PH_SPECULAR) {
+      cnt[CT_SPEC]++;
+      dir[ax] = -dir[ax];
+    } else {
+      cnt[CT_DIFF]++;
+      ++hits;
+      const uint4 w = philox((uint32_t)pk, ev, 1u + hits, a.tag, a.k0, a.k1);
+      const double ct = sqrt(uo(w.x)), st = sqrt(fmax(0.0, 1.0 - ct * ct)), ph = 2.0 * kPi * uo(w.y);
+      const int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+      dir[ax] = up ? -ct : ct;
+      dir[a1] = st * cos(ph);
+      dir[a2] = st * sin(ph);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.ncell; i += blockDim.x)
+    if (s_t[i] != 0.0) unsafeAtomicAdd(a.t_cell + i, s_t[i]);
+#pragma unroll
+  for (int i = 0; i < CT_N; ++i) {
+    unsigned long long s = cnt[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0 && s) atomicAdd(a.counts + i, s);
+  }
+}
+
+// temperature rise per subcell: P t_c / (N C_v V_c)
+__global__ void k_ph_dT(const double* __restrict__ t_cell, const double* __restrict__ sums, int ncell,
+                        double n_packets, double vc_m3, double* dT) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncell) dT[i] = sums[0] * t_cell[i] * 1e-15 / (n_packets * sums[1] * vc_m3);
+}
+
+struct PhLayout {
+  size_t cum_cell, cum_emit, counts, next, sums, total;
+};
+
+PhLayout ph_layout(const ph_mc_config* c) {
+  PhLayout L;
+  size_t off = 0;
+  auto take = [&](size_t b) { const size_t o = off; off += (b + 255) & ~(size_t)255; return o; };
+  const size_t nc = (size_t)c->n_cells[0] * c->n_cells[1] * c->n_cells[2];
+  L.cum_cell = take(8 * nc);
+  L.cum_emit = take(8 * (size_t)c->n_bins);
+  L.counts = take(8 * CT_N);
+  L.next = take(8);
+  L.sums = take(8 * 4);
+  L.total = off;
+  return L;
+}
+
+bool ph_valid(const ph_mc_config* c) {
+  if (!c || c->n_bins < 1 || c->n_bins > 4096 || c->n_packets < 1 || c->n_packets > (1ll << 32) ||
+      c->max_events < 1)
+    return false;
+  long long nc = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (c->n_cells[d] < 1 || !(c->L_nm[d] > 0.0)) return false;
+    nc *= c->n_cells[d];
+  }
+  if (nc > 4096) return false;
+  for (int f = 0; f < 6; ++f)
+    if (c->face[f] < PH_SPECULAR || c->face[f] > PH_ISOTHERMAL) return false;
+  return c->instance < (1u << 27);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ph_fermi_level(double n_m3, double m_dos, double T_K, double* d_out, void* stream) {
+  if (!(n_m3 > 0.0) || !(m_dos > 0.0) || !(T_K > 0.0) || !d_out) return PH_E_ARG;
+  k_fermi_level<<<1, kFdThreads, 0, (hipStream_t)stream>>>(n_m3, m_dos, T_K, d_out);
+  return hipGetLastError() == hipSuccess ? PH_OK : PH_E_HIP;
+}
+
+int ph_tables(const ph_material* m, const ph_electrons* e, double T_K, int n_bins, double* d_tables,
+              double* d_fermi, void* stream) {
+  if (!m || !(m->w_max > 0.0) || !(m->q0 > 0.0) || !(T_K > 0.0) || n_bins < 1 || n_bins > 4096 || !d_tables)
+    return PH_E_ARG;
+  if (e && e->n_m3 > 0.0 && (!d_fermi || !(e->m_dos > 0.0) || !(e->rho > 0.0) || !(e->v_g > 0.0)))
+    return PH_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const bool use_e = e && e->n_m3 > 0.0;
+  ph_electrons ee;
+  std::memset(&ee, 0, sizeof(ee));
+  if (use_e) {
+    ee = *e;
+    const int rc = ph_fermi_level(e->n_m3, e->m_dos, T_K, d_fermi, stream);
+    if (rc != PH_OK) return rc;
+  }
+  k_ph_tables<<<(n_bins + 255) / 256, 256, 0, st>>>(*m, use_e ? 1 : 0, ee, use_e ? d_fermi : nullptr, T_K, n_bins,
+                                                    d_tables);
+  return hipGetLastError() == hipSuccess ? PH_OK : PH_E_HIP;
+}
+
+int ph_interface(const ph_material* m1, const ph_material* m2, const double* d_tables1, int n_bins, double* d_tau12,
+                 double* d_sums, void* stream) {
+  if (!m1 || !m2 || !d_tables1 || n_bins < 1 || n_bins > 4096 || !d_sums) return PH_E_ARG;
+  k_ph_interface<<<1, 256, 0, (hipStream_t)stream>>>(*m1, *m2, d_tables1, n_bins, d_tau12, d_sums);
+  return hipGetLastError() == hipSuccess ? PH_OK : PH_E_HIP;
+}
+
+size_t ph_mc_workspace_bytes(const ph_mc_config* c) { return ph_valid(c) ? ph_layout(c).total : 0; }
+
+int ph_mc_run(const ph_mc_config* c, const double* d_tables, const double* d_q_cell, double* d_t_cell, double* d_dT,
+              uint32_t* d_packet_scatterings, uint64_t* h_counts, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!ph_valid(c) || !d_tables || !d_q_cell || !d_t_cell) return PH_E_ARG;
+  const PhLayout L = ph_layout(c);
+  if (!d_ws || ws_bytes < L.total || ((uintptr_t)d_ws & 255u)) return PH_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)d_ws;
+  const int nc = c->n_cells[0] * c->n_cells[1] * c->n_cells[2], nb = c->n_bins;
+  PhArgs a;
+  std::memset(&a, 0, sizeof(a));
+  for (int d = 0; d < 3; ++d) {
+    a.L[d] = c->L_nm[d];
+    a.n[d] = c->n_cells[d];
+    a.d[d] = c->L_nm[d] / c->n_cells[d];
+  }
+  for (int f = 0; f < 6; ++f) a.face[f] = c->face[f];
+  a.ncell = nc;
+  a.nb = nb;
+  a.max_events = c->max_events;
+  a.k0 = (uint32_t)(c->seed & 0xffffffffu);
+  a.k1 = (uint32_t)(c->seed >> 32);
+  a.tag = (c->instance << 4) | 5u;
+  a.n_packets = c->n_packets;
+  a.cum_cell = (const double*)(ws + L.cum_cell);
+  a.tab = d_tables;
+  a.cum_emit = (const double*)(ws + L.cum_emit);
+  a.t_cell = d_t_cell;
+  a.pk_scat = d_packet_scatterings;
+  a.counts = (unsigned long long*)(ws + L.counts);
+  a.next = (unsigned long long*)(ws + L.next);
+  double* sums = (double*)(ws + L.sums);
+  k_ph_setup<<<(nc + 255) / 256, 256, 0, st>>>(d_q_cell, nc, d_tables, nb, (double*)(ws + L.cum_cell),
+                                              (double*)(ws + L.cum_emit), d_t_cell, a.counts, a.next, sums);
+  int dev = 0, ncu = 0, per = 0;
+  const size_t lds = sizeof(double) * (3 * (size_t)nb + nc);
+  if (lds > 160 * 1024) return PH_E_ARG;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_ph_packets, kPhBlock, lds) != hipSuccess)
+    return PH_E_HIP;
+  long long need = (c->n_packets + kPhBlock - 1) / kPhBlock;
+  long long grid = (long long)ncu * (per > 0 ? per : 1);
+  if (grid > need) grid = need;
+  k_ph_packets<<<(unsigned)grid, kPhBlock, lds, st>>>(a);
+  if (d_dT)
+    k_ph_dT<<<(nc + 255) / 256, 256, 0, st>>>(d_t_cell, sums, nc, (double)c->n_packets,
+                                             a.d[0] * a.d[1] * a.d[2] * 1e-27, d_dT);
+  if (hipGetLastError() != hipSuccess) return PH_E_HIP;
+  if (h_counts) {
+    if (hipMemcpyAsync(h_counts, ws + L.counts, 8 * CT_N, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return PH_E_HIP;
+  }
+  return PH_OK;
+}
+
+}  // extern "C"

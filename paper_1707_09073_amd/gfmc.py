@@ -560,3 +560,141 @@ class SurrogateNet:
         self._chk(_sg_lib().sg_get_grads(self._ctx, int(member), int(layer), _p(dW, C.c_float), _p(db, C.c_float)),
                   "sg_get_grads")
         return dW, db
+
+
+# ---------------------------------------------------------------------------
+# Phonon side (ph_* entry points, include/gfph.h)
+# ---------------------------------------------------------------------------
+PH_OK, PH_E_ARG, PH_E_HIP = 0, -1, -2
+PH_FACE = {"specular": 0, "diffuse": 1, "isothermal": 2}
+
+
+class PhMaterial(C.Structure):
+    _fields_ = [("q0", C.c_double), ("w_max", C.c_double), ("A", C.c_double), ("B1", C.c_double), ("B2", C.c_double)]
+
+
+class PhElectrons(C.Structure):
+    _fields_ = [("n_m3", C.c_double), ("m_dos", C.c_double), ("D_a_eV", C.c_double), ("rho", C.c_double),
+                ("v_g", C.c_double)]
+
+
+class PhMcConfig(C.Structure):
+    _fields_ = [("L_nm", C.c_double * 3), ("n_cells", C.c_int32 * 3), ("face", C.c_int32 * 6), ("n_bins", C.c_int32),
+                ("seed", C.c_uint64), ("instance", C.c_uint32), ("max_events", C.c_int32), ("n_packets", C.c_int64)]
+
+
+PH_EXPORTS = ["ph_fermi_level", "ph_tables", "ph_interface", "ph_mc_workspace_bytes", "ph_mc_run"]
+EXPORTS = EXPORTS + PH_EXPORTS
+_ph_ready = False
+
+
+def _ph_lib():
+    global _ph_ready
+    L = lib()
+    if not _ph_ready:
+        vp, dp = C.c_void_p, C.c_void_p
+        L.ph_fermi_level.argtypes = [C.c_double, C.c_double, C.c_double, dp, vp]
+        L.ph_tables.argtypes = [C.POINTER(PhMaterial), C.POINTER(PhElectrons), C.c_double, C.c_int, dp, dp, vp]
+        L.ph_interface.argtypes = [C.POINTER(PhMaterial), C.POINTER(PhMaterial), dp, C.c_int, dp, dp, vp]
+        L.ph_mc_workspace_bytes.argtypes = [C.POINTER(PhMcConfig)]
+        L.ph_mc_workspace_bytes.restype = C.c_size_t
+        L.ph_mc_run.argtypes = [C.POINTER(PhMcConfig), dp, dp, dp, dp, dp, C.POINTER(C.c_uint64), vp, C.c_size_t, vp]
+        for n in ("ph_fermi_level", "ph_tables", "ph_interface", "ph_mc_run"):
+            getattr(L, n).restype = C.c_int
+        _ph_ready = True
+    return L
+
+
+def _ph_chk(rc, where):
+    if rc != PH_OK:
+        raise MCError(rc, where, "phonon call failed")
+
+
+def ph_material(m: dict) -> PhMaterial:
+    return PhMaterial(float(m["q0"]), float(m["w_max"]), float(m["A"]), float(m["B1"]), float(m["B2"]))
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def ph_fermi_level(n_m3: float, m_dos: float, T_K: float, stream=None):
+    import torch
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    _ph_chk(_ph_lib().ph_fermi_level(float(n_m3), float(m_dos), float(T_K), _dptr(out), _stream_ptr(stream)),
+            "ph_fermi_level")
+    return out
+
+
+def ph_tables(material: dict, T_K: float, n_bins: int, electrons: dict | None = None, stream=None):
+    """Bin tables [4, n_bins] (device FP64: omega, v_g, C_bin, 1/tau) and the
+    Fermi level tensor (None without electrons)."""
+    import torch
+    tab = torch.empty((4, int(n_bins)), dtype=torch.float64, device="cuda")
+    ef = None
+    e = None
+    if electrons:
+        e = PhElectrons(float(electrons["n_m3"]), float(electrons["m_dos"]), float(electrons["D_a_eV"]),
+                        float(electrons["rho"]), float(electrons["v_g"]))
+        ef = torch.zeros(1, dtype=torch.float64, device="cuda")
+    m = ph_material(material)
+    _ph_chk(_ph_lib().ph_tables(C.byref(m), None if e is None else C.byref(e), float(T_K), int(n_bins), _dptr(tab),
+                                _dptr(ef), _stream_ptr(stream)), "ph_tables")
+    return tab, ef
+
+
+def ph_interface(m1: dict, m2: dict, tables1, stream=None):
+    """(tau_12 per bin of material 1, [1/R_K, bulk kappa of material 1]) as device tensors."""
+    import torch
+    nb = int(tables1.shape[1])
+    tau = torch.empty(nb, dtype=torch.float64, device="cuda")
+    sums = torch.empty(2, dtype=torch.float64, device="cuda")
+    a, b = ph_material(m1), ph_material(m2)
+    _ph_chk(_ph_lib().ph_interface(C.byref(a), C.byref(b), _dptr(tables1), nb, _dptr(tau), _dptr(sums),
+                                   _stream_ptr(stream)), "ph_interface")
+    return tau, sums
+
+
+class PhononMC:
+    """Workspace and configuration of ph_mc_run."""
+
+    def __init__(self, cfg: dict):
+        import torch
+        c = PhMcConfig()
+        c.L_nm[:] = [float(x) for x in cfg["L_nm"]]
+        c.n_cells[:] = [int(x) for x in cfg["n_cells"]]
+        c.face[:] = [PH_FACE[f] for f in cfg["faces"]]
+        c.n_bins = int(cfg["n_bins"])
+        c.seed = int(cfg["seed"]) & 0xFFFFFFFFFFFFFFFF
+        c.instance = int(cfg.get("instance", 0))
+        c.max_events = int(cfg.get("max_events", 1 << 20))
+        c.n_packets = int(cfg["n_packets"])
+        self.cfg = c
+        self.ncell = int(np.prod(cfg["n_cells"]))
+        n = int(_ph_lib().ph_mc_workspace_bytes(C.byref(c)))
+        if n == 0:
+            raise MCError(PH_E_ARG, "ph_mc_workspace_bytes", "invalid configuration")
+        self.workspace = torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def ph_mc_run(self, tables, q_cell, stream=None, packet_scatterings: bool = False) -> dict:
+        """Per-subcell packet time (fs) and temperature rise (K) as device
+        tensors, and the event counts (synchronises); optionally each
+        packet's scatterings."""
+        import torch
+        t = torch.empty(self.ncell, dtype=torch.float64, device="cuda")
+        dT = torch.empty(self.ncell, dtype=torch.float64, device="cuda")
+        q = q_cell.to(dtype=torch.float64, device="cuda").contiguous()
+        pk = torch.zeros(int(self.cfg.n_packets), dtype=torch.int32, device="cuda") if packet_scatterings else None
+        cnt = np.zeros(10, np.uint64)
+        _ph_chk(_ph_lib().ph_mc_run(C.byref(self.cfg), _dptr(tables), _dptr(q), _dptr(t), _dptr(dT), _dptr(pk),
+                                    cnt.ctypes.data_as(C.POINTER(C.c_uint64)), C.c_void_p(self.workspace.data_ptr()),
+                                    self.workspace.numel(), _stream_ptr(stream)), "ph_mc_run")
+        return dict(t_fs=t, dT=dT, scatterings=int(cnt[0]), wall_specular=int(cnt[1]), wall_diffuse=int(cnt[2]),
+                    absorbed=cnt[3:9].astype(np.int64), dropped=int(cnt[9]),
+                    packet_scatterings=None if pk is None else pk.cpu().numpy().view(np.uint32))

@@ -10,11 +10,11 @@ import tempfile
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gfmc.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("gfmc.h", "gfph.h")]
 
 
 def _declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
     return sorted(set(names))
@@ -47,6 +47,7 @@ def test_struct_layouts_match_the_header(gfmc):
 #include <stdio.h>
 #include <stddef.h>
 #include "gfmc.h"
+#include "gfph.h"
 int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(mc_material), sizeof(mc_config), sizeof(mc_tally_out),
          sizeof(mc_particles_view), offsetof(mc_config, seed));
@@ -54,6 +55,8 @@ int main(void) {
          offsetof(mc_tally_out, real), offsetof(mc_tally_out, flags));
   printf("%zu %zu %zu %zu\n", sizeof(mc_observables_out), offsetof(mc_observables_out, drift_velocity_ms),
          offsetof(mc_observables_out, half_se), offsetof(mc_observables_out, steady));
+  printf("%zu %zu %zu %zu\n", sizeof(ph_mc_config), offsetof(ph_mc_config, seed), offsetof(ph_mc_config, n_packets),
+         sizeof(ph_electrons));
   return 0;
 }
 """
@@ -67,7 +70,9 @@ int main(void) {
             C.sizeof(gfmc.McParticlesView), gfmc.McConfig.seed.offset, gfmc.McConfig.n_cells.offset,
             gfmc.McConfig.Vds.offset, gfmc.McTallyOut.real.offset, gfmc.McTallyOut.flags.offset,
             C.sizeof(gfmc.McObservablesOut), gfmc.McObservablesOut.drift_velocity_ms.offset,
-            gfmc.McObservablesOut.half_se.offset, gfmc.McObservablesOut.steady.offset]
+            gfmc.McObservablesOut.half_se.offset, gfmc.McObservablesOut.steady.offset,
+            C.sizeof(gfmc.PhMcConfig), gfmc.PhMcConfig.seed.offset, gfmc.PhMcConfig.n_packets.offset,
+            C.sizeof(gfmc.PhElectrons)]
     assert [int(x) for x in out] == want
 
 
