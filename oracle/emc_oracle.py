@@ -63,7 +63,8 @@ def phonon_mc(cfg: dict, q_cell, v_ms, inv_tau, C_bin, n_packets: int, threads: 
     """Steady-state phonon packets of the wire domain (see phonon_mc_oracle.c):
     cfg has L_nm, n_cells, faces (six of 'specular', 'diffuse', 'isothermal'
     for x0 x1 y0 y1 z0 z1), seed, instance, max_events; q_cell the power per
-    subcell (W); per frequency bin the group velocity (m/s), relaxation rate
+    subcell (W, either sign: a sink's packets carry negative energy); per
+    frequency bin the group velocity (m/s), relaxation rate
     (1/s) and heat capacity (J/(m^3 K)).  Returns the time packets spent per
     subcell (fs), the temperature rise per subcell (K) and the counts."""
     c = OrPhConfig()
@@ -86,7 +87,7 @@ def phonon_mc(cfg: dict, q_cell, v_ms, inv_tau, C_bin, n_packets: int, threads: 
     pk = np.zeros(int(n_packets), np.uint32)
     lib().or_ph_run(C.byref(c), _p(q, C.c_double), _p(v, C.c_double), _p(tau, C.c_double), _p(cum, C.c_double),
                     int(n_packets), int(threads), _p(t, C.c_double), C.byref(cnt), _p(pk, C.c_uint32))
-    P = float(q.sum())
+    P = float(np.abs(q).sum())
     Vc = np.prod(np.asarray(cfg["L_nm"], float) / np.asarray(cfg["n_cells"], float)) * 1e-27
     dT = P * t * 1e-15 / n_packets / (Cb.sum() * Vc)
     return dict(t_fs=t, dT=dT, scatterings=int(cnt.scatterings), wall_specular=int(cnt.wall_specular),

@@ -13,10 +13,12 @@
  *    (J/(m^3 K), all three branches, the bin's width included) and the
  *    relaxation rate 1/tau_b at the linearisation temperature;
  *  - energy-based deviational phonon packets in the steady state: the heat
- *    generated per subcell (the hot electrons' emitted phonon power, handed
+ *    generated per subcell (the hot electrons' net phonon emission, handed
  *    from the non-propagating LO phonons to the acoustic branches in place)
- *    is split into N packets of equal power P/N; each packet starts in a
- *    subcell drawn by power, with a bin drawn from C_b / tau_b (the
+ *    is split into N packets of equal power P/N, P the sum of |q_c| over the
+ *    subcells; a subcell where absorption outweighs emission is a sink and
+ *    its packets carry negative energy; each packet starts in a
+ *    subcell drawn by |q_c|, with a bin drawn from C_b / tau_b (the
  *    distribution relaxation re-emits) and an isotropic direction, flies
  *    for exponential times of mean tau_b, and at each scattering takes a new
  *    bin from C_b / tau_b and a new isotropic direction; it ends at an
@@ -24,8 +26,8 @@
  *  - faces: specular (symmetry planes A and B), diffuse (adiabatic free
  *    surfaces, cosine-law re-emission), isothermal (absorbing);
  *  - the track-length estimator: the energy of subcell c is P/N times the
- *    total time packets spend in it, and its temperature rise that energy
- *    over C_v V_c (C_v = sum of C_b).
+ *    signed total time packets spend in it, and its temperature rise that
+ *    energy over C_v V_c (C_v = sum of C_b).
  *
  * Random numbers: Philox4x32-10 with counter (packet, event, sub, tag).
  * Event 0 is the emission: sub 0 the subcell and position, sub 1 the bin,
@@ -89,11 +91,12 @@ static void iso_dir(double u1, double u2, double d[3]) {
   d[2] = mu;
 }
 
-/* Run n_packets packets of the source `q_cell` (W per subcell, the power of
- * each subcell) with the bin tables v (nm/fs), cumulative re-emission weights
- * (C_b / tau_b, summed in bin order) and tau (fs).  Adds each subcell's
- * packet time (fs) to t_cell and the event counts to cnt; pk_events (may be
- * NULL) receives each packet's number of scatterings. */
+/* Run n_packets packets of the source `q_cell` (W per subcell, either sign)
+ * with the bin tables v (nm/fs), cumulative re-emission weights (C_b / tau_b,
+ * summed in bin order) and tau (fs).  Adds each subcell's signed packet time
+ * (fs; a packet from a subcell with q < 0 counts negative) to t_cell and the
+ * event counts to cnt; pk_events (may be NULL) receives each packet's number
+ * of scatterings. */
 void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs, const double *tau_fs,
                const double *cum_emit, long n_packets, int n_threads, double *t_cell, or_ph_counts *cnt,
                uint32_t *pk_events) {
@@ -102,7 +105,7 @@ void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs
   const int nn[3] = {nx, ny, nz};
   double *cum_cell = malloc(sizeof(double) * nc);
   double acc = 0.0;
-  for (int i = 0; i < nc; ++i) { acc += q_cell[i]; cum_cell[i] = acc; }
+  for (int i = 0; i < nc; ++i) { acc += fabs(q_cell[i]); cum_cell[i] = acc; }
 #ifdef _OPENMP
   int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
 #else
@@ -125,6 +128,7 @@ void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs
     uint32_t w[4];
     ph_rng(c, (uint32_t)pk, 0u, 0u, w);
     int cell = draw(cum_cell, nc, u01(w[0]));
+    const double sg = q_cell[cell] < 0.0 ? -1.0 : 1.0; /* the packet's sign */
     int ic[3] = {cell / (ny * nz), (cell / nz) % ny, cell % nz};
     double r[3] = {(ic[0] + u01(w[1])) * d[0], (ic[1] + u01(w[2])) * d[1], (ic[2] + u01(w[3])) * d[2]};
     ph_rng(c, (uint32_t)pk, 0u, 1u, w);
@@ -149,7 +153,7 @@ void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs
       }
       if (tmin < 0.0) tmin = 0.0;
       const int cc = (ic[0] * ny + ic[1]) * nz + ic[2];
-      T[cc] += tmin / v_nmfs[b];
+      T[cc] += sg * (tmin / v_nmfs[b]);
       C->path_nm += tmin;
       for (int a = 0; a < 3; ++a) r[a] += tmin * dir[a];
       left -= tmin;

@@ -99,3 +99,39 @@ def test_specular_and_diffuse_walls_conserve_packets(oracle_mod):
     assert r["wall_specular"] > 0 and r["wall_diffuse"] > 0
     prof = r["dT"].reshape(100, 18).mean(1)
     assert 70 <= int(np.argmax(prof)) < 80
+
+
+def test_sinks_carry_negative_packets(oracle_mod):
+    """A subcell where the electrons absorb more phonon energy than they emit
+    is a heat sink: its packets carry negative energy.  Reversing every
+    source reverses every temperature rise exactly (same packets, same
+    paths); in a box that is mirror-symmetric in x, a source in the left half
+    and the mirrored sink in the right half give an antisymmetric profile,
+    and its size is set by the sum of |q| (a total of q, zero here, would
+    give no rise at all)."""
+    w, v, Cb, _ = P.bin_tables(GAN, 300.0, 64)
+    it = np.full(64, 1e-30)                              # ballistic: no scattering
+    L = np.array([200.0, 100.0, 50.0])
+    cfg = _bar((4, 2, 1), L, ["isothermal"] * 6)
+    q = np.array([1.0, 1.0, 0.5, 0.5, -0.5, -0.5, -1.0, -1.0])   # index (ix*2 + iy)
+    a = oracle_mod.phonon_mc(cfg, q, v, it, Cb, 30000, threads=1)    # one thread: one summation order
+    b = oracle_mod.phonon_mc(cfg, -q, v, it, Cb, 30000, threads=1)
+    assert np.array_equal(a["dT"], -b["dT"]) and np.array_equal(a["packet_scatterings"], b["packet_scatterings"])
+    assert a["absorbed"].sum() == 30000
+    R, A = [], []
+    for seed in range(10):
+        r = oracle_mod.phonon_mc(dict(cfg, seed=100 + seed), q, v, it, Cb, 20000)["dT"].reshape(4, 2)
+        R.append((r + r[::-1]).sum())                    # zero by the mirror symmetry
+        A.append(r[:2].sum() - r[2:].sum())
+    R, A = np.array(R), np.array(A)
+    se = lambda x: x.std(ddof=1) / math.sqrt(len(x))
+    assert abs(R.mean()) < 4 * se(R), (R.mean(), se(R))
+    assert A.mean() > 20 * se(A)
+    # the same packets from |q|, all positive: the rise of the left half is
+    # the same packets' time, so it equals the signed run's there up to the
+    # right half's negative packets that cross over
+    pos = oracle_mod.phonon_mc(dict(cfg, seed=100), np.abs(q), v, it, Cb, 20000)["dT"].reshape(4, 2)
+    mix = oracle_mod.phonon_mc(dict(cfg, seed=100), q, v, it, Cb, 20000)["dT"].reshape(4, 2)
+    half = 0.5 * (pos + mix)                             # the positive packets alone
+    assert np.all(half >= -1e-12 * np.abs(pos).max()) and np.all(pos - half >= -1e-12 * np.abs(pos).max())
+    assert mix[0].sum() > 0.5 * pos[0].sum()
