@@ -31,6 +31,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "electron scatter+flight events/s per MI355X; surrogate vs MC heat-map time @2% err"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+# Algorithmic FP64 operations of the phonon packet kernel, counted from the
+# method's arithmetic (a division, square root, logarithm, sine or cosine
+# counts as one): per straight flight piece, the distance to the subcell
+# boundary along each axis (3 x 3), the time in the subcell and its signed
+# tally (3), the move (6) and the remaining free path (1); per scattering,
+# four uniforms (8), the bin draw (1), the isotropic direction (10) and the
+# free path (4); per diffuse reflection, two uniforms and the cosine-law
+# direction (13); per packet, its emission (38).
+PH_FLOPS = {"segment": 19, "scattering": 23, "diffuse": 13, "packet": 38}
 # VALU issue peak in lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes
 # x 2.4 GHz (one non-packed FP32 or integer operation per lane and cycle; the
 # build disables packed FP32 math)
@@ -202,6 +212,75 @@ def sweep64(args) -> dict:
                 refresh_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]))
 
 
+def phonon_packets(args) -> dict:
+    """The phonon packet kernel alone on the half-wire domain: GaN tables at
+    300 K with Eq. (1) (1024 bins), the synthetic net heat map of an electron
+    window (1 mW around the drain-side gate edge), `--packets` packets per
+    launch.  Per-launch device time from HIP events on the launch stream."""
+    import torch
+    from paper_1707_09073_amd import gfmc, workloads as W
+    dev = W.device_config(n_particles=1000)
+    tab, _ = gfmc.ph_tables(W.GAN_PHONONS, 300.0, 1024, W.WIRE_ELECTRONS)
+    L, nc = dev["L_nm"], dev["n_cells"]
+    vc_m3 = (L[0] / nc[0]) * (L[1] / nc[1]) * (L[2] / nc[2]) * 1e-27
+    q = torch.tensor(W.wire_heat_map(dev) * vc_m3, dtype=torch.float64, device="cuda")   # W per subcell
+    n = int(args.packets)
+    mc = gfmc.PhononMC(dict(L_nm=dev["L_nm"], n_cells=dev["n_cells"], faces=W.WIRE_FACES, n_bins=1024,
+                            seed=W.BASE_SEED + 11, instance=0, max_events=1 << 22, n_packets=n))
+    st = torch.cuda.current_stream()
+    for _ in range(max(1, args.warmup)):
+        mc.ph_mc_run(tab, q, stream=st)
+    torch.cuda.synchronize()
+    tot = dict(segments=0, scatterings=0, wall_diffuse=0, wall_specular=0, dropped=0)
+    ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        r = mc.ph_mc_run(tab, q, stream=st)
+        b.record(st)
+        b.synchronize()
+        ms += a.elapsed_time(b)
+        for k in tot:
+            tot[k] += r[k]
+    wall = time.perf_counter() - t0
+    dT = r["dT"].cpu().numpy()
+    return dict(n=n, wall=wall, avg_ms=ms / args.steps, dT_max=float(dT.max()), **tot)
+
+
+def hybrid_sweep(args) -> dict:
+    """The electro-thermal iteration as a batched drain-voltage sweep: five
+    device instances (Vds = 2, 4, 6, 8, 10 V, Vgs = 0, 2e6 electrons each,
+    FP32 state) in one context from 300 K; per iteration 50 settling and 150
+    window intervals, then 2^21 phonon packets per instance in the half-wire
+    domain; three iterations.  Reports the thermal resistance against Vds."""
+    import torch
+    from paper_1707_09073_amd import gfmc, workloads as W
+    vds = [2.0, 4.0, 6.0, 8.0, 10.0]
+    per = max(10_000, args.particles // len(vds))
+    cfgs = []
+    for i, v in enumerate(vds):
+        c = W.device_config(n_particles=per, precision="fp32", Vds=v, Vgs=0.0, seed=W.BASE_SEED + 40 + i)
+        c["instance"] = i
+        cfgs.append(c)
+    hy = dict(mat=W.GAN_PHONONS, electrons=W.WIRE_ELECTRONS, n_bins=1024,
+              faces=W.WIRE_FACES, n_packets=1 << 21, seed=W.BASE_SEED + 12, T_sink_K=300.0, T_lin_K=0.0,
+              warmup_intervals=50, window_intervals=150, max_iterations=3, relax=1.0, tol_K=0.0)
+    ens = gfmc.Ensemble(cfgs, device="cuda:0")
+    ens.mc_use_graph(True)
+    ens.mc_step(10 * cfgs[0]["substeps"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = gfmc.hy_run(ens, hy)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    last = [x for x in r["records"] if x["iteration"] == r["iterations"] - 1]
+    return dict(wall=wall, iterations=r["iterations"], electrons=per * len(vds), vds=vds,
+                R_th_KW=[x["R_th_KW"] for x in last], dT_max_K=[x["dT_max_K"] for x in last],
+                emit_W=[x["emit_W"] for x in last], drain_current_A=[x["drain_current_A"] for x in last],
+                hot_x_nm=[(x["hot_cell"] // 18 + 0.5) * 10.0 for x in last], records=r["records"])
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,8 +297,12 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true", help="keep the default (or given) launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sg-batch", type=int, default=4096, help="batch of the surrogate workload")
-    ap.add_argument("--workload", choices=["device1e7", "sweep64", "surrogate"], default="device1e7",
-                    help="device1e7: one 10M-electron device (the headline); sweep64: 64-instance batched sweep")
+    ap.add_argument("--workload", choices=["device1e7", "sweep64", "surrogate", "phonon", "hybrid"],
+                    default="device1e7",
+                    help="device1e7: one 10M-electron device (the headline); sweep64: 64-instance batched sweep; "
+                         "phonon: the phonon packet kernel; hybrid: the electro-thermal iteration over five drain "
+                         "voltages")
+    ap.add_argument("--packets", type=int, default=1 << 23, help="packets per launch of the phonon workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration) and exit")
     args = ap.parse_args()
@@ -256,6 +339,44 @@ def main() -> int:
             "roofline": {"bound": "mfma", "achieved": fw["tflops"], "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": fw["tflops"] / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
                          "flops_per_forward": r["flops_forward"]}}), flush=True)
+        return 0
+    if args.workload == "phonon":
+        r = phonon_packets(args)
+        segs_launch = r["segments"] / args.steps
+        flops = (PH_FLOPS["segment"] * r["segments"] + PH_FLOPS["scattering"] * r["scatterings"] +
+                 PH_FLOPS["diffuse"] * r["wall_diffuse"] + PH_FLOPS["packet"] * r["n"] * args.steps) / args.steps
+        achieved = flops / (r["avg_ms"] * 1e-3) / 1e12
+        print(json.dumps({
+            "metric": "phonon packet flight segments/s", "value": r["segments"] / (r["avg_ms"] * 1e-3 * args.steps),
+            "unit": "segments/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["avg_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "phonon packets in the half-wire domain (1000 x 60 x 120 nm, 100 x 3 x 6 "
+                                   "subcells, contacts and film isothermal, symmetry cut specular, sidewall and top "
+                                   "diffuse), GaN tables at 300 K with Eq. (1), 1024 bins, 1 mW synthetic heat map",
+                       "packets": r["n"]},
+            "segments_per_launch": segs_launch, "scatterings_per_launch": r["scatterings"] / args.steps,
+            "diffuse_per_launch": r["wall_diffuse"] / args.steps, "dropped": r["dropped"], "dT_max_K": r["dT_max"],
+            "packets_per_s": r["n"] / (r["avg_ms"] * 1e-3),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_ph_packets",
+                         "algorithmic_flops_per_launch": flops, "flops_per_unit": PH_FLOPS,
+                         "avg_launch_ms": r["avg_ms"],
+                         "note": "launch time includes the one-thread set-up and the temperature kernels; "
+                                 "divisions and transcendentals count one operation each"}}), flush=True)
+        return 0
+    if args.workload == "hybrid":
+        r = hybrid_sweep(args)
+        print(json.dumps({
+            "metric": "electro-thermal iterations/s (electron windows + phonon packets, five drain voltages)",
+            "value": r["iterations"] / r["wall"], "unit": "iterations/s", "n_gpus": 1, "steps": r["iterations"],
+            "warmup": 10, "ms_per_step": r["wall"] / r["iterations"] * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "hybrid iteration: 5 half-nanowire instances (Vds 2-10 V, Vgs 0, 1e18 cm^-3) "
+                                   "in one context, 50 + 150 intervals and 2^21 phonon packets per instance and "
+                                   "iteration, 3 iterations from 300 K", "electrons": r["electrons"]},
+            "vds_V": r["vds"], "R_th_KW": r["R_th_KW"], "dT_max_K": r["dT_max_K"], "emit_W": r["emit_W"],
+            "drain_current_A": r["drain_current_A"], "hot_x_nm": r["hot_x_nm"]}), flush=True)
         return 0
     if args.workload == "sweep64":
         r = sweep64(args)

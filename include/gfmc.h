@@ -285,6 +285,12 @@ int mc_get_launch(const mc_ctx *ctx, int *block, int *tile, int *n_tiles);
  * mode): the length of every per-subcell array of the API. */
 int mc_get_ncell(const mc_ctx *ctx, int *ncell);
 
+/* Number of instances of the context, and its HIP stream (the hipStream_t
+ * given to mc_init, as void*): work a caller enqueues there is ordered with
+ * the context's own. */
+int mc_get_instances(const mc_ctx *ctx, int *n_instances);
+int mc_get_stream(const mc_ctx *ctx, void **stream);
+
 /* Residency of the particle kernel (current variant and precision) at
  * workgroup size `block`: workgroups per compute unit given its registers and
  * LDS histogram, and the device's compute units.  Lets a tuner pick tile

@@ -96,26 +96,30 @@ typedef struct {
 size_t ph_mc_workspace_bytes(const ph_mc_config *cfg);
 
 /* Steady-state phonon packet Monte Carlo (phonon and coupling paragraphs):
- * the heat generated per subcell, d_q_cell (device, W per subcell), is split
- * into n_packets packets of equal power.  A packet starts at a uniform point
- * of a subcell drawn by power, in a bin drawn from C_b / tau_b (what
- * relaxation re-emits: the linearised relaxation-time model, tables from
- * ph_tables at the linearisation temperature) with an isotropic direction;
- * it flies for exponential times of mean tau_b at the bin's group velocity,
- * takes a new bin and direction at each scattering, reflects at specular and
- * diffuse faces and ends at an isothermal one.  Random numbers: Philox4x32-10
- * with counter (packet, event, sub, tag): event 0 the emission (sub 0 the
- * subcell and point, sub 1 the bin, direction and first flight), event j the
- * j-th scattering (sub 0), its h-th diffuse reflection sub 1 + h.
- * Outputs: d_t_cell (device, ncell) the packets' total time per subcell (fs);
- * d_dT (device, ncell, may be NULL) the temperature rise over the isothermal
- * faces' reference, P t_c / (N C_v V_c) with C_v = sum_b C_b;
+ * the heat generated per subcell, d_q_cell (device, W per subcell, either
+ * sign: the electrons' net phonon emission, negative where they absorb more
+ * than they emit), is split into n_packets packets of equal power
+ * P / n_packets, P the sum of |q|.  A packet starts at a uniform point of a
+ * subcell drawn by |q|, with the sign of that subcell's q, in a bin drawn
+ * from C_b / tau_b (what relaxation re-emits: the linearised relaxation-time
+ * model, tables from ph_tables at the linearisation temperature) with an
+ * isotropic direction; it flies for exponential times of mean tau_b at the
+ * bin's group velocity, takes a new bin and direction at each scattering,
+ * reflects at specular and diffuse faces and ends at an isothermal one.
+ * Random numbers: Philox4x32-10 with counter (packet, event, sub, tag): event
+ * 0 the emission (sub 0 the subcell and point, sub 1 the bin, direction and
+ * first flight), event j the j-th scattering (sub 0), its h-th diffuse
+ * reflection sub 1 + h.
+ * Outputs: d_t_cell (device, ncell) the packets' signed total time per
+ * subcell (fs); d_dT (device, ncell, may be NULL) the temperature rise over
+ * the isothermal faces' reference, P t_c / (N C_v V_c) with C_v = sum_b C_b;
  * d_packet_scatterings (device, n_packets u32, may be NULL) each packet's
- * number of scatterings, for diagnostics; h_counts (host,
- * 10 u64, may be NULL; then nothing synchronises) scatterings, specular
- * reflections, diffuse reflections, packets absorbed at each of the six
- * faces, packets dropped at max_events.  The per-subcell times are FP64
- * sums whose order varies between runs at rounding level.
+ * number of scatterings, for diagnostics; h_counts (host, 11 u64, may be
+ * NULL; then nothing synchronises) scatterings, specular reflections, diffuse
+ * reflections, packets absorbed at each of the six faces, packets dropped at
+ * max_events, segments (straight pieces of flight: each ends at a subcell
+ * boundary, a scattering or a face).  The per-subcell times are FP64 sums whose order varies between
+ * runs at rounding level.  q must be finite.
  * PH_E_ARG for an invalid configuration or pointer, or a workspace that is
  * too small or not 256-byte aligned. */
 int ph_mc_run(const ph_mc_config *cfg, const double *d_tables, const double *d_q_cell, double *d_t_cell,

@@ -53,7 +53,8 @@ class OrPhConfig(C.Structure):
 
 class OrPhCounts(C.Structure):
     _fields_ = [("scatterings", C.c_uint64), ("wall_specular", C.c_uint64), ("wall_diffuse", C.c_uint64),
-                ("absorbed", C.c_uint64 * 6), ("dropped", C.c_uint64), ("path_nm", C.c_double)]
+                ("absorbed", C.c_uint64 * 6), ("dropped", C.c_uint64), ("segments", C.c_uint64),
+                ("path_nm", C.c_double)]
 
 
 FACE = {"specular": 0, "diffuse": 1, "isothermal": 2}
@@ -92,7 +93,7 @@ def phonon_mc(cfg: dict, q_cell, v_ms, inv_tau, C_bin, n_packets: int, threads: 
     dT = P * t * 1e-15 / n_packets / (Cb.sum() * Vc)
     return dict(t_fs=t, dT=dT, scatterings=int(cnt.scatterings), wall_specular=int(cnt.wall_specular),
                 wall_diffuse=int(cnt.wall_diffuse), absorbed=np.array(cnt.absorbed[:], np.int64),
-                dropped=int(cnt.dropped), path_nm=cnt.path_nm, packet_scatterings=pk)
+                dropped=int(cnt.dropped), segments=int(cnt.segments), path_nm=cnt.path_nm, packet_scatterings=pk)
 
 
 def build(force: bool = False) -> str:

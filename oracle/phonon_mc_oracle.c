@@ -61,6 +61,7 @@ typedef struct {
 
 typedef struct {
   uint64_t scatterings, wall_specular, wall_diffuse, absorbed[6], dropped;
+  uint64_t segments; /* straight flight pieces: each ends at a cell boundary, a scattering or a face */
   double path_nm;
 } or_ph_counts;
 
@@ -152,6 +153,7 @@ void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs
         }
       }
       if (tmin < 0.0) tmin = 0.0;
+      C->segments++;
       const int cc = (ic[0] * ny + ic[1]) * nz + ic[2];
       T[cc] += sg * (tmin / v_nmfs[b]);
       C->path_nm += tmin;
@@ -199,6 +201,7 @@ void or_ph_run(const or_ph_config *c, const double *q_cell, const double *v_nmfs
     or_ph_counts *s = tc + th;
     cnt->scatterings += s->scatterings; cnt->wall_specular += s->wall_specular;
     cnt->wall_diffuse += s->wall_diffuse; cnt->dropped += s->dropped; cnt->path_nm += s->path_nm;
+    cnt->segments += s->segments;
     for (int f = 0; f < 6; ++f) cnt->absorbed[f] += s->absorbed[f];
   }
   free(tt);

@@ -330,7 +330,11 @@ int refresh_rates(mc_ctx* c) {
   dim3 gf((c->ncell + 255) / 256, c->n_inst);
   k_factors<<<gf, 256, 0, c->st>>>(c->p<double>(c->o.Tcell), c->p<InstParams>(c->o.ip), c->ncell, m.eps_s,
                                    m.hw_lo_eV, m.hw_iv_eV, c->p<double>(c->o.fac64), c->p<float>(c->o.fac32));
-  dim3 gg(c->n_inst, 3);
+  // Gamma_v as maxima over chunks of distinct subcells (zeroed first; this
+  // runs outside any graph capture)
+  HIPCHK(c, hipMemsetAsync(c->ws + c->o.gamma64, 0, sizeof(double) * 4 * c->n_inst, c->st));
+  HIPCHK(c, hipMemsetAsync(c->ws + c->o.gamma32, 0, sizeof(float) * 4 * c->n_inst, c->st));
+  dim3 gg(c->n_inst, 3, (c->ncell + kGammaReps - 1) / kGammaReps);
   k_gamma<double><<<gg, 256, 0, c->st>>>(c->p<double>(c->o.table64), c->p<double>(c->o.fac64), c->p<int>(c->o.reps),
                                          c->p<int>(c->o.nrep), c->ncell, c->nb, c->p<double>(c->o.gamma64));
   k_gamma<float><<<gg, 256, 0, c->st>>>(c->p<float>(c->o.table32), c->p<float>(c->o.fac32), c->p<int>(c->o.reps),
@@ -1151,6 +1155,18 @@ int mc_get_launch(const mc_ctx* c, int* block, int* tile, int* n_tiles) {
 int mc_get_ncell(const mc_ctx* c, int* ncell) {
   if (!c || !ncell) return MC_E_ARG;
   *ncell = c->ncell;
+  return MC_OK;
+}
+
+int mc_get_instances(const mc_ctx* c, int* n) {
+  if (!c || !n) return MC_E_ARG;
+  *n = c->n_inst;
+  return MC_OK;
+}
+
+int mc_get_stream(const mc_ctx* c, void** stream) {
+  if (!c || !stream) return MC_E_ARG;
+  *stream = (void*)c->st;
   return MC_OK;
 }
 

@@ -526,16 +526,33 @@ __global__ void k_factors(const double* __restrict__ Tcell, const InstParams* __
 }
 
 // Gamma_v: the maximum of the tabulated total over bins and the instance's
-// distinct-temperature subcells, in the precision that uses it.
+// distinct-temperature subcells, in the precision that uses it.  Grid
+// (instance, valley, chunk of kGammaReps distinct subcells); each block's
+// maximum joins gamma (zeroed beforehand) by an atomic maximum on the bit
+// pattern, which orders non-negative floats as their values.  A maximum does
+// not depend on the order of its terms, so the result is the same for any
+// split.
+constexpr int kGammaReps = 32;
+
+__device__ inline void atomic_max_nonneg(double* p, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+__device__ inline void atomic_max_nonneg(float* p, float v) {
+  atomicMax(reinterpret_cast<unsigned int*>(p), __float_as_uint(v));
+}
+
 template <typename T>
 __global__ void k_gamma(const T* __restrict__ table, const T* __restrict__ fac, const int* __restrict__ reps,
                         const int* __restrict__ nrep, int ncell, int nb, T* gamma) {
   const int inst = blockIdx.x, v = blockIdx.y;
+  const int r0 = blockIdx.z * kGammaReps;
+  const int n = nrep[inst];
+  if (r0 >= n) return;
+  const int nr = min(kGammaReps, n - r0);
   __shared__ T smax[1024];
   T g = (T)0;
-  const int n = nrep[inst];
-  for (int idx = threadIdx.x; idx < n * nb; idx += blockDim.x) {
-    const int r = idx / nb, b = idx % nb;
+  for (int idx = threadIdx.x; idx < nr * nb; idx += blockDim.x) {
+    const int r = r0 + idx / nb, b = idx % nb;
     const T* S = table + ((size_t)v * nb + b) * kTRow;
     const T* f = fac + ((size_t)inst * ncell + reps[(size_t)inst * ncell + r]) * kFRow;
     const T tot = tab_total<T>(S, f);
@@ -547,7 +564,7 @@ __global__ void k_gamma(const T* __restrict__ table, const T* __restrict__ fac, 
     if (threadIdx.x < (unsigned)o) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) gamma[inst * 4 + v] = smax[0];
+  if (threadIdx.x == 0) atomic_max_nonneg(gamma + inst * 4 + v, smax[0]);
 }
 
 // ---------------------------------------------------------------------------

@@ -193,14 +193,15 @@ __device__ __forceinline__ void iso(double u1, double u2, double d[3]) {
   d[2] = mu;
 }
 
-enum { CT_SCAT = 0, CT_SPEC = 1, CT_DIFF = 2, CT_ABS0 = 3, CT_DROP = 9, CT_N = 10 };
+enum { CT_SCAT = 0, CT_SPEC = 1, CT_DIFF = 2, CT_ABS0 = 3, CT_DROP = 9, CT_SEG = 10, CT_N = 11 };
 
 struct PhArgs {
   double L[3], d[3];
   int n[3], face[6], ncell, nb, max_events;
   uint32_t k0, k1, tag;
   long long n_packets;
-  const double* cum_cell;  // [ncell] cumulative power in subcell order
+  const double* q;         // [ncell] source power per subcell, W (either sign)
+  const double* cum_cell;  // [ncell] cumulative |power| in subcell order
   const double* tab;       // [4][nb] bin tables
   const double* cum_emit;  // [nb] cumulative C_b / tau_b in bin order
   double* t_cell;          // [ncell] packet time per subcell, fs (atomic sums)
@@ -209,7 +210,7 @@ struct PhArgs {
   unsigned long long* next;    // packet counter of the launch
 };
 
-// Set-up of a run: cumulative source and re-emission weights (one thread
+// Set-up of a run: cumulative |source| and re-emission weights (one thread
 // each, in order), the packet counter and the tallies cleared.
 __global__ void k_ph_setup(const double* __restrict__ q, int ncell, const double* __restrict__ tab, int nb,
                            double* cum_cell, double* cum_emit, double* t_cell, unsigned long long* counts,
@@ -217,8 +218,8 @@ __global__ void k_ph_setup(const double* __restrict__ q, int ncell, const double
 #pragma clang fp contract(off)
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double a = 0.0;
-    for (int i = 0; i < ncell; ++i) { a += q[i]; cum_cell[i] = a; }
-    sums[0] = a;  // total power, W
+    for (int i = 0; i < ncell; ++i) { a += fabs(q[i]); cum_cell[i] = a; }
+    sums[0] = a;  // total |power|, W: each packet carries sums[0] / N
     double e = 0.0, cv = 0.0;
     for (int b = 0; b < nb; ++b) {
       e += tab[2 * nb + b] * tab[3 * nb + b];
@@ -238,6 +239,17 @@ __global__ void k_ph_setup(const double* __restrict__ q, int ncell, const double
 // bin tables and re-emission weights sit in LDS; each workgroup keeps its
 // packet times per subcell in LDS and adds them to the global sums at the
 // end (FP64 atomic adds: the order of the sums varies at rounding level).
+template <typename T>
+__device__ __forceinline__ T get3(const T (&v)[3], int i) {
+  return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]);
+}
+template <typename T>
+__device__ __forceinline__ void set3(T (&v)[3], int i, T x) {
+  v[0] = i == 0 ? x : v[0];
+  v[1] = i == 1 ? x : v[1];
+  v[2] = i == 2 ? x : v[2];
+}
+
 constexpr int kPhBlock = 256;
 constexpr int kPhChunk = 256;  // packet indices a wavefront claims at a time
 __global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
@@ -256,15 +268,19 @@ __global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
     s_cum[b] = a.cum_emit[b];
   }
   for (int i = threadIdx.x; i < a.ncell; i += blockDim.x) s_t[i] = 0.0;
+  // absorptions per face in LDS (rare; a face-indexed register array would
+  // live in scratch memory); the frequent counts in plain registers
+  __shared__ unsigned long long s_abs[6];
+  if (threadIdx.x < 6) s_abs[threadIdx.x] = 0ull;
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int ny = a.n[1], nz = a.n[2];
-  unsigned long long cnt[CT_N];
-#pragma unroll
-  for (int i = 0; i < CT_N; ++i) cnt[i] = 0ull;
+  const int faces = a.face[0] | a.face[1] << 2 | a.face[2] << 4 | a.face[3] << 6 | a.face[4] << 8 | a.face[5] << 10;
+  unsigned long long n_seg = 0, n_scat = 0, n_spec = 0, n_diff = 0, n_drop = 0;
   bool has = false;
   long long pk = 0;
   double r[3] = {0, 0, 0}, dir[3] = {0, 0, 1}, left = 0.0;
+  double sg = 1.0;  // the packet's sign: negative from a subcell that is a net sink
   int ic[3] = {0, 0, 0}, b = 0;
   uint32_t ev = 0, hits = 0;
   long long events = 0;
@@ -292,6 +308,7 @@ __global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
         pk = cpos + rank;
         uint4 w = philox((uint32_t)pk, 0u, 0u, a.tag, a.k0, a.k1);
         const int cell = draw_cum(a.cum_cell, a.ncell, uo(w.x));
+        sg = a.q[cell] < 0.0 ? -1.0 : 1.0;
         ic[0] = cell / (ny * nz); ic[1] = (cell / nz) % ny; ic[2] = cell % nz;
         r[0] = (ic[0] + uo(w.y)) * a.d[0];
         r[1] = (ic[1] + uo(w.z)) * a.d[1];
@@ -322,20 +339,21 @@ __global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
       }
     }
     if (tmin < 0.0) tmin = 0.0;
+    ++n_seg;
     const int cc = (ic[0] * ny + ic[1]) * nz + ic[2];
-    unsafeAtomicAdd(s_t + cc, tmin / s_v[b]);
+    unsafeAtomicAdd(s_t + cc, sg * (tmin / s_v[b]));
 #pragma unroll
     for (int q = 0; q < 3; ++q) r[q] += tmin * dir[q];
     left -= tmin;
     if (ax < 0) {
       if (++events > a.max_events) {
-        cnt[CT_DROP]++;
+        ++n_drop;
         if (a.pk_scat) a.pk_scat[pk] = ev;
         has = false;
         continue;
       }
       ++ev;
-      cnt[CT_SCAT]++;
+      ++n_scat;
       hits = 0;
       const uint4 w = philox((uint32_t)pk, ev, 0u, a.tag, a.k0, a.k1);
       b = draw_cum(s_cum, a.nb, uo(w.x));
@@ -343,46 +361,56 @@ __global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
       left = -log(uo(w.w)) * s_tau[b] * s_v[b];
       continue;
     }
-    const bool up = dir[ax] > 0.0;
-    r[ax] = (ic[ax] + (up ? 1 : 0)) * a.d[ax];
-    const int nxt = ic[ax] + (up ? 1 : -1);
-    if (nxt >= 0 && nxt < a.n[ax]) { ic[ax] = nxt; continue; }
+    // the boundary of axis ax (per lane): selects instead of indexing, so
+    // the three-component state stays in registers
+    const double dax = get3(dir, ax);
+    const bool up = dax > 0.0;
+    const int icx = get3(ic, ax);
+    set3(r, ax, (icx + (up ? 1 : 0)) * get3(a.d, ax));
+    const int nxt = icx + (up ? 1 : -1);
+    if (nxt >= 0 && nxt < get3(a.n, ax)) { set3(ic, ax, nxt); continue; }
     const int f = 2 * ax + (up ? 1 : 0);
-    if (a.face[f] == PH_ISOTHERMAL) {
-      cnt[CT_ABS0 + f]++;
+    const int kind = (faces >> (2 * f)) & 3;
+    if (kind == PH_ISOTHERMAL) {
+      atomicAdd(s_abs + f, 1ull);
       if (a.pk_scat) a.pk_scat[pk] = ev;
       has = false;
       continue;
     }
     if (++events > a.max_events) {
-      cnt[CT_DROP]++;
+      ++n_drop;
       if (a.pk_scat) a.pk_scat[pk] = ev;
       has = false;
       continue;
     }
-    if (a.face[f] == PH_SPECULAR) {
-      cnt[CT_SPEC]++;
-      dir[ax] = -dir[ax];
+    if (kind == PH_SPECULAR) {
+      ++n_spec;
+      set3(dir, ax, -dax);
     } else {
-      cnt[CT_DIFF]++;
+      ++n_diff;
       ++hits;
       const uint4 w = philox((uint32_t)pk, ev, 1u + hits, a.tag, a.k0, a.k1);
       const double ct = sqrt(uo(w.x)), st = sqrt(fmax(0.0, 1.0 - ct * ct)), ph = 2.0 * kPi * uo(w.y);
-      const int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
-      dir[ax] = up ? -ct : ct;
-      dir[a1] = st * cos(ph);
-      dir[a2] = st * sin(ph);
+      // cosine-law direction about the inward normal of axis ax; the two
+      // tangential components on axes ax + 1 and ax + 2 (cyclic)
+      const double dn = up ? -ct : ct, t1 = st * cos(ph), t2 = st * sin(ph);
+      dir[0] = ax == 0 ? dn : (ax == 1 ? t2 : t1);
+      dir[1] = ax == 1 ? dn : (ax == 2 ? t2 : t1);
+      dir[2] = ax == 2 ? dn : (ax == 0 ? t2 : t1);
     }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < a.ncell; i += blockDim.x)
     if (s_t[i] != 0.0) unsafeAtomicAdd(a.t_cell + i, s_t[i]);
+  const unsigned long long mine[5] = {n_seg, n_scat, n_spec, n_diff, n_drop};
+  const int slot[5] = {CT_SEG, CT_SCAT, CT_SPEC, CT_DIFF, CT_DROP};
 #pragma unroll
-  for (int i = 0; i < CT_N; ++i) {
-    unsigned long long s = cnt[i];
+  for (int i = 0; i < 5; ++i) {
+    unsigned long long s = mine[i];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0 && s) atomicAdd(a.counts + i, s);
+    if (lane == 0 && s) atomicAdd(a.counts + slot[i], s);
   }
+  if (threadIdx.x < 6 && s_abs[threadIdx.x]) atomicAdd(a.counts + CT_ABS0 + threadIdx.x, s_abs[threadIdx.x]);
 }
 
 // temperature rise per subcell: P t_c / (N C_v V_c)
@@ -487,6 +515,7 @@ int ph_mc_run(const ph_mc_config* c, const double* d_tables, const double* d_q_c
   a.k1 = (uint32_t)(c->seed >> 32);
   a.tag = (c->instance << 4) | 5u;
   a.n_packets = c->n_packets;
+  a.q = d_q_cell;
   a.cum_cell = (const double*)(ws + L.cum_cell);
   a.tab = d_tables;
   a.cum_emit = (const double*)(ws + L.cum_emit);

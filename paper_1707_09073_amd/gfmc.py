@@ -61,7 +61,8 @@ class McParticlesView(C.Structure):
 EXPORTS = ["mc_status_string", "mc_last_error", "mc_workspace_bytes", "mc_init", "mc_destroy",
            "mc_set_lattice_temperature", "mc_set_tables", "mc_step", "poisson_update", "mc_tally", "mc_maps",
            "mc_history", "mc_observables", "mc_particles", "mc_read_particles", "mc_write_particles", "mc_read_fields",
-           "mc_read_tables", "mc_get_config", "mc_get_lattice_temperature", "mc_set_launch", "mc_get_launch", "mc_get_ncell", "mc_occupancy", "mc_set_variant", "mc_use_graph", "mc_profile", "mc_profile_read",
+           "mc_read_tables", "mc_get_config", "mc_get_lattice_temperature", "mc_set_launch", "mc_get_launch", "mc_get_ncell",
+           "mc_get_instances", "mc_get_stream", "mc_occupancy", "mc_set_variant", "mc_use_graph", "mc_profile", "mc_profile_read",
            "mc_checkpoint", "mc_restore"]
 
 _lib = None
@@ -99,6 +100,8 @@ def lib():
         L.mc_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.mc_get_launch.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.mc_get_ncell.argtypes = [vp, C.POINTER(C.c_int)]
+        L.mc_get_instances.argtypes = [vp, C.POINTER(C.c_int)]
+        L.mc_get_stream.argtypes = [vp, C.POINTER(vp)]
         L.mc_occupancy.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.mc_use_graph.argtypes = [vp, C.c_int]
         L.mc_set_variant.argtypes = [vp, C.c_int]
@@ -691,10 +694,102 @@ class PhononMC:
         dT = torch.empty(self.ncell, dtype=torch.float64, device="cuda")
         q = q_cell.to(dtype=torch.float64, device="cuda").contiguous()
         pk = torch.zeros(int(self.cfg.n_packets), dtype=torch.int32, device="cuda") if packet_scatterings else None
-        cnt = np.zeros(10, np.uint64)
+        cnt = np.zeros(11, np.uint64)
         _ph_chk(_ph_lib().ph_mc_run(C.byref(self.cfg), _dptr(tables), _dptr(q), _dptr(t), _dptr(dT), _dptr(pk),
                                     cnt.ctypes.data_as(C.POINTER(C.c_uint64)), C.c_void_p(self.workspace.data_ptr()),
                                     self.workspace.numel(), _stream_ptr(stream)), "ph_mc_run")
         return dict(t_fs=t, dT=dT, scatterings=int(cnt[0]), wall_specular=int(cnt[1]), wall_diffuse=int(cnt[2]),
-                    absorbed=cnt[3:9].astype(np.int64), dropped=int(cnt[9]),
+                    absorbed=cnt[3:9].astype(np.int64), dropped=int(cnt[9]), segments=int(cnt[10]),
                     packet_scatterings=None if pk is None else pk.cpu().numpy().view(np.uint32))
+
+
+# --- electro-thermal iteration (include/gfhy.h) ---
+
+class HyConfig(C.Structure):
+    _fields_ = [("mat", PhMaterial), ("elec", PhElectrons), ("n_bins", C.c_int32), ("face", C.c_int32 * 6),
+                ("max_events", C.c_int32), ("n_packets", C.c_int64), ("seed", C.c_uint64), ("T_sink_K", C.c_double),
+                ("T_lin_K", C.c_double), ("warmup_intervals", C.c_int32), ("window_intervals", C.c_int32),
+                ("max_iterations", C.c_int32), ("relax", C.c_double), ("tol_K", C.c_double)]
+
+
+class HyRecord(C.Structure):
+    _fields_ = [("iteration", C.c_int32), ("instance", C.c_int32), ("source", C.c_int32), ("steady", C.c_int32),
+                ("drain_current_A", C.c_double), ("heat_W", C.c_double), ("emit_W", C.c_double),
+                ("T_lin_K", C.c_double), ("dT_max_K", C.c_double), ("dT_mean_K", C.c_double),
+                ("hot_cell", C.c_int32), ("pad", C.c_int32), ("change_K", C.c_double), ("R_th_KW", C.c_double),
+                ("packets_absorbed", C.c_uint64), ("packets_dropped", C.c_uint64)]
+
+
+HY_EXPORTS = ["hy_workspace_bytes", "hy_run"]
+EXPORTS = EXPORTS + HY_EXPORTS
+_hy_ready = False
+
+
+def _hy_lib():
+    global _hy_ready
+    L = lib()
+    if not _hy_ready:
+        vp = C.c_void_p
+        L.hy_workspace_bytes.argtypes = [vp, C.POINTER(HyConfig)]
+        L.hy_workspace_bytes.restype = C.c_size_t
+        L.hy_run.argtypes = [vp, C.POINTER(HyConfig), C.POINTER(C.c_double), vp, C.c_size_t, C.POINTER(HyRecord),
+                             C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.hy_run.restype = C.c_int
+        _hy_ready = True
+    return L
+
+
+def hy_config(h: dict) -> HyConfig:
+    """hy_config from a dict: mat (Table II dict), electrons (dict or None),
+    n_bins, faces (six names), max_events, n_packets, seed, T_sink_K,
+    T_lin_K, warmup_intervals, window_intervals, max_iterations, relax, tol_K."""
+    c = HyConfig()
+    c.mat = ph_material(h["mat"])
+    e = h.get("electrons")
+    if e:
+        c.elec = PhElectrons(float(e["n_m3"]), float(e["m_dos"]), float(e["D_a_eV"]), float(e["rho"]), float(e["v_g"]))
+    c.n_bins = int(h["n_bins"])
+    c.face[:] = [PH_FACE[f] for f in h["faces"]]
+    c.max_events = int(h.get("max_events", 1 << 22))
+    c.n_packets = int(h["n_packets"])
+    c.seed = int(h["seed"]) & 0xFFFFFFFFFFFFFFFF
+    c.T_sink_K = float(h["T_sink_K"])
+    c.T_lin_K = float(h.get("T_lin_K", 0.0))
+    c.warmup_intervals = int(h["warmup_intervals"])
+    c.window_intervals = int(h["window_intervals"])
+    c.max_iterations = int(h["max_iterations"])
+    c.relax = float(h.get("relax", 1.0))
+    c.tol_K = float(h.get("tol_K", 0.0))
+    return c
+
+
+def hy_workspace_bytes(ens: "Ensemble", h: dict) -> int:
+    c = hy_config(h)
+    return int(_hy_lib().hy_workspace_bytes(ens._ctx, C.byref(c)))
+
+
+def hy_run(ens: "Ensemble", h: dict, heat0_Wm3=None) -> dict:
+    """The coupled iteration on every instance of `ens` (device mode).
+    Returns the records (list of dicts, one per instance and iteration),
+    the iterations done and each instance's final lattice temperature."""
+    import torch
+    c = hy_config(h)
+    L = _hy_lib()
+    n = int(L.hy_workspace_bytes(ens._ctx, C.byref(c)))
+    if n == 0:
+        raise MCError(MC_E_ARG, "hy_workspace_bytes", "invalid configuration for this context")
+    ws = torch.empty(n, dtype=torch.uint8, device=ens.device)
+    cap = ens.n * c.max_iterations
+    recs = (HyRecord * cap)()
+    nrec, nit = C.c_int(0), C.c_int(0)
+    h0 = None
+    if heat0_Wm3 is not None:
+        h0 = np.ascontiguousarray(heat0_Wm3, dtype=np.float64).reshape(ens.n, ens.ncell)
+    rc = L.hy_run(ens._ctx, C.byref(c), None if h0 is None else _p(h0, C.c_double), C.c_void_p(ws.data_ptr()), n,
+                  recs, cap, C.byref(nrec), C.byref(nit))
+    out = [{k: getattr(recs[i], k) for k, _ in HyRecord._fields_ if k != "pad"} for i in range(nrec.value)]
+    ens._chk(rc, "hy_run")
+    T = np.zeros((ens.n, ens.ncell))
+    for i in range(ens.n):
+        ens._chk(lib().mc_get_lattice_temperature(ens._ctx, i, _p(T[i], C.c_double)), "mc_get_lattice_temperature")
+    return dict(records=out, iterations=nit.value, T_cells=T)

@@ -81,6 +81,38 @@ def device_config(n_particles: int = 200_000, Vgs: float = 0.0, Vds: float = 5.0
     return c
 
 
+# Table II: GaN's acoustic branches (q0 is the table's k0) and relaxation
+# constants; and the free electrons of the doped wire for Eq. (1) (the
+# electron density of 1e18 cm^-3 doping, Gamma1 mass, acoustic deformation
+# potential and mass density of Table I, and the averaged group velocity).
+GAN_PHONONS = dict(q0=10.94e9, w_max=3.50e13, A=5.26e-45, B1=1.10e-19, B2=200.0)
+WIRE_ELECTRONS = dict(n_m3=1e24, m_dos=0.21, D_a_eV=8.3, rho=6095.0, v_g=3338.0)
+
+# Phonon faces of the half-nanowire box (x = 0, x = L, y = 0, y = L, z = 0,
+# z = L): the source and drain contacts and the junction with the film below
+# are isothermal sinks, the cut along the wire's symmetry plane is specular,
+# the free sidewall and the top are diffuse.
+WIRE_FACES = ["isothermal", "isothermal", "specular", "diffuse", "isothermal", "diffuse"]
+
+
+def wire_heat_map(cfg: dict, power_W: float = 1e-3, x0_nm: float | None = None, sigma_nm: float = 60.0,
+                  seed: int = BASE_SEED + 7, noise: float = 0.3) -> np.ndarray:
+    """Synthetic net heat map (W/m^3 per subcell, index (ix*ny + iy)*nz + iz)
+    of the shape the electron windows produce: a Gaussian along x centred
+    just past the drain-side gate edge, uniform across the cut, with
+    multiplicative noise of relative size `noise` (so a few subcells turn
+    into sinks), scaled to `power_W` in total."""
+    nx, ny, nz = cfg["n_cells"]
+    L = cfg["L_nm"]
+    x0 = cfg["gate_x_nm"][1] + 50.0 if x0_nm is None else x0_nm
+    xc = (np.arange(nx) + 0.5) * L[0] / nx
+    prof = np.exp(-0.5 * ((xc - x0) / sigma_nm) ** 2)
+    rng = np.random.default_rng(seed)
+    q = prof[:, None] * (1.0 + noise * rng.standard_normal((nx, ny * nz)))
+    vc = (L[0] / nx) * (L[1] / ny) * (L[2] / nz) * 1e-27
+    return (q * power_W / (q.sum() * vc)).reshape(-1)
+
+
 def hotspot_T_map(cfg: dict, dT: float = 150.0, x0_nm: float | None = None, sigma_nm: float = 100.0) -> np.ndarray:
     """Lattice temperature per subcell: T0 plus a Gaussian hot spot along x,
     uniform in y and z (peak at the drain end unless x0 is given)."""

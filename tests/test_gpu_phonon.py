@@ -91,7 +91,7 @@ def _mc_case(G, oracle_mod, cfg, q, tables, n_packets):
     tab = torch.tensor(np.stack(tables), dtype=torch.float64, device="cuda")
     r = mc.ph_mc_run(tab, torch.tensor(q, dtype=torch.float64))
     t = r["t_fs"].cpu().numpy()
-    for key in ("scatterings", "wall_specular", "wall_diffuse", "dropped"):
+    for key in ("scatterings", "wall_specular", "wall_diffuse", "dropped", "segments"):
         assert r[key] == ref[key], (key, r[key], ref[key])
     assert np.array_equal(r["absorbed"], ref["absorbed"])
     scale = np.abs(ref["t_fs"]).max()

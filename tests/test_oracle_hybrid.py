@@ -1,0 +1,77 @@
+"""Pins of the reference electro-thermal iteration (coupling paragraph) and
+of the thermal resistance of the thermal-resistance passage.  The pieces it
+composes are pinned on their own (electron Monte Carlo, phonon tables,
+packet run); here: the temperature map is the isothermal faces' temperature
+plus a rise that is linear in the heat map, the update is the stated
+under-relaxation, the warm start replaces the first window, the rise peaks
+where the heat is generated (subcell indexing shared by both maps), every
+packet leaves through an isothermal face, and the stopping rule."""
+import numpy as np
+import pytest
+
+from oracle import hybrid_oracle as H
+from oracle import phonon_oracle as P
+from paper_1707_09073_amd import workloads as W
+
+GAN = P.table2("GaN")
+
+
+def _hy(**kw):
+    h = dict(mat=GAN, electrons=None, n_bins=128, faces=W.WIRE_FACES, n_packets=6000, seed=9, T_sink_K=300.0,
+             T_lin_K=300.0, warmup_intervals=4, window_intervals=10, max_iterations=1, relax=1.0, tol_K=0.0)
+    h.update(kw)
+    return h
+
+
+def _cfg(**kw):
+    return W.device_config(n_particles=1000, precision="fp64", **kw)
+
+
+def _heat0():
+    q = np.zeros((100, 18))
+    q[70:80] = 4e17                                      # W/m^3, a slab near the drain-side gate edge
+    q[20:22, :9] = -1e17                                 # and a weak sink
+    return q.reshape(1, 1800)
+
+
+def test_warm_start_rise_is_linear_in_the_heat_and_relaxed():
+    cfg = _cfg(Vds=3.0)
+    q = _heat0()
+    a = H.hybrid([cfg], _hy(), heat0_Wm3=q, threads=1)
+    b = H.hybrid([cfg], _hy(), heat0_Wm3=2.0 * q, threads=1)
+    ra, rb = a["records"][0], b["records"][0]
+    assert ra["source"] == 1 and ra["emit_W"] == 0.0 and ra["R_th_KW"] == 0.0
+    vc = (10.0 * 20.0 * 20.0) * 1e-27
+    assert ra["heat_W"] == pytest.approx(q.sum() * vc, rel=1e-12)
+    # same packets, twice the power per packet: twice the rise, exactly
+    assert np.array_equal(b["dT_maps"][0], 2.0 * a["dT_maps"][0])
+    assert np.allclose(a["T_cells"][0], 300.0 + a["dT_maps"][0], rtol=0, atol=1e-10)
+    # relax 0.4 from a uniform 320 K start: T = 320 + 0.4 (300 + dT - 320)
+    c = H.hybrid([dict(cfg, T_cells=np.full(1800, 320.0))], _hy(relax=0.4), heat0_Wm3=q, threads=1)
+    assert np.allclose(c["T_cells"][0], 320.0 + 0.4 * (300.0 + a["dT_maps"][0] - 320.0), rtol=0, atol=1e-10)
+    assert c["records"][0]["change_K"] == pytest.approx(np.abs(300.0 + a["dT_maps"][0] - 320.0).max(), rel=1e-12)
+
+
+def test_rise_peaks_where_the_heat_is_and_packets_leave_through_sinks():
+    r = H.hybrid([_cfg(Vds=3.0)], _hy(n_packets=20000), heat0_Wm3=_heat0())
+    rec = r["records"][0]
+    assert 70 <= rec["hot_cell"] // 18 < 80
+    prof = r["dT_maps"][0].reshape(100, 18).mean(1)
+    assert prof[70:80].min() > prof[:60].max()
+    assert prof[20:22].mean() < prof[40:50].mean()           # the sink cools its neighbourhood
+    assert rec["packets_absorbed"] == 20000 and rec["packets_dropped"] == 0
+
+
+def test_iterations_feed_the_temperature_back_and_stop_at_tolerance():
+    """Two electron windows: the second runs at the temperatures the first
+    produced (its tables linearised at their mean), and a tolerance above
+    any change stops after one iteration."""
+    cfg = _cfg(Vds=3.0)
+    r = H.hybrid([cfg], _hy(T_lin_K=0.0, max_iterations=2))
+    r0, r1 = r["records"]
+    assert r0["source"] == r1["source"] == 0 and r["iterations"] == 2
+    assert r0["T_lin_K"] == 300.0
+    assert r1["T_lin_K"] == pytest.approx(300.0 + r0["dT_mean_K"], rel=1e-12)
+    assert r0["emit_W"] > 0 and r0["R_th_KW"] == pytest.approx(r0["dT_max_K"] / r0["emit_W"], rel=1e-12)
+    s = H.hybrid([cfg], _hy(max_iterations=3, tol_K=1e9))
+    assert s["iterations"] == 1 and len(s["records"]) == 1
