@@ -110,3 +110,18 @@ def test_interface_conductance_detailed_balance_and_classical_limit():
     assert P.interface_conductance(GAN, GAN, T) == pytest.approx(want, rel=1e-5)
     # GaN/SiC at room temperature: a thermal boundary resistance of order 1e-8 m^2 K / W
     assert 5e-9 < 1.0 / P.interface_conductance(GAN, SIC, 300.0) < 1e-7
+
+
+def test_mean_free_path_accumulation_matches_the_paper():
+    """The thermal-resistance passage states that in bulk GaN at 415 K about
+    60% of the lattice conductivity comes from phonons with mean free paths
+    between 100 nm and 2 um.  Table II's dispersion, heat capacity and
+    relaxation times give that share (0.587)."""
+    m, T = GAN, 415.0
+    w = np.linspace(1e-6, 1.0 - 1e-9, 200001) * m["w_max"]
+    v = P.vg_of_w(m, w)
+    tau = 1.0 / P.inv_tau_bulk(m, w, T)
+    mfp = v * tau
+    c = P.heat_capacity(m, w, T) * v * v * tau
+    share = c[(mfp >= 100e-9) & (mfp < 2e-6)].sum() / c.sum()
+    assert 0.55 < share < 0.65, share
