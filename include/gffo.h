@@ -55,6 +55,20 @@ size_t fo_workspace_bytes(const fo_config *cfg);
 int fo_solve(const fo_config *cfg, const double *d_edges, const double *d_kappa, const double *d_q, double *d_T,
              int *iterations, double *rel_residual, void *d_ws, size_t ws_bytes, void *stream);
 
+/* Per-cell inputs of a chip problem: d_kappa[c] = h_kappa_by_material[
+ * d_material[c]] (host table of n_materials values, W/(m K); material ids
+ * 0 .. n_materials - 1), and d_q[c] = scale * d_src[d_src_index[c]] where
+ * d_src_index[c] >= 0 (the cell lies in a wire and takes that subcell's
+ * heat: the electron Monte Carlo's map, W per subcell, times the ratio of
+ * the cell's volume to the subcell's in `scale`), else 0.  Every wire takes
+ * the same map (the coupling paragraph finds the heat generation of the
+ * wires of the array nearly equal).  Device arrays of ncell entries (u8,
+ * i32), d_src of n_src entries.  Asynchronous.  MC_E_ARG for a bad pointer,
+ * count or material table (at most 16). */
+int fo_chip_fields(const uint8_t *d_material, const double *h_kappa_by_material, int n_materials,
+                   const int32_t *d_src_index, const double *d_src, int n_src, double scale, long long ncell,
+                   double *d_kappa, double *d_q, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

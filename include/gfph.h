@@ -74,6 +74,15 @@ int ph_tables(const ph_material *m, const ph_electrons *e, double T_K, int n_bin
 int ph_interface(const ph_material *m1, const ph_material *m2, const double *d_tables1, int n_bins, double *d_tau12,
                  double *d_sums, void *stream);
 
+/* Conductivity of a structure from the bins of one material (d_tables from
+ * ph_tables): kappa = sum_b C_b v_b^2 / (3 (1/tau_b + v_b / d)), the bulk
+ * mean free paths limited by the structure size d_m (Matthiessen's rule;
+ * the coupling paragraph limits them by the film thickness and the wire
+ * diameter for the Fourier analysis); d_m <= 0 gives the bulk value.  One
+ * device double to d_kappa (W/(m K)), summed over the bins in order.
+ * PH_E_ARG for a bad pointer or n_bins. */
+int ph_conductivity(const double *d_tables, int n_bins, double d_m, double *d_kappa, void *stream);
+
 /* Faces of the packet domain: specular (symmetry planes A and B of the
  * coupling paragraph), diffuse (adiabatic free surfaces, cosine-law
  * re-emission), isothermal (absorbing: the heat sink or the Fourier region

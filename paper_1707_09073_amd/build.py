@@ -10,9 +10,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgfmc.so")
 SOURCES = [os.path.join(CSRC, "gfmc.hip"), os.path.join(CSRC, "surrogate.hip"), os.path.join(CSRC, "phonon.hip"),
-           os.path.join(CSRC, "hybrid.hip")]
+           os.path.join(CSRC, "hybrid.hip"), os.path.join(CSRC, "fourier.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")] + \
-    [os.path.join(ROOT, "include", f) for f in ("gfmc.h", "gfph.h", "gfhy.h")]
+    [os.path.join(ROOT, "include", f) for f in ("gfmc.h", "gfph.h", "gfhy.h", "gffo.h")]
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                # packed FP32 VALU ops stay off (see the design notes)

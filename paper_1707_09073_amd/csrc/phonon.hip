@@ -420,6 +420,26 @@ __global__ void k_ph_dT(const double* __restrict__ t_cell, const double* __restr
   if (i < ncell) dT[i] = sums[0] * t_cell[i] * 1e-15 / (n_packets * sums[1] * vc_m3);
 }
 
+// size-limited conductivity: one workgroup, bins in order per thread, then a
+// fixed tree
+__global__ void __launch_bounds__(256) k_ph_conductivity(const double* __restrict__ tab, int nb, double d_m,
+                                                         double* out) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const double v = tab[nb + b], C = tab[2 * nb + b], it = tab[3 * nb + b];
+    const double rate = d_m > 0.0 ? it + v / d_m : it;
+    a += C * v * v / (3.0 * rate);
+  }
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
 struct PhLayout {
   size_t cum_cell, cum_emit, counts, next, sums, total;
 };
@@ -487,6 +507,12 @@ int ph_interface(const ph_material* m1, const ph_material* m2, const double* d_t
                  double* d_sums, void* stream) {
   if (!m1 || !m2 || !d_tables1 || n_bins < 1 || n_bins > 4096 || !d_sums) return PH_E_ARG;
   k_ph_interface<<<1, 256, 0, (hipStream_t)stream>>>(*m1, *m2, d_tables1, n_bins, d_tau12, d_sums);
+  return hipGetLastError() == hipSuccess ? PH_OK : PH_E_HIP;
+}
+
+int ph_conductivity(const double* d_tables, int n_bins, double d_m, double* d_kappa, void* stream) {
+  if (!d_tables || !d_kappa || n_bins < 1 || n_bins > 4096 || !std::isfinite(d_m)) return PH_E_ARG;
+  k_ph_conductivity<<<1, 256, 0, (hipStream_t)stream>>>(d_tables, n_bins, d_m, d_kappa);
   return hipGetLastError() == hipSuccess ? PH_OK : PH_E_HIP;
 }
 

@@ -586,7 +586,7 @@ class PhMcConfig(C.Structure):
                 ("seed", C.c_uint64), ("instance", C.c_uint32), ("max_events", C.c_int32), ("n_packets", C.c_int64)]
 
 
-PH_EXPORTS = ["ph_fermi_level", "ph_tables", "ph_interface", "ph_mc_workspace_bytes", "ph_mc_run"]
+PH_EXPORTS = ["ph_fermi_level", "ph_tables", "ph_interface", "ph_conductivity", "ph_mc_workspace_bytes", "ph_mc_run"]
 EXPORTS = EXPORTS + PH_EXPORTS
 _ph_ready = False
 
@@ -599,10 +599,11 @@ def _ph_lib():
         L.ph_fermi_level.argtypes = [C.c_double, C.c_double, C.c_double, dp, vp]
         L.ph_tables.argtypes = [C.POINTER(PhMaterial), C.POINTER(PhElectrons), C.c_double, C.c_int, dp, dp, vp]
         L.ph_interface.argtypes = [C.POINTER(PhMaterial), C.POINTER(PhMaterial), dp, C.c_int, dp, dp, vp]
+        L.ph_conductivity.argtypes = [dp, C.c_int, C.c_double, dp, vp]
         L.ph_mc_workspace_bytes.argtypes = [C.POINTER(PhMcConfig)]
         L.ph_mc_workspace_bytes.restype = C.c_size_t
         L.ph_mc_run.argtypes = [C.POINTER(PhMcConfig), dp, dp, dp, dp, dp, C.POINTER(C.c_uint64), vp, C.c_size_t, vp]
-        for n in ("ph_fermi_level", "ph_tables", "ph_interface", "ph_mc_run"):
+        for n in ("ph_fermi_level", "ph_tables", "ph_interface", "ph_conductivity", "ph_mc_run"):
             getattr(L, n).restype = C.c_int
         _ph_ready = True
     return L
@@ -662,6 +663,16 @@ def ph_interface(m1: dict, m2: dict, tables1, stream=None):
     _ph_chk(_ph_lib().ph_interface(C.byref(a), C.byref(b), _dptr(tables1), nb, _dptr(tau), _dptr(sums),
                                    _stream_ptr(stream)), "ph_interface")
     return tau, sums
+
+
+def ph_conductivity(tables, d_m: float, stream=None):
+    """Conductivity (W/m/K, a device tensor of one element) from bin tables
+    with the mean free paths limited by a structure size d_m (<= 0: bulk)."""
+    import torch
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    _ph_chk(_ph_lib().ph_conductivity(_dptr(tables), int(tables.shape[1]), float(d_m), _dptr(out),
+                                      _stream_ptr(stream)), "ph_conductivity")
+    return out
 
 
 class PhononMC:
@@ -793,3 +804,87 @@ def hy_run(ens: "Ensemble", h: dict, heat0_Wm3=None) -> dict:
     for i in range(ens.n):
         ens._chk(lib().mc_get_lattice_temperature(ens._ctx, i, _p(T[i], C.c_double)), "mc_get_lattice_temperature")
     return dict(records=out, iterations=nit.value, T_cells=T)
+
+
+# --- Fourier's-law spreading (include/gffo.h) ---
+
+class FoConfig(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("dirichlet", C.c_int32 * 6), ("k_interface", C.c_int32),
+                ("R_K_m2KW", C.c_double), ("T_sink_K", C.c_double), ("max_iterations", C.c_int32),
+                ("rtol", C.c_double)]
+
+
+FO_EXPORTS = ["fo_workspace_bytes", "fo_solve", "fo_chip_fields"]
+EXPORTS = EXPORTS + FO_EXPORTS
+_fo_ready = False
+
+
+def _fo_lib():
+    global _fo_ready
+    L = lib()
+    if not _fo_ready:
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.fo_workspace_bytes.argtypes = [C.POINTER(FoConfig)]
+        L.fo_workspace_bytes.restype = C.c_size_t
+        L.fo_solve.argtypes = [C.POINTER(FoConfig), vp, vp, vp, vp, C.POINTER(C.c_int), dp, vp, C.c_size_t, vp]
+        L.fo_solve.restype = C.c_int
+        L.fo_chip_fields.argtypes = [vp, dp, C.c_int, vp, vp, C.c_int, C.c_double, C.c_longlong, vp, vp, vp]
+        L.fo_chip_fields.restype = C.c_int
+        _fo_ready = True
+    return L
+
+
+def fo_config(cfg: dict) -> FoConfig:
+    c = FoConfig()
+    c.n[:] = [int(v) for v in cfg["n"]]
+    c.dirichlet[:] = [int(v) for v in cfg["dirichlet"]]
+    c.k_interface = int(cfg.get("k_interface", -1))
+    c.R_K_m2KW = float(cfg.get("R_K_m2KW", 0.0))
+    c.T_sink_K = float(cfg["T_sink_K"])
+    c.max_iterations = int(cfg.get("max_iterations", 20000))
+    c.rtol = float(cfg.get("rtol", 1e-12))
+    return c
+
+
+def fo_solve(cfg: dict, edges, kappa, q, stream=None, check: bool = True) -> dict:
+    """Temperature per cell (device tensor, K) of a conduction problem; edges
+    is the x, y, z edge coordinates (m) concatenated or a list of three."""
+    import torch
+    c = fo_config(cfg)
+    L = _fo_lib()
+    n = int(L.fo_workspace_bytes(C.byref(c)))
+    if n == 0:
+        raise MCError(MC_E_ARG, "fo_workspace_bytes", "invalid configuration")
+    if isinstance(edges, (list, tuple)):
+        edges = np.concatenate([np.asarray(e, np.float64) for e in edges])
+    e = torch.as_tensor(np.asarray(edges, np.float64) if not hasattr(edges, "data_ptr") else edges,
+                        dtype=torch.float64).to("cuda").contiguous()
+    k = torch.as_tensor(kappa, dtype=torch.float64).to("cuda").contiguous()
+    qq = torch.as_tensor(q, dtype=torch.float64).to("cuda").contiguous()
+    T = torch.empty_like(k)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    it, rel = C.c_int(0), C.c_double(0.0)
+    st = _stream_ptr(stream)
+    torch.cuda.current_stream().synchronize()
+    rc = L.fo_solve(C.byref(c), _dptr(e), _dptr(k), _dptr(qq), _dptr(T), C.byref(it), C.byref(rel), _dptr(ws), n, st)
+    if check and rc != MC_OK:
+        raise MCError(rc, "fo_solve", f"after {it.value} iterations, relative residual {rel.value:.3e}")
+    return dict(T=T, iterations=it.value, rel_residual=rel.value, status=rc)
+
+
+def fo_chip_fields(material, kappa_by_material, src_index, src, scale: float = 1.0, stream=None):
+    """Per-cell conductivity and heat of a chip problem (device tensors)."""
+    import torch
+    m = torch.as_tensor(material, dtype=torch.uint8).to("cuda").contiguous()
+    si = torch.as_tensor(src_index, dtype=torch.int32).to("cuda").contiguous()
+    sv = torch.as_tensor(src, dtype=torch.float64).to("cuda").contiguous()
+    kt = np.ascontiguousarray(kappa_by_material, dtype=np.float64)
+    nc = m.numel()
+    kap = torch.empty(nc, dtype=torch.float64, device="cuda")
+    q = torch.empty(nc, dtype=torch.float64, device="cuda")
+    torch.cuda.current_stream().synchronize()
+    rc = _fo_lib().fo_chip_fields(_dptr(m), _p(kt, C.c_double), int(kt.size), _dptr(si), _dptr(sv), int(sv.numel()),
+                                  float(scale), nc, _dptr(kap), _dptr(q), _stream_ptr(stream))
+    if rc != MC_OK:
+        raise MCError(rc, "fo_chip_fields")
+    return kap, q

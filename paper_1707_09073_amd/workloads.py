@@ -113,6 +113,82 @@ def wire_heat_map(cfg: dict, power_W: float = 1e-3, x0_nm: float | None = None, 
     return (q * power_W / (q.sum() * vc)).reshape(-1)
 
 
+def _graded(first: float, total: float, ratio: float) -> np.ndarray:
+    """Widths growing geometrically from `first` until they span `total`
+    (the last one trimmed to fit)."""
+    w, acc = [], 0.0
+    while acc < total * (1 - 1e-12):
+        d = min(first * ratio ** len(w), total - acc)
+        if d < 0.3 * first * ratio ** max(len(w) - 1, 0) and w:
+            w[-1] += d
+            break
+        w.append(d)
+        acc += d
+    return np.array(w)
+
+
+def chip_geometry(device: dict | None = None, n_wires: int = 31, pitch_nm: float = 240.0, margin_x_um: float = 7.0,
+                  margin_y_um: float = 4.0, film_um: float = 2.0, substrate_um: float = 30.0,
+                  growth: float = 1.25) -> dict:
+    """Half of the nanowire-array chip for the Fourier analysis (Fig. 1 of the
+    paper is absent; its dimensions here are readings): n_wires GaN wires of
+    twice the electron domain's cut width (y) and its height (z), one pitch
+    apart, over the electron domain's channel (x); a GaN film of film_um on
+    a SiC substrate of substrate_um whose bottom is the heat sink; graded
+    margins of margin_x_um and margin_y_um around the array.  The cut runs
+    through the middle wire's centre plane (a symmetry plane: adiabatic), so
+    that wire's half is the electron domain itself.
+
+    Wire cells have the electron subcells' widths, so every wire takes the
+    electron heat map cell for cell (mirrored about its own centre plane).
+    Returns n, edges (x, y, z in m), material per cell (0 void, 1 SiC,
+    2 GaN film, 3 GaN wire), src_index per cell (the electron subcell, or
+    -1), k_interface (first film cell), the wire and chip extents, and the
+    cell index of the middle wire's subcells."""
+    dev = device or device_config(n_particles=1000)
+    (Lx, Ly, Lz), (nxw, nyw, nzw) = dev["L_nm"], dev["n_cells"]
+    dxw, dyw, dzw = Lx / nxw, Ly / nyw, Lz / nzw
+    half = int(n_wires) // 2                               # full wires beside the middle one
+    # x: the channel at the subcell width, graded margins on both sides
+    mx = _graded(dxw, margin_x_um * 1e3, growth)
+    wx = np.concatenate([mx[::-1], np.full(nxw, dxw), mx])
+    i0 = len(mx)
+    # y: from the middle wire's centre plane through the last wire, then a margin
+    span_y = half * pitch_nm + Ly
+    ny_arr = int(round(span_y / dyw))
+    assert abs(ny_arr * dyw - span_y) < 1e-6 * span_y and abs(pitch_nm / dyw - round(pitch_nm / dyw)) < 1e-9
+    wy = np.concatenate([np.full(ny_arr, dyw), _graded(dyw, margin_y_um * 1e3, growth)])
+    # z: substrate (graded toward the sink), film (graded toward the interface), the wire layer
+    film = _graded(dzw, film_um * 1e3, growth)[::-1]
+    sub = _graded(film[0] * growth, substrate_um * 1e3, growth)[::-1]
+    wz = np.concatenate([sub, film, np.full(nzw, dzw)])
+    k_if, k_w = len(sub), len(sub) + len(film)
+    nx, ny, nz = len(wx), len(wy), len(wz)
+    ex = np.concatenate([[0.0], np.cumsum(wx)]) - mx.sum()       # x = 0 at the source end of the channel
+    ey = np.concatenate([[0.0], np.cumsum(wy)])
+    ez = np.concatenate([[0.0], np.cumsum(wz)]) - (sub.sum() + film.sum())   # z = 0 at the wires' foot
+    mat = np.zeros((nx, ny, nz), np.uint8)
+    mat[:, :, :k_if] = 1
+    mat[:, :, k_if:k_w] = 2
+    src = np.full((nx, ny, nz), -1, np.int32)
+    step = int(round(pitch_nm / dyw))
+    for w in range(half + 1):
+        for jj in range(-nyw, nyw):
+            j = w * step + jj
+            if j < 0:
+                continue                                   # the middle wire's other half lies across the cut
+            iy = jj if jj >= 0 else -jj - 1                # distance from the wire's centre plane, in subcells
+            for kk in range(nzw):
+                for ii in range(nxw):
+                    mat[i0 + ii, j, k_w + kk] = 3
+                    src[i0 + ii, j, k_w + kk] = (ii * nyw + iy) * nzw + kk
+    middle = np.array([((i0 + ii) * ny + iy) * nz + k_w + kk
+                       for ii in range(nxw) for iy in range(nyw) for kk in range(nzw)])
+    return dict(n=[nx, ny, nz], edges=[ex * 1e-9, ey * 1e-9, ez * 1e-9], material=mat.ravel(), src_index=src.ravel(),
+                k_interface=k_if, k_wire=k_w, i_wire=i0, middle_cells=middle, wires=half + 1,
+                half_wires=2 * half + 1)
+
+
 def hotspot_T_map(cfg: dict, dT: float = 150.0, x0_nm: float | None = None, sigma_nm: float = 100.0) -> np.ndarray:
     """Lattice temperature per subcell: T0 plus a Gaussian hot spot along x,
     uniform in y and z (peak at the drain end unless x0 is given)."""

@@ -1,5 +1,5 @@
 """Host-only checks of the C ABI: the library loads, exports every entry
-point declared in include/gfmc.h, gfph.h and gfhy.h, and the binding's struct layouts equal the
+point declared in include/gfmc.h, gfph.h, gfhy.h and gffo.h, and the binding's struct layouts equal the
 C compiler's.  No compute call is made (there may be no GPU)."""
 import ctypes as C
 import os
@@ -10,7 +10,7 @@ import tempfile
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("gfmc.h", "gfph.h", "gfhy.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("gfmc.h", "gfph.h", "gfhy.h", "gffo.h")]
 
 
 def _declared_functions():
@@ -49,6 +49,7 @@ def test_struct_layouts_match_the_header(gfmc):
 #include "gfmc.h"
 #include "gfph.h"
 #include "gfhy.h"
+#include "gffo.h"
 int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(mc_material), sizeof(mc_config), sizeof(mc_tally_out),
          sizeof(mc_particles_view), offsetof(mc_config, seed));
@@ -60,6 +61,7 @@ int main(void) {
          sizeof(ph_electrons));
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(hy_config), offsetof(hy_config, n_packets), offsetof(hy_config, tol_K),
          sizeof(hy_record), offsetof(hy_record, hot_cell), offsetof(hy_record, packets_dropped));
+  printf("%zu %zu %zu\n", sizeof(fo_config), offsetof(fo_config, R_K_m2KW), offsetof(fo_config, rtol));
   return 0;
 }
 """
@@ -77,7 +79,8 @@ int main(void) {
             C.sizeof(gfmc.PhMcConfig), gfmc.PhMcConfig.seed.offset, gfmc.PhMcConfig.n_packets.offset,
             C.sizeof(gfmc.PhElectrons),
             C.sizeof(gfmc.HyConfig), gfmc.HyConfig.n_packets.offset, gfmc.HyConfig.tol_K.offset,
-            C.sizeof(gfmc.HyRecord), gfmc.HyRecord.hot_cell.offset, gfmc.HyRecord.packets_dropped.offset]
+            C.sizeof(gfmc.HyRecord), gfmc.HyRecord.hot_cell.offset, gfmc.HyRecord.packets_dropped.offset,
+            C.sizeof(gfmc.FoConfig), gfmc.FoConfig.R_K_m2KW.offset, gfmc.FoConfig.rtol.offset]
     assert [int(x) for x in out] == want
 
 
