@@ -266,19 +266,43 @@ def hybrid_sweep(args) -> dict:
     hy = dict(mat=W.GAN_PHONONS, electrons=W.WIRE_ELECTRONS, n_bins=1024,
               faces=W.WIRE_FACES, n_packets=1 << 21, seed=W.BASE_SEED + 12, T_sink_K=300.0, T_lin_K=0.0,
               warmup_intervals=50, window_intervals=150, max_iterations=3, relax=1.0, tol_K=0.0)
+    chip = None
+    if args.chip:
+        # the 31-wire half chip: conductivities from the bins at T_sink (the
+        # wire and film with their mean free paths limited by 120 nm and
+        # 2 um), 1/R_K of Eq. (3) from GaN's side; the wire's contact ends
+        # adiabatic, its foot on the film
+        geom = W.chip_geometry(cfgs[0])
+        tg, _ = gfmc.ph_tables(W.GAN_PHONONS, 300.0, 2048)
+        ts, _ = gfmc.ph_tables(W.SIC_PHONONS, 300.0, 2048)
+        kt = [0.0, float(gfmc.ph_conductivity(ts, 0.0).cpu()[0]), float(gfmc.ph_conductivity(tg, 2e-6).cpu()[0]),
+              float(gfmc.ph_conductivity(tg, 120e-9).cpu()[0])]
+        _, sums = gfmc.ph_interface(W.GAN_PHONONS, W.SIC_PHONONS, tg)
+        chip = dict(fo=dict(n=geom["n"], dirichlet=[0, 0, 0, 0, 1, 0], k_interface=geom["k_interface"],
+                            R_K_m2KW=1.0 / float(sums.cpu()[0]), rtol=1e-10, max_iterations=100000),
+                    edges=geom["edges"], material=geom["material"], src_index=geom["src_index"],
+                    base_index=geom["base_index"], kappa_by_material=kt, half_wires=2 * geom["half_wires"])
+        hy["faces"] = W.WIRE_FACES_ON_CHIP
     ens = gfmc.Ensemble(cfgs, device="cuda:0")
     ens.mc_use_graph(True)
     ens.mc_step(10 * cfgs[0]["substeps"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = gfmc.hy_run(ens, hy)
+    r = gfmc.hy_run(ens, hy, chip=chip)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     last = [x for x in r["records"] if x["iteration"] == r["iterations"] - 1]
-    return dict(wall=wall, iterations=r["iterations"], electrons=per * len(vds), vds=vds,
-                R_th_KW=[x["R_th_KW"] for x in last], dT_max_K=[x["dT_max_K"] for x in last],
-                emit_W=[x["emit_W"] for x in last], drain_current_A=[x["drain_current_A"] for x in last],
-                hot_x_nm=[(x["hot_cell"] // 18 + 0.5) * 10.0 for x in last], records=r["records"])
+    out = dict(wall=wall, iterations=r["iterations"], electrons=per * len(vds), vds=vds,
+               R_th_KW=[x["R_th_KW"] for x in last], dT_max_K=[x["dT_max_K"] for x in last],
+               emit_W=[x["emit_W"] for x in last], drain_current_A=[x["drain_current_A"] for x in last],
+               hot_x_nm=[(x["hot_cell"] // 18 + 0.5) * 10.0 for x in last], records=r["records"])
+    if chip:
+        out.update(R_th_device_KW=[x["R_th_device_KW"] for x in last],
+                   R_th_fourier_KW=[x["R_th_fourier_KW"] for x in last],
+                   dT_junction_max_K=[x["dT_junction_max_K"] for x in last],
+                   dT_fourier_max_K=[x["dT_fourier_max_K"] for x in last],
+                   fo_iterations=[x["fo_iterations"] for x in last])
+    return out
 
 
 def main() -> int:
@@ -303,6 +327,8 @@ def main() -> int:
                          "phonon: the phonon packet kernel; hybrid: the electro-thermal iteration over five drain "
                          "voltages")
     ap.add_argument("--packets", type=int, default=1 << 23, help="packets per launch of the phonon workload")
+    ap.add_argument("--chip", action="store_true",
+                    help="hybrid workload: add the Fourier's-law stage over the 31-wire chip")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration) and exit")
     args = ap.parse_args()
@@ -374,9 +400,13 @@ def main() -> int:
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "hybrid iteration: 5 half-nanowire instances (Vds 2-10 V, Vgs 0, 1e18 cm^-3) "
                                    "in one context, 50 + 150 intervals and 2^21 phonon packets per instance and "
-                                   "iteration, 3 iterations from 300 K", "electrons": r["electrons"]},
+                                   "iteration, 3 iterations from 300 K" +
+                                   (", with the Fourier stage over the 31-wire half chip" if args.chip else ""),
+                       "electrons": r["electrons"]},
             "vds_V": r["vds"], "R_th_KW": r["R_th_KW"], "dT_max_K": r["dT_max_K"], "emit_W": r["emit_W"],
-            "drain_current_A": r["drain_current_A"], "hot_x_nm": r["hot_x_nm"]}), flush=True)
+            "drain_current_A": r["drain_current_A"], "hot_x_nm": r["hot_x_nm"],
+            **({k: r[k] for k in ("R_th_device_KW", "R_th_fourier_KW", "dT_junction_max_K", "dT_fourier_max_K",
+                                  "fo_iterations")} if args.chip else {})}), flush=True)
         return 0
     if args.workload == "sweep64":
         r = sweep64(args)

@@ -20,6 +20,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "gffo.h"
 #include "gfmc.h"
 #include "gfph.h"
 
@@ -45,6 +46,26 @@ typedef struct {
   double tol_K;             /* stop once every instance's largest change |T_sink + dT - T| is at most tol_K */
 } hy_config;
 
+/* The chip around the wire for the Fourier's-law stage of the iteration
+ * (coupling paragraph: the Fourier analysis covers the whole chip, the
+ * phonon Monte Carlo refines the temperature along the wire).  Every wire
+ * of the array takes the instance's heat map; the chip's temperature below
+ * each electron subcell column becomes that column's reference in place of
+ * T_sink: T = T_chip(base) + dT_packets.  The packet domain's faces then
+ * should pass the wire's heat to the film only (its foot isothermal, its
+ * contact ends adiabatic). */
+typedef struct {
+  fo_config fo;                  /* grid, held faces (the sink), interface plane and R_K, solver settings; its
+                                    T_sink_K is replaced by hy_config's */
+  const double *d_edges;         /* device: the chip's edges, as fo_solve takes them */
+  const uint8_t *d_material;     /* device, per chip cell */
+  const int32_t *d_src_index;    /* device, per chip cell: the electron subcell whose heat it takes, or -1 */
+  const int32_t *d_base_index;   /* device, per electron subcell: the chip cell below its column (in the film) */
+  double kappa_by_material[16];  /* W/(m K), by material id */
+  int32_t n_materials;
+  int32_t half_wires;            /* half-wires of the whole device: its power is half_wires x E_Emit */
+} hy_chip;
+
 /* One instance's record of one iteration. */
 typedef struct {
   int32_t iteration, instance;
@@ -61,11 +82,18 @@ typedef struct {
   double change_K;          /* largest |T_sink + dT - T| over the subcells, before relaxation */
   double R_th_KW;           /* dT_max / emit_W (0 when emit_W is 0) */
   uint64_t packets_absorbed, packets_dropped;
+  /* with a chip (zero without): */
+  double dT_junction_max_K; /* largest rise of the chip below the wire */
+  double dT_fourier_max_K;  /* largest rise of the chip anywhere (the wire by Fourier's law) */
+  double R_th_device_KW;    /* dT_max / (half_wires x emit_W): the device thermal resistance */
+  double R_th_fourier_KW;   /* dT_fourier_max / (half_wires x emit_W) */
+  int32_t fo_iterations;
+  int32_t pad2;
 } hy_record;
 
 /* Device workspace bytes of hy_run on ctx with cfg (256-byte aligned), 0 if
  * the configuration is invalid for the context. */
-size_t hy_workspace_bytes(const mc_ctx *ctx, const hy_config *cfg);
+size_t hy_workspace_bytes(const mc_ctx *ctx, const hy_config *cfg, const hy_chip *chip);
 
 /* The coupled iteration over every instance of a device-mode context.  Per
  * iteration: every instance's electrons run warmup_intervals, a new window
@@ -82,13 +110,16 @@ size_t hy_workspace_bytes(const mc_ctx *ctx, const hy_config *cfg);
  * h_records (host, may be NULL) receives one record per instance and
  * iteration, in order, at most max_records; *n_records the number written,
  * *iterations the iterations done (either may be NULL).  Synchronises the
- * stream every iteration.  Returns MC_OK; MC_E_ARG for a bad argument or
- * configuration (bulk mode, faces, sizes, a workspace that is too small or
- * not 256-byte aligned, a temperature that would not be positive); or the
- * first error of an electron call (its sticky device flags included), after
- * writing the records done so far. */
-int hy_run(mc_ctx *ctx, const hy_config *cfg, const double *h_heat0_Wm3, void *d_ws, size_t ws_bytes,
-           hy_record *h_records, int max_records, int *n_records, int *iterations);
+ * stream every iteration.  chip (may be NULL): the Fourier stage above, run
+ * after each packet run on the same heat map.  Returns MC_OK; MC_E_ARG for a
+ * bad argument or configuration (bulk mode, faces, sizes, a chip whose
+ * indices or tables do not fit, a workspace that is too small or not
+ * 256-byte aligned, a temperature that would not be positive); MC_E_RANGE
+ * if a chip solve misses its tolerance; or the first error of an electron
+ * call (its sticky device flags included), after writing the records done
+ * so far. */
+int hy_run(mc_ctx *ctx, const hy_config *cfg, const hy_chip *chip, const double *h_heat0_Wm3, void *d_ws,
+           size_t ws_bytes, hy_record *h_records, int max_records, int *n_records, int *iterations);
 
 #ifdef __cplusplus
 }

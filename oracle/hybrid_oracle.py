@@ -18,12 +18,18 @@ until no subcell moves by more than tol_K or after max_iterations.  The
 thermal resistance of an iteration is max dT over the emitted phonon power
 (emission only) of its window.  The phonon domain of an instance is its own
 box and subcells.
+
+With a chip (the Fourier's-law stage of the coupling paragraph), every
+wire of the array takes the instance's heat map, the chip's steady
+conduction problem is solved (fourier_oracle), and the chip's temperature
+below each subcell column replaces T_sink in step 3.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from oracle import emc_oracle as E
+from oracle import fourier_oracle as F
 from oracle import phonon_oracle as P
 
 
@@ -34,15 +40,17 @@ def _mean(x) -> float:
     return s / len(x)
 
 
-def hybrid(mc_cfgs: list[dict], hy: dict, heat0_Wm3=None, threads: int = 0) -> dict:
+def hybrid(mc_cfgs: list[dict], hy: dict, heat0_Wm3=None, threads: int = 0, chip: dict | None = None) -> dict:
     """mc_cfgs: device-mode instance configurations (emc_oracle.make_config
     keys; a T_cells entry sets the starting temperature); hy: mat (Table II
     dict), electrons (dict or None), n_bins, faces, max_events, n_packets,
     seed, T_sink_K, T_lin_K (<= 0: the instance's mean subcell temperature
     at the iteration's start), warmup_intervals, window_intervals,
     max_iterations, relax, tol_K.  heat0_Wm3 ([n_inst][ncell] or None): a
-    warm-start heat map for the first iteration.  Returns the records (one
-    per instance and iteration, as the library's hy_record), the iterations
+    warm-start heat map for the first iteration.  chip (or None): fo (n,
+    dirichlet, k_interface, R_K_m2KW), edges, material, src_index,
+    base_index, kappa_by_material, half_wires.  Returns the records (one per
+    instance and iteration, as the library's hy_record), the iterations
     done, the final temperatures, and per record the dT map."""
     ors = [E.Oracle(c) for c in mc_cfgs]
     n = len(ors)
@@ -85,13 +93,29 @@ def hybrid(mc_cfgs: list[dict], hy: dict, heat0_Wm3=None, threads: int = 0) -> d
                         max_events=int(hy.get("max_events", 1 << 22)))
             ph = E.phonon_mc(pcfg, q, v, inv_tau, Cb, int(hy["n_packets"]), threads)
             dT = ph["dT"]
-            T_new = hy["T_sink_K"] + dT
+            base = np.full(nc, float(hy["T_sink_K"]))
+            if chip is not None:
+                kap = np.asarray(chip["kappa_by_material"], np.float64)[np.asarray(chip["material"])]
+                si = np.asarray(chip["src_index"])
+                qc = np.where(si >= 0, q[np.maximum(si, 0)], 0.0)
+                fcfg = dict(chip["fo"], T_sink_K=hy["T_sink_K"])
+                T_chip = F.solve(fcfg, chip["edges"], kap, qc)
+                base = T_chip[np.asarray(chip["base_index"])]
+            rise = (base - hy["T_sink_K"]) + dT
+            T_new = base + dT
             change = float(np.abs(T_new - T[i]).max())
             T[i] = T[i] + hy["relax"] * (T_new - T[i])
             o.set_temperature(T[i])
-            r.update(dT_max_K=float(dT.max()), dT_mean_K=_mean(dT), hot_cell=int(np.argmax(dT)), change_K=change,
-                     R_th_KW=float(dT.max()) / r["emit_W"] if r["emit_W"] > 0 else 0.0,
+            mx = float(rise.max())
+            r.update(dT_max_K=mx, dT_mean_K=_mean(rise), hot_cell=int(np.argmax(rise)), change_K=change,
+                     R_th_KW=mx / r["emit_W"] if r["emit_W"] > 0 else 0.0,
                      packets_absorbed=int(ph["absorbed"].sum()), packets_dropped=int(ph["dropped"]))
+            if chip is not None:
+                P_dev = chip["half_wires"] * r["emit_W"]
+                fmax = float(T_chip.max()) - hy["T_sink_K"]
+                r.update(dT_junction_max_K=max(0.0, float((base - hy["T_sink_K"]).max())), dT_fourier_max_K=fmax,
+                         R_th_device_KW=mx / P_dev if P_dev > 0 else 0.0,
+                         R_th_fourier_KW=fmax / P_dev if P_dev > 0 else 0.0)
             records.append(r)
             maps.append(dT)
             worst = max(worst, change)

@@ -24,6 +24,31 @@ size_t up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
 
 int from_ph(int rc) { return rc == PH_OK ? MC_OK : rc == PH_E_ARG ? MC_E_ARG : MC_E_HIP; }
 
+// the chip's temperature below each electron subcell column (NaN for an
+// index outside the chip, which the host refuses)
+__global__ void k_hy_gather(const double* __restrict__ T_chip, long long nc_chip, const int32_t* __restrict__ base,
+                            int n, double* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) {
+    const long long b = base[c];
+    out[c] = (b >= 0 && b < nc_chip) ? T_chip[b] : __longlong_as_double(0x7ff8000000000000ll);
+  }
+}
+
+// largest value of a chip array (one workgroup, fixed order)
+__global__ void __launch_bounds__(1024) k_hy_max(const double* __restrict__ v, long long n, double* out) {
+  __shared__ double s[1024];
+  double m = -1.0e300;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, v[i]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
 // Per-instance slice of the workspace: tables [4][nb], Fermi level, source,
 // packet times, temperature rise, and the packet run's own workspace.
 struct Slice {
@@ -61,15 +86,53 @@ ph_mc_config phonon_domain(const mc_config& m, const hy_config& h, int inst) {
   return p;
 }
 
+// The chip stage's region, shared by the instances (they run it in turn):
+// conductivity, heat and temperature per chip cell, the gathered reference
+// per subcell, the largest rise, the solver's workspace.
+struct ChipSlice {
+  size_t kap, q, T, base, mx, fo, fo_bytes, total;
+  long long nc;
+};
+
 // Everything hy_run needs to know about the context, validated.
 struct Plan {
   int n_inst = 0, ncell = 0;
   std::vector<mc_config> cfg;
   std::vector<ph_mc_config> ph;
   Slice sl;
+  bool chip = false;
+  fo_config fo;
+  ChipSlice cs;
 };
 
-int plan_of(const mc_ctx* ctx, const hy_config* h, Plan* p) {
+int plan_chip(const hy_config* h, const hy_chip* chip, int ncell, Plan* p) {
+  if (!chip) return MC_OK;
+  if (!chip->d_edges || !chip->d_material || !chip->d_src_index || !chip->d_base_index || chip->n_materials < 1 ||
+      chip->n_materials > 16 || chip->half_wires < 1)
+    return MC_E_ARG;
+  for (int t = 0; t < chip->n_materials; ++t)
+    if (!(chip->kappa_by_material[t] >= 0.0) || !std::isfinite(chip->kappa_by_material[t])) return MC_E_ARG;
+  p->fo = chip->fo;
+  p->fo.T_sink_K = h->T_sink_K;
+  const size_t fb = fo_workspace_bytes(&p->fo);
+  if (fb == 0) return MC_E_ARG;
+  ChipSlice& c = p->cs;
+  c.nc = (long long)p->fo.n[0] * p->fo.n[1] * p->fo.n[2];
+  size_t off = 0;
+  auto take = [&](size_t b) { const size_t o = off; off += up(b); return o; };
+  c.kap = take(sizeof(double) * c.nc);
+  c.q = take(sizeof(double) * c.nc);
+  c.T = take(sizeof(double) * c.nc);
+  c.base = take(sizeof(double) * ncell);
+  c.mx = take(sizeof(double));
+  c.fo = take(fb);
+  c.fo_bytes = fb;
+  c.total = off;
+  p->chip = true;
+  return MC_OK;
+}
+
+int plan_of(const mc_ctx* ctx, const hy_config* h, const hy_chip* chip, Plan* p) {
   if (!ctx || !h) return MC_E_ARG;
   if (mc_get_instances(ctx, &p->n_inst) != MC_OK || mc_get_ncell(ctx, &p->ncell) != MC_OK) return MC_E_ARG;
   if (h->window_intervals < 1 || h->warmup_intervals < 0 || h->max_iterations < 1 || !(h->relax > 0.0) ||
@@ -86,27 +149,29 @@ int plan_of(const mc_ctx* ctx, const hy_config* h, Plan* p) {
     if (b > ph_bytes) ph_bytes = b;
   }
   p->sl = slice_of(h->n_bins, p->ncell, ph_bytes);
-  return MC_OK;
+  return plan_chip(h, chip, p->ncell, p);
 }
+
+size_t total_bytes(const Plan& p) { return p.sl.total * (size_t)p.n_inst + (p.chip ? p.cs.total : 0); }
 
 }  // namespace
 
 extern "C" {
 
-size_t hy_workspace_bytes(const mc_ctx* ctx, const hy_config* cfg) {
+size_t hy_workspace_bytes(const mc_ctx* ctx, const hy_config* cfg, const hy_chip* chip) {
   Plan p;
-  if (plan_of(ctx, cfg, &p) != MC_OK) return 0;
-  return p.sl.total * (size_t)p.n_inst;
+  if (plan_of(ctx, cfg, chip, &p) != MC_OK) return 0;
+  return total_bytes(p);
 }
 
-int hy_run(mc_ctx* ctx, const hy_config* h, const double* h_heat0, void* d_ws, size_t ws_bytes, hy_record* rec,
-           int max_records, int* n_records, int* iterations) {
+int hy_run(mc_ctx* ctx, const hy_config* h, const hy_chip* chip, const double* h_heat0, void* d_ws, size_t ws_bytes,
+           hy_record* rec, int max_records, int* n_records, int* iterations) {
   if (n_records) *n_records = 0;
   if (iterations) *iterations = 0;
   Plan p;
-  int rc = plan_of(ctx, h, &p);
+  int rc = plan_of(ctx, h, chip, &p);
   if (rc != MC_OK) return rc;
-  if (!d_ws || ((uintptr_t)d_ws & (kAlign - 1)) || ws_bytes < p.sl.total * (size_t)p.n_inst || max_records < 0)
+  if (!d_ws || ((uintptr_t)d_ws & (kAlign - 1)) || ws_bytes < total_bytes(p) || max_records < 0)
     return MC_E_ARG;
   void* stream = nullptr;
   if (mc_get_stream(ctx, &stream) != MC_OK) return MC_E_ARG;
@@ -118,7 +183,9 @@ int hy_run(mc_ctx* ctx, const hy_config* h, const double* h_heat0, void* d_ws, s
   std::vector<std::vector<double>> T(p.n_inst, std::vector<double>(nc));
   for (int i = 0; i < p.n_inst; ++i)
     if ((rc = mc_get_lattice_temperature(ctx, i, T[i].data())) != MC_OK) return rc;
-  std::vector<double> heat(nc), q(nc), dT(nc), Tn(nc);
+  std::vector<double> heat(nc), q(nc), dT(nc), Tn(nc), base(nc, h->T_sink_K);
+  char* cw = ws + p.sl.total * (size_t)p.n_inst;  // the chip region
+  auto cat = [&](size_t off) { return (double*)(cw + off); };
   int written = 0;
 
   for (int it = 0; it < h->max_iterations; ++it) {
@@ -177,18 +244,42 @@ int hy_run(mc_ctx* ctx, const hy_config* h, const double* h_heat0, void* d_ws, s
       if ((rc = from_ph(ph_mc_run(&p.ph[i], d_tab, d_q, (double*)at(i, p.sl.t), d_dT, nullptr, cnt,
                                   at(i, p.sl.ph), p.sl.ph_bytes, stream))) != MC_OK)
         return rc;
+      double fo_max = 0.0;
+      if (p.chip) {
+        // the Fourier stage: every wire takes this heat map; the chip's
+        // temperature below each subcell column is its reference
+        const ChipSlice& cs = p.cs;
+        if ((rc = fo_chip_fields(chip->d_material, chip->kappa_by_material, chip->n_materials, chip->d_src_index,
+                                 d_q, nc, 1.0, cs.nc, cat(cs.kap), cat(cs.q), stream)) != MC_OK)
+          return rc;
+        int fit = 0;
+        double rel = 0.0;
+        rc = fo_solve(&p.fo, chip->d_edges, cat(cs.kap), cat(cs.q), cat(cs.T), &fit, &rel, cw + cs.fo, cs.fo_bytes,
+                      stream);
+        r.fo_iterations = fit;
+        if (rc != MC_OK) return rc;
+        k_hy_gather<<<(nc + 255) / 256, 256, 0, st>>>(cat(cs.T), cs.nc, chip->d_base_index, nc, cat(cs.base));
+        k_hy_max<<<1, 1024, 0, st>>>(cat(cs.T), cs.nc, cat(cs.mx));
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(base.data(), cat(cs.base), sizeof(double) * nc, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&fo_max, cat(cs.mx), sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+          return MC_E_HIP;
+      }
       if (hipMemcpyAsync(dT.data(), d_dT, sizeof(double) * nc, hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)
         return MC_E_HIP;
       for (int f = 0; f < 6; ++f) r.packets_absorbed += cnt[3 + f];
       r.packets_dropped = cnt[9];
       // the new temperature map and its under-relaxed update
-      double mx = dT[0], sum = 0.0, change = 0.0;
+      double mx = -1.0e300, sum = 0.0, change = 0.0, jmax = 0.0;
       int hot = 0;
       for (int c = 0; c < nc; ++c) {
-        if (dT[c] > mx) { mx = dT[c]; hot = c; }
-        sum += dT[c];
-        const double tn = h->T_sink_K + dT[c];
+        if (!std::isfinite(base[c])) return MC_E_ARG;
+        const double rise = base[c] - h->T_sink_K + dT[c];
+        if (rise > mx) { mx = rise; hot = c; }
+        if (base[c] - h->T_sink_K > jmax) jmax = base[c] - h->T_sink_K;
+        sum += rise;
+        const double tn = base[c] + dT[c];
         const double d = std::fabs(tn - T[i][c]);
         if (d > change) change = d;
         Tn[c] = T[i][c] + h->relax * (tn - T[i][c]);
@@ -199,6 +290,13 @@ int hy_run(mc_ctx* ctx, const hy_config* h, const double* h_heat0, void* d_ws, s
       r.hot_cell = hot;
       r.change_K = change;
       r.R_th_KW = r.emit_W > 0.0 ? mx / r.emit_W : 0.0;
+      if (p.chip) {
+        r.dT_junction_max_K = jmax;
+        r.dT_fourier_max_K = fo_max - h->T_sink_K;
+        const double P = chip->half_wires * r.emit_W;
+        r.R_th_device_KW = P > 0.0 ? mx / P : 0.0;
+        r.R_th_fourier_KW = P > 0.0 ? r.dT_fourier_max_K / P : 0.0;
+      }
       if ((rc = mc_set_lattice_temperature(ctx, i, Tn.data())) != MC_OK) return rc;
       T[i] = Tn;
       if (change > worst) worst = change;

@@ -714,98 +714,6 @@ class PhononMC:
                     packet_scatterings=None if pk is None else pk.cpu().numpy().view(np.uint32))
 
 
-# --- electro-thermal iteration (include/gfhy.h) ---
-
-class HyConfig(C.Structure):
-    _fields_ = [("mat", PhMaterial), ("elec", PhElectrons), ("n_bins", C.c_int32), ("face", C.c_int32 * 6),
-                ("max_events", C.c_int32), ("n_packets", C.c_int64), ("seed", C.c_uint64), ("T_sink_K", C.c_double),
-                ("T_lin_K", C.c_double), ("warmup_intervals", C.c_int32), ("window_intervals", C.c_int32),
-                ("max_iterations", C.c_int32), ("relax", C.c_double), ("tol_K", C.c_double)]
-
-
-class HyRecord(C.Structure):
-    _fields_ = [("iteration", C.c_int32), ("instance", C.c_int32), ("source", C.c_int32), ("steady", C.c_int32),
-                ("drain_current_A", C.c_double), ("heat_W", C.c_double), ("emit_W", C.c_double),
-                ("T_lin_K", C.c_double), ("dT_max_K", C.c_double), ("dT_mean_K", C.c_double),
-                ("hot_cell", C.c_int32), ("pad", C.c_int32), ("change_K", C.c_double), ("R_th_KW", C.c_double),
-                ("packets_absorbed", C.c_uint64), ("packets_dropped", C.c_uint64)]
-
-
-HY_EXPORTS = ["hy_workspace_bytes", "hy_run"]
-EXPORTS = EXPORTS + HY_EXPORTS
-_hy_ready = False
-
-
-def _hy_lib():
-    global _hy_ready
-    L = lib()
-    if not _hy_ready:
-        vp = C.c_void_p
-        L.hy_workspace_bytes.argtypes = [vp, C.POINTER(HyConfig)]
-        L.hy_workspace_bytes.restype = C.c_size_t
-        L.hy_run.argtypes = [vp, C.POINTER(HyConfig), C.POINTER(C.c_double), vp, C.c_size_t, C.POINTER(HyRecord),
-                             C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
-        L.hy_run.restype = C.c_int
-        _hy_ready = True
-    return L
-
-
-def hy_config(h: dict) -> HyConfig:
-    """hy_config from a dict: mat (Table II dict), electrons (dict or None),
-    n_bins, faces (six names), max_events, n_packets, seed, T_sink_K,
-    T_lin_K, warmup_intervals, window_intervals, max_iterations, relax, tol_K."""
-    c = HyConfig()
-    c.mat = ph_material(h["mat"])
-    e = h.get("electrons")
-    if e:
-        c.elec = PhElectrons(float(e["n_m3"]), float(e["m_dos"]), float(e["D_a_eV"]), float(e["rho"]), float(e["v_g"]))
-    c.n_bins = int(h["n_bins"])
-    c.face[:] = [PH_FACE[f] for f in h["faces"]]
-    c.max_events = int(h.get("max_events", 1 << 22))
-    c.n_packets = int(h["n_packets"])
-    c.seed = int(h["seed"]) & 0xFFFFFFFFFFFFFFFF
-    c.T_sink_K = float(h["T_sink_K"])
-    c.T_lin_K = float(h.get("T_lin_K", 0.0))
-    c.warmup_intervals = int(h["warmup_intervals"])
-    c.window_intervals = int(h["window_intervals"])
-    c.max_iterations = int(h["max_iterations"])
-    c.relax = float(h.get("relax", 1.0))
-    c.tol_K = float(h.get("tol_K", 0.0))
-    return c
-
-
-def hy_workspace_bytes(ens: "Ensemble", h: dict) -> int:
-    c = hy_config(h)
-    return int(_hy_lib().hy_workspace_bytes(ens._ctx, C.byref(c)))
-
-
-def hy_run(ens: "Ensemble", h: dict, heat0_Wm3=None) -> dict:
-    """The coupled iteration on every instance of `ens` (device mode).
-    Returns the records (list of dicts, one per instance and iteration),
-    the iterations done and each instance's final lattice temperature."""
-    import torch
-    c = hy_config(h)
-    L = _hy_lib()
-    n = int(L.hy_workspace_bytes(ens._ctx, C.byref(c)))
-    if n == 0:
-        raise MCError(MC_E_ARG, "hy_workspace_bytes", "invalid configuration for this context")
-    ws = torch.empty(n, dtype=torch.uint8, device=ens.device)
-    cap = ens.n * c.max_iterations
-    recs = (HyRecord * cap)()
-    nrec, nit = C.c_int(0), C.c_int(0)
-    h0 = None
-    if heat0_Wm3 is not None:
-        h0 = np.ascontiguousarray(heat0_Wm3, dtype=np.float64).reshape(ens.n, ens.ncell)
-    rc = L.hy_run(ens._ctx, C.byref(c), None if h0 is None else _p(h0, C.c_double), C.c_void_p(ws.data_ptr()), n,
-                  recs, cap, C.byref(nrec), C.byref(nit))
-    out = [{k: getattr(recs[i], k) for k, _ in HyRecord._fields_ if k != "pad"} for i in range(nrec.value)]
-    ens._chk(rc, "hy_run")
-    T = np.zeros((ens.n, ens.ncell))
-    for i in range(ens.n):
-        ens._chk(lib().mc_get_lattice_temperature(ens._ctx, i, _p(T[i], C.c_double)), "mc_get_lattice_temperature")
-    return dict(records=out, iterations=nit.value, T_cells=T)
-
-
 # --- Fourier's-law spreading (include/gffo.h) ---
 
 class FoConfig(C.Structure):
@@ -888,3 +796,131 @@ def fo_chip_fields(material, kappa_by_material, src_index, src, scale: float = 1
     if rc != MC_OK:
         raise MCError(rc, "fo_chip_fields")
     return kap, q
+
+
+# --- electro-thermal iteration (include/gfhy.h) ---
+
+class HyConfig(C.Structure):
+    _fields_ = [("mat", PhMaterial), ("elec", PhElectrons), ("n_bins", C.c_int32), ("face", C.c_int32 * 6),
+                ("max_events", C.c_int32), ("n_packets", C.c_int64), ("seed", C.c_uint64), ("T_sink_K", C.c_double),
+                ("T_lin_K", C.c_double), ("warmup_intervals", C.c_int32), ("window_intervals", C.c_int32),
+                ("max_iterations", C.c_int32), ("relax", C.c_double), ("tol_K", C.c_double)]
+
+
+class HyRecord(C.Structure):
+    _fields_ = [("iteration", C.c_int32), ("instance", C.c_int32), ("source", C.c_int32), ("steady", C.c_int32),
+                ("drain_current_A", C.c_double), ("heat_W", C.c_double), ("emit_W", C.c_double),
+                ("T_lin_K", C.c_double), ("dT_max_K", C.c_double), ("dT_mean_K", C.c_double),
+                ("hot_cell", C.c_int32), ("pad", C.c_int32), ("change_K", C.c_double), ("R_th_KW", C.c_double),
+                ("packets_absorbed", C.c_uint64), ("packets_dropped", C.c_uint64),
+                ("dT_junction_max_K", C.c_double), ("dT_fourier_max_K", C.c_double), ("R_th_device_KW", C.c_double),
+                ("R_th_fourier_KW", C.c_double), ("fo_iterations", C.c_int32), ("pad2", C.c_int32)]
+
+
+HY_EXPORTS = ["hy_workspace_bytes", "hy_run"]
+EXPORTS = EXPORTS + HY_EXPORTS
+_hy_ready = False
+
+
+def _hy_lib():
+    global _hy_ready
+    L = lib()
+    if not _hy_ready:
+        vp = C.c_void_p
+        L.hy_workspace_bytes.argtypes = [vp, C.POINTER(HyConfig), vp]
+        L.hy_workspace_bytes.restype = C.c_size_t
+        L.hy_run.argtypes = [vp, C.POINTER(HyConfig), vp, C.POINTER(C.c_double), vp, C.c_size_t, C.POINTER(HyRecord),
+                             C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.hy_run.restype = C.c_int
+        _hy_ready = True
+    return L
+
+
+def hy_config(h: dict) -> HyConfig:
+    """hy_config from a dict: mat (Table II dict), electrons (dict or None),
+    n_bins, faces (six names), max_events, n_packets, seed, T_sink_K,
+    T_lin_K, warmup_intervals, window_intervals, max_iterations, relax, tol_K."""
+    c = HyConfig()
+    c.mat = ph_material(h["mat"])
+    e = h.get("electrons")
+    if e:
+        c.elec = PhElectrons(float(e["n_m3"]), float(e["m_dos"]), float(e["D_a_eV"]), float(e["rho"]), float(e["v_g"]))
+    c.n_bins = int(h["n_bins"])
+    c.face[:] = [PH_FACE[f] for f in h["faces"]]
+    c.max_events = int(h.get("max_events", 1 << 22))
+    c.n_packets = int(h["n_packets"])
+    c.seed = int(h["seed"]) & 0xFFFFFFFFFFFFFFFF
+    c.T_sink_K = float(h["T_sink_K"])
+    c.T_lin_K = float(h.get("T_lin_K", 0.0))
+    c.warmup_intervals = int(h["warmup_intervals"])
+    c.window_intervals = int(h["window_intervals"])
+    c.max_iterations = int(h["max_iterations"])
+    c.relax = float(h.get("relax", 1.0))
+    c.tol_K = float(h.get("tol_K", 0.0))
+    return c
+
+
+class HyChip(C.Structure):
+    _fields_ = [("fo", FoConfig), ("d_edges", C.c_void_p), ("d_material", C.c_void_p), ("d_src_index", C.c_void_p),
+                ("d_base_index", C.c_void_p), ("kappa_by_material", C.c_double * 16), ("n_materials", C.c_int32),
+                ("half_wires", C.c_int32)]
+
+
+def hy_chip(chip: dict):
+    """(HyChip, the device tensors it points to) from a dict: fo (an fo_solve
+    configuration), edges, material, src_index, base_index (host arrays or
+    tensors), kappa_by_material, half_wires."""
+    import torch
+    keep = dict(edges=torch.as_tensor(np.concatenate([np.asarray(e, np.float64) for e in chip["edges"]]),
+                                      dtype=torch.float64).cuda(),
+                material=torch.as_tensor(np.asarray(chip["material"], np.uint8)).cuda(),
+                src=torch.as_tensor(np.asarray(chip["src_index"], np.int32)).cuda(),
+                base=torch.as_tensor(np.asarray(chip["base_index"], np.int32)).cuda())
+    c = HyChip()
+    c.fo = fo_config(dict(chip["fo"], T_sink_K=chip["fo"].get("T_sink_K", 0.0)))
+    c.d_edges, c.d_material = keep["edges"].data_ptr(), keep["material"].data_ptr()
+    c.d_src_index, c.d_base_index = keep["src"].data_ptr(), keep["base"].data_ptr()
+    kt = list(chip["kappa_by_material"])
+    c.kappa_by_material[:len(kt)] = [float(v) for v in kt]
+    c.n_materials = len(kt)
+    c.half_wires = int(chip["half_wires"])
+    torch.cuda.synchronize()
+    return c, keep
+
+
+def hy_workspace_bytes(ens: "Ensemble", h: dict, chip: dict | None = None) -> int:
+    c = hy_config(h)
+    ch = hy_chip(chip) if chip else None
+    return int(_hy_lib().hy_workspace_bytes(ens._ctx, C.byref(c), None if ch is None else C.byref(ch[0])))
+
+
+def hy_run(ens: "Ensemble", h: dict, heat0_Wm3=None, chip: dict | None = None) -> dict:
+    """The coupled iteration on every instance of `ens` (device mode), with
+    the Fourier stage when `chip` is given (see hy_chip).  Returns the
+    records (list of dicts, one per instance and iteration), the iterations
+    done and each instance's final lattice temperature."""
+    import torch
+    c = hy_config(h)
+    L = _hy_lib()
+    ch = hy_chip(chip) if chip else None
+    chp = None if ch is None else C.byref(ch[0])
+    n = int(L.hy_workspace_bytes(ens._ctx, C.byref(c), chp))
+    if n == 0:
+        raise MCError(MC_E_ARG, "hy_workspace_bytes", "invalid configuration for this context")
+    ws = torch.empty(n, dtype=torch.uint8, device=ens.device)
+    cap = ens.n * c.max_iterations
+    recs = (HyRecord * cap)()
+    nrec, nit = C.c_int(0), C.c_int(0)
+    h0 = None
+    if heat0_Wm3 is not None:
+        h0 = np.ascontiguousarray(heat0_Wm3, dtype=np.float64).reshape(ens.n, ens.ncell)
+    torch.cuda.synchronize()
+    rc = L.hy_run(ens._ctx, C.byref(c), chp, None if h0 is None else _p(h0, C.c_double), C.c_void_p(ws.data_ptr()),
+                  n, recs, cap, C.byref(nrec), C.byref(nit))
+    out = [{k: getattr(recs[i], k) for k, _ in HyRecord._fields_ if k not in ("pad", "pad2")}
+           for i in range(nrec.value)]
+    ens._chk(rc, "hy_run")
+    T = np.zeros((ens.n, ens.ncell))
+    for i in range(ens.n):
+        ens._chk(lib().mc_get_lattice_temperature(ens._ctx, i, _p(T[i], C.c_double)), "mc_get_lattice_temperature")
+    return dict(records=out, iterations=nit.value, T_cells=T)

@@ -81,11 +81,12 @@ def device_config(n_particles: int = 200_000, Vgs: float = 0.0, Vds: float = 5.0
     return c
 
 
-# Table II: GaN's acoustic branches (q0 is the table's k0) and relaxation
-# constants; and the free electrons of the doped wire for Eq. (1) (the
+# Table II: GaN's and 6H-SiC's acoustic branches (q0 is the table's k0) and
+# relaxation constants; and the free electrons of the doped wire for Eq. (1) (the
 # electron density of 1e18 cm^-3 doping, Gamma1 mass, acoustic deformation
 # potential and mass density of Table I, and the averaged group velocity).
 GAN_PHONONS = dict(q0=10.94e9, w_max=3.50e13, A=5.26e-45, B1=1.10e-19, B2=200.0)
+SIC_PHONONS = dict(q0=8.94e9, w_max=7.12e13, A=1.00e-45, B1=0.596e-19, B2=235.0)
 WIRE_ELECTRONS = dict(n_m3=1e24, m_dos=0.21, D_a_eV=8.3, rho=6095.0, v_g=3338.0)
 
 # Phonon faces of the half-nanowire box (x = 0, x = L, y = 0, y = L, z = 0,
@@ -93,6 +94,10 @@ WIRE_ELECTRONS = dict(n_m3=1e24, m_dos=0.21, D_a_eV=8.3, rho=6095.0, v_g=3338.0)
 # are isothermal sinks, the cut along the wire's symmetry plane is specular,
 # the free sidewall and the top are diffuse.
 WIRE_FACES = ["isothermal", "isothermal", "specular", "diffuse", "isothermal", "diffuse"]
+# The same box when the chip around it is solved by Fourier's law: the wire's
+# heat passes to the film only, so the contact ends are adiabatic (diffuse)
+# and the foot, held at the film's temperature below it, is the one sink.
+WIRE_FACES_ON_CHIP = ["diffuse", "diffuse", "specular", "diffuse", "isothermal", "diffuse"]
 
 
 def wire_heat_map(cfg: dict, power_W: float = 1e-3, x0_nm: float | None = None, sigma_nm: float = 60.0,
@@ -184,8 +189,11 @@ def chip_geometry(device: dict | None = None, n_wires: int = 31, pitch_nm: float
                     src[i0 + ii, j, k_w + kk] = (ii * nyw + iy) * nzw + kk
     middle = np.array([((i0 + ii) * ny + iy) * nz + k_w + kk
                        for ii in range(nxw) for iy in range(nyw) for kk in range(nzw)])
+    # per electron subcell: the film cell below its column, under the middle wire
+    base = np.array([((i0 + ii) * ny + iy) * nz + k_w - 1
+                     for ii in range(nxw) for iy in range(nyw) for kk in range(nzw)], np.int32)
     return dict(n=[nx, ny, nz], edges=[ex * 1e-9, ey * 1e-9, ez * 1e-9], material=mat.ravel(), src_index=src.ravel(),
-                k_interface=k_if, k_wire=k_w, i_wire=i0, middle_cells=middle, wires=half + 1,
+                base_index=base, k_interface=k_if, k_wire=k_w, i_wire=i0, middle_cells=middle, wires=half + 1,
                 half_wires=2 * half + 1)
 
 

@@ -131,3 +131,31 @@ def test_hybrid_full_device(G):
     i_cold = c.mc_observables()["drain_current_A"]
     _say("second window: heated", recs[1]["drain_current_A"], "A, at 300 K", i_cold, "A")
     assert recs[1]["drain_current_A"] < i_cold
+
+
+def test_hybrid_with_the_chip_matches_the_reference(G):
+    """The iteration with the Fourier's-law stage on a small array (five
+    wires over a 200 nm channel): each window's heat map heats every wire,
+    the chip's junction temperature lifts the packets' rise; records and
+    temperatures against the reference iteration (direct chip solves).
+    Counts exact; what the chip's temperature enters to 2e-7: the
+    conjugate gradients stop at a relative residual of 1e-13, and the error
+    of the temperature is that times the operator's condition number (3e-8
+    of the rise measured here)."""
+    dev = W.device_config(n_particles=3000, precision="fp64", Vds=3.0, n_cells=(20, 3, 6), L_nm=(200.0, 60.0, 120.0),
+                          seed=107)
+    g = W.chip_geometry(dev, n_wires=5, margin_x_um=0.4, margin_y_um=0.3, film_um=0.3, substrate_um=1.0)
+    chip = dict(fo=dict(n=g["n"], dirichlet=[0, 0, 0, 0, 1, 0], k_interface=g["k_interface"], R_K_m2KW=2.3e-8,
+                        rtol=1e-13, max_iterations=50000),
+                edges=g["edges"], material=g["material"], src_index=g["src_index"], base_index=g["base_index"],
+                kappa_by_material=[0.0, 350.0, 125.0, 35.6], half_wires=5)
+    hy = _hy(faces=W.WIRE_FACES_ON_CHIP, n_packets=10000, warmup_intervals=4, window_intervals=10)
+    _say("hybrid with chip: small device and array, 2 iterations")
+    e = G.Ensemble(dev)
+    g_run = G.hy_run(e, hy, chip=chip)
+    o = H.hybrid([dev], hy, chip=chip)
+    _compare(g_run, o, rel_ph=2e-7)
+    for a, b in zip(g_run["records"], o["records"]):
+        for k in ("dT_junction_max_K", "dT_fourier_max_K", "R_th_device_KW", "R_th_fourier_KW"):
+            assert a[k] == pytest.approx(b[k], rel=2e-7), (k, a[k], b[k])
+        assert a["fo_iterations"] > 0 and a["dT_junction_max_K"] > 0

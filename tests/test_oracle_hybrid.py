@@ -75,3 +75,34 @@ def test_iterations_feed_the_temperature_back_and_stop_at_tolerance():
     assert r0["emit_W"] > 0 and r0["R_th_KW"] == pytest.approx(r0["dT_max_K"] / r0["emit_W"], rel=1e-12)
     s = H.hybrid([cfg], _hy(max_iterations=3, tol_K=1e9))
     assert s["iterations"] == 1 and len(s["records"]) == 1
+
+
+def _small_chip(kappa=(0.0, 350.0, 125.0, 35.0), R_K=2.3e-8):
+    dev = W.device_config(n_particles=600, precision="fp64", Vds=3.0, n_cells=(20, 3, 6), L_nm=(200.0, 60.0, 120.0))
+    g = W.chip_geometry(dev, n_wires=5, margin_x_um=0.4, margin_y_um=0.3, film_um=0.3, substrate_um=1.0)
+    chip = dict(fo=dict(n=g["n"], dirichlet=[0, 0, 0, 0, 1, 0], k_interface=g["k_interface"], R_K_m2KW=R_K),
+                edges=g["edges"], material=g["material"], src_index=g["src_index"], base_index=g["base_index"],
+                kappa_by_material=list(kappa), half_wires=5)
+    return dev, g, chip
+
+
+def test_chip_stage_reduces_to_the_sink_and_adds_the_spreading():
+    """A chip of near-infinite conductivity without interface resistance
+    holds every junction at T_sink: the iteration is the one without a chip.
+    With GaN and SiC conductivities, the junction below the wire rises and
+    the wire's temperature is that rise plus the packets' rise above it."""
+    dev, g, chip = _small_chip()
+    hy = _hy(faces=W.WIRE_FACES_ON_CHIP, warmup_intervals=2, window_intervals=6, n_packets=3000)
+    q = np.zeros((20, 18))
+    q[12:16] = 4e17
+    heat0 = q.reshape(1, -1)
+    plain = H.hybrid([dev], hy, heat0_Wm3=heat0, threads=1)
+    stiff = dict(chip, kappa_by_material=[0.0, 1e12, 1e12, 1e12], fo=dict(chip["fo"], R_K_m2KW=0.0))
+    s = H.hybrid([dev], hy, heat0_Wm3=heat0, threads=1, chip=stiff)
+    assert np.allclose(s["T_cells"], plain["T_cells"], rtol=0, atol=1e-6)
+    c = H.hybrid([dev], hy, heat0_Wm3=heat0, threads=1, chip=chip)
+    r = c["records"][0]
+    assert r["dT_junction_max_K"] > 0 and r["dT_fourier_max_K"] > r["dT_junction_max_K"]
+    rise = c["T_cells"][0] - 300.0
+    assert np.all(rise >= plain["T_cells"][0] - 300.0 - 1e-9)       # the same packets, lifted by the junction
+    assert r["dT_max_K"] == pytest.approx(rise.max(), rel=1e-12)
