@@ -248,6 +248,42 @@ def phonon_packets(args) -> dict:
     return dict(n=n, wall=wall, avg_ms=ms / args.steps, dT_max=float(dT.max()), **tot)
 
 
+FO_BYTES_PER_CELL_ITERATION = 136   # SpMV 48 (diag, p, three conductances read, Ap written), update 56, direction 32
+
+
+def fourier_chip(args) -> dict:
+    """The Fourier's-law solve over the 31-wire half chip (1.03e6 cells):
+    conductivities from the bins at 300 K, the interface resistance of
+    Eq. (3), a 1 mW synthetic heat map per half-wire on every wire."""
+    import numpy as np
+    import torch
+    from paper_1707_09073_amd import gfmc, workloads as W
+    dev = W.device_config(n_particles=1000)
+    geom = W.chip_geometry(dev)
+    tg, _ = gfmc.ph_tables(W.GAN_PHONONS, 300.0, 2048)
+    ts, _ = gfmc.ph_tables(W.SIC_PHONONS, 300.0, 2048)
+    kt = [0.0, float(gfmc.ph_conductivity(ts, 0.0).cpu()[0]), float(gfmc.ph_conductivity(tg, 2e-6).cpu()[0]),
+          float(gfmc.ph_conductivity(tg, 120e-9).cpu()[0])]
+    _, sums = gfmc.ph_interface(W.GAN_PHONONS, W.SIC_PHONONS, tg)
+    L, nc = dev["L_nm"], dev["n_cells"]
+    vc = (L[0] / nc[0]) * (L[1] / nc[1]) * (L[2] / nc[2]) * 1e-27
+    kap, q = gfmc.fo_chip_fields(geom["material"], kt, geom["src_index"], W.wire_heat_map(dev, power_W=1e-3) * vc)
+    cfg = dict(n=geom["n"], dirichlet=[0, 0, 0, 0, 1, 0], k_interface=geom["k_interface"],
+               R_K_m2KW=1.0 / float(sums.cpu()[0]), T_sink_K=300.0, rtol=1e-10, max_iterations=100000)
+    for _ in range(max(1, args.warmup)):
+        gfmc.fo_solve(cfg, geom["edges"], kap, q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for _ in range(args.steps):
+        r = gfmc.fo_solve(cfg, geom["edges"], kap, q)
+        its += r["iterations"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    T = r["T"].cpu().numpy()
+    return dict(cells=int(np.prod(geom["n"])), wall=wall, iterations=its, dT_max=float(T.max()) - 300.0)
+
+
 def hybrid_sweep(args) -> dict:
     """The electro-thermal iteration as a batched drain-voltage sweep: five
     device instances (Vds = 2, 4, 6, 8, 10 V, Vgs = 0, 2e6 electrons each,
@@ -321,11 +357,11 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true", help="keep the default (or given) launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sg-batch", type=int, default=4096, help="batch of the surrogate workload")
-    ap.add_argument("--workload", choices=["device1e7", "sweep64", "surrogate", "phonon", "hybrid"],
+    ap.add_argument("--workload", choices=["device1e7", "sweep64", "surrogate", "phonon", "hybrid", "fourier"],
                     default="device1e7",
                     help="device1e7: one 10M-electron device (the headline); sweep64: 64-instance batched sweep; "
                          "phonon: the phonon packet kernel; hybrid: the electro-thermal iteration over five drain "
-                         "voltages")
+                         "voltages; fourier: the chip-scale conduction solve")
     ap.add_argument("--packets", type=int, default=1 << 23, help="packets per launch of the phonon workload")
     ap.add_argument("--chip", action="store_true",
                     help="hybrid workload: add the Fourier's-law stage over the 31-wire chip")
@@ -390,6 +426,25 @@ def main() -> int:
                          "avg_launch_ms": r["avg_ms"],
                          "note": "launch time includes the one-thread set-up and the temperature kernels; "
                                  "divisions and transcendentals count one operation each"}}), flush=True)
+        return 0
+    if args.workload == "fourier":
+        r = fourier_chip(args)
+        ci = r["cells"] * r["iterations"]
+        achieved = ci * FO_BYTES_PER_CELL_ITERATION / r["wall"] / 1e9
+        print(json.dumps({
+            "metric": "chip conduction: conjugate-gradient cell-iterations/s", "value": ci / r["wall"],
+            "unit": "cell-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["wall"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "Fourier's-law solve of the 31-wire GaN-on-SiC half chip (146 x 201 x 35 cells), "
+                                   "size-limited conductivities, Eq. (3) interface resistance, 1 mW per half-wire",
+                       "cells": r["cells"]},
+            "iterations_per_solve": r["iterations"] / args.steps, "dT_max_K": r["dT_max"],
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "bytes_per_cell_iteration": FO_BYTES_PER_CELL_ITERATION,
+                         "note": "whole solves timed on the host clock (five launches per iteration and a host "
+                                 "check every 25 iterations included)"}}), flush=True)
         return 0
     if args.workload == "hybrid":
         r = hybrid_sweep(args)
