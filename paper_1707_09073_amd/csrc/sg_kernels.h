@@ -63,6 +63,32 @@ __device__ __forceinline__ uint4 load_chunk(const bf16* p, long ld, int r, int c
   return v;
 }
 
+// The 32 x 32 block of C at (r0, c0) held by one wavefront's accumulator
+// (lane l, item j: row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32), with
+// the product's epilogue: store, + bias, + bias and GELU (pre-activation in
+// FP32 and activation in BF16), or times the GELU derivative.
+template <int EPI>
+__device__ __forceinline__ void epilogue(const GemmArgs& g, const f32x16& acc, int r0, int c0, int lane) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int row = r0 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+    const int col = c0 + (lane & 31);
+    if (row >= g.M || col >= g.N) continue;
+    const float v = acc[j];
+    if (EPI == EPI_STORE) {
+      g.Cf[(long)row * g.ldcf + col] = v;
+    } else if (EPI == EPI_BIAS) {
+      g.Cf[(long)row * g.ldcf + col] = v + g.bias[col];
+    } else if (EPI == EPI_BIAS_GELU) {
+      const float z = v + g.bias[col];
+      g.Cf[(long)row * g.ldcf + col] = z;
+      g.Cb[(long)row * g.ldcb + col] = (bf16)gelu(z);
+    } else {
+      g.Cb[(long)row * g.ldcb + col] = (bf16)(v * gelu_grad(g.Z[(long)row * g.ldz + col]));
+    }
+  }
+}
+
 // C[M x N] = opA(A)[M x K] opB(B)[K x N], BF16 in, FP32 accumulate, with an
 // epilogue.  opA(i,k) = A[i*lda + k] (TA false) or A[k*lda + i] (TA true);
 // opB(k,j) = B[k*ldb + j] (TB false) or B[j*ldb + k] (TB true).
@@ -176,25 +202,119 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
   for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < MB; ++ni)
+    for (int ni = 0; ni < MB; ++ni) epilogue<EPI>(g, acc[mi][ni], m0 + wm + mi * 32, n0 + wn + ni * 32, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Products whose operands are both K-contiguous (A [M][K], B [N][K]: the
+// forward products and dX): the K slabs go from global memory straight into
+// LDS (global_load_lds_dwordx4: each lane's 16 bytes land at the wavefront's
+// LDS base + 16 x lane), so no registers stage them; the next slab's copy is
+// in flight while the matrix cores work on the current one (two stages per
+// workgroup, 64 KB, so two workgroups per compute unit share its LDS).
+// These products are bound by how fast operand tiles reach the compute
+// units from L2 (about 14 B per clock per CU measured), so the tiles are
+// 128 x 128 (half the traffic of 64 x 64 per flop) and each XCD takes a
+// contiguous eighth of the tiles (a few row tiles by all column tiles), so
+// that its operands stay in its own L2.  Rows and K chunks outside the
+// matrices read a 16-byte block of zeros.  K must be a multiple of 8.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+static __device__ __attribute__((aligned(16))) const uint4 g_zero16[1] = {{0u, 0u, 0u, 0u}};
+
+// s_waitcnt with vmcnt <= n (expcnt and lgkmcnt not waited for)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+constexpr int kLdsBM = 128, kLdsBK = 64, kLdsStages = 2;
+constexpr int kLdsChunks = kLdsBK / 8;                   // 16-byte chunks per slab row
+constexpr int kLdsSlab = kLdsBM * kLdsChunks * 16;       // bytes of one operand's slab
+constexpr int kLdsBytes = kLdsStages * 2 * kLdsSlab;     // 64 KB per workgroup
+
+// LDS position (16-byte units) of chunk c of slab row r: chunks permuted by
+// r & 7 within the row, so the fragment reads of 8 consecutive rows at one
+// chunk fall on distinct bank groups
+__device__ __forceinline__ int lds_pos(int r, int c) { return r * kLdsChunks + (c ^ (r & 7)); }
+
+__host__ __device__ inline int lds_tiles(int M, int N) { return ((N + kLdsBM - 1) / kLdsBM) * ((M + kLdsBM - 1) / kLdsBM); }
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm_lds(GemmArgs g) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // workgroup w runs on XCD w % 8; XCD x takes tiles [x per, (x + 1) per)
+  const int gx = (g.N + kLdsBM - 1) / kLdsBM, T = lds_tiles(g.M, g.N), per = (T + 7) / 8;
+  const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (t >= T) return;
+  const int m0 = (t / gx) * kLdsBM, n0 = (t % gx) * kLdsBM;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int nk = (g.K + kLdsBK - 1) / kLdsBK;
+  // one stage: each wavefront copies 4 blocks of 8 slab rows (1 KB) of A and
+  // 4 of B; lane l of a block fills LDS unit l, i.e. row l / 8, the chunk
+  // that lds_pos puts there
+  auto issue = [&](int s) {
+    char* sa = lds + (s % kLdsStages) * 2 * kLdsSlab;
+    char* sb = sa + kLdsSlab;
+    const int k0 = s * kLdsBK;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int row = m0 + wm + mi * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-        const int col = n0 + wn + ni * 32 + (lane & 31);
-        if (row >= g.M || col >= g.N) continue;
-        const float v = acc[mi][ni][j];
-        if (EPI == EPI_STORE) {
-          g.Cf[(long)row * g.ldcf + col] = v;
-        } else if (EPI == EPI_BIAS) {
-          g.Cf[(long)row * g.ldcf + col] = v + g.bias[col];
-        } else if (EPI == EPI_BIAS_GELU) {
-          const float z = v + g.bias[col];
-          g.Cf[(long)row * g.ldcf + col] = z;
-          g.Cb[(long)row * g.ldcb + col] = (bf16)gelu(z);
-        } else {
-          g.Cb[(long)row * g.ldcb + col] = (bf16)(v * gelu_grad(g.Z[(long)row * g.ldz + col]));
-        }
+    for (int i = 0; i < 4; ++i) {
+      const int blk = wave * 4 + i;
+      const int u = blk * 64 + lane;
+      const int r = u / kLdsChunks, c = (u % kLdsChunks) ^ (r & 7);
+      const int kk = k0 + c * 8;
+      const bf16* pa = (m0 + r < g.M && kk < g.K) ? g.A + (long)(m0 + r) * g.lda + kk : (const bf16*)g_zero16;
+      const bf16* pb = (n0 + r < g.N && kk < g.K) ? g.B + (long)(n0 + r) * g.ldb + kk : (const bf16*)g_zero16;
+      __builtin_amdgcn_global_load_lds((glb_void_t*)pa, (lds_void_t*)(sa + blk * 1024), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((glb_void_t*)pb, (lds_void_t*)(sb + blk * 1024), 16, 0, 0);
+    }
+  };
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
+  issue(0);
+  for (int s = 0; s < nk; ++s) {
+    // this wavefront's copies of slab s have landed (nothing else of it is
+    // in flight); the barrier then covers every wavefront's, and every
+    // wavefront is done reading the buffer the next slab goes into (a plain
+    // barrier: a fence would also wait for stores that need not finish)
+    wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (s + 1 < nk) issue(s + 1);
+    const bf16* sa = (const bf16*)(lds + (s % kLdsStages) * 2 * kLdsSlab);
+    const bf16* sb = (const bf16*)(lds + (s % kLdsStages) * 2 * kLdsSlab + kLdsSlab);
+#pragma unroll
+    for (int ks = 0; ks < kLdsBK / 16; ++ks) {
+      const int ch = ks * 2 + (lane >> 5);
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) {
+        const int r = wm + mi * 32 + (lane & 31);
+        a[mi] = *reinterpret_cast<const bf16x8*>(sa + lds_pos(r, ch) * 8);
       }
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        const int r = wn + ni * 32 + (lane & 31);
+        b[ni] = *reinterpret_cast<const bf16x8*>(sb + lds_pos(r, ch) * 8);
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) epilogue<EPI>(g, acc[mi][ni], m0 + wm + mi * 32, n0 + wn + ni * 32, lane);
 }
 
 // Normalised BF16 input rows: (x - mean) / std, zero padding to ldx.
