@@ -214,7 +214,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 // workgroup, 64 KB, so two workgroups per compute unit share its LDS).
 // These products are bound by how fast operand tiles reach the compute
 // units from L2 (about 14 B per clock per CU measured), so the tiles are
-// 128 x 128 (half the traffic of 64 x 64 per flop) and each XCD takes a
+// 128 x 128 or 128 x 64 (half or three quarters of the traffic of 64 x 64
+// per flop) and each XCD takes a
 // contiguous eighth of the tiles (a few row tiles by all column tiles), so
 // that its operands stay in its own L2.  Rows and K chunks outside the
 // matrices read a 16-byte block of zeros.  K must be a multiple of 8.
@@ -232,51 +233,55 @@ __device__ __forceinline__ void wait_vmcnt() {
 
 constexpr int kLdsBM = 128, kLdsBK = 64, kLdsStages = 2;
 constexpr int kLdsChunks = kLdsBK / 8;                   // 16-byte chunks per slab row
-constexpr int kLdsSlab = kLdsBM * kLdsChunks * 16;       // bytes of one operand's slab
-constexpr int kLdsBytes = kLdsStages * 2 * kLdsSlab;     // 64 KB per workgroup
+// bytes of one stage (A slab of 128 rows, B slab of BN rows) and of a workgroup's LDS
+template <int BN> constexpr int lds_stage_bytes() { return (kLdsBM + BN) * kLdsChunks * 16; }
+template <int BN> constexpr int lds_bytes() { return kLdsStages * lds_stage_bytes<BN>(); }
 
 // LDS position (16-byte units) of chunk c of slab row r: chunks permuted by
 // r & 7 within the row, so the fragment reads of 8 consecutive rows at one
 // chunk fall on distinct bank groups
 __device__ __forceinline__ int lds_pos(int r, int c) { return r * kLdsChunks + (c ^ (r & 7)); }
 
-__host__ __device__ inline int lds_tiles(int M, int N) { return ((N + kLdsBM - 1) / kLdsBM) * ((M + kLdsBM - 1) / kLdsBM); }
+__host__ __device__ inline int lds_tiles(int M, int N, int BN) { return ((N + BN - 1) / BN) * ((M + kLdsBM - 1) / kLdsBM); }
 
-template <int EPI>
+// Tile 128 x BN (BN = 128 or 64), four wavefronts of 64 x BN/2.
+template <int EPI, int BN>
 __global__ void __launch_bounds__(256) k_gemm_lds(GemmArgs g) {
+  constexpr int NB = BN / 64;                 // 32-column MFMA blocks per wavefront
+  constexpr int SA = kLdsBM * kLdsChunks * 16, SB = BN * kLdsChunks * 16;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // workgroup w runs on XCD w % 8; XCD x takes tiles [x per, (x + 1) per)
-  const int gx = (g.N + kLdsBM - 1) / kLdsBM, T = lds_tiles(g.M, g.N), per = (T + 7) / 8;
+  const int gx = (g.N + BN - 1) / BN, T = lds_tiles(g.M, g.N, BN), per = (T + 7) / 8;
   const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (t >= T) return;
-  const int m0 = (t / gx) * kLdsBM, n0 = (t % gx) * kLdsBM;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int m0 = (t / gx) * kLdsBM, n0 = (t % gx) * BN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * (BN / 2);
   const int nk = (g.K + kLdsBK - 1) / kLdsBK;
-  // one stage: each wavefront copies 4 blocks of 8 slab rows (1 KB) of A and
-  // 4 of B; lane l of a block fills LDS unit l, i.e. row l / 8, the chunk
-  // that lds_pos puts there
+  // one stage: 1 KB blocks of 8 slab rows, A's 16 and B's BN / 8 spread over
+  // the wavefronts; lane l of a block fills LDS unit l, i.e. row l / 8, the
+  // chunk that lds_pos puts there
+  auto copy = [&](const bf16* P, long ld, int rows, int row0, char* dst, int blk, int k0) {
+    const int u = blk * 64 + lane;
+    const int r = u / kLdsChunks, c = (u % kLdsChunks) ^ (r & 7);
+    const int kk = k0 + c * 8;
+    const bf16* p = (row0 + r < rows && kk < g.K) ? P + (long)(row0 + r) * ld + kk : (const bf16*)g_zero16;
+    __builtin_amdgcn_global_load_lds((glb_void_t*)p, (lds_void_t*)(dst + blk * 1024), 16, 0, 0);
+  };
   auto issue = [&](int s) {
-    char* sa = lds + (s % kLdsStages) * 2 * kLdsSlab;
-    char* sb = sa + kLdsSlab;
+    char* sa = lds + (s % kLdsStages) * (SA + SB);
+    char* sb = sa + SA;
     const int k0 = s * kLdsBK;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int blk = wave * 4 + i;
-      const int u = blk * 64 + lane;
-      const int r = u / kLdsChunks, c = (u % kLdsChunks) ^ (r & 7);
-      const int kk = k0 + c * 8;
-      const bf16* pa = (m0 + r < g.M && kk < g.K) ? g.A + (long)(m0 + r) * g.lda + kk : (const bf16*)g_zero16;
-      const bf16* pb = (n0 + r < g.N && kk < g.K) ? g.B + (long)(n0 + r) * g.ldb + kk : (const bf16*)g_zero16;
-      __builtin_amdgcn_global_load_lds((glb_void_t*)pa, (lds_void_t*)(sa + blk * 1024), 16, 0, 0);
-      __builtin_amdgcn_global_load_lds((glb_void_t*)pb, (lds_void_t*)(sb + blk * 1024), 16, 0, 0);
-    }
+    for (int i = 0; i < 4; ++i) copy(g.A, g.lda, g.M, m0, sa, wave * 4 + i, k0);
+#pragma unroll
+    for (int i = 0; i < BN / 32; ++i) copy(g.B, g.ldb, g.N, n0, sb, wave * (BN / 32) + i, k0);
   };
-  f32x16 acc[2][2];
+  f32x16 acc[2][NB];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
   issue(0);
@@ -288,33 +293,33 @@ __global__ void __launch_bounds__(256) k_gemm_lds(GemmArgs g) {
     wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
     if (s + 1 < nk) issue(s + 1);
-    const bf16* sa = (const bf16*)(lds + (s % kLdsStages) * 2 * kLdsSlab);
-    const bf16* sb = (const bf16*)(lds + (s % kLdsStages) * 2 * kLdsSlab + kLdsSlab);
+    const bf16* sa = (const bf16*)(lds + (s % kLdsStages) * (SA + SB));
+    const bf16* sb = (const bf16*)(lds + (s % kLdsStages) * (SA + SB) + SA);
 #pragma unroll
     for (int ks = 0; ks < kLdsBK / 16; ++ks) {
       const int ch = ks * 2 + (lane >> 5);
-      bf16x8 a[2], b[2];
+      bf16x8 a[2], b[NB];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) {
         const int r = wm + mi * 32 + (lane & 31);
         a[mi] = *reinterpret_cast<const bf16x8*>(sa + lds_pos(r, ch) * 8);
       }
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni) {
+      for (int ni = 0; ni < NB; ++ni) {
         const int r = wn + ni * 32 + (lane & 31);
         b[ni] = *reinterpret_cast<const bf16x8*>(sb + lds_pos(r, ch) * 8);
       }
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
+        for (int ni = 0; ni < NB; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
   }
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) epilogue<EPI>(g, acc[mi][ni], m0 + wm + mi * 32, n0 + wn + ni * 32, lane);
+    for (int ni = 0; ni < NB; ++ni) epilogue<EPI>(g, acc[mi][ni], m0 + wm + mi * 32, n0 + wn + ni * 32, lane);
 }
 
 // Normalised BF16 input rows: (x - mean) / std, zero padding to ldx.

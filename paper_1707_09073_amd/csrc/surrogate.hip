@@ -143,15 +143,20 @@ void gemm(sg_ctx* c, const GemmArgs& g) {
     c->bad_gemm = true;
     return;
   }
-  // both operands K-contiguous, K a multiple of 8, and at least two 128 x 128
-  // tiles per compute unit: direct-to-LDS slabs (measured at batch 4096: the
-  // 1024 -> 3600 output layer 109.8 -> 59.6 µs; with one tile per compute
-  // unit the epilogue and the copy latency stay exposed, and the hidden
-  // layers and dX run faster as 64 x 64 tiles, four workgroups per unit)
+  // both operands K-contiguous and K a multiple of 8: direct-to-LDS slabs in
+  // 128 x 128 tiles, or 128 x 64 tiles, when either gives at least two tiles
+  // per compute unit (with one, the epilogue and the copy latency stay
+  // exposed; measured at batch 4096: the 1024 -> 3600 output layer 109.8 ->
+  // 59.6 µs in 128 x 128 tiles)
   if (!TA && TB && g.K % 8 == 0) {
-    const int T = lds_tiles(g.M, g.N);
-    if (T >= 512) {
-      k_gemm_lds<EPI><<<((T + 7) / 8) * 8, 256, kLdsBytes, c->st>>>(g);
+    if (lds_tiles(g.M, g.N, 128) >= 512) {
+      const int T = lds_tiles(g.M, g.N, 128);
+      k_gemm_lds<EPI, 128><<<((T + 7) / 8) * 8, 256, lds_bytes<128>(), c->st>>>(g);
+      return;
+    }
+    if (lds_tiles(g.M, g.N, 64) >= 512) {
+      const int T = lds_tiles(g.M, g.N, 64);
+      k_gemm_lds<EPI, 64><<<((T + 7) / 8) * 8, 256, lds_bytes<64>(), c->st>>>(g);
       return;
     }
   }
@@ -325,13 +330,13 @@ int sg_init(sg_ctx** out, const sg_config* cfg, void* d_ws, size_t bytes, void* 
     unsigned char* scr = nullptr;  // the allocation-free predictor's scratch on this device
     SGCHK(c, static_scratch_of(c->dev, &scr));
   }
-  // the direct-to-LDS products take 64 KB of dynamic LDS per workgroup
-  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kLdsBytes));
-  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS_GELU>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kLdsBytes));
-  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_GELU_GRAD>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kLdsBytes));
+  // the direct-to-LDS products take up to 64 KB of dynamic LDS per workgroup
+  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS, 128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               lds_bytes<128>()));
+  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS_GELU, 128>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<128>()));
+  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_GELU_GRAD, 128>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<128>()));
   SGCHK(c, hipMemsetAsync(c->ws, 0, s.total, c->st));
   for (int e = 0; e < cfg->ensemble; ++e)
     for (int l = 0; l < s.L; ++l) {
