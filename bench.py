@@ -53,7 +53,7 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # 2.000 + WRITE_SIZE x 1.000, scales from a 1 GiB device copy).
 KERNELS = {0: "k_flight_refill<float,true>", 1: "k_flight<float,true>", 2: "k_flight_persist<float,true>"}
 KERNEL_COUNTERS = {
-    0: {"sources_digest": "fc22754904390b71", "valu_lane_ops_per_segment": 173.2, "hbm_bytes_per_segment": 8.76,
+    0: {"sources_digest": "cefecf43f470509e", "valu_lane_ops_per_segment": 173.2, "hbm_bytes_per_segment": 8.76,
         "active_lane_fraction": 0.46, "profile": "profiles/k_flight_refill_device1e7_counters.md"},
 }
 

@@ -143,12 +143,15 @@ void gemm(sg_ctx* c, const GemmArgs& g) {
     c->bad_gemm = true;
     return;
   }
-  // both operands K-contiguous and K a multiple of 8: direct-to-LDS slabs in
-  // 128 x 128 tiles, or 128 x 64 tiles, when either gives at least two tiles
-  // per compute unit (with one, the epilogue and the copy latency stay
-  // exposed; measured at batch 4096: the 1024 -> 3600 output layer 109.8 ->
-  // 59.6 µs in 128 x 128 tiles)
-  if (!TA && TB && g.K % 8 == 0) {
+  // forward products (both operands K-contiguous, K a multiple of 8):
+  // direct-to-LDS slabs in 128 x 128 tiles, or 128 x 64 tiles, when either
+  // gives at least two tiles per compute unit (with one, the epilogue and the
+  // copy latency stay exposed).  Measured at batch 4096: the 1024 -> 3600
+  // output layer 109.8 -> 61 µs in 128 x 128 tiles, the four GELU layers
+  // (input and hidden) 28.6 µs on average in 128 x 64, against 29.9 for the
+  // hidden ones alone before; dX (the GELU-derivative epilogue reads the
+  // pre-activations) ran 47 µs against 43 in 64 x 64 tiles and stays there.
+  if (!TA && TB && EPI != EPI_GELU_GRAD && g.K % 8 == 0) {
     if (lds_tiles(g.M, g.N, 128) >= 512) {
       const int T = lds_tiles(g.M, g.N, 128);
       k_gemm_lds<EPI, 128><<<((T + 7) / 8) * 8, 256, lds_bytes<128>(), c->st>>>(g);
@@ -335,8 +338,7 @@ int sg_init(sg_ctx** out, const sg_config* cfg, void* d_ws, size_t bytes, void* 
                                lds_bytes<128>()));
   SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS_GELU, 128>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<128>()));
-  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_GELU_GRAD, 128>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<128>()));
+
   SGCHK(c, hipMemsetAsync(c->ws, 0, s.total, c->st));
   for (int e = 0; e < cfg->ensemble; ++e)
     for (int l = 0; l < s.L; ++l) {
