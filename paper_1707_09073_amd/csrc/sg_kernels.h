@@ -213,9 +213,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 // in flight while the matrix cores work on the current one (two stages per
 // workgroup, 64 KB, so two workgroups per compute unit share its LDS).
 // These products are bound by how fast operand tiles reach the compute
-// units from L2 (about 14 B per clock per CU measured), so the tiles are
-// 128 x 128 or 128 x 64 (half or three quarters of the traffic of 64 x 64
-// per flop) and each XCD takes a
+// units from L2 (about 14 B per clock per CU measured), so the tiles are as
+// large as the product allows while every compute unit still gets work
+// (256 x 256, 128 x 128 or 128 x 64), and each XCD takes a
 // contiguous eighth of the tiles (a few row tiles by all column tiles), so
 // that its operands stay in its own L2.  Rows and K chunks outside the
 // matrices read a 16-byte block of zeros.  K must be a multiple of 8.
@@ -231,36 +231,42 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
-constexpr int kLdsBM = 128, kLdsBK = 64, kLdsStages = 2;
+constexpr int kLdsBK = 64, kLdsStages = 2;
 constexpr int kLdsChunks = kLdsBK / 8;                   // 16-byte chunks per slab row
-// bytes of one stage (A slab of 128 rows, B slab of BN rows) and of a workgroup's LDS
-template <int BN> constexpr int lds_stage_bytes() { return (kLdsBM + BN) * kLdsChunks * 16; }
-template <int BN> constexpr int lds_bytes() { return kLdsStages * lds_stage_bytes<BN>(); }
+// bytes of one stage (an A slab of BM rows and a B slab of BN rows) and of a
+// workgroup's LDS
+template <int BM, int BN> constexpr int lds_bytes() { return kLdsStages * (BM + BN) * kLdsChunks * 16; }
 
 // LDS position (16-byte units) of chunk c of slab row r: chunks permuted by
 // r & 7 within the row, so the fragment reads of 8 consecutive rows at one
 // chunk fall on distinct bank groups
 __device__ __forceinline__ int lds_pos(int r, int c) { return r * kLdsChunks + (c ^ (r & 7)); }
 
-__host__ __device__ inline int lds_tiles(int M, int N, int BN) { return ((N + BN - 1) / BN) * ((M + kLdsBM - 1) / kLdsBM); }
+__host__ __device__ inline int lds_tiles(int M, int N, int BM, int BN) {
+  return ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
+}
 
-// Tile 128 x BN (BN = 128 or 64), four wavefronts of 64 x BN/2.
-template <int EPI, int BN>
-__global__ void __launch_bounds__(256) k_gemm_lds(GemmArgs g) {
-  constexpr int NB = BN / 64;                 // 32-column MFMA blocks per wavefront
-  constexpr int SA = kLdsBM * kLdsChunks * 16, SB = BN * kLdsChunks * 16;
+// Tile BM x BN with W wavefronts: 2 rows of W / 2 wavefronts, each
+// BM / 2 x 2 BN / W, in 32 x 32 MFMA blocks.
+template <int EPI, int BM, int BN, int W>
+__global__ void __launch_bounds__(64 * W) k_gemm_lds(GemmArgs g) {
+  constexpr int WM = BM / 2, WN = 2 * BN / W;      // a wavefront's share of the tile
+  constexpr int MB = WM / 32, NB = WN / 32;        // its 32 x 32 MFMA blocks
+  constexpr int SA = BM * kLdsChunks * 16, SB = BN * kLdsChunks * 16;
+  constexpr int BA = BM / 8 / W, BB = BN / 8 / W;  // 1 KB blocks per wavefront and stage
+  static_assert(BA * W * 8 == BM && BB * W * 8 == BN, "slab rows must split evenly over the wavefronts");
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // workgroup w runs on XCD w % 8; XCD x takes tiles [x per, (x + 1) per)
-  const int gx = (g.N + BN - 1) / BN, T = lds_tiles(g.M, g.N, BN), per = (T + 7) / 8;
+  const int gx = (g.N + BN - 1) / BN, T = lds_tiles(g.M, g.N, BM, BN), per = (T + 7) / 8;
   const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (t >= T) return;
-  const int m0 = (t / gx) * kLdsBM, n0 = (t % gx) * BN;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * (BN / 2);
+  const int m0 = (t / gx) * BM, n0 = (t % gx) * BN;
+  const int wm = (wave / (W / 2)) * WM, wn = (wave % (W / 2)) * WN;
   const int nk = (g.K + kLdsBK - 1) / kLdsBK;
-  // one stage: 1 KB blocks of 8 slab rows, A's 16 and B's BN / 8 spread over
-  // the wavefronts; lane l of a block fills LDS unit l, i.e. row l / 8, the
-  // chunk that lds_pos puts there
+  // one stage: 1 KB blocks of 8 slab rows spread over the wavefronts; lane l
+  // of a block fills LDS unit l, i.e. row l / 8, the chunk that lds_pos puts
+  // there
   auto copy = [&](const bf16* P, long ld, int rows, int row0, char* dst, int blk, int k0) {
     const int u = blk * 64 + lane;
     const int r = u / kLdsChunks, c = (u % kLdsChunks) ^ (r & 7);
@@ -273,13 +279,13 @@ __global__ void __launch_bounds__(256) k_gemm_lds(GemmArgs g) {
     char* sb = sa + SA;
     const int k0 = s * kLdsBK;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) copy(g.A, g.lda, g.M, m0, sa, wave * 4 + i, k0);
+    for (int i = 0; i < BA; ++i) copy(g.A, g.lda, g.M, m0, sa, wave * BA + i, k0);
 #pragma unroll
-    for (int i = 0; i < BN / 32; ++i) copy(g.B, g.ldb, g.N, n0, sb, wave * (BN / 32) + i, k0);
+    for (int i = 0; i < BB; ++i) copy(g.B, g.ldb, g.N, n0, sb, wave * BB + i, k0);
   };
-  f32x16 acc[2][NB];
+  f32x16 acc[MB][NB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -298,9 +304,9 @@ __global__ void __launch_bounds__(256) k_gemm_lds(GemmArgs g) {
 #pragma unroll
     for (int ks = 0; ks < kLdsBK / 16; ++ks) {
       const int ch = ks * 2 + (lane >> 5);
-      bf16x8 a[2], b[NB];
+      bf16x8 a[MB], b[NB];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) {
+      for (int mi = 0; mi < MB; ++mi) {
         const int r = wm + mi * 32 + (lane & 31);
         a[mi] = *reinterpret_cast<const bf16x8*>(sa + lds_pos(r, ch) * 8);
       }
@@ -310,14 +316,14 @@ __global__ void __launch_bounds__(256) k_gemm_lds(GemmArgs g) {
         b[ni] = *reinterpret_cast<const bf16x8*>(sb + lds_pos(r, ch) * 8);
       }
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
         for (int ni = 0; ni < NB; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
     for (int ni = 0; ni < NB; ++ni) epilogue<EPI>(g, acc[mi][ni], m0 + wm + mi * 32, n0 + wn + ni * 32, lane);
 }

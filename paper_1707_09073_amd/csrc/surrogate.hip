@@ -152,14 +152,19 @@ void gemm(sg_ctx* c, const GemmArgs& g) {
   // hidden ones alone before; dX (the GELU-derivative epilogue reads the
   // pre-activations) ran 47 µs against 43 in 64 x 64 tiles and stays there.
   if (!TA && TB && EPI != EPI_GELU_GRAD && g.K % 8 == 0) {
-    if (lds_tiles(g.M, g.N, 128) >= 512) {
-      const int T = lds_tiles(g.M, g.N, 128);
-      k_gemm_lds<EPI, 128><<<((T + 7) / 8) * 8, 256, lds_bytes<128>(), c->st>>>(g);
+    if (lds_tiles(g.M, g.N, 256, 256) >= 224) {
+      const int T = lds_tiles(g.M, g.N, 256, 256);
+      k_gemm_lds<EPI, 256, 256, 8><<<((T + 7) / 8) * 8, 512, lds_bytes<256, 256>(), c->st>>>(g);
       return;
     }
-    if (lds_tiles(g.M, g.N, 64) >= 512) {
-      const int T = lds_tiles(g.M, g.N, 64);
-      k_gemm_lds<EPI, 64><<<((T + 7) / 8) * 8, 256, lds_bytes<64>(), c->st>>>(g);
+    if (lds_tiles(g.M, g.N, 128, 128) >= 512) {
+      const int T = lds_tiles(g.M, g.N, 128, 128);
+      k_gemm_lds<EPI, 128, 128, 4><<<((T + 7) / 8) * 8, 256, lds_bytes<128, 128>(), c->st>>>(g);
+      return;
+    }
+    if (lds_tiles(g.M, g.N, 128, 64) >= 512) {
+      const int T = lds_tiles(g.M, g.N, 128, 64);
+      k_gemm_lds<EPI, 128, 64, 4><<<((T + 7) / 8) * 8, 256, lds_bytes<128, 64>(), c->st>>>(g);
       return;
     }
   }
@@ -333,12 +338,15 @@ int sg_init(sg_ctx** out, const sg_config* cfg, void* d_ws, size_t bytes, void* 
     unsigned char* scr = nullptr;  // the allocation-free predictor's scratch on this device
     SGCHK(c, static_scratch_of(c->dev, &scr));
   }
-  // the direct-to-LDS products take up to 64 KB of dynamic LDS per workgroup
-  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS, 128>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               lds_bytes<128>()));
-  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS_GELU, 128>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<128>()));
-
+  // the direct-to-LDS products take up to 128 KB of dynamic LDS per workgroup
+  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS, 256, 256, 8>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<256, 256>()));
+  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS_GELU, 256, 256, 8>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<256, 256>()));
+  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS, 128, 128, 4>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<128, 128>()));
+  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS_GELU, 128, 128, 4>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<128, 128>()));
   SGCHK(c, hipMemsetAsync(c->ws, 0, s.total, c->st));
   for (int e = 0; e < cfg->ensemble; ++e)
     for (int l = 0; l < s.L; ++l) {
