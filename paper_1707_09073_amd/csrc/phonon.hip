@@ -233,12 +233,6 @@ __global__ void k_ph_setup(const double* __restrict__ q, int ncell, const double
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += gridDim.x * blockDim.x) t_cell[i] = 0.0;
 }
 
-// One packet per lane at a time: when a lane's packet ends it takes the next
-// packet index from the launch's counter (64 at a time per wavefront), so
-// lanes do not idle while the longest packet of their wavefront runs.  The
-// bin tables and re-emission weights sit in LDS; each workgroup keeps its
-// packet times per subcell in LDS and adds them to the global sums at the
-// end (FP64 atomic adds: the order of the sums varies at rounding level).
 template <typename T>
 __device__ __forceinline__ T get3(const T (&v)[3], int i) {
   return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]);
@@ -250,8 +244,24 @@ __device__ __forceinline__ void set3(T (&v)[3], int i, T x) {
   v[2] = i == 2 ? x : v[2];
 }
 
+// One packet per lane.  A lane moves its packet straight to the next subcell
+// boundary, scattering point or face (a few operations: the common step);
+// what costs more, a scattering (a new bin, direction and free path), a
+// diffuse reflection (a cosine-law direction) or a new packet (claimed from
+// the launch's counter, 256 indices per wavefront at a time, then emitted),
+// the lane only marks as pending.  The wavefront runs those paths together,
+// once pending and free lanes make up half of its active lanes or no lane can
+// move, so that the generator, the logarithm, sine and cosine and the binary
+// searches run with most lanes busy instead of for the few that need them at
+// each step.  Each packet still goes through the same operations in the same
+// order with the same random numbers; only the interleaving of packets
+// changes.  The bin tables and re-emission weights sit in LDS; each
+// workgroup keeps its packet times per subcell in LDS and adds them to the
+// global sums at the end (FP64 atomic adds: the order of the sums varies at
+// rounding level).
 constexpr int kPhBlock = 256;
 constexpr int kPhChunk = 256;  // packet indices a wavefront claims at a time
+enum { PH_MOVE = 0, PH_EMIT = 1, PH_SCATTER = 2, PH_WALL = 3 };
 __global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
   // separate multiplies and adds, as the FP64 reference rounds them: the
   // packet's path (and which boundary or face it meets first) then follows
@@ -277,11 +287,13 @@ __global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
   const int ny = a.n[1], nz = a.n[2];
   const int faces = a.face[0] | a.face[1] << 2 | a.face[2] << 4 | a.face[3] << 6 | a.face[4] << 8 | a.face[5] << 10;
   unsigned long long n_seg = 0, n_scat = 0, n_spec = 0, n_diff = 0, n_drop = 0;
-  bool has = false;
+  bool has = false;                  // the lane holds a packet (moving or pending)
+  int pend = PH_MOVE;                // what the packet waits for
   long long pk = 0;
   double r[3] = {0, 0, 0}, dir[3] = {0, 0, 1}, left = 0.0;
   double sg = 1.0;  // the packet's sign: negative from a subcell that is a net sink
-  int ic[3] = {0, 0, 0}, b = 0;
+  int ic[3] = {0, 0, 0}, b = 0, fax = 0;
+  bool fup = false;                  // the face a pending diffuse reflection is at
   uint32_t ev = 0, hits = 0;
   long long events = 0;
   // wavefront-uniform chunk [cpos, cend) of packet indices claimed from the
@@ -290,42 +302,75 @@ __global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
   long long cpos = 0, cend = 0;
   bool exhausted = false;
   for (;;) {
-    // refill: lanes without a packet take the next indices of the chunk
-    unsigned long long want = __ballot(!has && !exhausted);
-    while (want) {
-      if (cpos >= cend) {
-        const int first = __ffsll((long long)want) - 1;
-        unsigned long long base = 0;
-        if (lane == first) base = atomicAdd(a.next, (unsigned long long)kPhChunk);
-        base = __shfl(base, first);
-        if ((long long)base >= a.n_packets) { exhausted = true; break; }
-        cpos = (long long)base;
-        cend = cpos + kPhChunk < a.n_packets ? cpos + kPhChunk : a.n_packets;
+    const bool free_lane = !has && !exhausted;
+    const int n_wait = __popcll(__ballot(free_lane || (has && pend != PH_MOVE)));
+    const int n_mov = __popcll(__ballot(has && pend == PH_MOVE));
+    if (n_wait + n_mov == 0) break;
+    if (n_mov == 0 || 2 * n_wait >= n_wait + n_mov) {
+      // ---- the expensive paths, for every lane that waits ----
+      // free lanes take the next indices of the wavefront's chunk
+      unsigned long long want = __ballot(!has && !exhausted);
+      while (want) {
+        if (cpos >= cend) {
+          const int first = __ffsll((long long)want) - 1;
+          unsigned long long base = 0;
+          if (lane == first) base = atomicAdd(a.next, (unsigned long long)kPhChunk);
+          base = __shfl(base, first);
+          if ((long long)base >= a.n_packets) {
+            exhausted = true;
+            break;
+          }
+          cpos = (long long)base;
+          cend = cpos + kPhChunk < a.n_packets ? cpos + kPhChunk : a.n_packets;
+        }
+        const long long take = min((long long)__popcll(want), cend - cpos);
+        const long long rank = __popcll(want & ((1ull << lane) - 1ull));
+        if (((want >> lane) & 1ull) && rank < take) {
+          pk = cpos + rank;
+          has = true;
+          pend = PH_EMIT;
+        }
+        cpos += take;
+        want = __ballot(!has && !exhausted);
       }
-      const long long take = min((long long)__popcll(want), cend - cpos);
-      const long long rank = __popcll(want & ((1ull << lane) - 1ull));
-      if (((want >> lane) & 1ull) && rank < take) {
-        pk = cpos + rank;
-        uint4 w = philox((uint32_t)pk, 0u, 0u, a.tag, a.k0, a.k1);
+      // emission, first draw: the subcell (by |q|) and the point in it
+      if (has && pend == PH_EMIT) {
+        const uint4 w = philox((uint32_t)pk, 0u, 0u, a.tag, a.k0, a.k1);
         const int cell = draw_cum(a.cum_cell, a.ncell, uo(w.x));
         sg = a.q[cell] < 0.0 ? -1.0 : 1.0;
         ic[0] = cell / (ny * nz); ic[1] = (cell / nz) % ny; ic[2] = cell % nz;
         r[0] = (ic[0] + uo(w.y)) * a.d[0];
         r[1] = (ic[1] + uo(w.z)) * a.d[1];
         r[2] = (ic[2] + uo(w.w)) * a.d[2];
-        w = philox((uint32_t)pk, 0u, 1u, a.tag, a.k0, a.k1);
-        b = draw_cum(s_cum, a.nb, uo(w.x));
-        iso(uo(w.y), uo(w.z), dir);
-        left = -log(uo(w.w)) * s_tau[b] * s_v[b];
         ev = 0; hits = 0; events = 0;
-        has = true;
       }
-      cpos += take;
-      want = __ballot(!has && !exhausted);
+      if (has && pend != PH_MOVE) {
+        // one generator call for every waiting packet: the emission's second
+        // draw (packet, 0, 1), the j-th scattering (packet, j, 0), the h-th
+        // diffuse reflection after it (packet, j, 1 + h)
+        const uint32_t sub = pend == PH_WALL ? 1u + hits : (pend == PH_EMIT ? 1u : 0u);
+        const uint4 w = philox((uint32_t)pk, ev, sub, a.tag, a.k0, a.k1);
+        if (pend == PH_WALL) {
+          const double ct = sqrt(uo(w.x)), st = sqrt(fmax(0.0, 1.0 - ct * ct)), ph = 2.0 * kPi * uo(w.y);
+          // cosine-law direction about the inward normal of axis fax; the two
+          // tangential components on axes fax + 1 and fax + 2 (cyclic)
+          const double dn = fup ? -ct : ct, t1 = st * cos(ph), t2 = st * sin(ph);
+          dir[0] = fax == 0 ? dn : (fax == 1 ? t2 : t1);
+          dir[1] = fax == 1 ? dn : (fax == 2 ? t2 : t1);
+          dir[2] = fax == 2 ? dn : (fax == 0 ? t2 : t1);
+        } else {
+          // a new bin (by C_b / tau_b), an isotropic direction, a free path
+          b = draw_cum(s_cum, a.nb, uo(w.x));
+          iso(uo(w.y), uo(w.z), dir);
+          left = -log(uo(w.w)) * s_tau[b] * s_v[b];
+        }
+        pend = PH_MOVE;
+      }
+      continue;
     }
-    if (!__any(has)) break;
-    if (!has) continue;
-    // one step: to the nearest cell boundary, or to the scattering point
+    if (!has || pend != PH_MOVE) continue;
+    // ---- the common step: to the nearest subcell boundary, or to the
+    // scattering point ----
     double tmin = left;
     int ax = -1;
 #pragma unroll
@@ -355,10 +400,7 @@ __global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
       ++ev;
       ++n_scat;
       hits = 0;
-      const uint4 w = philox((uint32_t)pk, ev, 0u, a.tag, a.k0, a.k1);
-      b = draw_cum(s_cum, a.nb, uo(w.x));
-      iso(uo(w.y), uo(w.z), dir);
-      left = -log(uo(w.w)) * s_tau[b] * s_v[b];
+      pend = PH_SCATTER;
       continue;
     }
     // the boundary of axis ax (per lane): selects instead of indexing, so
@@ -389,14 +431,9 @@ __global__ void __launch_bounds__(kPhBlock) k_ph_packets(PhArgs a) {
     } else {
       ++n_diff;
       ++hits;
-      const uint4 w = philox((uint32_t)pk, ev, 1u + hits, a.tag, a.k0, a.k1);
-      const double ct = sqrt(uo(w.x)), st = sqrt(fmax(0.0, 1.0 - ct * ct)), ph = 2.0 * kPi * uo(w.y);
-      // cosine-law direction about the inward normal of axis ax; the two
-      // tangential components on axes ax + 1 and ax + 2 (cyclic)
-      const double dn = up ? -ct : ct, t1 = st * cos(ph), t2 = st * sin(ph);
-      dir[0] = ax == 0 ? dn : (ax == 1 ? t2 : t1);
-      dir[1] = ax == 1 ? dn : (ax == 2 ? t2 : t1);
-      dir[2] = ax == 2 ? dn : (ax == 0 ? t2 : t1);
+      fax = ax;
+      fup = up;
+      pend = PH_WALL;
     }
   }
   __syncthreads();
