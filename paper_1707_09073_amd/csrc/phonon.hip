@@ -210,25 +210,50 @@ struct PhArgs {
   unsigned long long* next;    // packet counter of the launch
 };
 
-// Set-up of a run: cumulative |source| and re-emission weights (one thread
-// each, in order), the packet counter and the tallies cleared.
-__global__ void k_ph_setup(const double* __restrict__ q, int ncell, const double* __restrict__ tab, int nb,
-                           double* cum_cell, double* cum_emit, double* t_cell, unsigned long long* counts,
-                           unsigned long long* next, double* sums) {
+// Set-up of a run: cumulative |source| and re-emission weights, the packet
+// counter and the tallies cleared.  The running sums keep the reference's
+// order (one thread, element by element: the draws compare against them bit
+// for bit); workgroup 0 first stages each sequence's terms in LDS, so that
+// the serial loop waits on LDS rather than on global memory.
+constexpr int kPhSetupBlock = 256;
+__global__ void __launch_bounds__(kPhSetupBlock) k_ph_setup(const double* __restrict__ q, int ncell,
+                                                            const double* __restrict__ tab, int nb, double* cum_cell,
+                                                            double* cum_emit, double* t_cell,
+                                                            unsigned long long* counts, unsigned long long* next,
+                                                            double* sums) {
 #pragma clang fp contract(off)
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double a = 0.0;
-    for (int i = 0; i < ncell; ++i) { a += fabs(q[i]); cum_cell[i] = a; }
-    sums[0] = a;  // total |power|, W: each packet carries sums[0] / N
-    double e = 0.0, cv = 0.0;
-    for (int b = 0; b < nb; ++b) {
-      e += tab[2 * nb + b] * tab[3 * nb + b];
-      cum_emit[b] = e;
-      cv += tab[2 * nb + b];
+  __shared__ double buf[4096];  // ncell and nb are at most 4096
+  if (blockIdx.x == 0) {
+    // |q| per subcell, summed in subcell order
+    for (int i = threadIdx.x; i < ncell; i += blockDim.x) buf[i] = fabs(q[i]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < ncell; ++i) { a += buf[i]; cum_cell[i] = a; }
+      sums[0] = a;  // total |power|, W: each packet carries sums[0] / N
     }
-    sums[1] = cv;  // volumetric heat capacity, J/(m^3 K)
-    for (int i = 0; i < CT_N; ++i) counts[i] = 0ull;
-    *next = 0ull;
+    __syncthreads();
+    // re-emission weights C_b / tau_b, summed in bin order
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) buf[b] = tab[2 * nb + b] * tab[3 * nb + b];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double e = 0.0;
+#pragma unroll 8
+      for (int b = 0; b < nb; ++b) { e += buf[b]; cum_emit[b] = e; }
+    }
+    __syncthreads();
+    // the heat capacity, summed in bin order
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) buf[b] = tab[2 * nb + b];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double cv = 0.0;
+#pragma unroll 8
+      for (int b = 0; b < nb; ++b) cv += buf[b];
+      sums[1] = cv;  // volumetric heat capacity, J/(m^3 K)
+      for (int i = 0; i < CT_N; ++i) counts[i] = 0ull;
+      *next = 0ull;
+    }
   }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += gridDim.x * blockDim.x) t_cell[i] = 0.0;
 }
@@ -587,8 +612,9 @@ int ph_mc_run(const ph_mc_config* c, const double* d_tables, const double* d_q_c
   a.counts = (unsigned long long*)(ws + L.counts);
   a.next = (unsigned long long*)(ws + L.next);
   double* sums = (double*)(ws + L.sums);
-  k_ph_setup<<<(nc + 255) / 256, 256, 0, st>>>(d_q_cell, nc, d_tables, nb, (double*)(ws + L.cum_cell),
-                                              (double*)(ws + L.cum_emit), d_t_cell, a.counts, a.next, sums);
+  k_ph_setup<<<(nc + kPhSetupBlock - 1) / kPhSetupBlock, kPhSetupBlock, 0, st>>>(
+      d_q_cell, nc, d_tables, nb, (double*)(ws + L.cum_cell), (double*)(ws + L.cum_emit), d_t_cell, a.counts, a.next,
+      sums);
   int dev = 0, ncu = 0, per = 0;
   const size_t lds = sizeof(double) * (3 * (size_t)nb + nc);
   if (lds > 160 * 1024) return PH_E_ARG;
