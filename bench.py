@@ -443,7 +443,7 @@ def main() -> int:
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "bytes_per_cell_iteration": FO_BYTES_PER_CELL_ITERATION,
-                         "note": "whole solves timed on the host clock (five launches per iteration and a host "
+                         "note": "whole solves timed on the host clock (three launches per iteration and a host "
                                  "check every 25 iterations included)"}}), flush=True)
         return 0
     if args.workload == "hybrid":

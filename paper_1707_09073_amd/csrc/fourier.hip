@@ -8,9 +8,15 @@
 // once per solve (each face by both of its cells, from the same operands in
 // the same order, so the operator is exactly symmetric); every iteration is
 // a matrix-vector product, two dot products and three vector updates, all
-// streaming HBM (about 90 B per cell and iteration).  Dot products go
-// through per-workgroup partial sums added in a fixed order, so a solve gives
-// the same bits for any launch.
+// streaming HBM, in three kernels.  Dot products go through per-workgroup
+// partial sums; the kernel that needs a dot product's value adds the
+// partials itself, in every workgroup, in one fixed order (so every
+// workgroup holds the same bits, and a solve gives the same bits for any
+// launch), after it has issued its own cells' loads.  The conductance arrays
+// and the search direction carry a zero halo of one x-plane at each end, so
+// the matrix-vector product needs no cell coordinates: a neighbour across
+// the grid's edge is either in the halo or, in y and z, a cell of the next
+// column or plane whose face conductance is zero.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -22,7 +28,8 @@
 namespace {
 
 constexpr int kFoBlock = 256;
-constexpr int kFoMaxBlocks = 4096;  // partial sums per dot product
+constexpr int kFoMaxBlocks = 1024;  // partial sums per dot product (each workgroup of a reading kernel adds them all)
+constexpr int kFoUnroll = 4;        // cells per thread loaded before a dot product's partials are added
 constexpr int kFoCheck = 25;        // iterations between convergence checks on the host
 
 struct FoGrid {
@@ -33,8 +40,10 @@ struct FoGrid {
   const double* ez;  // nz + 1
 };
 
-// Scalars of the iteration, on the device.
-enum { S_RZ = 0, S_PAP, S_ALPHA, S_BETA, S_RR, S_BB, S_N };
+// Scalars of the iteration, on the device: r.z of the current iteration in
+// slot S_RZ + (iteration & 1) (the direction kernel writes the next one into
+// the other slot while its workgroups read this one), r.r, b.b.
+enum { S_RZ = 0, S_RZ1, S_RR, S_BB, S_N };
 
 __device__ inline double face_g(double k1, double k2, double d1, double d2, double area, double extra) {
   if (!(k1 > 0.0) || !(k2 > 0.0)) return 0.0;
@@ -48,16 +57,40 @@ __device__ inline void cell_ijk(long long c, const FoGrid& g, int* i, int* j, in
   *i = (int)(t / g.ny);
 }
 
-// Block sum in a fixed tree order into part[blockIdx.x].
-__device__ inline void block_sum(double v, double* part) {
-  __shared__ double s[kFoBlock];
-  s[threadIdx.x] = v;
+// The cells [*c0, *c1) of this workgroup in the iteration kernels.  The grid
+// has a multiple of 8 workgroups, cpw cells each (a multiple of kFoBlock);
+// workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b % 8),
+// so workgroup b takes the (b / 8)-th span of XCD b % 8's eighth of the
+// cells: each XCD sweeps one contiguous block of x-planes, and the x-
+// neighbours a product reads lie in its own L2.
+__device__ inline void wg_span(long long nc, long long cpw, long long* c0, long long* c1) {
+  const long long per = gridDim.x / 8;
+  const long long l = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  *c0 = l * cpw < nc ? l * cpw : nc;
+  *c1 = *c0 + cpw < nc ? *c0 + cpw : nc;
+}
+
+// Workgroup total in a fixed order, returned to every thread: a butterfly
+// across each wavefront (every lane adds the same two operands at each step,
+// so every lane ends with the same bits), then the wavefront totals in
+// wavefront order.
+__device__ inline double wg_total(double v) {
+  __shared__ double s[kFoBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int o = kFoBlock / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+  double t = s[0];
+#pragma unroll
+  for (int w = 1; w < kFoBlock / 64; ++w) t += s[w];
+  __syncthreads();  // s may be written again by the next call
+  return t;
+}
+
+// Workgroup total into part[blockIdx.x].
+__device__ inline void block_sum(double v, double* part) {
+  const double t = wg_total(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // Conductances to the +x, +y, +z neighbours, the diagonal (with the held
@@ -66,11 +99,13 @@ __device__ inline void block_sum(double v, double* part) {
 __global__ void __launch_bounds__(kFoBlock) k_fo_setup(FoGrid g, const int* __restrict__ held, int k_if, double R_K,
                                                        const double* __restrict__ kap, const double* __restrict__ q,
                                                        double* gx, double* gy, double* gz, double* diag, double* x,
-                                                       double* r, double* p, double* part_rz, double* part_bb) {
+                                                       double* r, double* p, long long cpw, double* part_rz,
+                                                       double* part_bb) {
   double rz = 0.0, bb = 0.0;
   const long long sx = (long long)g.ny * g.nz, sy = g.nz;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.nc;
-       c += (long long)gridDim.x * blockDim.x) {
+  long long c0, c1;
+  wg_span(g.nc, cpw, &c0, &c1);
+  for (long long c = c0 + threadIdx.x; c < c1; c += kFoBlock) {
     int i, j, k;
     cell_ijk(c, g, &i, &j, &k);
     const double dx = g.ex[i + 1] - g.ex[i], dy = g.ey[j + 1] - g.ey[j], dz = g.ez[k + 1] - g.ez[k];
@@ -107,53 +142,52 @@ __global__ void __launch_bounds__(kFoBlock) k_fo_setup(FoGrid g, const int* __re
     rz += b * z;
     bb += b * b;
   }
+  // the halos: one x-plane of zeros before and after the conductances and p
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < sx; c += (long long)gridDim.x * blockDim.x) {
+    gx[c - sx] = 0.0; gy[c - sx] = 0.0; gz[c - sx] = 0.0; p[c - sx] = 0.0;
+    gx[g.nc + c] = 0.0; gy[g.nc + c] = 0.0; gz[g.nc + c] = 0.0; p[g.nc + c] = 0.0;
+  }
   block_sum(rz, part_rz);
-  __syncthreads();
   block_sum(bb, part_bb);
 }
 
-// Ap = A p and partial sums of p.Ap
-__global__ void __launch_bounds__(kFoBlock) k_fo_spmv(FoGrid g, const double* __restrict__ gx,
-                                                      const double* __restrict__ gy, const double* __restrict__ gz,
-                                                      const double* __restrict__ diag, const double* __restrict__ p,
-                                                      double* __restrict__ Ap, double* part) {
+// Ap = A p and partial sums of p.Ap.  gx, gy, gz and p have their halos (a
+// zero conductance or a zero entry multiplies every neighbour outside the
+// grid); the neighbour terms are subtracted in the order +x, -x, +y, -y, +z,
+// -z.
+__global__ void __launch_bounds__(kFoBlock) k_fo_spmv(long long nc, long long cpw, long long sx, long long sy,
+                                                      const double* __restrict__ gx, const double* __restrict__ gy,
+                                                      const double* __restrict__ gz, const double* __restrict__ diag,
+                                                      const double* __restrict__ p, double* __restrict__ Ap,
+                                                      double* part) {
   double acc = 0.0;
-  const long long sx = (long long)g.ny * g.nz, sy = g.nz;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.nc;
-       c += (long long)gridDim.x * blockDim.x) {
-    int i, j, k;
-    cell_ijk(c, g, &i, &j, &k);
+  long long c0, c1;
+  wg_span(nc, cpw, &c0, &c1);
+  for (long long c = c0 + threadIdx.x; c < c1; c += kFoBlock) {
     const double pc = p[c];
     double a = diag[c] * pc;
-    if (i + 1 < g.nx) a -= gx[c] * p[c + sx];
-    if (i > 0) a -= gx[c - sx] * p[c - sx];
-    if (j + 1 < g.ny) a -= gy[c] * p[c + sy];
-    if (j > 0) a -= gy[c - sy] * p[c - sy];
-    if (k + 1 < g.nz) a -= gz[c] * p[c + 1];
-    if (k > 0) a -= gz[c - 1] * p[c - 1];
+    a -= gx[c] * p[c + sx];
+    a -= gx[c - sx] * p[c - sx];
+    a -= gy[c] * p[c + sy];
+    a -= gy[c - sy] * p[c - sy];
+    a -= gz[c] * p[c + 1];
+    a -= gz[c - 1] * p[c - 1];
     Ap[c] = a;
     acc += pc * a;
   }
   block_sum(acc, part);
 }
 
-// One workgroup: the partial sums in a fixed order.
+// The n partial sums of a dot product, added by one workgroup of kFoBlock
+// threads in a fixed order (strided per thread, then wg_total): every
+// workgroup that calls this gets the same bits.
 __device__ inline double sum_parts(const double* part, int n) {
-  __shared__ double s[1024];
   double v = 0.0;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) v += part[t];
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-    __syncthreads();
-  }
-  const double out = s[0];
-  __syncthreads();
-  return out;
+  for (int t = threadIdx.x; t < n; t += kFoBlock) v += part[t];
+  return wg_total(v);
 }
 
-__global__ void __launch_bounds__(1024) k_fo_start(const double* part_rz, const double* part_bb, int n, double* sc) {
+__global__ void __launch_bounds__(kFoBlock) k_fo_start(const double* part_rz, const double* part_bb, int n, double* sc) {
   const double rz = sum_parts(part_rz, n), bb = sum_parts(part_bb, n);
   if (threadIdx.x == 0) {
     sc[S_RZ] = rz;
@@ -162,22 +196,45 @@ __global__ void __launch_bounds__(1024) k_fo_start(const double* part_rz, const 
   }
 }
 
-__global__ void __launch_bounds__(1024) k_fo_alpha(const double* part, int n, double* sc) {
-  const double pap = sum_parts(part, n);
-  if (threadIdx.x == 0) {
-    sc[S_PAP] = pap;
-    sc[S_ALPHA] = pap > 0.0 ? sc[S_RZ] / pap : 0.0;
+// alpha = r.z / p.Ap (p.Ap from the product's partials, added here);
+// x += alpha p; r -= alpha Ap; partial sums of r.z (z = r / diag) and r.r.
+// The first kFoUnroll cells of each thread are loaded before the partials
+// are added, so their latency overlaps.
+__global__ void __launch_bounds__(kFoBlock) k_fo_update(long long nc, long long cpw, int slot,
+                                                        const double* __restrict__ part_pap, int n_part,
+                                                        const double* __restrict__ sc, const double* __restrict__ diag,
+                                                        const double* __restrict__ p, const double* __restrict__ Ap,
+                                                        double* __restrict__ x, double* __restrict__ r,
+                                                        double* part_rz, double* part_rr) {
+  long long s0, s1;
+  wg_span(nc, cpw, &s0, &s1);
+  const long long stride = kFoBlock, c0 = s0 + threadIdx.x;
+  double vp[kFoUnroll], vA[kFoUnroll], vx[kFoUnroll], vr[kFoUnroll], vd[kFoUnroll];
+#pragma unroll
+  for (int u = 0; u < kFoUnroll; ++u) {
+    const long long c = c0 + u * stride;
+    const bool in = c < s1;
+    vp[u] = in ? p[c] : 0.0;
+    vA[u] = in ? Ap[c] : 0.0;
+    vx[u] = in ? x[c] : 0.0;
+    vr[u] = in ? r[c] : 0.0;
+    vd[u] = in ? diag[c] : 1.0;
   }
-}
-
-// x += alpha p; r -= alpha Ap; partial sums of r.z (z = r / diag) and r.r
-__global__ void __launch_bounds__(kFoBlock) k_fo_update(long long nc, const double* __restrict__ sc,
-                                                        const double* __restrict__ diag, const double* __restrict__ p,
-                                                        const double* __restrict__ Ap, double* __restrict__ x,
-                                                        double* __restrict__ r, double* part_rz, double* part_rr) {
-  const double alpha = sc[S_ALPHA];
+  const double pap = sum_parts(part_pap, n_part);
+  const double alpha = pap > 0.0 ? sc[S_RZ + slot] / pap : 0.0;
   double rz = 0.0, rr = 0.0;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < nc; c += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+  for (int u = 0; u < kFoUnroll; ++u) {
+    const long long c = c0 + u * stride;
+    if (c < s1) {
+      x[c] = vx[u] + alpha * vp[u];
+      const double rc = vr[u] - alpha * vA[u];
+      r[c] = rc;
+      rz += rc * (rc / vd[u]);
+      rr += rc * rc;
+    }
+  }
+  for (long long c = c0 + kFoUnroll * stride; c < s1; c += stride) {
     x[c] += alpha * p[c];
     const double rc = r[c] - alpha * Ap[c];
     r[c] = rc;
@@ -185,26 +242,44 @@ __global__ void __launch_bounds__(kFoBlock) k_fo_update(long long nc, const doub
     rr += rc * rc;
   }
   block_sum(rz, part_rz);
-  __syncthreads();
   block_sum(rr, part_rr);
 }
 
-__global__ void __launch_bounds__(1024) k_fo_beta(const double* part_rz, const double* part_rr, int n, double* sc) {
-  const double rz = sum_parts(part_rz, n), rr = sum_parts(part_rr, n);
-  if (threadIdx.x == 0) {
-    sc[S_BETA] = sc[S_RZ] > 0.0 ? rz / sc[S_RZ] : 0.0;
-    sc[S_RZ] = rz;
-    sc[S_RR] = rr;
-  }
-}
-
-// p = z + beta p
-__global__ void __launch_bounds__(kFoBlock) k_fo_direction(long long nc, const double* __restrict__ sc,
-                                                           const double* __restrict__ diag,
+// beta = r.z (new, from the update's partials, added here) / r.z (old, in
+// slot); p = z + beta p.  Workgroup 0 also stores the new r.z in the other
+// slot and r.r for the host's convergence check.
+__global__ void __launch_bounds__(kFoBlock) k_fo_direction(long long nc, long long cpw, int slot,
+                                                           const double* __restrict__ part_rz,
+                                                           const double* __restrict__ part_rr, int n_part,
+                                                           double* __restrict__ sc, const double* __restrict__ diag,
                                                            const double* __restrict__ r, double* __restrict__ p) {
-  const double beta = sc[S_BETA];
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < nc; c += (long long)gridDim.x * blockDim.x)
-    p[c] = r[c] / diag[c] + beta * p[c];
+  long long s0, s1;
+  wg_span(nc, cpw, &s0, &s1);
+  const long long stride = kFoBlock, c0 = s0 + threadIdx.x;
+  double vr[kFoUnroll], vd[kFoUnroll], vp[kFoUnroll];
+#pragma unroll
+  for (int u = 0; u < kFoUnroll; ++u) {
+    const long long c = c0 + u * stride;
+    const bool in = c < s1;
+    vr[u] = in ? r[c] : 0.0;
+    vd[u] = in ? diag[c] : 1.0;
+    vp[u] = in ? p[c] : 0.0;
+  }
+  const double rz = sum_parts(part_rz, n_part), rz_old = sc[S_RZ + slot];
+  const double beta = rz_old > 0.0 ? rz / rz_old : 0.0;
+  if (blockIdx.x == 0) {
+    const double rr = sum_parts(part_rr, n_part);
+    if (threadIdx.x == 0) {
+      sc[S_RZ + (slot ^ 1)] = rz;
+      sc[S_RR] = rr;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kFoUnroll; ++u) {
+    const long long c = c0 + u * stride;
+    if (c < s1) p[c] = vr[u] / vd[u] + beta * vp[u];
+  }
+  for (long long c = c0 + kFoUnroll * stride; c < s1; c += stride) p[c] = r[c] / diag[c] + beta * p[c];
 }
 
 __global__ void __launch_bounds__(kFoBlock) k_fo_temperature(long long nc, const double* __restrict__ kap,
@@ -234,7 +309,7 @@ __global__ void __launch_bounds__(kFoBlock) k_fo_chip_fields(const uint8_t* __re
 }
 
 struct FoLayout {
-  size_t gx, gy, gz, diag, x, r, p, Ap, part0, part1, held, sc, total;
+  size_t gx, gy, gz, diag, x, r, p, Ap, part0, part1, part2, held, sc, total;
 };
 
 bool fo_valid(const fo_config* c) {
@@ -260,16 +335,18 @@ FoLayout fo_layout(const fo_config* c) {
   const size_t nc = (size_t)c->n[0] * c->n[1] * c->n[2];
   size_t off = 0;
   auto take = [&](size_t b) { const size_t o = off; off += (b + 255) & ~(size_t)255; return o; };
-  L.gx = take(8 * nc);
-  L.gy = take(8 * nc);
-  L.gz = take(8 * nc);
+  const size_t halo = (size_t)c->n[1] * c->n[2];  // one x-plane before and after: offsets are of cell 0
+  L.gx = take(8 * (nc + 2 * halo)) + 8 * halo;
+  L.gy = take(8 * (nc + 2 * halo)) + 8 * halo;
+  L.gz = take(8 * (nc + 2 * halo)) + 8 * halo;
   L.diag = take(8 * nc);
   L.x = take(8 * nc);
   L.r = take(8 * nc);
-  L.p = take(8 * nc);
+  L.p = take(8 * (nc + 2 * halo)) + 8 * halo;
   L.Ap = take(8 * nc);
   L.part0 = take(8 * kFoMaxBlocks);
   L.part1 = take(8 * kFoMaxBlocks);
+  L.part2 = take(8 * kFoMaxBlocks);
   L.held = take(4 * 6);
   L.sc = take(8 * S_N);
   L.total = off;
@@ -317,15 +394,20 @@ int fo_solve(const fo_config* c, const double* d_edges, const double* d_kappa, c
   g.ex = d_edges;
   g.ey = d_edges + g.nx + 1;
   g.ez = d_edges + g.nx + 1 + g.ny + 1;
-  long long need = (g.nc + kFoBlock - 1) / kFoBlock;
-  const int nb = (int)(need < kFoMaxBlocks ? need : kFoMaxBlocks);
+  // workgroups of the solve: about kFoUnroll cells per thread, at most
+  // kFoMaxBlocks, a multiple of 8 (one span per XCD in turn); cpw cells each,
+  // a multiple of kFoBlock, so that nb cpw >= nc
+  const long long need = (g.nc + (long long)kFoBlock * kFoUnroll - 1) / ((long long)kFoBlock * kFoUnroll);
+  const int nb = (int)(((need < kFoMaxBlocks ? need : kFoMaxBlocks) + 7) / 8 * 8);
+  const long long cpw = ((g.nc + nb - 1) / nb + kFoBlock - 1) / kFoBlock * kFoBlock;
+  const long long sx = (long long)g.ny * g.nz, sy = g.nz;
   if (hipMemcpyAsync(ws + L.held, c->dirichlet, sizeof(int) * 6, hipMemcpyHostToDevice, st) != hipSuccess)
     return MC_E_HIP;
   double* sc = P(L.sc);
   k_fo_setup<<<nb, kFoBlock, 0, st>>>(g, (const int*)(ws + L.held), c->k_interface, c->R_K_m2KW, d_kappa, d_q,
-                                     P(L.gx), P(L.gy), P(L.gz), P(L.diag), P(L.x), P(L.r), P(L.p), P(L.part0),
+                                     P(L.gx), P(L.gy), P(L.gz), P(L.diag), P(L.x), P(L.r), P(L.p), cpw, P(L.part0),
                                      P(L.part1));
-  k_fo_start<<<1, 1024, 0, st>>>(P(L.part0), P(L.part1), nb, sc);
+  k_fo_start<<<1, kFoBlock, 0, st>>>(P(L.part0), P(L.part1), nb, sc);
   if (hipGetLastError() != hipSuccess) return MC_E_HIP;
   double h[S_N];
   if (hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
@@ -335,12 +417,18 @@ int fo_solve(const fo_config* c, const double* d_edges, const double* d_kappa, c
   double rel = 0.0;
   if (bb > 0.0) {
     const double stop = c->rtol * c->rtol * bb;
+    // partial sums: p.Ap in part2 (written by the product, read by the
+    // update), r.z and r.r in part0 and part1 (written by the update, read by
+    // the direction kernel); the direction of the last iteration is formed
+    // but not used
     for (;;) {
-      k_fo_spmv<<<nb, kFoBlock, 0, st>>>(g, P(L.gx), P(L.gy), P(L.gz), P(L.diag), P(L.p), P(L.Ap), P(L.part0));
-      k_fo_alpha<<<1, 1024, 0, st>>>(P(L.part0), nb, sc);
-      k_fo_update<<<nb, kFoBlock, 0, st>>>(g.nc, sc, P(L.diag), P(L.p), P(L.Ap), P(L.x), P(L.r), P(L.part0),
-                                          P(L.part1));
-      k_fo_beta<<<1, 1024, 0, st>>>(P(L.part0), P(L.part1), nb, sc);
+      const int slot = it & 1;
+      k_fo_spmv<<<nb, kFoBlock, 0, st>>>(g.nc, cpw, sx, sy, P(L.gx), P(L.gy), P(L.gz), P(L.diag), P(L.p), P(L.Ap),
+                                         P(L.part2));
+      k_fo_update<<<nb, kFoBlock, 0, st>>>(g.nc, cpw, slot, P(L.part2), nb, sc, P(L.diag), P(L.p), P(L.Ap), P(L.x),
+                                          P(L.r), P(L.part0), P(L.part1));
+      k_fo_direction<<<nb, kFoBlock, 0, st>>>(g.nc, cpw, slot, P(L.part0), P(L.part1), nb, sc, P(L.diag), P(L.r),
+                                             P(L.p));
       ++it;
       const bool check = it % kFoCheck == 0 || it == c->max_iterations;
       if (check) {
@@ -354,7 +442,6 @@ int fo_solve(const fo_config* c, const double* d_edges, const double* d_kappa, c
           break;
         }
       }
-      k_fo_direction<<<nb, kFoBlock, 0, st>>>(g.nc, sc, P(L.diag), P(L.r), P(L.p));
     }
     rel = std::sqrt(h[S_RR] / bb);
   }
