@@ -37,6 +37,8 @@ def main(argv=None) -> int:
     ap.add_argument("--per-cell-scale", action="store_true",
                     help="z-score every output on its own (default: one scale per map)")
     ap.add_argument("--tol", type=float, default=0.02)
+    ap.add_argument("--save-data", default="", help="write the Monte Carlo data (.npz) for later fits")
+    ap.add_argument("--load-data", default="", help="fit on Monte Carlo data written by --save-data")
     ap.add_argument("--out", default="")
     a = ap.parse_args(argv)
 
@@ -47,26 +49,38 @@ def main(argv=None) -> int:
     def log(*x):
         print(*x, file=sys.stderr, flush=True)
 
-    train_cfgs = W.surrogate_inputs(a.train, seed=11)
-    val_cfgs = W.surrogate_inputs(a.val, seed=23)
-    for c in train_cfgs + val_cfgs:
-        c["n_particles"] = a.particles
-        c["capacity"] = int(a.particles * 1.3)
-    log(f"MC training data: {a.train} bias points x {a.particles} electrons, {a.warm}+{a.window} intervals")
-    X, Y, t_train = S.generate(train_cfgs, a.warm, a.window, log=log)
-    log(f"MC held-out references: {a.val} bias points x {a.ref_seeds} seeds")
-    Xv = np.stack([S.features(c) for c in val_cfgs])
-    Yv = np.zeros((a.val, 2 * S.N_CELL), np.float32)
-    Yv_single = None
-    t_ref = 0.0
-    for r in range(a.ref_seeds):
-        cfgs = [dict(c, seed=c["seed"] + 100003 * (r + 1)) for c in val_cfgs]
-        _, Yr, tr = S.generate(cfgs, a.warm, a.window, log=log)
-        t_ref += tr
-        Yv += Yr / a.ref_seeds
-        if Yv_single is None:
-            Yv_single = Yr
-    mc_time_per_point = t_ref / (a.ref_seeds * a.val)
+    if a.load_data:
+        d = np.load(a.load_data)
+        X, Y, Xv, Yv, Yv_single = d["X"], d["Y"], d["Xv"], d["Yv"], d["Yv_single"]
+        t_train, mc_time_per_point = float(d["t_train"]), float(d["mc_time_per_point"])
+        a.train, a.val = X.shape[0], Xv.shape[0]
+        a.ref_seeds, a.warm, a.window, a.particles = (int(d[k]) for k in ("ref_seeds", "warm", "window", "particles"))
+        log(f"MC data from {a.load_data}: {a.train} training and {a.val} held-out points")
+    else:
+        train_cfgs = W.surrogate_inputs(a.train, seed=11)
+        val_cfgs = W.surrogate_inputs(a.val, seed=23)
+        for c in train_cfgs + val_cfgs:
+            c["n_particles"] = a.particles
+            c["capacity"] = int(a.particles * 1.3)
+        log(f"MC training data: {a.train} bias points x {a.particles} electrons, {a.warm}+{a.window} intervals")
+        X, Y, t_train = S.generate(train_cfgs, a.warm, a.window, log=log)
+        log(f"MC held-out references: {a.val} bias points x {a.ref_seeds} seeds")
+        Xv = np.stack([S.features(c) for c in val_cfgs])
+        Yv = np.zeros((a.val, 2 * S.N_CELL), np.float32)
+        Yv_single = None
+        t_ref = 0.0
+        for r in range(a.ref_seeds):
+            cfgs = [dict(c, seed=c["seed"] + 100003 * (r + 1)) for c in val_cfgs]
+            _, Yr, tr = S.generate(cfgs, a.warm, a.window, log=log)
+            t_ref += tr
+            Yv += Yr / a.ref_seeds
+            if Yv_single is None:
+                Yv_single = Yr
+        mc_time_per_point = t_ref / (a.ref_seeds * a.val)
+        if a.save_data:
+            np.savez(a.save_data, X=X, Y=Y, Xv=Xv, Yv=Yv, Yv_single=Yv_single, t_train=t_train,
+                     mc_time_per_point=mc_time_per_point, ref_seeds=a.ref_seeds, warm=a.warm, window=a.window,
+                     particles=a.particles)
     # noise of one MC run against the averaged reference (an estimate of
     # the MC's own error at this ensemble size and window)
     mc_err = S.rel_l2(Yv_single, Yv).max(axis=1) * np.sqrt(a.ref_seeds / max(1, a.ref_seeds - 1))
