@@ -159,9 +159,18 @@ __device__ __forceinline__ T kane_E(T gam, T a) {
   return Ar<T>::dv((T)2 * gam, (T)1 + Ar<T>::sq((T)1 + (T)4 * a * gam));
 }
 
+// Sums of products written as explicit fused multiply-adds.  Left to the
+// compiler, which product of such a sum it fuses can differ between two
+// kernels that inline the same code, and with it the last bit; the kernels
+// of the particle step must agree bit for bit.
+template <typename T>
+__device__ __forceinline__ T ksq(T kx, T ky, T kz) { return fma(kx, kx, fma(ky, ky, kz * kz)); }
+template <typename T>
+__device__ __forceinline__ T dot3(T a0, T b0, T a1, T b1, T a2, T b2) { return fma(a0, b0, fma(a1, b1, a2 * b2)); }
+
 template <typename T>
 __device__ __forceinline__ T energy(const Mat<T>& M, int v, T kx, T ky, T kz) {
-  const T k2 = kx * kx + ky * ky + kz * kz;
+  const T k2 = ksq(kx, ky, kz);
   return kane_E(Ar<T>::dv(M.ck * k2, pick3(M.m, v)), pick3(M.alpha, v));
 }
 

@@ -122,7 +122,7 @@ __device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const
                                        T& kz, const uint4 w, int cell, int ncell, Cnt& c, uint32_t* sh_heat,
                                        uint32_t* sh_real) {
   const Mat<T>& M = a.M;
-  const T k2 = kx * kx + ky * ky + kz * kz;
+  const T k2 = ksq(kx, ky, kz);
   const T g = Ar<T>::dv(M.ck * k2, pick3(M.m, v));
   const T E = kane_E(g, pick3(M.alpha, v));
   const T eb = Ar<T>::dv(E, a.dE);
@@ -187,9 +187,10 @@ __device__ __forceinline__ int scatter(const FlightArgs<T>& a, const T* f, const
   onb<T>(nx, ny, nz, e1, e2);
   const T gpp = Ep * ((T)1 + pick3(M.alpha, vp) * Ep);
   const T kp = Ar<T>::sq(Ar<T>::dv(gpp * pick3(M.m, vp), M.ck));
-  kx = kp * (st * cp * e1[0] + st * sp * e2[0] + ct * nx);
-  ky = kp * (st * cp * e1[1] + st * sp * e2[1] + ct * ny);
-  kz = kp * (st * cp * e1[2] + st * sp * e2[2] + ct * nz);
+  const T sc = st * cp, ss = st * sp;
+  kx = kp * dot3(sc, e1[0], ss, e2[0], ct, nx);
+  ky = kp * dot3(sc, e1[1], ss, e2[1], ct, ny);
+  kz = kp * dot3(sc, e1[2], ss, e2[2], ct, nz);
   v = vp;
   return m;
 }
@@ -205,9 +206,10 @@ __device__ __forceinline__ int drift(const FlightArgs<T>& a, int v, T dt, T fx, 
   if (DEV) {
     const T s0 = vel_factor(M, v, energy(M, v, kx, ky, kz));
     const T s1 = vel_factor(M, v, energy(M, v, k1x, k1y, k1z));
-    x += (T)0.5 * dt * (s0 * kx + s1 * k1x);
-    y += (T)0.5 * dt * (s0 * ky + s1 * k1y);
-    z += (T)0.5 * dt * (s0 * kz + s1 * k1z);
+    const T h = (T)0.5 * dt;  // explicit fused forms, as in drift_e
+    x = fma(h, fma(s0, kx, s1 * k1x), x);
+    y = fma(h, fma(s0, ky, s1 * k1y), y);
+    z = fma(h, fma(s0, kz, s1 * k1z), z);
   }
   kx = k1x; ky = k1y; kz = k1z;
   if (!DEV) return -1;
@@ -387,7 +389,7 @@ __device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* Sr, co
     const int hs = m == 3 ? 0 : (m == 2 ? 1 : (m >= 4 ? (((m - 4) & 1) ? 2 : 3) : -1));
     if (hs >= 0) atomicAdd(sh_heat + hs * ncell + cell, 1u);
   }
-  const T k2 = kx * kx + ky * ky + kz * kz;
+  const T k2 = ksq(kx, ky, kz);
   const T g = E * ((T)1 + pick3(M.alpha, v) * E);
   const T u2 = Ar<T>::u01(w.z), u3 = Ar<T>::u01(w.w);
   T X;
@@ -414,9 +416,10 @@ __device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* Sr, co
   onb<T>(nx, ny, nz, e1, e2);
   const T gpp = Ep * ((T)1 + pick3(M.alpha, vp) * Ep);
   const T kp = Ar<T>::sq(Ar<T>::dv(gpp * pick3(M.m, vp), M.ck));
-  kx = kp * (st * cp * e1[0] + st * sp * e2[0] + ct * nx);
-  ky = kp * (st * cp * e1[1] + st * sp * e2[1] + ct * ny);
-  kz = kp * (st * cp * e1[2] + st * sp * e2[2] + ct * nz);
+  const T sc = st * cp, ss = st * sp;
+  kx = kp * dot3(sc, e1[0], ss, e2[0], ct, nx);
+  ky = kp * dot3(sc, e1[1], ss, e2[1], ct, ny);
+  kz = kp * dot3(sc, e1[2], ss, e2[2], ct, nz);
   v = vp;
   E = Ep;
   return m;
@@ -448,9 +451,13 @@ __device__ __forceinline__ int drift_e(const FlightArgs<T>& a, int v, T dt, T fx
   if (DEV) {
     const T s0 = vel_factor(M, v, E);
     const T s1 = vel_factor(M, v, E1);
-    x += (T)0.5 * dt * (s0 * kx + s1 * k1x);
-    y += (T)0.5 * dt * (s0 * ky + s1 * k1y);
-    z += (T)0.5 * dt * (s0 * kz + s1 * k1z);
+    // the trapezoid written with explicit fused multiply-adds: left to the
+    // compiler, which of the two products it fuses can differ between the
+    // kernels that inline this, and with it the last bit of the position
+    const T h = (T)0.5 * dt;
+    x = fma(h, fma(s0, kx, s1 * k1x), x);
+    y = fma(h, fma(s0, ky, s1 * k1y), y);
+    z = fma(h, fma(s0, kz, s1 * k1z), z);
   }
   kx = k1x; ky = k1y; kz = k1z;
   E = E1;
@@ -487,6 +494,43 @@ __device__ __forceinline__ bool take_slot(const FlightArgs<T>& a, long long p, L
   L.x = lx; L.y = ly; L.z = lz;
   L.v = meta_valley(meta);
   L.id = meta_id(meta);
+  L.j = 0;
+  L.t = (T)0;
+  L.E = energy(a.M, L.v, L.kx, L.ky, L.kz);
+  return true;
+}
+
+// A slot's state loaded ahead of its use: the lane issues the loads when it
+// claims the slot and takes the electron over (adopt) once its current one
+// has ended, a segment later, so that the state's memory latency is covered
+// by that segment's work instead of stalling the wavefront at the refill.
+template <typename T>
+struct Prefetch {
+  long long p;
+  uint32_t meta;
+  T kx, ky, kz, x, y, z;
+};
+
+template <typename T, bool DEV>
+__device__ __forceinline__ void prefetch_slot(const FlightArgs<T>& a, long long p, Prefetch<T>& F) {
+  F.p = p;
+  F.meta = a.meta[p];
+  F.kx = a.kx[p]; F.ky = a.ky[p]; F.kz = a.kz[p];
+  F.x = (T)0; F.y = (T)0; F.z = (T)0;
+  if (DEV) { F.x = a.x[p]; F.y = a.y[p]; F.z = a.z[p]; }
+}
+
+// The prefetched slot becomes the lane's electron if it holds a live one
+// (a free slot is counted and dropped), exactly as take_slot would load it.
+template <typename T>
+__device__ __forceinline__ bool adopt_slot(const FlightArgs<T>& a, const Prefetch<T>& F, LaneE<T>& L, Cnt& c) {
+  if (!(F.meta & kAlive)) { c.dead++; return false; }
+  c.proc++;
+  L.p = F.p;
+  L.kx = F.kx; L.ky = F.ky; L.kz = F.kz;
+  L.x = F.x; L.y = F.y; L.z = F.z;
+  L.v = meta_valley(F.meta);
+  L.id = meta_id(F.meta);
   L.j = 0;
   L.t = (T)0;
   L.E = energy(a.M, L.v, L.kx, L.ky, L.kz);
@@ -600,8 +644,12 @@ __device__ __forceinline__ void flush_workgroup(const Cnt& c, const uint32_t* rc
 // of an electron's interval, or one scattering event plus the next flight)
 // and pulls the next electron of the tile from a workgroup queue as soon as
 // its electron reaches the end of the interval, so lanes do not idle while
-// the busiest lane of the wavefront finishes its events.  Per-electron
-// arithmetic and random-number use are the same as in k_flight.
+// the busiest lane of the wavefront finishes its events.  Each lane keeps
+// the next slot it claimed from the queue prefetched (Prefetch), so that a
+// refill rarely waits for the state's loads.  Per-electron arithmetic and
+// random-number use are the same as in k_flight, and the order in which
+// lanes take electrons changes no result (every electron has its own
+// random-number stream; the histograms are sums of counts).
 // Workgroups of up to 1024 lanes for FP32 state; FP64 state needs more than
 // the 128 registers a 1024-lane workgroup leaves each lane, so 512 at most.
 template <typename T>
@@ -638,27 +686,41 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
   Cnt c = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
   if (threadIdx.x == 0) c.dead = (uint32_t)td.count - lim;
   bool guard_hit = false, nan_hit = false;
-  bool has = false, exhausted = false;
+  bool has = false, exhausted = false, pf = false;
   LaneE<T> L = {};
+  Prefetch<T> F = {};
   uint32_t rc[kNM];
 #pragma unroll
   for (int q = 0; q < kNM; ++q) rc[q] = 0u;
   for (;;) {
-    // refill: lanes without an electron take the next live slots of the tile
-    bool want = !has && !exhausted;
-    unsigned long long m = __ballot(want);
-    while (m) {
-      const int first = __ffsll((long long)m) - 1;
-      uint32_t base = 0;
-      if (lane == first) base = atomicAdd(sh_q, (uint32_t)__popcll(m));
-      base = __shfl(base, first);
-      if (want) {
-        const uint32_t idx = base + (uint32_t)__popcll(m & lt);
-        if (idx < lim) has = take_slot<T, DEV>(a, td.start + idx, L, c);
-        else exhausted = true;
+    // refill: a lane without an electron adopts its prefetched slot; a lane
+    // without a prefetched slot claims the next index of the tile's queue and
+    // issues its loads.  Repeated only while some lane still has neither an
+    // electron nor a slot it could adopt at once (the tile's first slots, a
+    // free slot adopted).
+    for (;;) {
+      if (!has && pf) {
+        has = adopt_slot<T>(a, F, L, c);
+        pf = false;
       }
-      want = !has && !exhausted;
-      m = __ballot(want);
+      const bool want = !pf && !exhausted;
+      const unsigned long long m = __ballot(want);
+      if (m) {
+        const int first = __ffsll((long long)m) - 1;
+        uint32_t base = 0;
+        if (lane == first) base = atomicAdd(sh_q, (uint32_t)__popcll(m));
+        base = __shfl(base, first);
+        if (want) {
+          const uint32_t idx = base + (uint32_t)__popcll(m & lt);
+          if (idx < lim) {
+            prefetch_slot<T, DEV>(a, td.start + idx, F);
+            pf = true;
+          } else {
+            exhausted = true;
+          }
+        }
+      }
+      if (!__any(!has && pf)) break;
     }
     if (!__any(has)) break;
     if (has) {
