@@ -77,6 +77,8 @@ template <> struct Ar<double> {
   __device__ static double fl(double x) { return floor(x); }
   // position -> cell coordinate: a correctly rounded division in FP64
   __device__ static double cs(double x, double d, double) { return x / d; }
+  // x clamped to [0, hi] (a NaN to 0)
+  __device__ static double clamp0(double x, double hi) { return fmin(fmax(x, 0.0), hi); }
 };
 template <> struct Ar<float> {
   // 23 random bits so that (w + 1/2) 2^-23 is exact and lies in (0, 1)
@@ -99,6 +101,9 @@ template <> struct Ar<float> {
   __device__ static float l1p(float x) { return __builtin_amdgcn_logf(1.0f + x) * 0.693147180559945f; }
   __device__ static float fl(float x) { return floorf(x); }
   __device__ static float cs(float x, float, float inv_d) { return x * inv_d; }
+  // x clamped to [0, hi] in one v_med3_f32 (a NaN comes out as 0, 0 or hi:
+  // in range either way)
+  __device__ static float clamp0(float x, float hi) { return __builtin_amdgcn_fmed3f(x, 0.0f, hi); }
 };
 
 // Row loads of 16-byte vectors (rows are 16-byte aligned).
@@ -182,13 +187,11 @@ __device__ __forceinline__ T vel_factor(const Mat<T>& M, int v, T E) {
 
 template <typename T>
 __device__ __forceinline__ int cell_of(const Geo<T>& G, T x, T y, T z) {
-  // clamp in floating point first so non-finite input still lands in range
-  T fx = Ar<T>::fl(Ar<T>::cs(x, G.d[0], G.inv_d[0]));
-  T fy = Ar<T>::fl(Ar<T>::cs(y, G.d[1], G.inv_d[1]));
-  T fz = Ar<T>::fl(Ar<T>::cs(z, G.d[2], G.inv_d[2]));
-  fx = fmin(fmax(fx, (T)0), (T)(G.nx - 1));
-  fy = fmin(fmax(fy, (T)0), (T)(G.ny - 1));
-  fz = fmin(fmax(fz, (T)0), (T)(G.nz - 1));
+  // clamp in floating point first so that non-finite input still lands in
+  // range; a coordinate clamped to [0, n - 1] truncates to its floor
+  const T fx = Ar<T>::clamp0(Ar<T>::cs(x, G.d[0], G.inv_d[0]), (T)(G.nx - 1));
+  const T fy = Ar<T>::clamp0(Ar<T>::cs(y, G.d[1], G.inv_d[1]), (T)(G.ny - 1));
+  const T fz = Ar<T>::clamp0(Ar<T>::cs(z, G.d[2], G.inv_d[2]), (T)(G.nz - 1));
   return ((int)fx * G.ny + (int)fy) * G.nz + (int)fz;
 }
 

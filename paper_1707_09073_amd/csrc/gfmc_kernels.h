@@ -363,15 +363,19 @@ __device__ __forceinline__ int scatter_e(const FlightArgs<T>& a, const T* Sr, co
                                          uint32_t* sh_heat, uint32_t* sh_real, uint32_t* rc) {
   const Mat<T>& M = a.M;
   const T rs = Ar<T>::u01(w.y) * pick3(gam, v);
+  // the selected mechanism is the first whose running sum exceeds rs; the
+  // terms are rates times occupations, none negative, so the running sums
+  // do not decrease and that index is the count of sums at or below rs
+  // (kNM: none exceeds it, self-scattering)
   T cum = (T)0;
-  int m = -1;
+  int m = 0;
 #pragma unroll
   for (int q = 0; q < kNM; ++q) {
     cum += tab_term<T>(Sr, f, q);
-    if (m < 0 && rs < cum) m = q;
+    m += cum <= rs ? 1 : 0;
   }
   c.sel++;
-  if (m < 0) { c.self++; return -1; }
+  if (m == kNM) { c.self++; return -1; }
   // final energy by selects (every lane computes the intervalley form)
   const int vp = m >= 4 ? (m - 4) >> 1 : v;
   const T Eiv = E + pick3(M.Ec, v) - pick3(M.Ec, vp) + (((m - 4) & 1) ? -M.hw_iv : M.hw_iv);
@@ -506,14 +510,15 @@ __device__ __forceinline__ bool take_slot(const FlightArgs<T>& a, long long p, L
 // by that segment's work instead of stalling the wavefront at the refill.
 template <typename T>
 struct Prefetch {
-  long long p;
+  uint32_t idx;  // slot within the tile
   uint32_t meta;
   T kx, ky, kz, x, y, z;
 };
 
 template <typename T, bool DEV>
-__device__ __forceinline__ void prefetch_slot(const FlightArgs<T>& a, long long p, Prefetch<T>& F) {
-  F.p = p;
+__device__ __forceinline__ void prefetch_slot(const FlightArgs<T>& a, long long start, uint32_t idx, Prefetch<T>& F) {
+  const long long p = start + idx;
+  F.idx = idx;
   F.meta = a.meta[p];
   F.kx = a.kx[p]; F.ky = a.ky[p]; F.kz = a.kz[p];
   F.x = (T)0; F.y = (T)0; F.z = (T)0;
@@ -523,10 +528,11 @@ __device__ __forceinline__ void prefetch_slot(const FlightArgs<T>& a, long long 
 // The prefetched slot becomes the lane's electron if it holds a live one
 // (a free slot is counted and dropped), exactly as take_slot would load it.
 template <typename T>
-__device__ __forceinline__ bool adopt_slot(const FlightArgs<T>& a, const Prefetch<T>& F, LaneE<T>& L, Cnt& c) {
+__device__ __forceinline__ bool adopt_slot(const FlightArgs<T>& a, long long start, const Prefetch<T>& F, LaneE<T>& L,
+                                           Cnt& c) {
   if (!(F.meta & kAlive)) { c.dead++; return false; }
   c.proc++;
-  L.p = F.p;
+  L.p = start + F.idx;
   L.kx = F.kx; L.ky = F.ky; L.kz = F.kz;
   L.x = F.x; L.y = F.y; L.z = F.z;
   L.v = meta_valley(F.meta);
@@ -556,7 +562,7 @@ __device__ __forceinline__ int lane_segment(const FlightArgs<T>& a, const InstPa
   const bool ovf = !(eb < (T)a.nb);
   const int bin = (int)fmin(eb, (T)(a.nb - 1));  // NaN -> last bin
   T Sr[kTRow], f[kFRow], F[4];
-  load_row<kTRow>(a.table + ((size_t)L.v * a.nb + bin) * kTRow, Sr);
+  load_row<kTRow>(a.table + (uint32_t)((L.v * a.nb + bin) * kTRow), Sr);
   load_row<kFRow>(fac + kFRow * cell, f);
   load_row<4>(field + 4 * cell, F);
   __builtin_amdgcn_sched_barrier(0);  // keep the loads above the generator
@@ -693,16 +699,17 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
 #pragma unroll
   for (int q = 0; q < kNM; ++q) rc[q] = 0u;
   for (;;) {
-    // refill: a lane without an electron adopts its prefetched slot; a lane
-    // without a prefetched slot claims the next index of the tile's queue and
-    // issues its loads.  Repeated only while some lane still has neither an
-    // electron nor a slot it could adopt at once (the tile's first slots, a
-    // free slot adopted).
-    for (;;) {
-      if (!has && pf) {
-        has = adopt_slot<T>(a, F, L, c);
-        pf = false;
-      }
+    // refill: a lane without an electron adopts the slot it prefetched (a
+    // free slot leaves it idle for this iteration); a lane without a
+    // prefetched slot claims the next index of the tile's queue and issues
+    // its loads, to be adopted in a later iteration.  The lane's electron is
+    // written only here and in the segment, outside any inner loop, which
+    // keeps the compiler from copying its state around the refill.
+    if (!has && pf) {
+      has = adopt_slot<T>(a, td.start, F, L, c);
+      pf = false;
+    }
+    {
       const bool want = !pf && !exhausted;
       const unsigned long long m = __ballot(want);
       if (m) {
@@ -713,22 +720,28 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
         if (want) {
           const uint32_t idx = base + (uint32_t)__popcll(m & lt);
           if (idx < lim) {
-            prefetch_slot<T, DEV>(a, td.start + idx, F);
+            prefetch_slot<T, DEV>(a, td.start, idx, F);
             pf = true;
           } else {
             exhausted = true;
           }
         }
       }
-      if (!__any(!has && pf)) break;
     }
-    if (!__any(has)) break;
-    if (has) {
-      const int r = lane_segment<T, DEV>(a, P, fac, field, gam, n_int, ncell, L, c, sh_heat, sh_real, rc, guard_hit);
-      if (r > -2) {
-        retire<T, DEV>(a, L, r, c, sh_dep, true, nan_hit);
-        has = false;
-      }
+    if (!__any(has || pf)) break;
+    // Every lane runs the segment, so that the lane's electron is updated in
+    // code without a branch around it.  A lane without an electron runs it on
+    // its stale state (an electron it finished, or the zero state: its
+    // subcell and energy bin are in range) with the event counter held at
+    // zero, so that it selects no event and counts nothing, and its outcome
+    // is dropped.
+    if (!has) L.j = 0;
+    const uint32_t refl0 = c.refl;
+    const int r = lane_segment<T, DEV>(a, P, fac, field, gam, n_int, ncell, L, c, sh_heat, sh_real, rc, guard_hit);
+    if (!has) c.refl = refl0;
+    if (has && r > -2) {
+      retire<T, DEV>(a, L, r, c, sh_dep, true, nan_hit);
+      has = false;
     }
   }
   if (guard_hit) set_flag(a.flags, td.inst, -4);
