@@ -53,8 +53,13 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # 2.000 + WRITE_SIZE x 1.000, scales from a 1 GiB device copy).
 KERNELS = {0: "k_flight_refill<float,true>", 1: "k_flight<float,true>", 2: "k_flight_persist<float,true>"}
 KERNEL_COUNTERS = {
-    0: {"sources_digest": "cefecf43f470509e", "valu_lane_ops_per_segment": 173.2, "hbm_bytes_per_segment": 8.76,
-        "active_lane_fraction": 0.46, "profile": "profiles/k_flight_refill_device1e7_counters.md"},
+    0: {"sources_digest": "d93c2d4f4f304f12", "valu_lane_ops_per_segment": 183.5, "hbm_bytes_per_segment": 13.53,
+        "active_lane_fraction": 0.536, "profile": "profiles/k_flight_refill_device1e7_counters.md",
+        "note": "counters at block 1024 / tile 8192; the active lanes include lanes without an electron, which run "
+                "the segment on stale state and drop it, so the useful fraction is an upper bound"},
+    2: {"sources_digest": "d93c2d4f4f304f12", "valu_lane_ops_per_segment": 172.8, "hbm_bytes_per_segment": 11.54,
+        "active_lane_fraction": 0.418, "profile": "profiles/k_flight_persist_device1e7_counters.md",
+        "note": "counters at block 1024 / tile 8192 (one resident workgroup of 1024 lanes per CU)"},
 }
 
 
@@ -547,7 +552,7 @@ def main() -> int:
                 active_lane_fraction=kc.get("active_lane_fraction"),
                 frac_useful=(ops * kc["active_lane_fraction"] / flight_s / ALU_PEAK_LANE_OPS
                              if kc.get("active_lane_fraction") else None),
-                profile=kc["profile"])
+                profile=kc["profile"], note=kc.get("note"))
     out = {
         "metric": METRIC,
         "value": value,
