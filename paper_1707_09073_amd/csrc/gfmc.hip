@@ -366,6 +366,9 @@ FlightArgs<T> flight_args(mc_ctx* c, const Mat<T>& M, const Geo<T>& G, size_t ta
   a.plan = c->p<Plan>(c->o.plan);
   a.tile = c->tile;
   a.chunk = c->chunk;
+  a.n_inst = c->n_inst;
+  // the Infinity Cache (256 MB) over the state bytes per slot
+  a.nt_slots = (uint32_t)((256ull << 20) / (6 * sizeof(T) + sizeof(uint32_t)));
   a.M = M;
   a.G = G;
   a.nb = c->nb;

@@ -96,6 +96,8 @@ struct FlightArgs {
   const Plan* plan;     // lane-refill kernel (device mode): slots in use per instance
   const int* wg_inst;  // persistent kernel: instance of each workgroup
   int tile, chunk;     // persistent kernel: tile and chunk sizes (slots)
+  int n_inst;
+  uint32_t nt_slots;   // device mode: state is read non-temporally once more slots than this are in use
   Mat<T> M;
   Geo<T> G;
   int nb;
@@ -473,12 +475,31 @@ __device__ __forceinline__ int drift_e(const FlightArgs<T>& a, int v, T dt, T fx
   return -1;
 }
 
+// A load of particle state, which a launch reads once.  When the state in
+// use outgrows the Infinity Cache (nt), the loads are non-temporal: the
+// state streaming through from HBM then does not push out the lines of
+// state the lanes are writing back (partly written until all their slots'
+// electrons have ended the interval).  While the state fits the cache,
+// plain loads keep it there, and are faster.
+template <typename T>
+__device__ __forceinline__ T sload(const T* p, bool nt) { return nt ? __builtin_nontemporal_load(p) : *p; }
+
+// Whether the state in use (the slots below every instance's bound)
+// outgrows the Infinity Cache: wavefront-uniform, from the refill plan.
+template <typename T>
+__device__ __forceinline__ bool state_outgrows_cache(const FlightArgs<T>& a) {
+  unsigned long long n = 0;
+  for (int i = 0; i < a.n_inst; ++i) n += a.plan[i].hw;
+  return n > a.nt_slots;
+}
+
 // The electron a lane is working on in the lane-refill kernels.
 template <typename T>
 struct LaneE {
   T kx, ky, kz, x, y, z, t, E;
   int v;
   uint32_t id, j;
+  uint32_t meta0;  // the slot's meta word when the lane took the electron
   long long p;  // slot
 };
 
@@ -486,14 +507,15 @@ struct LaneE {
 // per slot; a free slot's stale state is discarded).  Returns whether the
 // slot holds a live electron, which then becomes the lane's electron.
 template <typename T, bool DEV>
-__device__ __forceinline__ bool take_slot(const FlightArgs<T>& a, long long p, LaneE<T>& L, Cnt& c) {
-  const uint32_t meta = a.meta[p];
-  const T lkx = a.kx[p], lky = a.ky[p], lkz = a.kz[p];
+__device__ __forceinline__ bool take_slot(const FlightArgs<T>& a, long long p, LaneE<T>& L, Cnt& c, bool nt) {
+  const uint32_t meta = sload(a.meta + p, nt);
+  const T lkx = sload(a.kx + p, nt), lky = sload(a.ky + p, nt), lkz = sload(a.kz + p, nt);
   T lx = (T)0, ly = (T)0, lz = (T)0;
-  if (DEV) { lx = a.x[p]; ly = a.y[p]; lz = a.z[p]; }
+  if (DEV) { lx = sload(a.x + p, nt); ly = sload(a.y + p, nt); lz = sload(a.z + p, nt); }
   if (!(meta & kAlive)) { c.dead++; return false; }
   c.proc++;
   L.p = p;
+  L.meta0 = meta;
   L.kx = lkx; L.ky = lky; L.kz = lkz;
   L.x = lx; L.y = ly; L.z = lz;
   L.v = meta_valley(meta);
@@ -516,13 +538,14 @@ struct Prefetch {
 };
 
 template <typename T, bool DEV>
-__device__ __forceinline__ void prefetch_slot(const FlightArgs<T>& a, long long start, uint32_t idx, Prefetch<T>& F) {
+__device__ __forceinline__ void prefetch_slot(const FlightArgs<T>& a, long long start, uint32_t idx, Prefetch<T>& F,
+                                              bool nt) {
   const long long p = start + idx;
   F.idx = idx;
-  F.meta = a.meta[p];
-  F.kx = a.kx[p]; F.ky = a.ky[p]; F.kz = a.kz[p];
+  F.meta = sload(a.meta + p, nt);
+  F.kx = sload(a.kx + p, nt); F.ky = sload(a.ky + p, nt); F.kz = sload(a.kz + p, nt);
   F.x = (T)0; F.y = (T)0; F.z = (T)0;
-  if (DEV) { F.x = a.x[p]; F.y = a.y[p]; F.z = a.z[p]; }
+  if (DEV) { F.x = sload(a.x + p, nt); F.y = sload(a.y + p, nt); F.z = sload(a.z + p, nt); }
 }
 
 // The prefetched slot becomes the lane's electron if it holds a live one
@@ -533,6 +556,7 @@ __device__ __forceinline__ bool adopt_slot(const FlightArgs<T>& a, long long sta
   if (!(F.meta & kAlive)) { c.dead++; return false; }
   c.proc++;
   L.p = start + F.idx;
+  L.meta0 = F.meta;
   L.kx = F.kx; L.ky = F.ky; L.kz = F.kz;
   L.x = F.x; L.y = F.y; L.z = F.z;
   L.v = meta_valley(F.meta);
@@ -595,7 +619,11 @@ __device__ __forceinline__ void retire(const FlightArgs<T>& a, const LaneE<T>& L
   const long long p = L.p;
   a.kx[p] = L.kx; a.ky[p] = L.ky; a.kz[p] = L.kz;
   if (DEV) { a.x[p] = L.x; a.y[p] = L.y; a.z[p] = L.z; }
-  a.meta[p] = (L.id << 3) | (alive ? kAlive : 0u) | (uint32_t)L.v;
+  // the meta word changes only with the valley or at an exit: most
+  // electrons leave it as it is, which spares one of the seven scattered
+  // partial-line writes
+  const uint32_t meta = (L.id << 3) | (alive ? kAlive : 0u) | (uint32_t)L.v;
+  if (meta != L.meta0) a.meta[p] = meta;
   if (!alive) c.dead++;
   else if (DEV) {
     const int cell = cell_of(a.G, L.x, L.y, L.z);
@@ -687,6 +715,7 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
     const uint32_t hw = a.plan[td.inst].hw, rel = (uint32_t)(td.start - P.base);
     lim = hw > rel ? min(lim, hw - rel) : 0u;
   }
+  const bool nt = DEV && state_outgrows_cache(a);
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = (1ull << lane) - 1ull;
   Cnt c = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
@@ -720,7 +749,7 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_refill(FlightA
         if (want) {
           const uint32_t idx = base + (uint32_t)__popcll(m & lt);
           if (idx < lim) {
-            prefetch_slot<T, DEV>(a, td.start, idx, F);
+            prefetch_slot<T, DEV>(a, td.start, idx, F, nt);
             pf = true;
           } else {
             exhausted = true;
@@ -789,6 +818,7 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_persist(Flight
   const T gam[3] = {gp[0], gp[1], gp[2]};  // workgroup-uniform
   const uint32_t n_int = a.ctl[CTL_INTERVAL];
   const int r = (int)blockIdx.x - P.w0, nw = P.w1 - P.w0;
+  const bool nt = DEV && state_outgrows_cache(a);
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = (1ull << lane) - 1ull;
   const int cpt = (a.tile + a.chunk - 1) / a.chunk;  // chunks per tile
@@ -834,7 +864,7 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_persist(Flight
       const int rank = __popcll(m & lt);
       bool live = false;
       if (want && rank < take) {
-        live = take_slot<T, DEV>(a, P.base + cpos + rank, L, c);
+        live = take_slot<T, DEV>(a, P.base + cpos + rank, L, c, nt);
         has = live;
         ltile = ctile;
       }
