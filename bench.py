@@ -53,13 +53,15 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # 2.000 + WRITE_SIZE x 1.000, scales from a 1 GiB device copy).
 KERNELS = {0: "k_flight_refill<float,true>", 1: "k_flight<float,true>", 2: "k_flight_persist<float,true>"}
 KERNEL_COUNTERS = {
-    0: {"sources_digest": "d93c2d4f4f304f12", "valu_lane_ops_per_segment": 183.5, "hbm_bytes_per_segment": 13.53,
-        "active_lane_fraction": 0.536, "profile": "profiles/k_flight_refill_device1e7_counters.md",
-        "note": "counters at block 1024 / tile 8192; the active lanes include lanes without an electron, which run "
-                "the segment on stale state and drop it, so the useful fraction is an upper bound"},
-    2: {"sources_digest": "d93c2d4f4f304f12", "valu_lane_ops_per_segment": 172.8, "hbm_bytes_per_segment": 11.54,
-        "active_lane_fraction": 0.418, "profile": "profiles/k_flight_persist_device1e7_counters.md",
-        "note": "counters at block 1024 / tile 8192 (one resident workgroup of 1024 lanes per CU)"},
+    0: {"sources_digest": "fc66861e836725ba", "valu_lane_ops_per_segment": 183.9, "hbm_bytes_per_segment": 11.46,
+        "active_lane_fraction": 0.534, "profile": "profiles/k_flight_refill_device1e7_counters.md",
+        "note": "counters at block 1024 / tile 8192 over intervals 6-10 (9.9e6 electrons, state beyond the "
+                "Infinity Cache, non-temporal state loads); the active lanes include lanes without an electron, "
+                "which run the segment on stale state and drop it, so the useful fraction is an upper bound"},
+    2: {"sources_digest": "fc66861e836725ba", "valu_lane_ops_per_segment": 156.1, "hbm_bytes_per_segment": 8.82,
+        "active_lane_fraction": 0.460, "profile": "profiles/k_flight_persist_device1e7_counters.md",
+        "note": "counters at block 1024 / tile 8192 over intervals 6-10 (9.9e6 electrons, state beyond the "
+                "Infinity Cache, non-temporal state loads); one resident workgroup of 1024 lanes per CU"},
 }
 
 
