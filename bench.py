@@ -544,8 +544,9 @@ def main() -> int:
             refresh_avg_ms=prof["refresh_ms"] / max(1, prof["n_refresh"]),
             flight_share=prof["flight_ms"] / (prof["flight_ms"] + prof["refresh_ms"]),
             counters_current=fresh,
-            note="the kernel is bound by VALU issue, not by HBM: the ten sub-steps of an interval run in "
-                 "registers, so the state crosses HBM once per interval")
+            note="the ten sub-steps of an interval run in registers, so the state crosses HBM once per "
+                 "interval; the kernel is bound by memory latency while the state in use outgrows the "
+                 "Infinity Cache and by VALU issue once it fits, not by HBM bandwidth")
         if fresh:
             ops = kc["valu_lane_ops_per_segment"] * segs_launch
             roofline["valu_issue"] = dict(
