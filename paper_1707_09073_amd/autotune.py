@@ -59,8 +59,30 @@ def _key(ens) -> str:
     return f"{c['mode']}/{c.get('precision', 'fp64')}/{len(ens.cfgs)}/{cap}"
 
 
-def autotune(ens, candidates=None, trials: int = 5, cache_file: str | None = None, log=None) -> dict:
-    """Pick the fastest launch shape for `ens` (a gfmc.Ensemble) and apply it."""
+def _time_candidate(ens, blob, block, tile, variant, intervals, K):
+    """ms per interval of one shape over `intervals` flight intervals from
+    the checkpoint `blob` (None if the shape is refused)."""
+    ens.mc_restore(blob)
+    try:
+        ens.mc_set_launch(block, tile)
+    except Exception:
+        return None
+    ens.mc_set_variant(variant)
+    ens.mc_profile(True)
+    ens.mc_profile_read(reset=True)
+    ens.mc_step(intervals * K)
+    p = ens.mc_profile_read(reset=True)
+    ens.mc_profile(False)
+    return (p["flight_ms"] + p["refresh_ms"]) / max(1, p["n_flight"]), p["flight_ms"] / max(1, p["n_flight"])
+
+
+def autotune(ens, candidates=None, trials: int = 5, cache_file: str | None = None, log=None,
+             refine: int = 4) -> dict:
+    """Pick the fastest launch shape for `ens` (a gfmc.Ensemble) and apply it.
+    Every candidate is timed once over `trials` intervals; the `refine`
+    fastest are timed twice more over twice as many intervals, and the
+    lowest median of their three timings wins (a single short timing can
+    be off by several percent)."""
     key = _key(ens)
     if cache_file and os.path.exists(cache_file) and not _cache:
         try:
@@ -83,23 +105,28 @@ def autotune(ens, candidates=None, trials: int = 5, cache_file: str | None = Non
     blob = ens.mc_checkpoint()
     results = []
     for block, tile, variant in candidates:
-        ens.mc_restore(blob)
-        try:
-            ens.mc_set_launch(block, tile)
-        except Exception:
+        t = _time_candidate(ens, blob, block, tile, variant, trials, K)
+        if t is None:
             continue
-        ens.mc_set_variant(variant)
-        ens.mc_profile(True)
-        ens.mc_profile_read(reset=True)
-        ens.mc_step(trials * K)
-        p = ens.mc_profile_read(reset=True)
-        ens.mc_profile(False)
-        ms = (p["flight_ms"] + p["refresh_ms"]) / max(1, p["n_flight"])
-        results.append(dict(block=block, tile=tile, variant=variant, ms_per_interval=ms,
-                            flight_ms=p["flight_ms"] / max(1, p["n_flight"])))
+        ms, fl = t
+        results.append(dict(block=block, tile=tile, variant=variant, ms_per_interval=ms, flight_ms=fl))
         if log:
             log(f"  autotune block {block} tile {tile} variant {variant}: {ms:.3f} ms/interval")
-    best = min(results, key=lambda r: r["ms_per_interval"])
+    top = sorted(results, key=lambda r: r["ms_per_interval"])[:max(1, refine)]
+    if refine > 1:
+        for r in top:
+            times = [r["ms_per_interval"]]
+            for _ in range(2):
+                t = _time_candidate(ens, blob, r["block"], r["tile"], r["variant"], 2 * trials, K)
+                if t is not None:
+                    times.append(t[0])
+            r["refined_ms_per_interval"] = sorted(times)[len(times) // 2]
+            if log:
+                log(f"  autotune refine block {r['block']} tile {r['tile']} variant {r['variant']}: "
+                    f"{', '.join(f'{x:.3f}' for x in times)} ms/interval")
+        best = min(top, key=lambda r: r["refined_ms_per_interval"])
+    else:
+        best = top[0]
     ens.mc_restore(blob)
     ens.mc_set_launch(best["block"], best["tile"])
     ens.mc_set_variant(best["variant"])
