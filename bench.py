@@ -65,15 +65,37 @@ KERNEL_COUNTERS = {
 }
 
 
-def _kernel_digest() -> str:
-    """Digest of the particle-kernel sources (the kernels and the device
-    arithmetic they use; the refresh kernels live in a header of their own)
-    with comments and blank lines removed, so that a comment edit does not
-    invalidate the counters."""
+# The phonon packet kernel's counters (profiles/k_ph_packets_wire_trace.md),
+# valid for the phonon.hip whose digest is given: VALU lane-instructions per
+# flight segment and the share of active lanes.
+PH_COUNTERS = {"sources_digest": "2bce4086be64c092", "valu_lane_ops_per_segment": 778.7, "active_lane_fraction": 0.359,
+               "profile": "profiles/k_ph_packets_wire_trace.md"}
+
+
+def _ph_issue(segs_launch: float, avg_ms: float):
+    """VALU issue of the packet kernel from its counters (None once
+    phonon.hip differs from the sources they were taken on): the kernel is
+    bound by divergent VALU issue, not by its algorithmic operations."""
+    if _kernel_digest(("phonon.hip",)) != PH_COUNTERS["sources_digest"]:
+        return None
+    ops = PH_COUNTERS["valu_lane_ops_per_segment"] * segs_launch
+    rate = ops / (avg_ms * 1e-3)
+    return dict(lane_instructions_per_launch=ops, achieved=rate / 1e12, peak=ALU_PEAK_LANE_OPS / 1e12,
+                unit="T lane-instr/s", frac_issue=rate / ALU_PEAK_LANE_OPS,
+                active_lane_fraction=PH_COUNTERS["active_lane_fraction"],
+                frac_useful=rate * PH_COUNTERS["active_lane_fraction"] / ALU_PEAK_LANE_OPS,
+                profile=PH_COUNTERS["profile"])
+
+
+def _kernel_digest(files=("gfmc_kernels.h", "gfmc_device.h")) -> str:
+    """Digest of kernel sources (by default the particle kernels and the
+    device arithmetic they use; the refresh kernels live in a header of their
+    own) with comments and blank lines removed, so that a comment edit does
+    not invalidate the counters."""
     import hashlib
     import re
     h = []
-    for f in ("gfmc_kernels.h", "gfmc_device.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1707_09073_amd", "csrc", f)) as fh:
             code = [re.sub(r"//.*$", "", line).rstrip() for line in fh]
         h.append(hashlib.sha256("\n".join(l for l in code if l.strip()).encode()).hexdigest())
@@ -432,7 +454,8 @@ def main() -> int:
                          "algorithmic_flops_per_launch": flops, "flops_per_unit": PH_FLOPS,
                          "avg_launch_ms": r["avg_ms"],
                          "note": "launch time includes the one-thread set-up and the temperature kernels; "
-                                 "divisions and transcendentals count one operation each"}}), flush=True)
+                                 "divisions and transcendentals count one operation each",
+                         "valu_issue": _ph_issue(segs_launch, r["avg_ms"])}}), flush=True)
         return 0
     if args.workload == "fourier":
         r = fourier_chip(args)
