@@ -51,7 +51,8 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # digest is given: VALU lane-instructions issued per free-flight segment
 # (SQ_INSTS_VALU x 64 / segments) and HBM bytes per segment (FETCH_SIZE x
 # 2.000 + WRITE_SIZE x 1.000, scales from a 1 GiB device copy).
-KERNELS = {0: "k_flight_refill<float,true>", 1: "k_flight<float,true>", 2: "k_flight_persist<float,true>"}
+KERNELS = {0: "k_flight_refill<float,true>", 1: "k_flight<float,true>", 2: "k_flight_persist<float,true>",
+           3: "k_flight_persist_staged<float,true>"}
 KERNEL_COUNTERS = {
     0: {"sources_digest": "fc66861e836725ba", "valu_lane_ops_per_segment": 183.9, "hbm_bytes_per_segment": 11.46,
         "active_lane_fraction": 0.534, "profile": "profiles/k_flight_refill_device1e7_counters.md",

@@ -271,13 +271,14 @@ int mc_read_fields(mc_ctx *ctx, int instance, double *h_phi, double *h_field, ui
 int mc_read_tables(mc_ctx *ctx, int instance, double *h_shape, double *h_k4, double *h_factors, double *h_gamma);
 
 /* Launch shape of the particle kernel: workgroup size (64..1024, multiple of
- * 64; above 512 only for FP32 state and variants 0 and 2, else mc_step
+ * 64; above 512 only for FP32 state and variants 0, 2 and 3, else mc_step
  * returns MC_E_ARG) and tile
  * size (particles per tile, multiple of the workgroup size).
- * Variants 0 and 1 launch one workgroup per tile; variant 2 launches as many
- * workgroups as the GPU holds at once and uses the tiles only for the contact
- * refill's free-slot counts.  Results do not depend on the shape.  MC_E_ARG
- * if unsupported.  n_tiles reports the tiles, not the variant-2 grid. */
+ * Variants 0 and 1 launch one workgroup per tile; variants 2 and 3 launch as
+ * many workgroups as the GPU holds at once and use the tiles only for the
+ * contact refill's free-slot counts.  Results do not depend on the shape.
+ * MC_E_ARG if unsupported.  n_tiles reports the tiles, not the persistent
+ * grid. */
 int mc_set_launch(mc_ctx *ctx, int block, int tile);
 int mc_get_launch(const mc_ctx *ctx, int *block, int *tile, int *n_tiles);
 
@@ -304,10 +305,13 @@ int mc_occupancy(mc_ctx *ctx, int block, int *wg_per_cu, int *n_cu);
  * holds at once, each bound to one instance in proportion to its slots and
  * owning every nw-th chunk of 256 slots of it, so each samples the whole slot
  * range and the launch is balanced however the live electrons are spread over
- * the slots).  Results are identical up to the compiler's floating-point
- * contraction choices in each variant (variants 0 and 2 share the
- * per-electron code).  MC_E_ARG for another value, MC_E_HIP if the occupancy
- * query for variant 2 fails. */
+ * the slots), 3 = persistent with staged slots (as 2; each wavefront copies
+ * the next 64 slots of its chunks into LDS while its lanes take electrons from
+ * the current 64, which pays off while the state outgrows the Infinity
+ * Cache).  Results are identical up to the compiler's floating-point
+ * contraction choices in each variant (variants 0, 2 and 3 share the
+ * per-electron code and give the same bits).  MC_E_ARG for another value,
+ * MC_E_HIP if the occupancy query for variant 2 or 3 fails. */
 int mc_set_variant(mc_ctx *ctx, int variant);
 
 /* Replay each interval from a captured hipGraph (1) or launch eagerly (0). */

@@ -14,15 +14,17 @@ import os
 # (workgroup size, tile size, kernel variant).  Tile sizes step finely
 # because the last round of resident workgroups is partly idle: the best
 # tile is one whose tile count is just under a multiple of the resident count.
-# The persistent variant (2) has no rounds: its grid is the resident count
-# (one 1024-lane workgroup per compute unit, or two of 512), and its tile
-# size only sets the contact refill's free-slot blocks.
+# The persistent variants (2, and 3 with staged slots) have no rounds: their
+# grid is the resident count (one 1024-lane workgroup per compute unit, or
+# two of 512), and their tile size only sets the contact refill's free-slot
+# blocks.
 DEFAULT_CANDIDATES = [
     (256, 1536, 0), (256, 2048, 0), (256, 2560, 0), (256, 3072, 0), (256, 4096, 0),
     (256, 5120, 0), (256, 6144, 0), (256, 8192, 0),
     (512, 2048, 0), (512, 2560, 0), (512, 3072, 0), (512, 4096, 0), (512, 8192, 0), (384, 3072, 0), (384, 6144, 0),
     (128, 2048, 0), (256, 4096, 1),
     (1024, 4096, 2), (1024, 8192, 2), (512, 4096, 2),
+    (1024, 4096, 3), (1024, 8192, 3), (512, 4096, 3),
 ]
 # FP32 state only: 1024-lane workgroups (16 wavefronts sharing one refill
 # queue; FP64 state needs more registers than they leave each lane)

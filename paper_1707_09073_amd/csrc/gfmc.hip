@@ -276,9 +276,9 @@ int upload_tiles(mc_ctx* c) {
     tot += I.nchunk;
   }
   int wg = c->n_inst;
-  if (c->variant == 2) {
+  if (c->variant >= 2) {
     int per = 0, ncu = 0, rc;
-    if ((rc = flight_occupancy(c, 2, c->block, &per, &ncu)) != MC_OK) return rc;
+    if ((rc = flight_occupancy(c, c->variant, c->block, &per, &ncu)) != MC_OK) return rc;
     if (per < 1) return fail(c, MC_E_ARG, "persistent kernel does not fit this workgroup size");
     wg = std::max(c->n_inst, std::min(per * ncu, c->max_tiles));
   }
@@ -461,15 +461,21 @@ hipEvent_t prof_event(mc_ctx* c) {
   return c->ev_pool[c->ev_used++];
 }
 
-size_t flight_lds_bytes(const mc_ctx* c, int variant) {
-  (void)variant;  // every lane-refill variant keeps the same LDS histogram
-  return sizeof(uint32_t) * flight_lds_words(c->ncell);
+// LDS of a particle-kernel workgroup: the histogram (every variant), and
+// for variant 3 each wavefront's two staged pieces of slots
+size_t flight_lds_bytes(const mc_ctx* c, int variant, int block) {
+  size_t b = sizeof(uint32_t) * flight_lds_words(c->ncell);
+  if (variant == 3) b += (size_t)(block / 64) * 2 * (c->f32 ? piece_bytes<float>() : piece_bytes<double>());
+  return b;
 }
 
 template <typename T>
 void launch_flight(mc_ctx* c, const FlightArgs<T>& a) {
-  const size_t lds = flight_lds_bytes(c, c->variant);
-  if (c->variant == 2) {
+  const size_t lds = flight_lds_bytes(c, c->variant, c->block);
+  if (c->variant == 3) {
+    if (c->dev) k_flight_persist_staged<T, true><<<c->n_wg, c->block, lds, c->st>>>(a);
+    else k_flight_persist_staged<T, false><<<c->n_wg, c->block, lds, c->st>>>(a);
+  } else if (c->variant == 2) {
     if (c->dev) k_flight_persist<T, true><<<c->n_wg, c->block, lds, c->st>>>(a);
     else k_flight_persist<T, false><<<c->n_wg, c->block, lds, c->st>>>(a);
   } else if (c->variant == 0) {
@@ -483,7 +489,10 @@ void launch_flight(mc_ctx* c, const FlightArgs<T>& a) {
 
 template <typename T>
 hipError_t occupancy_of(const mc_ctx* c, int variant, int block, int* n) {
-  const size_t lds = flight_lds_bytes(c, variant);
+  const size_t lds = flight_lds_bytes(c, variant, block);
+  if (variant == 3)
+    return c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_flight_persist_staged<T, true>, block, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_flight_persist_staged<T, false>, block, lds);
   if (variant == 2)
     return c->dev ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_flight_persist<T, true>, block, lds)
                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_flight_persist<T, false>, block, lds);
@@ -590,6 +599,22 @@ int mc_init(mc_ctx** out, const mc_config* cfgs, int n, void* d_ws, size_t ws_by
   c->ws_bytes = ws_bytes;
   c->o = o;
   c->nb = cfgs[0].n_bins;
+  // variant 3's staged slot pieces take its LDS above the default 64 KB of
+  // dynamic shared memory
+  {
+    const int lds_max = 160 * 1024;
+    if (hipFuncSetAttribute((const void*)k_flight_persist_staged<float, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_flight_persist_staged<float, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_flight_persist_staged<double, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_flight_persist_staged<double, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) != hipSuccess) {
+      delete c;
+      return MC_E_HIP;
+    }
+  }
   if (c->dev) {
     c->nx = cfgs[0].n_cells[0]; c->ny = cfgs[0].n_cells[1]; c->nz = cfgs[0].n_cells[2];
   }
@@ -1135,7 +1160,7 @@ int mc_set_launch(mc_ctx* c, int block, int tile) {
 }
 
 int mc_set_variant(mc_ctx* c, int variant) {
-  if (!c || variant < 0 || variant > 2) return fail(c, MC_E_ARG, "unknown kernel variant");
+  if (!c || variant < 0 || variant > 3) return fail(c, MC_E_ARG, "unknown kernel variant");
   c->variant = variant;
   drop_graph(c);
   return upload_tiles(c);

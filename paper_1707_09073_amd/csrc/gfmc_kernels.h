@@ -889,4 +889,208 @@ __global__ void __launch_bounds__(max_flight_block<T>()) k_flight_persist(Flight
                        a.counters + (size_t)inst * kNCnt, nullptr);
 }
 
+
+// Slot state staged in LDS (variant 3, k_flight_persist_staged): each
+// wavefront keeps two pieces of kPiece consecutive slots of its chunks, the
+// one its lanes take electrons from and the next, whose loads go straight
+// from global memory into LDS (global_load_lds, four bytes per lane, no
+// registers; non-temporal) while the current one is used.  A refill then
+// reads LDS, and the state's memory latency is covered by the work on the
+// current piece.  This pays off while the state in use outgrows the
+// Infinity Cache and every refill of variant 2 waits on HBM; while the
+// state fits, variant 2 is faster, so the variants are timed and chosen.
+// Piece layout: kx, ky, kz, x, y, z (kPiece values of T each), then the
+// meta words.
+constexpr int kPiece = 64;
+template <typename T>
+__host__ __device__ constexpr int piece_bytes() { return kPiece * (6 * (int)sizeof(T) + 4); }
+typedef __attribute__((address_space(3))) void flight_lds_t;
+typedef __attribute__((address_space(1))) void flight_glb_t;
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima): the staged
+// loads have landed in LDS
+__device__ __forceinline__ void wait_staged() {
+  __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8));
+  asm volatile("" ::: "memory");  // no LDS read of the staged piece moves above the wait
+}
+
+// Issue the non-temporal copy of cnt (1..kPiece) elements of E bytes from
+// src into dst (LDS, wavefront-uniform): pass k moves bytes
+// [256 k, 256 k + 256), lane l the four at 256 k + 4 l.  Lanes past the
+// piece's end read its last four bytes instead (in bounds) and write LDS
+// bytes that are never read.
+template <int E>
+__device__ __forceinline__ void stage_array(const void* src, char* dst, int cnt, int lane) {
+  const int last = cnt * E - 4;
+#pragma unroll
+  for (int k = 0; k < E / 4; ++k) {
+    const int b = min(256 * k + 4 * lane, last);
+    __builtin_amdgcn_global_load_lds((flight_glb_t*)((const char*)src + b), (flight_lds_t*)(dst + 256 * k), 4, 0,
+                                     2);
+  }
+}
+
+template <typename T, bool DEV>
+__device__ __forceinline__ void stage_piece(const FlightArgs<T>& a, long long first, int cnt, char* buf, int lane) {
+  constexpr int A = kPiece * (int)sizeof(T);
+  stage_array<sizeof(T)>(a.kx + first, buf, cnt, lane);
+  stage_array<sizeof(T)>(a.ky + first, buf + A, cnt, lane);
+  stage_array<sizeof(T)>(a.kz + first, buf + 2 * A, cnt, lane);
+  if (DEV) {
+    stage_array<sizeof(T)>(a.x + first, buf + 3 * A, cnt, lane);
+    stage_array<sizeof(T)>(a.y + first, buf + 4 * A, cnt, lane);
+    stage_array<sizeof(T)>(a.z + first, buf + 5 * A, cnt, lane);
+  }
+  stage_array<4>(a.meta + first, buf + 6 * A, cnt, lane);
+}
+
+// Slot i of a staged piece becomes the lane's electron if it holds a live
+// one (a free slot is counted and dropped), as take_slot would load it.
+template <typename T, bool DEV>
+__device__ __forceinline__ bool take_staged(const FlightArgs<T>& a, const char* buf, int i, long long p, LaneE<T>& L,
+                                            Cnt& c) {
+  constexpr int A = kPiece * (int)sizeof(T);
+  const uint32_t meta = ((const uint32_t*)(buf + 6 * A))[i];
+  if (!(meta & kAlive)) { c.dead++; return false; }
+  c.proc++;
+  const T* v = (const T*)buf;
+  L.p = p;
+  L.meta0 = meta;
+  L.kx = v[i]; L.ky = v[kPiece + i]; L.kz = v[2 * kPiece + i];
+  L.x = (T)0; L.y = (T)0; L.z = (T)0;
+  if (DEV) { L.x = v[3 * kPiece + i]; L.y = v[4 * kPiece + i]; L.z = v[5 * kPiece + i]; }
+  L.v = meta_valley(meta);
+  L.id = meta_id(meta);
+  L.j = 0;
+  L.t = (T)0;
+  L.E = energy(a.M, L.v, L.kx, L.ky, L.kz);
+  return true;
+}
+
+// Persistent variant with staged slots (variant 3): the workgroups, chunks
+// and counting of k_flight_persist; its wavefronts cut each chunk into
+// pieces of kPiece slots and stage them one ahead.  Per-electron arithmetic
+// and random-number use are those of k_flight_refill.
+template <typename T, bool DEV>
+__global__ void __launch_bounds__(max_flight_block<T>()) k_flight_persist_staged(FlightArgs<T> a) {
+  extern __shared__ uint32_t sh[];
+  const int ncell = DEV ? a.G.ncell : 1;
+  uint32_t* sh_dep = sh;
+  uint32_t* sh_heat = sh + dep_words(ncell);
+  uint32_t* sh_real = sh_heat + 4 * ncell;
+  uint32_t* sh_misc = sh_real + 32;
+  uint32_t* sh_claim = sh_misc + 8;
+  const int nsh = flight_lds_words(ncell);
+  for (int i = threadIdx.x; i < nsh; i += blockDim.x) sh[i] = 0u;
+  __syncthreads();
+  const int inst = a.wg_inst[blockIdx.x];
+  const InstParams P = a.ip[inst];
+  const T* fac = a.fac + (size_t)inst * ncell * kFRow;
+  const T* field = a.field + (size_t)inst * ncell * 4;
+  const T* gp = a.gamma + inst * 4;
+  const T gam[3] = {gp[0], gp[1], gp[2]};  // workgroup-uniform
+  const uint32_t n_int = a.ctl[CTL_INTERVAL];
+  const int r = (int)blockIdx.x - P.w0, nw = P.w1 - P.w0;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const int cpt = (a.tile + a.chunk - 1) / a.chunk;  // chunks per tile
+  // slots at or above the instance's bound of slots in use are free: they
+  // are counted, not read
+  const int hw = DEV ? (int)min(a.plan[inst].hw, (uint32_t)P.cap) : P.cap;
+  Cnt c = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  bool guard_hit = false, nan_hit = false;
+  bool has = false;
+  // this wavefront's two staging buffers, after the histogram
+  char* stage = (char*)(sh + nsh) + (size_t)(threadIdx.x >> 6) * 2 * piece_bytes<T>();
+  // wavefront-uniform: no chunks left; the chunk being cut into pieces,
+  // [cpos, cend) of tile ctile; the current piece [ppos, pend) in buffer b,
+  // taken up to pcur, of tile ptile; the next piece [npos, nend) of tile
+  // ntile in flight into buffer b ^ 1 (nvalid); free slots met in the
+  // current piece's tile so far
+  bool exhausted = false;
+  int cpos = 0, cend = 0, ctile = 0;
+  int b = 0, ppos = 0, pend = 0, pcur = 0, ptile = 0;
+  bool nvalid = false;
+  int npos = 0, nend = 0, ntile = 0;
+  uint32_t dacc = 0;
+  int ltile = 0;  // tile of the lane's electron
+  LaneE<T> L = {};
+  uint32_t rc[kNM];
+#pragma unroll
+  for (int q = 0; q < kNM; ++q) rc[q] = 0u;
+  // the next piece of the wavefront's chunks (claiming chunks as they run
+  // out), its loads issued into buffer b ^ 1
+  auto stage_next = [&]() {
+    nvalid = false;
+    while (cpos >= cend) {
+      uint32_t i = 0;
+      if (lane == 0) i = atomicAdd(sh_claim, 1u);
+      i = __builtin_amdgcn_readfirstlane(i);
+      const uint32_t k = (uint32_t)r + i * (uint32_t)nw;  // < nchunk + nw: no wrap
+      if (k >= (uint32_t)P.nchunk) return;
+      const int t = (int)(k / (uint32_t)cpt), sub = (int)(k % (uint32_t)cpt);
+      cpos = t * a.tile + sub * a.chunk;
+      cend = min(cpos + a.chunk, min((t + 1) * a.tile, P.cap));
+      ctile = P.t0 + t;
+      if (cend > hw) {
+        if (DEV && lane == 0) atomicAdd(a.tile_dead + ctile, (uint32_t)(cend - max(cpos, hw)));
+        cend = max(cpos, hw);
+      }
+    }
+    npos = cpos;
+    nend = min(cpos + kPiece, cend);
+    ntile = ctile;
+    cpos = nend;
+    stage_piece<T, DEV>(a, P.base + npos, nend - npos, stage + (b ^ 1) * piece_bytes<T>(), lane);
+    nvalid = true;
+  };
+  stage_next();
+  for (;;) {
+    bool want = !has && !exhausted;
+    unsigned long long m = __ballot(want);
+    while (m) {
+      if (pcur >= pend) {
+        // the current piece is used up: move to the staged one and stage
+        // the piece after it
+        if (!nvalid) { exhausted = true; break; }
+        wait_staged();
+        if (DEV && ptile != ntile) {
+          if (lane == 0 && dacc) atomicAdd(a.tile_dead + ptile, dacc);
+          dacc = 0;
+        }
+        b ^= 1;
+        ppos = npos; pend = nend; pcur = npos; ptile = ntile;
+        stage_next();
+      }
+      const int n = __popcll(m);
+      const int take = min(n, pend - pcur);
+      const int rank = __popcll(m & lt);
+      bool live = false;
+      if (want && rank < take) {
+        live = take_staged<T, DEV>(a, stage + b * piece_bytes<T>(), pcur + rank - ppos, P.base + pcur + rank, L, c);
+        has = live;
+        ltile = ptile;
+      }
+      if (DEV) dacc += (uint32_t)__popcll(__ballot(want && rank < take && !live));
+      pcur += take;
+      want = !has;
+      m = __ballot(want);
+    }
+    if (!__any(has)) break;
+    if (has) {
+      const int rr = lane_segment<T, DEV>(a, P, fac, field, gam, n_int, ncell, L, c, sh_heat, sh_real, rc, guard_hit);
+      if (rr > -2) {
+        retire<T, DEV>(a, L, rr, c, sh_dep, true, nan_hit);
+        if (DEV && rr >= 0) atomicAdd(a.tile_dead + ltile, 1u);
+        has = false;
+      }
+    }
+  }
+  if (DEV && lane == 0 && dacc) atomicAdd(a.tile_dead + ptile, dacc);
+  if (guard_hit) set_flag(a.flags, inst, -4);
+  if (nan_hit) set_flag(a.flags, inst, -6);
+  flush_workgroup<DEV>(c, rc, sh_dep, true, sh_heat, sh_real, sh_misc, ncell, a.acc + (size_t)inst * 5 * ncell,
+                       a.counters + (size_t)inst * kNCnt, nullptr);
+}
+
 }  // namespace gfmc

@@ -27,7 +27,7 @@ REL = 1e-10
 K_FLOOR = 0.1  # 1/nm, as in the smaller parity tests
 QE = 1.602176634e-19
 BLOCK, TILE = 256, 4096                   # FP64 state
-FP32_SHAPES = [(512, 3584, 0), (512, 5120, 0), (1024, 20480, 0), (1024, 8192, 2)]
+FP32_SHAPES = [(512, 3584, 0), (512, 5120, 0), (1024, 20480, 0), (1024, 8192, 0), (1024, 8192, 2), (1024, 8192, 3)]
 
 
 def _by_id(p):

@@ -160,7 +160,7 @@ def test_batched_instances_match_one_oracle_each(G, oracle_mod):
         assert np.abs(phi - pho).max() <= REL * np.abs(pho).max()
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 2, 3])
 def test_energies_above_the_table_top(G, oracle_mod, variant):
     """500 kV/cm: a few percent of the selections find the electron above the
     3 eV table top (clamped to the last bin and counted).  Electrons and

@@ -98,7 +98,7 @@ def test_initial_state_matches_oracle(G, oracle_mod, mode):
         assert np.abs(F - Fo).max() <= 1e-9 * np.abs(Fo).max()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_bulk_fp64_per_particle_parity(G, oracle_mod, variant):
     """Bulk GaN, 10 kV/cm along c, 1e17 cm^-3, 300 K, 1 fs steps."""
     cfg = W.bulk_config(n_particles=10000, substeps=1)
@@ -137,7 +137,7 @@ def _device_small(n=20000, Vds=5.0, Vgs=0.0, prec="fp64", cells=(100, 3, 6), L=(
     return W.device_config(n_particles=n, precision=prec, Vds=Vds, Vgs=Vgs, n_cells=cells, L_nm=L)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_device_fp64_per_particle_parity(G, oracle_mod, variant):
     """Half-nanowire device, 3x6x100 subcells, Vds = 5 V: particles, deposit,
     heat counts, contacts and the Poisson field after 30 refreshes."""
@@ -162,7 +162,7 @@ def test_device_fp64_per_particle_parity(G, oracle_mod, variant):
     _say("device max rel err k", ek, "r", er)
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 2, 3])
 def test_device_fp64_parity_gated_and_ragged(G, oracle_mod, variant):
     """Negative gate bias, a grid of 37x2x5 subcells and a capacity that is
     not a multiple of the tile (ragged last tile, and for the persistent
@@ -195,7 +195,7 @@ def test_tiny_bulk_ensembles_match_oracle(G, oracle_mod, n, field, variant):
     _compare_counts(e.mc_tally(), o.counts())
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 2, 3])
 def test_sparse_device_matches_oracle(G, oracle_mod, variant):
     """One superparticle per subcell on average (the contact refill then tops
     each contact subcell up to about one electron)."""
@@ -212,7 +212,7 @@ def test_sparse_device_matches_oracle(G, oracle_mod, variant):
     assert np.array_equal(m["heat4"], heat_o) and np.array_equal(m["dens_sum"], dens_o)
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 2, 3])
 def test_compaction_closes_holes_and_keeps_order(G, oracle_mod, variant):
     """The live electrons spread over the whole capacity (holes between them)
     on both sides; after one interval the GPU has compacted its slots: every
@@ -254,7 +254,8 @@ def test_launch_shape_and_graph_do_not_change_results(G):
     for block, tile, graph, variant in ((256, 8192, False, 0), (64, 1024, False, 0), (128, 4096, True, 0),
                                         (256, 2048, True, 0), (64, 1024, False, 2), (320, 4160, False, 2),
                                         (512, 4096, True, 2), (1024, 4096, False, 2), (1024, 8192, True, 0),
-                                        (512, 5120, False, 0)):
+                                        (512, 5120, False, 0), (1024, 8192, False, 3), (512, 4096, True, 3),
+                                        (128, 2048, False, 3)):
         _say("launch shape", block, tile, "graph" if graph else "eager", "variant", variant)
         e = G.Ensemble(cfg)
         e.mc_set_launch(block, tile)
@@ -285,7 +286,7 @@ def test_shape_and_variant_changes_mid_run_do_not_change_results(G):
     a.mc_set_launch(512, 5120)
     a.mc_step(600)
     b = G.Ensemble(cfg)
-    for block, tile, variant in ((256, 2048, 2), (1024, 8192, 0), (512, 4096, 0)):
+    for block, tile, variant in ((256, 2048, 2), (512, 4096, 3), (1024, 8192, 0)):
         _say("mid-run shape", block, tile, "variant", variant)
         b.mc_set_launch(block, tile)
         b.mc_set_variant(variant)
@@ -299,7 +300,7 @@ def test_shape_and_variant_changes_mid_run_do_not_change_results(G):
     ma, mb = a.mc_maps(), b.mc_maps()
     assert np.array_equal(ma["heat4"], mb["heat4"]) and np.array_equal(ma["dens_sum"], mb["dens_sum"])
 
-@pytest.mark.parametrize("n_inst,variant", [(3, 0), (3, 2), (18, 0)])
+@pytest.mark.parametrize("n_inst,variant", [(3, 0), (3, 2), (3, 3), (18, 0)])
 def test_batched_instances_equal_separate_runs(G, n_inst, variant):
     """Bias points in one context equal separate runs, per particle; with the
     persistent queue each instance has its own share of the workgroups and
