@@ -387,7 +387,8 @@ def main() -> int:
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--graph", action="store_true", help="replay intervals from a hipGraph (no per-kernel timing)")
     ap.add_argument("--variant", type=int, default=0,
-                    help="particle kernel: 0 lane refill per tile, 1 one electron per lane, 2 persistent")
+                    help="particle kernel: 0 lane refill per tile, 1 one electron per lane, 2 persistent, "
+                         "3 persistent with staged slots")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default (or given) launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sg-batch", type=int, default=4096, help="batch of the surrogate workload")
