@@ -95,3 +95,44 @@ def test_unsupported_shapes_are_skipped_not_fatal(precision):
     r = A.autotune(e, trials=1)
     assert r["trials"], "some shape must be usable"
     assert all(t["tile"] % t["block"] == 0 for t in r["trials"])
+
+
+class NoisyEnsemble(FakeEnsemble):
+    """Per shape, a list of ms-per-interval figures, one taken per timing
+    (the last figure repeats)."""
+
+    def __init__(self, precision, seq):
+        super().__init__(precision)
+        self.seq = {k: list(v) for k, v in seq.items()}
+        self.timings = {}
+
+    def mc_step(self, n):
+        s = self.seq.get(self.shape)
+        if s is not None:
+            i = self.timings.get(self.shape, 0)
+            self.timings[self.shape] = i + 1
+            self.times[self.shape] = s[min(i, len(s) - 1)]
+        super().mc_step(n)
+
+
+def test_refinement_takes_the_median_not_one_lucky_timing():
+    A._cache.clear()
+    lucky = (1024, 8192, 2)        # fast once, slow on both re-timings
+    steady = (1024, 8192, 3)
+    e = NoisyEnsemble("fp32", {lucky: [0.40, 0.60, 0.62], steady: [0.45, 0.46, 0.44]})
+    before = e.state
+    r = A.autotune(e, candidates=[lucky, steady, (512, 4096, 0)], trials=2, refine=2)
+    assert (r["block"], r["tile"], r["variant"]) == steady
+    assert r["refined_ms_per_interval"] == pytest.approx(0.45)
+    assert e.timings[lucky] == 3 and e.timings[steady] == 3
+    # the third candidate (1.0 ms) is outside the top two: timed once only
+    assert e.state == before and e.shape == steady
+
+
+def test_refinement_off_keeps_the_first_timing():
+    A._cache.clear()
+    lucky, steady = (1024, 8192, 2), (1024, 8192, 3)
+    e = NoisyEnsemble("fp32", {lucky: [0.40, 0.60, 0.62], steady: [0.45, 0.46, 0.44]})
+    r = A.autotune(e, candidates=[lucky, steady], trials=2, refine=1)
+    assert (r["block"], r["tile"], r["variant"]) == lucky
+    assert e.timings[lucky] == 1 and e.timings[steady] == 1
