@@ -27,7 +27,7 @@ template <int TM> constexpr int slab_depth() { return TM == 32 ? 128 : 64; }
 template <int KP>
 __device__ __forceinline__ int lds_at(int r, int c) { return r * KP + ((c ^ ((r >> 3) & 7)) << 3); }
 
-enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
+enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3, EPI_BIAS_GELU_ONLY = 4 };
 
 struct GemmArgs {
   const bf16* A;
@@ -66,7 +66,8 @@ __device__ __forceinline__ uint4 load_chunk(const bf16* p, long ld, int r, int c
 // The 32 x 32 block of C at (r0, c0) held by one wavefront's accumulator
 // (lane l, item j: row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32), with
 // the product's epilogue: store, + bias, + bias and GELU (pre-activation in
-// FP32 and activation in BF16), or times the GELU derivative.
+// FP32 and activation in BF16, or, for passes without a backward, the
+// activation alone), or times the GELU derivative.
 template <int EPI>
 __device__ __forceinline__ void epilogue(const GemmArgs& g, const f32x16& acc, int r0, int c0, int lane) {
 #pragma unroll
@@ -83,6 +84,8 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, const f32x16& acc, i
       const float z = v + g.bias[col];
       g.Cf[(long)row * g.ldcf + col] = z;
       g.Cb[(long)row * g.ldcb + col] = (bf16)gelu(z);
+    } else if (EPI == EPI_BIAS_GELU_ONLY) {
+      g.Cb[(long)row * g.ldcb + col] = (bf16)gelu(v + g.bias[col]);
     } else {
       g.Cb[(long)row * g.ldcb + col] = (bf16)(v * gelu_grad(g.Z[(long)row * g.ldz + col]));
     }
@@ -209,13 +212,14 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 // Products whose operands are both K-contiguous (A [M][K], B [N][K]: the
 // forward products and dX): the K slabs go from global memory straight into
 // LDS (global_load_lds_dwordx4: each lane's 16 bytes land at the wavefront's
-// LDS base + 16 x lane), so no registers stage them; the next slab's copy is
-// in flight while the matrix cores work on the current one (two stages per
-// workgroup, 64 KB, so two workgroups per compute unit share its LDS).
-// These products are bound by how fast operand tiles reach the compute
-// units from L2 (about 14 B per clock per CU measured), so the tiles are as
-// large as the product allows while every compute unit still gets work
-// (256 x 256, 128 x 128 or 128 x 64), and each XCD takes a
+// LDS base + 16 x lane), so no registers stage them; the next slabs' copies
+// are in flight while the matrix cores work on the current one (S stages per
+// workgroup).  These products are bound by how fast operand tiles reach the
+// compute units from L2 (about 14 B per clock per CU measured), a rate that
+// grows with the wavefronts issuing copies and not with the stages in flight,
+// so the tiles are as large as the product allows while every compute unit
+// still gets work (256 x 256, 128 x 128 or 128 x 64), with up to 16
+// wavefronts per tile, and each XCD takes a
 // contiguous eighth of the tiles (a few row tiles by all column tiles), so
 // that its operands stay in its own L2.  Rows and K chunks outside the
 // matrices read a 16-byte block of zeros.  K must be a multiple of 8.
@@ -231,11 +235,11 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
-constexpr int kLdsBK = 64, kLdsStages = 2;
+constexpr int kLdsBK = 64;
 constexpr int kLdsChunks = kLdsBK / 8;                   // 16-byte chunks per slab row
-// bytes of one stage (an A slab of BM rows and a B slab of BN rows) and of a
-// workgroup's LDS
-template <int BM, int BN> constexpr int lds_bytes() { return kLdsStages * (BM + BN) * kLdsChunks * 16; }
+// bytes of a workgroup's LDS: S stages, each an A slab of BM rows and a B
+// slab of BN rows
+template <int BM, int BN, int S = 2> constexpr int lds_bytes() { return S * (BM + BN) * kLdsChunks * 16; }
 
 // LDS position (16-byte units) of chunk c of slab row r: chunks permuted by
 // r & 7 within the row, so the fragment reads of 8 consecutive rows at one
@@ -247,14 +251,18 @@ __host__ __device__ inline int lds_tiles(int M, int N, int BM, int BN) {
 }
 
 // Tile BM x BN with W wavefronts: 2 rows of W / 2 wavefronts, each
-// BM / 2 x 2 BN / W, in 32 x 32 MFMA blocks.
-template <int EPI, int BM, int BN, int W>
+// BM / 2 x 2 BN / W, in 32 x 32 MFMA blocks.  S stages of LDS: while the
+// matrix cores work on slab s, the copies of slabs s + 1 .. s + S - 1 are in
+// flight.
+template <int EPI, int BM, int BN, int W, int S = 2>
 __global__ void __launch_bounds__(64 * W) k_gemm_lds(GemmArgs g) {
   constexpr int WM = BM / 2, WN = 2 * BN / W;      // a wavefront's share of the tile
   constexpr int MB = WM / 32, NB = WN / 32;        // its 32 x 32 MFMA blocks
   constexpr int SA = BM * kLdsChunks * 16, SB = BN * kLdsChunks * 16;
   constexpr int BA = BM / 8 / W, BB = BN / 8 / W;  // 1 KB blocks per wavefront and stage
+  constexpr int LB = BA + BB;                      // copies per wavefront and stage
   static_assert(BA * W * 8 == BM && BB * W * 8 == BN, "slab rows must split evenly over the wavefronts");
+  static_assert(S >= 2 && (S - 2) * LB <= 63, "vmcnt counts at most 63 copies in flight");
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // workgroup w runs on XCD w % 8; XCD x takes tiles [x per, (x + 1) per)
@@ -275,7 +283,7 @@ __global__ void __launch_bounds__(64 * W) k_gemm_lds(GemmArgs g) {
     __builtin_amdgcn_global_load_lds((glb_void_t*)p, (lds_void_t*)(dst + blk * 1024), 16, 0, 0);
   };
   auto issue = [&](int s) {
-    char* sa = lds + (s % kLdsStages) * (SA + SB);
+    char* sa = lds + (s % S) * (SA + SB);
     char* sb = sa + SA;
     const int k0 = s * kLdsBK;
 #pragma unroll
@@ -290,17 +298,22 @@ __global__ void __launch_bounds__(64 * W) k_gemm_lds(GemmArgs g) {
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
-  issue(0);
+  for (int s = 0; s < S - 1 && s < nk; ++s) issue(s);
   for (int s = 0; s < nk; ++s) {
-    // this wavefront's copies of slab s have landed (nothing else of it is
-    // in flight); the barrier then covers every wavefront's, and every
-    // wavefront is done reading the buffer the next slab goes into (a plain
-    // barrier: a fence would also wait for stores that need not finish)
-    wait_vmcnt<0>();
+    // this wavefront's copies of slab s have landed: the copies issued after
+    // them (slabs s + 1 .. s + S - 2, LB each, in order) may still be in
+    // flight, and near the end, where fewer were issued, nothing is.  The
+    // barrier then covers every wavefront's copies, and every wavefront is
+    // done reading the buffer that slab s + S - 1 goes into, slab s - 1's (a
+    // plain barrier: a fence would also wait for stores that need not finish)
+    if (s + S - 2 < nk)
+      wait_vmcnt<(S - 2) * LB>();
+    else
+      wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
-    if (s + 1 < nk) issue(s + 1);
-    const bf16* sa = (const bf16*)(lds + (s % kLdsStages) * (SA + SB));
-    const bf16* sb = (const bf16*)(lds + (s % kLdsStages) * (SA + SB) + SA);
+    if (s + S - 1 < nk) issue(s + S - 1);
+    const bf16* sa = (const bf16*)(lds + (s % S) * (SA + SB));
+    const bf16* sb = (const bf16*)(lds + (s % S) * (SA + SB) + SA);
 #pragma unroll
     for (int ks = 0; ks < kLdsBK / 16; ++ks) {
       const int ch = ks * 2 + (lane >> 5);

@@ -53,6 +53,7 @@ bool sg_valid(const sg_config* c) {
          c->max_batch <= 65536;
 }
 
+
 SgLayout sg_layout(const sg_config* c) {
   SgLayout s;
   Lay L;
@@ -135,6 +136,18 @@ int sfail(sg_ctx* c, int code, const std::string& m) {
     if (e_ != hipSuccess) return sfail((ctx), MC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Dynamic LDS beyond the default 64 KB for the direct-to-LDS products of one
+// epilogue
+template <int EPI>
+hipError_t allow_lds() {
+  const auto attr = hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e = hipFuncSetAttribute((const void*)k_gemm_lds<EPI, 256, 256, 16>, attr, lds_bytes<256, 256>());
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_gemm_lds<EPI, 128, 128, 8>, attr, lds_bytes<128, 128>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_gemm_lds<EPI, 128, 128, 8, 3>, attr, lds_bytes<128, 128, 3>());
+  return e;
+}
+
 template <bool TA, bool TB, int EPI>
 void gemm(sg_ctx* c, const GemmArgs& g) {
   // the 16-byte tile loads need leading dimensions that are multiples of 8
@@ -144,22 +157,30 @@ void gemm(sg_ctx* c, const GemmArgs& g) {
     return;
   }
   // forward products (both operands K-contiguous, K a multiple of 8):
-  // direct-to-LDS slabs in 128 x 128 tiles, or 128 x 64 tiles, when either
-  // gives at least two tiles per compute unit (with one, the epilogue and the
-  // copy latency stay exposed).  Measured at batch 4096: the 1024 -> 3600
-  // output layer 109.8 -> 61 µs in 128 x 128 tiles, the four GELU layers
-  // (input and hidden) 28.6 µs on average in 128 x 64, against 29.9 for the
-  // hidden ones alone before; dX (the GELU-derivative epilogue reads the
-  // pre-activations) ran 47 µs against 43 in 64 x 64 tiles and stays there.
+  // direct-to-LDS slabs in the largest tiles that still give every compute
+  // unit work.  The copies reach the compute units at a rate that grows with
+  // the wavefronts issuing them, not with the slabs in flight (3 or 4 stages
+  // of 128 x 128 tiles ran no faster than 2), so the large tiles take 8 or 16
+  // wavefronts.  Measured at batch 4096 (µs per product, 4 wavefronts per
+  // tile before): the 1024 -> 3600 output layer 53.3 -> 48.1 in 256 x 256
+  // tiles; a hidden layer 21.2 (128 x 64) -> 20.1, the input layer 31.3 ->
+  // 30.3 in 128 x 128 tiles, one per compute unit with three stages.  dX
+  // (the GELU-derivative epilogue reads the pre-activations) stays in the
+  // register-staged 64 x 64 tiles: 43 µs, against 47 in 128 x 64 direct-to-LDS
+  // tiles and 43.7 in 128 x 128 tiles of 8 wavefronts.
   if (!TA && TB && EPI != EPI_GELU_GRAD && g.K % 8 == 0) {
     if (lds_tiles(g.M, g.N, 256, 256) >= 224) {
       const int T = lds_tiles(g.M, g.N, 256, 256);
-      k_gemm_lds<EPI, 256, 256, 8><<<((T + 7) / 8) * 8, 512, lds_bytes<256, 256>(), c->st>>>(g);
+      k_gemm_lds<EPI, 256, 256, 16><<<((T + 7) / 8) * 8, 1024, lds_bytes<256, 256>(), c->st>>>(g);
       return;
     }
-    if (lds_tiles(g.M, g.N, 128, 128) >= 512) {
-      const int T = lds_tiles(g.M, g.N, 128, 128);
-      k_gemm_lds<EPI, 128, 128, 4><<<((T + 7) / 8) * 8, 256, lds_bytes<128, 128>(), c->st>>>(g);
+    const int T128 = lds_tiles(g.M, g.N, 128, 128);
+    if (T128 >= 512) {
+      k_gemm_lds<EPI, 128, 128, 8><<<((T128 + 7) / 8) * 8, 512, lds_bytes<128, 128>(), c->st>>>(g);
+      return;
+    }
+    if (T128 >= 256) {
+      k_gemm_lds<EPI, 128, 128, 8, 3><<<((T128 + 7) / 8) * 8, 512, lds_bytes<128, 128, 3>(), c->st>>>(g);
       return;
     }
     if (lds_tiles(g.M, g.N, 128, 64) >= 512) {
@@ -196,8 +217,10 @@ GemmArgs ga(const bf16* A, long lda, const bf16* B, long ldb, int M, int N, int 
 }
 
 // forward of one member on `batch` rows of raw FP32 inputs; normalised
-// predictions to `out` (FP32 [batch][n_out])
-void enqueue_forward(sg_ctx* c, int e, const float* d_x, int batch, float* out) {
+// predictions to `out` (FP32 [batch][n_out]).  The hidden layers'
+// pre-activations are kept (for the GELU derivative) only when a backward
+// pass follows; the activations are the same either way.
+void enqueue_forward(sg_ctx* c, int e, const float* d_x, int batch, float* out, bool keep_z) {
   const SgLayout& s = c->s;
   k_input<<<blocks((long)batch * s.K0p), 256, 0, c->st>>>(d_x, batch, c->c.n_in, c->p<float>(s.xmean),
                                                            c->p<float>(s.xstd), c->p<bf16>(s.X0), s.K0p);
@@ -208,9 +231,13 @@ void enqueue_forward(sg_ctx* c, int e, const float* d_x, int batch, float* out) 
     GemmArgs g = ga(X, ldx, c->p<bf16>(o.Wt), s.K[l], batch, s.N[l], s.K[l]);  // weights N-major
     g.bias = c->p<float>(o.b);
     if (l < s.L - 1) {
-      g.Cf = c->p<float>(s.Z[l]); g.ldcf = s.N[l];
       g.Cb = c->p<bf16>(s.A[l]); g.ldcb = s.N[l];
-      gemm<false, true, EPI_BIAS_GELU>(c, g);
+      if (keep_z) {
+        g.Cf = c->p<float>(s.Z[l]); g.ldcf = s.N[l];
+        gemm<false, true, EPI_BIAS_GELU>(c, g);
+      } else {
+        gemm<false, true, EPI_BIAS_GELU_ONLY>(c, g);
+      }
       X = c->p<bf16>(s.A[l]);
       ldx = s.N[l];
     } else {
@@ -339,14 +366,9 @@ int sg_init(sg_ctx** out, const sg_config* cfg, void* d_ws, size_t bytes, void* 
     SGCHK(c, static_scratch_of(c->dev, &scr));
   }
   // the direct-to-LDS products take up to 128 KB of dynamic LDS per workgroup
-  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS, 256, 256, 8>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<256, 256>()));
-  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS_GELU, 256, 256, 8>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<256, 256>()));
-  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS, 128, 128, 4>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<128, 128>()));
-  SGCHK(c, hipFuncSetAttribute((const void*)k_gemm_lds<EPI_BIAS_GELU, 128, 128, 4>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<128, 128>()));
+  SGCHK(c, allow_lds<EPI_BIAS>());
+  SGCHK(c, allow_lds<EPI_BIAS_GELU>());
+  SGCHK(c, allow_lds<EPI_BIAS_GELU_ONLY>());
   SGCHK(c, hipMemsetAsync(c->ws, 0, s.total, c->st));
   for (int e = 0; e < cfg->ensemble; ++e)
     for (int l = 0; l < s.L; ++l) {
@@ -442,7 +464,7 @@ int sg_set_normalization(sg_ctx* c, const float* xm, const float* xs, const floa
 int sg_forward(sg_ctx* c, int member, const float* d_x, int batch, float* d_pred) {
   if (!c || member < 0 || member >= c->c.ensemble || !d_x || !d_pred || batch < 1 || batch > c->c.max_batch)
     return sfail(c, MC_E_ARG, "bad argument");
-  enqueue_forward(c, member, d_x, batch, d_pred);
+  enqueue_forward(c, member, d_x, batch, d_pred, false);
   SGCHK(c, hipGetLastError());
   if (c->bad_gemm) return sfail(c, MC_E_ARG, "GEMM operands not 16-byte aligned");
   return MC_OK;
@@ -454,7 +476,7 @@ int sg_backward(sg_ctx* c, int member, const float* d_x, const float* d_y, int b
   const SgLayout& s = c->s;
   const int n_out = c->c.n_out;
   float* pred = c->p<float>(s.preds) + (size_t)member * c->c.max_batch * n_out;
-  enqueue_forward(c, member, d_x, batch, pred);
+  enqueue_forward(c, member, d_x, batch, pred, true);
   const long tot = (long)batch * n_out;
   bf16* dcur = c->p<bf16>(s.dA0);
   bf16* dnext = c->p<bf16>(s.dA1);
@@ -526,7 +548,7 @@ int sg_predict(sg_ctx* c, const float* d_x, int batch, float* d_mean, float* d_s
     enqueue_forward_small(c, d_x, batch, workspace_scratch(c));
   } else {
     for (int e = 0; e < c->c.ensemble; ++e)
-      enqueue_forward(c, e, d_x, batch, c->p<float>(s.preds) + (size_t)e * per);
+      enqueue_forward(c, e, d_x, batch, c->p<float>(s.preds) + (size_t)e * per, false);
   }
   k_ensemble<<<blocks(per), 256, 0, c->st>>>(c->p<float>(s.preds), c->c.ensemble, per, c->c.n_out,
                                              c->p<float>(s.ymean), c->p<float>(s.ystd), d_mean, d_std);
