@@ -306,8 +306,8 @@ int mc_occupancy(mc_ctx *ctx, int block, int *wg_per_cu, int *n_cu);
  * owning every nw-th chunk of 256 slots of it, so each samples the whole slot
  * range and the launch is balanced however the live electrons are spread over
  * the slots), 3 = persistent with staged slots (as 2; each wavefront copies
- * the next 64 slots of its chunks into LDS while its lanes take electrons from
- * the current 64, which pays off while the state outgrows the Infinity
+ * the next 128 slots of its chunks into LDS while its lanes take electrons from
+ * the current 128, which pays off while the state outgrows the Infinity
  * Cache).  Results are identical up to the compiler's floating-point
  * contraction choices in each variant (variants 0, 2 and 3 share the
  * per-electron code and give the same bits).  MC_E_ARG for another value,

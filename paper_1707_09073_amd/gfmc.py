@@ -331,7 +331,7 @@ class Ensemble:
     def mc_set_variant(self, variant: int):
         """Particle kernel: 0 lane refill per tile, 1 one electron per lane,
         2 persistent (resident workgroups, each working every nw-th slot chunk
-        of its instance), 3 persistent with each wavefront's next 64 slots
+        of its instance), 3 persistent with each wavefront's next 128 slots
         staged in LDS."""
         self._chk(lib().mc_set_variant(self._ctx, int(variant)), "mc_set_variant")
 

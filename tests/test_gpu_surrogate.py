@@ -171,20 +171,21 @@ def test_small_batch_predict_matches_oracle_and_gemm_path(torch_mod, shape):
         assert _rel(s, big_s[lo:hi]) <= 2e-2
 
 
-@pytest.mark.parametrize("width,n_out", [(1024, 3600), (2048, 600)])
-def test_large_batch_output_layer_matches_oracle(torch_mod, width, n_out):
-    """Batch 4096 through 1803 -> width -> n_out, in the forward products and
-    the backward products of the training step.  Width 1024: the output
-    layer has 16 x 15 tiles of 256 x 256 (16-wavefront workgroups), the
-    input layer 32 x 8 tiles of 128 x 128 (one per compute unit, three LDS
-    stages).  Width 2048: the input layer has 32 x 16 tiles of 128 x 128
-    (two stages), the 600-wide output layer takes the register-staged
-    kernel."""
+@pytest.mark.parametrize("width,n_out,batch", [(1024, 3600, 4096), (2048, 600, 4096), (1024, 3600, 3999)])
+def test_large_batch_output_layer_matches_oracle(torch_mod, width, n_out, batch):
+    """Batches of about 4096 through 1803 -> width -> n_out, in the forward
+    products and the backward products of the training step.  Width 1024:
+    the output layer has 16 x 15 tiles of 256 x 256 (16-wavefront
+    workgroups), the input layer 32 x 8 tiles of 128 x 128 (one per compute
+    unit, three LDS stages); batch 3999 leaves the last row of tiles ragged
+    and the K slabs of the 1803-wide input a ragged tail.  Width 2048: the
+    input layer has 32 x 16 tiles of 128 x 128 (two stages), the 600-wide
+    output layer takes the register-staged kernel."""
     torch = torch_mod
-    net, (o,), x, y = _make(torch, n_in=1803, n_out=n_out, width=width, depth=1, batch=4096, seed=23)
-    _say(f"surrogate batch 4096, width {width}, {n_out} outputs: forward and gradients vs oracle")
+    net, (o,), x, y = _make(torch, n_in=1803, n_out=n_out, width=width, depth=1, batch=batch, seed=23)
+    _say(f"surrogate batch {batch}, width {width}, {n_out} outputs: forward and gradients vs oracle")
     xd, yd = torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda")
-    out = torch.empty((4096, n_out), device="cuda", dtype=torch.float32)
+    out = torch.empty((batch, n_out), device="cuda", dtype=torch.float32)
     net.sg_forward(0, xd, out)
     torch.cuda.synchronize()
     loss_o, dW_o, db_o, pred_o = o.loss_and_grads(x, y)
