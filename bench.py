@@ -54,19 +54,21 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 KERNELS = {0: "k_flight_refill<float,true>", 1: "k_flight<float,true>", 2: "k_flight_persist<float,true>",
            3: "k_flight_persist_staged<float,true>"}
 KERNEL_COUNTERS = {
-    0: {"sources_digest": "eb2142028a12b8ed", "valu_lane_ops_per_segment": 183.9, "hbm_bytes_per_segment": 11.46,
+    0: {"sources_digest": "6a8849d84a4d64a0", "valu_lane_ops_per_segment": 183.9, "hbm_bytes_per_segment": 11.46,
         "active_lane_fraction": 0.534, "profile": "profiles/k_flight_refill_device1e7_counters.md",
         "note": "counters at block 1024 / tile 8192 over intervals 6-10 (9.9e6 electrons, state beyond the "
                 "Infinity Cache, non-temporal state loads); the active lanes include lanes without an electron, "
                 "which run the segment on stale state and drop it, so the useful fraction is an upper bound"},
-    2: {"sources_digest": "eb2142028a12b8ed", "valu_lane_ops_per_segment": 156.1, "hbm_bytes_per_segment": 8.82,
-        "active_lane_fraction": 0.460, "profile": "profiles/k_flight_persist_device1e7_counters.md",
+    2: {"sources_digest": "6a8849d84a4d64a0", "valu_lane_ops_per_segment": 157.7, "hbm_bytes_per_segment": 8.71,
+        "active_lane_fraction": 0.458, "profile": "profiles/k_flight_persist_device1e7_counters.md",
         "note": "counters at block 1024 / tile 8192 over intervals 6-10 (9.9e6 electrons, state beyond the "
-                "Infinity Cache, non-temporal state loads); one resident workgroup of 1024 lanes per CU"},
-    3: {"sources_digest": "eb2142028a12b8ed", "valu_lane_ops_per_segment": 167.8, "hbm_bytes_per_segment": 6.70,
+                "Infinity Cache, non-temporal state loads); one resident workgroup of 1024 lanes per CU, chunks of "
+                "128 slots"},
+    3: {"sources_digest": "6a8849d84a4d64a0", "valu_lane_ops_per_segment": 168.2, "hbm_bytes_per_segment": 6.66,
         "active_lane_fraction": 0.431, "profile": "profiles/k_flight_persist_staged_device1e7_counters.md",
         "note": "counters at block 1024 / tile 8192 over intervals 6-10 (9.9e6 electrons, state beyond the "
-                "Infinity Cache); slots staged in LDS a piece of 128 ahead, one resident workgroup per CU"},
+                "Infinity Cache); slots staged in LDS a piece of 128 ahead, one resident workgroup per CU, chunks "
+                "of 128 slots"},
 }
 
 
@@ -92,11 +94,12 @@ def _ph_issue(segs_launch: float, avg_ms: float):
                 profile=PH_COUNTERS["profile"])
 
 
-def _kernel_digest(files=("gfmc_kernels.h", "gfmc_device.h")) -> str:
-    """Digest of kernel sources (by default the particle kernels and the
-    device arithmetic they use; the refresh kernels live in a header of their
-    own) with comments and blank lines removed, so that a comment edit does
-    not invalidate the counters."""
+def _kernel_digest(files=("gfmc_kernels.h", "gfmc_device.h", "gfmc.hip")) -> str:
+    """Digest of kernel sources (by default the particle kernels, the device
+    arithmetic they use and the host code that sets their launch, chunks
+    included; the refresh kernels live in a header of their own) with
+    comments and blank lines removed, so that a comment edit does not
+    invalidate the counters."""
     import hashlib
     import re
     h = []

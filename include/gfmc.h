@@ -303,7 +303,7 @@ int mc_occupancy(mc_ctx *ctx, int block, int *wg_per_cu, int *n_cu);
  * of its tile as soon as its own finishes the interval; default), 1 = one
  * electron per lane per pass, 2 = persistent (as many workgroups as the GPU
  * holds at once, each bound to one instance in proportion to its slots and
- * owning every nw-th chunk of 256 slots of it, so each samples the whole slot
+ * owning every nw-th chunk of 128 slots of it, so each samples the whole slot
  * range and the launch is balanced however the live electrons are spread over
  * the slots), 3 = persistent with staged slots (as 2; each wavefront copies
  * the next 128 slots of its chunks into LDS while its lanes take electrons from

@@ -190,7 +190,10 @@ struct mc_ctx {
   int block = 256, tile = 0, n_tiles = 0;
   int max_tiles = 0;        // tiles at the smallest tile size: per-tile entries the workspace holds
   long long max_cap = 0;    // largest instance capacity
-  int n_wg = 0, chunk = 256;  // persistent kernel: workgroups, slots per chunk
+  // persistent kernels: workgroups, slots per chunk (128: one staged piece;
+  // 256 was 1-2% slower and 64 4% slower, 512 and 1024 left the workgroups
+  // unevenly loaded)
+  int n_wg = 0, chunk = 128;
   unsigned inj_blocks = 0;  // refill grid: covers the most electrons one instance can need
   size_t total_cap = 0;
   std::vector<long long> base;
