@@ -42,6 +42,11 @@ struct GemmArgs {
   const float* bias;
   const float* Z;  // pre-activations for the GELU derivative
   long ldz;
+  // split K (k_gemm, store epilogue): workgroup z of the grid's z range
+  // takes k in [z kz, (z + 1) kz) and stores its partial product at
+  // Cf + z zs; 0: no split
+  int kz;
+  long zs;
 };
 
 // GELU with the exact normal CDF: x Phi(x)
@@ -103,6 +108,13 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, const f32x16& acc, i
 template <bool TA, bool TB, int EPI, int TM>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   constexpr int BK = slab_depth<TM>(), KP = BK + 8, CPR = BK / 8;
+  if (g.kz > 0) {
+    const int k0 = (int)blockIdx.z * g.kz;
+    g.A += TA ? (long)k0 * g.lda : (long)k0;
+    g.B += TB ? (long)k0 : (long)k0 * g.ldb;
+    g.K = min(g.kz, g.K - k0);
+    g.Cf += (long)blockIdx.z * g.zs;
+  }
   constexpr int BM = 2 * TM, BN = 2 * TM, MB = TM / 32, NCH = BM * CPR / 256;
   __shared__ __attribute__((aligned(16))) bf16 As[BM * KP];
   __shared__ __attribute__((aligned(16))) bf16 Bs[BN * KP];  // n-major: Bs[n][k]
@@ -377,6 +389,16 @@ __global__ void k_loss(const float* __restrict__ pred, const float* __restrict__
     __syncthreads();
   }
   if (threadIdx.x == 0) loss_part[blockIdx.x] = s[0];
+}
+
+// out[i] = part[i] + part[zs + i] + ... + part[(S - 1) zs + i], in that
+// order (the split-K partial products of one GEMM)
+__global__ void k_split_sum(const float* __restrict__ part, int S, long n, long zs, float* __restrict__ out) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    float v = part[i];
+    for (int z = 1; z < S; ++z) v += part[z * zs + i];
+    out[i] = v;
+  }
 }
 
 // Column sums of a BF16 [M x N] gradient (bias gradient): one workgroup of

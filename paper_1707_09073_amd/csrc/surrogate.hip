@@ -38,6 +38,7 @@ struct SgLayout {
   std::vector<int> K, N;  // per layer
   std::vector<std::vector<LayerOff>> lo;  // [member][layer]
   size_t xmean, xstd, ymean, ystd, X0, preds, dA0, dA1, loss, idx;
+  size_t dWpart = 0;        // split-K partial products of dW
   size_t qx, qm, qs;        // one query of sg_predict_or_mc: features, mean, spread
   int msmall = 0;          // rows of the small-batch inference path
   size_t Asm, gvp;         // its activations [2][member][msmall][width] and split partials
@@ -53,6 +54,22 @@ bool sg_valid(const sg_config* c) {
          c->max_batch <= 65536;
 }
 
+
+// Splits of K (the batch) for dW = X^T dZ [M x N] in 64 x 64 tiles: doubled,
+// up to kDwSplitMax, while the workgroups stay within kDwSplitTarget and,
+// for a batch K > 0, each split is a whole number of 128-deep slabs; 0 below
+// 2 splits.  With K = 0, the most any batch can take (the workspace's
+// partials).  Measured on the training step at batch 4096 (1803 -> 1024 x 4
+// -> 3600): 1.029 ms without splits, 0.981 with at most 1024 workgroups,
+// 0.939 with 2048, 0.910 with 4096, 0.905 with 8192 (twice the partials:
+// 118 MB), 0.950 with 8192 and up to 16 splits.
+constexpr int kDwSplitTarget = 4096, kDwSplitMax = 8;
+int dw_splits(int M, int N, int K) {
+  const long tiles = (long)((N + 63) / 64) * ((M + 63) / 64);
+  int S = 1;
+  while (S < kDwSplitMax && tiles * S * 2 <= kDwSplitTarget && (K == 0 || K % (2 * S * 128) == 0)) S *= 2;
+  return S > 1 ? S : 0;
+}
 
 SgLayout sg_layout(const sg_config* c) {
   SgLayout s;
@@ -96,6 +113,10 @@ SgLayout sg_layout(const sg_config* c) {
   s.dA0 = L.take(2 * MB * wmax);
   s.dA1 = L.take(2 * MB * wmax);
   s.loss = L.take(4 * ((MB * s.Np + 255) / 256 + 1));
+  size_t part = 0;
+  for (int l = 0; l < s.L; ++l)
+    part = std::max(part, (size_t)dw_splits(s.K[l], s.N[l], 0) * s.K[l] * s.N[l]);
+  if (part > 0) s.dWpart = L.take(4 * part);
   s.msmall = (int)std::min<size_t>(kSmallM, MB);
   s.Asm = L.take(2 * 2 * (size_t)c->ensemble * s.msmall * c->width);
   s.gvp = L.take(4 * (size_t)c->ensemble * kGvMaxSplit * s.msmall * wmax);
@@ -149,7 +170,7 @@ hipError_t allow_lds() {
 }
 
 template <bool TA, bool TB, int EPI>
-void gemm(sg_ctx* c, const GemmArgs& g) {
+void gemm(sg_ctx* c, const GemmArgs& g, int splits = 1) {
   // the 16-byte tile loads need leading dimensions that are multiples of 8
   // elements and 16-byte aligned operands (all buffers come from the workspace)
   if ((g.lda & 7) || (g.ldb & 7) || ((uintptr_t)g.A & 15) || ((uintptr_t)g.B & 15)) {
@@ -192,11 +213,12 @@ void gemm(sg_ctx* c, const GemmArgs& g) {
   // 128 x 128 tiles unless they would give fewer than two workgroups per
   // compute unit (256 on the MI355X); 64 x 64 tiles then
   const long big = (long)((g.N + 127) / 128) * ((g.M + 127) / 128);
-  if (big >= 512) {
+  if (big >= 512 && splits == 1) {
     dim3 grid((g.N + 127) / 128, (g.M + 127) / 128);
     k_gemm<TA, TB, EPI, 64><<<grid, 256, 0, c->st>>>(g);
   } else {
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    // split products (the grid's z range) take the 64 x 64 tiles
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
     k_gemm<TA, TB, EPI, 32><<<grid, 256, 0, c->st>>>(g);
   }
 }
@@ -489,7 +511,20 @@ int sg_backward(sg_ctx* c, int member, const float* d_x, const float* d_y, int b
     // dW = X^T dZ   [K x N]
     GemmArgs gw = ga(Xin, ldx, dcur, s.N[l], s.K[l], s.N[l], batch);
     gw.Cf = c->p<float>(o.dW); gw.ldcf = s.N[l];
-    gemm<true, false, EPI_STORE>(c, gw);
+    const int S = dw_splits(s.K[l], s.N[l], batch);
+    if (S > 1) {
+      // S partial products over batch slices into the partials, then their
+      // sum in slice order: S times the workgroups of one product over K
+      const long n = (long)s.K[l] * s.N[l];
+      gw.Cf = c->p<float>(s.dWpart);
+      gw.kz = batch / S;
+      gw.zs = n;
+      gemm<true, false, EPI_STORE>(c, gw, S);
+      k_split_sum<<<std::min<long>(blocks(n), 4096), 256, 0, c->st>>>(c->p<float>(s.dWpart), S, n, n,
+                                                                      c->p<float>(o.dW));
+    } else {
+      gemm<true, false, EPI_STORE>(c, gw);
+    }
     k_colsum<<<blocks(s.N[l], 64), 64 * kCsRows, 0, c->st>>>(dcur, batch, s.N[l], s.N[l], c->p<float>(o.db));
     if (l > 0) {
       // dZ_{l-1} = (dZ_l W^T) * gelu'(Z_{l-1})
