@@ -392,38 +392,66 @@ __global__ void k_loss(const float* __restrict__ pred, const float* __restrict__
 }
 
 // out[i] = part[i] + part[zs + i] + ... + part[(S - 1) zs + i], in that
-// order (the split-K partial products of one GEMM)
+// order (the split-K partial products of one GEMM, S <= 8): the S loads are
+// in flight before their adds
 __global__ void k_split_sum(const float* __restrict__ part, int S, long n, long zs, float* __restrict__ out) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    float v = part[i];
-    for (int z = 1; z < S; ++z) v += part[z * zs + i];
-    out[i] = v;
+    float v[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) v[z] = z < S ? part[z * zs + i] : 0.0f;
+    float t = v[0];
+#pragma unroll
+    for (int z = 1; z < 8; ++z)
+      if (z < S) t += v[z];
+    out[i] = t;
   }
 }
 
 // Column sums of a BF16 [M x N] gradient (bias gradient): one workgroup of
-// kCsRows x 64 lanes per 64 columns; lane group r sums rows r, r + kCsRows,
-// ... (independent loads, unrolled), and the groups' sums are added in group
-// order, so the result does not depend on timing.
+// kCsRows x 64 lanes per 64 columns and row block y (rows [y rp, (y + 1) rp)
+// of the grid's y range); lane group r sums rows r, r + kCsRows, ... of the
+// block (independent loads, unrolled), and the groups' sums are added in
+// group order.  One row block writes out; several write part[y][N], which
+// k_colsum_reduce adds in block order, so the result does not depend on
+// timing.
 constexpr int kCsRows = 16;
-__global__ void __launch_bounds__(64 * kCsRows) k_colsum(const bf16* __restrict__ d, int M, int N, long ld,
-                                                          float* out) {
-  __shared__ float part[kCsRows][64];
+__global__ void __launch_bounds__(64 * kCsRows) k_colsum(const bf16* __restrict__ d, int M, int N, long ld, int rp,
+                                                          float* out, float* part) {
+  __shared__ float acc[kCsRows][64];
   const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + c;
+  const int i0 = (int)blockIdx.y * rp, i1 = min(M, i0 + rp);
   float s = 0.0f;
   if (j < N) {
 #pragma unroll 8
-    for (int i = r; i < M; i += kCsRows) s += (float)d[(long)i * ld + j];
+    for (int i = i0 + r; i < i1; i += kCsRows) s += (float)d[(long)i * ld + j];
   }
-  part[r][c] = s;
+  acc[r][c] = s;
   __syncthreads();
   if (r == 0 && j < N) {
     float t = 0.0f;
 #pragma unroll
-    for (int g = 0; g < kCsRows; ++g) t += part[g][c];
-    out[j] = t;
+    for (int g = 0; g < kCsRows; ++g) t += acc[g][c];
+    if (gridDim.y == 1) out[j] = t;
+    else part[(long)blockIdx.y * N + j] = t;
   }
+}
+
+// out[j] = part[0][j] + part[1][j] + ... in row-block order; eight loads in
+// flight before their adds
+__global__ void k_colsum_reduce(const float* __restrict__ part, int R, int N, float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  float t = 0.0f;
+  for (int y0 = 0; y0 < R; y0 += 8) {
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = y0 + q < R ? part[(long)(y0 + q) * N + j] : 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (y0 + q < R) t += v[q];
+  }
+  out[j] = t;
 }
 
 // Adam (bias-corrected) on FP32 master weights with decoupled weight decay

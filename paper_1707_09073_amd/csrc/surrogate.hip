@@ -39,6 +39,7 @@ struct SgLayout {
   std::vector<std::vector<LayerOff>> lo;  // [member][layer]
   size_t xmean, xstd, ymean, ystd, X0, preds, dA0, dA1, loss, idx;
   size_t dWpart = 0;        // split-K partial products of dW
+  size_t dbpart = 0;        // row-block column sums of the bias gradient
   size_t qx, qm, qs;        // one query of sg_predict_or_mc: features, mean, spread
   int msmall = 0;          // rows of the small-batch inference path
   size_t Asm, gvp;         // its activations [2][member][msmall][width] and split partials
@@ -64,6 +65,8 @@ bool sg_valid(const sg_config* c) {
 // 0.939 with 2048, 0.910 with 4096, 0.905 with 8192 (twice the partials:
 // 118 MB), 0.950 with 8192 and up to 16 splits.
 constexpr int kDwSplitTarget = 4096, kDwSplitMax = 8;
+// row blocks of the bias gradient's column sums, at most
+constexpr int kCsMaxBlocks = 32;
 int dw_splits(int M, int N, int K) {
   const long tiles = (long)((N + 63) / 64) * ((M + 63) / 64);
   int S = 1;
@@ -117,6 +120,7 @@ SgLayout sg_layout(const sg_config* c) {
   for (int l = 0; l < s.L; ++l)
     part = std::max(part, (size_t)dw_splits(s.K[l], s.N[l], 0) * s.K[l] * s.N[l]);
   if (part > 0) s.dWpart = L.take(4 * part);
+  s.dbpart = L.take(4 * (size_t)kCsMaxBlocks * wmax);
   s.msmall = (int)std::min<size_t>(kSmallM, MB);
   s.Asm = L.take(2 * 2 * (size_t)c->ensemble * s.msmall * c->width);
   s.gvp = L.take(4 * (size_t)c->ensemble * kGvMaxSplit * s.msmall * wmax);
@@ -525,7 +529,17 @@ int sg_backward(sg_ctx* c, int member, const float* d_x, const float* d_y, int b
     } else {
       gemm<true, false, EPI_STORE>(c, gw);
     }
-    k_colsum<<<blocks(s.N[l], 64), 64 * kCsRows, 0, c->st>>>(dcur, batch, s.N[l], s.N[l], c->p<float>(o.db));
+    {
+      // bias gradient: row blocks so that about 512 workgroups share the
+      // batch (a 1024-wide layer has only 16 column blocks)
+      const int nbx = (int)blocks(s.N[l], 64);
+      const int R = std::max(1, std::min(kCsMaxBlocks, 512 / nbx));
+      const int rp = (batch + R - 1) / R;
+      const int Ry = (batch + rp - 1) / rp;
+      k_colsum<<<dim3(nbx, Ry), 64 * kCsRows, 0, c->st>>>(dcur, batch, s.N[l], s.N[l], rp, c->p<float>(o.db),
+                                                          c->p<float>(s.dbpart));
+      if (Ry > 1) k_colsum_reduce<<<blocks(s.N[l], 64), 64, 0, c->st>>>(c->p<float>(s.dbpart), Ry, s.N[l], c->p<float>(o.db));
+    }
     if (l > 0) {
       // dZ_{l-1} = (dZ_l W^T) * gelu'(Z_{l-1})
       GemmArgs gx = ga(dcur, s.N[l], c->p<bf16>(o.Wb), s.N[l], batch, s.K[l], s.N[l]);
