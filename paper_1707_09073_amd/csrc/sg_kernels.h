@@ -362,33 +362,62 @@ __global__ void k_input(const float* __restrict__ x, int M, int n_in, const floa
   X0[e] = (bf16)(k < n_in ? (x[(long)i * n_in + k] - mean[k]) / stdv[k] : 0.0f);
 }
 
-// MSE on z-scored targets; writes dL/dpred (BF16, row stride np, zero in the
-// padding columns) and per-block loss sums.
-__global__ void k_loss(const float* __restrict__ pred, const float* __restrict__ y, int M, int n_out, int np,
-                       const float* __restrict__ ymean, const float* __restrict__ ystd, bf16* dpred,
-                       float* loss_part) {
-  __shared__ float s[256];
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+// MSE on z-scored targets; writes dL/dpred (BF16, row stride np, a multiple
+// of 8, zero in the padding columns) and per-workgroup loss sums.  Thread t
+// of the grid's x range takes columns 4t .. 4t+3 of rows blockIdx.y,
+// blockIdx.y + gridDim.y, ...: 16-byte loads when n_out is a multiple of 4
+// and both inputs are 16-byte aligned (every row then is), 8-byte stores.
+// Workgroup (x, y)'s sum goes to loss_part[y gridDim.x + x].
+__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ pred, const float* __restrict__ y, int M,
+                                              int n_out, int np, const float* __restrict__ ymean,
+                                              const float* __restrict__ ystd, bf16* dpred, float* loss_part) {
+  __shared__ float s[4];
+  const int j0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
   float l = 0.0f;
-  if (e < (long)M * np) {
-    const int i = (int)(e / np), j = (int)(e % np);
-    if (j < n_out) {
-      const long o = (long)i * n_out + j;
-      const float t = (y[o] - ymean[j]) / ystd[j];
-      const float d = pred[o] - t;
-      l = d * d;
-      dpred[e] = (bf16)(2.0f * d / (float)((long)M * n_out));
-    } else {
-      dpred[e] = (bf16)0.0f;
+  if (j0 < np) {
+    float mu[4], sd[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool out = j0 + q < n_out;
+      mu[q] = out ? ymean[j0 + q] : 0.0f;
+      sd[q] = out ? ystd[j0 + q] : 1.0f;
+    }
+    const float n = (float)((long)M * n_out);
+    const bool vec = (n_out & 3) == 0 && j0 + 4 <= n_out && (((uintptr_t)pred | (uintptr_t)y) & 15) == 0;
+#pragma unroll 4
+    for (int i = blockIdx.y; i < M; i += gridDim.y) {
+      const long o = (long)i * n_out + j0;
+      float pv[4], yv[4];
+      if (vec) {
+        const float4 a = *reinterpret_cast<const float4*>(pred + o), b = *reinterpret_cast<const float4*>(y + o);
+        pv[0] = a.x; pv[1] = a.y; pv[2] = a.z; pv[3] = a.w;
+        yv[0] = b.x; yv[1] = b.y; yv[2] = b.z; yv[3] = b.w;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          pv[q] = j0 + q < n_out ? pred[o + q] : 0.0f;
+          yv[q] = j0 + q < n_out ? y[o + q] : 0.0f;
+        }
+      }
+      bf16 g[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        g[q] = (bf16)0.0f;
+        if (j0 + q < n_out) {
+          const float t = (yv[q] - mu[q]) / sd[q];
+          const float d = pv[q] - t;
+          l += d * d;
+          g[q] = (bf16)(2.0f * d / n);
+        }
+      }
+      *reinterpret_cast<uint2*>(dpred + (long)i * np + j0) = *reinterpret_cast<const uint2*>(g);
     }
   }
-  s[threadIdx.x] = l;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = l;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < (unsigned)o) s[threadIdx.x] += s[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) loss_part[blockIdx.x] = s[0];
+  if (threadIdx.x == 0) loss_part[blockIdx.y * gridDim.x + blockIdx.x] = s[0] + s[1] + s[2] + s[3];
 }
 
 // out[i] = part[i] + part[zs + i] + ... + part[(S - 1) zs + i], in that

@@ -67,6 +67,8 @@ bool sg_valid(const sg_config* c) {
 constexpr int kDwSplitTarget = 4096, kDwSplitMax = 8;
 // row blocks of the bias gradient's column sums, at most
 constexpr int kCsMaxBlocks = 32;
+// row slots of the loss kernel's grid (its partial sums: row slots x 1024-column blocks)
+constexpr int kLossRows = 256;
 int dw_splits(int M, int N, int K) {
   const long tiles = (long)((N + 63) / 64) * ((M + 63) / 64);
   int S = 1;
@@ -115,7 +117,7 @@ SgLayout sg_layout(const sg_config* c) {
   const size_t wmax = std::max(c->width, s.Np);
   s.dA0 = L.take(2 * MB * wmax);
   s.dA1 = L.take(2 * MB * wmax);
-  s.loss = L.take(4 * ((MB * s.Np + 255) / 256 + 1));
+  s.loss = L.take(4 * (std::min<size_t>(MB, kLossRows) * ((s.Np + 1023) / 1024) + 1));
   size_t part = 0;
   for (int l = 0; l < s.L; ++l)
     part = std::max(part, (size_t)dw_splits(s.K[l], s.N[l], 0) * s.K[l] * s.N[l]);
@@ -133,6 +135,7 @@ SgLayout sg_layout(const sg_config* c) {
 }
 
 unsigned blocks(long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+dim3 loss_grid(int rows, int np) { return dim3((unsigned)((np + 1023) / 1024), (unsigned)std::min(rows, kLossRows)); }
 
 }  // namespace
 
@@ -506,8 +509,8 @@ int sg_backward(sg_ctx* c, int member, const float* d_x, const float* d_y, int b
   const long tot = (long)batch * n_out;
   bf16* dcur = c->p<bf16>(s.dA0);
   bf16* dnext = c->p<bf16>(s.dA1);
-  k_loss<<<blocks((long)batch * s.Np), 256, 0, c->st>>>(pred, d_y, batch, n_out, s.Np, c->p<float>(s.ymean),
-                                                         c->p<float>(s.ystd), dcur, c->p<float>(s.loss));
+  k_loss<<<loss_grid(batch, s.Np), 256, 0, c->st>>>(pred, d_y, batch, n_out, s.Np, c->p<float>(s.ymean),
+                                                     c->p<float>(s.ystd), dcur, c->p<float>(s.loss));
   for (int l = s.L - 1; l >= 0; --l) {
     const LayerOff& o = s.lo[member][l];
     const bf16* Xin = l == 0 ? c->p<bf16>(s.X0) : c->p<bf16>(s.A[l - 1]);
@@ -552,7 +555,8 @@ int sg_backward(sg_ctx* c, int member, const float* d_x, const float* d_y, int b
   SGCHK(c, hipGetLastError());
   if (c->bad_gemm) return sfail(c, MC_E_ARG, "GEMM operands not 16-byte aligned");
   if (h_loss) {
-    const int nb = (int)blocks((long)batch * s.Np);
+    const dim3 lg = loss_grid(batch, s.Np);
+    const int nb = (int)(lg.x * lg.y);
     std::vector<float> part(nb);
     SGCHK(c, hipMemcpyAsync(part.data(), c->p<float>(s.loss), 4 * (size_t)nb, hipMemcpyDeviceToHost, c->st));
     SGCHK(c, hipStreamSynchronize(c->st));
