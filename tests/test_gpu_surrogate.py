@@ -192,12 +192,19 @@ def test_large_batch_output_layer_matches_oracle(torch_mod, width, n_out, batch)
     assert _rel(out.cpu().numpy(), pred_o) <= 1e-3
     loss = net.sg_backward(0, xd, yd)
     assert loss == pytest.approx(loss_o, rel=1e-4)
+    first = [net.sg_get_grads(0, l) for l in range(2)]
     for l in range(2):
-        dW, db = net.sg_get_grads(0, l)
+        dW, db = first[l]
         dWo = dW_o[l][:1803] if l == 0 else dW_o[l]
         dW = dW[:1803] if l == 0 else dW
         assert _rel(dW, dWo) <= 1e-3, (l, _rel(dW, dWo))
         assert _rel(db, db_o[l]) <= 1e-3, (l, _rel(db, db_o[l]))
+    # the split products and column sums are added in a fixed order: a second
+    # backward on the same inputs gives the same bits
+    assert net.sg_backward(0, xd, yd) == loss
+    for l in range(2):
+        dW, db = net.sg_get_grads(0, l)
+        assert np.array_equal(dW, first[l][0]) and np.array_equal(db, first[l][1]), l
 
 
 def test_predict_or_mc_answers_from_surrogate_or_monte_carlo(torch_mod):
