@@ -302,10 +302,11 @@ int mc_occupancy(mc_ctx *ctx, int block, int *wg_per_cu, int *n_cu);
 /* Particle-kernel variant: 0 = lane refill (each lane pulls the next electron
  * of its tile as soon as its own finishes the interval; default), 1 = one
  * electron per lane per pass, 2 = persistent (as many workgroups as the GPU
- * holds at once, each bound to one instance in proportion to its slots and
- * owning every nw-th chunk of 128 slots of it, so each samples the whole slot
- * range and the launch is balanced however the live electrons are spread over
- * the slots), 3 = persistent with staged slots (as 2; each wavefront copies
+ * holds at once, each bound to one instance, in proportion to its slots at
+ * first and then, with several instances, to its segments over the previous
+ * interval, and owning every nw-th chunk of 128 slots of it, so each samples
+ * the whole slot range and the launch is balanced however the live electrons
+ * are spread over the slots), 3 = persistent with staged slots (as 2; each wavefront copies
  * the next 128 slots of its chunks into LDS while its lanes take electrons from
  * the current 128, which pays off while the state outgrows the Infinity
  * Cache).  Results are identical up to the compiler's floating-point

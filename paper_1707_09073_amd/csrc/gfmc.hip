@@ -38,7 +38,7 @@ struct Layout {
 struct Offsets {
   size_t table64, table32, fac64, fac32, field64, field32, phi, gamma64, gamma32, Tcell, count, heat, dens,
       counters, flags, ctl, next_id, ip, tiles, acc, tile_dead, tile_off, plan, slots, minv, ainv, rhs, hist, reps,
-      nrep, bpart, wg_inst;
+      nrep, bpart, wg_inst, share_prev;
   size_t kx, ky, kz, x, y, z, meta;
   size_t skx, sky, skz, sx, sy, sz, smeta;  // compaction scratch (device mode)
   std::vector<std::pair<size_t, size_t>> kept;  // evolving state: the regions a checkpoint carries
@@ -145,6 +145,7 @@ Offsets layout(const mc_config* c, int n, size_t* total) {
   o.tile_dead = L.take(sizeof(uint32_t) * max_tiles);
   o.tile_off = L.take(sizeof(uint32_t) * max_tiles);
   o.wg_inst = L.take(sizeof(int) * max_tiles);
+  o.share_prev = L.take(sizeof(unsigned long long) * (n + 1));  // previous segment counts, valid flag
   o.plan = L.keep(sizeof(Plan) * n);
   o.slots = L.take(dev ? sizeof(uint32_t) * cap : 0);  // contact-refill slot list
   o.minv = L.take(dev ? sizeof(double) * c[0].n_cells[0] * (size_t)(c[0].n_cells[1] * c[0].n_cells[2]) *
@@ -300,6 +301,8 @@ int upload_tiles(mc_ctx* c) {
   c->n_wg = (int)wg_inst.size();
   HIPCHK(c, hipMemcpyAsync(c->ws + c->o.tiles, tp.tiles.data(), sizeof(TileDesc) * tp.tiles.size(),
                            hipMemcpyHostToDevice, c->st));
+  // the work-proportional shares start again from these slot shares
+  HIPCHK(c, hipMemsetAsync(c->ws + c->o.share_prev, 0, sizeof(unsigned long long) * (c->n_inst + 1), c->st));
   HIPCHK(c, hipMemcpyAsync(c->ws + c->o.wg_inst, wg_inst.data(), sizeof(int) * wg_inst.size(), hipMemcpyHostToDevice,
                            c->st));
   // free-slot counts start from zero under the new tiling
@@ -524,6 +527,12 @@ void enqueue_interval(mc_ctx* c) {
     e0 = prof_event(c); e1 = prof_event(c); e2 = prof_event(c);
     if (e0) (void)hipEventRecord(e0, c->st);
   }
+  // several instances under a persistent kernel: workgroups follow the
+  // previous interval's segments
+  if (c->variant >= 2 && c->n_inst > 1 && c->n_inst <= kShareMax)
+    k_share_work<<<1, 256, 0, c->st>>>(c->p<InstParams>(c->o.ip), c->n_inst, c->p<unsigned long long>(c->o.counters),
+                                       c->p<unsigned long long>(c->o.share_prev), c->p<int>(c->o.wg_inst), c->n_wg,
+                                       kMaxTile / c->chunk);
   if (c->f32)
     launch_flight<float>(c, flight_args<float>(c, c->M32, c->G32, c->o.table32, c->o.fac32, c->o.field32,
                                                c->o.gamma32));

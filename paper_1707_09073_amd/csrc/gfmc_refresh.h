@@ -244,6 +244,107 @@ __global__ void k_set_hw(Plan* plan, int inst, uint32_t hw) {
   if (threadIdx.x == 0) plan[inst].hw = hw;
 }
 
+// Exclusive prefix sum of a[0..n) in place (n <= kShareMax, one workgroup of
+// 256 threads, each a run of consecutive entries); returns the total.
+__device__ inline int block_scan_excl(int* a, int n, int* tmp) {
+  const int tid = threadIdx.x, per = (n + 255) / 256, b = min(n, tid * per), e = min(n, b + per);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += a[i];
+  tmp[tid] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int v = tid >= o ? tmp[tid - o] : 0;
+    __syncthreads();
+    tmp[tid] += v;
+    __syncthreads();
+  }
+  int run = tid ? tmp[tid - 1] : 0;
+  const int total = tmp[255];
+  for (int i = b; i < e; ++i) {
+    const int v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  __syncthreads();
+  return total;
+}
+
+// Workgroups of the persistent particle kernels per instance, in proportion
+// to each instance's segments (selections and electrons taken) over the
+// previous interval rather than to its slots: per-electron work differs
+// between bias points.  prev[0..n) holds the counts at the previous call and
+// prev[n] is non-zero once they are valid (the host clears it whenever it
+// sets the slot shares).  Each instance keeps at least one workgroup and
+// enough that none owns more than max_chunks chunks, at most one per chunk;
+// the shares add up to the launched grid (total, at most the chunks of all
+// instances), the remainder of the rounding going to the instances with
+// chunks to spare in instance order.  With no valid previous counts (the
+// first interval, or counters put back by a restore) the shares stay.
+// Which workgroup takes an electron does not change its result.
+constexpr int kShareMax = 1024;
+__global__ void __launch_bounds__(256) k_share_work(InstParams* ip, int n, const unsigned long long* counters,
+                                                    unsigned long long* prev, int* wg_inst, int total, int max_chunks) {
+  __shared__ unsigned long long s_work[kShareMax];
+  __shared__ int s_share[kShareMax], s_room[kShareMax], s_tmp[256];
+  __shared__ unsigned long long s_tot;
+  __shared__ int s_ok, s_min;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_ok = prev[n] != 0ull;
+    s_tot = 0ull;
+    s_min = 0;
+  }
+  __syncthreads();
+  unsigned long long tot = 0ull;
+  int bad = 0, mins = 0;
+  for (int i = tid; i < n; i += 256) {
+    const unsigned long long cur = counters[(size_t)i * kNCnt + C_SEL] + counters[(size_t)i * kNCnt + C_PROC];
+    const unsigned long long pv = prev[i];
+    bad |= cur < pv;
+    s_work[i] = cur >= pv ? cur - pv : 0ull;
+    tot += s_work[i];
+    prev[i] = cur;
+    mins += max(1, (ip[i].nchunk + max_chunks - 1) / max_chunks);
+  }
+  if (bad) atomicAnd(&s_ok, 0);
+  atomicAdd(&s_tot, tot);
+  atomicAdd(&s_min, mins);
+  __syncthreads();
+  if (tid == 0) prev[n] = 1ull;
+  if (!s_ok || s_tot == 0ull || s_min > total) return;
+  const double E = (double)(total - s_min), T = (double)s_tot;
+  for (int i = tid; i < n; i += 256) {
+    const int nc = ip[i].nchunk;
+    const int m = max(1, (nc + max_chunks - 1) / max_chunks);
+    const int sh = min(nc, m + (int)(E * (double)s_work[i] / T));
+    s_share[i] = sh;
+    s_room[i] = nc - sh;
+  }
+  __syncthreads();
+  // shares so far, and the remainder placed in instance order where chunks
+  // are to spare
+  int* sh_copy = reinterpret_cast<int*>(s_work);  // the work counts are no longer needed
+  for (int i = tid; i < n; i += 256) sh_copy[i] = s_share[i];
+  __syncthreads();
+  const int assigned = block_scan_excl(sh_copy, n, s_tmp);
+  const int R = total - assigned;
+  block_scan_excl(s_room, n, s_tmp);  // s_room now holds the room before each instance
+  for (int i = tid; i < n; i += 256) {
+    const int room = ip[i].nchunk - s_share[i];
+    s_share[i] += max(0, min(room, R - s_room[i]));
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += 256) sh_copy[i] = s_share[i];
+  __syncthreads();
+  block_scan_excl(sh_copy, n, s_tmp);  // first workgroup of each instance
+  for (int i = tid; i < n; i += 256) {
+    const int w0 = sh_copy[i], w1 = w0 + s_share[i];
+    ip[i].w0 = w0;
+    ip[i].w1 = w1;
+    for (int w = w0; w < w1; ++w) wg_inst[w] = i;
+  }
+}
+
 // Stable compaction of an instance's slots (device mode), in a refresh where k_inject_plan
 // found the free slots below the live count above 1/32 of the live
 // electrons: every live electron keeps its order and moves to the slot of its
