@@ -79,12 +79,13 @@ def _time_candidate(ens, blob, block, tile, variant, intervals, K):
 
 
 def autotune(ens, candidates=None, trials: int = 5, cache_file: str | None = None, log=None,
-             refine: int = 4) -> dict:
+             refine: int = 4, retimes: int = 4) -> dict:
     """Pick the fastest launch shape for `ens` (a gfmc.Ensemble) and apply it.
     Every candidate is timed once over `trials` intervals; the `refine`
-    fastest are timed twice more over twice as many intervals, and the
-    lowest median of their three timings wins (a single short timing can
-    be off by several percent)."""
+    fastest are timed `retimes` times more over twice as many intervals, and
+    the lowest median of their timings wins (a single short timing can be
+    off by several percent, and the staged variant's two tile sizes differ
+    by about 1%)."""
     key = _key(ens)
     if cache_file and os.path.exists(cache_file) and not _cache:
         try:
@@ -118,7 +119,7 @@ def autotune(ens, candidates=None, trials: int = 5, cache_file: str | None = Non
     if refine > 1:
         for r in top:
             times = [r["ms_per_interval"]]
-            for _ in range(2):
+            for _ in range(retimes):
                 t = _time_candidate(ens, blob, r["block"], r["tile"], r["variant"], 2 * trials, K)
                 if t is not None:
                     times.append(t[0])

@@ -117,16 +117,26 @@ class NoisyEnsemble(FakeEnsemble):
 
 def test_refinement_takes_the_median_not_one_lucky_timing():
     A._cache.clear()
-    lucky = (1024, 8192, 2)        # fast once, slow on both re-timings
+    lucky = (1024, 8192, 2)        # fast once, slow on the re-timings
     steady = (1024, 8192, 3)
     e = NoisyEnsemble("fp32", {lucky: [0.40, 0.60, 0.62], steady: [0.45, 0.46, 0.44]})
     before = e.state
     r = A.autotune(e, candidates=[lucky, steady, (512, 4096, 0)], trials=2, refine=2)
     assert (r["block"], r["tile"], r["variant"]) == steady
-    assert r["refined_ms_per_interval"] == pytest.approx(0.45)
-    assert e.timings[lucky] == 3 and e.timings[steady] == 3
+    # five timings: 0.45, 0.46, 0.44, 0.44, 0.44
+    assert r["refined_ms_per_interval"] == pytest.approx(0.44)
+    assert e.timings[lucky] == 5 and e.timings[steady] == 5
     # the third candidate (1.0 ms) is outside the top two: timed once only
     assert e.state == before and e.shape == steady
+
+
+def test_refinement_resolves_a_small_steady_difference():
+    A._cache.clear()
+    a, b = (1024, 4096, 3), (1024, 8192, 3)
+    # b is luckier on the first, short timing; a is 1% faster on most re-timings
+    e = NoisyEnsemble("fp32", {a: [0.580, 0.574, 0.585, 0.573, 0.575], b: [0.575, 0.581, 0.579, 0.586, 0.580]})
+    r = A.autotune(e, candidates=[a, b], trials=2, refine=2)
+    assert (r["block"], r["tile"], r["variant"]) == a
 
 
 def test_refinement_off_keeps_the_first_timing():
