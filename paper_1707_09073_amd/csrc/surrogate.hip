@@ -251,8 +251,8 @@ GemmArgs ga(const bf16* A, long lda, const bf16* B, long ldb, int M, int N, int 
 // pass follows; the activations are the same either way.
 void enqueue_forward(sg_ctx* c, int e, const float* d_x, int batch, float* out, bool keep_z) {
   const SgLayout& s = c->s;
-  k_input<<<blocks((long)batch * s.K0p), 256, 0, c->st>>>(d_x, batch, c->c.n_in, c->p<float>(s.xmean),
-                                                           c->p<float>(s.xstd), c->p<bf16>(s.X0), s.K0p);
+  k_input<<<dim3(blocks(s.K0p), (batch + kInRows - 1) / kInRows), 256, 0, c->st>>>(
+      d_x, batch, c->c.n_in, c->p<float>(s.xmean), c->p<float>(s.xstd), c->p<bf16>(s.X0), s.K0p);
   const bf16* X = c->p<bf16>(s.X0);
   long ldx = s.K0p;
   for (int l = 0; l < s.L; ++l) {
@@ -295,8 +295,8 @@ struct SmallScratch {
 void enqueue_forward_small(sg_ctx* c, const float* d_x, int batch, const SmallScratch& sc) {
   const SgLayout& s = c->s;
   const int E = c->c.ensemble, width = c->c.width;
-  k_input<<<blocks((long)batch * s.K0p), 256, 0, c->st>>>(d_x, batch, c->c.n_in, c->p<float>(s.xmean),
-                                                           c->p<float>(s.xstd), sc.X0, s.K0p);
+  k_input<<<dim3(blocks(s.K0p), (batch + kInRows - 1) / kInRows), 256, 0, c->st>>>(
+      d_x, batch, c->c.n_in, c->p<float>(s.xmean), c->p<float>(s.xstd), sc.X0, s.K0p);
   const size_t abuf = (size_t)E * s.msmall * width;  // one activation buffer, all members
   int cur = -1;
   for (int l = 0; l < s.L; ++l) {
