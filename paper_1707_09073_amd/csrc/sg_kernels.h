@@ -496,18 +496,45 @@ __global__ void k_colsum_reduce(const float* __restrict__ part, int R, int N, fl
 
 // Adam (bias-corrected) on FP32 master weights with decoupled weight decay
 // wd (Loshchilov & Hutter), then the BF16 copy.
+__device__ __forceinline__ float adam_one(float& w, float& m, float& v, float g, float lr, float b1, float b2, float eps,
+                                          float c1, float c2, float wd) {
+  m = b1 * m + (1.0f - b1) * g;
+  v = b2 * v + (1.0f - b2) * g * g;
+  w = w - lr * ((m / c1) / (sqrtf(v / c2) + eps) + wd * w);
+  return w;
+}
+
+// Four elements per thread: 16-byte loads and stores where the four are in
+// range (the buffers are 256-byte aligned), one at a time at the tail.
 __global__ void k_adam(float* w, float* m, float* v, const float* __restrict__ g, bf16* wb, long n, float lr,
                        float b1, float b2, float eps, float c1, float c2, float wd) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float wi = w[i] - lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * w[i]);
-  w[i] = wi;
-  if (wb) wb[i] = (bf16)wi;
+  const long i0 = 4 * ((long)blockIdx.x * blockDim.x + threadIdx.x);
+  if (i0 >= n) return;
+  if (i0 + 4 <= n) {
+    const float4 G = *reinterpret_cast<const float4*>(g + i0);
+    float4 W = *reinterpret_cast<const float4*>(w + i0), M = *reinterpret_cast<const float4*>(m + i0),
+           V = *reinterpret_cast<const float4*>(v + i0);
+    adam_one(W.x, M.x, V.x, G.x, lr, b1, b2, eps, c1, c2, wd);
+    adam_one(W.y, M.y, V.y, G.y, lr, b1, b2, eps, c1, c2, wd);
+    adam_one(W.z, M.z, V.z, G.z, lr, b1, b2, eps, c1, c2, wd);
+    adam_one(W.w, M.w, V.w, G.w, lr, b1, b2, eps, c1, c2, wd);
+    *reinterpret_cast<float4*>(m + i0) = M;
+    *reinterpret_cast<float4*>(v + i0) = V;
+    *reinterpret_cast<float4*>(w + i0) = W;
+    if (wb) {
+      bf16 o[4] = {(bf16)W.x, (bf16)W.y, (bf16)W.z, (bf16)W.w};
+      *reinterpret_cast<uint2*>(wb + i0) = *reinterpret_cast<const uint2*>(o);
+    }
+  } else {
+    for (long i = i0; i < n; ++i) {
+      float wi = w[i], mi = m[i], vi = v[i];
+      adam_one(wi, mi, vi, g[i], lr, b1, b2, eps, c1, c2, wd);
+      m[i] = mi;
+      v[i] = vi;
+      w[i] = wi;
+      if (wb) wb[i] = (bf16)wi;
+    }
+  }
 }
 
 // N-major copy of a BF16 weight matrix: out[c][r] = in[r][c] for in R x C

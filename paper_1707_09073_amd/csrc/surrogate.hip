@@ -577,9 +577,9 @@ int sg_adam(sg_ctx* c, int member, float lr) {
     const LayerOff& o = s.lo[member][l];
     // layer 0: only the rows of real inputs train (padding stays zero)
     const long n = (long)(l == 0 ? c->c.n_in : s.K[l]) * s.N[l];
-    k_adam<<<blocks(n), 256, 0, c->st>>>(c->p<float>(o.W), c->p<float>(o.m), c->p<float>(o.v), c->p<float>(o.dW),
+    k_adam<<<blocks((n + 3) / 4), 256, 0, c->st>>>(c->p<float>(o.W), c->p<float>(o.m), c->p<float>(o.v), c->p<float>(o.dW),
                                          c->p<bf16>(o.Wb), n, lr, b1, b2, c->c.eps, c1, c2, c->c.weight_decay);
-    k_adam<<<blocks(s.N[l]), 256, 0, c->st>>>(c->p<float>(o.b), c->p<float>(o.bm), c->p<float>(o.bv),
+    k_adam<<<blocks((s.N[l] + 3) / 4), 256, 0, c->st>>>(c->p<float>(o.b), c->p<float>(o.bm), c->p<float>(o.bv),
                                               c->p<float>(o.db), nullptr, s.N[l], lr, b1, b2, c->c.eps, c1, c2, 0.0f);
     enqueue_wt(c, member, l);
   }
