@@ -54,17 +54,17 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 KERNELS = {0: "k_flight_refill<float,true>", 1: "k_flight<float,true>", 2: "k_flight_persist<float,true>",
            3: "k_flight_persist_staged<float,true>"}
 KERNEL_COUNTERS = {
-    0: {"sources_digest": "b1ebdd28c91e88df", "valu_lane_ops_per_segment": 183.9, "hbm_bytes_per_segment": 11.50,
+    0: {"sources_digest": "35e64eb5d2ea9021", "valu_lane_ops_per_segment": 183.9, "hbm_bytes_per_segment": 11.48,
         "active_lane_fraction": 0.534, "profile": "profiles/k_flight_refill_device1e7_counters.md",
         "note": "counters at block 1024 / tile 8192 over intervals 6-10 (9.9e6 electrons, state beyond the "
                 "Infinity Cache, non-temporal state loads); the active lanes include lanes without an electron, "
                 "which run the segment on stale state and drop it, so the useful fraction is an upper bound"},
-    2: {"sources_digest": "b1ebdd28c91e88df", "valu_lane_ops_per_segment": 157.7, "hbm_bytes_per_segment": 8.80,
+    2: {"sources_digest": "35e64eb5d2ea9021", "valu_lane_ops_per_segment": 157.7, "hbm_bytes_per_segment": 8.80,
         "active_lane_fraction": 0.458, "profile": "profiles/k_flight_persist_device1e7_counters.md",
         "note": "counters at block 1024 / tile 8192 over intervals 6-10 (9.9e6 electrons, state beyond the "
                 "Infinity Cache, non-temporal state loads); one resident workgroup of 1024 lanes per CU, chunks of "
                 "128 slots"},
-    3: {"sources_digest": "b1ebdd28c91e88df", "valu_lane_ops_per_segment": 168.2, "hbm_bytes_per_segment": 6.62,
+    3: {"sources_digest": "35e64eb5d2ea9021", "valu_lane_ops_per_segment": 168.2, "hbm_bytes_per_segment": 6.62,
         "active_lane_fraction": 0.431, "profile": "profiles/k_flight_persist_staged_device1e7_counters.md",
         "note": "counters at block 1024 / tile 8192 over intervals 6-10 (9.9e6 electrons, state beyond the "
                 "Infinity Cache); slots staged in LDS a piece of 128 ahead, one resident workgroup per CU, chunks "

@@ -559,14 +559,6 @@ void enqueue_interval(mc_ctx* c) {
   if (e2) (void)hipEventRecord(e2, c->st);
 }
 
-int check_flags(mc_ctx* c, int inst, int* flag_out) {
-  int f = 0;
-  HIPCHK(c, hipMemcpyAsync(&f, c->p<int>(c->o.flags) + inst, sizeof(int), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(c, hipStreamSynchronize(c->st));
-  *flag_out = f;
-  return MC_OK;
-}
-
 }  // namespace
 
 extern "C" {
