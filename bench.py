@@ -75,7 +75,7 @@ KERNEL_COUNTERS = {
 # The phonon packet kernel's counters (profiles/k_ph_packets_wire_trace.md),
 # valid for the phonon.hip whose digest is given: VALU lane-instructions per
 # flight segment and the share of active lanes.
-PH_COUNTERS = {"sources_digest": "2bce4086be64c092", "valu_lane_ops_per_segment": 778.7, "active_lane_fraction": 0.359,
+PH_COUNTERS = {"sources_digest": "823147b268c32621", "valu_lane_ops_per_segment": 793.0, "active_lane_fraction": 0.354,
                "profile": "profiles/k_ph_packets_wire_trace.md"}
 
 
