@@ -35,6 +35,8 @@ typedef struct {
   double T_sink_K;
   int32_t max_iterations; /* conjugate-gradient iterations (>= 1) */
   double rtol;            /* stop when ||b - A x|| <= rtol ||b|| (2-norms, > 0) */
+  int32_t warm_start;     /* 1: start from the rise d_T holds on entry (d_T - T_sink in live cells; an
+                             earlier solution of a nearby problem), 0: from zero */
 } fo_config;
 
 /* Device workspace bytes for cfg (256-byte aligned), 0 if cfg is invalid
@@ -45,9 +47,10 @@ size_t fo_workspace_bytes(const fo_config *cfg);
  * increasing coordinates in m, the x edges, then y, then z), d_kappa
  * (device, ncell, W/(m K); 0 marks a void cell, which takes T_sink and no
  * heat), d_q (device, ncell, W generated in the cell), d_T (device, ncell,
- * out, K).  Jacobi-preconditioned conjugate gradients on the rise above
- * T_sink, dot products reduced in a fixed order (results do not depend on
- * the launch).  Synchronises the stream; *iterations and *rel_residual (may
+ * in with warm_start, out, K).  Jacobi-preconditioned conjugate gradients
+ * on the rise above T_sink, dot products reduced in a fixed order (results
+ * do not depend on the launch); with warm_start the iteration starts from
+ * the rise d_T holds, with the same stopping rule.  Synchronises the stream; *iterations and *rel_residual (may
  * be NULL) receive the iterations done and ||b - A x|| / ||b||.  MC_E_ARG for
  * an invalid configuration, pointer or workspace; MC_E_RANGE if the
  * tolerance is not reached within max_iterations (d_T then holds the last

@@ -56,7 +56,8 @@ typedef struct {
  * contact ends adiabatic). */
 typedef struct {
   fo_config fo;                  /* grid, held faces (the sink), interface plane and R_K, solver settings; its
-                                    T_sink_K is replaced by hy_config's */
+                                    T_sink_K is replaced by hy_config's, and its warm_start by the iteration's
+                                    (each instance's solve starts from its previous one after the first) */
   const double *d_edges;         /* device: the chip's edges, as fo_solve takes them */
   const uint8_t *d_material;     /* device, per chip cell */
   const int32_t *d_src_index;    /* device, per chip cell: the electron subcell whose heat it takes, or -1 */

@@ -187,13 +187,47 @@ __device__ inline double sum_parts(const double* part, int n) {
   return wg_total(v);
 }
 
-__global__ void __launch_bounds__(kFoBlock) k_fo_start(const double* part_rz, const double* part_bb, int n, double* sc) {
+// The iteration's scalars from the set-up's partial sums; r.r is b.b unless
+// a warm start gave its own partials (part_rr non-null)
+__global__ void __launch_bounds__(kFoBlock) k_fo_start(const double* part_rz, const double* part_bb,
+                                                       const double* part_rr, int n, double* sc) {
   const double rz = sum_parts(part_rz, n), bb = sum_parts(part_bb, n);
+  const double rr = part_rr ? sum_parts(part_rr, n) : bb;
   if (threadIdx.x == 0) {
     sc[S_RZ] = rz;
     sc[S_BB] = bb;
-    sc[S_RR] = bb;
+    sc[S_RR] = rr;
   }
+}
+
+// Warm start, first step: the initial rise x0 = T - T_sink (0 in void
+// cells) into p, whose halos the set-up zeroed.
+__global__ void __launch_bounds__(kFoBlock) k_fo_warm_x(long long nc, long long cpw, const double* __restrict__ kap,
+                                                        const double* __restrict__ T, double T_sink, double* p) {
+  long long c0, c1;
+  wg_span(nc, cpw, &c0, &c1);
+  for (long long c = c0 + threadIdx.x; c < c1; c += kFoBlock) p[c] = kap[c] > 0.0 ? T[c] - T_sink : 0.0;
+}
+
+// Warm start, second step (after Ap = A x0): x = x0, r = b - A x0 (r holds
+// b), z = p = r / diag; partial sums of r.z and r.r.
+__global__ void __launch_bounds__(kFoBlock) k_fo_warm_r(long long nc, long long cpw, const double* __restrict__ diag,
+                                                        const double* __restrict__ Ap, double* p, double* x,
+                                                        double* r, double* part_rz, double* part_rr) {
+  double rz = 0.0, rr = 0.0;
+  long long c0, c1;
+  wg_span(nc, cpw, &c0, &c1);
+  for (long long c = c0 + threadIdx.x; c < c1; c += kFoBlock) {
+    x[c] = p[c];
+    const double rc = r[c] - Ap[c];
+    const double z = rc / diag[c];
+    r[c] = rc;
+    p[c] = z;
+    rz += rc * z;
+    rr += rc * rc;
+  }
+  block_sum(rz, part_rz);
+  block_sum(rr, part_rr);
 }
 
 // alpha = r.z / p.Ap (p.Ap from the product's partials, added here);
@@ -313,7 +347,8 @@ struct FoLayout {
 };
 
 bool fo_valid(const fo_config* c) {
-  if (!c || c->max_iterations < 1 || !(c->rtol > 0.0) || !std::isfinite(c->T_sink_K) || !(c->R_K_m2KW >= 0.0))
+  if (!c || c->max_iterations < 1 || !(c->rtol > 0.0) || !std::isfinite(c->T_sink_K) || !(c->R_K_m2KW >= 0.0) ||
+      (c->warm_start != 0 && c->warm_start != 1))
     return false;
   long long nc = 1;
   for (int d = 0; d < 3; ++d) {
@@ -407,7 +442,18 @@ int fo_solve(const fo_config* c, const double* d_edges, const double* d_kappa, c
   k_fo_setup<<<nb, kFoBlock, 0, st>>>(g, (const int*)(ws + L.held), c->k_interface, c->R_K_m2KW, d_kappa, d_q,
                                      P(L.gx), P(L.gy), P(L.gz), P(L.diag), P(L.x), P(L.r), P(L.p), cpw, P(L.part0),
                                      P(L.part1));
-  k_fo_start<<<1, kFoBlock, 0, st>>>(P(L.part0), P(L.part1), nb, sc);
+  if (c->warm_start) {
+    // r = b - A x0 for the rise d_T holds; the product's p.Ap partials are
+    // not used
+    k_fo_warm_x<<<nb, kFoBlock, 0, st>>>(g.nc, cpw, d_kappa, d_T, c->T_sink_K, P(L.p));
+    k_fo_spmv<<<nb, kFoBlock, 0, st>>>(g.nc, cpw, sx, sy, P(L.gx), P(L.gy), P(L.gz), P(L.diag), P(L.p), P(L.Ap),
+                                       P(L.part2));
+    k_fo_warm_r<<<nb, kFoBlock, 0, st>>>(g.nc, cpw, P(L.diag), P(L.Ap), P(L.p), P(L.x), P(L.r), P(L.part0),
+                                         P(L.part2));
+    k_fo_start<<<1, kFoBlock, 0, st>>>(P(L.part0), P(L.part1), P(L.part2), nb, sc);
+  } else {
+    k_fo_start<<<1, kFoBlock, 0, st>>>(P(L.part0), P(L.part1), nullptr, nb, sc);
+  }
   if (hipGetLastError() != hipSuccess) return MC_E_HIP;
   double h[S_N];
   if (hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)

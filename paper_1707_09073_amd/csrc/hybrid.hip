@@ -122,7 +122,7 @@ int plan_chip(const hy_config* h, const hy_chip* chip, int ncell, Plan* p) {
   auto take = [&](size_t b) { const size_t o = off; off += up(b); return o; };
   c.kap = take(sizeof(double) * c.nc);
   c.q = take(sizeof(double) * c.nc);
-  c.T = take(sizeof(double) * c.nc);
+  c.T = take(sizeof(double) * c.nc * (size_t)p->n_inst);  // per instance: each solve starts from its last
   c.base = take(sizeof(double) * ncell);
   c.mx = take(sizeof(double));
   c.fo = take(fb);
@@ -254,12 +254,16 @@ int hy_run(mc_ctx* ctx, const hy_config* h, const hy_chip* chip, const double* h
           return rc;
         int fit = 0;
         double rel = 0.0;
-        rc = fo_solve(&p.fo, chip->d_edges, cat(cs.kap), cat(cs.q), cat(cs.T), &fit, &rel, cw + cs.fo, cs.fo_bytes,
-                      stream);
+        // each instance keeps its chip temperature; from the second
+        // iteration its solve starts there (the heat map moves little)
+        double* Ti = cat(cs.T) + (size_t)i * cs.nc;
+        fo_config fo = p.fo;
+        fo.warm_start = it > 0 ? 1 : 0;
+        rc = fo_solve(&fo, chip->d_edges, cat(cs.kap), cat(cs.q), Ti, &fit, &rel, cw + cs.fo, cs.fo_bytes, stream);
         r.fo_iterations = fit;
         if (rc != MC_OK) return rc;
-        k_hy_gather<<<(nc + 255) / 256, 256, 0, st>>>(cat(cs.T), cs.nc, chip->d_base_index, nc, cat(cs.base));
-        k_hy_max<<<1, 1024, 0, st>>>(cat(cs.T), cs.nc, cat(cs.mx));
+        k_hy_gather<<<(nc + 255) / 256, 256, 0, st>>>(Ti, cs.nc, chip->d_base_index, nc, cat(cs.base));
+        k_hy_max<<<1, 1024, 0, st>>>(Ti, cs.nc, cat(cs.mx));
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(base.data(), cat(cs.base), sizeof(double) * nc, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipMemcpyAsync(&fo_max, cat(cs.mx), sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)

@@ -720,7 +720,7 @@ class PhononMC:
 class FoConfig(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("dirichlet", C.c_int32 * 6), ("k_interface", C.c_int32),
                 ("R_K_m2KW", C.c_double), ("T_sink_K", C.c_double), ("max_iterations", C.c_int32),
-                ("rtol", C.c_double)]
+                ("rtol", C.c_double), ("warm_start", C.c_int32)]
 
 
 FO_EXPORTS = ["fo_workspace_bytes", "fo_solve", "fo_chip_fields"]
@@ -752,14 +752,19 @@ def fo_config(cfg: dict) -> FoConfig:
     c.T_sink_K = float(cfg["T_sink_K"])
     c.max_iterations = int(cfg.get("max_iterations", 20000))
     c.rtol = float(cfg.get("rtol", 1e-12))
+    c.warm_start = int(cfg.get("warm_start", 0))
     return c
 
 
-def fo_solve(cfg: dict, edges, kappa, q, stream=None, check: bool = True) -> dict:
+def fo_solve(cfg: dict, edges, kappa, q, stream=None, check: bool = True, T0=None) -> dict:
     """Temperature per cell (device tensor, K) of a conduction problem; edges
-    is the x, y, z edge coordinates (m) concatenated or a list of three."""
+    is the x, y, z edge coordinates (m) concatenated or a list of three.
+    With T0 (per cell, K) the iteration starts from that temperature (a
+    warm start) instead of T_sink."""
     import torch
     c = fo_config(cfg)
+    if T0 is not None:
+        c.warm_start = 1
     L = _fo_lib()
     n = int(L.fo_workspace_bytes(C.byref(c)))
     if n == 0:
@@ -770,7 +775,12 @@ def fo_solve(cfg: dict, edges, kappa, q, stream=None, check: bool = True) -> dic
                         dtype=torch.float64).to("cuda").contiguous()
     k = torch.as_tensor(kappa, dtype=torch.float64).to("cuda").contiguous()
     qq = torch.as_tensor(q, dtype=torch.float64).to("cuda").contiguous()
-    T = torch.empty_like(k)
+    if T0 is not None:
+        T = torch.as_tensor(T0, dtype=torch.float64).to("cuda").clone().contiguous()
+        if T.numel() != k.numel():
+            raise MCError(MC_E_ARG, "fo_solve", "T0 must have one value per cell")
+    else:
+        T = torch.empty_like(k)
     ws = torch.empty(n, dtype=torch.uint8, device="cuda")
     it, rel = C.c_int(0), C.c_double(0.0)
     st = _stream_ptr(stream)
